@@ -1,0 +1,219 @@
+/*
+ * kcenter.h -- C ABI of libkcenter, the MI355X (gfx950) k-center hot path of
+ * McClintock & Wirth, "Efficient Parallel Algorithms for k-Center
+ * Clustering" (arXiv 1604.03228).
+ *
+ * Common rules for every entry point
+ * ----------------------------------
+ * Points.   A kc_points names a row-major FP32 array X[n][ld] in device
+ *           memory (only the first d columns are read), optionally with a
+ *           BF16 copy B[n][ld] (bit patterns, device memory).  The distance
+ *           is Euclidean (Section 7.2: computed from coordinates as needed).
+ * Indices.  Point indices are int64 row numbers of X.  Reported radii are
+ *           Euclidean distances in FP64.
+ * Ties.     Among equally far points the lowest index wins; among equally
+ *           near centers the lowest center position wins.  The paper leaves
+ *           these choices arbitrary but consistent (Sections 3.1, 6).
+ * Streams.  `stream` is a hipStream_t (NULL: the default stream).  Every
+ *           call only enqueues work on it and returns; results are valid once
+ *           the stream has synchronised.  Exceptions are stated per call.
+ * Memory.   The caller owns every input and output buffer.  The library
+ *           owns only its workspace (held by the handle, grown on demand with
+ *           hipMalloc, freed by kc_destroy) and never frees caller memory.
+ *           Calls on one handle must not overlap (one stream at a time).
+ * Errors.   Every entry point returns KC_OK or a negative kc_status.  All
+ *           argument checks happen on the host before any device work; a
+ *           failed check enqueues nothing.  kc_last_error() gives the text of
+ *           the last failure on a handle.  Nothing aborts or throws.
+ * Inputs.   Non-finite coordinates give unspecified (but memory-safe)
+ *           results.  n must be below 2^32 - 1 and d at most 256.
+ */
+#ifndef KCENTER_H
+#define KCENTER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kc_handle kc_handle;
+
+typedef enum {
+    KC_OK = 0,
+    KC_EINVAL = -1,        /* invalid argument                              */
+    KC_ENOMEM = -2,        /* workspace allocation failed                   */
+    KC_EHIP = -3,          /* a HIP runtime call failed                     */
+    KC_ENOCONV = -4,       /* EIM did not converge within max_iters         */
+    KC_EUNSUPPORTED = -6,  /* valid request this build cannot serve         */
+    KC_EDEVICE = -7        /* a device-side check failed (see kc_device_status) */
+} kc_status;
+
+typedef enum {
+    KC_FP32 = 0,           /* stream FP32 points                            */
+    KC_BF16_RESCORE = 1    /* stream BF16 points, rescore near-ties in FP32 */
+} kc_precision;
+
+typedef struct {
+    const float* f32;      /* device [n][ld] FP32, required                  */
+    const uint16_t* bf16;  /* device [n][ld] BF16 bits; required iff
+                              prec == KC_BF16_RESCORE, ignored otherwise     */
+    int64_t n;             /* points, 1 <= n < 2^32 - 1                      */
+    int32_t d;             /* coordinates per point, 1 <= d <= 256           */
+    int64_t ld;            /* row stride in elements, ld >= d                */
+    int32_t prec;          /* kc_precision                                   */
+} kc_points;
+
+/* Handle life cycle.  kc_create binds the handle to the current HIP device.
+ * Returns KC_OK, KC_EINVAL (out == NULL), KC_ENOMEM or KC_EHIP. */
+int kc_create(kc_handle** out);
+void kc_destroy(kc_handle* h);
+const char* kc_strerror(int status);
+const char* kc_last_error(const kc_handle* h);
+
+/* Options (name, value): "graphs" 0/1 (capture per-step launches in a HIP
+ * graph, default 1); "resident" 0/1 (use the register-resident persistent
+ * Gonzalez kernel when the points fit, default 1).  KC_EINVAL for an unknown
+ * name. */
+int kc_set_option(kc_handle* h, const char* name, int64_t value);
+
+/* Synchronises `stream`, then reads and clears the handle's device status
+ * word (bit 0: a persistent kernel's grid barrier timed out; bit 1: a
+ * candidate buffer overflowed).  *status receives the word.  Returns KC_OK,
+ * or KC_EDEVICE when the word was non-zero. */
+int kc_device_status(kc_handle* h, void* stream, uint32_t* status);
+
+/*
+ * kcenter_gonzalez -- Gonzalez's farthest-first traversal (Section 3.1; its
+ * cost model in Section 5.1).  The first center is `first`; each later center
+ * is a point farthest from the centers chosen so far, until k are chosen or
+ * every point coincides with a center (the problem asks for at most k
+ * centers, Section 1.1).
+ *   pts           points (prec selects the FP32 or BF16+rescore stream; both
+ *                 choose the same centers).
+ *   k             centers wanted, k >= 1 (k >= n is allowed).
+ *   first         index of the first center, 0 <= first < n.
+ *   centers       device int64 [k]: chosen indices in selection order, -1
+ *                 after an early stop.
+ *   radius_trace  device double [k] or NULL: radius_trace[t] is the FP64
+ *                 distance of the point chosen at step t+1 to its nearest of
+ *                 centers 0..t, i.e. the covering radius after t+1 centers
+ *                 (within the FP32 tie band of the exact value); the entry of
+ *                 the last chosen center is the exact FP64 covering radius of
+ *                 all chosen centers; 0 after an early stop.
+ *   n_chosen      device int64 [1]: number of centers chosen.
+ */
+int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t first,
+                     int64_t* centers, double* radius_trace, int64_t* n_chosen,
+                     void* stream);
+
+/*
+ * kcenter_mrg -- two-round MRG (Algorithm 1 with one pass of its loop;
+ * Lemma 2 gives the factor 4).  Round 1 runs Gonzalez(k) on each partition
+ * (first center: the partition's first point), all partitions in the same
+ * launches; round 2 runs Gonzalez(k) on the union of their centers in
+ * ascending index order (first center: the smallest index); the result is
+ * assigned to all points for its covering radius.
+ *   offsets   HOST int64 [m+1], 0 = o_0 <= o_1 <= ... <= o_m = n: partition
+ *             p is rows [o_p, o_{p+1}); empty partitions are allowed.
+ *   m         partitions, 1 <= m.
+ *   k         centers, k >= 1.
+ *   centers   device int64 [k] (-1 padded), n_centers device int64 [1].
+ *   radius    device double [1]: exact FP64 covering radius over all points.
+ *   round1    device int64 [m*k] or NULL: partition p's centers at p*k.
+ *   r1        device double [m] or NULL: round-1 covering radius per
+ *             partition (0 if empty).
+ *   uni       device int64 [m*k] or NULL: the union, ascending, and
+ *   n_union   device int64 [1] or NULL: its size.
+ *   r2        device double [1] or NULL: round-2 covering radius of the union.
+ */
+int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int32_t m,
+                int64_t k, int64_t* centers, int64_t* n_centers, double* radius,
+                int64_t* round1, double* r1, int64_t* uni, int64_t* n_union,
+                double* r2, void* stream);
+
+/*
+ * kcenter_assign -- nearest-center assignment and covering radius (the
+ * k-center objective of Section 1.1: each point is served by its nearest
+ * center; the solution value is the largest such distance).  Distances run
+ * as |x|^2 + |c|^2 - 2 x.c on MFMA (FP32, or BF16 when pts->prec is
+ * KC_BF16_RESCORE); every point whose nearest center is not certified by the
+ * a-priori error bound, and every point that may attain the maximum, is
+ * rescored exactly in FP64.
+ *   centers  device int64 [k], point indices, 1 <= k <= 4096.
+ *   labels   device int32 [n] or NULL: position in centers of the nearest.
+ *   radius   device double [1]: exact FP64 covering radius.
+ */
+int kcenter_assign(kc_handle* h, const kc_points* pts, const int64_t* centers,
+                   int64_t k, int32_t* labels, double* radius, void* stream);
+
+/* EIM parameters (Algorithm 2 and Select, Algorithm 3, with phi). */
+typedef struct {
+    double eps;          /* 0 < eps < 1                                     */
+    double phi;          /* phi > 0; the original algorithm has phi = 8      */
+    uint64_t seed;       /* Philox4x64-10 key word 0                          */
+    int32_t max_iters;   /* >= 1; KC_ENOCONV if R is still large after it    */
+} kc_eim_params;
+
+/* Per-iteration record of kcenter_eim. */
+typedef struct {
+    int64_t r_size;      /* |R| at the start of the iteration                 */
+    int64_t ds_size;     /* points drawn into S in this iteration             */
+    int64_t h_size;      /* |H|                                               */
+    int64_t s_size;      /* |S| after the draw                                */
+    double tau;          /* squared threshold d(v,S)^2 (-inf if H is empty)   */
+    double p_s, p_h;     /* sampling probabilities                            */
+} kc_eim_iter;
+
+/*
+ * kcenter_eim -- EIM-MapReduce-Sample (Algorithm 2) with Select (Algorithm
+ * 3, parameter phi) and the termination changes of Section 4.1, then
+ * Gonzalez on the sample C = S u R (the extra round) and the covering radius
+ * over all points.  With L = ln n: while |R| > (4/eps) k n^eps L, every
+ * x in R joins S with probability min(1, 9 k n^eps L / |R|) and H with
+ * probability min(1, 4 n^eps L / |R|) (independent Philox4x64-10 draws:
+ * key (seed, 0), counter (x, iteration, 0, 0), words 0 and 1, top 53 bits);
+ * tau is the min(ceil(phi L), |H|)-th largest d(h,S)^2 over H; R keeps x iff
+ * x is not in S and d(x,S)^2 > tau.  Distances of R to the new samples run on
+ * MFMA; every keep/remove decision the error bound cannot certify is made in
+ * FP64.  SYNCHRONISES the stream once per iteration (to size the next one).
+ *   centers    device int64 [k]; n_centers device int64 [1]; radius device
+ *              double [1].
+ *   sample     device int64 [n] or NULL: C ascending; n_sample HOST int64.
+ *   iters      HOST kc_eim_iter [max_iters] or NULL; n_iters HOST int32.
+ */
+int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k, const kc_eim_params* prm,
+                int64_t* centers, int64_t* n_centers, double* radius, int64_t* sample,
+                int64_t* n_sample, kc_eim_iter* iters, int32_t* n_iters, void* stream);
+
+typedef enum { KC_ALGO_GON = 0, KC_ALGO_MRG = 1, KC_ALGO_EIM = 2 } kc_algo;
+
+/* One independent problem of a batch. */
+typedef struct {
+    kc_points pts;
+    int32_t algo;              /* kc_algo                                      */
+    int64_t k;
+    int64_t first;             /* GON only                                     */
+    const int64_t* offsets;    /* MRG only: HOST [m+1]                         */
+    int32_t m;                 /* MRG only                                     */
+    kc_eim_params eim;         /* EIM only                                     */
+    int64_t* centers;          /* device int64 [k]                             */
+    int64_t* n_centers;        /* device int64 [1]                             */
+    double* radius;            /* device double [1]: exact covering radius     */
+} kc_problem;
+
+/*
+ * kcenter_batch -- solve `count` independent problems of mixed n, d, k and
+ * algorithm.  Gonzalez problems and MRG first rounds of equal d share the
+ * same step launches (one tile list over all of them, a HIP graph per plan);
+ * MRG second rounds likewise; EIM problems run their sampling loop (which
+ * synchronises the stream per iteration) and join the shared launches for
+ * their final Gonzalez.  Outputs as for the single-problem calls.
+ */
+int kcenter_batch(kc_handle* h, const kc_problem* probs, int32_t count, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KCENTER_H */

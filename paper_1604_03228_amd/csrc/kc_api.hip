@@ -1,0 +1,382 @@
+// kc_api.hip -- host side of libkcenter: the C ABI declared in
+// include/kcenter.h, argument checks, workspace, launch planning and HIP
+// graph capture of the per-step launch sequences.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/kcenter.h"
+#include "kc_internal.h"
+#include "kc_host.h"
+
+// ---------------------------------------------------------------------------
+// handle
+
+kc_handle::~kc_handle()
+{
+    clear_graphs();
+    for (auto& kv : bufs) hipFree(kv.second.p);
+    if (status_word) hipFree(status_word);
+}
+
+void kc_handle::clear_graphs()
+{
+    for (auto& kv : graphs) {
+        hipGraphExecDestroy(kv.second.exec);
+        hipGraphDestroy(kv.second.graph);
+    }
+    graphs.clear();
+}
+
+int kc_handle::fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    last_error = buf;
+    return code;
+}
+
+void* kc_handle::ws(const std::string& name, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    bytes = (bytes + 255) & ~(size_t)255;
+    auto it = bufs.find(name);
+    if (it != bufs.end() && it->second.bytes >= bytes) return it->second.p;
+    if (it != bufs.end()) {
+        // growing invalidates every captured graph (they embed the old address)
+        hipDeviceSynchronize();
+        clear_graphs();
+        hipFree(it->second.p);
+        bufs.erase(it);
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    bufs[name] = DevBuf{p, bytes};
+    return p;
+}
+
+// Upload a host table to a named workspace buffer, skipping the copy when the
+// same bytes were uploaded last time (so repeated identical calls stay free
+// of host-device synchronisation).
+void* kc_handle::upload(const std::string& name, const void* src, size_t bytes)
+{
+    void* p = ws(name, bytes);
+    if (!p) return nullptr;
+    auto& shadow = shadows[name];
+    if (shadow.size() == bytes && bytes > 0 && memcmp(shadow.data(), src, bytes) == 0 &&
+        shadow_ptr[name] == p)
+        return p;
+    if (bytes > 0 && hipMemcpy(p, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    shadow.assign((const char*)src, (const char*)src + bytes);
+    shadow_ptr[name] = p;
+    return p;
+}
+
+// Run `enqueue` on `stream`, through a cached HIP graph when graphs are on and
+// the stream is not already being captured by the caller.
+int kc_handle::run_graph(const std::string& key, hipStream_t stream,
+                         const std::function<void(hipStream_t)>& enqueue)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        cs = hipStreamCaptureStatusNone;
+    }
+    if (!use_graphs || cs != hipStreamCaptureStatusNone || stream == nullptr) {
+        enqueue(stream);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? KC_OK : fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
+    }
+    auto it = graphs.find(key);
+    if (it == graphs.end()) {
+        if (graphs.size() >= 32) clear_graphs();
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ex = nullptr;
+        hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return fail(KC_EHIP, "begin capture: %s", hipGetErrorString(e));
+        enqueue(stream);
+        e = hipStreamEndCapture(stream, &g);
+        if (e != hipSuccess) return fail(KC_EHIP, "end capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(g);
+            return fail(KC_EHIP, "instantiate: %s", hipGetErrorString(e));
+        }
+        it = graphs.emplace(key, GraphEntry{g, ex}).first;
+    }
+    hipError_t e = hipGraphLaunch(it->second.exec, stream);
+    return e == hipSuccess ? KC_OK : fail(KC_EHIP, "graph launch: %s", hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// argument checks
+
+int kc_check_points(kc_handle* h, const kc_points* p, bool need_bf16_if_asked)
+{
+    if (!p) return h->fail(KC_EINVAL, "points: NULL");
+    if (!p->f32) return h->fail(KC_EINVAL, "points: f32 is NULL");
+    if (p->n < 1 || p->n >= (int64_t)0xFFFFFFFFll)
+        return h->fail(KC_EINVAL, "points: n=%lld out of range", (long long)p->n);
+    if (p->d < 1 || p->d > KC_MAXD)
+        return h->fail(KC_EINVAL, "points: d=%d out of range [1,%d]", p->d, KC_MAXD);
+    if (p->ld < p->d) return h->fail(KC_EINVAL, "points: ld < d");
+    if (p->prec != KC_FP32 && p->prec != KC_BF16_RESCORE)
+        return h->fail(KC_EINVAL, "points: unknown precision %d", p->prec);
+    if (need_bf16_if_asked && p->prec == KC_BF16_RESCORE && !p->bf16)
+        return h->fail(KC_EINVAL, "points: BF16 precision needs a bf16 copy");
+    return KC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched Gonzalez planning
+
+int kc_plan_gon(kc_handle* h, const std::string& pre, int d,
+                const std::vector<KcGonJob>& jobs, KcGonRun& R, KcGonHost& H)
+{
+    const int nseg = (int)jobs.size();
+    H.segs.assign(nseg, KcSeg{});
+    H.blk_seg.clear();
+    H.blk_start.clear();
+    H.pairs_seg.clear();
+    H.pairs_t.clear();
+    uint64_t base = 0, keyoff = 0, total = 0;
+    uint32_t kmax = 0;
+    for (int s = 0; s < nseg; ++s) {
+        const KcGonJob& j = jobs[s];
+        KcSeg& sg = H.segs[s];
+        sg.src = j.row0;
+        sg.base = base;
+        sg.len = j.len;
+        sg.first = j.first;
+        sg.ksteps = j.len == 0 ? 0 : j.k;
+        sg.keyoff = (uint32_t)keyoff;
+        for (uint32_t st = 0; st < j.len; st += KC_BLOCK * 4) {
+            H.blk_seg.push_back((uint32_t)s);
+            H.blk_start.push_back(st);
+        }
+        for (uint32_t t = 0; t < sg.ksteps; ++t) {
+            H.pairs_seg.push_back((uint32_t)s);
+            H.pairs_t.push_back(t);
+        }
+        base += kc_pad64(j.len);
+        keyoff += j.k;
+        total += j.len;
+        kmax = std::max(kmax, sg.ksteps);
+    }
+    if (keyoff >= 0xFFFFFFFFull) return h->fail(KC_EINVAL, "too many centers in one batch");
+    const uint64_t stride = std::max<uint64_t>(base, 64);
+    R.d = d;
+    R.nseg = nseg;
+    R.kmax = kmax;
+    R.stride = stride;
+    R.nblk = (uint32_t)H.blk_seg.size();
+    R.npairs = (uint32_t)H.pairs_seg.size();
+    R.band = 2.0 * kc_gamma32(d) + 4.0 * 5.9604644775390625e-8;
+    R.cand_cap = (uint32_t)std::max<uint64_t>(total, 1);
+    float* xs = (float*)h->ws(pre + "xs", sizeof(float) * (size_t)d * stride);
+    R.xs = xs;
+    R.mind = (float*)h->ws(pre + "mind", sizeof(float) * stride);
+    R.keys = (u64*)h->ws(pre + "keys", sizeof(u64) * std::max<uint64_t>(keyoff, 1));
+    R.ccoord = (float*)h->ws(pre + "ccoord", sizeof(float) * (size_t)d * std::max<uint64_t>(keyoff, 1));
+    R.radius2 = (double*)h->ws(pre + "radius2", sizeof(double) * nseg);
+    R.cand = (u64*)h->ws(pre + "cand", sizeof(u64) * R.cand_cap);
+    R.ncand = (uint32_t*)h->ws(pre + "ncand", sizeof(uint32_t));
+    if (!R.xs || !R.mind || !R.keys || !R.ccoord || !R.radius2 || !R.cand || !R.ncand)
+        return h->fail(KC_ENOMEM, "workspace allocation failed");
+    R.segs = (KcSeg*)h->upload(pre + "segs", H.segs.data(), sizeof(KcSeg) * nseg);
+    R.blk_seg = (uint32_t*)h->upload(pre + "blk_seg", H.blk_seg.data(), 4 * H.blk_seg.size());
+    R.blk_start = (uint32_t*)h->upload(pre + "blk_start", H.blk_start.data(), 4 * H.blk_start.size());
+    R.pairs_seg = (uint32_t*)h->upload(pre + "pairs_seg", H.pairs_seg.data(), 4 * H.pairs_seg.size());
+    R.pairs_t = (uint32_t*)h->upload(pre + "pairs_t", H.pairs_t.data(), 4 * H.pairs_t.size());
+    if (!R.segs || !R.blk_seg || !R.blk_start || !R.pairs_seg || !R.pairs_t)
+        return h->fail(KC_ENOMEM, "plan upload failed");
+    R.keysum = keyoff;
+    return KC_OK;
+}
+
+// Enqueue staging + init + all steps (streaming engine) of a planned run.
+void kc_enqueue_gon_stream(const KcGonRun& R, const KcGonHost& H,
+                           const std::vector<KcGonJob>& jobs, hipStream_t s)
+{
+    for (size_t q = 0; q < jobs.size(); ++q)
+        if (jobs[q].X)
+            kc_stage_soa(jobs[q].X, jobs[q].ld, R.d, jobs[q].row0, jobs[q].len, (float*)R.xs,
+                         R.stride, H.segs[q].base, s);
+    kc_fill_u32((uint32_t*)R.mind, 0x7F800000u, R.stride, s);   // +inf
+    kc_fill_u64(R.keys, 0ull, R.keysum, s);
+    for (uint32_t t = 0; t < R.kmax; ++t)
+        kc_gon_step(R.xs, R.stride, R.d, R.mind, R.keys, R.segs, R.blk_seg, R.blk_start,
+                    R.nblk, (int)t, s);
+}
+
+// ---------------------------------------------------------------------------
+// public entry points
+
+extern "C" {
+
+int kc_create(kc_handle** out)
+{
+    if (!out) return KC_EINVAL;
+    *out = nullptr;
+    kc_handle* h = new (std::nothrow) kc_handle();
+    if (!h) return KC_ENOMEM;
+    if (hipGetDevice(&h->device) != hipSuccess ||
+        hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, h->device) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        return KC_EHIP;
+    }
+    if (hipMalloc(&h->status_word, 256) != hipSuccess ||
+        hipMemset(h->status_word, 0, 256) != hipSuccess) {
+        (void)hipGetLastError();
+        delete h;
+        return KC_ENOMEM;
+    }
+    *out = h;
+    return KC_OK;
+}
+
+void kc_destroy(kc_handle* h)
+{
+    if (!h) return;
+    hipDeviceSynchronize();
+    delete h;
+}
+
+const char* kc_strerror(int status)
+{
+    switch (status) {
+    case KC_OK: return "ok";
+    case KC_EINVAL: return "invalid argument";
+    case KC_ENOMEM: return "out of device memory";
+    case KC_EHIP: return "HIP runtime error";
+    case KC_ENOCONV: return "EIM did not converge within max_iters";
+    case KC_EUNSUPPORTED: return "unsupported request";
+    case KC_EDEVICE: return "device-side check failed";
+    default: return "unknown status";
+    }
+}
+
+const char* kc_last_error(const kc_handle* h)
+{
+    return h ? h->last_error.c_str() : "NULL handle";
+}
+
+int kc_set_option(kc_handle* h, const char* name, int64_t value)
+{
+    if (!h || !name) return KC_EINVAL;
+    if (!strcmp(name, "graphs")) {
+        h->use_graphs = value != 0;
+        return KC_OK;
+    }
+    if (!strcmp(name, "resident")) {
+        h->allow_resident = value != 0;
+        return KC_OK;
+    }
+    if (!strcmp(name, "spin_limit")) {
+        if (value < 1 || value > 0x7FFFFFFF) return h->fail(KC_EINVAL, "spin_limit range");
+        h->spin_limit = (uint32_t)value;
+        return KC_OK;
+    }
+    return h->fail(KC_EINVAL, "unknown option '%s'", name);
+}
+
+int kc_device_status(kc_handle* h, void* stream, uint32_t* status)
+{
+    if (!h || !status) return KC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t w[2] = {0, 0};
+    if (hipStreamSynchronize(s) != hipSuccess ||
+        hipMemcpy(w, h->status_word, 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemset(h->status_word, 0, 256) != hipSuccess) {
+        hipError_t e = hipGetLastError();
+        return h->fail(KC_EHIP, "status: %s", hipGetErrorString(e));
+    }
+    *status = w[0] | w[1];
+    return *status ? h->fail(KC_EDEVICE, "device status 0x%x", *status) : KC_OK;
+}
+
+int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t first,
+                     int64_t* centers, double* radius_trace, int64_t* n_chosen, void* stream)
+{
+    if (!h) return KC_EINVAL;
+    int rc = kc_check_points(h, pts, true);
+    if (rc) return rc;
+    if (k < 1 || k >= (int64_t)0x7FFFFFFF) return h->fail(KC_EINVAL, "k=%lld", (long long)k);
+    if (first < 0 || first >= pts->n) return h->fail(KC_EINVAL, "first out of range");
+    if (!centers || !n_chosen) return h->fail(KC_EINVAL, "centers/n_chosen NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (pts->prec == KC_BF16_RESCORE)
+        return kc_gonzalez_bf16(h, pts, k, first, centers, radius_trace, n_chosen, s);
+
+    std::vector<KcGonJob> jobs(1);
+    jobs[0] = KcGonJob{pts->f32, pts->ld, 0, (uint32_t)pts->n, (uint32_t)first, (uint32_t)k};
+    KcGonRun R;
+    KcGonHost H;
+    rc = kc_plan_gon(h, "g.", pts->d, jobs, R, H);
+    if (rc) return rc;
+
+    // register-resident persistent kernel when the whole problem fits
+    if (h->allow_resident) {
+        const uint32_t G = kc_resident_blocks_for(pts->d, (uint32_t)pts->n);
+        const int Gmax = G ? h->resident_max(pts->d) : 0;
+        if (G > 0 && (int)G <= Gmax) {
+            uint32_t* arrive = (uint32_t*)h->ws("g.arrive", sizeof(uint32_t) * (size_t)k);
+            uint32_t* abort_flag = (uint32_t*)h->ws("g.abort", 64);
+            if (!arrive || !abort_flag) return h->fail(KC_ENOMEM, "workspace allocation failed");
+            kc_stage_soa(pts->f32, pts->ld, pts->d, 0, (uint32_t)pts->n, (float*)R.xs,
+                         R.stride, 0, s);
+            kc_fill_u32((uint32_t*)R.mind, 0x7F800000u, R.stride, s);
+            kc_fill_u64(R.keys, 0ull, R.keysum, s);
+            kc_fill_u32(arrive, 0u, (uint64_t)k, s);
+            kc_fill_u32(abort_flag, 0u, 1, s);
+            hipError_t e = kc_gon_resident(pts->d, G, R.xs, R.stride, 0, (uint32_t)pts->n,
+                                           (uint32_t)first, (int)k, R.mind, R.keys, arrive,
+                                           abort_flag, h->spin_limit, s);
+            if (e == hipSuccess) {
+                kc_or_status(abort_flag, h->status_word, 1u, s);
+                kc_gon_finish(R, centers, n_chosen, radius_trace, nullptr, nullptr, s);
+                e = hipGetLastError();
+                return e == hipSuccess ? KC_OK
+                                       : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
+            }
+            (void)hipGetLastError();   // not co-resident: fall back to streaming
+        }
+    }
+
+    char key[256];
+    snprintf(key, sizeof key, "gon:%p:%lld:%d:%lld:%lld:%lld:%p:%p:%p", (const void*)pts->f32,
+             (long long)pts->n, pts->d, (long long)pts->ld, (long long)k, (long long)first,
+             (void*)centers, (void*)radius_trace, (void*)n_chosen);
+    return h->run_graph(key, s, [&](hipStream_t st) {
+        kc_enqueue_gon_stream(R, H, jobs, st);
+        kc_gon_finish(R, centers, n_chosen, radius_trace, nullptr, nullptr, st);
+    });
+}
+
+}  // extern "C"
+
+int kc_handle::resident_max(int d)
+{
+    auto it = resident_cache.find(d);
+    if (it != resident_cache.end()) return it->second;
+    int v = kc_resident_max_blocks(d);
+    resident_cache[d] = v;
+    return v;
+}

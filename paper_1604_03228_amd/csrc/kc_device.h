@@ -1,0 +1,97 @@
+// kc_device.h -- device helpers shared by the HIP kernels of libkcenter.
+//
+// Conventions used by every kernel:
+//  * A point's squared distance to a center in FP32 is the "canonical" value
+//      s = 0; for t in 0..d-1: diff = x_t - c_t; s = fmaf(diff, diff, s)
+//    computed by one lane per point in ascending t.  Every path that compares
+//    FP32 distances (the FP32 stream, the BF16 path's exact rescoring) uses
+//    this one function, so tiling and launch shape never change a result.
+//    Its relative error against the exact value is at most gamma_{d+2},
+//    gamma_m = m u / (1 - m u), u = 2^-24.
+//  * The FP64 distance is the sum of separately rounded squares of exact
+//    FP64 differences, ascending t, no FMA contraction.
+//  * Farthest-point selection packs (value, index) into one 64-bit key:
+//    high word = bits of the non-negative FP32 value (monotone as unsigned),
+//    low word  = 0xFFFFFFFF - index, so the maximum key is the farthest point
+//    and, among equal values, the lowest index (ties to the lowest index).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define KC_BLOCK 256
+#define KC_MAXD 256
+
+typedef unsigned long long u64;
+
+// One problem or partition of a batched Gonzalez run.
+struct KcSeg {
+    uint64_t src;     // first row of this segment in the caller's [n][ld] array
+    uint64_t base;    // first column of this segment in the SoA staging copy
+    uint32_t len;     // points in the segment
+    uint32_t first;   // local index of the first center
+    uint32_t ksteps;  // centers to choose
+    uint32_t keyoff;  // this segment's keys live at keys[keyoff + t]
+};
+
+__device__ __forceinline__ float kc_d32_step(float s, float x, float c)
+{
+    float diff = x - c;
+    return __builtin_fmaf(diff, diff, s);
+}
+
+__device__ __forceinline__ double kc_d64_step(double s, double x, double c)
+{
+    double diff = x - c;
+    double sq = __dmul_rn(diff, diff);
+    return __dadd_rn(s, sq);
+}
+
+__device__ __forceinline__ u64 kc_pack(float v, uint32_t idx)
+{
+    return ((u64)__float_as_uint(v) << 32) | (u64)(0xFFFFFFFFu - idx);
+}
+__device__ __forceinline__ uint32_t kc_key_idx(u64 k) { return 0xFFFFFFFFu - (uint32_t)k; }
+__device__ __forceinline__ float kc_key_val(u64 k) { return __uint_as_float((uint32_t)(k >> 32)); }
+
+__device__ __forceinline__ u64 kc_umax64(u64 a, u64 b) { return a > b ? a : b; }
+
+__device__ __forceinline__ u64 kc_wave_max64(u64 v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        u64 o = __shfl_xor(v, off, 64);
+        v = kc_umax64(v, o);
+    }
+    return v;
+}
+
+// Block-wide max of a 64-bit key; the result is valid in every thread.
+// `red` must hold blockDim.x / 64 entries.
+__device__ __forceinline__ u64 kc_block_max64(u64 v, u64* red)
+{
+    v = kc_wave_max64(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    u64 r = red[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = kc_umax64(r, red[i]);
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double kc_wave_min_f64(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Non-negative doubles order like their bit patterns as unsigned integers.
+__device__ __forceinline__ void kc_atomic_max_f64_nonneg(double* p, double v)
+{
+    atomicMax((u64*)p, (u64)__double_as_longlong(v));
+}
+__device__ __forceinline__ void kc_atomic_max_f32_nonneg(float* p, float v)
+{
+    atomicMax((unsigned*)p, __float_as_uint(v));
+}

@@ -1,0 +1,71 @@
+// kc_host.h -- host-side types of libkcenter (handle, workspace, plans).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <functional>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/kcenter.h"
+#include "kc_internal.h"
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct kc_handle {
+    int device = 0;
+    int num_cu = 0;
+    bool use_graphs = true;
+    bool allow_resident = true;
+    uint32_t spin_limit = 1u << 24;   // polls before a barrier wait gives up
+    uint32_t* status_word = nullptr;  // device, see kc_device_status
+    std::string last_error;
+    std::map<std::string, DevBuf> bufs;
+    std::map<std::string, std::vector<char>> shadows;
+    std::map<std::string, void*> shadow_ptr;
+    std::map<std::string, GraphEntry> graphs;
+    std::map<int, int> resident_cache;
+
+    ~kc_handle();
+    void clear_graphs();
+    int fail(int code, const char* fmt, ...);
+    void* ws(const std::string& name, size_t bytes);
+    void* upload(const std::string& name, const void* src, size_t bytes);
+    int run_graph(const std::string& key, hipStream_t stream,
+                  const std::function<void(hipStream_t)>& enqueue);
+    int resident_max(int d);
+};
+
+// One segment of a batched Gonzalez run, as the host describes it.
+struct KcGonJob {
+    const float* X = nullptr;  // source rows (NULL: xs already filled)
+    int64_t ld = 0;
+    uint64_t row0 = 0;         // first source row
+    uint32_t len = 0;
+    uint32_t first = 0;        // local index of the first center
+    uint32_t k = 0;
+};
+
+// Host copies of a run's tables.
+struct KcGonHost {
+    std::vector<KcSeg> segs;
+    std::vector<uint32_t> blk_seg, blk_start, pairs_seg, pairs_t;
+};
+
+int kc_check_points(kc_handle* h, const kc_points* p, bool need_bf16_if_asked);
+int kc_plan_gon(kc_handle* h, const std::string& pre, int d,
+                const std::vector<KcGonJob>& jobs, KcGonRun& R, KcGonHost& H);
+void kc_enqueue_gon_stream(const KcGonRun& R, const KcGonHost& H,
+                           const std::vector<KcGonJob>& jobs, hipStream_t s);
+int kc_gonzalez_bf16(kc_handle* h, const kc_points* pts, int64_t k, int64_t first,
+                     int64_t* centers, double* radius_trace, int64_t* n_chosen,
+                     hipStream_t s);

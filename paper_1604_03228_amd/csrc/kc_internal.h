@@ -1,0 +1,61 @@
+// kc_internal.h -- launchers shared between the kernel files and the host
+// library of libkcenter (not part of the public C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kc_device.h"
+
+static inline uint32_t kc_pad64(uint32_t n) { return (n + 63u) & ~63u; }
+
+// Relative error bound of the canonical FP32 squared distance in d
+// dimensions: gamma_{d+2} with u = 2^-24.
+static inline double kc_gamma32(int d)
+{
+    const double u = 5.9604644775390625e-8;
+    const double m = (double)(d + 2);
+    return m * u / (1.0 - m * u);
+}
+
+// Everything the step engines and the finishing kernels of one batched
+// Gonzalez run need (device pointers unless noted).
+struct KcGonRun {
+    int d = 0;
+    int nseg = 0;
+    uint32_t kmax = 0;          // largest ksteps over segments (host)
+    const float* xs = nullptr;  // SoA staging copy
+    uint64_t stride = 0;        // columns per coordinate row
+    float* mind = nullptr;      // [stride]
+    u64* keys = nullptr;        // [sum ksteps]
+    KcSeg* segs = nullptr;      // [nseg]
+    uint32_t* blk_seg = nullptr;
+    uint32_t* blk_start = nullptr;
+    uint32_t nblk = 0;          // tiles of 1024 points (host)
+    uint32_t* pairs_seg = nullptr;  // (segment, step) pairs, one per key
+    uint32_t* pairs_t = nullptr;
+    uint32_t npairs = 0;
+    float* ccoord = nullptr;    // [sum ksteps][d]
+    double* radius2 = nullptr;  // [nseg]
+    u64* cand = nullptr;        // [cand_cap]
+    uint32_t* ncand = nullptr;  // [1]
+    uint32_t cand_cap = 0;
+    double band = 0.0;          // 2 gamma_{d+2} + 4u
+    uint64_t keysum = 0;        // keys in use (host)
+};
+
+void kc_fill_u64(u64* p, u64 v, uint64_t n, hipStream_t s);
+void kc_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+void kc_stage_soa(const float* X, int64_t ld, int d, uint64_t row0, uint32_t len,
+                  float* xs, uint64_t stride, uint64_t base, hipStream_t s);
+void kc_gon_step(const float* xs, uint64_t stride, int d, float* mind, u64* keys,
+                 const KcSeg* segs, const uint32_t* blk_seg, const uint32_t* blk_start,
+                 uint32_t nblk, int t, hipStream_t s);
+int kc_resident_max_blocks(int d);
+uint32_t kc_resident_blocks_for(int d, uint32_t len);
+hipError_t kc_gon_resident(int d, uint32_t G, const float* xs, uint64_t stride,
+                           uint64_t base, uint32_t len, uint32_t first, int k, float* mind,
+                           u64* keys, uint32_t* arrive, uint32_t* abort_flag,
+                           uint32_t spin_limit, hipStream_t s);
+void kc_gon_finish(const KcGonRun& R, int64_t* centers, int64_t* n_chosen, double* trace,
+                   double* radius_out, const int64_t* report_base, hipStream_t s);
+void kc_or_status(const uint32_t* flag, uint32_t* status, uint32_t bit, hipStream_t s);

@@ -1,0 +1,163 @@
+"""GPU parity of kcenter_gonzalez against the FP64 oracle.
+
+Integer-coordinate inputs (exact FP32 squared distances) must match the
+oracle bit for bit: centers, trace and radius.  Float inputs are replayed
+through the oracle: every GPU choice must be a farthest point up to the FP32
+error band 2*gamma_{d+2} (a certified tie), and the final radius -- the exact
+FP64 covering radius of the GPU's centers -- must equal the oracle's value
+for those centers."""
+import numpy as np
+import pytest
+
+from paper_1604_03228_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def band(d):
+    m = d + 2
+    g = m * U32 / (1 - m * U32)
+    return 2 * g + 1e-12
+
+
+@pytest.fixture(scope="module")
+def kc():
+    import paper_1604_03228_amd as kc
+    assert torch.cuda.is_available()
+    return kc
+
+
+def run_gon(kc, X, k, first=0, resident=True, graphs=True):
+    # a non-default stream, so that graph capture is exercised
+    h = kc.Handle(graphs=graphs, resident=resident)
+    Xd = torch.from_numpy(X).cuda()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        c, tr, nch = kc.gonzalez(Xd, k, first, handle=h)
+        assert h.device_status() == 0
+    torch.cuda.synchronize()
+    out = c.cpu().numpy(), tr.cpu().numpy(), int(nch.item())
+    h.close()
+    return out
+
+
+def check_float(orc, X, k, first, c, tr, got):
+    seq = c[:got]
+    bad, ties, otr = orc.gon_replay(X, k, seq, band(X.shape[1]))
+    assert bad == -1, "step %d not a certified farthest point" % bad
+    # final radius: exact FP64 covering radius of the GPU's centers
+    _, R = orc.assign(X, seq)
+    assert tr[got - 1] == R
+    # trace entries: FP64 distance of each chosen point, within the band of
+    # the oracle's maximum along the same sequence
+    rel = np.abs(tr[:got] - otr) / np.maximum(otr, 1e-300)
+    assert np.all(rel <= band(X.shape[1]))
+    assert np.all(tr[got:] == 0)
+    return ties
+
+
+@pytest.mark.parametrize("resident", [True, False])
+def test_config1_uniform(kc, orc, resident):
+    X = W.config1()
+    c, tr, got = run_gon(kc, X, 20, 0, resident=resident)
+    assert got == 20
+    ties = check_float(orc, X, 20, 0, c, tr, got)
+    oc, otr, _ = orc.gon(X, 20, 0)
+    if ties == 0:
+        assert np.array_equal(c, oc)
+    assert abs(tr[-1] - otr[-1]) <= 1e-6 * otr[-1]
+
+
+@pytest.mark.parametrize("n,resident", [(50_000, True), (50_000, False),
+                                        (1_000_000, True), (1_000_000, False)])
+def test_config2_intgrid_bitexact(kc, orc, n, resident):
+    X = W.config2(n)
+    k = 1000 if n == 1_000_000 else 300
+    orc.set_threads(16)
+    oc, otr, og = orc.gon(X, k, 0)
+    c, tr, got = run_gon(kc, X, k, 0, resident=resident)
+    assert got == og
+    assert np.array_equal(c, oc)
+    assert np.array_equal(tr, otr)
+
+
+def test_config2_prefix(kc):
+    X = W.config2(200_000)
+    c1, t1, _ = run_gon(kc, X, 100, 0)
+    c2, t2, _ = run_gon(kc, X, 1000, 0)
+    assert np.array_equal(c1, c2[:100])
+    assert np.array_equal(t1[:99], t2[:99])
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 8, 10, 16, 32, 41, 70])
+@pytest.mark.parametrize("resident", [True, False])
+def test_dims_ragged(kc, orc, d, resident):
+    # n not a multiple of 4, 64 or the tile; generic and unrolled dims
+    rng = np.random.default_rng(100 + d)
+    n = 7_919
+    X = rng.normal(size=(n, d)).astype(np.float32)
+    k = 37
+    c, tr, got = run_gon(kc, X, k, 11, resident=resident)
+    assert got == k and c[0] == 11
+    check_float(orc, X, k, 11, c, tr, got)
+
+
+@pytest.mark.parametrize("resident", [True, False])
+def test_early_stop_duplicates(kc, orc, resident):
+    base = np.random.default_rng(5).integers(0, 9, (13, 3)).astype(np.float32)
+    base = np.unique(base, axis=0)
+    X = np.repeat(base, 40, axis=0)
+    k = 50
+    c, tr, got = run_gon(kc, X, k, 0, resident=resident)
+    oc, otr, og = orc.gon(X, k, 0)
+    assert got == og == len(base)
+    assert np.array_equal(c, oc) and np.array_equal(tr, otr)
+    assert np.all(c[got:] == -1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 1023, 1024, 1025])
+def test_tiny_and_tile_edges(kc, orc, n):
+    X = np.random.default_rng(n).integers(-50, 50, (n, 4)).astype(np.float32)
+    k = min(n + 2, 30)
+    for resident in (True, False):
+        c, tr, got = run_gon(kc, X, k, n // 2, resident=resident)
+        oc, otr, og = orc.gon(X, k, n // 2)
+        assert got == og and np.array_equal(c, oc) and np.array_equal(tr, otr)
+
+
+def test_graphs_off_and_repeat(kc):
+    X = W.config2(100_000)
+    a = run_gon(kc, X, 200, 3, resident=False, graphs=False)
+    b = run_gon(kc, X, 200, 3, resident=False, graphs=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    h = kc.Handle(resident=False)
+    Xd = torch.from_numpy(X).cuda()
+    outs = []
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    for _ in range(3):   # replays of one captured graph, eager work between
+        with torch.cuda.stream(st):
+            c, tr, nch = kc.gonzalez(Xd, 200, 3, handle=h)
+        st.synchronize()
+        outs.append((c.cpu().numpy().copy(), tr.cpu().numpy().copy()))
+        torch.zeros(1000, device="cuda").sum().item()
+    for o in outs:
+        assert np.array_equal(o[0], a[0]) and np.array_equal(o[1], a[1])
+
+
+def test_invalid_arguments(kc):
+    h = kc.Handle()
+    X = torch.zeros(10, 3, device="cuda")
+    with pytest.raises(kc.KCenterError) as e:
+        kc.gonzalez(X, 0, 0, handle=h)
+    assert e.value.status == -1
+    with pytest.raises(kc.KCenterError):
+        kc.gonzalez(X, 3, 10, handle=h)
+    with pytest.raises(kc.KCenterError):
+        kc.gonzalez(X, 3, -1, handle=h)
+    with pytest.raises(ValueError):
+        kc.gonzalez(X.t(), 3, 0, handle=h)
