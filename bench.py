@@ -1,0 +1,191 @@
+"""Benchmark of the k-center hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-mrg]
+
+Workload (one "step"): Gonzalez's traversal with k = 1000 on n = 1,000,000
+synthetic integer-grid points in d = 10 (five coordinates uniform in {1..4},
+five in {1..13}, stored FP32), first center 0, through kcenter_gonzalez:
+staging, all k steps, the FP64 radius trace and the exact FP64 radius.  The
+points are resident in HBM before the timed region.
+
+Prints ONE JSON line: value = n*k distance updates per second over the K
+timed steps, plus
+  roofline      the dominant kernel (live HIP-event timing from the library,
+                on the stream it launches on) against its MI355X peak;
+  cpu_baseline  the FP64 oracle on the host cores (same workload);
+  mrg           two-round MRG on n = 8,000,000, d = 16, m = 64 Dirichlet
+                partitions, k = 200: FP32 vs BF16+rescore wall time and
+                whether the centers agree (when --no-mrg is not given).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP32_VEC_PEAK_TFS = 157.3    # MI355X FP32 vector (dense)
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--k", type=int, default=1000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-mrg", action="store_true")
+    ap.add_argument("--engine", choices=["auto", "stream"], default="auto")
+    return ap.parse_args()
+
+
+def cpu_baseline(X, k):
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    used = oracle.set_threads(cores)
+    t0 = time.perf_counter()
+    oracle.gon(X, k, 0)
+    dt = time.perf_counter() - t0
+    return {"value": len(X) * k / dt, "unit": "dist-updates/s",
+            "cores": used, "kind": "oracle",
+            "sample": "full workload (n=%d, d=%d, k=%d), one run, %.1f s"
+                      % (len(X), X.shape[1], k, dt)}
+
+
+def stored_traffic(kernel, workload):
+    try:
+        t = json.load(open(PROFILE_TRAFFIC))
+        return t.get(kernel + "|" + workload)
+    except (OSError, ValueError):
+        return None
+
+
+def bench_mrg(kc, torch, steps):
+    from paper_1604_03228_amd import workloads as W
+    X, off = W.config3()
+    Xd = torch.from_numpy(X).cuda()
+    B = torch.from_numpy(W.to_bf16_rne(X).view(np.int16)).cuda()
+    k = W.CONFIG3["k"]
+    out = {}
+    cents = {}
+    for mode in ("fp32", "bf16"):
+        h = kc.Handle()
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            bf = B if mode == "bf16" else None
+            for _ in range(2):
+                r = kc.mrg(Xd, off, k, bf16=bf, handle=h)
+            st.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(steps):
+                r = kc.mrg(Xd, off, k, bf16=bf, handle=h)
+            e1.record(st)
+            st.synchronize()
+        out[mode + "_ms"] = e0.elapsed_time(e1) / steps
+        cents[mode] = r[0].cpu().numpy()
+        out[mode + "_radius"] = float(r[2].item())
+        h.close()
+    out["same_centers"] = bool(np.array_equal(cents["fp32"], cents["bf16"]))
+    out["workload"] = "mrg_gauss50_n8000000_d16_m64_k200"
+    out["speedup_bf16"] = out["fp32_ms"] / out["bf16_ms"]
+    return out
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py: this build measures one GPU only (the hot path runs "
+              "on a single MI355X); --gpus %d is not supported" % a.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1604_03228_amd as kc
+    from paper_1604_03228_amd import workloads as W
+
+    n, d, k = 1_000_000, 10, a.k
+    X = W.config2(n)
+    Xd = torch.from_numpy(X).cuda()
+    h = kc.Handle(resident=(a.engine == "auto"))
+    h.set_option("timing", 1)
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    with torch.cuda.stream(st):
+        for _ in range(a.warmup):
+            c, tr, nch = kc.gonzalez(Xd, k, 0, handle=h)
+        st.synchronize()
+        for name in ("gon_resident", "gon_step"):
+            h.timing_read(name)           # drop warm-up spans
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record(st)
+        for _ in range(a.steps):
+            c, tr, nch = kc.gonzalez(Xd, k, 0, handle=h)
+        e1.record(st)
+        st.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1) / a.steps
+    status = h.device_status()
+    if status:
+        raise SystemExit("device status 0x%x" % status)
+    value = n * k / (ms * 1e-3)
+
+    res_ms, res_l, _ = h.timing_read("gon_resident")
+    stp_ms, stp_l, _ = h.timing_read("gon_step")
+    if res_l > 0:
+        kern = "k_gon_resident"
+        per = res_ms / res_l
+        flops = n * k * 3 * d             # sub + fma per coordinate
+        ach = flops / (per * 1e-3) / 1e12
+        roof = {"kernel": kern, "bound": "alu", "achieved": ach,
+                "peak": FP32_VEC_PEAK_TFS, "unit": "TFLOP/s",
+                "frac": ach / FP32_VEC_PEAK_TFS,
+                "avg_launch_ms": per, "launches": res_l,
+                "work_per_launch": "%d updates x %d flop" % (n * k, 3 * d)}
+    else:
+        kern = "k_gon_step"
+        per = stp_ms / stp_l
+        byt = n * (4 * d + 8)             # read d coords + mind, write mind
+        ach = byt / (per * 1e-3) / 1e9
+        roof = {"kernel": kern, "bound": "hbm", "achieved": ach,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS,
+                "avg_launch_ms": per, "launches": stp_l,
+                "work_per_launch": "%d points x %d B" % (n, 4 * d + 8)}
+    roof["traffic"] = stored_traffic(kern, "gon_intgrid_n1000000_d10_k%d" % k)
+
+    line = {"metric": "n*k dist-updates/s (Gonzalez, 1 GPU)",
+            "value": value, "unit": "dist-updates/s", "n_gpus": 1,
+            "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms,
+            "wall_s": wall, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic (seeded integer grid, stands in for the "
+                    "Poker Hand schema)",
+            "config": {"workload": "gon_intgrid_n1000000_d10_k%d" % k,
+                       "n": n, "d": d, "k": k, "first": 0,
+                       "engine": kern},
+            "roofline": roof}
+    h.close()
+    if not a.no_mrg:
+        try:
+            line["mrg"] = bench_mrg(kc, torch, max(2, min(a.steps, 5)))
+        except kc.KCenterError as e:
+            line["mrg"] = {"error": str(e)}
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(X, k)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

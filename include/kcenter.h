@@ -73,9 +73,23 @@ const char* kc_last_error(const kc_handle* h);
 
 /* Options (name, value): "graphs" 0/1 (capture per-step launches in a HIP
  * graph, default 1); "resident" 0/1 (use the register-resident persistent
- * Gonzalez kernel when the points fit, default 1).  KC_EINVAL for an unknown
- * name. */
+ * Gonzalez kernel when the points fit, default 1); "timing" 0/1 (record
+ * kernel timing events, default 0); "spin_limit" (polls before a persistent
+ * kernel's barrier wait gives up, default 2^24).  KC_EINVAL for an unknown
+ * name or a value out of range. */
 int kc_set_option(kc_handle* h, const char* name, int64_t value);
+
+/* Kernel timing.  With option "timing" = 1 every call records a pair of HIP
+ * events on its stream around its dominant kernel or launch sequence, under
+ * one of the names "gon_resident" (persistent Gonzalez, 1 launch),
+ * "gon_step" (k streaming step launches), "gon_bf16" (BF16 stream steps),
+ * "mrg_round1" (MRG first-round step launches), "assign_mfma" (the MFMA
+ * distance kernel of an assignment), "eim_dist" (EIM distance passes).
+ * kc_timing_read synchronises the device, returns the summed milliseconds,
+ * the number of kernel launches those intervals cover and the number of
+ * intervals, for one name, and forgets them.  KC_EINVAL for NULL args. */
+int kc_timing_read(kc_handle* h, const char* name, double* ms, int64_t* launches,
+                   int64_t* intervals);
 
 /* Synchronises `stream`, then reads and clears the handle's device status
  * word (bit 0: a persistent kernel's grid barrier timed out; bit 1: a

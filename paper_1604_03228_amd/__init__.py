@@ -55,7 +55,8 @@ class KCenterError(RuntimeError):
 
 
 EXPORTS = ["kc_create", "kc_destroy", "kc_strerror", "kc_last_error",
-           "kc_set_option", "kc_device_status", "kcenter_gonzalez",
+           "kc_set_option", "kc_device_status", "kc_timing_read",
+           "kcenter_gonzalez",
            "kcenter_mrg", "kcenter_assign", "kcenter_eim", "kcenter_batch"]
 
 _lib = None
@@ -79,6 +80,9 @@ def load_library(path=LIB_PATH):
     L.kc_last_error.restype = ctypes.c_char_p
     L.kc_set_option.argtypes = [_p, ctypes.c_char_p, _i64]
     L.kc_device_status.argtypes = [_p, _p, ctypes.POINTER(ctypes.c_uint32)]
+    L.kc_timing_read.argtypes = [_p, ctypes.c_char_p,
+                                 ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
     L.kcenter_gonzalez.argtypes = [_p, ctypes.POINTER(KcPoints), _i64, _i64,
                                    _p, _p, _p, _p]
     L.kcenter_mrg.argtypes = [_p, ctypes.POINTER(KcPoints), _p, _i32, _i64,
@@ -91,6 +95,7 @@ def load_library(path=LIB_PATH):
                               ctypes.POINTER(_i32), _p]
     L.kcenter_batch.argtypes = [_p, _p, _i32, _p]
     for name in ("kc_create", "kc_set_option", "kc_device_status",
+                 "kc_timing_read",
                  "kcenter_gonzalez", "kcenter_mrg", "kcenter_assign",
                  "kcenter_eim", "kcenter_batch"):
         getattr(L, name).restype = ctypes.c_int
@@ -138,6 +143,17 @@ class Handle:
     def set_option(self, name, value):
         self._check(load_library().kc_set_option(self._h, name.encode(),
                                                  int(value)))
+
+    def timing_read(self, name):
+        """(milliseconds, kernel launches, intervals) recorded under `name`
+        since the last read (needs option timing=1); synchronises."""
+        ms = ctypes.c_double(0)
+        la = _i64(0)
+        iv = _i64(0)
+        self._check(load_library().kc_timing_read(
+            self._h, name.encode(), ctypes.byref(ms), ctypes.byref(la),
+            ctypes.byref(iv)))
+        return ms.value, la.value, iv.value
 
     def device_status(self):
         """Synchronise the current stream and read/clear the status word."""

@@ -21,8 +21,45 @@
 kc_handle::~kc_handle()
 {
     clear_graphs();
+    for (auto& kv : spans)
+        for (auto& sp : kv.second) {
+            hipEventDestroy(sp.a);
+            hipEventDestroy(sp.b);
+        }
+    for (hipEvent_t e : event_pool) hipEventDestroy(e);
     for (auto& kv : bufs) hipFree(kv.second.p);
     if (status_word) hipFree(status_word);
+}
+
+hipEvent_t kc_handle::span_begin(hipStream_t s)
+{
+    if (!timing) return nullptr;
+    hipEvent_t e = nullptr;
+    if (!event_pool.empty()) {
+        e = event_pool.back();
+        event_pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    hipEventRecord(e, s);
+    return e;
+}
+
+void kc_handle::span_end(const char* name, hipEvent_t a, int64_t launches, hipStream_t s)
+{
+    if (!timing || !a) return;
+    hipEvent_t b = nullptr;
+    if (!event_pool.empty()) {
+        b = event_pool.back();
+        event_pool.pop_back();
+    } else if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipGetLastError();
+        event_pool.push_back(a);
+        return;
+    }
+    hipEventRecord(b, s);
+    spans[name].push_back(TimedSpan{a, b, launches});
 }
 
 void kc_handle::clear_graphs()
@@ -192,11 +229,14 @@ int kc_plan_gon(kc_handle* h, const std::string& pre, int d,
     R.xs = xs;
     R.mind = (float*)h->ws(pre + "mind", sizeof(float) * stride);
     R.keys = (u64*)h->ws(pre + "keys", sizeof(u64) * std::max<uint64_t>(keyoff, 1));
+    R.part = (u64*)h->ws(pre + "part", sizeof(u64) * KC_PARTS * KC_PSTRIDE *
+                                           std::max<uint64_t>(keyoff, 1));
     R.ccoord = (float*)h->ws(pre + "ccoord", sizeof(float) * (size_t)d * std::max<uint64_t>(keyoff, 1));
     R.radius2 = (double*)h->ws(pre + "radius2", sizeof(double) * nseg);
     R.cand = (u64*)h->ws(pre + "cand", sizeof(u64) * R.cand_cap);
     R.ncand = (uint32_t*)h->ws(pre + "ncand", sizeof(uint32_t));
-    if (!R.xs || !R.mind || !R.keys || !R.ccoord || !R.radius2 || !R.cand || !R.ncand)
+    if (!R.xs || !R.mind || !R.keys || !R.part || !R.ccoord || !R.radius2 || !R.cand ||
+        !R.ncand)
         return h->fail(KC_ENOMEM, "workspace allocation failed");
     R.segs = (KcSeg*)h->upload(pre + "segs", H.segs.data(), sizeof(KcSeg) * nseg);
     R.blk_seg = (uint32_t*)h->upload(pre + "blk_seg", H.blk_seg.data(), 4 * H.blk_seg.size());
@@ -209,19 +249,42 @@ int kc_plan_gon(kc_handle* h, const std::string& pre, int d,
     return KC_OK;
 }
 
-// Enqueue staging + init + all steps (streaming engine) of a planned run.
-void kc_enqueue_gon_stream(const KcGonRun& R, const KcGonHost& H,
-                           const std::vector<KcGonJob>& jobs, hipStream_t s)
+// Enqueue staging + init of a planned run (streaming engine).
+void kc_enqueue_gon_prep(const KcGonRun& R, const KcGonHost& H,
+                         const std::vector<KcGonJob>& jobs, hipStream_t s)
 {
     for (size_t q = 0; q < jobs.size(); ++q)
         if (jobs[q].X)
             kc_stage_soa(jobs[q].X, jobs[q].ld, R.d, jobs[q].row0, jobs[q].len, (float*)R.xs,
                          R.stride, H.segs[q].base, s);
     kc_fill_u32((uint32_t*)R.mind, 0x7F800000u, R.stride, s);   // +inf
-    kc_fill_u64(R.keys, 0ull, R.keysum, s);
+    kc_fill_u64(R.part, 0ull, R.keysum * KC_PARTS * KC_PSTRIDE, s);
+}
+
+// Enqueue all step launches of a planned run (streaming engine).
+void kc_enqueue_gon_steps(const KcGonRun& R, hipStream_t s)
+{
     for (uint32_t t = 0; t < R.kmax; ++t)
-        kc_gon_step(R.xs, R.stride, R.d, R.mind, R.keys, R.segs, R.blk_seg, R.blk_start,
+        kc_gon_step(R.xs, R.stride, R.d, R.mind, R.part, R.segs, R.blk_seg, R.blk_start,
                     R.nblk, (int)t, s);
+    kc_part_collect(R.part, R.keys, R.keysum, s);
+}
+
+// Prep, steps and finish of a streaming run as three cached graphs; the
+// steps graph is bracketed by a timing span called `span`.
+int kc_run_gon_stream(kc_handle* h, const std::string& key, const KcGonRun& R,
+                      const KcGonHost& H, const std::vector<KcGonJob>& jobs,
+                      const char* span, hipStream_t s,
+                      const std::function<void(hipStream_t)>& finish)
+{
+    int rc = h->run_graph(key + ":prep", s,
+                          [&](hipStream_t st) { kc_enqueue_gon_prep(R, H, jobs, st); });
+    if (rc) return rc;
+    hipEvent_t ev = h->span_begin(s);
+    rc = h->run_graph(key + ":steps", s, [&](hipStream_t st) { kc_enqueue_gon_steps(R, st); });
+    h->span_end(span, ev, R.kmax, s);
+    if (rc) return rc;
+    return h->run_graph(key + ":finish", s, finish);
 }
 
 // ---------------------------------------------------------------------------
@@ -289,12 +352,45 @@ int kc_set_option(kc_handle* h, const char* name, int64_t value)
         h->allow_resident = value != 0;
         return KC_OK;
     }
+    if (!strcmp(name, "timing")) {
+        h->timing = value != 0;
+        return KC_OK;
+    }
     if (!strcmp(name, "spin_limit")) {
         if (value < 1 || value > 0x7FFFFFFF) return h->fail(KC_EINVAL, "spin_limit range");
         h->spin_limit = (uint32_t)value;
         return KC_OK;
     }
     return h->fail(KC_EINVAL, "unknown option '%s'", name);
+}
+
+int kc_timing_read(kc_handle* h, const char* name, double* ms, int64_t* launches,
+                   int64_t* intervals)
+{
+    if (!h || !name || !ms || !launches || !intervals) return KC_EINVAL;
+    *ms = 0.0;
+    *launches = 0;
+    *intervals = 0;
+    auto it = h->spans.find(name);
+    if (it == h->spans.end()) return KC_OK;
+    if (hipDeviceSynchronize() != hipSuccess) {
+        hipError_t e = hipGetLastError();
+        return h->fail(KC_EHIP, "timing sync: %s", hipGetErrorString(e));
+    }
+    for (auto& sp : it->second) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, sp.a, sp.b) == hipSuccess) {
+            *ms += t;
+            *launches += sp.launches;
+            *intervals += 1;
+        } else {
+            (void)hipGetLastError();
+        }
+        h->event_pool.push_back(sp.a);
+        h->event_pool.push_back(sp.b);
+    }
+    h->spans.erase(it);
+    return KC_OK;
 }
 
 int kc_device_status(kc_handle* h, void* stream, uint32_t* status)
@@ -337,18 +433,21 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
         const uint32_t G = kc_resident_blocks_for(pts->d, (uint32_t)pts->n);
         const int Gmax = G ? h->resident_max(pts->d) : 0;
         if (G > 0 && (int)G <= Gmax) {
-            uint32_t* arrive = (uint32_t*)h->ws("g.arrive", sizeof(uint32_t) * (size_t)k);
+            const uint64_t bw = kc_resident_slot_words((int)k, G);
+            u64* bar = (u64*)h->ws("g.bar", sizeof(u64) * bw);
             uint32_t* abort_flag = (uint32_t*)h->ws("g.abort", 64);
-            if (!arrive || !abort_flag) return h->fail(KC_ENOMEM, "workspace allocation failed");
+            if (!bar || !abort_flag) return h->fail(KC_ENOMEM, "workspace allocation failed");
             kc_stage_soa(pts->f32, pts->ld, pts->d, 0, (uint32_t)pts->n, (float*)R.xs,
                          R.stride, 0, s);
             kc_fill_u32((uint32_t*)R.mind, 0x7F800000u, R.stride, s);
             kc_fill_u64(R.keys, 0ull, R.keysum, s);
-            kc_fill_u32(arrive, 0u, (uint64_t)k, s);
+            kc_fill_u64(bar, 0ull, bw, s);
             kc_fill_u32(abort_flag, 0u, 1, s);
+            hipEvent_t ev = h->span_begin(s);
             hipError_t e = kc_gon_resident(pts->d, G, R.xs, R.stride, 0, (uint32_t)pts->n,
-                                           (uint32_t)first, (int)k, R.mind, R.keys, arrive,
+                                           (uint32_t)first, (int)k, R.mind, R.keys, bar,
                                            abort_flag, h->spin_limit, s);
+            h->span_end("gon_resident", ev, 1, s);
             if (e == hipSuccess) {
                 kc_or_status(abort_flag, h->status_word, 1u, s);
                 kc_gon_finish(R, centers, n_chosen, radius_trace, nullptr, nullptr, s);
@@ -364,8 +463,7 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
     snprintf(key, sizeof key, "gon:%p:%lld:%d:%lld:%lld:%lld:%p:%p:%p", (const void*)pts->f32,
              (long long)pts->n, pts->d, (long long)pts->ld, (long long)k, (long long)first,
              (void*)centers, (void*)radius_trace, (void*)n_chosen);
-    return h->run_graph(key, s, [&](hipStream_t st) {
-        kc_enqueue_gon_stream(R, H, jobs, st);
+    return kc_run_gon_stream(h, key, R, H, jobs, "gon_step", s, [&](hipStream_t st) {
         kc_gon_finish(R, centers, n_chosen, radius_trace, nullptr, nullptr, st);
     });
 }

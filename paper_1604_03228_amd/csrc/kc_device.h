@@ -79,6 +79,45 @@ __device__ __forceinline__ u64 kc_block_max64(u64 v, u64* red)
     return r;
 }
 
+// Partial argmax slots of a streaming step.  Many blocks meeting at one
+// 64-bit atomic serialise at the memory side, so each step's key is split
+// over KC_PARTS slots on separate 128-byte lines (block b uses slot b mod
+// KC_PARTS); the step's key is the max over its slots.
+#define KC_PARTS 16
+#define KC_PSTRIDE 16   // u64 per slot: one 128-byte line
+__device__ __forceinline__ u64* kc_part_slot(u64* part, uint64_t key, uint32_t slot)
+{
+    return part + (key * KC_PARTS + slot) * KC_PSTRIDE;
+}
+
+// Max over the KC_PARTS slots of one key, computed by the first wave of the
+// block; the result is valid in every thread.  `red` holds one u64.
+__device__ __forceinline__ u64 kc_part_reduce(const u64* part, uint64_t key, u64* red)
+{
+    if (threadIdx.x < 64) {
+        u64 v = 0;
+        if (threadIdx.x < KC_PARTS)
+            v = __hip_atomic_load(part + (key * KC_PARTS + threadIdx.x) * KC_PSTRIDE,
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v = kc_wave_max64(v);
+        if (threadIdx.x == 0) *red = v;
+    }
+    __syncthreads();
+    u64 r = *red;
+    __syncthreads();
+    return r;
+}
+
+// Offer a block's key to its slot: skip the atomic when the slot already
+// holds a larger key (a stale read is never larger than the true value, so
+// skipping is always safe).
+__device__ __forceinline__ void kc_part_offer(u64* part, uint64_t key, uint32_t slot, u64 v)
+{
+    u64* p = kc_part_slot(part, key, slot);
+    u64 cur = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (v > cur) __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ double kc_wave_min_f64(double v)
 {
 #pragma unroll

@@ -100,40 +100,52 @@ void kc_stage_soa(const float* X, int64_t ld, int d, uint64_t row0, uint32_t len
 template <int D>
 __global__ __launch_bounds__(KC_BLOCK) void k_gon_step(
     const float* __restrict__ xs, uint64_t stride, int d_rt,
-    float* __restrict__ mind, u64* __restrict__ keys,
+    float* __restrict__ mind, u64* __restrict__ part,
     const KcSeg* __restrict__ segs, const uint32_t* __restrict__ blk_seg,
     const uint32_t* __restrict__ blk_start, int t)
 {
     const int d = D > 0 ? D : d_rt;
-    __shared__ float cc[KC_MAXD];
     __shared__ u64 red[KC_BLOCK / 64];
     const uint32_t b = blockIdx.x;
     const KcSeg sg = segs[blk_seg[b]];
     if ((uint32_t)t >= sg.ksteps) return;
+    const uint32_t loc = blk_start[b] + threadIdx.x * KC_STEP_PTS;
+    const uint64_t col = sg.base + loc;
+    const bool live = loc < sg.len;
+
+    // issue this lane's point and min-distance loads before resolving the
+    // center, so their latency overlaps the key reduction
+    float4 v[D > 0 ? D : 1];
+    float4 m = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (D > 0 && live) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = *(const float4*)(xs + (uint64_t)j * stride + col);
+    }
+    if (live) m = *(const float4*)(mind + col);
+
+    // newest center: max over the previous step's partial keys, reduced by
+    // every wave on its own (uniform across the block, no barrier needed)
     uint32_t c;
     if (t == 0) {
         c = sg.first;
     } else {
-        u64 prev = keys[sg.keyoff + t - 1];
-        if ((prev >> 32) == 0) return;   // radius reached 0: segment finished
-        c = kc_key_idx(prev);
+        const int lane = threadIdx.x & 63;
+        u64 pv = 0;
+        if (lane < KC_PARTS)
+            pv = __hip_atomic_load(kc_part_slot(part, sg.keyoff + t - 1, lane),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        pv = kc_wave_max64(pv);
+        if ((pv >> 32) == 0) return;   // radius reached 0: segment finished
+        c = __builtin_amdgcn_readfirstlane(kc_key_idx(pv));
     }
-    for (int j = threadIdx.x; j < d; j += KC_BLOCK)
-        cc[j] = xs[(uint64_t)j * stride + sg.base + c];
-    __syncthreads();
+    const float* xc = xs + sg.base + c;   // uniform: scalar loads
 
-    const uint32_t loc = blk_start[b] + threadIdx.x * KC_STEP_PTS;
-    const uint64_t col = sg.base + loc;
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-    if (loc < sg.len) {
+    if (live) {
         if (D > 0) {
-            float4 v[D > 0 ? D : 1];
-#pragma unroll
-            for (int j = 0; j < D; ++j)
-                v[j] = *(const float4*)(xs + (uint64_t)j * stride + col);
 #pragma unroll
             for (int j = 0; j < D; ++j) {
-                const float cj = cc[j];
+                const float cj = xc[(uint64_t)j * stride];
                 s0 = kc_d32_step(s0, v[j].x, cj);
                 s1 = kc_d32_step(s1, v[j].y, cj);
                 s2 = kc_d32_step(s2, v[j].z, cj);
@@ -142,18 +154,17 @@ __global__ __launch_bounds__(KC_BLOCK) void k_gon_step(
         } else {
 #pragma unroll 4
             for (int j = 0; j < d; ++j) {
-                float4 v = *(const float4*)(xs + (uint64_t)j * stride + col);
-                const float cj = cc[j];
-                s0 = kc_d32_step(s0, v.x, cj);
-                s1 = kc_d32_step(s1, v.y, cj);
-                s2 = kc_d32_step(s2, v.z, cj);
-                s3 = kc_d32_step(s3, v.w, cj);
+                const float4 w = *(const float4*)(xs + (uint64_t)j * stride + col);
+                const float cj = xc[(uint64_t)j * stride];
+                s0 = kc_d32_step(s0, w.x, cj);
+                s1 = kc_d32_step(s1, w.y, cj);
+                s2 = kc_d32_step(s2, w.z, cj);
+                s3 = kc_d32_step(s3, w.w, cj);
             }
         }
     }
     u64 key = 0;
-    if (loc < sg.len) {
-        float4 m = *(float4*)(mind + col);
+    if (live) {
         m.x = fminf(m.x, s0);
         m.y = fminf(m.y, s1);
         m.z = fminf(m.z, s2);
@@ -165,16 +176,37 @@ __global__ __launch_bounds__(KC_BLOCK) void k_gon_step(
         if (loc + 3 < sg.len) key = kc_umax64(key, kc_pack(m.w, loc + 3));
     }
     key = kc_block_max64(key, red);
-    if (threadIdx.x == 0) atomicMax(&keys[sg.keyoff + t], key);
+    if (threadIdx.x == 0) kc_part_offer(part, sg.keyoff + t, b % KC_PARTS, key);
+}
+
+// keys[q] = max over the partial slots of key q, for every key of a run.
+__global__ void k_part_collect(const u64* __restrict__ part, u64* __restrict__ keys,
+                               uint64_t nkeys)
+{
+    const uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (q >= nkeys) return;
+    u64 v = 0;
+    for (uint32_t s = 0; s < KC_PARTS; ++s) {
+        const u64 x = part[(q * KC_PARTS + s) * KC_PSTRIDE];
+        v = x > v ? x : v;
+    }
+    keys[q] = v;
+}
+
+void kc_part_collect(const u64* part, u64* keys, uint64_t nkeys, hipStream_t s)
+{
+    if (nkeys == 0) return;
+    hipLaunchKernelGGL(k_part_collect, dim3((unsigned)((nkeys + 255) / 256)), dim3(256), 0, s,
+                       part, keys, nkeys);
 }
 
 #define KC_STEP_CASE(DD)                                                          \
     case DD:                                                                      \
         hipLaunchKernelGGL(k_gon_step<DD>, dim3(nblk), dim3(KC_BLOCK), 0, s, xs,  \
-                           stride, d, mind, keys, segs, blk_seg, blk_start, t);   \
+                           stride, d, mind, part, segs, blk_seg, blk_start, t);   \
         break;
 
-void kc_gon_step(const float* xs, uint64_t stride, int d, float* mind, u64* keys,
+void kc_gon_step(const float* xs, uint64_t stride, int d, float* mind, u64* part,
                  const KcSeg* segs, const uint32_t* blk_seg, const uint32_t* blk_start,
                  uint32_t nblk, int t, hipStream_t s)
 {
@@ -188,209 +220,60 @@ void kc_gon_step(const float* xs, uint64_t stride, int d, float* mind, u64* keys
         KC_STEP_CASE(41)
     default:
         hipLaunchKernelGGL(k_gon_step<0>, dim3(nblk), dim3(KC_BLOCK), 0, s, xs, stride,
-                           d, mind, keys, segs, blk_seg, blk_start, t);
+                           d, mind, part, segs, blk_seg, blk_start, t);
     }
-}
-
-// ---------------------------------------------------------------------------
-// resident persistent engine: one segment, G blocks, PPT points per thread.
-// Thread (g, tid) owns local points i = g*KC_BLOCK*PPT + p*KC_BLOCK + tid.
-// arrive[t] counts blocks that finished step t; abort is raised by any block
-// whose wait exceeds the spin limit, which ends every block's loop.
-
-template <int D, int PPT>
-__global__ __launch_bounds__(KC_BLOCK, 1) void k_gon_resident(
-    const float* __restrict__ xs, uint64_t stride, uint64_t base, uint32_t len,
-    uint32_t first, int k, float* __restrict__ mind, u64* __restrict__ keys,
-    uint32_t* __restrict__ arrive, uint32_t* __restrict__ abort_flag,
-    uint32_t spin_limit)
-{
-    __shared__ float cc[D];
-    __shared__ u64 red[KC_BLOCK / 64];
-    __shared__ u64 bkey;
-    const uint32_t G = gridDim.x;
-    const uint32_t i0 = blockIdx.x * (KC_BLOCK * PPT) + threadIdx.x;
-
-    float x[PPT][D];
-    float m[PPT];
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-        const uint32_t i = i0 + p * KC_BLOCK;
-        const uint32_t ii = i < len ? i : 0;
-#pragma unroll
-        for (int j = 0; j < D; ++j) x[p][j] = xs[(uint64_t)j * stride + base + ii];
-        m[p] = __builtin_inff();
-    }
-
-    uint32_t c = first;
-    int t = 0;
-    for (; t < k; ++t) {
-        if (threadIdx.x < D) cc[threadIdx.x] = xs[(uint64_t)threadIdx.x * stride + base + c];
-        __syncthreads();
-        u64 key = 0;
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-            float s = 0.f;
-#pragma unroll
-            for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[p][j], cc[j]);
-            m[p] = fminf(m[p], s);
-            const uint32_t i = i0 + p * KC_BLOCK;
-            if (i < len) key = kc_umax64(key, kc_pack(m[p], i));
-        }
-        key = kc_block_max64(key, red);
-        if (threadIdx.x == 0) {
-            __hip_atomic_fetch_max(&keys[t], key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&arrive[t], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            uint32_t spins = 0;
-            while (__hip_atomic_load(&arrive[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < G) {
-                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                    break;
-                if (++spins > spin_limit) {
-                    __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-            __atomic_thread_fence(__ATOMIC_ACQUIRE);
-            u64 kk = __hip_atomic_load(&keys[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-                kk = 0;   // abandon: makes every block leave the loop
-            bkey = kk;
-        }
-        __syncthreads();
-        const u64 kk = bkey;
-        __syncthreads();
-        if ((kk >> 32) == 0) break;   // radius 0 (or abort): stop
-        c = kc_key_idx(kk);
-    }
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-        const uint32_t i = i0 + p * KC_BLOCK;
-        if (i < len) mind[base + i] = m[p];
-    }
-}
-
-// Largest points-per-thread whose coordinates fit in about 192 VGPRs.
-static int resident_ppt(int d)
-{
-    switch (d) {
-    case 2: return 32;
-    case 3: return 32;
-    case 8: return 16;
-    case 10: return 16;
-    case 16: return 8;
-    case 32: return 4;
-    case 41: return 4;
-    default: return 0;
-    }
-}
-
-uint64_t kc_resident_capacity(int d, int max_blocks)
-{
-    return (uint64_t)resident_ppt(d) * KC_BLOCK * (uint64_t)max_blocks;
-}
-
-template <int D, int PPT>
-static hipError_t launch_resident(uint32_t G, const float* xs, uint64_t stride,
-                                  uint64_t base, uint32_t len, uint32_t first, int k,
-                                  float* mind, u64* keys, uint32_t* arrive,
-                                  uint32_t* abort_flag, uint32_t spin_limit, hipStream_t s)
-{
-    void* args[] = {(void*)&xs,   (void*)&stride, (void*)&base,  (void*)&len,
-                    (void*)&first, (void*)&k,     (void*)&mind,  (void*)&keys,
-                    (void*)&arrive, (void*)&abort_flag, (void*)&spin_limit};
-    return hipLaunchCooperativeKernel((const void*)k_gon_resident<D, PPT>, dim3(G),
-                                      dim3(KC_BLOCK), args, 0, s);
-}
-
-template <int D, int PPT>
-static int max_resident_blocks()
-{
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gon_resident<D, PPT>,
-                                                     KC_BLOCK, 0) != hipSuccess)
-        return 0;
-    int dev = 0, cus = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    return per_cu * cus;
-}
-
-int kc_resident_max_blocks(int d)
-{
-    switch (d) {
-    case 2: return max_resident_blocks<2, 32>();
-    case 3: return max_resident_blocks<3, 32>();
-    case 8: return max_resident_blocks<8, 16>();
-    case 10: return max_resident_blocks<10, 16>();
-    case 16: return max_resident_blocks<16, 8>();
-    case 32: return max_resident_blocks<32, 4>();
-    case 41: return max_resident_blocks<41, 4>();
-    default: return 0;
-    }
-}
-
-// Returns hipSuccess, or an error when the shape has no resident kernel or
-// the grid cannot be co-resident (the caller then streams instead).
-hipError_t kc_gon_resident(int d, uint32_t G, const float* xs, uint64_t stride,
-                           uint64_t base, uint32_t len, uint32_t first, int k, float* mind,
-                           u64* keys, uint32_t* arrive, uint32_t* abort_flag,
-                           uint32_t spin_limit, hipStream_t s)
-{
-    switch (d) {
-#define KC_RES_CASE(DD, PP)                                                              \
-    case DD:                                                                             \
-        return launch_resident<DD, PP>(G, xs, stride, base, len, first, k, mind, keys,   \
-                                       arrive, abort_flag, spin_limit, s);
-        KC_RES_CASE(2, 32)
-        KC_RES_CASE(3, 32)
-        KC_RES_CASE(8, 16)
-        KC_RES_CASE(10, 16)
-        KC_RES_CASE(16, 8)
-        KC_RES_CASE(32, 4)
-        KC_RES_CASE(41, 4)
-#undef KC_RES_CASE
-    default:
-        return hipErrorInvalidValue;
-    }
-}
-
-uint32_t kc_resident_blocks_for(int d, uint32_t len)
-{
-    const uint64_t per = (uint64_t)resident_ppt(d) * KC_BLOCK;
-    if (per == 0) return 0;
-    return (uint32_t)((len + per - 1) / per);
 }
 
 // ---------------------------------------------------------------------------
 // finishing: per segment n_chosen, centers, center coordinates, FP64 trace
 // and exact FP64 radius.
 
-// One thread per segment: n_chosen = first step whose key reached radius 0
-// (+1), else ksteps; centers[keyoff + t] = reported index or -1.
-__global__ void k_gon_finish_centers(const KcSeg* __restrict__ segs, int nseg,
-                                     const u64* __restrict__ keys,
-                                     int64_t* __restrict__ centers,
-                                     int64_t* __restrict__ n_chosen,
-                                     const int64_t* __restrict__ report_base,
-                                     uint32_t kmax)
+// n_chosen of a segment = 1 + the first step whose key reached radius 0, else
+// ksteps (0 for an empty segment): initialised per segment, then lowered by
+// one thread per (segment, step).
+__global__ void k_gon_nchosen_init(const KcSeg* __restrict__ segs, int nseg,
+                                   int64_t* __restrict__ n_chosen)
 {
     int sidx = blockIdx.x * blockDim.x + threadIdx.x;
     if (sidx >= nseg) return;
     const KcSeg sg = segs[sidx];
-    uint32_t nch = 0;
-    if (sg.len > 0 && sg.ksteps > 0) {
-        nch = sg.ksteps;
-        for (uint32_t t = 0; t < sg.ksteps; ++t)
-            if ((keys[sg.keyoff + t] >> 32) == 0) { nch = t + 1; break; }
+    n_chosen[sidx] = (sg.len > 0) ? (int64_t)sg.ksteps : 0;
+}
+
+__global__ void k_gon_nchosen_min(const KcSeg* __restrict__ segs,
+                                  const uint32_t* __restrict__ pairs_seg,
+                                  const uint32_t* __restrict__ pairs_t, uint32_t npairs,
+                                  const u64* __restrict__ keys, int64_t* __restrict__ n_chosen)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npairs) return;
+    const uint32_t sidx = pairs_seg[q];
+    const KcSeg sg = segs[sidx];
+    const uint32_t t = pairs_t[q];
+    if ((keys[sg.keyoff + t] >> 32) == 0)
+        atomicMin((long long*)&n_chosen[sidx], (long long)(t + 1));
+}
+
+// centers[keyoff + t] = reported index of center t, or -1 past n_chosen.
+__global__ void k_gon_centers_out(const KcSeg* __restrict__ segs,
+                                  const uint32_t* __restrict__ pairs_seg,
+                                  const uint32_t* __restrict__ pairs_t, uint32_t npairs,
+                                  const u64* __restrict__ keys,
+                                  const int64_t* __restrict__ n_chosen,
+                                  const int64_t* __restrict__ report_base,
+                                  int64_t* __restrict__ centers)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npairs) return;
+    const uint32_t sidx = pairs_seg[q];
+    const KcSeg sg = segs[sidx];
+    const uint32_t t = pairs_t[q];
+    int64_t v = -1;
+    if ((int64_t)t < n_chosen[sidx]) {
+        const int64_t rb = report_base ? report_base[sidx] : 0;
+        v = rb + (int64_t)(t == 0 ? sg.first : kc_key_idx(keys[sg.keyoff + t - 1]));
     }
-    const int64_t rb = report_base ? report_base[sidx] : 0;
-    for (uint32_t t = 0; t < kmax && t < sg.ksteps; ++t) {
-        int64_t v = -1;
-        if (t < nch) v = rb + (int64_t)(t == 0 ? sg.first : kc_key_idx(keys[sg.keyoff + t - 1]));
-        centers[sg.keyoff + t] = v;
-    }
-    n_chosen[sidx] = nch;
+    centers[sg.keyoff + t] = v;
 }
 
 // ccoord[(keyoff + t) * d + j] = coordinate j of center t (FP32, compact).
@@ -538,8 +421,15 @@ void kc_gon_finish(const KcGonRun& R, int64_t* centers, int64_t* n_chosen,
                    hipStream_t s)
 {
     const int nseg = R.nseg;
-    hipLaunchKernelGGL(k_gon_finish_centers, dim3((nseg + 63) / 64), dim3(64), 0, s, R.segs,
-                       nseg, R.keys, centers, n_chosen, report_base, R.kmax);
+    const dim3 pg((R.npairs + 255) / 256);
+    hipLaunchKernelGGL(k_gon_nchosen_init, dim3((nseg + 63) / 64), dim3(64), 0, s, R.segs,
+                       nseg, n_chosen);
+    if (R.npairs > 0) {
+        hipLaunchKernelGGL(k_gon_nchosen_min, pg, dim3(256), 0, s, R.segs, R.pairs_seg,
+                           R.pairs_t, R.npairs, R.keys, n_chosen);
+        hipLaunchKernelGGL(k_gon_centers_out, pg, dim3(256), 0, s, R.segs, R.pairs_seg,
+                           R.pairs_t, R.npairs, R.keys, n_chosen, report_base, centers);
+    }
     hipLaunchKernelGGL(k_gon_gather_centers, dim3((R.npairs + 255) / 256), dim3(256), 0, s,
                        R.segs, R.pairs_seg, R.pairs_t, R.npairs, R.xs, R.stride, R.d, R.keys,
                        R.ccoord);

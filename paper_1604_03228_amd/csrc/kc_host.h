@@ -34,8 +34,18 @@ struct kc_handle {
     std::map<std::string, void*> shadow_ptr;
     std::map<std::string, GraphEntry> graphs;
     std::map<int, int> resident_cache;
+    bool timing = false;
+    struct TimedSpan {
+        hipEvent_t a, b;
+        int64_t launches;
+    };
+    std::map<std::string, std::vector<TimedSpan>> spans;
+    std::vector<hipEvent_t> event_pool;
 
     ~kc_handle();
+    // Record the opening event of a timed span (no-op unless timing is on).
+    hipEvent_t span_begin(hipStream_t s);
+    void span_end(const char* name, hipEvent_t a, int64_t launches, hipStream_t s);
     void clear_graphs();
     int fail(int code, const char* fmt, ...);
     void* ws(const std::string& name, size_t bytes);
@@ -64,8 +74,13 @@ struct KcGonHost {
 int kc_check_points(kc_handle* h, const kc_points* p, bool need_bf16_if_asked);
 int kc_plan_gon(kc_handle* h, const std::string& pre, int d,
                 const std::vector<KcGonJob>& jobs, KcGonRun& R, KcGonHost& H);
-void kc_enqueue_gon_stream(const KcGonRun& R, const KcGonHost& H,
-                           const std::vector<KcGonJob>& jobs, hipStream_t s);
+void kc_enqueue_gon_prep(const KcGonRun& R, const KcGonHost& H,
+                         const std::vector<KcGonJob>& jobs, hipStream_t s);
+void kc_enqueue_gon_steps(const KcGonRun& R, hipStream_t s);
+int kc_run_gon_stream(kc_handle* h, const std::string& key, const KcGonRun& R,
+                      const KcGonHost& H, const std::vector<KcGonJob>& jobs,
+                      const char* span, hipStream_t s,
+                      const std::function<void(hipStream_t)>& finish);
 int kc_gonzalez_bf16(kc_handle* h, const kc_points* pts, int64_t k, int64_t first,
                      int64_t* centers, double* radius_trace, int64_t* n_chosen,
                      hipStream_t s);

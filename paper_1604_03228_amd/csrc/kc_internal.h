@@ -27,6 +27,7 @@ struct KcGonRun {
     uint64_t stride = 0;        // columns per coordinate row
     float* mind = nullptr;      // [stride]
     u64* keys = nullptr;        // [sum ksteps]
+    u64* part = nullptr;        // [sum ksteps][KC_PARTS][KC_PSTRIDE] partial keys
     KcSeg* segs = nullptr;      // [nseg]
     uint32_t* blk_seg = nullptr;
     uint32_t* blk_start = nullptr;
@@ -47,14 +48,16 @@ void kc_fill_u64(u64* p, u64 v, uint64_t n, hipStream_t s);
 void kc_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 void kc_stage_soa(const float* X, int64_t ld, int d, uint64_t row0, uint32_t len,
                   float* xs, uint64_t stride, uint64_t base, hipStream_t s);
-void kc_gon_step(const float* xs, uint64_t stride, int d, float* mind, u64* keys,
+void kc_part_collect(const u64* part, u64* keys, uint64_t nkeys, hipStream_t s);
+uint64_t kc_resident_slot_words(int k, uint32_t G);
+void kc_gon_step(const float* xs, uint64_t stride, int d, float* mind, u64* part,
                  const KcSeg* segs, const uint32_t* blk_seg, const uint32_t* blk_start,
                  uint32_t nblk, int t, hipStream_t s);
 int kc_resident_max_blocks(int d);
 uint32_t kc_resident_blocks_for(int d, uint32_t len);
 hipError_t kc_gon_resident(int d, uint32_t G, const float* xs, uint64_t stride,
                            uint64_t base, uint32_t len, uint32_t first, int k, float* mind,
-                           u64* keys, uint32_t* arrive, uint32_t* abort_flag,
+                           u64* keys, u64* slots, uint32_t* abort_flag,
                            uint32_t spin_limit, hipStream_t s);
 void kc_gon_finish(const KcGonRun& R, int64_t* centers, int64_t* n_chosen, double* trace,
                    double* radius_out, const int64_t* report_base, hipStream_t s);
