@@ -182,7 +182,7 @@ int kc_check_points(kc_handle* h, const kc_points* p, bool need_bf16_if_asked)
 // ---------------------------------------------------------------------------
 // batched Gonzalez planning
 
-int kc_plan_gon(kc_handle* h, const std::string& pre, int d,
+int kc_plan_gon(kc_handle* h, const std::string& pre, int d, uint32_t tile,
                 const std::vector<KcGonJob>& jobs, KcGonRun& R, KcGonHost& H)
 {
     const int nseg = (int)jobs.size();
@@ -202,7 +202,7 @@ int kc_plan_gon(kc_handle* h, const std::string& pre, int d,
         sg.first = j.first;
         sg.ksteps = j.len == 0 ? 0 : j.k;
         sg.keyoff = (uint32_t)keyoff;
-        for (uint32_t st = 0; st < j.len; st += KC_BLOCK * 4) {
+        for (uint32_t st = 0; st < j.len; st += tile) {
             H.blk_seg.push_back((uint32_t)s);
             H.blk_start.push_back(st);
         }
@@ -222,6 +222,7 @@ int kc_plan_gon(kc_handle* h, const std::string& pre, int d,
     R.kmax = kmax;
     R.stride = stride;
     R.nblk = (uint32_t)H.blk_seg.size();
+    R.tile = tile;
     R.npairs = (uint32_t)H.pairs_seg.size();
     R.band = 2.0 * kc_gamma32(d) + 4.0 * 5.9604644775390625e-8;
     R.cand_cap = (uint32_t)std::max<uint64_t>(total, 1);
@@ -425,7 +426,7 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
     jobs[0] = KcGonJob{pts->f32, pts->ld, 0, (uint32_t)pts->n, (uint32_t)first, (uint32_t)k};
     KcGonRun R;
     KcGonHost H;
-    rc = kc_plan_gon(h, "g.", pts->d, jobs, R, H);
+    rc = kc_plan_gon(h, "g.", pts->d, 1024, jobs, R, H);
     if (rc) return rc;
 
     // register-resident persistent kernel when the whole problem fits
@@ -444,13 +445,13 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
             kc_fill_u64(bar, 0ull, bw, s);
             kc_fill_u32(abort_flag, 0u, 1, s);
             hipEvent_t ev = h->span_begin(s);
-            hipError_t e = kc_gon_resident(pts->d, G, R.xs, R.stride, 0, (uint32_t)pts->n,
+            hipError_t e = kc_gon_resident(pts->d, G, R.xs, R.stride, 0, (uint32_t)pts->n, nullptr,
                                            (uint32_t)first, (int)k, R.mind, R.keys, bar,
                                            abort_flag, h->spin_limit, s);
             h->span_end("gon_resident", ev, 1, s);
             if (e == hipSuccess) {
                 kc_or_status(abort_flag, h->status_word, 1u, s);
-                kc_gon_finish(R, centers, n_chosen, radius_trace, nullptr, nullptr, s);
+                kc_gon_finish(R, centers, n_chosen, radius_trace, nullptr, nullptr, nullptr, s);
                 e = hipGetLastError();
                 return e == hipSuccess ? KC_OK
                                        : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
@@ -464,7 +465,7 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
              (long long)pts->n, pts->d, (long long)pts->ld, (long long)k, (long long)first,
              (void*)centers, (void*)radius_trace, (void*)n_chosen);
     return kc_run_gon_stream(h, key, R, H, jobs, "gon_step", s, [&](hipStream_t st) {
-        kc_gon_finish(R, centers, n_chosen, radius_trace, nullptr, nullptr, st);
+        kc_gon_finish(R, centers, n_chosen, radius_trace, nullptr, nullptr, nullptr, st);
     });
 }
 

@@ -46,6 +46,27 @@ __device__ __forceinline__ double kc_d64_step(double s, double x, double c)
     return __dadd_rn(s, sq);
 }
 
+// Correctly rounded FP64 square root (reported radii must equal a host
+// sqrt bit for bit).  The hardware-assisted sqrt is within an ulp; Tuckerman's
+// test then fixes the last bit: y = RN(sqrt(x)) iff y*pred(y) < x <=
+// y*succ(y), and the signs of x - y*y' are exact through one FMA.
+__device__ __forceinline__ double kc_sqrt_rn(double x)
+{
+    if (!(x > 0.0) || x == __builtin_inf()) return __builtin_sqrt(x);
+    double y = __builtin_sqrt(x);
+    for (int it = 0; it < 3; ++it) {
+        const long long b = __double_as_longlong(y);
+        const double yd = __longlong_as_double(b - 1), yu = __longlong_as_double(b + 1);
+        if (__fma_rn(-y, yd, x) <= 0.0)
+            y = yd;
+        else if (__fma_rn(-y, yu, x) > 0.0)
+            y = yu;
+        else
+            break;
+    }
+    return y;
+}
+
 __device__ __forceinline__ u64 kc_pack(float v, uint32_t idx)
 {
     return ((u64)__float_as_uint(v) << 32) | (u64)(0xFFFFFFFFu - idx);

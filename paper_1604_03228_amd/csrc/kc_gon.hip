@@ -261,6 +261,7 @@ __global__ void k_gon_centers_out(const KcSeg* __restrict__ segs,
                                   const u64* __restrict__ keys,
                                   const int64_t* __restrict__ n_chosen,
                                   const int64_t* __restrict__ report_base,
+                                  const int64_t* __restrict__ remap,
                                   int64_t* __restrict__ centers)
 {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -270,8 +271,11 @@ __global__ void k_gon_centers_out(const KcSeg* __restrict__ segs,
     const uint32_t t = pairs_t[q];
     int64_t v = -1;
     if ((int64_t)t < n_chosen[sidx]) {
-        const int64_t rb = report_base ? report_base[sidx] : 0;
-        v = rb + (int64_t)(t == 0 ? sg.first : kc_key_idx(keys[sg.keyoff + t - 1]));
+        const uint32_t loc = t == 0 ? sg.first : kc_key_idx(keys[sg.keyoff + t - 1]);
+        if (remap)
+            v = remap[sg.src + loc];
+        else
+            v = (report_base ? report_base[sidx] : 0) + (int64_t)loc;
     }
     centers[sg.keyoff + t] = v;
 }
@@ -332,7 +336,7 @@ __global__ void k_gon_trace(const KcSeg* __restrict__ segs,
         best = fmin(best, s);
     }
     best = kc_wave_min_f64(best);
-    if (lane == 0) trace[sg.keyoff + t] = sqrt(best);
+    if (lane == 0) trace[sg.keyoff + t] = kc_sqrt_rn(best);
 }
 
 // Candidates for the exact radius: every point whose FP32 min-distance is at
@@ -411,14 +415,15 @@ __global__ void k_gon_radius_finish(const KcSeg* __restrict__ segs, int nseg,
     if (sidx >= nseg) return;
     const KcSeg sg = segs[sidx];
     const int64_t nch = n_chosen[sidx];
-    const double r = sqrt(radius2[sidx]);
+    const double r = kc_sqrt_rn(radius2[sidx]);
     if (nch > 0 && trace) trace[sg.keyoff + nch - 1] = r;
     if (radius_out) radius_out[sidx] = nch > 0 ? r : 0.0;
 }
 
-void kc_gon_finish(const KcGonRun& R, int64_t* centers, int64_t* n_chosen,
-                   double* trace, double* radius_out, const int64_t* report_base,
-                   hipStream_t s)
+void kc_gon_finish_impl(const KcGonRun& R, int64_t* centers, int64_t* n_chosen,
+                        double* trace, double* radius_out, const int64_t* report_base,
+                        const int64_t* remap, bool gather, hipStream_t s,
+                        const std::function<void(hipStream_t)>& radius_cand)
 {
     const int nseg = R.nseg;
     const dim3 pg((R.npairs + 255) / 256);
@@ -428,22 +433,35 @@ void kc_gon_finish(const KcGonRun& R, int64_t* centers, int64_t* n_chosen,
         hipLaunchKernelGGL(k_gon_nchosen_min, pg, dim3(256), 0, s, R.segs, R.pairs_seg,
                            R.pairs_t, R.npairs, R.keys, n_chosen);
         hipLaunchKernelGGL(k_gon_centers_out, pg, dim3(256), 0, s, R.segs, R.pairs_seg,
-                           R.pairs_t, R.npairs, R.keys, n_chosen, report_base, centers);
+                           R.pairs_t, R.npairs, R.keys, n_chosen, report_base, remap,
+                           centers);
+        if (gather)
+            hipLaunchKernelGGL(k_gon_gather_centers, pg, dim3(256), 0, s, R.segs, R.pairs_seg,
+                               R.pairs_t, R.npairs, R.xs, R.stride, R.d, R.keys, R.ccoord);
+        if (trace)
+            hipLaunchKernelGGL(k_gon_trace, dim3((R.npairs + 3) / 4), dim3(256), 0, s, R.segs,
+                               R.pairs_seg, R.pairs_t, R.npairs, R.d, n_chosen, R.ccoord,
+                               trace);
     }
-    hipLaunchKernelGGL(k_gon_gather_centers, dim3((R.npairs + 255) / 256), dim3(256), 0, s,
-                       R.segs, R.pairs_seg, R.pairs_t, R.npairs, R.xs, R.stride, R.d, R.keys,
-                       R.ccoord);
-    if (trace)
-        hipLaunchKernelGGL(k_gon_trace, dim3((R.npairs + 3) / 4), dim3(256), 0, s, R.segs,
-                           R.pairs_seg, R.pairs_t, R.npairs, R.d, n_chosen, R.ccoord, trace);
     kc_fill_u32(R.ncand, 0u, 1, s);
     kc_fill_u64((u64*)R.radius2, 0ull, (uint64_t)nseg, s);
-    hipLaunchKernelGGL(k_gon_radius_cand, dim3(R.nblk), dim3(KC_BLOCK), 0, s, R.segs,
-                       R.blk_seg, R.blk_start, R.mind, R.keys, n_chosen, R.band, R.cand,
-                       R.ncand, R.cand_cap);
+    if (R.nblk > 0) radius_cand(s);
     hipLaunchKernelGGL(k_gon_radius_rescore, dim3(1024), dim3(256), 0, s, R.segs, R.cand,
                        R.ncand, R.cand_cap, R.xs, R.stride, R.d, n_chosen, R.ccoord,
                        R.radius2);
     hipLaunchKernelGGL(k_gon_radius_finish, dim3((nseg + 63) / 64), dim3(64), 0, s, R.segs,
                        nseg, n_chosen, R.radius2, trace, radius_out);
+}
+
+void kc_gon_finish(const KcGonRun& R, int64_t* centers, int64_t* n_chosen,
+                   double* trace, double* radius_out, const int64_t* report_base,
+                   const int64_t* remap, hipStream_t s)
+{
+    kc_gon_finish_impl(R, centers, n_chosen, trace, radius_out, report_base, remap, true, s,
+                       [&](hipStream_t st) {
+                           hipLaunchKernelGGL(k_gon_radius_cand, dim3(R.nblk), dim3(KC_BLOCK),
+                                              0, st, R.segs, R.blk_seg, R.blk_start, R.mind,
+                                              R.keys, n_chosen, R.band, R.cand, R.ncand,
+                                              R.cand_cap);
+                       });
 }

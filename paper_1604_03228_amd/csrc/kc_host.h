@@ -63,6 +63,7 @@ struct KcGonJob {
     uint32_t len = 0;
     uint32_t first = 0;        // local index of the first center
     uint32_t k = 0;
+    const uint16_t* Xb = nullptr;  // BF16 source rows (BF16 mode)
 };
 
 // Host copies of a run's tables.
@@ -72,7 +73,7 @@ struct KcGonHost {
 };
 
 int kc_check_points(kc_handle* h, const kc_points* p, bool need_bf16_if_asked);
-int kc_plan_gon(kc_handle* h, const std::string& pre, int d,
+int kc_plan_gon(kc_handle* h, const std::string& pre, int d, uint32_t tile,
                 const std::vector<KcGonJob>& jobs, KcGonRun& R, KcGonHost& H);
 void kc_enqueue_gon_prep(const KcGonRun& R, const KcGonHost& H,
                          const std::vector<KcGonJob>& jobs, hipStream_t s);
@@ -81,6 +82,21 @@ int kc_run_gon_stream(kc_handle* h, const std::string& key, const KcGonRun& R,
                       const KcGonHost& H, const std::vector<KcGonJob>& jobs,
                       const char* span, hipStream_t s,
                       const std::function<void(hipStream_t)>& finish);
+// BF16 stream engine (kc_bf16.hip)
+void kc_enqueue_bf16_prep(const KcGonRun& R, const KcBf16Run& B, const KcGonHost& H,
+                          const std::vector<KcGonJob>& jobs, hipStream_t s);
+void kc_enqueue_bf16_steps(const KcGonRun& R, const KcBf16Run& B, hipStream_t s);
+void kc_bf16_finish(const KcGonRun& R, const KcBf16Run& B, int64_t* centers,
+                    int64_t* n_chosen, double* trace, double* radius_out,
+                    const int64_t* report_base, hipStream_t s);
+int kc_bf16_alloc(kc_handle* h, const std::string& pre, const KcGonRun& R, KcBf16Run& B);
+int kc_run_bf16(kc_handle* h, const std::string& key, const KcGonRun& R, const KcBf16Run& B,
+                const KcGonHost& H, const std::vector<KcGonJob>& jobs, const char* span,
+                hipStream_t s, const std::function<void(hipStream_t)>& finish);
+int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, uint32_t k,
+                  const int64_t* k_dev, int32_t* labels, double* radius, hipStream_t s,
+                  const std::string& pre);
+
 int kc_gonzalez_bf16(kc_handle* h, const kc_points* pts, int64_t k, int64_t first,
                      int64_t* centers, double* radius_trace, int64_t* n_chosen,
                      hipStream_t s);

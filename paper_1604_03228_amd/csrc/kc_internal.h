@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+
 #include "kc_device.h"
 
 static inline uint32_t kc_pad64(uint32_t n) { return (n + 63u) & ~63u; }
@@ -42,6 +44,7 @@ struct KcGonRun {
     uint32_t cand_cap = 0;
     double band = 0.0;          // 2 gamma_{d+2} + 4u
     uint64_t keysum = 0;        // keys in use (host)
+    uint32_t tile = 1024;       // points per step block (host)
 };
 
 void kc_fill_u64(u64* p, u64 v, uint64_t n, hipStream_t s);
@@ -56,9 +59,49 @@ void kc_gon_step(const float* xs, uint64_t stride, int d, float* mind, u64* part
 int kc_resident_max_blocks(int d);
 uint32_t kc_resident_blocks_for(int d, uint32_t len);
 hipError_t kc_gon_resident(int d, uint32_t G, const float* xs, uint64_t stride,
-                           uint64_t base, uint32_t len, uint32_t first, int k, float* mind,
+                           uint64_t base, uint32_t len, const uint32_t* len_ptr,
+                           uint32_t first, int k, float* mind,
                            u64* keys, u64* slots, uint32_t* abort_flag,
                            uint32_t spin_limit, hipStream_t s);
 void kc_gon_finish(const KcGonRun& R, int64_t* centers, int64_t* n_chosen, double* trace,
-                   double* radius_out, const int64_t* report_base, hipStream_t s);
+                   double* radius_out, const int64_t* report_base, const int64_t* remap,
+                   hipStream_t s);
+// The finishing sequence with a caller-supplied radius-candidate launch;
+// `gather` copies the chosen centers' coordinates from the SoA staging copy.
+void kc_gon_finish_impl(const KcGonRun& R, int64_t* centers, int64_t* n_chosen,
+                        double* trace, double* radius_out, const int64_t* report_base,
+                        const int64_t* remap, bool gather, hipStream_t s,
+                        const std::function<void(hipStream_t)>& radius_cand);
+
+// BF16 stream state (kc_bf16.hip); tiles of KC_BLOCK*8 points.
+struct KcBf16Run {
+    uint16_t* xb = nullptr;       // SoA BF16 copy [d][stride]
+    float* ex = nullptr;          // [stride] per-point BF16 rounding radius
+    uint32_t* lpart = nullptr;    // [sum ksteps][KC_PARTS][32] max lower bound
+    float* blk_hi = nullptr;      // [nblk] max upper bound per block
+    float* exm = nullptr;         // [stride] cached exact FP32 min-distance
+    uint32_t* exupto = nullptr;   // [stride] centers covered by exm
+    uint32_t* ncand = nullptr;    // [kmax] candidates per step
+    uint32_t rescore_blocks = 256;
+    float g = 0.f;                // gamma_{d+2} + 16u
+};
+#define KC_BF_TILE_PTS (KC_BLOCK * 8)
 void kc_or_status(const uint32_t* flag, uint32_t* status, uint32_t bit, hipStream_t s);
+
+// MFMA nearest-center distances (kc_assign.hip)
+int kc_mindist_ksteps(int d, bool bf);
+int kc_mindist_dpad(int d, bool bf);
+void kc_mindist(const float* X, const uint16_t* Xb, int64_t ld, uint32_t n, int d,
+                const float* Cf, const uint16_t* Cb, const float* cnorm, uint32_t kpad,
+                int32_t* arg, float* m1, float* m2, float* nx, hipStream_t s);
+void kc_stage_centers(const float* X, const uint16_t* Xb, int64_t ld, int d, uint32_t n,
+                      const int64_t* idx, const uint32_t* idx32, uint32_t k,
+                      const int64_t* k_dev, uint32_t kpad, int dp, float* Cf, uint16_t* Cb,
+                      float* cnorm, float* cmax, uint32_t* status, hipStream_t s);
+void kc_bf16_err(const float* X, const uint16_t* Xb, int64_t ld, int d, uint32_t n, float* ex,
+                 hipStream_t s);
+void kc_assign_finish(uint32_t n, int d, const float* X, int64_t ld, const float* Cf, int dp,
+                      uint32_t k, const int64_t* k_dev, const int32_t* arg, const float* m1,
+                      const float* m2, const float* nx, const float* ex, const float* cmax,
+                      int32_t* labels, float* hi, uint32_t* list, uint32_t* nlist,
+                      float* lo_max, double* radius2, double* radius_out, hipStream_t s);

@@ -1,0 +1,332 @@
+// kc_mrg.hip -- two-round MRG (Algorithm 1, one pass of its loop), the BF16
+// Gonzalez entry, and the assignment entry point.
+//
+// MRG on the device, without host synchronisation:
+//   round 1   all m partitions are segments of one batched Gonzalez run
+//             (FP32 stream, or BF16 stream + exact FP32 rescoring);
+//   union     k_mrg_union sorts each partition's centers (global indices)
+//             by rank and concatenates them in partition order, which is
+//             ascending global order because partitions are contiguous row
+//             ranges; it also writes the union size into round 2's segment
+//             table, so round 2's kernels see the true length;
+//   round 2   Gonzalez on the gathered union (register-resident when it
+//             fits, else streamed), first center = smallest index;
+//   radius    the MFMA assignment of every point to the final centers.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "kc_host.h"
+
+// One block per partition p: its n_p centers (distinct global indices),
+// ranked by value, land at uni[off_p + rank], off_p = sum_{q<p} n_q.
+__global__ void k_mrg_union(const int64_t* __restrict__ cent, const int64_t* __restrict__ nch,
+                            int m, int k, int64_t* __restrict__ uni,
+                            int64_t* __restrict__ n_union, uint32_t* __restrict__ seg_len)
+{
+    const int p = blockIdx.x;
+    __shared__ int64_t off;
+    if (threadIdx.x == 0) {
+        int64_t o = 0;
+        for (int q = 0; q < p; ++q) o += nch[q];
+        off = o;
+        if (p == m - 1) {
+            const int64_t tot = o + nch[p];
+            *n_union = tot;
+            *seg_len = (uint32_t)tot;
+        }
+    }
+    __syncthreads();
+    const int64_t np = nch[p];
+    const int64_t* c = cent + (int64_t)p * k;
+    for (int64_t i = threadIdx.x; i < np; i += blockDim.x) {
+        const int64_t v = c[i];
+        int64_t r = 0;
+        for (int64_t j = 0; j < np; ++j) r += c[j] < v;
+        uni[off + r] = v;
+    }
+}
+
+// SoA copy of the listed rows: column i <- row uni[i] (padding repeats uni[0]).
+__global__ void k_gather_soa(const float* __restrict__ X, int64_t ld, int d,
+                             const int64_t* __restrict__ uni, const int64_t* __restrict__ nu,
+                             uint32_t padded, float* __restrict__ xs, uint64_t stride)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= padded) return;
+    const int64_t cnt = *nu;
+    const uint64_t r = (uint64_t)((int64_t)i < cnt ? uni[i] : uni[0]);
+    for (int j = 0; j < d; ++j) xs[(uint64_t)j * stride + i] = X[r * ld + j];
+}
+
+static std::string kc_key(const char* tag, std::initializer_list<const void*> ptrs,
+                          std::initializer_list<long long> vals)
+{
+    std::string s(tag);
+    char b[40];
+    for (const void* p : ptrs) {
+        snprintf(b, sizeof b, ":%p", p);
+        s += b;
+    }
+    for (long long v : vals) {
+        snprintf(b, sizeof b, ":%lld", v);
+        s += b;
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// BF16 engine buffers for a planned run
+
+int kc_bf16_alloc(kc_handle* h, const std::string& pre, const KcGonRun& R, KcBf16Run& B)
+{
+    B.xb = (uint16_t*)h->ws(pre + "xb", sizeof(uint16_t) * (size_t)R.d * R.stride);
+    B.ex = (float*)h->ws(pre + "ex", sizeof(float) * R.stride);
+    B.lpart = (uint32_t*)h->ws(pre + "lpart", sizeof(uint32_t) * KC_PARTS * 32 *
+                                                  std::max<uint64_t>(R.keysum, 1));
+    B.blk_hi = (float*)h->ws(pre + "blkhi", sizeof(float) * std::max<uint32_t>(R.nblk, 1));
+    B.exm = (float*)h->ws(pre + "exm", sizeof(float) * R.stride);
+    B.exupto = (uint32_t*)h->ws(pre + "exupto", sizeof(uint32_t) * R.stride);
+    B.ncand = (uint32_t*)h->ws(pre + "ncand", sizeof(uint32_t) * std::max<uint32_t>(R.kmax, 1));
+    if (!B.xb || !B.ex || !B.lpart || !B.blk_hi || !B.exm || !B.exupto || !B.ncand)
+        return h->fail(KC_ENOMEM, "workspace allocation failed");
+    const double u = 5.9604644775390625e-8;
+    B.g = (float)((kc_gamma32(R.d) + 16.0 * u) * (1.0 + 1e-6));
+    B.rescore_blocks = 256;
+    return KC_OK;
+}
+
+// prep / steps (timed under `span`) / finish graphs of a BF16 run
+int kc_run_bf16(kc_handle* h, const std::string& key, const KcGonRun& R, const KcBf16Run& B,
+                const KcGonHost& H, const std::vector<KcGonJob>& jobs, const char* span,
+                hipStream_t s, const std::function<void(hipStream_t)>& finish)
+{
+    int rc = h->run_graph(key + ":prep", s,
+                          [&](hipStream_t st) { kc_enqueue_bf16_prep(R, B, H, jobs, st); });
+    if (rc) return rc;
+    hipEvent_t ev = h->span_begin(s);
+    rc = h->run_graph(key + ":steps", s, [&](hipStream_t st) { kc_enqueue_bf16_steps(R, B, st); });
+    h->span_end(span, ev, 3 * (int64_t)R.kmax, s);
+    if (rc) return rc;
+    return h->run_graph(key + ":finish", s, finish);
+}
+
+int kc_gonzalez_bf16(kc_handle* h, const kc_points* pts, int64_t k, int64_t first,
+                     int64_t* centers, double* radius_trace, int64_t* n_chosen, hipStream_t s)
+{
+    std::vector<KcGonJob> jobs(1);
+    jobs[0].X = pts->f32;
+    jobs[0].Xb = pts->bf16;
+    jobs[0].ld = pts->ld;
+    jobs[0].row0 = 0;
+    jobs[0].len = (uint32_t)pts->n;
+    jobs[0].first = (uint32_t)first;
+    jobs[0].k = (uint32_t)k;
+    KcGonRun R;
+    KcGonHost H;
+    int rc = kc_plan_gon(h, "g.", pts->d, KC_BF_TILE_PTS, jobs, R, H);
+    if (rc) return rc;
+    KcBf16Run B;
+    rc = kc_bf16_alloc(h, "gb.", R, B);
+    if (rc) return rc;
+    const std::string key = kc_key("gonbf", {pts->f32, pts->bf16, centers, radius_trace, n_chosen},
+                                   {pts->n, pts->d, pts->ld, k, first});
+    return kc_run_bf16(h, key, R, B, H, jobs, "gon_bf16", s, [&](hipStream_t st) {
+        kc_bf16_finish(R, B, centers, n_chosen, radius_trace, nullptr, nullptr, st);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// assignment
+
+int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, uint32_t k,
+                  const int64_t* k_dev, int32_t* labels, double* radius, hipStream_t s,
+                  const std::string& pre)
+{
+    const bool bf = pts->prec == KC_BF16_RESCORE;
+    const uint32_t n = (uint32_t)pts->n;
+    const int d = pts->d;
+    const int dp = kc_mindist_dpad(d, bf);
+    const uint32_t kpad = (k + 15u) & ~15u;
+    float* Cf = (float*)h->ws(pre + "cf", sizeof(float) * (size_t)kpad * dp);
+    uint16_t* Cb = bf ? (uint16_t*)h->ws(pre + "cb", sizeof(uint16_t) * (size_t)kpad * dp)
+                      : nullptr;
+    float* cnorm = (float*)h->ws(pre + "cn", sizeof(float) * kpad);
+    float* cmax = (float*)h->ws(pre + "cmax", 16);
+    int32_t* arg = (int32_t*)h->ws(pre + "arg", sizeof(int32_t) * n);
+    float* m1 = (float*)h->ws(pre + "m1", sizeof(float) * n);
+    float* m2 = (float*)h->ws(pre + "m2", sizeof(float) * n);
+    float* nx = (float*)h->ws(pre + "nx", sizeof(float) * n);
+    float* hi = (float*)h->ws(pre + "hi", sizeof(float) * n);
+    uint32_t* list = (uint32_t*)h->ws(pre + "list", sizeof(uint32_t) * 2 * (size_t)n);
+    uint32_t* nlist = (uint32_t*)h->ws(pre + "nlist", 16);
+    float* lo_max = (float*)h->ws(pre + "lomax", 16);
+    double* r2 = (double*)h->ws(pre + "r2", 16);
+    float* ex = bf ? (float*)h->ws(pre + "ex", sizeof(float) * n) : nullptr;
+    if (!Cf || (bf && !Cb) || !cnorm || !cmax || !arg || !m1 || !m2 || !nx || !hi || !list ||
+        !nlist || !lo_max || !r2 || (bf && !ex))
+        return h->fail(KC_ENOMEM, "workspace allocation failed");
+    const std::string key =
+        kc_key("assign", {pts->f32, pts->bf16, centers, k_dev, labels, radius},
+               {pts->n, d, pts->ld, k, bf, (long long)(pre.size() ? pre[0] : 0)});
+    int rc = h->run_graph(key + ":stage", s, [&](hipStream_t st) {
+        if (bf) kc_bf16_err(pts->f32, pts->bf16, pts->ld, d, n, ex, st);
+        kc_stage_centers(pts->f32, bf ? pts->bf16 : nullptr, pts->ld, d, n, centers, nullptr, k,
+                         k_dev, kpad, dp, Cf, Cb, cnorm, cmax, h->status_word, st);
+    });
+    if (rc) return rc;
+    hipEvent_t ev = h->span_begin(s);
+    rc = h->run_graph(key + ":mfma", s, [&](hipStream_t st) {
+        kc_mindist(pts->f32, bf ? pts->bf16 : nullptr, pts->ld, n, d, Cf, Cb, cnorm, kpad, arg, m1,
+                   m2, nx, st);
+    });
+    h->span_end("assign_mfma", ev, 1, s);
+    if (rc) return rc;
+    return h->run_graph(key + ":finish", s, [&](hipStream_t st) {
+        kc_assign_finish(n, d, pts->f32, pts->ld, Cf, dp, k, k_dev, arg, m1, m2, nx, ex, cmax,
+                         labels, hi, list, nlist, lo_max, r2, radius, st);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// public entry points
+
+extern "C" {
+
+int kcenter_assign(kc_handle* h, const kc_points* pts, const int64_t* centers, int64_t k,
+                   int32_t* labels, double* radius, void* stream)
+{
+    if (!h) return KC_EINVAL;
+    int rc = kc_check_points(h, pts, true);
+    if (rc) return rc;
+    if (k < 1 || k >= (1 << 24)) return h->fail(KC_EINVAL, "k=%lld out of range", (long long)k);
+    if (!centers || !radius) return h->fail(KC_EINVAL, "centers/radius NULL");
+    return kc_assign_run(h, pts, centers, (uint32_t)k, nullptr, labels, radius,
+                         (hipStream_t)stream, "a.");
+}
+
+int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int32_t m,
+                int64_t k, int64_t* centers, int64_t* n_centers, double* radius,
+                int64_t* round1, double* r1, int64_t* uni, int64_t* n_union, double* r2,
+                void* stream)
+{
+    if (!h) return KC_EINVAL;
+    int rc = kc_check_points(h, pts, true);
+    if (rc) return rc;
+    if (m < 1) return h->fail(KC_EINVAL, "m=%d", m);
+    if (!offsets) return h->fail(KC_EINVAL, "offsets NULL");
+    if (offsets[0] != 0 || offsets[m] != pts->n)
+        return h->fail(KC_EINVAL, "offsets must start at 0 and end at n");
+    for (int p = 0; p < m; ++p)
+        if (offsets[p + 1] < offsets[p]) return h->fail(KC_EINVAL, "offsets not monotone");
+    if (k < 1 || k >= (1 << 24)) return h->fail(KC_EINVAL, "k=%lld out of range", (long long)k);
+    if ((int64_t)m * k >= (int64_t)0xFFFFFFFFll) return h->fail(KC_EINVAL, "m*k too large");
+    if (!centers || !n_centers || !radius) return h->fail(KC_EINVAL, "outputs NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const bool bf = pts->prec == KC_BF16_RESCORE;
+    const int d = pts->d;
+
+    // ---- round 1: every partition is a segment of one run
+    std::vector<KcGonJob> jobs(m);
+    for (int p = 0; p < m; ++p) {
+        jobs[p].X = pts->f32;
+        jobs[p].Xb = pts->bf16;
+        jobs[p].ld = pts->ld;
+        jobs[p].row0 = (uint64_t)offsets[p];
+        jobs[p].len = (uint32_t)(offsets[p + 1] - offsets[p]);
+        jobs[p].first = 0;
+        jobs[p].k = (uint32_t)k;
+    }
+    KcGonRun R1;
+    KcGonHost H1;
+    rc = kc_plan_gon(h, "m1.", d, bf ? KC_BF_TILE_PTS : 1024, jobs, R1, H1);
+    if (rc) return rc;
+    const int64_t* rb =
+        (const int64_t*)h->upload("m1.rb", offsets, sizeof(int64_t) * (size_t)m);
+    int64_t* cent1 = round1 ? round1 : (int64_t*)h->ws("m1.cent", sizeof(int64_t) * m * k);
+    int64_t* nch1 = (int64_t*)h->ws("m1.nch", sizeof(int64_t) * m);
+    double* rad1 = r1 ? r1 : (double*)h->ws("m1.rad", sizeof(double) * m);
+    if (!rb || !cent1 || !nch1 || !rad1) return h->fail(KC_ENOMEM, "workspace allocation failed");
+    const std::string key1 = kc_key("mrg1", {pts->f32, pts->bf16, cent1, rad1},
+                                    {pts->n, d, pts->ld, k, m, bf});
+    auto finish1 = [&](hipStream_t st) {
+        kc_fill_u64((u64*)cent1, ~0ull, (uint64_t)m * k, st);
+        kc_gon_finish(R1, cent1, nch1, nullptr, rad1, rb, nullptr, st);
+    };
+    if (bf) {
+        KcBf16Run B1;
+        rc = kc_bf16_alloc(h, "m1b.", R1, B1);
+        if (rc) return rc;
+        rc = kc_run_bf16(h, key1, R1, B1, H1, jobs, "mrg_round1", s, [&](hipStream_t st) {
+            kc_fill_u64((u64*)cent1, ~0ull, (uint64_t)m * k, st);
+            kc_bf16_finish(R1, B1, cent1, nch1, nullptr, rad1, rb, st);
+        });
+    } else {
+        rc = kc_run_gon_stream(h, key1, R1, H1, jobs, "mrg_round1", s, finish1);
+    }
+    if (rc) return rc;
+
+    // ---- union and round 2
+    const uint64_t cap = std::min<uint64_t>((uint64_t)m * k, (uint64_t)pts->n);
+    std::vector<KcGonJob> jobs2(1);
+    jobs2[0].X = nullptr;   // filled by the gather kernel
+    jobs2[0].ld = pts->ld;
+    jobs2[0].len = (uint32_t)cap;
+    jobs2[0].first = 0;
+    jobs2[0].k = (uint32_t)k;
+    KcGonRun R2;
+    KcGonHost H2;
+    rc = kc_plan_gon(h, "m2.", d, 1024, jobs2, R2, H2);
+    if (rc) return rc;
+    int64_t* uni_b = uni ? uni : (int64_t*)h->ws("m2.uni", sizeof(int64_t) * cap);
+    int64_t* nu = n_union ? n_union : (int64_t*)h->ws("m2.nu", 16);
+    double* r2b = r2 ? r2 : (double*)h->ws("m2.r2", 16);
+    if (!uni_b || !nu || !r2b) return h->fail(KC_ENOMEM, "workspace allocation failed");
+    uint32_t* len_ptr = (uint32_t*)((char*)R2.segs + offsetof(KcSeg, len));
+    const std::string key2 = kc_key("mrg2", {pts->f32, cent1, uni_b, nu, centers, n_centers, r2b},
+                                    {pts->n, d, pts->ld, k, m});
+    rc = h->run_graph(key2 + ":prep", s, [&](hipStream_t st) {
+        hipLaunchKernelGGL(k_mrg_union, dim3(m), dim3(256), 0, st, cent1, nch1, m, (int)k, uni_b,
+                           nu, len_ptr);
+        const uint32_t padded = kc_pad64((uint32_t)cap);
+        hipLaunchKernelGGL(k_gather_soa, dim3((padded + 255) / 256), dim3(256), 0, st,
+                           pts->f32, pts->ld, d, uni_b, nu, padded, (float*)R2.xs, R2.stride);
+        kc_enqueue_gon_prep(R2, H2, jobs2, st);
+    });
+    if (rc) return rc;
+    bool done = false;
+    if (h->allow_resident) {
+        const uint32_t G = kc_resident_blocks_for(d, (uint32_t)cap);
+        if (G > 0 && (int)G <= h->resident_max(d)) {
+            const uint64_t sw = kc_resident_slot_words((int)k, G);
+            u64* slots = (u64*)h->ws("m2.slots", sizeof(u64) * sw);
+            uint32_t* abort_flag = (uint32_t*)h->ws("m2.abort", 64);
+            if (!slots || !abort_flag) return h->fail(KC_ENOMEM, "workspace allocation failed");
+            kc_fill_u64(slots, 0ull, sw, s);
+            kc_fill_u32(abort_flag, 0u, 1, s);
+            hipError_t e = kc_gon_resident(d, G, R2.xs, R2.stride, 0, (uint32_t)cap, len_ptr, 0,
+                                           (int)k, R2.mind, R2.keys, slots, abort_flag,
+                                           h->spin_limit, s);
+            if (e == hipSuccess) {
+                kc_or_status(abort_flag, h->status_word, 1u, s);
+                done = true;
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+    }
+    if (!done) {
+        rc = h->run_graph(key2 + ":steps", s, [&](hipStream_t st) { kc_enqueue_gon_steps(R2, st); });
+        if (rc) return rc;
+    }
+    rc = h->run_graph(key2 + ":finish", s, [&](hipStream_t st) {
+        kc_gon_finish(R2, centers, n_centers, nullptr, r2b, nullptr, uni_b, st);
+    });
+    if (rc) return rc;
+
+    // ---- covering radius over all points
+    return kc_assign_run(h, pts, centers, (uint32_t)k, n_centers, nullptr, radius, s, "m3.");
+}
+
+}  // extern "C"

@@ -20,9 +20,11 @@
 template <int D, int PPT>
 __global__ __launch_bounds__(KC_BLOCK, 1) void k_gon_resident(
     const float* __restrict__ xs, uint64_t stride, uint64_t base, uint32_t len,
-    uint32_t first, int k, float* __restrict__ mind, u64* __restrict__ keys,
-    u64* __restrict__ slots, uint32_t* __restrict__ abort_flag, uint32_t spin_limit)
+    const uint32_t* __restrict__ len_ptr, uint32_t first, int k, float* __restrict__ mind,
+    u64* __restrict__ keys, u64* __restrict__ slots, uint32_t* __restrict__ abort_flag,
+    uint32_t spin_limit)
 {
+    if (len_ptr) len = min(len, *len_ptr);   // actual length known on the device
     __shared__ float cc[D];
     __shared__ u64 red[KC_BLOCK / 64];
     const uint32_t G = gridDim.x;   // <= KC_BLOCK (checked by the host)
@@ -119,12 +121,13 @@ static int resident_ppt(int d)
 
 template <int D, int PPT>
 static hipError_t launch_resident(uint32_t G, const float* xs, uint64_t stride,
-                                  uint64_t base, uint32_t len, uint32_t first, int k,
+                                  uint64_t base, uint32_t len, const uint32_t* len_ptr,
+                                  uint32_t first, int k,
                                   float* mind, u64* keys, u64* slots, uint32_t* abort_flag,
                                   uint32_t spin_limit, hipStream_t s)
 {
     void* args[] = {(void*)&xs,    (void*)&stride, (void*)&base, (void*)&len,
-                    (void*)&first, (void*)&k,      (void*)&mind, (void*)&keys,
+                    (void*)&len_ptr, (void*)&first, (void*)&k,      (void*)&mind, (void*)&keys,
                     (void*)&slots, (void*)&abort_flag, (void*)&spin_limit};
     return hipLaunchCooperativeKernel((const void*)k_gon_resident<D, PPT>, dim3(G),
                                       dim3(KC_BLOCK), args, 0, s);
@@ -171,7 +174,8 @@ uint64_t kc_resident_slot_words(int k, uint32_t G) { return (uint64_t)k * G; }
 // Returns hipSuccess, or an error when the shape has no resident kernel or
 // the grid cannot be co-resident (the caller then streams instead).
 hipError_t kc_gon_resident(int d, uint32_t G, const float* xs, uint64_t stride,
-                           uint64_t base, uint32_t len, uint32_t first, int k, float* mind,
+                           uint64_t base, uint32_t len, const uint32_t* len_ptr,
+                           uint32_t first, int k, float* mind,
                            u64* keys, u64* slots, uint32_t* abort_flag, uint32_t spin_limit,
                            hipStream_t s)
 {
@@ -179,7 +183,7 @@ hipError_t kc_gon_resident(int d, uint32_t G, const float* xs, uint64_t stride,
     switch (d) {
 #define KC_CASE(DD, PP)                                                                  \
     case DD:                                                                             \
-        return launch_resident<DD, PP>(G, xs, stride, base, len, first, k, mind, keys,   \
+        return launch_resident<DD, PP>(G, xs, stride, base, len, len_ptr, first, k, mind, keys, \
                                        slots, abort_flag, spin_limit, s);
         KC_RES_DIMS(KC_CASE)
 #undef KC_CASE

@@ -1,0 +1,190 @@
+"""GPU parity of kcenter_assign (MFMA + FP64 certification) and kcenter_mrg
+(two-round MRG) against the FP64 oracle.
+
+Assignment labels must equal the oracle's exactly (certified points by the
+error bound, the rest rescored in FP64 with the oracle's arithmetic), and
+the radius must equal the oracle's exact FP64 covering radius.  MRG on
+integer coordinates (exact FP32 distances) must match the oracle in every
+output; on float coordinates every round is replayed through the oracle
+(certified ties only) and the radius is the exact one of the GPU's centers.
+"""
+import numpy as np
+import pytest
+
+from paper_1604_03228_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def band(d):
+    m = d + 2
+    return 2 * m * U32 / (1 - m * U32) + 1e-12
+
+
+@pytest.fixture(scope="module")
+def kc():
+    import paper_1604_03228_amd as kc
+    assert torch.cuda.is_available()
+    return kc
+
+
+def on_stream(fn):
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        out = fn()
+    st.synchronize()
+    return out
+
+
+def gpu_assign(kc, X, C, bf16=False, handle=None):
+    h = handle or kc.Handle()
+    Xd = torch.from_numpy(X).cuda()
+    B = torch.from_numpy(W.to_bf16_rne(X).view(np.int16)).cuda() if bf16 else None
+    Cd = torch.from_numpy(np.asarray(C, np.int64)).cuda()
+    lab, r = on_stream(lambda: kc.assign(Xd, Cd, bf16=B, handle=h))
+    assert h.device_status() == 0
+    return lab.cpu().numpy(), float(r.item())
+
+
+@pytest.mark.parametrize("d", [1, 2, 5, 16, 41, 70])
+@pytest.mark.parametrize("k", [1, 7, 200])
+@pytest.mark.parametrize("bf16", [False, True])
+def test_assign_random(kc, orc, d, k, bf16):
+    rng = np.random.default_rng(1000 * d + k)
+    n = 9_999
+    X = (rng.normal(size=(n, d)) * rng.uniform(0.1, 50, d)).astype(np.float32)
+    C = rng.choice(n, k, replace=False)
+    lab, R = gpu_assign(kc, X, C, bf16)
+    olab, oR = orc.assign(X, C)
+    assert np.array_equal(lab, olab)
+    assert R == oR
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_assign_ties_and_duplicates(kc, orc, bf16):
+    # integer grid: many exactly equal distances; duplicate centers too
+    X = W.config2(30_000)
+    c, _, _ = orc.gon(X, 64, 0)
+    C = np.r_[c, c[:5], c[10:12]]
+    lab, R = gpu_assign(kc, X, C, bf16)
+    olab, oR = orc.assign(X, C)
+    assert np.array_equal(lab, olab) and R == oR
+
+
+def test_assign_radius_equals_gon(kc, orc):
+    X = W.config1()
+    c, tr, got = orc.gon(X, 20, 0)
+    lab, R = gpu_assign(kc, X, c)
+    assert R == tr[-1]
+
+
+def test_assign_bad_center_is_reported(kc):
+    h = kc.Handle()
+    X = np.random.default_rng(3).random((1000, 3)).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    Cd = torch.tensor([0, 5, 5000], dtype=torch.int64, device="cuda")
+    on_stream(lambda: kc.assign(Xd, Cd, handle=h))
+    assert h.device_status() & 4
+
+
+def gpu_mrg(kc, X, off, k, bf16=False, handle=None):
+    h = handle or kc.Handle()
+    Xd = torch.from_numpy(X).cuda()
+    B = torch.from_numpy(W.to_bf16_rne(X).view(np.int16)).cuda() if bf16 else None
+    c, nc, r, ex = on_stream(lambda: kc.mrg(Xd, off, k, bf16=B, handle=h,
+                                            details=True))
+    assert h.device_status() == 0
+    m = len(off) - 1
+    nu = int(ex["n_union"].item())
+    return dict(centers=c.cpu().numpy(), n_centers=int(nc.item()),
+                radius=float(r.item()),
+                round1=ex["round1"].cpu().numpy().reshape(m, k),
+                r1=ex["r1"].cpu().numpy(),
+                union=ex["union"].cpu().numpy()[:nu], r2=float(ex["r2"].item()))
+
+
+def int_points(n, d, seed):
+    rng = np.random.default_rng(seed)
+    return rng.integers(-100, 101, (n, d)).astype(np.float32)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_mrg_integer_exact(kc, orc, bf16):
+    X = int_points(60_000, 16, 7)
+    off = W.partition_offsets(60_000, 12, 0.5, seed=7)
+    off = np.r_[off[:3], off[3], off[3:]]   # an extra empty partition
+    k = 25
+    g = gpu_mrg(kc, X, off, k, bf16)
+    o = orc.mrg(X, off, k)
+    assert np.array_equal(g["round1"], o["round1"])
+    assert np.array_equal(g["r1"], o["r1"])
+    assert np.array_equal(g["union"], o["union"])
+    assert g["n_centers"] == o["n_centers"]
+    assert np.array_equal(g["centers"], o["centers"])
+    assert g["r2"] == o["r2"] and g["radius"] == o["radius"]
+
+
+def test_mrg_small_partitions_and_k_above(kc, orc):
+    # partitions smaller than k (all their points are centers), k > |U|
+    X = int_points(3_000, 4, 9)
+    off = np.r_[0, 5, 5, 17, 40, 3000]
+    k = 30
+    g = gpu_mrg(kc, X, off, k)
+    o = orc.mrg(X, off, k)
+    assert np.array_equal(g["round1"], o["round1"])
+    assert np.array_equal(g["centers"], o["centers"])
+    assert g["radius"] == o["radius"]
+
+
+def check_mrg_float(orc, X, off, k, g):
+    # every partition's round-1 sequence is a certified farthest-first run
+    b = band(X.shape[1])
+    for p in range(len(off) - 1):
+        lo, hi = off[p], off[p + 1]
+        if hi == lo:
+            assert np.all(g["round1"][p] == -1)
+            continue
+        seq = g["round1"][p]
+        seq = seq[seq >= 0] - lo
+        bad, _, _ = orc.gon_replay(X[lo:hi], k, seq, b)
+        assert bad == -1, "partition %d step %d" % (p, bad)
+        _, R = orc.assign(X[lo:hi], seq)
+        assert g["r1"][p] == R
+    U = np.sort(g["round1"][g["round1"] >= 0])
+    assert np.array_equal(U, g["union"])
+    loc = np.searchsorted(U, g["centers"][:g["n_centers"]])
+    bad, _, _ = orc.gon_replay(X[U], k, loc, b)
+    assert bad == -1
+    _, R2 = orc.assign(X[U], loc)
+    assert g["r2"] == R2
+    _, R = orc.assign(X, g["centers"][:g["n_centers"]])
+    assert g["radius"] == R
+
+
+def test_mrg_gauss_small(kc, orc):
+    X, off = W.config3(200_000, 16)
+    k = 40
+    g = gpu_mrg(kc, X, off, k)
+    check_mrg_float(orc, X, off, k, g)
+    gb = gpu_mrg(kc, X, off, k, bf16=True)
+    assert np.array_equal(g["round1"], gb["round1"])
+    assert np.array_equal(g["centers"], gb["centers"])
+    assert g["radius"] == gb["radius"]
+
+
+@pytest.mark.slow
+def test_mrg_config3_full(kc, orc):
+    orc.set_threads(16)
+    X, off = W.config3()
+    k = W.CONFIG3["k"]
+    h = kc.Handle()
+    g = gpu_mrg(kc, X, off, k, handle=h)
+    check_mrg_float(orc, X, off, k, g)
+    gb = gpu_mrg(kc, X, off, k, bf16=True, handle=h)
+    assert np.array_equal(g["centers"], gb["centers"])
+    assert np.array_equal(g["round1"], gb["round1"])
+    assert g["radius"] == gb["radius"]
