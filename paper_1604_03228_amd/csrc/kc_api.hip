@@ -247,6 +247,26 @@ int kc_plan_gon(kc_handle* h, const std::string& pre, int d, uint32_t tile,
     if (!R.segs || !R.blk_seg || !R.blk_start || !R.pairs_seg || !R.pairs_t)
         return h->fail(KC_ENOMEM, "plan upload failed");
     R.keysum = keyoff;
+    // with segments in descending order of k, the tiles still active at step
+    // t form a prefix of the tile list: launch only those
+    bool desc = true;
+    uint32_t prev = 0xFFFFFFFFu;
+    for (int q = 0; q < nseg; ++q) {
+        if (H.segs[q].len == 0) continue;   // no tiles
+        if (H.segs[q].ksteps > prev) desc = false;
+        prev = H.segs[q].ksteps;
+    }
+    H.nblk_at.clear();
+    R.nblk_at = nullptr;
+    if (desc && nseg > 1) {
+        H.nblk_at.assign(kmax, 0);
+        uint32_t b = (uint32_t)H.blk_seg.size();
+        for (uint32_t t = 0; t < kmax; ++t) {
+            while (b > 0 && H.segs[H.blk_seg[b - 1]].ksteps <= t) --b;
+            H.nblk_at[t] = b;
+        }
+        R.nblk_at = H.nblk_at.data();
+    }
     return KC_OK;
 }
 
@@ -265,9 +285,12 @@ void kc_enqueue_gon_prep(const KcGonRun& R, const KcGonHost& H,
 // Enqueue all step launches of a planned run (streaming engine).
 void kc_enqueue_gon_steps(const KcGonRun& R, hipStream_t s)
 {
-    for (uint32_t t = 0; t < R.kmax; ++t)
-        kc_gon_step(R.xs, R.stride, R.d, R.mind, R.part, R.segs, R.blk_seg, R.blk_start,
-                    R.nblk, (int)t, s);
+    for (uint32_t t = 0; t < R.kmax; ++t) {
+        const uint32_t nb = R.nblk_at ? R.nblk_at[t] : R.nblk;
+        if (nb > 0)
+            kc_gon_step(R.xs, R.stride, R.d, R.mind, R.part, R.segs, R.blk_seg, R.blk_start,
+                        nb, (int)t, s);
+    }
     kc_part_collect(R.part, R.keys, R.keysum, s);
 }
 

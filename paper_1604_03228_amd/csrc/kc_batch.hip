@@ -1,0 +1,366 @@
+// kc_batch.hip -- many independent k-center problems of mixed n, d, k and
+// algorithm in shared launches.
+//
+// For every dimension d present:
+//   stage 1  every Gonzalez problem and every partition of every MRG problem
+//            is one segment of a single batched run (segments in descending
+//            order of k, so step t launches only the tiles of segments that
+//            still have centers to choose); one HIP graph per plan;
+//   stage 2  the MRG unions (built on the device) are the segments of a
+//            second batched run;
+//   stage 3  each MRG problem's covering radius by the MFMA assignment.
+// EIM problems run their sampling loop (which synchronises per iteration)
+// and finish on the single-problem path; problems streamed in BF16 also take
+// their single-problem entry point.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <numeric>
+
+#include "kc_host.h"
+
+struct KcBatchOut {
+    int64_t keyoff;       // first key / center slot of the segment
+    int64_t k;
+    int64_t seg;          // segment index (n_chosen, radius)
+    int64_t* centers;     // caller's [k]
+    int64_t* n_centers;   // caller's [1] or NULL
+    double* radius;       // caller's [1] or NULL
+};
+
+__global__ void k_batch_out(const KcBatchOut* __restrict__ tab, int count,
+                            const int64_t* __restrict__ cent, const int64_t* __restrict__ nch,
+                            const double* __restrict__ rad)
+{
+    const int i = blockIdx.x;
+    if (i >= count) return;
+    const KcBatchOut o = tab[i];
+    for (int64_t t = threadIdx.x; t < o.k; t += blockDim.x) o.centers[t] = cent[o.keyoff + t];
+    if (threadIdx.x == 0) {
+        if (o.n_centers) *o.n_centers = nch[o.seg];
+        if (o.radius) *o.radius = rad[o.seg];
+    }
+}
+
+// MRG unions of several problems: block p of problem q sorts its partition's
+// centers into uni[uoff_q + ...]; see k_mrg_union for one problem.
+struct KcUnionJob {
+    int64_t keyoff;       // first center slot of the problem's first partition
+    int64_t seg0;         // its first segment (n_chosen index)
+    int64_t m, k;
+    int64_t uoff;         // offset of the problem's union in uni
+    int64_t seg2;         // the problem's segment in the round-2 run
+};
+
+__global__ void k_batch_union(const KcUnionJob* __restrict__ jobs, const int32_t* __restrict__ blk_job,
+                              const int32_t* __restrict__ blk_part,
+                              const int64_t* __restrict__ cent, const int64_t* __restrict__ nch,
+                              int64_t* __restrict__ uni, int64_t* __restrict__ nuni,
+                              KcSeg* __restrict__ segs2)
+{
+    const KcUnionJob J = jobs[blk_job[blockIdx.x]];
+    const int64_t p = blk_part[blockIdx.x];
+    __shared__ int64_t off;
+    if (threadIdx.x == 0) {
+        int64_t o = 0;
+        for (int64_t q = 0; q < p; ++q) o += nch[J.seg0 + q];
+        off = o;
+        if (p == J.m - 1) {
+            const int64_t tot = o + nch[J.seg0 + p];
+            nuni[blk_job[blockIdx.x]] = tot;
+            segs2[J.seg2].len = (uint32_t)tot;
+        }
+    }
+    __syncthreads();
+    const int64_t np = nch[J.seg0 + p];
+    const int64_t* c = cent + J.keyoff + p * J.k;
+    for (int64_t i = threadIdx.x; i < np; i += blockDim.x) {
+        const int64_t v = c[i];
+        int64_t r = 0;
+        for (int64_t j = 0; j < np; ++j) r += c[j] < v;
+        uni[J.uoff + off + r] = v;
+    }
+}
+
+// SoA columns [base, base+padded) <- rows uni[uoff + i] of X (padding repeats
+// the union's first row)
+__global__ void k_batch_gather(const float* __restrict__ X, int64_t ld, int d,
+                               const int64_t* __restrict__ uni, int64_t uoff,
+                               const int64_t* __restrict__ nu, uint32_t padded,
+                               float* __restrict__ xs, uint64_t stride, uint64_t base)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= padded) return;
+    const int64_t cnt = *nu;
+    const uint64_t r = (uint64_t)((int64_t)i < cnt ? uni[uoff + i] : uni[uoff]);
+    for (int j = 0; j < d; ++j) xs[(uint64_t)j * stride + base + i] = X[r * ld + j];
+}
+
+static int check_problem(kc_handle* h, const kc_problem& p, int i)
+{
+    int rc = kc_check_points(h, &p.pts, true);
+    if (rc) return h->fail(rc, "problem %d: %s", i, h->last_error.c_str());
+    if (p.k < 1 || p.k >= (1 << 24)) return h->fail(KC_EINVAL, "problem %d: k out of range", i);
+    if (!p.centers || !p.n_centers || !p.radius)
+        return h->fail(KC_EINVAL, "problem %d: outputs NULL", i);
+    switch (p.algo) {
+    case KC_ALGO_GON:
+        if (p.first < 0 || p.first >= p.pts.n)
+            return h->fail(KC_EINVAL, "problem %d: first out of range", i);
+        return KC_OK;
+    case KC_ALGO_MRG:
+        if (p.m < 1 || !p.offsets || p.offsets[0] != 0 || p.offsets[p.m] != p.pts.n)
+            return h->fail(KC_EINVAL, "problem %d: bad offsets", i);
+        for (int q = 0; q < p.m; ++q)
+            if (p.offsets[q + 1] < p.offsets[q])
+                return h->fail(KC_EINVAL, "problem %d: offsets not monotone", i);
+        return KC_OK;
+    case KC_ALGO_EIM:
+        if (!(p.eim.eps > 0.0 && p.eim.eps < 1.0) || !(p.eim.phi > 0.0) || p.eim.max_iters < 1)
+            return h->fail(KC_EINVAL, "problem %d: bad EIM parameters", i);
+        return KC_OK;
+    default:
+        return h->fail(KC_EINVAL, "problem %d: unknown algorithm %d", i, p.algo);
+    }
+}
+
+struct SegTag {
+    int prob;   // problem index
+    int part;   // partition (MRG) or -1 (GON)
+};
+
+static int run_group(kc_handle* h, const kc_problem* probs, const std::vector<int>& ids, int d,
+                     hipStream_t s)
+{
+    char pre[32];
+    snprintf(pre, sizeof pre, "b%d.", d);
+    const std::string P(pre);
+
+    // ---- stage 1: one run over all Gonzalez problems and MRG partitions
+    std::vector<KcGonJob> jobs;
+    std::vector<SegTag> tags;
+    std::vector<int64_t> rbase;
+    for (int i : ids) {
+        const kc_problem& p = probs[i];
+        if (p.algo == KC_ALGO_GON) {
+            KcGonJob j;
+            j.X = p.pts.f32;
+            j.ld = p.pts.ld;
+            j.row0 = 0;
+            j.len = (uint32_t)p.pts.n;
+            j.first = (uint32_t)p.first;
+            j.k = (uint32_t)p.k;
+            jobs.push_back(j);
+            tags.push_back({i, -1});
+            rbase.push_back(0);
+        } else {
+            for (int q = 0; q < p.m; ++q) {
+                KcGonJob j;
+                j.X = p.pts.f32;
+                j.ld = p.pts.ld;
+                j.row0 = (uint64_t)p.offsets[q];
+                j.len = (uint32_t)(p.offsets[q + 1] - p.offsets[q]);
+                j.first = 0;
+                j.k = (uint32_t)p.k;
+                jobs.push_back(j);
+                tags.push_back({i, q});
+                rbase.push_back(p.offsets[q]);
+            }
+        }
+    }
+    // descending k, stable (an MRG problem's partitions stay together)
+    std::vector<int> ord(jobs.size());
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return jobs[a].k > jobs[b].k; });
+    std::vector<KcGonJob> sj;
+    std::vector<SegTag> st;
+    std::vector<int64_t> sr;
+    for (int q : ord) {
+        sj.push_back(jobs[q]);
+        st.push_back(tags[q]);
+        sr.push_back(rbase[q]);
+    }
+    KcGonRun R;
+    KcGonHost H;
+    int rc = kc_plan_gon(h, P + "1.", d, 1024, sj, R, H);
+    if (rc) return rc;
+    const int nseg = (int)sj.size();
+    const int64_t* rb = (const int64_t*)h->upload(P + "1.rb", sr.data(), 8 * sr.size());
+    int64_t* cent = (int64_t*)h->ws(P + "1.cent", 8 * std::max<uint64_t>(R.keysum, 1));
+    int64_t* nch = (int64_t*)h->ws(P + "1.nch", 8 * (size_t)nseg);
+    double* rad = (double*)h->ws(P + "1.rad", 8 * (size_t)nseg);
+    if (!rb || !cent || !nch || !rad) return h->fail(KC_ENOMEM, "workspace allocation failed");
+
+    // outputs of the Gonzalez problems; layout of the MRG problems
+    std::vector<KcBatchOut> outs;
+    std::map<int, int> first_seg;   // MRG problem -> its first segment
+    for (int q = 0; q < nseg; ++q) {
+        const SegTag& t = st[q];
+        const kc_problem& p = probs[t.prob];
+        if (t.part < 0)
+            outs.push_back({(int64_t)H.segs[q].keyoff, p.k, q, p.centers, p.n_centers, p.radius});
+        else if (t.part == 0)
+            first_seg[t.prob] = q;
+    }
+    const KcBatchOut* outs_d = outs.empty() ? nullptr
+        : (const KcBatchOut*)h->upload(P + "1.outs", outs.data(), sizeof(KcBatchOut) * outs.size());
+    std::string key = P + "run1";
+    for (int i : ids) {
+        char b[64];
+        snprintf(b, sizeof b, ":%p:%lld", (const void*)probs[i].pts.f32, (long long)probs[i].k);
+        key += b;
+    }
+    rc = kc_run_gon_stream(h, key, R, H, sj, "batch_gon", s, [&](hipStream_t sst) {
+        kc_gon_finish(R, cent, nch, nullptr, rad, rb, nullptr, sst);
+        if (!outs.empty())
+            hipLaunchKernelGGL(k_batch_out, dim3((unsigned)outs.size()), dim3(256), 0, sst, outs_d,
+                               (int)outs.size(), cent, nch, rad);
+    });
+    if (rc) return rc;
+    if (first_seg.empty()) return KC_OK;
+
+    // ---- stage 2: MRG second rounds as the segments of one run
+    std::vector<KcUnionJob> uj;
+    std::vector<int32_t> blk_job, blk_part;
+    std::vector<KcGonJob> j2;
+    std::vector<int> mrg_ids;
+    int64_t uoff = 0;
+    for (auto& kv : first_seg) {
+        const kc_problem& p = probs[kv.first];
+        const int64_t cap = std::min<int64_t>((int64_t)p.m * p.k, p.pts.n);
+        KcUnionJob J;
+        J.keyoff = H.segs[kv.second].keyoff;
+        J.seg0 = kv.second;
+        J.m = p.m;
+        J.k = p.k;
+        J.uoff = uoff;
+        J.seg2 = 0;   // set after the round-2 order is known
+        for (int q = 0; q < p.m; ++q) {
+            blk_job.push_back((int32_t)uj.size());
+            blk_part.push_back(q);
+        }
+        uj.push_back(J);
+        KcGonJob g;
+        g.X = nullptr;   // gathered
+        g.ld = p.pts.ld;
+        g.row0 = (uint64_t)uoff;
+        g.len = (uint32_t)cap;
+        g.first = 0;
+        g.k = (uint32_t)p.k;
+        j2.push_back(g);
+        mrg_ids.push_back(kv.first);
+        uoff += cap;
+    }
+    std::vector<int> o2(j2.size());
+    std::iota(o2.begin(), o2.end(), 0);
+    std::stable_sort(o2.begin(), o2.end(), [&](int a, int b) { return j2[a].k > j2[b].k; });
+    std::vector<KcGonJob> sj2;
+    for (int q = 0; q < (int)o2.size(); ++q) {
+        sj2.push_back(j2[o2[q]]);
+        uj[o2[q]].seg2 = q;
+    }
+    KcGonRun R2;
+    KcGonHost H2;
+    rc = kc_plan_gon(h, P + "2.", d, 1024, sj2, R2, H2);
+    if (rc) return rc;
+    const int nu = (int)uj.size();
+    int64_t* uni = (int64_t*)h->ws(P + "2.uni", 8 * (size_t)std::max<int64_t>(uoff, 1));
+    int64_t* nuni = (int64_t*)h->ws(P + "2.nu", 8 * (size_t)nu);
+    int64_t* cent2 = (int64_t*)h->ws(P + "2.cent", 8 * std::max<uint64_t>(R2.keysum, 1));
+    int64_t* nch2 = (int64_t*)h->ws(P + "2.nch", 8 * (size_t)nu);
+    const KcUnionJob* uj_d = (const KcUnionJob*)h->upload(P + "2.uj", uj.data(), sizeof(KcUnionJob) * nu);
+    const int32_t* bj_d = (const int32_t*)h->upload(P + "2.bj", blk_job.data(), 4 * blk_job.size());
+    const int32_t* bp_d = (const int32_t*)h->upload(P + "2.bp", blk_part.data(), 4 * blk_part.size());
+    if (!uni || !nuni || !cent2 || !nch2 || !uj_d || !bj_d || !bp_d)
+        return h->fail(KC_ENOMEM, "workspace allocation failed");
+    std::vector<KcBatchOut> outs2;
+    for (int q = 0; q < nu; ++q) {
+        const kc_problem& p = probs[mrg_ids[o2[q]]];
+        outs2.push_back({(int64_t)H2.segs[q].keyoff, p.k, q, p.centers, p.n_centers, nullptr});
+    }
+    const KcBatchOut* outs2_d =
+        (const KcBatchOut*)h->upload(P + "2.outs", outs2.data(), sizeof(KcBatchOut) * nu);
+    if (!outs2_d) return h->fail(KC_ENOMEM, "workspace allocation failed");
+    rc = h->run_graph(key + ":u", s, [&](hipStream_t sst) {
+        hipLaunchKernelGGL(k_batch_union, dim3((unsigned)blk_job.size()), dim3(256), 0, sst, uj_d,
+                           bj_d, bp_d, cent, nch, uni, nuni, R2.segs);
+        for (int q = 0; q < nu; ++q) {
+            const KcUnionJob& J = uj[o2[q]];
+            const kc_problem& p = probs[mrg_ids[o2[q]]];
+            const uint32_t padded = kc_pad64(sj2[q].len);
+            hipLaunchKernelGGL(k_batch_gather, dim3((padded + 255) / 256), dim3(256), 0, sst,
+                               p.pts.f32, p.pts.ld, d, uni, J.uoff, nuni + o2[q], padded,
+                               (float*)R2.xs, R2.stride, H2.segs[q].base);
+        }
+    });
+    if (rc) return rc;
+    rc = kc_run_gon_stream(h, key + ":r2", R2, H2, sj2, "batch_gon", s, [&](hipStream_t sst) {
+        kc_gon_finish(R2, cent2, nch2, nullptr, nullptr, nullptr, uni, sst);
+        hipLaunchKernelGGL(k_batch_out, dim3((unsigned)nu), dim3(256), 0, sst, outs2_d, nu, cent2,
+                           nch2, (const double*)nullptr);
+    });
+    if (rc) return rc;
+
+    // ---- stage 3: covering radius of every MRG problem (FP32 MFMA)
+    for (int i : mrg_ids) {
+        const kc_problem& p = probs[i];
+        kc_points p32 = p.pts;
+        p32.prec = KC_FP32;
+        p32.bf16 = nullptr;
+        rc = kc_assign_run(h, &p32, p.centers, (uint32_t)p.k, p.n_centers, nullptr, p.radius, s,
+                           P + "a.");
+        if (rc) return rc;
+    }
+    return KC_OK;
+}
+
+extern "C" int kcenter_batch(kc_handle* h, const kc_problem* probs, int32_t count, void* stream)
+{
+    if (!h) return KC_EINVAL;
+    if (count < 0 || (count > 0 && !probs)) return h->fail(KC_EINVAL, "bad problem list");
+    for (int i = 0; i < count; ++i) {
+        int rc = check_problem(h, probs[i], i);
+        if (rc) return rc;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    std::map<int, std::vector<int>> groups;
+    std::vector<int> others;
+    for (int i = 0; i < count; ++i) {
+        const kc_problem& p = probs[i];
+        const bool fp32 = p.pts.prec == KC_FP32;
+        if (p.algo != KC_ALGO_EIM && fp32)
+            groups[p.pts.d].push_back(i);
+        else
+            others.push_back(i);
+    }
+    for (auto& g : groups) {
+        int rc = run_group(h, probs, g.second, g.first, s);
+        if (rc) return rc;
+    }
+    for (int i : others) {
+        const kc_problem& p = probs[i];
+        int rc;
+        if (p.algo == KC_ALGO_EIM) {
+            int64_t ns = 0;
+            int32_t ni = 0;
+            rc = kcenter_eim(h, &p.pts, p.k, &p.eim, p.centers, p.n_centers, p.radius, nullptr, &ns,
+                             nullptr, &ni, s);
+        } else if (p.algo == KC_ALGO_GON) {
+            double* tr = (double*)h->ws("bo.trace", 8 * (size_t)p.k);
+            if (!tr) return h->fail(KC_ENOMEM, "workspace allocation failed");
+            rc = kcenter_gonzalez(h, &p.pts, p.k, p.first, p.centers, tr, p.n_centers, s);
+            if (!rc) {
+                // radius: the last chosen entry of the trace, via the assignment
+                rc = kc_assign_run(h, &p.pts, p.centers, (uint32_t)p.k, p.n_centers, nullptr,
+                                   p.radius, s, "bo.a.");
+            }
+        } else {
+            rc = kcenter_mrg(h, &p.pts, p.offsets, p.m, p.k, p.centers, p.n_centers, p.radius,
+                             nullptr, nullptr, nullptr, nullptr, nullptr, s);
+        }
+        if (rc) return h->fail(rc, "problem %d: %s", i, h->last_error.c_str());
+    }
+    return KC_OK;
+}

@@ -280,6 +280,85 @@ __global__ void k_bf16_rescore(const u64* __restrict__ cand,
     }
 }
 
+// Candidates and their rescoring in one pass over the step's tiles: a block
+// whose largest upper bound is below L_t leaves at once; otherwise it lists
+// its candidates in LDS, rescores each with one wave (lanes over the centers
+// chosen since the point was last rescored) and offers the block's best key.
+__global__ __launch_bounds__(KC_BLOCK) void k_bf16_cand_rescore(
+    const float* __restrict__ mind, const float* __restrict__ ex,
+    const float* __restrict__ blk_hi, const uint32_t* __restrict__ lpart,
+    const float* __restrict__ xs, uint64_t stride, int d, const float* __restrict__ ccoord,
+    const KcSeg* __restrict__ segs, const uint32_t* __restrict__ blk_seg,
+    const uint32_t* __restrict__ blk_start, int t, float g, float* __restrict__ exm,
+    uint32_t* __restrict__ exupto, u64* __restrict__ part)
+{
+    __shared__ uint32_t list[KC_BF_TILE];
+    __shared__ uint32_t nlist;
+    __shared__ float sL;
+    __shared__ u64 red[KC_BLOCK / 64];
+    const uint32_t b = blockIdx.x;
+    const KcSeg sg = segs[blk_seg[b]];
+    if ((uint32_t)t >= sg.ksteps) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (w == 0) {
+        u64 pv = 1ull << 32;
+        if (t > 0) {   // a segment that stopped at the previous step is done
+            pv = 0;
+            if (lane < KC_PARTS)
+                pv = __hip_atomic_load(kc_part_slot(part, sg.keyoff + t - 1, lane),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            pv = kc_wave_max64(pv);
+        }
+        uint32_t lv = 0;
+        if (lane < KC_PARTS)
+            lv = __hip_atomic_load(lpart + ((uint64_t)(sg.keyoff + t) * KC_PARTS + lane) * 32,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int off = 32; off >= 1; off >>= 1) {
+            const uint32_t o = __shfl_xor(lv, off, 64);
+            lv = o > lv ? o : lv;
+        }
+        if (lane == 0) {
+            // stopped segments and blocks without candidates skip the step
+            sL = ((pv >> 32) == 0 || blk_hi[b] < __uint_as_float(lv)) ? -1.f
+                                                                     : __uint_as_float(lv);
+            nlist = 0;
+        }
+    }
+    __syncthreads();
+    const float L = sL;
+    if (L < 0.f) return;
+    for (int q = 0; q < KC_BF_PTS; ++q) {
+        const uint32_t loc = blk_start[b] + q * KC_BLOCK + threadIdx.x;
+        if (loc < sg.len) {
+            const uint64_t col = sg.base + loc;
+            if (kc_bf_hi(mind[col], ex[col], g) >= L) list[atomicAdd(&nlist, 1u)] = loc;
+        }
+    }
+    __syncthreads();
+    const uint32_t nl = nlist;
+    u64 key = 0;
+    for (uint32_t q = w; q < nl; q += KC_BLOCK / 64) {
+        const uint32_t loc = list[q];
+        const uint64_t col = sg.base + loc;
+        const uint32_t from = exupto[col];
+        float best = exm[col];
+        for (uint32_t j = from + lane; j <= (uint32_t)t; j += 64) {
+            const float* cj = ccoord + (uint64_t)(sg.keyoff + j) * d;
+            float s = 0.f;
+            for (int u = 0; u < d; ++u) s = kc_d32_step(s, xs[(uint64_t)u * stride + col], cj[u]);
+            best = fminf(best, s);
+        }
+        for (int off = 32; off >= 1; off >>= 1) best = fminf(best, __shfl_xor(best, off, 64));
+        if (lane == 0) {
+            exm[col] = best;
+            exupto[col] = (uint32_t)t + 1;
+        }
+        key = kc_umax64(key, kc_pack(best, loc));
+    }
+    key = kc_block_max64(key, red);
+    if (threadIdx.x == 0 && key) kc_part_offer(part, sg.keyoff + t, b % KC_PARTS, key);
+}
+
 // Final-radius candidates in BF16 mode: hi_i >= L_last * (1 - band), where
 // L_last is the largest lower bound after the last step; the band covers the
 // FP32 error between the exact maximiser and the FP32 values.
@@ -332,12 +411,9 @@ void kc_enqueue_bf16_steps(const KcGonRun& R, const KcBf16Run& B, hipStream_t s)
                                R.xs, R.stride, R.d, B.ex, R.mind, R.part, B.lpart, B.blk_hi,
                                R.ccoord, R.segs, R.blk_seg, R.blk_start, t, B.g);
         }
-        hipLaunchKernelGGL(k_bf16_cand, dim3(R.nblk), dim3(KC_BLOCK), 0, s, R.mind, B.ex,
-                           B.blk_hi, B.lpart, R.segs, R.blk_seg, R.blk_start, t, B.g, R.cand,
-                           B.ncand, R.cand_cap, R.part);
-        hipLaunchKernelGGL(k_bf16_rescore, dim3(B.rescore_blocks), dim3(256), 0, s, R.cand,
-                           B.ncand + t, R.cand_cap, R.xs, R.stride, R.d, R.ccoord, R.segs,
-                           B.exm, B.exupto, R.part, t);
+        hipLaunchKernelGGL(k_bf16_cand_rescore, dim3(R.nblk), dim3(KC_BLOCK), 0, s, R.mind,
+                           B.ex, B.blk_hi, B.lpart, R.xs, R.stride, R.d, R.ccoord, R.segs,
+                           R.blk_seg, R.blk_start, t, B.g, B.exm, B.exupto, R.part);
     }
     kc_part_collect(R.part, R.keys, R.keysum, s);
 }

@@ -1,0 +1,538 @@
+// kc_eim.hip -- the EIM sampling pass (Algorithm 2 with Select, Algorithm 3,
+// and the Section 4.1 changes) on gfx950, followed by Gonzalez on the sample.
+//
+// Per iteration (host-driven, one synchronisation to size the next one):
+//   k_eim_draw        Philox4x64-10 Bernoulli draws for every x in R: into
+//                     S with probability p_S, into H with probability p_H
+//                     (one counter-based block per point and iteration);
+//   compaction        stable scans split R into dS (new samples), H and the
+//                     points that stay candidates (not sampled);
+//   k_eim_dist_h      exact FP64 d(h,S)^2 for h in H (split over S, min via
+//                     64-bit atomics on the bits of non-negative doubles);
+//   k_eim_select      tau = the min(r,|H|)-th largest d(h,S)^2 (rank count);
+//   distance pass     d(x,dS)^2 for the remaining x on MFMA; per point the
+//                     certified interval [lo, hi] of d(x,S)^2 is narrowed by
+//                     a running min over the iterations;
+//   k_eim_decide      keep x iff d(x,S)^2 > tau: decided by the interval when
+//                     it does not contain tau, otherwise in exact FP64 over
+//                     all of S (k_eim_exact).
+// Every draw and decision is per point, so the result is independent of how
+// the paper's mappers partition R.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "kc_host.h"
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11): ten rounds of two 64x64->128-bit
+// products with the published multipliers; the key advances by the published
+// Weyl constants between rounds.
+
+__device__ __forceinline__ void kc_philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+        const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+// flags: bit 0 = drawn into S, bit 1 = drawn into H
+__global__ void k_eim_draw(const uint32_t* __restrict__ R, uint32_t nr, uint64_t seed, int it,
+                           double pS, double pH, uint8_t* __restrict__ fS,
+                           uint8_t* __restrict__ fH, uint8_t* __restrict__ fKeep)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nr) return;
+    uint64_t c[4] = {(uint64_t)R[j], (uint64_t)it, 0ull, 0ull};
+    kc_philox4x64_10(c, seed, 0ull);
+    const double uS = (double)(c[0] >> 11) * 0x1.0p-53;
+    const double uH = (double)(c[1] >> 11) * 0x1.0p-53;
+    const bool s = uS < pS;
+    fS[j] = s;
+    fH[j] = uH < pH;
+    fKeep[j] = !s;   // sampled points always leave R
+}
+
+// ---------------------------------------------------------------------------
+// stable compaction: out[rank] = in[i] (or i) for every flagged i, in order
+
+#define KC_CMP_ITEMS 1024   // items per block (256 threads x 4)
+
+__global__ void k_cmp_count(const uint8_t* __restrict__ f, uint32_t n,
+                            uint32_t* __restrict__ blk_cnt)
+{
+    __shared__ uint32_t red[4];
+    const uint32_t base = blockIdx.x * KC_CMP_ITEMS;
+    uint32_t c = 0;
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t i = base + q * 256 + threadIdx.x;
+        if (i < n) c += f[i] != 0;
+    }
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) blk_cnt[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// one block: exclusive scan of nb block counts; total -> *count
+__global__ void k_cmp_scan(uint32_t* __restrict__ blk, uint32_t nb, uint32_t* __restrict__ count)
+{
+    __shared__ uint32_t carry;
+    __shared__ uint32_t wsum[16];
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t b0 = 0; b0 < nb; b0 += blockDim.x) {
+        const uint32_t i = b0 + threadIdx.x;
+        const uint32_t v = i < nb ? blk[i] : 0u;
+        // inclusive scan within the wave
+        uint32_t x = v;
+        const int lane = threadIdx.x & 63;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[threadIdx.x >> 6] = x;
+        __syncthreads();
+        uint32_t wpre = 0;
+        for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wpre += wsum[w];
+        const uint32_t excl = carry + wpre + x - v;
+        __syncthreads();
+        if (i < nb) blk[i] = excl;
+        if (threadIdx.x == blockDim.x - 1) carry = excl + v;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = carry;
+}
+
+__global__ void k_cmp_scatter(const uint8_t* __restrict__ f, const uint32_t* __restrict__ in,
+                              uint32_t n, const uint32_t* __restrict__ blk_off,
+                              uint32_t* __restrict__ out)
+{
+    __shared__ uint32_t wcnt[16];
+    const uint32_t base = blockIdx.x * KC_CMP_ITEMS;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t run = blk_off[blockIdx.x];
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t i = base + q * 256 + threadIdx.x;
+        const bool on = i < n && f[i] != 0;
+        const u64 mask = __ballot(on);
+        const uint32_t before = __popcll(mask & ((1ull << lane) - 1ull));
+        if (lane == 0) wcnt[w] = __popcll(mask);
+        __syncthreads();
+        uint32_t wpre = 0;
+        for (int v = 0; v < w; ++v) wpre += wcnt[v];
+        if (on) out[run + wpre + before] = in ? in[i] : i;
+        uint32_t tot = 0;
+        for (int v = 0; v < 4; ++v) tot += wcnt[v];
+        __syncthreads();
+        run += tot;
+    }
+}
+
+struct KcCompact {
+    uint32_t* blk = nullptr;   // [nblocks]
+    uint32_t nb_cap = 0;
+};
+
+static void kc_compact(const KcCompact& C, const uint8_t* f, const uint32_t* in, uint32_t n,
+                       uint32_t* out, uint32_t* count, hipStream_t s)
+{
+    if (n == 0) {
+        kc_fill_u32(count, 0u, 1, s);
+        return;
+    }
+    const uint32_t nb = (n + KC_CMP_ITEMS - 1) / KC_CMP_ITEMS;
+    hipLaunchKernelGGL(k_cmp_count, dim3(nb), dim3(256), 0, s, f, n, C.blk);
+    hipLaunchKernelGGL(k_cmp_scan, dim3(1), dim3(1024), 0, s, C.blk, nb, count);
+    hipLaunchKernelGGL(k_cmp_scatter, dim3(nb), dim3(256), 0, s, f, in, n, C.blk, out);
+}
+
+// ---------------------------------------------------------------------------
+// Select (Algorithm 3): d(h,S)^2 for h in H exactly, then tau
+
+// grid.x covers H, grid.y splits S; one wave per (h, slice)
+__global__ void k_eim_dist_h(const float* __restrict__ X, int64_t ld, int d,
+                             const uint32_t* __restrict__ H, uint32_t nh,
+                             const uint32_t* __restrict__ S, uint32_t ns,
+                             double* __restrict__ dH)
+{
+    const uint32_t h = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (h >= nh) return;
+    const float* xh = X + (uint64_t)H[h] * ld;
+    const uint32_t per = (ns + gridDim.y - 1) / gridDim.y;
+    const uint32_t s0 = blockIdx.y * per, s1 = min(ns, s0 + per);
+    double best = __builtin_inf();
+    for (uint32_t q = s0 + lane; q < s1; q += 64) {
+        const float* xs = X + (uint64_t)S[q] * ld;
+        double a = 0.0;
+        for (int u = 0; u < d; ++u) a = kc_d64_step(a, (double)xh[u], (double)xs[u]);
+        best = fmin(best, a);
+    }
+    best = kc_wave_min_f64(best);
+    if (lane == 0 && best < __builtin_inf())
+        atomicMin((u64*)&dH[h], (u64)__double_as_longlong(best));
+}
+
+// tau = the r-th largest of dH[0..nh) (rank by counting; ties share a value)
+__global__ void k_eim_select(const double* __restrict__ dH, uint32_t nh, uint32_t r,
+                             double* __restrict__ tau)
+{
+    for (uint32_t i = threadIdx.x; i < nh; i += blockDim.x) {
+        const double v = dH[i];
+        uint32_t greater = 0, equal = 0;
+        for (uint32_t j = 0; j < nh; ++j) {
+            greater += dH[j] > v;
+            equal += dH[j] == v;
+        }
+        if (greater < r && r <= greater + equal) *tau = v;   // all writers agree
+    }
+}
+
+// ---------------------------------------------------------------------------
+// distance pass bounds and the keep decision
+
+// XR[j][*] = X[R[j]][*] for the candidates (compact AoS, row stride d)
+__global__ void k_gather_rows(const float* __restrict__ X, int64_t ld, int d,
+                              const uint32_t* __restrict__ idx, uint32_t n,
+                              float* __restrict__ out)
+{
+    const uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (q >= (uint64_t)n * d) return;
+    const uint64_t j = q / d, u = q % d;
+    out[q] = X[(uint64_t)idx[j] * ld + u];
+}
+
+// Narrow [lo, hi] of d(x,S)^2 with this iteration's new samples (MFMA values).
+__global__ void k_eim_bounds(uint32_t nc, int d, const uint32_t* __restrict__ cand,
+                             const float* __restrict__ m1, const float* __restrict__ nxv,
+                             const float* __restrict__ cmax, float* __restrict__ lo,
+                             float* __restrict__ hi)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nc) return;
+    const uint32_t x = cand[j];
+    const double g = (6.0 * d + 32.0) * 5.9604644775390625e-8;
+    const double nx = nxv[j];
+    const double s = sqrt(nx) * (1.0 + 1e-6) + (double)cmax[0];
+    const double err = g * s * s + 1e-30 * d;
+    const double v = nx + (double)m1[j];
+    double l = (v - err) * (1.0 - 1e-12);
+    if (l < 0.0) l = 0.0;
+    const double u = (v + err) * (1.0 + 1e-12);
+    lo[x] = fminf(lo[x], (float)l * (1.f - 1e-6f));
+    hi[x] = fminf(hi[x], (float)u * (1.f + 1e-6f));
+}
+
+// keep iff d(x,S)^2 > tau; interval decides, else the exact pass does
+__global__ void k_eim_decide(uint32_t nc, const uint32_t* __restrict__ cand,
+                             const float* __restrict__ lo, const float* __restrict__ hi,
+                             const double* __restrict__ tau, uint8_t* __restrict__ keep,
+                             uint32_t* __restrict__ unsure, uint32_t* __restrict__ nunsure)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nc) return;
+    const uint32_t x = cand[j];
+    const double t = *tau;
+    if ((double)lo[x] > t) {
+        keep[j] = 1;
+    } else if ((double)hi[x] <= t) {
+        keep[j] = 0;
+    } else {
+        keep[j] = 0;
+        unsure[atomicAdd(nunsure, 1u)] = j;
+    }
+}
+
+// exact FP64 d(x,S)^2 for an undecided candidate: one block per candidate
+__global__ void k_eim_exact(const float* __restrict__ X, int64_t ld, int d,
+                            const uint32_t* __restrict__ cand,
+                            const uint32_t* __restrict__ unsure,
+                            const uint32_t* __restrict__ nunsure,
+                            const uint32_t* __restrict__ S, uint32_t ns,
+                            const double* __restrict__ tau, uint8_t* __restrict__ keep,
+                            float* __restrict__ lo, float* __restrict__ hi)
+{
+    __shared__ double red[16];
+    const uint32_t nu = *nunsure;
+    for (uint32_t q = blockIdx.x; q < nu; q += gridDim.x) {
+        const uint32_t j = unsure[q];
+        const uint32_t x = cand[j];
+        const float* xp = X + (uint64_t)x * ld;
+        double best = __builtin_inf();
+        for (uint32_t i = threadIdx.x; i < ns; i += blockDim.x) {
+            const float* sp = X + (uint64_t)S[i] * ld;
+            double a = 0.0;
+            for (int u = 0; u < d; ++u) a = kc_d64_step(a, (double)xp[u], (double)sp[u]);
+            best = fmin(best, a);
+        }
+        best = kc_wave_min_f64(best);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double b = red[0];
+            for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b = fmin(b, red[w]);
+            keep[j] = b > *tau;
+            // the exact value is its own interval from now on
+            lo[x] = (float)b * (1.f - 1e-6f);
+            hi[x] = (float)b * (1.f + 1e-6f);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_mark(const uint32_t* __restrict__ idx, uint32_t n, uint8_t* __restrict__ f)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) f[idx[j]] = 1;
+}
+
+__global__ void k_iota(uint32_t* __restrict__ p, uint32_t n)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) p[j] = j;
+}
+
+__global__ void k_u32_to_i64(const uint32_t* __restrict__ a, uint32_t n, int64_t* __restrict__ b)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) b[j] = a[j];
+}
+
+__global__ void k_gather_soa32(const float* __restrict__ X, int64_t ld, int d,
+                               const uint32_t* __restrict__ idx, uint32_t n, uint32_t padded,
+                               float* __restrict__ xs, uint64_t stride)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= padded) return;
+    const uint64_t r = idx[i < n ? i : 0];
+    for (int j = 0; j < d; ++j) xs[(uint64_t)j * stride + i] = X[r * ld + j];
+}
+
+// ---------------------------------------------------------------------------
+// host driver
+
+static inline dim3 g1(uint64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
+
+static int kc_read_u32(kc_handle* h, const uint32_t* dev, uint32_t* out, hipStream_t s)
+{
+    if (hipMemcpyAsync(out, dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        hipError_t e = hipGetLastError();
+        return h->fail(KC_EHIP, "readback: %s", hipGetErrorString(e));
+    }
+    return KC_OK;
+}
+
+extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
+                           const kc_eim_params* prm, int64_t* centers, int64_t* n_centers,
+                           double* radius, int64_t* sample, int64_t* n_sample,
+                           kc_eim_iter* iters, int32_t* n_iters, void* stream)
+{
+    if (!h) return KC_EINVAL;
+    int rc = kc_check_points(h, pts, true);
+    if (rc) return rc;
+    if (!prm) return h->fail(KC_EINVAL, "params NULL");
+    if (!(prm->eps > 0.0 && prm->eps < 1.0)) return h->fail(KC_EINVAL, "eps must be in (0,1)");
+    if (!(prm->phi > 0.0)) return h->fail(KC_EINVAL, "phi must be > 0");
+    if (prm->max_iters < 1) return h->fail(KC_EINVAL, "max_iters must be >= 1");
+    if (k < 1 || k >= (1 << 24)) return h->fail(KC_EINVAL, "k out of range");
+    if (!centers || !n_centers || !radius) return h->fail(KC_EINVAL, "outputs NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t n = (uint32_t)pts->n;
+    const int d = pts->d;
+    const float* X = pts->f32;
+    const int64_t ld = pts->ld;
+
+    // constants of Algorithm 2 and Select, in FP64 on the host (natural log)
+    const double L = log((double)n);
+    const double ne = pow((double)n, prm->eps);
+    const double A_S = 9.0 * (double)k * ne * L;
+    const double A_H = 4.0 * ne * L;
+    const double thr = (4.0 / prm->eps) * (double)k * ne * L;
+    int64_t rsel = (int64_t)ceil(prm->phi * L);
+    if (rsel < 1) rsel = 1;
+
+    uint32_t* R = (uint32_t*)h->ws("e.R", 4ull * n);
+    uint32_t* R2 = (uint32_t*)h->ws("e.R2", 4ull * n);
+    uint32_t* S = (uint32_t*)h->ws("e.S", 4ull * n);
+    uint32_t* H = (uint32_t*)h->ws("e.H", 4ull * n);
+    uint32_t* cand = (uint32_t*)h->ws("e.cand", 4ull * n);
+    uint8_t* fS = (uint8_t*)h->ws("e.fS", n);
+    uint8_t* fH = (uint8_t*)h->ws("e.fH", n);
+    uint8_t* fK = (uint8_t*)h->ws("e.fK", n);
+    uint8_t* keep = (uint8_t*)h->ws("e.keep", n);
+    float* lo = (float*)h->ws("e.lo", 4ull * n);
+    float* hi = (float*)h->ws("e.hi", 4ull * n);
+    double* dH = (double*)h->ws("e.dH", 8ull * n);
+    double* tau = (double*)h->ws("e.tau", 16);
+    uint32_t* cnt = (uint32_t*)h->ws("e.cnt", 64);   // [0] dS [1] H [2] cand [3] R [4] unsure
+    uint32_t* unsure = (uint32_t*)h->ws("e.uns", 4ull * n);
+    KcCompact C;
+    C.nb_cap = (n + KC_CMP_ITEMS - 1) / KC_CMP_ITEMS + 1;
+    C.blk = (uint32_t*)h->ws("e.blk", 4ull * C.nb_cap);
+    if (!R || !R2 || !S || !H || !cand || !fS || !fH || !fK || !keep || !lo || !hi || !dH ||
+        !tau || !cnt || !unsure || !C.blk)
+        return h->fail(KC_ENOMEM, "workspace allocation failed");
+
+    hipLaunchKernelGGL(k_iota, g1(n), dim3(256), 0, s, R, n);
+    kc_fill_u32((uint32_t*)lo, 0x7F800000u, n, s);
+    kc_fill_u32((uint32_t*)hi, 0x7F800000u, n, s);
+    uint32_t nr = n, ns = 0;
+    int it = 0;
+    while ((double)nr > thr) {
+        if (it >= prm->max_iters) {
+            if (n_iters) *n_iters = it;
+            return h->fail(KC_ENOCONV, "R still has %u points after %d iterations", nr, it);
+        }
+        double pS = A_S / (double)nr;
+        if (pS > 1.0) pS = 1.0;
+        double pH = A_H / (double)nr;
+        if (pH > 1.0) pH = 1.0;
+        hipLaunchKernelGGL(k_eim_draw, g1(nr), dim3(256), 0, s, R, nr, prm->seed, it, pS, pH,
+                           fS, fH, fK);
+        kc_compact(C, fS, R, nr, S + ns, cnt + 0, s);
+        kc_compact(C, fH, R, nr, H, cnt + 1, s);
+        kc_compact(C, fK, R, nr, cand, cnt + 2, s);
+        uint32_t hc[3];
+        if (hipMemcpyAsync(hc, cnt, 12, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return h->fail(KC_EHIP, "readback failed");
+        const uint32_t nds = hc[0], nh = hc[1], nc = hc[2];
+        ns += nds;
+        double tau_h = -INFINITY;
+        uint32_t new_nr = nr;
+        if (ns > 0) {
+            // Select: tau over H (exact FP64 against all of S)
+            if (nh > 0) {
+                kc_fill_u64((u64*)dH, 0x7FF0000000000000ull, nh, s);   // +inf
+                const uint32_t splits = std::max<uint32_t>(1, std::min<uint32_t>(64, ns / 4096));
+                hipLaunchKernelGGL(k_eim_dist_h, dim3((nh + 3) / 4, splits), dim3(256), 0, s, X,
+                                   ld, d, H, nh, S, ns, dH);
+                const uint32_t rr = (uint32_t)std::min<int64_t>(rsel, nh);
+                hipLaunchKernelGGL(k_eim_select, dim3(1), dim3(1024), 0, s, dH, nh, rr, tau);
+            } else {
+                kc_fill_u64((u64*)tau, 0xFFF0000000000000ull, 1, s);   // -inf
+            }
+            // distance pass of the candidates against this iteration's samples
+            if (nds > 0 && nc > 0) {
+                const int dp = kc_mindist_dpad(d, false);
+                const uint32_t kpad = (nds + 15u) & ~15u;
+                float* XR = (float*)h->ws("e.XR", 4ull * nc * d);
+                float* Cf = (float*)h->ws("e.cf", 4ull * kpad * dp);
+                float* cn = (float*)h->ws("e.cn", 4ull * kpad);
+                float* cmax = (float*)h->ws("e.cmax", 16);
+                int32_t* arg = (int32_t*)h->ws("e.arg", 4ull * nc);
+                float* m1 = (float*)h->ws("e.m1", 4ull * nc);
+                float* m2 = (float*)h->ws("e.m2", 4ull * nc);
+                float* nx = (float*)h->ws("e.nx", 4ull * nc);
+                if (!XR || !Cf || !cn || !cmax || !arg || !m1 || !m2 || !nx)
+                    return h->fail(KC_ENOMEM, "workspace allocation failed");
+                hipLaunchKernelGGL(k_gather_rows, g1((uint64_t)nc * d), dim3(256), 0, s, X, ld,
+                                   d, cand, nc, XR);
+                kc_stage_centers(X, nullptr, ld, d, n, nullptr, S + ns - nds, nds, nullptr,
+                                 kpad, dp, Cf, nullptr, cn, cmax, h->status_word, s);
+                hipEvent_t ev = h->span_begin(s);
+                kc_mindist(XR, nullptr, d, nc, d, Cf, nullptr, cn, kpad, arg, m1, m2, nx, s);
+                h->span_end("eim_dist", ev, 1, s);
+                hipLaunchKernelGGL(k_eim_bounds, g1(nc), dim3(256), 0, s, nc, d, cand, m1, nx,
+                                   cmax, lo, hi);
+            }
+            // keep / remove
+            kc_fill_u32(cnt + 4, 0u, 1, s);
+            hipLaunchKernelGGL(k_eim_decide, g1(nc), dim3(256), 0, s, nc, cand, lo, hi, tau,
+                               keep, unsure, cnt + 4);
+            hipLaunchKernelGGL(k_eim_exact, dim3(2048), dim3(256), 0, s, X, ld, d, cand, unsure,
+                               cnt + 4, S, ns, tau, keep, lo, hi);
+            kc_compact(C, keep, cand, nc, R2, cnt + 3, s);
+            std::swap(R, R2);
+            if (hipMemcpyAsync(&new_nr, cnt + 3, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipMemcpyAsync(&tau_h, tau, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return h->fail(KC_EHIP, "readback failed");
+        }
+        if (iters) {
+            kc_eim_iter& rec = iters[it];
+            rec.r_size = nr;
+            rec.ds_size = nds;
+            rec.h_size = nh;
+            rec.s_size = ns;
+            rec.tau = tau_h;
+            rec.p_s = pS;
+            rec.p_h = pH;
+        }
+        nr = new_nr;
+        ++it;
+    }
+    if (n_iters) *n_iters = it;
+
+    // C = S u R, ascending: mark and compact the index range
+    uint8_t* mark = fS;
+    uint32_t* Cidx = H;
+    hipMemsetAsync(mark, 0, n, s);
+    if (ns) hipLaunchKernelGGL(k_mark, g1(ns), dim3(256), 0, s, S, ns, mark);
+    if (nr) hipLaunchKernelGGL(k_mark, g1(nr), dim3(256), 0, s, R, nr, mark);
+    kc_compact(C, mark, nullptr, n, Cidx, cnt + 5, s);
+    uint32_t nc = 0;
+    rc = kc_read_u32(h, cnt + 5, &nc, s);
+    if (rc) return rc;
+    if (n_sample) *n_sample = nc;
+    int64_t* C64 = sample ? sample : (int64_t*)h->ws("e.C64", 8ull * nc);
+    if (!C64) return h->fail(KC_ENOMEM, "workspace allocation failed");
+    hipLaunchKernelGGL(k_u32_to_i64, g1(nc), dim3(256), 0, s, Cidx, nc, C64);
+
+    // Gonzalez on the sample (first center: its smallest index), then the
+    // covering radius over all points
+    std::vector<KcGonJob> jobs(1);
+    jobs[0].X = nullptr;
+    jobs[0].ld = ld;
+    jobs[0].len = nc;
+    jobs[0].first = 0;
+    jobs[0].k = (uint32_t)k;
+    KcGonRun RG;
+    KcGonHost HG;
+    rc = kc_plan_gon(h, "e2.", d, 1024, jobs, RG, HG);
+    if (rc) return rc;
+    const uint32_t padded = kc_pad64(nc);
+    hipLaunchKernelGGL(k_gather_soa32, g1(padded), dim3(256), 0, s, X, ld, d, Cidx, nc, padded,
+                       (float*)RG.xs, RG.stride);
+    kc_enqueue_gon_prep(RG, HG, jobs, s);
+    bool done = false;
+    if (h->allow_resident) {
+        const uint32_t G = kc_resident_blocks_for(d, nc);
+        if (G > 0 && (int)G <= h->resident_max(d)) {
+            const uint64_t sw = kc_resident_slot_words((int)k, G);
+            u64* slots = (u64*)h->ws("e2.slots", 8ull * sw);
+            uint32_t* abort_flag = (uint32_t*)h->ws("e2.abort", 64);
+            if (!slots || !abort_flag) return h->fail(KC_ENOMEM, "workspace allocation failed");
+            kc_fill_u64(slots, 0ull, sw, s);
+            kc_fill_u32(abort_flag, 0u, 1, s);
+            if (kc_gon_resident(d, G, RG.xs, RG.stride, 0, nc, nullptr, 0, (int)k, RG.mind,
+                                RG.keys, slots, abort_flag, h->spin_limit, s) == hipSuccess) {
+                kc_or_status(abort_flag, h->status_word, 1u, s);
+                done = true;
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+    }
+    if (!done) kc_enqueue_gon_steps(RG, s);
+    kc_gon_finish(RG, centers, n_centers, nullptr, nullptr, nullptr, C64, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
+    return kc_assign_run(h, pts, centers, (uint32_t)k, n_centers, nullptr, radius, s, "e3.");
+}

@@ -70,6 +70,7 @@ struct KcGonJob {
 struct KcGonHost {
     std::vector<KcSeg> segs;
     std::vector<uint32_t> blk_seg, blk_start, pairs_seg, pairs_t;
+    std::vector<uint32_t> nblk_at;   // see KcGonRun::nblk_at
 };
 
 int kc_check_points(kc_handle* h, const kc_points* p, bool need_bf16_if_asked);

@@ -45,6 +45,9 @@ struct KcGonRun {
     double band = 0.0;          // 2 gamma_{d+2} + 4u
     uint64_t keysum = 0;        // keys in use (host)
     uint32_t tile = 1024;       // points per step block (host)
+    // host [kmax]: blocks still active at step t when segments are ordered by
+    // descending k (their tiles then form a prefix); NULL: all blocks
+    const uint32_t* nblk_at = nullptr;
 };
 
 void kc_fill_u64(u64* p, u64 v, uint64_t n, hipStream_t s);

@@ -325,8 +325,12 @@ int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int3
     });
     if (rc) return rc;
 
-    // ---- covering radius over all points
-    return kc_assign_run(h, pts, centers, (uint32_t)k, n_centers, nullptr, radius, s, "m3.");
+    // ---- covering radius over all points: FP32 MFMA in either precision (one
+    // pass over the points; the FP32 bound leaves far fewer points for FP64)
+    kc_points p32 = *pts;
+    p32.prec = KC_FP32;
+    p32.bf16 = nullptr;
+    return kc_assign_run(h, &p32, centers, (uint32_t)k, n_centers, nullptr, radius, s, "m3.");
 }
 
 }  // extern "C"

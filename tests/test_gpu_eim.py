@@ -1,0 +1,106 @@
+"""GPU parity of kcenter_eim against the FP64 oracle.
+
+Every draw (Philox4x64-10) and every keep/remove decision is certified, so
+the sample C = S u R and the per-iteration records (sizes, probabilities,
+the threshold tau) must equal the oracle's exactly.  The final Gonzalez on
+the sample is replayed through the oracle (certified ties only) and the
+radius is the exact FP64 covering radius of the GPU's centers."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def band(d):
+    m = d + 2
+    return 2 * m * U32 / (1 - m * U32) + 1e-12
+
+
+@pytest.fixture(scope="module")
+def kc():
+    import paper_1604_03228_amd as kc
+    assert torch.cuda.is_available()
+    return kc
+
+
+def gpu_eim(kc, X, k, eps, phi, seed, max_iters=64):
+    h = kc.Handle()
+    Xd = torch.from_numpy(X).cuda()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        c, nc, r, smp, its = kc.eim(Xd, k, eps, phi, seed, max_iters, handle=h)
+        assert h.device_status() == 0
+    st.synchronize()
+    return dict(centers=c.cpu().numpy(), n_centers=int(nc.item()),
+                radius=float(r.item()), sample=smp.cpu().numpy(), iters=its)
+
+
+def check(orc, X, k, eps, phi, seed, g):
+    o = orc.eim(X, k, eps, phi, seed)
+    assert np.array_equal(g["sample"], o["sample"])
+    assert len(g["iters"]) == len(o["iters"])
+    for a, b in zip(g["iters"], o["iters"]):
+        for key in ("r_size", "ds_size", "h_size", "s_size"):
+            assert a[key] == b[key], key
+        assert a["p_s"] == b["p_s"] and a["p_h"] == b["p_h"]
+        assert a["tau"] == b["tau"]
+    C = o["sample"]
+    got = g["n_centers"]
+    loc = np.searchsorted(C, g["centers"][:got])
+    assert np.array_equal(C[loc], g["centers"][:got])
+    bad, ties, _ = orc.gon_replay(X[C], k, loc, band(X.shape[1]))
+    assert bad == -1
+    _, R = orc.assign(X, g["centers"][:got])
+    assert g["radius"] == R
+    if ties == 0:
+        assert np.array_equal(g["centers"], o["centers"])
+        assert g["radius"] == o["radius"]
+    return o
+
+
+def test_no_sampling_is_gon(kc, orc):
+    X = np.random.default_rng(41).normal(size=(1000, 3)).astype(np.float32)
+    g = gpu_eim(kc, X, 10, 0.1, 8.0, 1)
+    o = check(orc, X, 10, 0.1, 8.0, 1, g)
+    assert g["iters"] == [] and len(g["sample"]) == 1000
+
+
+def test_one_iteration(kc, orc):
+    X = np.random.default_rng(42).normal(size=(20000, 2)).astype(np.float32)
+    g = gpu_eim(kc, X, 2, 0.1, 1.0, 1234)
+    check(orc, X, 2, 0.1, 1.0, 1234, g)
+    assert len(g["iters"]) == 1
+
+
+@pytest.mark.parametrize("phi", [1.0, 4.0, 6.0, 8.0])
+def test_iterations_gauss(kc, orc, phi):
+    rng = np.random.default_rng(int(phi))
+    X = (rng.normal(size=(60000, 3)) * 10).astype(np.float32)
+    g = gpu_eim(kc, X, 3, 0.1, phi, 7 + int(phi))
+    check(orc, X, 3, 0.1, phi, 7 + int(phi), g)
+    assert len(g["iters"]) >= 1
+
+
+def test_all_duplicates(kc, orc):
+    X = np.ones((10000, 2), np.float32)
+    g = gpu_eim(kc, X, 1, 0.5, 1.0, 3)
+    check(orc, X, 1, 0.5, 1.0, 3, g)
+    assert len(g["iters"]) == 1 and g["radius"] == 0.0
+
+
+def test_unbalanced_blobs(kc, orc):
+    from paper_1604_03228_amd import workloads as W
+    X = W.points_gauss_mixture(100_000, 8, 25, seed=77, heavy=0.9)
+    g = gpu_eim(kc, X, 20, 0.1, 4.0, 5 * 2**32 + 1)
+    check(orc, X, 20, 0.1, 4.0, 5 * 2**32 + 1, g)
+
+
+def test_max_iters_reports_noconv(kc):
+    X = np.random.default_rng(5).normal(size=(60000, 3)).astype(np.float32)
+    with pytest.raises(kc.KCenterError) as e:
+        gpu_eim(kc, X, 3, 0.1, 8.0, 9, max_iters=1)
+    assert e.value.status == -4
