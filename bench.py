@@ -42,7 +42,34 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mrg", action="store_true")
     ap.add_argument("--engine", choices=["auto", "stream"], default="auto")
+    ap.add_argument("--mrg-only", action="store_true",
+                    help="only the MRG FP32 vs BF16 comparison")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="copy 1 GiB device-to-device 5 times (calibrates "
+                         "the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def copy_probe():
+    import torch
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": nbytes,
+                      "copy_probe_bytes_written": nbytes, "launches": 5}))
+
+
+def kernel_source_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_1604_03228_amd", "csrc", f),
+                      "rb").read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(X, k):
@@ -58,11 +85,17 @@ def cpu_baseline(X, k):
                       % (len(X), X.shape[1], k, dt)}
 
 
-def stored_traffic(kernel, workload):
+def stored_traffic(kernel, workload, sources):
+    """HBM bytes per launch measured by the FETCH_SIZE / WRITE_SIZE counters
+    (scaled by the copy-probe factor), as recorded in profiles/traffic.json;
+    None when absent or when the kernel's sources changed since."""
     try:
         t = json.load(open(PROFILE_TRAFFIC))
-        return t.get(kernel + "|" + workload)
-    except (OSError, ValueError):
+        e = t.get(kernel + "|" + workload)
+        if e is None or e.get("source_hash") != kernel_source_hash(sources):
+            return None
+        return e["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
         return None
 
 
@@ -106,9 +139,16 @@ def main():
               "on a single MI355X); --gpus %d is not supported" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if a.copy_probe:
+        copy_probe()
+        return
     import torch
     import paper_1604_03228_amd as kc
     from paper_1604_03228_amd import workloads as W
+
+    if a.mrg_only:
+        print(json.dumps({"mrg": bench_mrg(kc, torch, max(2, a.steps))}))
+        return
 
     n, d, k = 1_000_000, 10, a.k
     X = W.config2(n)
@@ -145,6 +185,7 @@ def main():
     stp_ms, stp_l, _ = h.timing_read("gon_step")
     if res_l > 0:
         kern = "k_gon_resident"
+        srcs = ["kc_resident.hip", "kc_device.h"]
         per = res_ms / res_l
         flops = n * k * 3 * d             # sub + fma per coordinate
         ach = flops / (per * 1e-3) / 1e12
@@ -155,6 +196,7 @@ def main():
                 "work_per_launch": "%d updates x %d flop" % (n * k, 3 * d)}
     else:
         kern = "k_gon_step"
+        srcs = ["kc_gon.hip", "kc_device.h"]
         per = stp_ms / stp_l
         byt = n * (4 * d + 8)             # read d coords + mind, write mind
         ach = byt / (per * 1e-3) / 1e9
@@ -163,7 +205,8 @@ def main():
                 "frac": ach / HBM_PEAK_GBS,
                 "avg_launch_ms": per, "launches": stp_l,
                 "work_per_launch": "%d points x %d B" % (n, 4 * d + 8)}
-    roof["traffic"] = stored_traffic(kern, "gon_intgrid_n1000000_d10_k%d" % k)
+    roof["traffic"] = stored_traffic(kern, "gon_intgrid_n1000000_d10_k%d" % k,
+                                     srcs)
 
     line = {"metric": "n*k dist-updates/s (Gonzalez, 1 GPU)",
             "value": value, "unit": "dist-updates/s", "n_gpus": 1,
