@@ -125,10 +125,51 @@ def bench_mrg(kc, torch, steps):
         out[mode + "_ms"] = e0.elapsed_time(e1) / steps
         cents[mode] = r[0].cpu().numpy()
         out[mode + "_radius"] = float(r[2].item())
+        if mode == "bf16":
+            out["bf16_rescored_per_step"] = h.counter("bf16_rescored") / k
+            out["bf16_listed_per_step"] = h.counter("bf16_listed") / k
         h.close()
     out["same_centers"] = bool(np.array_equal(cents["fp32"], cents["bf16"]))
     out["workload"] = "mrg_gauss50_n8000000_d16_m64_k200"
     out["speedup_bf16"] = out["fp32_ms"] / out["bf16_ms"]
+    return out
+
+
+def bench_gon_bf16(kc, torch, steps):
+    """Gonzalez k=500 on the 5,000,000 x 41 mixed-scale workload, FP32 vs
+    BF16 stream + exact FP32 rescoring (same centers required)."""
+    from paper_1604_03228_amd import workloads as W
+    X, Xb = W.config4()
+    Xd = torch.from_numpy(X).cuda()
+    B = torch.from_numpy(Xb.view(np.int16)).cuda()
+    k = W.CONFIG4["k"]
+    out = {"workload": "gon_mixed41_n5000000_k500"}
+    cents = {}
+    for mode in ("fp32", "bf16"):
+        h = kc.Handle()
+        st = torch.cuda.Stream()
+        bf = B if mode == "bf16" else None
+        with torch.cuda.stream(st):
+            for _ in range(2):
+                r = kc.gonzalez(Xd, k, 0, bf16=bf, handle=h)
+            st.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(steps):
+                r = kc.gonzalez(Xd, k, 0, bf16=bf, handle=h)
+            e1.record(st)
+            st.synchronize()
+        out[mode + "_ms"] = e0.elapsed_time(e1) / steps
+        cents[mode] = r[0].cpu().numpy()
+        out[mode + "_radius"] = float(r[1][-1].item())
+        if mode == "bf16":
+            out["bf16_rescored_per_step"] = h.counter("bf16_rescored") / k
+            out["bf16_listed_per_step"] = h.counter("bf16_listed") / k
+        h.close()
+    out["same_centers"] = bool(np.array_equal(cents["fp32"], cents["bf16"]))
+    out["speedup_bf16"] = out["fp32_ms"] / out["bf16_ms"]
+    out["dist_updates_per_s_bf16"] = len(X) * k / (out["bf16_ms"] * 1e-3)
     return out
 
 
@@ -147,7 +188,8 @@ def main():
     from paper_1604_03228_amd import workloads as W
 
     if a.mrg_only:
-        print(json.dumps({"mrg": bench_mrg(kc, torch, max(2, a.steps))}))
+        print(json.dumps({"mrg": bench_mrg(kc, torch, max(2, a.steps)),
+                          "gon_bf16": bench_gon_bf16(kc, torch, max(2, a.steps))}))
         return
 
     n, d, k = 1_000_000, 10, a.k
@@ -223,6 +265,7 @@ def main():
     if not a.no_mrg:
         try:
             line["mrg"] = bench_mrg(kc, torch, max(2, min(a.steps, 5)))
+            line["gon_bf16"] = bench_gon_bf16(kc, torch, max(2, min(a.steps, 5)))
         except kc.KCenterError as e:
             line["mrg"] = {"error": str(e)}
     if not a.no_cpu:

@@ -75,7 +75,7 @@ const char* kc_last_error(const kc_handle* h);
  * graph, default 1); "resident" 0/1 (use the register-resident persistent
  * Gonzalez kernel when the points fit, default 1); "timing" 0/1 (record
  * kernel timing events, default 0); "spin_limit" (polls before a persistent
- * kernel's barrier wait gives up, default 2^24).  KC_EINVAL for an unknown
+ * kernel's barrier wait gives up, default 2^20).  KC_EINVAL for an unknown
  * name or a value out of range. */
 int kc_set_option(kc_handle* h, const char* name, int64_t value);
 
@@ -90,6 +90,12 @@ int kc_set_option(kc_handle* h, const char* name, int64_t value);
  * intervals, for one name, and forgets them.  KC_EINVAL for NULL args. */
 int kc_timing_read(kc_handle* h, const char* name, double* ms, int64_t* launches,
                    int64_t* intervals);
+
+/* Work counters of the most recent BF16+rescore Gonzalez run on the handle
+ * (synchronises the device): "bf16_listed" is the number of (point, step)
+ * pairs listed by the stream as possible candidates, "bf16_rescored" the
+ * number rescored exactly in FP32.  KC_EINVAL for an unknown name. */
+int kc_counter_read(kc_handle* h, const char* name, int64_t* value);
 
 /* Synchronises `stream`, then reads and clears the handle's device status
  * word (bit 0: a persistent kernel's grid barrier timed out; bit 1: a

@@ -56,6 +56,7 @@ class KCenterError(RuntimeError):
 
 EXPORTS = ["kc_create", "kc_destroy", "kc_strerror", "kc_last_error",
            "kc_set_option", "kc_device_status", "kc_timing_read",
+           "kc_counter_read",
            "kcenter_gonzalez",
            "kcenter_mrg", "kcenter_assign", "kcenter_eim", "kcenter_batch"]
 
@@ -83,6 +84,7 @@ def load_library(path=LIB_PATH):
     L.kc_timing_read.argtypes = [_p, ctypes.c_char_p,
                                  ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+    L.kc_counter_read.argtypes = [_p, ctypes.c_char_p, ctypes.POINTER(_i64)]
     L.kcenter_gonzalez.argtypes = [_p, ctypes.POINTER(KcPoints), _i64, _i64,
                                    _p, _p, _p, _p]
     L.kcenter_mrg.argtypes = [_p, ctypes.POINTER(KcPoints), _p, _i32, _i64,
@@ -95,7 +97,7 @@ def load_library(path=LIB_PATH):
                               ctypes.POINTER(_i32), _p]
     L.kcenter_batch.argtypes = [_p, _p, _i32, _p]
     for name in ("kc_create", "kc_set_option", "kc_device_status",
-                 "kc_timing_read",
+                 "kc_timing_read", "kc_counter_read",
                  "kcenter_gonzalez", "kcenter_mrg", "kcenter_assign",
                  "kcenter_eim", "kcenter_batch"):
         getattr(L, name).restype = ctypes.c_int
@@ -154,6 +156,13 @@ class Handle:
             self._h, name.encode(), ctypes.byref(ms), ctypes.byref(la),
             ctypes.byref(iv)))
         return ms.value, la.value, iv.value
+
+    def counter(self, name):
+        """A work counter of the last BF16 run (see kc_counter_read)."""
+        v = _i64(0)
+        self._check(load_library().kc_counter_read(self._h, name.encode(),
+                                                   ctypes.byref(v)))
+        return v.value
 
     def device_status(self):
         """Synchronise the current stream and read/clear the status word."""

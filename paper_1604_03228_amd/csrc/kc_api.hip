@@ -417,6 +417,32 @@ int kc_timing_read(kc_handle* h, const char* name, double* ms, int64_t* launches
     return KC_OK;
 }
 
+int kc_counter_read(kc_handle* h, const char* name, int64_t* value)
+{
+    if (!h || !name || !value) return KC_EINVAL;
+    const uint32_t* src = nullptr;
+    size_t words = h->last_bf16_kmax, every = 1;
+    if (!strcmp(name, "bf16_listed")) {
+        src = h->last_bf16_listcnt;   // [kmax][KC_PARTS][32]: one count per line
+        words *= KC_PARTS * 32;
+        every = 32;
+    } else if (!strcmp(name, "bf16_rescored")) {
+        src = h->last_bf16_nresc;
+    } else {
+        return h->fail(KC_EINVAL, "unknown counter '%s'", name);
+    }
+    *value = 0;
+    if (!src || words == 0) return KC_OK;
+    std::vector<uint32_t> v(words);
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(v.data(), src, 4 * v.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+        hipError_t e = hipGetLastError();
+        return h->fail(KC_EHIP, "counter read: %s", hipGetErrorString(e));
+    }
+    for (size_t i = 0; i < words; i += every) *value += v[i];
+    return KC_OK;
+}
+
 int kc_device_status(kc_handle* h, void* stream, uint32_t* status)
 {
     if (!h || !status) return KC_EINVAL;

@@ -11,16 +11,18 @@
 //   hi(s) = (1+gamma) (sqrt(s/(1-gamma)) + e_i)^2
 // (triangle inequality for the BF16 rounding, gamma for the FP32 sums; both
 // bounds are monotone in s, so they survive the min over steps).  A step:
-//   k_gon_step_bf16   update s_i, reduce max lo into per-step partial slots,
-//                     record each block's max hi;
-//   k_bf16_cand       every point with hi_i >= L_t = max lo becomes a
-//                     candidate (blocks whose max hi is below L_t skip);
-//   k_bf16_rescore    one wave per candidate computes its exact canonical
-//                     FP32 min-distance over the centers chosen since it was
-//                     last rescored (cached per point) and offers the packed
-//                     key to the step's argmax slots.
+//   k_gon_step_bf16   updates s_i, reduces the largest lower bound into the
+//                     step's partial slots (L_t is their max) and lists every
+//                     point whose upper bound reaches its own tile's largest
+//                     lower bound -- a superset of the candidates, since a
+//                     tile's bound never exceeds L_t;
+//   k_bf16_rescore    keeps the listed points with hi_i >= L_t and computes
+//                     their exact canonical FP32 min-distance with one wave
+//                     each, over the centers chosen since the point was last
+//                     rescored (cached per point), then offers the packed key
+//                     to the step's argmax slots.
 // The farthest point of the FP32 path (lowest index on ties) always has
-// hi >= L_t, so the argmax over candidates is exactly the FP32 path's choice.
+// hi >= m >= L_t, so the argmax over candidates is exactly the FP32 path's.
 #include "kc_host.h"
 
 #define KC_BF_PTS 8   // points per lane: one 16-byte load per coordinate row
@@ -76,8 +78,8 @@ void kc_stage_bf16(const float* X, const uint16_t* Xb, int64_t ld, int d, uint64
                        row0, len, xb, ex, stride, base, padded);
 }
 
-// lo partial maxima: lpart[(key * KC_PARTS + slot) * 32] (u32 bits of a
-// non-negative float, one 128-byte line per slot)
+// largest-lower-bound partial maxima: lpart[(key * KC_PARTS + slot) * 32]
+// (u32 bits of a non-negative float, one 128-byte line per slot)
 __device__ __forceinline__ uint32_t* kc_lpart(uint32_t* lpart, uint64_t key, uint32_t slot)
 {
     return lpart + (key * KC_PARTS + slot) * 32;
@@ -97,15 +99,18 @@ template <int D>
 __global__ __launch_bounds__(KC_BLOCK) void k_gon_step_bf16(
     const uint16_t* __restrict__ xb, const float* __restrict__ xs, uint64_t stride, int d_rt,
     const float* __restrict__ ex, float* __restrict__ mind, u64* __restrict__ part,
-    uint32_t* __restrict__ lpart, float* __restrict__ blk_hi, float* __restrict__ ccoord,
-    const KcSeg* __restrict__ segs, const uint32_t* __restrict__ blk_seg,
-    const uint32_t* __restrict__ blk_start, int t, float g)
+    uint32_t* __restrict__ lpart, float* __restrict__ ccoord, const KcSeg* __restrict__ segs,
+    const uint32_t* __restrict__ blk_seg, const uint32_t* __restrict__ blk_start, int t,
+    float g, u64* __restrict__ list, float* __restrict__ list_hi,
+    uint32_t* __restrict__ listcnt, uint32_t region)
 {
     const int d = D > 0 ? D : d_rt;
     __shared__ float red[KC_BLOCK / 64];
-    __shared__ float redh[KC_BLOCK / 64];
+    __shared__ float sL;
+    __shared__ uint32_t scount, sbase;
     const uint32_t b = blockIdx.x;
-    const KcSeg sg = segs[blk_seg[b]];
+    const uint32_t sidx = blk_seg[b];
+    const KcSeg sg = segs[sidx];
     if ((uint32_t)t >= sg.ksteps) return;
     const uint32_t loc = blk_start[b] + threadIdx.x * KC_BF_PTS;
     const uint64_t col = sg.base + loc;
@@ -138,8 +143,8 @@ __global__ __launch_bounds__(KC_BLOCK) void k_gon_step_bf16(
         c = __builtin_amdgcn_readfirstlane(kc_key_idx(pv));
     }
     const float* xc = xs + sg.base + c;   // exact FP32 center, uniform
-    if (b == 0 || blk_start[b] == 0) {
-        // the segment's first block records the center's coordinates
+    if (blk_start[b] == 0) {
+        // the segment's first tile records the center's coordinates
         for (int j = threadIdx.x; j < d; j += KC_BLOCK)
             ccoord[(uint64_t)(sg.keyoff + t) * d + j] = xc[(uint64_t)j * stride];
     }
@@ -168,7 +173,10 @@ __global__ __launch_bounds__(KC_BLOCK) void k_gon_step_bf16(
             }
         }
     }
-    float lo = 0.f, hi = 0.f;
+    float lo = 0.f;
+    float hq[KC_BF_PTS];
+#pragma unroll
+    for (int q = 0; q < KC_BF_PTS; ++q) hq[q] = -1.f;
     if (live) {
         float mm[KC_BF_PTS] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
         const float ee[KC_BF_PTS] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
@@ -177,186 +185,168 @@ __global__ __launch_bounds__(KC_BLOCK) void k_gon_step_bf16(
             mm[q] = fminf(mm[q], s[q]);
             if (loc + q < sg.len) {
                 lo = fmaxf(lo, kc_bf_lo(mm[q], ee[q], g));
-                hi = fmaxf(hi, kc_bf_hi(mm[q], ee[q], g));
+                hq[q] = kc_bf_hi(mm[q], ee[q], g);
             }
         }
         *(float4*)(mind + col) = make_float4(mm[0], mm[1], mm[2], mm[3]);
         *(float4*)(mind + col + 4) = make_float4(mm[4], mm[5], mm[6], mm[7]);
     }
-    for (int off = 32; off >= 1; off >>= 1) {
-        lo = fmaxf(lo, __shfl_xor(lo, off, 64));
-        hi = fmaxf(hi, __shfl_xor(hi, off, 64));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        red[threadIdx.x >> 6] = lo;
-        redh[threadIdx.x >> 6] = hi;
-    }
+    for (int off = 32; off >= 1; off >>= 1) lo = fmaxf(lo, __shfl_xor(lo, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lo;
+    if (threadIdx.x == 0) scount = 0;
     __syncthreads();
+    const uint32_t slot = b % KC_PARTS;
     if (threadIdx.x == 0) {
-        float L = red[0], Hh = redh[0];
-        for (int w = 1; w < KC_BLOCK / 64; ++w) {
-            L = fmaxf(L, red[w]);
-            Hh = fmaxf(Hh, redh[w]);
-        }
-        blk_hi[b] = Hh;
-        uint32_t* p = kc_lpart(lpart, sg.keyoff + t, b % KC_PARTS);
+        float L = red[0];
+        for (int w = 1; w < KC_BLOCK / 64; ++w) L = fmaxf(L, red[w]);
+        sL = L;
+        uint32_t* p = kc_lpart(lpart, sg.keyoff + t, slot);
         const uint32_t lb = __float_as_uint(L);
         if (lb > __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             __hip_atomic_fetch_max(p, lb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-}
-
-// Candidates of step t: hi_i >= L_t.  cand entries are (segment << 32 | loc);
-// ncand[t] counts them over all segments (a fresh counter per step, so the
-// shared candidate list never needs resetting inside the step loop).
-__global__ void k_bf16_cand(const float* __restrict__ mind, const float* __restrict__ ex,
-                            const float* __restrict__ blk_hi, const uint32_t* __restrict__ lpart,
-                            const KcSeg* __restrict__ segs, const uint32_t* __restrict__ blk_seg,
-                            const uint32_t* __restrict__ blk_start, int t, float g,
-                            u64* __restrict__ cand, uint32_t* __restrict__ ncand, uint32_t cap,
-                            const u64* __restrict__ part)
-{
-    const uint32_t b = blockIdx.x;
-    const uint32_t sidx = blk_seg[b];
-    const KcSeg sg = segs[sidx];
-    if ((uint32_t)t >= sg.ksteps) return;
-    if (t > 0) {
-        // a segment that stopped at the previous step has nothing to do
-        const int lane = threadIdx.x & 63;
-        u64 pv = 0;
-        if (lane < KC_PARTS)
-            pv = __hip_atomic_load(kc_part_slot((u64*)part, sg.keyoff + t - 1, lane),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        pv = kc_wave_max64(pv);
-        if ((pv >> 32) == 0) return;
-    }
-    const float L = kc_lpart_max(lpart, sg.keyoff + t);
-    if (blk_hi[b] < L) return;
-    for (int q = 0; q < KC_BF_PTS; ++q) {
-        const uint32_t loc = blk_start[b] + q * KC_BLOCK + threadIdx.x;
-        if (loc >= sg.len) continue;
-        const uint64_t col = sg.base + loc;
-        if (kc_bf_hi(mind[col], ex[col], g) >= L) {
-            const uint32_t slot = atomicAdd(&ncand[t], 1u);
-            if (slot < cap) cand[slot] = ((u64)sidx << 32) | loc;
-        }
+    __syncthreads();
+    // list the tile's points that can reach the tile's own largest lower
+    // bound (a lower bound of L_t, so the list is a superset of the step's
+    // candidates; the rescoring kernel applies L_t itself)
+    const float Lb = sL;
+    uint32_t mine = 0;
+#pragma unroll
+    for (int q = 0; q < KC_BF_PTS; ++q) mine += hq[q] >= Lb;
+    const uint32_t off = mine ? atomicAdd(&scount, mine) : 0u;
+    __syncthreads();
+    // one of KC_PARTS list regions (each on its own counter line), so tiles do
+    // not serialise on one address; region `slot` holds at most the points of
+    // the tiles b with b mod KC_PARTS == slot
+    if (threadIdx.x == 0)
+        sbase = scount ? slot * region + atomicAdd(&listcnt[((uint64_t)t * KC_PARTS + slot) * 32],
+                                                   scount)
+                       : 0u;
+    __syncthreads();
+    if (mine) {
+        uint32_t w = sbase + off;
+#pragma unroll
+        for (int q = 0; q < KC_BF_PTS; ++q)
+            if (hq[q] >= Lb) {
+                list[w] = ((u64)sidx << 32) | (loc + q);
+                list_hi[w] = hq[q];
+                ++w;
+            }
     }
 }
 
-// One wave per candidate: exact canonical FP32 min-distance over the centers
-// chosen since the point was last rescored (exm/exupto cache it), then its
-// packed key is offered to step t's argmax slots of its segment.
-__global__ void k_bf16_rescore(const u64* __restrict__ cand,
-                               const uint32_t* __restrict__ ncand_total, uint32_t cap,
-                               const float* __restrict__ xs, uint64_t stride, int d,
-                               const float* __restrict__ ccoord, const KcSeg* __restrict__ segs,
-                               float* __restrict__ exm, uint32_t* __restrict__ exupto,
-                               u64* __restrict__ part, int t)
-{
-    const int lane = threadIdx.x & 63;
-    uint32_t nc = *ncand_total;
-    if (nc > cap) nc = cap;
-    const uint32_t waves = gridDim.x * (blockDim.x / 64);
-    for (uint32_t q = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); q < nc;
-         q += waves) {
-        const u64 e = cand[q];
-        const uint32_t sidx = (uint32_t)(e >> 32), loc = (uint32_t)e;
-        const KcSeg sg = segs[sidx];
-        const uint64_t col = sg.base + loc;
-        const uint32_t from = exupto[col];
-        float best = exm[col];
-        for (uint32_t j = from + lane; j <= (uint32_t)t; j += 64) {
-            const float* cj = ccoord + (uint64_t)(sg.keyoff + j) * d;
-            float s = 0.f;
-            for (int u = 0; u < d; ++u) s = kc_d32_step(s, xs[(uint64_t)u * stride + col], cj[u]);
-            best = fminf(best, s);
-        }
-        for (int off = 32; off >= 1; off >>= 1) best = fminf(best, __shfl_xor(best, off, 64));
-        if (lane == 0) {
-            exm[col] = best;
-            exupto[col] = (uint32_t)t + 1;
-            kc_part_offer(part, sg.keyoff + t, q % KC_PARTS, kc_pack(best, loc));
-        }
-    }
-}
-
-// Candidates and their rescoring in one pass over the step's tiles: a block
-// whose largest upper bound is below L_t leaves at once; otherwise it lists
-// its candidates in LDS, rescores each with one wave (lanes over the centers
-// chosen since the point was last rescored) and offers the block's best key.
-__global__ __launch_bounds__(KC_BLOCK) void k_bf16_cand_rescore(
-    const float* __restrict__ mind, const float* __restrict__ ex,
-    const float* __restrict__ blk_hi, const uint32_t* __restrict__ lpart,
+// Rescoring of step t.  Every block first computes L_t of each segment (the
+// max over its partial slots) into LDS.  Then each wave takes 64 listed
+// points at a time, one per lane, keeps those with hi >= L_t of their segment
+// and rescores the kept ones one after another with the whole wave: lanes
+// over the centers chosen since the point was last rescored (exm/exupto
+// cache it), canonical FP32, then the packed key goes to the step's argmax
+// slots.  nresc[t] counts the rescored points.
+#define KC_RESC_SEGS 1024   // segments whose L_t fits the LDS table
+__global__ __launch_bounds__(256) void k_bf16_rescore(
+    const u64* __restrict__ list, const float* __restrict__ list_hi,
+    const uint32_t* __restrict__ listcnt, uint32_t region, const uint32_t* __restrict__ lpart,
     const float* __restrict__ xs, uint64_t stride, int d, const float* __restrict__ ccoord,
-    const KcSeg* __restrict__ segs, const uint32_t* __restrict__ blk_seg,
-    const uint32_t* __restrict__ blk_start, int t, float g, float* __restrict__ exm,
-    uint32_t* __restrict__ exupto, u64* __restrict__ part)
+    const KcSeg* __restrict__ segs, int nseg, float* __restrict__ exm,
+    uint32_t* __restrict__ exupto, u64* __restrict__ part, uint32_t* __restrict__ nresc, int t)
 {
-    __shared__ uint32_t list[KC_BF_TILE];
-    __shared__ uint32_t nlist;
-    __shared__ float sL;
-    __shared__ u64 red[KC_BLOCK / 64];
-    const uint32_t b = blockIdx.x;
-    const KcSeg sg = segs[blk_seg[b]];
-    if ((uint32_t)t >= sg.ksteps) return;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (w == 0) {
-        u64 pv = 1ull << 32;
-        if (t > 0) {   // a segment that stopped at the previous step is done
-            pv = 0;
-            if (lane < KC_PARTS)
-                pv = __hip_atomic_load(kc_part_slot(part, sg.keyoff + t - 1, lane),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            pv = kc_wave_max64(pv);
+    __shared__ float sL[KC_RESC_SEGS];
+    __shared__ uint32_t sinc[KC_PARTS];
+    __shared__ float sx[4 * KC_MAXD];   // one coordinate row per wave
+    const int lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (blockDim.x / 64);
+    // L_t per segment (the step's partial slots are final: written by the
+    // step kernel that ran before this one); KC_PARTS lanes per segment
+    const int nsl = nseg < KC_RESC_SEGS ? nseg : KC_RESC_SEGS;
+    for (int s0 = 0; s0 < nsl; s0 += (int)blockDim.x / KC_PARTS) {
+        const int s = s0 + (int)threadIdx.x / KC_PARTS, p = threadIdx.x % KC_PARTS;
+        uint32_t x = 0;
+        if (s < nsl) {
+            const KcSeg sg = segs[s];
+            if ((uint32_t)t < sg.ksteps)
+                x = lpart[((uint64_t)(sg.keyoff + t) * KC_PARTS + p) * 32];
         }
-        uint32_t lv = 0;
-        if (lane < KC_PARTS)
-            lv = __hip_atomic_load(lpart + ((uint64_t)(sg.keyoff + t) * KC_PARTS + lane) * 32,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        for (int off = 32; off >= 1; off >>= 1) {
-            const uint32_t o = __shfl_xor(lv, off, 64);
-            lv = o > lv ? o : lv;
+        for (int off = KC_PARTS / 2; off >= 1; off >>= 1) {
+            const uint32_t o = __shfl_xor(x, off, 64);
+            x = o > x ? o : x;
         }
-        if (lane == 0) {
-            // stopped segments and blocks without candidates skip the step
-            sL = ((pv >> 32) == 0 || blk_hi[b] < __uint_as_float(lv)) ? -1.f
-                                                                     : __uint_as_float(lv);
-            nlist = 0;
+        if (p == 0 && s < nsl) sL[s] = __uint_as_float(x);
+    }
+    if (threadIdx.x < 64) {
+        // inclusive prefix of the region counts
+        uint32_t inc = lane < KC_PARTS ? listcnt[((uint64_t)t * KC_PARTS + lane) * 32] : 0u;
+        for (int off = 1; off < KC_PARTS; off <<= 1) {
+            const uint32_t y = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += y;
         }
+        if (lane < KC_PARTS) sinc[lane] = inc;
     }
     __syncthreads();
-    const float L = sL;
-    if (L < 0.f) return;
-    for (int q = 0; q < KC_BF_PTS; ++q) {
-        const uint32_t loc = blk_start[b] + q * KC_BLOCK + threadIdx.x;
-        if (loc < sg.len) {
+    const uint32_t total = sinc[KC_PARTS - 1];
+    // every wave takes an equal share of the list, at most 64 entries at a time,
+    // so the rescoring of kept entries spreads over all waves of the grid
+    const uint32_t wid = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    uint32_t share = (total + waves - 1) / waves;
+    if (share > 64) share = 64;
+    if (share == 0) share = 1;
+    float* xw = sx + (threadIdx.x >> 6) * KC_MAXD;
+    uint32_t done = 0;
+    for (uint32_t base = wid * share; base < total; base += waves * share) {
+        const uint32_t q = base + lane;
+        bool keep = false;
+        u64 e = 0;
+        if (lane < (int)share && q < total) {
+            // flat index -> (region, offset)
+            uint32_t rg = 0;
+            while (sinc[rg] <= q) ++rg;
+            const uint32_t before = rg ? sinc[rg - 1] : 0u;
+            const uint64_t qi = (uint64_t)rg * region + (q - before);
+            e = list[qi];
+            const uint32_t sidx = (uint32_t)(e >> 32);
+            float L;
+            if (sidx < KC_RESC_SEGS) {
+                L = sL[sidx];
+            } else {
+                uint32_t v = 0;
+                const KcSeg sg = segs[sidx];
+                for (uint32_t p = 0; p < KC_PARTS; ++p) {
+                    const uint32_t x = lpart[((uint64_t)(sg.keyoff + t) * KC_PARTS + p) * 32];
+                    v = x > v ? x : v;
+                }
+                L = __uint_as_float(v);
+            }
+            keep = list_hi[qi] >= L;
+        }
+        u64 mask = __ballot(keep);
+        while (mask) {
+            const int j = __ffsll((long long)mask) - 1;
+            mask &= mask - 1;
+            const u64 ej = __shfl(e, j, 64);
+            const uint32_t sidx = (uint32_t)(ej >> 32), loc = (uint32_t)ej;
+            const KcSeg sg = segs[sidx];
             const uint64_t col = sg.base + loc;
-            if (kc_bf_hi(mind[col], ex[col], g) >= L) list[atomicAdd(&nlist, 1u)] = loc;
+            // the point's coordinates once into this wave's LDS row
+            for (int u = lane; u < d; u += 64) xw[u] = xs[(uint64_t)u * stride + col];
+            const uint32_t from = exupto[col];
+            float best = exm[col];
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t c = from + lane; c <= (uint32_t)t; c += 64) {
+                const float* cj = ccoord + (uint64_t)(sg.keyoff + c) * d;
+                float acc = 0.f;
+                for (int u = 0; u < d; ++u) acc = kc_d32_step(acc, xw[u], cj[u]);
+                best = fminf(best, acc);
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int off = 32; off >= 1; off >>= 1) best = fminf(best, __shfl_xor(best, off, 64));
+            if (lane == 0) {
+                exm[col] = best;
+                exupto[col] = (uint32_t)t + 1;
+                kc_part_offer(part, sg.keyoff + t, (base + j) % KC_PARTS, kc_pack(best, loc));
+            }
+            ++done;
         }
     }
-    __syncthreads();
-    const uint32_t nl = nlist;
-    u64 key = 0;
-    for (uint32_t q = w; q < nl; q += KC_BLOCK / 64) {
-        const uint32_t loc = list[q];
-        const uint64_t col = sg.base + loc;
-        const uint32_t from = exupto[col];
-        float best = exm[col];
-        for (uint32_t j = from + lane; j <= (uint32_t)t; j += 64) {
-            const float* cj = ccoord + (uint64_t)(sg.keyoff + j) * d;
-            float s = 0.f;
-            for (int u = 0; u < d; ++u) s = kc_d32_step(s, xs[(uint64_t)u * stride + col], cj[u]);
-            best = fminf(best, s);
-        }
-        for (int off = 32; off >= 1; off >>= 1) best = fminf(best, __shfl_xor(best, off, 64));
-        if (lane == 0) {
-            exm[col] = best;
-            exupto[col] = (uint32_t)t + 1;
-        }
-        key = kc_umax64(key, kc_pack(best, loc));
-    }
-    key = kc_block_max64(key, red);
-    if (threadIdx.x == 0 && key) kc_part_offer(part, sg.keyoff + t, b % KC_PARTS, key);
+    if (lane == 0 && done) atomicAdd(&nresc[t], done);
 }
 
 // Final-radius candidates in BF16 mode: hi_i >= L_last * (1 - band), where
@@ -389,11 +379,12 @@ __global__ void k_bf16_radius_cand(const float* __restrict__ mind, const float* 
     }
 }
 
-#define KC_BF_CASE(DD)                                                                   \
-    case DD:                                                                             \
-        hipLaunchKernelGGL(k_gon_step_bf16<DD>, dim3(R.nblk), dim3(KC_BLOCK), 0, s, B.xb, \
-                           R.xs, R.stride, R.d, B.ex, R.mind, R.part, B.lpart, B.blk_hi,  \
-                           R.ccoord, R.segs, R.blk_seg, R.blk_start, t, B.g);             \
+#define KC_BF_CASE(DD)                                                                    \
+    case DD:                                                                              \
+        hipLaunchKernelGGL(k_gon_step_bf16<DD>, dim3(R.nblk), dim3(KC_BLOCK), 0, s, B.xb,  \
+                           R.xs, R.stride, R.d, B.ex, R.mind, R.part, B.lpart, R.ccoord,   \
+                           R.segs, R.blk_seg, R.blk_start, t, B.g, B.list, B.list_hi,      \
+                           B.listcnt, B.region);                                           \
         break;
 
 void kc_enqueue_bf16_steps(const KcGonRun& R, const KcBf16Run& B, hipStream_t s)
@@ -408,12 +399,13 @@ void kc_enqueue_bf16_steps(const KcGonRun& R, const KcBf16Run& B, hipStream_t s)
             KC_BF_CASE(41)
         default:
             hipLaunchKernelGGL(k_gon_step_bf16<0>, dim3(R.nblk), dim3(KC_BLOCK), 0, s, B.xb,
-                               R.xs, R.stride, R.d, B.ex, R.mind, R.part, B.lpart, B.blk_hi,
-                               R.ccoord, R.segs, R.blk_seg, R.blk_start, t, B.g);
+                               R.xs, R.stride, R.d, B.ex, R.mind, R.part, B.lpart, R.ccoord,
+                               R.segs, R.blk_seg, R.blk_start, t, B.g, B.list, B.list_hi,
+                               B.listcnt, B.region);
         }
-        hipLaunchKernelGGL(k_bf16_cand_rescore, dim3(R.nblk), dim3(KC_BLOCK), 0, s, R.mind,
-                           B.ex, B.blk_hi, B.lpart, R.xs, R.stride, R.d, R.ccoord, R.segs,
-                           R.blk_seg, R.blk_start, t, B.g, B.exm, B.exupto, R.part);
+        hipLaunchKernelGGL(k_bf16_rescore, dim3(B.rescore_blocks), dim3(256), 0, s, B.list,
+                           B.list_hi, B.listcnt, B.region, B.lpart, R.xs, R.stride, R.d,
+                           R.ccoord, R.segs, R.nseg, B.exm, B.exupto, R.part, B.nresc, t);
     }
     kc_part_collect(R.part, R.keys, R.keysum, s);
 }
@@ -432,7 +424,8 @@ void kc_enqueue_bf16_prep(const KcGonRun& R, const KcBf16Run& B, const KcGonHost
     kc_fill_u32(B.exupto, 0u, R.stride, s);
     kc_fill_u64(R.part, 0ull, R.keysum * KC_PARTS * KC_PSTRIDE, s);
     kc_fill_u32(B.lpart, 0u, R.keysum * KC_PARTS * 32, s);
-    kc_fill_u32(B.ncand, 0u, R.kmax, s);
+    kc_fill_u32(B.listcnt, 0u, (uint64_t)R.kmax * KC_PARTS * 32, s);
+    kc_fill_u32(B.nresc, 0u, R.kmax, s);
 }
 
 // Finishing in BF16 mode: centers, trace (FP64, from the centers' exact

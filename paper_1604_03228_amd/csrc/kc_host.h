@@ -26,7 +26,7 @@ struct kc_handle {
     int num_cu = 0;
     bool use_graphs = true;
     bool allow_resident = true;
-    uint32_t spin_limit = 1u << 24;   // polls before a barrier wait gives up
+    uint32_t spin_limit = 1u << 20;   // polls before a barrier wait gives up
     uint32_t* status_word = nullptr;  // device, see kc_device_status
     std::string last_error;
     std::map<std::string, DevBuf> bufs;
@@ -41,6 +41,10 @@ struct kc_handle {
     };
     std::map<std::string, std::vector<TimedSpan>> spans;
     std::vector<hipEvent_t> event_pool;
+    // per-step counters of the most recent BF16 run (device, [kmax])
+    const uint32_t* last_bf16_listcnt = nullptr;
+    const uint32_t* last_bf16_nresc = nullptr;
+    uint32_t last_bf16_kmax = 0;
 
     ~kc_handle();
     // Record the opening event of a timed span (no-op unless timing is on).

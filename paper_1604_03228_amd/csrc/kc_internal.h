@@ -81,10 +81,13 @@ struct KcBf16Run {
     uint16_t* xb = nullptr;       // SoA BF16 copy [d][stride]
     float* ex = nullptr;          // [stride] per-point BF16 rounding radius
     uint32_t* lpart = nullptr;    // [sum ksteps][KC_PARTS][32] max lower bound
-    float* blk_hi = nullptr;      // [nblk] max upper bound per block
+    u64* list = nullptr;          // [KC_PARTS * region] listed points of a step
+    float* list_hi = nullptr;     // [KC_PARTS * region] their upper bounds
+    uint32_t* listcnt = nullptr;  // [kmax][KC_PARTS][32] listed points per region
+    uint32_t region = 0;          // entries per list region (host)
+    uint32_t* nresc = nullptr;    // [kmax] rescored points per step
     float* exm = nullptr;         // [stride] cached exact FP32 min-distance
     uint32_t* exupto = nullptr;   // [stride] centers covered by exm
-    uint32_t* ncand = nullptr;    // [kmax] candidates per step
     uint32_t rescore_blocks = 256;
     float g = 0.f;                // gamma_{d+2} + 16u
 };

@@ -85,12 +85,22 @@ int kc_bf16_alloc(kc_handle* h, const std::string& pre, const KcGonRun& R, KcBf1
     B.ex = (float*)h->ws(pre + "ex", sizeof(float) * R.stride);
     B.lpart = (uint32_t*)h->ws(pre + "lpart", sizeof(uint32_t) * KC_PARTS * 32 *
                                                   std::max<uint64_t>(R.keysum, 1));
-    B.blk_hi = (float*)h->ws(pre + "blkhi", sizeof(float) * std::max<uint32_t>(R.nblk, 1));
+    // region r of the list takes the tiles b with b mod KC_PARTS == r
+    B.region = ((R.nblk + KC_PARTS - 1) / KC_PARTS) * KC_BF_TILE_PTS;
+    const size_t ents = (size_t)KC_PARTS * std::max<uint32_t>(B.region, 1);
+    B.list = (u64*)h->ws(pre + "list", sizeof(u64) * ents);
+    B.list_hi = (float*)h->ws(pre + "listhi", sizeof(float) * ents);
     B.exm = (float*)h->ws(pre + "exm", sizeof(float) * R.stride);
     B.exupto = (uint32_t*)h->ws(pre + "exupto", sizeof(uint32_t) * R.stride);
-    B.ncand = (uint32_t*)h->ws(pre + "ncand", sizeof(uint32_t) * std::max<uint32_t>(R.kmax, 1));
-    if (!B.xb || !B.ex || !B.lpart || !B.blk_hi || !B.exm || !B.exupto || !B.ncand)
+    B.listcnt = (uint32_t*)h->ws(pre + "listcnt", sizeof(uint32_t) * KC_PARTS * 32 *
+                                                      std::max<uint32_t>(R.kmax, 1));
+    B.nresc = (uint32_t*)h->ws(pre + "nresc", sizeof(uint32_t) * std::max<uint32_t>(R.kmax, 1));
+    if (!B.xb || !B.ex || !B.lpart || !B.list || !B.list_hi || !B.exm || !B.exupto ||
+        !B.listcnt || !B.nresc)
         return h->fail(KC_ENOMEM, "workspace allocation failed");
+    h->last_bf16_listcnt = B.listcnt;
+    h->last_bf16_nresc = B.nresc;
+    h->last_bf16_kmax = R.kmax;
     const double u = 5.9604644775390625e-8;
     B.g = (float)((kc_gamma32(R.d) + 16.0 * u) * (1.0 + 1e-6));
     B.rescore_blocks = 256;

@@ -56,6 +56,10 @@ __global__ __launch_bounds__(KC_BLOCK, 1) void k_gon_resident(
             if (i < len) key = kc_umax64(key, kc_pack(m[p], i));
         }
         key = kc_block_max64(key, red);
+        // a block without points (the device-side length can be shorter than
+        // the grid's capacity) still publishes: key 1 is "no point", it never
+        // wins (a real index is below 0xFFFFFFFE) and is not the empty slot 0
+        if (key == 0) key = 1;
         u64* row = slots + (uint64_t)t * G;
         if (threadIdx.x == 0)
             __hip_atomic_store(row + blockIdx.x, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -140,6 +140,23 @@ def test_mrg_small_partitions_and_k_above(kc, orc):
     assert g["radius"] == o["radius"]
 
 
+def test_mrg_union_shorter_than_round2_grid(kc, orc):
+    # 15 tiny partitions and 5 large ones: the union (1,150 points) is far
+    # below the capacity m*k = 4,000 that sizes round 2's resident grid, so
+    # its trailing blocks own no point and must still pass every barrier
+    rng = np.random.default_rng(17)
+    sizes = [10] * 15 + [7_000] * 5
+    n = sum(sizes)
+    X = rng.integers(-80, 81, (n, 16)).astype(np.float32)
+    off = np.r_[0, np.cumsum(sizes)]
+    k = 200
+    g = gpu_mrg(kc, X, off, k)   # checks the device status word
+    o = orc.mrg(X, off, k)
+    assert len(g["union"]) == len(o["union"]) == 15 * 10 + 5 * 200
+    assert np.array_equal(g["centers"], o["centers"])
+    assert g["radius"] == o["radius"]
+
+
 def check_mrg_float(orc, X, off, k, g):
     # every partition's round-1 sequence is a certified farthest-first run
     b = band(X.shape[1])

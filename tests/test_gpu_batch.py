@@ -70,6 +70,7 @@ def run_and_compare(kc, probs):
     for pr, (c, nc, r) in zip(probs, outs):
         got = (c.cpu().numpy(), int(nc.item()), float(r.item()))
         ref = on_stream(lambda: single(kc, pr, h))
+        assert h.device_status() == 0
         assert got[1] == ref[1], pr["algo"]
         assert np.array_equal(got[0][:got[1]], ref[0][:ref[1]]), pr["algo"]
         assert got[2] == ref[2], pr["algo"]
