@@ -86,6 +86,65 @@ __device__ __forceinline__ u64 kc_wave_max64(u64 v)
     return v;
 }
 
+// One DPP exchange of a 64-bit value (both halves); lanes the control does
+// not write read 0, which never raises an unsigned max.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ u64 kc_dpp64(u64 v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROWS,
+                                                               0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL,
+                                                               ROWS, 0xF, false);
+    return ((u64)hi << 32) | lo;
+}
+
+// Wave-wide max of a 64-bit key through DPP (no LDS round trips): quad
+// swaps, half-row and row mirrors leave every lane with its row's max, the
+// row broadcasts of lanes 15 and 31 carry it up to lane 63, which is read
+// out.  Must be called with all 64 lanes active; the result is uniform.
+__device__ __forceinline__ u64 kc_wave_max64_dpp(u64 v)
+{
+    v = kc_umax64(v, kc_dpp64<0xB1, 0xF>(v));    // quad_perm [1,0,3,2]
+    v = kc_umax64(v, kc_dpp64<0x4E, 0xF>(v));    // quad_perm [2,3,0,1]
+    v = kc_umax64(v, kc_dpp64<0x141, 0xF>(v));   // row_half_mirror
+    v = kc_umax64(v, kc_dpp64<0x140, 0xF>(v));   // row_mirror
+    v = kc_umax64(v, kc_dpp64<0x142, 0xA>(v));   // row_bcast:15 into rows 1, 3
+    v = kc_umax64(v, kc_dpp64<0x143, 0xC>(v));   // row_bcast:31 into rows 2, 3
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((u64)hi << 32) | lo;
+}
+
+// Wave-wide max of a 32-bit unsigned value through DPP (the same exchange
+// pattern as kc_wave_max64_dpp, one word).  All 64 lanes active; uniform.
+__device__ __forceinline__ uint32_t kc_wave_max_u32_dpp(uint32_t v)
+{
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Wave-wide max of packed keys in two 32-bit passes: the value word, then
+// the index word among the lanes holding that value (skipped when only one
+// lane does).  All 64 lanes active; uniform.
+__device__ __forceinline__ u64 kc_wave_max_key(u64 v)
+{
+    const uint32_t hv = (uint32_t)(v >> 32);
+    const uint32_t mh = kc_wave_max_u32_dpp(hv);
+    const bool tie = hv == mh;
+    const u64 bal = __ballot(tie);
+    uint32_t lo;
+    if (__builtin_popcountll(bal) == 1)
+        lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, (int)__builtin_ctzll(bal));
+    else
+        lo = kc_wave_max_u32_dpp(tie ? (uint32_t)v : 0u);
+    return ((u64)mh << 32) | lo;
+}
+
 // Block-wide max of a 64-bit key; the result is valid in every thread.
 // `red` must hold blockDim.x / 64 entries.
 __device__ __forceinline__ u64 kc_block_max64(u64 v, u64* red)

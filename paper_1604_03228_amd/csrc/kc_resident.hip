@@ -1,85 +1,229 @@
-// kc_resident.hip -- register-resident persistent Gonzalez engine.
+// kc_resident.hip -- register-resident persistent Gonzalez engine with
+// certified lookahead.
 //
 // One cooperative launch runs all k steps of one segment whose points fit in
-// the register file of the grid: thread (g, tid) keeps the coordinates and
-// the running FP32 min-distance of local points
-//     i = g*KC_BLOCK*PPT + p*KC_BLOCK + tid,  p < PPT
-// in VGPRs, so a step reads nothing from memory but the new center's d
-// coordinates.  Bound by VALU work plus the per-step grid barrier.
+// the register file of the grid.  A block has one leader wave and
+// KC_LA_WORKERS worker waves; worker lane (g, w, lane) keeps the coordinates
+// and the running FP32 min-distance of local points
+//     i = g*KC_LA_WPTS*PPT + p*KC_LA_WPTS + w*64 + lane,  p < PPT
+// in VGPRs (KC_LA_WPTS = 64*KC_LA_WORKERS), so applying a center reads
+// nothing from memory but its d coordinates.
 //
-// Per-step barrier and argmax in one exchange: block b writes its packed key
-// to slots[t*G + b] (keys are never 0: their low word is 0xFFFFFFFF - index)
-// and every block polls all G slots until none is 0, then takes their max.
-// Only relaxed device-scope atomics carry data, and only keys travel, so no
-// cache write-back or invalidation sits on the critical path.  Any block
+// Gonzalez's traversal (Section 2.1) adds one farthest point per step, and a
+// plain parallel version needs one grid-wide argmax per step.  This engine
+// meets the grid once per *round* of several steps instead:
+//
+//  1. every worker wave publishes its K+1 largest keys (key = FP32
+//     min-distance and index, as in kc_device.h);
+//  2. every block reads all published words; tau is the largest (K+1)-th key
+//     over the waves, and the candidate set C is every published key above
+//     tau (at most CMAX of them: when more qualify, tau is raised to the
+//     smallest bound that leaves at most that many);
+//  3. the leader wave runs Gonzalez's step on C alone (the same canonical
+//     FP32 distances the owning lanes use) for as long as the best key of C
+//     stays above tau, and queues each chosen center in LDS; the worker
+//     waves apply the queued centers to their points as they appear.
+//
+// A point outside C had a key of at most tau when the round began and keys
+// only decrease, so a key of C above tau is the global maximum: the centers,
+// keys and min-distances equal those of the step-by-step traversal bit for
+// bit.  The first step of every round is always certified (the global
+// maximum is some wave's largest key and lies above every (K+1)-th key), so
+// each round makes progress.  The sequence of a round depends on C alone,
+// so the leader runs ahead of the workers and only the workers' arithmetic
+// on their points remains per step.
+//
+// Exchange words carry their round in the low word, so no word needs a
+// fence: (bits of the FP32 value << 32) | (tag << 12) | wave-local index,
+// index 4095 = "no point" (the leader's words, and waves without points).
+// Rounds alternate between two buffers; a block cannot write round r+2
+// before every block has read round r, because it first needs every block's
+// round r+1 words.  Only relaxed device-scope atomics carry data.  Any block
 // whose wait exceeds the spin limit raises abort_flag; every block then
 // leaves its loop.
 #include "kc_device.h"
 #include "kc_internal.h"
 
+#define KC_LA_BLOCK 512                                  // threads: two waves per SIMD
+#define KC_LA_WAVES (KC_LA_BLOCK / 64)
+#define KC_LA_WORKERS (KC_LA_WAVES - 1)                  // wave 0 leads
+#define KC_LA_WPTS (KC_LA_WORKERS * 64)                  // worker lanes per block
+#define KC_LA_GMAX 256                                   // blocks of the largest grid
+#define KC_LA_K 2                                        // candidates per wave
+#define KC_LA_KK (KC_LA_K + 1)                           // plus the wave's bound
+#define KC_LA_WMAX (KC_LA_GMAX * KC_LA_WAVES)            // waves of the largest grid
+#define KC_LA_QPJ (KC_LA_WMAX / KC_LA_BLOCK)             // words of one rank per thread
+#define KC_LA_NPT (KC_LA_QPJ * KC_LA_KK)                 // exchange words per thread
+#define KC_LA_BUF (KC_LA_WMAX * KC_LA_KK)                // words per round buffer
+#define KC_LA_NONE 0xFFFu
+
+// Candidate cap: the leader lane keeps CMAX/64 candidates in the registers
+// a worker lane uses for its PPT points (so at most PPT of them, and at most
+// 8: one candidate per thread when their coordinates are gathered).
+template <int PPT>
+struct KcLaCap {
+    static constexpr int value = 64 * (PPT < KC_LA_WAVES ? PPT : KC_LA_WAVES);
+};
+
+__device__ __forceinline__ uint32_t kc_la_tag(uint32_t r) { return (r + 1u) & 0xFFFFFu; }
+
+// Key of exchange word `w` published by global wave `wg`; 0 for "no point".
+template <int PPT>
+__device__ __forceinline__ u64 kc_la_decode(u64 w, uint32_t wg)
+{
+    const uint32_t lidx = (uint32_t)w & 0xFFFu;
+    const uint32_t wv = wg % KC_LA_WAVES;
+    if (lidx == KC_LA_NONE || wv == 0) return 0;
+    const uint32_t i = (wg / KC_LA_WAVES) * (KC_LA_WPTS * PPT) + (lidx >> 6) * KC_LA_WPTS +
+                       (wv - 1) * 64 + (lidx & 63u);
+    return (w & 0xFFFFFFFF00000000ull) | (u64)(0xFFFFFFFFu - i);
+}
+
+// An opaque copy: the compiler cannot hoist expressions of it out of the
+// loop it is taken in.
+__device__ __forceinline__ uint32_t kc_opaque(uint32_t v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// The wave's center coordinates, uniform: LDS broadcast read into SGPRs.
+template <int D, int CMAX>
+__device__ __forceinline__ void kc_la_center(float (&cc)[D], const float (*sCx)[CMAX],
+                                             uint32_t slot)
+{
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+        cc[j] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(sCx[j][slot])));
+}
+
 template <int D, int PPT>
-__global__ __launch_bounds__(KC_BLOCK, 1) void k_gon_resident(
+__global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
     const float* __restrict__ xs, uint64_t stride, uint64_t base, uint32_t len,
     const uint32_t* __restrict__ len_ptr, uint32_t first, int k, float* __restrict__ mind,
-    u64* __restrict__ keys, u64* __restrict__ slots, uint32_t* __restrict__ abort_flag,
+    u64* __restrict__ keys, u64* __restrict__ xbuf, uint32_t* __restrict__ abort_flag,
     uint32_t spin_limit)
 {
+    static_assert(PPT * 64 <= KC_LA_NONE, "wave-local index must fit in 12 bits");
+    constexpr uint32_t CMAX = KcLaCap<PPT>::value;
+    constexpr int QL = CMAX / 64;   // candidates per leader lane
+    static_assert(CMAX <= KC_LA_BLOCK, "one candidate per thread when gathering");
     if (len_ptr) len = min(len, *len_ptr);   // actual length known on the device
-    __shared__ float cc[D];
-    __shared__ u64 red[KC_BLOCK / 64];
-    const uint32_t G = gridDim.x;   // <= KC_BLOCK (checked by the host)
-    const uint32_t i0 = blockIdx.x * (KC_BLOCK * PPT) + threadIdx.x;
+    __shared__ u64 sW[KC_LA_BUF];             // the round's keys, grid-wide
+    __shared__ u64 sCk[CMAX];                 // candidate keys at the round's start
+    __shared__ float sCx[D][CMAX];            // candidate coordinates
+    __shared__ uint32_t sQ[CMAX];             // the round's centers (candidate slots)
+    __shared__ uint32_t sQn, sFin;            // centers queued; round's end state
+    __shared__ float cc0[D];
+    __shared__ u64 red[KC_LA_WAVES];
+    __shared__ uint32_t sWc[KC_LA_WAVES];
+
+    const uint32_t G = gridDim.x;   // <= KC_LA_GMAX (checked by the host)
+    const uint32_t NWV = G * KC_LA_WAVES;   // waves of this grid
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const bool leader = wave == 0;
+    const uint32_t blk0 = blockIdx.x * (KC_LA_WPTS * PPT);
+    const uint32_t i0 = blk0 + (leader ? 0u : (wave - 1) * 64 + lane);
+    const uint32_t wg = blockIdx.x * KC_LA_WAVES + wave;
+    const bool recorder = blockIdx.x == 0 && tid == 0;   // the leader of block 0
 
     float x[PPT][D];
     float m[PPT];
+    if (tid < D) cc0[tid] = xs[(uint64_t)tid * stride + base + first];
+    if (!leader) {
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-        const uint32_t i = i0 + p * KC_BLOCK;
-        const uint32_t ii = i < len ? i : 0;
+        for (int p = 0; p < PPT; ++p) {
+            const uint32_t i = i0 + p * KC_LA_WPTS;
+            const uint32_t ii = i < len ? i : 0;
 #pragma unroll
-        for (int j = 0; j < D; ++j) x[p][j] = xs[(uint64_t)j * stride + base + ii];
-        m[p] = __builtin_inff();
+            for (int j = 0; j < D; ++j) x[p][j] = xs[(uint64_t)j * stride + base + ii];
+        }
     }
-
-    uint32_t c = first;
-    for (int t = 0; t < k; ++t) {
-        if (threadIdx.x < D) cc[threadIdx.x] = xs[(uint64_t)threadIdx.x * stride + base + c];
-        __syncthreads();
-        u64 key = 0;
+    __syncthreads();
+    if (!leader) {
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             float s = 0.f;
 #pragma unroll
-            for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[p][j], cc[j]);
-            m[p] = fminf(m[p], s);
-            const uint32_t i = i0 + p * KC_BLOCK;
-            if (i < len) key = kc_umax64(key, kc_pack(m[p], i));
+            for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[p][j], cc0[j]);
+            m[p] = s;
         }
-        key = kc_block_max64(key, red);
-        // a block without points (the device-side length can be shorter than
-        // the grid's capacity) still publishes: key 1 is "no point", it never
-        // wins (a real index is below 0xFFFFFFFE) and is not the empty slot 0
-        if (key == 0) key = 1;
-        u64* row = slots + (uint64_t)t * G;
-        if (threadIdx.x == 0)
-            __hip_atomic_store(row + blockIdx.x, key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 
-        // wait until every block of the grid has published its key
-        u64 v = 0;
-        uint32_t spins = 0;
+    int t = 0;   // keys recorded (tracked by the leader)
+    for (uint32_t r = 0;; ++r) {
+        // per-round copies of the thread's position: values derived from
+        // them are recomputed each round instead of being held in VGPRs
+        // across the whole loop next to the points
+        const uint32_t tid_r = kc_opaque(tid);
+        const uint32_t i0_r = kc_opaque(i0);
+        // ---- 1. this wave's K+1 largest keys (keys are distinct): each lane
+        // keeps its own K+1 largest in order, then the wave pops its heads
+        u64 mine = 0;
+        if (!leader) {
+            u64 top[KC_LA_KK];
+#pragma unroll
+            for (int j = 0; j < KC_LA_KK; ++j) top[j] = 0;
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                const uint32_t i = i0_r + p * KC_LA_WPTS;
+                u64 v = i < len ? kc_pack(m[p], i) : 0ull;
+#pragma unroll
+                for (int j = 0; j < KC_LA_KK; ++j) {
+                    const u64 hi = kc_umax64(top[j], v);
+                    v = top[j] < v ? top[j] : v;
+                    top[j] = hi;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < KC_LA_KK; ++j) {
+                const u64 b = kc_wave_max_key(top[0]);
+                if (lane == (uint32_t)j) mine = b;
+                if (top[0] == b) {   // b != 0 is held by exactly one lane
+#pragma unroll
+                    for (int q = 0; q + 1 < KC_LA_KK; ++q) top[q] = top[q + 1];
+                    top[KC_LA_KK - 1] = 0;
+                }
+            }
+        }
+        u64* rb = xbuf + (uint64_t)(r & 1u) * KC_LA_BUF;
+        const uint32_t tag = kc_la_tag(r);
+        if (lane < KC_LA_KK) {
+            uint32_t lidx = KC_LA_NONE;
+            if (mine != 0) {
+                const uint32_t il = kc_key_idx(mine) - blk0;
+                lidx = ((il / KC_LA_WPTS) << 6) | (il & 63u);
+            }
+            const u64 w = (mine & 0xFFFFFFFF00000000ull) | (u64)((tag << 12) | lidx);
+            __hip_atomic_store(rb + (uint64_t)lane * KC_LA_WMAX + wg, w, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+
+        // ---- 2. every wave's words of this round
+        uint32_t have = 0, spins = 0;
         int aborted = 0;
         for (;;) {
             int ok = 1;
-            if (threadIdx.x < G) {
-                v = __hip_atomic_load(row + threadIdx.x, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-                ok = v != 0;
+#pragma unroll
+            for (int q = 0; q < KC_LA_NPT; ++q) {
+                const uint32_t e = tid_r + q * KC_LA_BLOCK;
+                const uint32_t src = (q % KC_LA_QPJ) * KC_LA_BLOCK + tid_r;
+                if (src < NWV && !((have >> q) & 1u)) {
+                    const u64 w = __hip_atomic_load(rb + e, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+                    if ((((uint32_t)w) >> 12) == tag) {
+                        sW[e] = kc_la_decode<PPT>(w, src);
+                        have |= 1u << q;
+                    } else {
+                        ok = 0;
+                    }
+                }
             }
             if (__syncthreads_and(ok)) break;
             ++spins;
             if ((spins & 63) == 0) {
                 int ab = 0;
-                if (threadIdx.x == 0) {
+                if (tid == 0) {
                     ab = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT) != 0;
                     if (!ab && spins > spin_limit) {
@@ -95,30 +239,224 @@ __global__ __launch_bounds__(KC_BLOCK, 1) void k_gon_resident(
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        u64 kk = kc_block_max64(threadIdx.x < G ? v : 0ull, red);
-        if (aborted) kk = 0;   // every block leaves the loop
-        if (blockIdx.x == 0 && threadIdx.x == 0) keys[t] = kk;
-        if ((kk >> 32) == 0) break;   // radius 0 (or abort): stop
-        c = kc_key_idx(kk);
-    }
+        if (aborted) {
+            if (recorder && t < k) keys[t] = 0;
+            break;
+        }
+
+        // ---- 3. bound tau and candidate set C (words j < K above tau)
+        const uint64_t ltmask = (1ull << lane) - 1ull;
+        u64 tl = 0;
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-        const uint32_t i = i0 + p * KC_BLOCK;
-        if (i < len) mind[base + i] = m[p];
+        for (int q = KC_LA_K * KC_LA_QPJ; q < KC_LA_NPT; ++q)
+            if ((q % KC_LA_QPJ) * KC_LA_BLOCK + tid_r < NWV)
+                tl = kc_umax64(tl, sW[tid_r + q * KC_LA_BLOCK]);
+        tl = kc_wave_max_key(tl);
+        if (lane == 0) red[wave] = tl;
+        if (tid == 0) {
+            sQn = 0;
+            sFin = 0;
+        }
+        __syncthreads();
+        u64 tau = red[0];
+#pragma unroll
+        for (int w = 1; w < KC_LA_WAVES; ++w) tau = kc_umax64(tau, red[w]);
+
+        // candidates above `thr` in the block, and those of the waves before
+        // this one (two barriers; sWc is free again on return)
+        auto count_above = [&](u64 thr, uint32_t& before) -> uint32_t {
+            uint32_t cw = 0;
+#pragma unroll
+            for (int q = 0; q < KC_LA_K * KC_LA_QPJ; ++q) {
+                const bool pr = (q % KC_LA_QPJ) * KC_LA_BLOCK + tid_r < NWV &&
+                                sW[tid_r + q * KC_LA_BLOCK] > thr;
+                cw += (uint32_t)__builtin_popcountll(__ballot(pr));
+            }
+            if (lane == 0) sWc[wave] = cw;
+            __syncthreads();
+            uint32_t tot = 0;
+            before = 0;
+#pragma unroll
+            for (int w = 0; w < KC_LA_WAVES; ++w) {
+                const uint32_t c = sWc[w];
+                if (w < (int)wave) before += c;
+                tot += c;
+            }
+            __syncthreads();
+            return tot;
+        };
+        uint32_t before = 0;
+        uint32_t nc = count_above(tau, before);
+        if (nc > CMAX) {
+            // raise tau to the smallest bound leaving at most CMAX candidates:
+            // keys are distinct, so count(> hi) >= CMAX at the end
+            u64 cl = 0;
+#pragma unroll
+            for (int q = 0; q < KC_LA_QPJ; ++q)
+                if (q * KC_LA_BLOCK + tid_r < NWV) cl = kc_umax64(cl, sW[tid_r + q * KC_LA_BLOCK]);
+            u64 lo = tau, hi = kc_block_max64(cl, red);
+            while (hi - lo > 1) {
+                const u64 mid = lo + (hi - lo) / 2;
+                if (count_above(mid, before) > CMAX) lo = mid;
+                else hi = mid;
+            }
+            tau = hi;
+            nc = count_above(tau, before);
+        }
+        {
+            uint32_t pos = before;
+#pragma unroll
+            for (int q = 0; q < KC_LA_K * KC_LA_QPJ; ++q) {
+                const uint32_t e = tid_r + q * KC_LA_BLOCK;
+                const bool pr = (q % KC_LA_QPJ) * KC_LA_BLOCK + tid_r < NWV && sW[e] > tau;
+                const u64 bal = __ballot(pr);
+                if (pr) sCk[pos + (uint32_t)__builtin_popcountll(bal & ltmask)] = sW[e];
+                pos += (uint32_t)__builtin_popcountll(bal);
+            }
+        }
+        __syncthreads();
+        if (tid_r < nc) {   // one candidate per thread: all loads in flight at once
+            const uint64_t col = base + kc_key_idx(sCk[tid_r]);
+            float v[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) v[j] = xs[(uint64_t)j * stride + col];
+#pragma unroll
+            for (int j = 0; j < D; ++j) sCx[j][tid_r] = v[j];
+        }
+        __syncthreads();
+
+        // ---- 4. certified steps.  state: 0 next step, 1 round over,
+        // 2 traversal over, 3 no progress
+        uint32_t state = 0;
+        if (leader) {
+            // Gonzalez's step on C: lane `lane` holds candidates q*64 + lane,
+            // q < QL, in the registers of a worker's points (coordinates in
+            // x[q], min-distance in m[q]); a candidate at or below tau can no
+            // longer be certified this round and stops competing
+            uint32_t ci[QL];
+            u64 bl = 0;
+            uint32_t bs = 0;
+#pragma unroll
+            for (int q = 0; q < QL; ++q) {
+                const uint32_t sl = q * 64 + lane;
+                const bool v = sl < nc;
+                const u64 kq = v ? sCk[sl] : 0ull;
+                m[q] = kc_key_val(kq);
+                ci[q] = kc_key_idx(kq);
+#pragma unroll
+                for (int j = 0; j < D; ++j) x[q][j] = v ? sCx[j][sl] : 0.f;
+                if (kq > bl) {   // every key of C is above tau
+                    bl = kq;
+                    bs = sl;
+                }
+            }
+            uint32_t nq = 0;
+            int ns = 0;
+            do {
+                const u64 b = kc_wave_max_key(bl);
+                if (b > tau) {
+                    if (recorder) keys[t] = b;
+                    ++t;
+                    ++ns;
+                    state = ((b >> 32) == 0 || t >= k) ? 2u : 0u;   // radius 0 or k centers
+                } else if (ns == 0) {
+                    // no certified step: only when the segment has no point
+                    // (b == 0, reported as radius 0); otherwise impossible
+                    if (b == 0) {
+                        if (recorder) keys[t] = 0;
+                        ++t;
+                        state = 2;
+                    } else {
+                        state = 3;
+                    }
+                } else {
+                    state = 1;
+                }
+                if (state == 0) {
+                    const u64 hb = __ballot(bl == b);
+                    const uint32_t slot =
+                        __builtin_amdgcn_readlane(bs, (int)__builtin_ctzll(hb));
+                    if (lane == 0) {
+                        sQ[nq] = slot;
+                        __hip_atomic_store(&sQn, nq + 1, __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    ++nq;
+                    float cc[D];
+                    kc_la_center<D, CMAX>(cc, sCx, slot);
+                    bl = 0;
+#pragma unroll
+                    for (int q = 0; q < QL; ++q) {
+                        if (q * 64 < nc) {
+                            float s = 0.f;
+#pragma unroll
+                            for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[q][j], cc[j]);
+                            m[q] = fminf(m[q], s);
+                            const u64 kq = kc_pack(m[q], ci[q]);
+                            if (q * 64 + lane < nc && kq > tau && kq > bl) {
+                                bl = kq;
+                                bs = q * 64 + lane;
+                            }
+                        }
+                    }
+                }
+            } while (state == 0);
+            if (state == 3 && recorder) {
+                keys[t] = 0;
+                __hip_atomic_store(abort_flag, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (lane == 0)
+                __hip_atomic_store(&sFin, state, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            // apply the queued centers as they appear (sQn is final once
+            // sFin is set: the leader stores it last)
+            uint32_t done = 0;
+            for (;;) {
+                const uint32_t fin =
+                    __hip_atomic_load(&sFin, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                const uint32_t n =
+                    __hip_atomic_load(&sQn, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                for (; done < n; ++done) {
+                    float cc[D];
+                    kc_la_center<D, CMAX>(cc, sCx, sQ[done]);
+#pragma unroll
+                    for (int p = 0; p < PPT; ++p) {
+                        float s = 0.f;
+#pragma unroll
+                        for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[p][j], cc[j]);
+                        m[p] = fminf(m[p], s);
+                    }
+                }
+                if (fin != 0) {
+                    state = fin;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (state >= 2) break;
+    }
+    if (!leader) {
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const uint32_t i = i0 + p * KC_LA_WPTS;
+            if (i < len) mind[base + i] = m[p];
+        }
     }
 }
 
-// Largest points-per-thread whose coordinates fit in about 200 VGPRs.
+// Points per worker lane: the coordinates take at most about 130 VGPRs, so
+// two waves of the 512-thread blocks share each SIMD.
 static int resident_ppt(int d)
 {
     switch (d) {
     case 2: return 32;
-    case 3: return 32;
-    case 8: return 16;
-    case 10: return 16;
-    case 16: return 8;
-    case 32: return 4;
-    case 41: return 4;
+    case 3: return 24;
+    case 8: return 12;
+    case 10: return 9;
+    case 16: return 6;
+    case 32: return 3;
+    case 41: return 3;
     default: return 0;
     }
 }
@@ -127,14 +465,14 @@ template <int D, int PPT>
 static hipError_t launch_resident(uint32_t G, const float* xs, uint64_t stride,
                                   uint64_t base, uint32_t len, const uint32_t* len_ptr,
                                   uint32_t first, int k,
-                                  float* mind, u64* keys, u64* slots, uint32_t* abort_flag,
+                                  float* mind, u64* keys, u64* xbuf, uint32_t* abort_flag,
                                   uint32_t spin_limit, hipStream_t s)
 {
     void* args[] = {(void*)&xs,    (void*)&stride, (void*)&base, (void*)&len,
                     (void*)&len_ptr, (void*)&first, (void*)&k,      (void*)&mind, (void*)&keys,
-                    (void*)&slots, (void*)&abort_flag, (void*)&spin_limit};
+                    (void*)&xbuf, (void*)&abort_flag, (void*)&spin_limit};
     return hipLaunchCooperativeKernel((const void*)k_gon_resident<D, PPT>, dim3(G),
-                                      dim3(KC_BLOCK), args, 0, s);
+                                      dim3(KC_LA_BLOCK), args, 0, s);
 }
 
 template <int D, int PPT>
@@ -142,7 +480,7 @@ static int max_resident_blocks()
 {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gon_resident<D, PPT>,
-                                                     KC_BLOCK, 0) != hipSuccess) {
+                                                     KC_LA_BLOCK, 0) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
@@ -150,10 +488,10 @@ static int max_resident_blocks()
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int g = per_cu * cus;
-    return g < KC_BLOCK ? g : KC_BLOCK;   // the barrier polls one slot per thread
+    return g < KC_LA_GMAX ? g : KC_LA_GMAX;   // the exchange buffer's capacity
 }
 
-#define KC_RES_DIMS(X) X(2, 32) X(3, 32) X(8, 16) X(10, 16) X(16, 8) X(32, 4) X(41, 4)
+#define KC_RES_DIMS(X) X(2, 32) X(3, 24) X(8, 12) X(10, 9) X(16, 6) X(32, 3) X(41, 3)
 
 int kc_resident_max_blocks(int d)
 {
@@ -168,12 +506,19 @@ int kc_resident_max_blocks(int d)
 
 uint32_t kc_resident_blocks_for(int d, uint32_t len)
 {
-    const uint64_t per = (uint64_t)resident_ppt(d) * KC_BLOCK;
+    const uint64_t per = (uint64_t)resident_ppt(d) * KC_LA_WPTS;
     if (per == 0) return 0;
     return (uint32_t)((len + per - 1) / per);
 }
 
-uint64_t kc_resident_slot_words(int k, uint32_t G) { return (uint64_t)k * G; }
+// Exchange buffer of the engine (two rounds), to be zero-filled before each
+// launch; independent of k and of the grid size.
+uint64_t kc_resident_slot_words(int k, uint32_t G)
+{
+    (void)k;
+    (void)G;
+    return 2ull * KC_LA_BUF;
+}
 
 // Returns hipSuccess, or an error when the shape has no resident kernel or
 // the grid cannot be co-resident (the caller then streams instead).
@@ -183,7 +528,7 @@ hipError_t kc_gon_resident(int d, uint32_t G, const float* xs, uint64_t stride,
                            u64* keys, u64* slots, uint32_t* abort_flag, uint32_t spin_limit,
                            hipStream_t s)
 {
-    if (G == 0 || G > KC_BLOCK) return hipErrorInvalidValue;
+    if (G == 0 || G > KC_LA_GMAX) return hipErrorInvalidValue;
     switch (d) {
 #define KC_CASE(DD, PP)                                                                  \
     case DD:                                                                             \

@@ -85,6 +85,31 @@ def test_config2_intgrid_bitexact(kc, orc, n, resident):
     assert np.array_equal(tr, otr)
 
 
+def test_resident_candidate_cap(kc, orc):
+    # Two far points inside every wave's share of the register-resident
+    # layout (d = 10: point g*4096 + p*256 + w*64 + lane sits in lane `lane`
+    # of wave w of block g), the rest on the {0,1} grid, first center on the
+    # grid: every wave's two largest keys are far points and its third is a
+    # grid point, so about 600 published keys exceed the round's bound and
+    # the candidate cap (a raised bound) applies.  Exact integer distances.
+    rng = np.random.default_rng(7)
+    n, d = 300_000, 10
+    X = rng.integers(0, 2, (n, d)).astype(np.float32)
+    far = np.array([g * 4096 + w * 64 + l for g in range((n + 4095) // 4096)
+                    for w in range(4) for l in (0, 1)])
+    far = far[far < n]
+    X[far] = rng.integers(100, 1000, (len(far), d)).astype(np.float32)
+    k = 800
+    orc.set_threads(16)
+    oc, otr, og = orc.gon(X, k, 2)
+    assert set(far) <= set(oc[:len(far) + 1])
+    for resident in (True, False):
+        c, tr, got = run_gon(kc, X, k, 2, resident=resident)
+        assert got == og
+        assert np.array_equal(c, oc)
+        assert np.array_equal(tr, otr)
+
+
 def test_config2_prefix(kc):
     X = W.config2(200_000)
     c1, t1, _ = run_gon(kc, X, 100, 0)
