@@ -496,7 +496,7 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
             hipEvent_t ev = h->span_begin(s);
             hipError_t e = kc_gon_resident(pts->d, G, R.xs, R.stride, 0, (uint32_t)pts->n, nullptr,
                                            (uint32_t)first, (int)k, R.mind, R.keys, bar,
-                                           abort_flag, h->spin_limit, s);
+                                           abort_flag, h->spin_limit, pts->f32, pts->ld, s);
             h->span_end("gon_resident", ev, 1, s);
             if (e == hipSuccess) {
                 kc_or_status(abort_flag, h->status_word, 1u, s);

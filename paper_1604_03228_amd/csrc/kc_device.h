@@ -39,6 +39,13 @@ __device__ __forceinline__ float kc_d32_step(float s, float x, float c)
     return __builtin_fmaf(diff, diff, s);
 }
 
+// Minimum of two non-negative FP32 values (squared distances, +inf) as
+// their bit patterns order: one integer instruction, no NaN quieting.
+__device__ __forceinline__ float kc_fmin_nn(float a, float b)
+{
+    return __uint_as_float(min(__float_as_uint(a), __float_as_uint(b)));
+}
+
 __device__ __forceinline__ double kc_d64_step(double s, double x, double c)
 {
     double diff = x - c;

@@ -61,11 +61,13 @@ void kc_gon_step(const float* xs, uint64_t stride, int d, float* mind, u64* part
                  uint32_t nblk, int t, hipStream_t s);
 int kc_resident_max_blocks(int d);
 uint32_t kc_resident_blocks_for(int d, uint32_t len);
+// `xa` (nullable): the same points as rows of lda floats (the caller's
+// array), used to gather candidate coordinates; NULL gathers from xs.
 hipError_t kc_gon_resident(int d, uint32_t G, const float* xs, uint64_t stride,
                            uint64_t base, uint32_t len, const uint32_t* len_ptr,
                            uint32_t first, int k, float* mind,
                            u64* keys, u64* slots, uint32_t* abort_flag,
-                           uint32_t spin_limit, hipStream_t s);
+                           uint32_t spin_limit, const float* xa, int64_t lda, hipStream_t s);
 void kc_gon_finish(const KcGonRun& R, int64_t* centers, int64_t* n_chosen, double* trace,
                    double* radius_out, const int64_t* report_base, const int64_t* remap,
                    hipStream_t s);

@@ -51,11 +51,10 @@
 #define KC_LA_GMAX 256                                   // blocks of the largest grid
 #define KC_LA_K 2                                        // candidates per wave
 #define KC_LA_KK (KC_LA_K + 1)                           // plus the wave's bound
-#define KC_LA_WMAX (KC_LA_GMAX * KC_LA_WAVES)            // waves of the largest grid
-#define KC_LA_QPJ (KC_LA_WMAX / KC_LA_BLOCK)             // words of one rank per thread
-#define KC_LA_NPT (KC_LA_QPJ * KC_LA_KK)                 // exchange words per thread
-#define KC_LA_BUF (KC_LA_WMAX * KC_LA_KK)                // words per round buffer
-#define KC_LA_NONE 0xFFFu
+#define KC_LA_WPB (KC_LA_WORKERS * KC_LA_K + 1)          // words per block: candidates, bound
+#define KC_LA_BUF (KC_LA_GMAX * KC_LA_WPB)               // words per round buffer
+#define KC_LA_NPT ((KC_LA_BUF + KC_LA_BLOCK - 1) / KC_LA_BLOCK)   // words per thread
+#define KC_LA_NONE 0xFFFFu
 
 // Candidate cap: the leader lane keeps CMAX/64 candidates in the registers
 // a worker lane uses for its PPT points (so at most PPT of them, and at most
@@ -65,17 +64,23 @@ struct KcLaCap {
     static constexpr int value = 64 * (PPT < KC_LA_WAVES ? PPT : KC_LA_WAVES);
 };
 
-__device__ __forceinline__ uint32_t kc_la_tag(uint32_t r) { return (r + 1u) & 0xFFFFFu; }
+__device__ __forceinline__ uint32_t kc_la_tag(uint32_t r) { return (r + 1u) & 0xFFFFu; }
 
-// Key of exchange word `w` published by global wave `wg`; 0 for "no point".
-template <int PPT>
-__device__ __forceinline__ u64 kc_la_decode(u64 w, uint32_t wg)
+// Exchange word of key `key` (0: no point) of the block whose points start
+// at `blk0`, in round tag `tag`.
+__device__ __forceinline__ u64 kc_la_word(u64 key, uint32_t blk0, uint32_t tag)
 {
-    const uint32_t lidx = (uint32_t)w & 0xFFFu;
-    const uint32_t wv = wg % KC_LA_WAVES;
-    if (lidx == KC_LA_NONE || wv == 0) return 0;
-    const uint32_t i = (wg / KC_LA_WAVES) * (KC_LA_WPTS * PPT) + (lidx >> 6) * KC_LA_WPTS +
-                       (wv - 1) * 64 + (lidx & 63u);
+    const uint32_t il = key != 0 ? kc_key_idx(key) - blk0 : KC_LA_NONE;
+    return (key & 0xFFFFFFFF00000000ull) | (u64)((tag << 16) | il);
+}
+
+// Key of exchange word `w` published by block `g`; 0 for "no point".
+template <int PPT>
+__device__ __forceinline__ u64 kc_la_decode(u64 w, uint32_t g)
+{
+    const uint32_t il = (uint32_t)w & 0xFFFFu;
+    if (il == KC_LA_NONE) return 0;
+    const uint32_t i = g * (KC_LA_WPTS * PPT) + il;
     return (w & 0xFFFFFFFF00000000ull) | (u64)(0xFFFFFFFFu - i);
 }
 
@@ -87,44 +92,35 @@ __device__ __forceinline__ uint32_t kc_opaque(uint32_t v)
     return v;
 }
 
-// The wave's center coordinates, uniform: LDS broadcast read into SGPRs.
-template <int D, int CMAX>
-__device__ __forceinline__ void kc_la_center(float (&cc)[D], const float (*sCx)[CMAX],
-                                             uint32_t slot)
-{
-#pragma unroll
-    for (int j = 0; j < D; ++j)
-        cc[j] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(sCx[j][slot])));
-}
-
 template <int D, int PPT>
 __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
     const float* __restrict__ xs, uint64_t stride, uint64_t base, uint32_t len,
     const uint32_t* __restrict__ len_ptr, uint32_t first, int k, float* __restrict__ mind,
     u64* __restrict__ keys, u64* __restrict__ xbuf, uint32_t* __restrict__ abort_flag,
-    uint32_t spin_limit)
+    uint32_t spin_limit, const float* __restrict__ xa, int64_t lda)
 {
-    static_assert(PPT * 64 <= KC_LA_NONE, "wave-local index must fit in 12 bits");
+    static_assert(KC_LA_WPTS * PPT <= KC_LA_NONE, "block-local index must fit in 16 bits");
     constexpr uint32_t CMAX = KcLaCap<PPT>::value;
     constexpr int QL = CMAX / 64;   // candidates per leader lane
     static_assert(CMAX <= KC_LA_BLOCK, "one candidate per thread when gathering");
     if (len_ptr) len = min(len, *len_ptr);   // actual length known on the device
-    __shared__ u64 sW[KC_LA_BUF];             // the round's keys, grid-wide
     __shared__ u64 sCk[CMAX];                 // candidate keys at the round's start
     __shared__ float sCx[D][CMAX];            // candidate coordinates
-    __shared__ uint32_t sQ[CMAX];             // the round's centers (candidate slots)
-    __shared__ uint32_t sQn, sFin;            // centers queued; round's end state
+    __shared__ float sQc[CMAX][D];            // the round's centers' coordinates
+    __shared__ uint32_t sQf[CMAX + 1];        // per entry: 0 empty, 1 center, 2 + end state
+    __shared__ float sPm[CMAX];               // the leader's packing of live candidates
+    __shared__ uint32_t sPi[CMAX], sPo[CMAX];
     __shared__ float cc0[D];
     __shared__ u64 red[KC_LA_WAVES];
     __shared__ uint32_t sWc[KC_LA_WAVES];
+    __shared__ u64 sT[KC_LA_WAVES];           // each worker wave's (K+1)-th key
 
     const uint32_t G = gridDim.x;   // <= KC_LA_GMAX (checked by the host)
-    const uint32_t NWV = G * KC_LA_WAVES;   // waves of this grid
+    const uint32_t NWB = G * KC_LA_WPB;     // exchange words of this grid
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
     const bool leader = wave == 0;
     const uint32_t blk0 = blockIdx.x * (KC_LA_WPTS * PPT);
     const uint32_t i0 = blk0 + (leader ? 0u : (wave - 1) * 64 + lane);
-    const uint32_t wg = blockIdx.x * KC_LA_WAVES + wave;
     const bool recorder = blockIdx.x == 0 && tid == 0;   // the leader of block 0
 
     float x[PPT][D];
@@ -186,90 +182,93 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                 }
             }
         }
+        // block g publishes words g*KC_LA_WPB + (w-1)*K + j (candidate j of
+        // worker wave w) and g*KC_LA_WPB + KC_LA_WPB-1 (the block's bound:
+        // the largest (K+1)-th key of its waves)
         u64* rb = xbuf + (uint64_t)(r & 1u) * KC_LA_BUF;
+        u64* rbb = rb + (uint64_t)blockIdx.x * KC_LA_WPB;
         const uint32_t tag = kc_la_tag(r);
-        if (lane < KC_LA_KK) {
-            uint32_t lidx = KC_LA_NONE;
-            if (mine != 0) {
-                const uint32_t il = kc_key_idx(mine) - blk0;
-                lidx = ((il / KC_LA_WPTS) << 6) | (il & 63u);
-            }
-            const u64 w = (mine & 0xFFFFFFFF00000000ull) | (u64)((tag << 12) | lidx);
-            __hip_atomic_store(rb + (uint64_t)lane * KC_LA_WMAX + wg, w, __ATOMIC_RELAXED,
+        if (!leader) {
+            if (lane < KC_LA_K)
+                __hip_atomic_store(rbb + (wave - 1) * KC_LA_K + lane, kc_la_word(mine, blk0, tag),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == KC_LA_K) sT[wave] = mine;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            u64 tb = 0;
+#pragma unroll
+            for (int w = 1; w < KC_LA_WAVES; ++w) tb = kc_umax64(tb, sT[w]);
+            __hip_atomic_store(rbb + KC_LA_WPB - 1, kc_la_word(tb, blk0, tag), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
 
-        // ---- 2. every wave's words of this round
-        uint32_t have = 0, spins = 0;
-        int aborted = 0;
-        for (;;) {
-            int ok = 1;
+        // ---- 2. every block's words of this round: each thread waits for
+        // its own words, then the block meets once
+        int ab = 0;
+        u64 tl = 0;   // largest bound word this thread received
+        u64 wv[KC_LA_NPT];   // this thread's words e = tid + q*KC_LA_BLOCK, decoded
 #pragma unroll
-            for (int q = 0; q < KC_LA_NPT; ++q) {
-                const uint32_t e = tid_r + q * KC_LA_BLOCK;
-                const uint32_t src = (q % KC_LA_QPJ) * KC_LA_BLOCK + tid_r;
-                if (src < NWV && !((have >> q) & 1u)) {
-                    const u64 w = __hip_atomic_load(rb + e, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-                    if ((((uint32_t)w) >> 12) == tag) {
-                        sW[e] = kc_la_decode<PPT>(w, src);
-                        have |= 1u << q;
-                    } else {
-                        ok = 0;
+        for (int q = 0; q < KC_LA_NPT; ++q) wv[q] = 0;
+        {
+            uint32_t have = 0, spins = 0;
+            for (;;) {
+                bool all = true;
+#pragma unroll
+                for (int q = 0; q < KC_LA_NPT; ++q) {
+                    const uint32_t e = tid_r + q * KC_LA_BLOCK;
+                    if (e < NWB && !((have >> q) & 1u)) {
+                        const u64 w = __hip_atomic_load(rb + e, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+                        if ((((uint32_t)w) >> 16) == tag) {
+                            const u64 kw = kc_la_decode<PPT>(w, e / KC_LA_WPB);
+                            if (e % KC_LA_WPB == KC_LA_WPB - 1) tl = kc_umax64(tl, kw);
+                            else wv[q] = kw;   // bound words stay 0 here
+                            have |= 1u << q;
+                        } else {
+                            all = false;
+                        }
                     }
                 }
-            }
-            if (__syncthreads_and(ok)) break;
-            ++spins;
-            if ((spins & 63) == 0) {
-                int ab = 0;
-                if (tid == 0) {
-                    ab = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT) != 0;
-                    if (!ab && spins > spin_limit) {
+                if (all) break;
+                if ((++spins & 63) == 0) {
+                    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        ab = 1;
+                        break;
+                    }
+                    if (spins > spin_limit) {
                         __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                         ab = 1;
+                        break;
                     }
                 }
-                if (__syncthreads_or(ab)) {
-                    aborted = 1;
-                    break;
-                }
+                __builtin_amdgcn_s_sleep(1);
             }
-            __builtin_amdgcn_s_sleep(1);
         }
-        if (aborted) {
+        tl = kc_wave_max_key(tl);
+        if (lane == 0) red[wave] = tl;
+        for (uint32_t e = tid; e <= CMAX; e += KC_LA_BLOCK) sQf[e] = 0;
+        if (__syncthreads_or(ab)) {
             if (recorder && t < k) keys[t] = 0;
             break;
         }
 
-        // ---- 3. bound tau and candidate set C (words j < K above tau)
+        // ---- 3. bound tau (the largest block bound) and candidate set C
+        // (candidate words above tau)
         const uint64_t ltmask = (1ull << lane) - 1ull;
-        u64 tl = 0;
-#pragma unroll
-        for (int q = KC_LA_K * KC_LA_QPJ; q < KC_LA_NPT; ++q)
-            if ((q % KC_LA_QPJ) * KC_LA_BLOCK + tid_r < NWV)
-                tl = kc_umax64(tl, sW[tid_r + q * KC_LA_BLOCK]);
-        tl = kc_wave_max_key(tl);
-        if (lane == 0) red[wave] = tl;
-        if (tid == 0) {
-            sQn = 0;
-            sFin = 0;
-        }
-        __syncthreads();
         u64 tau = red[0];
 #pragma unroll
         for (int w = 1; w < KC_LA_WAVES; ++w) tau = kc_umax64(tau, red[w]);
 
         // candidates above `thr` in the block, and those of the waves before
-        // this one (two barriers; sWc is free again on return)
+        // this one (one barrier; sWc is rewritten only after another)
         auto count_above = [&](u64 thr, uint32_t& before) -> uint32_t {
             uint32_t cw = 0;
 #pragma unroll
-            for (int q = 0; q < KC_LA_K * KC_LA_QPJ; ++q) {
-                const bool pr = (q % KC_LA_QPJ) * KC_LA_BLOCK + tid_r < NWV &&
-                                sW[tid_r + q * KC_LA_BLOCK] > thr;
+            for (int q = 0; q < KC_LA_NPT; ++q) {
+                const bool pr = wv[q] > thr;
                 cw += (uint32_t)__builtin_popcountll(__ballot(pr));
             }
             if (lane == 0) sWc[wave] = cw;
@@ -282,7 +281,6 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                 if (w < (int)wave) before += c;
                 tot += c;
             }
-            __syncthreads();
             return tot;
         };
         uint32_t before = 0;
@@ -290,15 +288,16 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
         if (nc > CMAX) {
             // raise tau to the smallest bound leaving at most CMAX candidates:
             // keys are distinct, so count(> hi) >= CMAX at the end
+            __syncthreads();
             u64 cl = 0;
 #pragma unroll
-            for (int q = 0; q < KC_LA_QPJ; ++q)
-                if (q * KC_LA_BLOCK + tid_r < NWV) cl = kc_umax64(cl, sW[tid_r + q * KC_LA_BLOCK]);
+            for (int q = 0; q < KC_LA_NPT; ++q) cl = kc_umax64(cl, wv[q]);
             u64 lo = tau, hi = kc_block_max64(cl, red);
             while (hi - lo > 1) {
                 const u64 mid = lo + (hi - lo) / 2;
                 if (count_above(mid, before) > CMAX) lo = mid;
                 else hi = mid;
+                __syncthreads();
             }
             tau = hi;
             nc = count_above(tau, before);
@@ -306,36 +305,53 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
         {
             uint32_t pos = before;
 #pragma unroll
-            for (int q = 0; q < KC_LA_K * KC_LA_QPJ; ++q) {
-                const uint32_t e = tid_r + q * KC_LA_BLOCK;
-                const bool pr = (q % KC_LA_QPJ) * KC_LA_BLOCK + tid_r < NWV && sW[e] > tau;
+            for (int q = 0; q < KC_LA_NPT; ++q) {
+                const bool pr = wv[q] > tau;
                 const u64 bal = __ballot(pr);
-                if (pr) sCk[pos + (uint32_t)__builtin_popcountll(bal & ltmask)] = sW[e];
+                if (pr) sCk[pos + (uint32_t)__builtin_popcountll(bal & ltmask)] = wv[q];
                 pos += (uint32_t)__builtin_popcountll(bal);
             }
         }
         __syncthreads();
         if (tid_r < nc) {   // one candidate per thread: all loads in flight at once
-            const uint64_t col = base + kc_key_idx(sCk[tid_r]);
+            const uint32_t ci = kc_key_idx(sCk[tid_r]);
             float v[D];
+            if (xa) {   // the caller's rows: one or two cache lines per candidate
+                const float* row = xa + (uint64_t)ci * (uint64_t)lda;
 #pragma unroll
-            for (int j = 0; j < D; ++j) v[j] = xs[(uint64_t)j * stride + col];
+                for (int j = 0; j < D; ++j) v[j] = row[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < D; ++j) v[j] = xs[(uint64_t)j * stride + base + ci];
+            }
 #pragma unroll
             for (int j = 0; j < D; ++j) sCx[j][tid_r] = v[j];
         }
         __syncthreads();
 
+        // tau and nc are block-uniform: into SGPRs
+        tau = ((u64)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(tau >> 32)) << 32) |
+              (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)tau);
+        nc = __builtin_amdgcn_readfirstlane(nc);
+
         // ---- 4. certified steps.  state: 0 next step, 1 round over,
         // 2 traversal over, 3 no progress
         uint32_t state = 0;
         if (leader) {
+            // The leader shares a SIMD with a worker wave; it issues first so
+            // that the workers never wait for a center.
+            __builtin_amdgcn_s_setprio(3);
             // Gonzalez's step on C: lane `lane` holds candidates q*64 + lane,
             // q < QL, in the registers of a worker's points (coordinates in
-            // x[q], min-distance in m[q]); a candidate at or below tau can no
-            // longer be certified this round and stops competing
-            uint32_t ci[QL];
+            // x[q], min-distance in m[q], index ci[q], slot in C os[q]).  A
+            // candidate at or below tau can no longer be certified this
+            // round: it stops competing, and once the live candidates fit in
+            // fewer chunks of 64 they are packed (through LDS) into the
+            // first nv positions, so a step touches ceil(nv/64) chunks.
+            uint32_t ci[QL], os[QL];
             u64 bl = 0;
             uint32_t bs = 0;
+            uint32_t nv = nc, qn = (nc + 63) / 64;
 #pragma unroll
             for (int q = 0; q < QL; ++q) {
                 const uint32_t sl = q * 64 + lane;
@@ -343,6 +359,7 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                 const u64 kq = v ? sCk[sl] : 0ull;
                 m[q] = kc_key_val(kq);
                 ci[q] = kc_key_idx(kq);
+                os[q] = sl;
 #pragma unroll
                 for (int j = 0; j < D; ++j) x[q][j] = v ? sCx[j][sl] : 0.f;
                 if (kq > bl) {   // every key of C is above tau
@@ -350,9 +367,20 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                     bs = sl;
                 }
             }
+            // coordinates of this lane's best candidate, read ahead of the
+            // wave's argmax so the winner's come out of registers
+            float bx[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) bx[j] = sCx[j][bs];
             uint32_t nq = 0;
             int ns = 0;
             do {
+                // the loop's control values are wave-uniform: keep them in
+                // SGPRs so its branches stay scalar
+                t = __builtin_amdgcn_readfirstlane(t);
+                nq = __builtin_amdgcn_readfirstlane(nq);
+                nv = __builtin_amdgcn_readfirstlane(nv);
+                qn = __builtin_amdgcn_readfirstlane(qn);
                 const u64 b = kc_wave_max_key(bl);
                 if (b > tau) {
                     if (recorder) keys[t] = b;
@@ -372,33 +400,81 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                 } else {
                     state = 1;
                 }
+                state = __builtin_amdgcn_readfirstlane(state);
                 if (state == 0) {
-                    const u64 hb = __ballot(bl == b);
-                    const uint32_t slot =
-                        __builtin_amdgcn_readlane(bs, (int)__builtin_ctzll(hb));
+                    // the winner's coordinates, into SGPRs; queued for the
+                    // workers (coordinates first, then the entry's flag: a
+                    // wave's LDS accesses are performed in order)
+                    const int wl = (int)__builtin_ctzll(__ballot(bl == b));
+                    float cc[D];
+#pragma unroll
+                    for (int j = 0; j < D; ++j)
+                        cc[j] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bx[j]), wl));
                     if (lane == 0) {
-                        sQ[nq] = slot;
-                        __hip_atomic_store(&sQn, nq + 1, __ATOMIC_RELEASE,
+#pragma unroll
+                        for (int j = 0; j < D; ++j) sQc[nq][j] = cc[j];
+                        __asm__ volatile("" ::: "memory");
+                        __hip_atomic_store(&sQf[nq], 1u, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
                     }
                     ++nq;
-                    float cc[D];
-                    kc_la_center<D, CMAX>(cc, sCx, slot);
                     bl = 0;
+                    uint32_t live = 0;
+                    // chunks in pairs without a branch between them
 #pragma unroll
-                    for (int q = 0; q < QL; ++q) {
-                        if (q * 64 < nc) {
-                            float s = 0.f;
+                    for (int g = 0; g < QL; g += 2) {
+                        if (g < (int)qn) {
 #pragma unroll
-                            for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[q][j], cc[j]);
-                            m[q] = fminf(m[q], s);
-                            const u64 kq = kc_pack(m[q], ci[q]);
-                            if (q * 64 + lane < nc && kq > tau && kq > bl) {
-                                bl = kq;
-                                bs = q * 64 + lane;
+                            for (int q = g; q < g + 2 && q < QL; ++q) {
+                                float s = 0.f;
+#pragma unroll
+                                for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[q][j], cc[j]);
+                                m[q] = kc_fmin_nn(m[q], s);
+                                const u64 kq = kc_pack(m[q], ci[q]);
+                                const bool lv = q * 64 + lane < nv && kq > tau;
+                                live += (uint32_t)__builtin_popcountll(__ballot(lv));
+                                if (lv && kq > bl) {
+                                    bl = kq;
+                                    bs = os[q];
+                                }
                             }
                         }
                     }
+                    if (live + 64 <= qn * 64) {
+                        // pack the live candidates into positions 0..live-1
+                        uint32_t pos = 0;
+#pragma unroll
+                        for (int q = 0; q < QL; ++q) {
+                            if (q < (int)qn) {
+                                const bool lv = q * 64 + lane < nv && kc_pack(m[q], ci[q]) > tau;
+                                const u64 bal = __ballot(lv);
+                                if (lv) {
+                                    const uint32_t p = pos + (uint32_t)__builtin_popcountll(bal & ltmask);
+                                    sPm[p] = m[q];
+                                    sPi[p] = ci[q];
+                                    sPo[p] = os[q];
+                                }
+                                pos += (uint32_t)__builtin_popcountll(bal);
+                            }
+                        }
+                        nv = pos;
+                        qn = (pos + 63) / 64;
+#pragma unroll
+                        for (int q = 0; q < QL; ++q) {
+                            if (q < (int)qn) {
+                                const uint32_t p = q * 64 + lane;
+                                if (p < nv) {
+                                    m[q] = sPm[p];
+                                    ci[q] = sPi[p];
+                                    os[q] = sPo[p];
+#pragma unroll
+                                    for (int j = 0; j < D; ++j) x[q][j] = sCx[j][os[q]];
+                                }
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < D; ++j) bx[j] = sCx[j][bs];
                 }
             } while (state == 0);
             if (state == 3 && recorder) {
@@ -406,32 +482,47 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                 __hip_atomic_store(abort_flag, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             if (lane == 0)
-                __hip_atomic_store(&sFin, state, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_store(&sQf[nq], 2u + state, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            __builtin_amdgcn_s_setprio(0);
         } else {
-            // apply the queued centers as they appear (sQn is final once
-            // sFin is set: the leader stores it last)
-            uint32_t done = 0;
+            // apply the queued centers in order.  Entry i+1 (flag, then
+            // coordinates: in order, so a set flag means the coordinates read
+            // after it are the center's) is read before center i is applied,
+            // so the LDS latency hides behind the arithmetic.
+            uint32_t i = 0, f = 0;
+            float cv[D];
             for (;;) {
-                const uint32_t fin =
-                    __hip_atomic_load(&sFin, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                const uint32_t n =
-                    __hip_atomic_load(&sQn, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                for (; done < n; ++done) {
-                    float cc[D];
-                    kc_la_center<D, CMAX>(cc, sCx, sQ[done]);
+                if (f == 0) {
+                    f = __hip_atomic_load(&sQf[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __asm__ volatile("" ::: "memory");
 #pragma unroll
-                    for (int p = 0; p < PPT; ++p) {
-                        float s = 0.f;
-#pragma unroll
-                        for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[p][j], cc[j]);
-                        m[p] = fminf(m[p], s);
+                    for (int j = 0; j < D; ++j) cv[j] = sQc[i < CMAX ? i : CMAX - 1][j];
+                    if (f == 0) {
+                        __builtin_amdgcn_s_sleep(1);
+                        continue;
                     }
                 }
-                if (fin != 0) {
-                    state = fin;
+                if (f >= 2) {
+                    state = f - 2;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(1);
+                float cc[D];   // uniform: held in SGPRs
+#pragma unroll
+                for (int j = 0; j < D; ++j)
+                    cc[j] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cv[j])));
+                ++i;
+                f = __hip_atomic_load(&sQf[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __asm__ volatile("" ::: "memory");
+#pragma unroll
+                for (int j = 0; j < D; ++j) cv[j] = sQc[i < CMAX ? i : CMAX - 1][j];
+#pragma unroll
+                for (int p = 0; p < PPT; ++p) {
+                    float s = 0.f;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[p][j], cc[j]);
+                    m[p] = kc_fmin_nn(m[p], s);
+                }
             }
         }
         if (state >= 2) break;
@@ -456,7 +547,7 @@ static int resident_ppt(int d)
     case 10: return 9;
     case 16: return 6;
     case 32: return 3;
-    case 41: return 3;
+    case 41: return 2;
     default: return 0;
     }
 }
@@ -466,11 +557,13 @@ static hipError_t launch_resident(uint32_t G, const float* xs, uint64_t stride,
                                   uint64_t base, uint32_t len, const uint32_t* len_ptr,
                                   uint32_t first, int k,
                                   float* mind, u64* keys, u64* xbuf, uint32_t* abort_flag,
-                                  uint32_t spin_limit, hipStream_t s)
+                                  uint32_t spin_limit, const float* xa, int64_t lda,
+                                  hipStream_t s)
 {
     void* args[] = {(void*)&xs,    (void*)&stride, (void*)&base, (void*)&len,
                     (void*)&len_ptr, (void*)&first, (void*)&k,      (void*)&mind, (void*)&keys,
-                    (void*)&xbuf, (void*)&abort_flag, (void*)&spin_limit};
+                    (void*)&xbuf, (void*)&abort_flag, (void*)&spin_limit, (void*)&xa,
+                    (void*)&lda};
     return hipLaunchCooperativeKernel((const void*)k_gon_resident<D, PPT>, dim3(G),
                                       dim3(KC_LA_BLOCK), args, 0, s);
 }
@@ -491,7 +584,7 @@ static int max_resident_blocks()
     return g < KC_LA_GMAX ? g : KC_LA_GMAX;   // the exchange buffer's capacity
 }
 
-#define KC_RES_DIMS(X) X(2, 32) X(3, 24) X(8, 12) X(10, 9) X(16, 6) X(32, 3) X(41, 3)
+#define KC_RES_DIMS(X) X(2, 32) X(3, 24) X(8, 12) X(10, 9) X(16, 6) X(32, 3) X(41, 2)
 
 int kc_resident_max_blocks(int d)
 {
@@ -526,14 +619,14 @@ hipError_t kc_gon_resident(int d, uint32_t G, const float* xs, uint64_t stride,
                            uint64_t base, uint32_t len, const uint32_t* len_ptr,
                            uint32_t first, int k, float* mind,
                            u64* keys, u64* slots, uint32_t* abort_flag, uint32_t spin_limit,
-                           hipStream_t s)
+                           const float* xa, int64_t lda, hipStream_t s)
 {
     if (G == 0 || G > KC_LA_GMAX) return hipErrorInvalidValue;
     switch (d) {
 #define KC_CASE(DD, PP)                                                                  \
     case DD:                                                                             \
         return launch_resident<DD, PP>(G, xs, stride, base, len, len_ptr, first, k, mind, keys, \
-                                       slots, abort_flag, spin_limit, s);
+                                       slots, abort_flag, spin_limit, xa, lda, s);
         KC_RES_DIMS(KC_CASE)
 #undef KC_CASE
     default:
