@@ -235,7 +235,8 @@ int kc_plan_gon(kc_handle* h, const std::string& pre, int d, uint32_t tile,
     R.ccoord = (float*)h->ws(pre + "ccoord", sizeof(float) * (size_t)d * std::max<uint64_t>(keyoff, 1));
     R.radius2 = (double*)h->ws(pre + "radius2", sizeof(double) * nseg);
     R.cand = (u64*)h->ws(pre + "cand", sizeof(u64) * R.cand_cap);
-    R.ncand = (uint32_t*)h->ws(pre + "ncand", sizeof(uint32_t));
+    R.ncand = (uint32_t*)h->ws(pre + "ncand", 2 * sizeof(uint32_t));
+    R.ticket = R.ncand ? R.ncand + 1 : nullptr;
     if (!R.xs || !R.mind || !R.keys || !R.part || !R.ccoord || !R.radius2 || !R.cand ||
         !R.ncand)
         return h->fail(KC_ENOMEM, "workspace allocation failed");
@@ -483,23 +484,25 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
         const uint32_t G = kc_resident_blocks_for(pts->d, (uint32_t)pts->n);
         const int Gmax = G ? h->resident_max(pts->d) : 0;
         if (G > 0 && (int)G <= Gmax) {
+            // exchange words, then the abort flag: one fill clears both.  The
+            // kernel writes every min-distance and every key (zeros past an
+            // early stop); candidate and center gathers read the caller's rows.
             const uint64_t bw = kc_resident_slot_words((int)k, G);
-            u64* bar = (u64*)h->ws("g.bar", sizeof(u64) * bw);
-            uint32_t* abort_flag = (uint32_t*)h->ws("g.abort", 64);
-            if (!bar || !abort_flag) return h->fail(KC_ENOMEM, "workspace allocation failed");
+            u64* bar = (u64*)h->ws("g.bar", sizeof(u64) * (bw + 8));
+            if (!bar) return h->fail(KC_ENOMEM, "workspace allocation failed");
+            uint32_t* abort_flag = (uint32_t*)(bar + bw);
             kc_stage_soa(pts->f32, pts->ld, pts->d, 0, (uint32_t)pts->n, (float*)R.xs,
                          R.stride, 0, s);
-            kc_fill_u32((uint32_t*)R.mind, 0x7F800000u, R.stride, s);
-            kc_fill_u64(R.keys, 0ull, R.keysum, s);
-            kc_fill_u64(bar, 0ull, bw, s);
-            kc_fill_u32(abort_flag, 0u, 1, s);
+            kc_fill_u64(bar, 0ull, bw + 1, s);
+            R.xa = pts->f32;
+            R.lda = pts->ld;
             hipEvent_t ev = h->span_begin(s);
             hipError_t e = kc_gon_resident(pts->d, G, R.xs, R.stride, 0, (uint32_t)pts->n, nullptr,
                                            (uint32_t)first, (int)k, R.mind, R.keys, bar,
-                                           abort_flag, h->spin_limit, pts->f32, pts->ld, s);
+                                           abort_flag, h->spin_limit, pts->f32, pts->ld,
+                                           h->status_word, s);
             h->span_end("gon_resident", ev, 1, s);
             if (e == hipSuccess) {
-                kc_or_status(abort_flag, h->status_word, 1u, s);
                 kc_gon_finish(R, centers, n_chosen, radius_trace, nullptr, nullptr, nullptr, s);
                 e = hipGetLastError();
                 return e == hipSuccess ? KC_OK

@@ -523,8 +523,7 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
             kc_fill_u32(abort_flag, 0u, 1, s);
             if (kc_gon_resident(d, G, RG.xs, RG.stride, 0, nc, nullptr, 0, (int)k, RG.mind,
                                 RG.keys, slots, abort_flag, h->spin_limit, nullptr, 0,
-                                s) == hipSuccess) {
-                kc_or_status(abort_flag, h->status_word, 1u, s);
+                                h->status_word, s) == hipSuccess) {
                 done = true;
             } else {
                 (void)hipGetLastError();

@@ -42,15 +42,6 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, uint64_t n)
         p[i] = v;
 }
 
-__global__ void k_or_status(const uint32_t* flag, uint32_t* status, uint32_t bit)
-{
-    if (threadIdx.x == 0 && *flag) atomicOr(status, bit);
-}
-
-void kc_or_status(const uint32_t* flag, uint32_t* status, uint32_t bit, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_or_status, dim3(1), dim3(64), 0, s, flag, status, bit);
-}
 
 void kc_fill_u64(u64* p, u64 v, uint64_t n, hipStream_t s)
 {
@@ -230,14 +221,17 @@ void kc_gon_step(const float* xs, uint64_t stride, int d, float* mind, u64* part
 
 // n_chosen of a segment = 1 + the first step whose key reached radius 0, else
 // ksteps (0 for an empty segment): initialised per segment, then lowered by
-// one thread per (segment, step).
+// one thread per (segment, step).  Also clears the exact-radius accumulators.
 __global__ void k_gon_nchosen_init(const KcSeg* __restrict__ segs, int nseg,
-                                   int64_t* __restrict__ n_chosen)
+                                   int64_t* __restrict__ n_chosen, uint32_t* __restrict__ ncand,
+                                   double* __restrict__ radius2)
 {
     int sidx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sidx == 0) *ncand = 0;
     if (sidx >= nseg) return;
     const KcSeg sg = segs[sidx];
     n_chosen[sidx] = (sg.len > 0) ? (int64_t)sg.ksteps : 0;
+    radius2[sidx] = 0.0;
 }
 
 __global__ void k_gon_nchosen_min(const KcSeg* __restrict__ segs,
@@ -285,6 +279,7 @@ __global__ void k_gon_gather_centers(const KcSeg* __restrict__ segs,
                                      const uint32_t* __restrict__ pairs_seg,
                                      const uint32_t* __restrict__ pairs_t, uint32_t npairs,
                                      const float* __restrict__ xs, uint64_t stride, int d,
+                                     const float* __restrict__ xa, int64_t lda,
                                      const u64* __restrict__ keys,
                                      float* __restrict__ ccoord)
 {
@@ -302,33 +297,30 @@ __global__ void k_gon_gather_centers(const KcSeg* __restrict__ segs,
         c = kc_key_idx(prev);
     }
     float* dst = ccoord + (uint64_t)(sg.keyoff + t) * d;
-    for (int j = 0; j < d; ++j) dst[j] = xs[(uint64_t)j * stride + sg.base + c];
+    if (xa) {
+        const float* row = xa + (sg.src + c) * (uint64_t)lda;
+        for (int j = 0; j < d; ++j) dst[j] = row[j];
+    } else {
+        for (int j = 0; j < d; ++j) dst[j] = xs[(uint64_t)j * stride + sg.base + c];
+    }
 }
 
 // One wave per (segment, t): trace[keyoff+t] = sqrt(min_{j<=t} D64(c_{t+1}, c_j))
 // for t < n_chosen-1 (the FP64 distance of the point chosen at step t to the
 // centers before it); 0 for t >= n_chosen.  The last chosen step is written
 // by the exact radius pass.
-__global__ void k_gon_trace(const KcSeg* __restrict__ segs,
-                            const uint32_t* __restrict__ pairs_seg,
-                            const uint32_t* __restrict__ pairs_t, uint32_t npairs, int d,
-                            const int64_t* __restrict__ n_chosen,
-                            const float* __restrict__ ccoord, double* __restrict__ trace)
+__device__ __forceinline__ void kc_trace_wave(const KcSeg& sg, uint32_t t, int64_t nch, int d,
+                                              const float* __restrict__ ccoord,
+                                              double* __restrict__ trace)
 {
-    const uint32_t q = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (q >= npairs) return;
-    const uint32_t sidx = pairs_seg[q];
-    const KcSeg sg = segs[sidx];
-    const uint32_t t = pairs_t[q];
-    if (t >= sg.ksteps) return;
-    const int64_t nch = n_chosen[sidx];
     if ((int64_t)t + 1 >= nch) {
         if ((int64_t)t >= nch && lane == 0) trace[sg.keyoff + t] = 0.0;
         return;
     }
     const float* a = ccoord + (uint64_t)(sg.keyoff + t + 1) * d;
     double best = __builtin_inf();
+#pragma unroll 4
     for (uint32_t j = lane; j <= t; j += 64) {
         const float* cj = ccoord + (uint64_t)(sg.keyoff + j) * d;
         double s = 0.0;
@@ -339,21 +331,32 @@ __global__ void k_gon_trace(const KcSeg* __restrict__ segs,
     if (lane == 0) trace[sg.keyoff + t] = kc_sqrt_rn(best);
 }
 
+__global__ void k_gon_trace(const KcSeg* __restrict__ segs,
+                            const uint32_t* __restrict__ pairs_seg,
+                            const uint32_t* __restrict__ pairs_t, uint32_t npairs, int d,
+                            const int64_t* __restrict__ n_chosen,
+                            const float* __restrict__ ccoord, double* __restrict__ trace)
+{
+    const uint32_t q = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (q >= npairs) return;
+    const uint32_t sidx = pairs_seg[q];
+    const KcSeg sg = segs[sidx];
+    const uint32_t t = pairs_t[q];
+    if (t >= sg.ksteps) return;
+    kc_trace_wave(sg, t, n_chosen[sidx], d, ccoord, trace);
+}
+
 // Candidates for the exact radius: every point whose FP32 min-distance is at
 // least M32 * (1 - 2 gamma - 4u), M32 the FP32 maximum after the last step.
 // Such a band contains the exact maximiser (FP32 distances are within a
 // relative gamma = gamma_{d+2} of the exact ones).  A segment whose FP32
 // maximum is 0 has exact radius 0 and no candidates.
-__global__ void k_gon_radius_cand(const KcSeg* __restrict__ segs,
-                                  const uint32_t* __restrict__ blk_seg,
-                                  const uint32_t* __restrict__ blk_start,
-                                  const float* __restrict__ mind,
-                                  const u64* __restrict__ keys,
-                                  const int64_t* __restrict__ n_chosen, double band,
-                                  u64* __restrict__ cand, uint32_t* __restrict__ ncand,
-                                  uint32_t cap)
+__device__ __forceinline__ void kc_radius_cand_block(
+    uint32_t b, const KcSeg* __restrict__ segs, const uint32_t* __restrict__ blk_seg,
+    const uint32_t* __restrict__ blk_start, const float* __restrict__ mind,
+    const u64* __restrict__ keys, const int64_t* __restrict__ n_chosen, double band,
+    u64* __restrict__ cand, uint32_t* __restrict__ ncand, uint32_t cap)
 {
-    const uint32_t b = blockIdx.x;
     const uint32_t sidx = blk_seg[b];
     const KcSeg sg = segs[sidx];
     const int64_t nch = n_chosen[sidx];
@@ -371,12 +374,180 @@ __global__ void k_gon_radius_cand(const KcSeg* __restrict__ segs,
     }
 }
 
+__global__ void k_gon_radius_cand(const KcSeg* __restrict__ segs,
+                                  const uint32_t* __restrict__ blk_seg,
+                                  const uint32_t* __restrict__ blk_start,
+                                  const float* __restrict__ mind,
+                                  const u64* __restrict__ keys,
+                                  const int64_t* __restrict__ n_chosen, double band,
+                                  u64* __restrict__ cand, uint32_t* __restrict__ ncand,
+                                  uint32_t cap)
+{
+    kc_radius_cand_block(blockIdx.x, segs, blk_seg, blk_start, mind, keys, n_chosen, band, cand,
+                         ncand, cap);
+}
+
+// ---- one segment reported as is (no remap or base): three launches.
+// Center coordinates are staged in LDS when k*d floats fit KC_FIN1_LDS.
+#define KC_FIN1_LDS 12288
+
+// n_chosen (every block scans the keys), the accumulator resets, and the
+// centers and center coordinates of this block's 256 steps.
+__global__ __launch_bounds__(256) void k_gon_fin1_head(
+    const KcSeg* __restrict__ segs, const u64* __restrict__ keys, int64_t* __restrict__ n_chosen,
+    uint32_t* __restrict__ ncand, uint32_t* __restrict__ ticket, double* __restrict__ radius2,
+    int64_t* __restrict__ centers, float* __restrict__ ccoord, const float* __restrict__ xs,
+    uint64_t stride, int d, const float* __restrict__ xa, int64_t lda)
+{
+    __shared__ int s_nch;
+    const KcSeg sg = segs[0];
+    if (threadIdx.x == 0) s_nch = sg.len > 0 ? (int)sg.ksteps : 0;
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < sg.ksteps; t += blockDim.x)
+        if ((keys[sg.keyoff + t] >> 32) == 0) atomicMin(&s_nch, (int)t + 1);
+    __syncthreads();
+    const int nch = s_nch;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        n_chosen[0] = nch;
+        *ncand = 0;
+        *ticket = 0;
+        radius2[0] = 0.0;
+    }
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= sg.ksteps) return;
+    int64_t v = -1;
+    if ((int)t < nch) {
+        const uint32_t c = t == 0 ? sg.first : kc_key_idx(keys[sg.keyoff + t - 1]);
+        v = c;
+        float* dst = ccoord + (uint64_t)(sg.keyoff + t) * d;
+        if (xa) {
+            const float* row = xa + (sg.src + c) * (uint64_t)lda;
+            for (int j = 0; j < d; ++j) dst[j] = row[j];
+        } else {
+            for (int j = 0; j < d; ++j) dst[j] = xs[(uint64_t)j * stride + sg.base + c];
+        }
+    }
+    centers[sg.keyoff + t] = v;
+}
+
+// trace[t] of one wave from centers C (rows of d floats)
+template <bool LDS>
+__device__ __forceinline__ void kc_trace_wave_c(uint32_t t, int64_t nch, int d,
+                                                const float* __restrict__ C,
+                                                double* __restrict__ trace)
+{
+    const int lane = threadIdx.x & 63;
+    if ((int64_t)t + 1 >= nch) {
+        if ((int64_t)t >= nch && lane == 0) trace[t] = 0.0;
+        return;
+    }
+    const float* a = C + (uint64_t)(t + 1) * d;
+    double best = __builtin_inf();
+    for (uint32_t j = lane; j <= t; j += 64) {
+        const float* cj = C + (uint64_t)j * d;
+        double s = 0.0;
+        for (int u = 0; u < d; ++u) s = kc_d64_step(s, (double)a[u], (double)cj[u]);
+        best = fmin(best, s);
+    }
+    best = kc_wave_min_f64(best);
+    if (lane == 0) trace[t] = kc_sqrt_rn(best);
+}
+
+// Blocks [0, tb) compute the FP64 trace (four steps per block), blocks
+// [tb, tb + nblk) list the exact-radius candidates of their tile.
+__global__ __launch_bounds__(KC_BLOCK) void k_gon_fin1_mid(
+    const KcSeg* __restrict__ segs, uint32_t tb, int d, const int64_t* __restrict__ n_chosen,
+    const float* __restrict__ ccoord, double* __restrict__ trace, int use_lds,
+    const uint32_t* __restrict__ blk_seg, const uint32_t* __restrict__ blk_start,
+    const float* __restrict__ mind, const u64* __restrict__ keys, double band,
+    u64* __restrict__ cand, uint32_t* __restrict__ ncand, uint32_t cap)
+{
+    extern __shared__ float sC[];
+    if (blockIdx.x < tb) {
+        if (!trace) return;
+        const KcSeg sg = segs[0];
+        const int64_t nch = n_chosen[0];
+        const float* C = ccoord + (uint64_t)sg.keyoff * d;
+        double* tr = trace + sg.keyoff;
+        const uint32_t t = blockIdx.x * (KC_BLOCK / 64) + (threadIdx.x >> 6);
+        if (use_lds) {
+            // rows 0..t+1 of this block's last step
+            const uint32_t rows = min((uint32_t)nch, (blockIdx.x + 1) * (KC_BLOCK / 64) + 1);
+            for (uint32_t e = threadIdx.x; e < rows * (uint32_t)d; e += KC_BLOCK) sC[e] = C[e];
+            __syncthreads();
+            if (t < sg.ksteps) kc_trace_wave_c<true>(t, nch, d, sC, tr);
+        } else if (t < sg.ksteps) {
+            kc_trace_wave_c<false>(t, nch, d, C, tr);
+        }
+    } else {
+        kc_radius_cand_block(blockIdx.x - tb, segs, blk_seg, blk_start, mind, keys, n_chosen,
+                             band, cand, ncand, cap);
+    }
+}
+
+// Exact FP64 radius over the candidates (one wave per candidate, centers in
+// LDS when they fit); the last block to finish writes sqrt(radius2) to the
+// trace's last chosen step and to radius_out.
+__global__ __launch_bounds__(KC_BLOCK) void k_gon_fin1_rescore(
+    const KcSeg* __restrict__ segs, const u64* __restrict__ cand,
+    const uint32_t* __restrict__ ncand, uint32_t cap, const float* __restrict__ xs,
+    uint64_t stride, int d, const float* __restrict__ xa, int64_t lda,
+    const int64_t* __restrict__ n_chosen, const float* __restrict__ ccoord, int use_lds,
+    double* __restrict__ radius2, uint32_t* __restrict__ ticket, double* __restrict__ trace,
+    double* __restrict__ radius_out)
+{
+    extern __shared__ float sC[];
+    __shared__ int s_last;
+    const int lane = threadIdx.x & 63;
+    const KcSeg sg = segs[0];
+    const int64_t nch = n_chosen[0];
+    uint32_t nc = *ncand;
+    if (nc > cap) nc = cap;
+    const float* C = ccoord + (uint64_t)sg.keyoff * d;
+    if (use_lds && nc > blockIdx.x * (KC_BLOCK / 64)) {
+        for (uint32_t e = threadIdx.x; e < (uint32_t)nch * (uint32_t)d; e += KC_BLOCK) sC[e] = C[e];
+        __syncthreads();
+        C = sC;
+    }
+    const uint32_t waves = gridDim.x * (KC_BLOCK / 64);
+    for (uint32_t q = blockIdx.x * (KC_BLOCK / 64) + (threadIdx.x >> 6); q < nc; q += waves) {
+        const uint32_t loc = (uint32_t)cand[q];
+        double best = __builtin_inf();
+        const float* row = xa ? xa + (sg.src + loc) * (uint64_t)lda : nullptr;
+        for (int64_t j = lane; j < nch; j += 64) {
+            const float* cj = C + (uint64_t)j * d;
+            double s = 0.0;
+            for (int u = 0; u < d; ++u)
+                s = kc_d64_step(s, (double)(row ? row[u] : xs[(uint64_t)u * stride + sg.base + loc]),
+                                (double)cj[u]);
+            best = fmin(best, s);
+        }
+        best = kc_wave_min_f64(best);
+        if (lane == 0) kc_atomic_max_f64_nonneg(&radius2[0], best);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        s_last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+        __threadfence();
+        const u64 bits = __hip_atomic_load((const u64*)radius2, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+        const double r = kc_sqrt_rn(__longlong_as_double((long long)bits));
+        if (nch > 0 && trace) trace[sg.keyoff + nch - 1] = r;
+        if (radius_out) radius_out[0] = nch > 0 ? r : 0.0;
+    }
+}
+
 // One wave per candidate: exact FP64 min over the segment's chosen centers;
 // radius2[seg] = max over candidates (as bits of a non-negative double).
 __global__ void k_gon_radius_rescore(const KcSeg* __restrict__ segs,
                                      const u64* __restrict__ cand,
                                      const uint32_t* __restrict__ ncand, uint32_t cap,
                                      const float* __restrict__ xs, uint64_t stride, int d,
+                                     const float* __restrict__ xa, int64_t lda,
                                      const int64_t* __restrict__ n_chosen,
                                      const float* __restrict__ ccoord,
                                      double* __restrict__ radius2)
@@ -392,11 +563,13 @@ __global__ void k_gon_radius_rescore(const KcSeg* __restrict__ segs,
         const KcSeg sg = segs[sidx];
         const int64_t nch = n_chosen[sidx];
         double best = __builtin_inf();
+        const float* row = xa ? xa + (sg.src + loc) * (uint64_t)lda : nullptr;
+#pragma unroll 4
         for (int64_t j = lane; j < nch; j += 64) {
             const float* cj = ccoord + (uint64_t)(sg.keyoff + j) * d;
             double s = 0.0;
             for (int u = 0; u < d; ++u)
-                s = kc_d64_step(s, (double)xs[(uint64_t)u * stride + sg.base + loc],
+                s = kc_d64_step(s, (double)(row ? row[u] : xs[(uint64_t)u * stride + sg.base + loc]),
                                 (double)cj[u]);
             best = fmin(best, s);
         }
@@ -428,7 +601,7 @@ void kc_gon_finish_impl(const KcGonRun& R, int64_t* centers, int64_t* n_chosen,
     const int nseg = R.nseg;
     const dim3 pg((R.npairs + 255) / 256);
     hipLaunchKernelGGL(k_gon_nchosen_init, dim3((nseg + 63) / 64), dim3(64), 0, s, R.segs,
-                       nseg, n_chosen);
+                       nseg, n_chosen, R.ncand, R.radius2);
     if (R.npairs > 0) {
         hipLaunchKernelGGL(k_gon_nchosen_min, pg, dim3(256), 0, s, R.segs, R.pairs_seg,
                            R.pairs_t, R.npairs, R.keys, n_chosen);
@@ -437,18 +610,17 @@ void kc_gon_finish_impl(const KcGonRun& R, int64_t* centers, int64_t* n_chosen,
                            centers);
         if (gather)
             hipLaunchKernelGGL(k_gon_gather_centers, pg, dim3(256), 0, s, R.segs, R.pairs_seg,
-                               R.pairs_t, R.npairs, R.xs, R.stride, R.d, R.keys, R.ccoord);
+                               R.pairs_t, R.npairs, R.xs, R.stride, R.d, R.xa, R.lda, R.keys,
+                               R.ccoord);
         if (trace)
             hipLaunchKernelGGL(k_gon_trace, dim3((R.npairs + 3) / 4), dim3(256), 0, s, R.segs,
                                R.pairs_seg, R.pairs_t, R.npairs, R.d, n_chosen, R.ccoord,
                                trace);
     }
-    kc_fill_u32(R.ncand, 0u, 1, s);
-    kc_fill_u64((u64*)R.radius2, 0ull, (uint64_t)nseg, s);
     if (R.nblk > 0) radius_cand(s);
     hipLaunchKernelGGL(k_gon_radius_rescore, dim3(1024), dim3(256), 0, s, R.segs, R.cand,
-                       R.ncand, R.cand_cap, R.xs, R.stride, R.d, n_chosen, R.ccoord,
-                       R.radius2);
+                       R.ncand, R.cand_cap, R.xs, R.stride, R.d, R.xa, R.lda, n_chosen,
+                       R.ccoord, R.radius2);
     hipLaunchKernelGGL(k_gon_radius_finish, dim3((nseg + 63) / 64), dim3(64), 0, s, R.segs,
                        nseg, n_chosen, R.radius2, trace, radius_out);
 }
@@ -457,6 +629,25 @@ void kc_gon_finish(const KcGonRun& R, int64_t* centers, int64_t* n_chosen,
                    double* trace, double* radius_out, const int64_t* report_base,
                    const int64_t* remap, hipStream_t s)
 {
+    if (R.nseg == 1 && !report_base && !remap) {
+        // one segment: 3 launches instead of 9
+        const uint32_t kst = R.npairs;   // steps of the one segment
+        const int use_lds = (uint64_t)kst * R.d <= KC_FIN1_LDS;
+        const size_t lds = use_lds ? sizeof(float) * (size_t)kst * R.d : 0;
+        if (kst > 0)
+            hipLaunchKernelGGL(k_gon_fin1_head, dim3((kst + 255) / 256), dim3(256), 0, s, R.segs,
+                               R.keys, n_chosen, R.ncand, R.ticket, R.radius2, centers, R.ccoord,
+                               R.xs, R.stride, R.d, R.xa, R.lda);
+        const uint32_t tb = (kst + KC_BLOCK / 64 - 1) / (KC_BLOCK / 64);
+        if (tb + R.nblk > 0)
+            hipLaunchKernelGGL(k_gon_fin1_mid, dim3(tb + R.nblk), dim3(KC_BLOCK), lds, s, R.segs,
+                               tb, R.d, n_chosen, R.ccoord, trace, use_lds, R.blk_seg,
+                               R.blk_start, R.mind, R.keys, R.band, R.cand, R.ncand, R.cand_cap);
+        hipLaunchKernelGGL(k_gon_fin1_rescore, dim3(256), dim3(KC_BLOCK), lds, s, R.segs, R.cand,
+                           R.ncand, R.cand_cap, R.xs, R.stride, R.d, R.xa, R.lda, n_chosen,
+                           R.ccoord, use_lds, R.radius2, R.ticket, trace, radius_out);
+        return;
+    }
     kc_gon_finish_impl(R, centers, n_chosen, trace, radius_out, report_base, remap, true, s,
                        [&](hipStream_t st) {
                            hipLaunchKernelGGL(k_gon_radius_cand, dim3(R.nblk), dim3(KC_BLOCK),

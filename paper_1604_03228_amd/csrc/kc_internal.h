@@ -26,6 +26,8 @@ struct KcGonRun {
     int nseg = 0;
     uint32_t kmax = 0;          // largest ksteps over segments (host)
     const float* xs = nullptr;  // SoA staging copy
+    const float* xa = nullptr;  // the caller's rows (nullable): finishing gathers read them
+    int64_t lda = 0;            //   row stride of xa, in floats
     uint64_t stride = 0;        // columns per coordinate row
     float* mind = nullptr;      // [stride]
     u64* keys = nullptr;        // [sum ksteps]
@@ -41,6 +43,7 @@ struct KcGonRun {
     double* radius2 = nullptr;  // [nseg]
     u64* cand = nullptr;        // [cand_cap]
     uint32_t* ncand = nullptr;  // [1]
+    uint32_t* ticket = nullptr; // [1] blocks done, for the one-segment exact radius
     uint32_t cand_cap = 0;
     double band = 0.0;          // 2 gamma_{d+2} + 4u
     uint64_t keysum = 0;        // keys in use (host)
@@ -62,12 +65,14 @@ void kc_gon_step(const float* xs, uint64_t stride, int d, float* mind, u64* part
 int kc_resident_max_blocks(int d);
 uint32_t kc_resident_blocks_for(int d, uint32_t len);
 // `xa` (nullable): the same points as rows of lda floats (the caller's
-// array), used to gather candidate coordinates; NULL gathers from xs.
+// array), used to gather candidate coordinates; NULL gathers from xs.  A
+// wait that exceeds the spin limit raises abort_flag and bit 0 of *status.
 hipError_t kc_gon_resident(int d, uint32_t G, const float* xs, uint64_t stride,
                            uint64_t base, uint32_t len, const uint32_t* len_ptr,
                            uint32_t first, int k, float* mind,
                            u64* keys, u64* slots, uint32_t* abort_flag,
-                           uint32_t spin_limit, const float* xa, int64_t lda, hipStream_t s);
+                           uint32_t spin_limit, const float* xa, int64_t lda, uint32_t* status,
+                           hipStream_t s);
 void kc_gon_finish(const KcGonRun& R, int64_t* centers, int64_t* n_chosen, double* trace,
                    double* radius_out, const int64_t* report_base, const int64_t* remap,
                    hipStream_t s);
@@ -94,7 +99,6 @@ struct KcBf16Run {
     float g = 0.f;                // gamma_{d+2} + 16u
 };
 #define KC_BF_TILE_PTS (KC_BLOCK * 8)
-void kc_or_status(const uint32_t* flag, uint32_t* status, uint32_t bit, hipStream_t s);
 
 // MFMA nearest-center distances (kc_assign.hip)
 int kc_mindist_ksteps(int d, bool bf);

@@ -317,9 +317,8 @@ int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int3
             kc_fill_u32(abort_flag, 0u, 1, s);
             hipError_t e = kc_gon_resident(d, G, R2.xs, R2.stride, 0, (uint32_t)cap, len_ptr, 0,
                                            (int)k, R2.mind, R2.keys, slots, abort_flag,
-                                           h->spin_limit, nullptr, 0, s);
+                                           h->spin_limit, nullptr, 0, h->status_word, s);
             if (e == hipSuccess) {
-                kc_or_status(abort_flag, h->status_word, 1u, s);
                 done = true;
             } else {
                 (void)hipGetLastError();

@@ -55,6 +55,7 @@
 #define KC_LA_BUF (KC_LA_GMAX * KC_LA_WPB)               // words per round buffer
 #define KC_LA_NPT ((KC_LA_BUF + KC_LA_BLOCK - 1) / KC_LA_BLOCK)   // words per thread
 #define KC_LA_NONE 0xFFFFu
+#define KC_LA_END 0x80000000u
 
 // Candidate cap: the leader lane keeps CMAX/64 candidates in the registers
 // a worker lane uses for its PPT points (so at most PPT of them, and at most
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
     const float* __restrict__ xs, uint64_t stride, uint64_t base, uint32_t len,
     const uint32_t* __restrict__ len_ptr, uint32_t first, int k, float* __restrict__ mind,
     u64* __restrict__ keys, u64* __restrict__ xbuf, uint32_t* __restrict__ abort_flag,
-    uint32_t spin_limit, const float* __restrict__ xa, int64_t lda)
+    uint32_t spin_limit, const float* __restrict__ xa, int64_t lda, uint32_t* __restrict__ status)
 {
     static_assert(KC_LA_WPTS * PPT <= KC_LA_NONE, "block-local index must fit in 16 bits");
     constexpr uint32_t CMAX = KcLaCap<PPT>::value;
@@ -106,8 +107,8 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
     if (len_ptr) len = min(len, *len_ptr);   // actual length known on the device
     __shared__ u64 sCk[CMAX];                 // candidate keys at the round's start
     __shared__ float sCx[D][CMAX];            // candidate coordinates
-    __shared__ float sQc[CMAX][D];            // the round's centers' coordinates
-    __shared__ uint32_t sQf[CMAX + 1];        // per entry: 0 empty, 1 center, 2 + end state
+    __shared__ uint32_t sQf[CMAX + 1];        // the round's queue: 0 empty, slot + 1 of a
+                                              // center, KC_LA_END | state at the end
     __shared__ float sPm[CMAX];               // the leader's packing of live candidates
     __shared__ uint32_t sPi[CMAX], sPo[CMAX];
     __shared__ float cc0[D];
@@ -123,16 +124,19 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
     const uint32_t i0 = blk0 + (leader ? 0u : (wave - 1) * 64 + lane);
     const bool recorder = blockIdx.x == 0 && tid == 0;   // the leader of block 0
 
+    // the points come from the staging copy (coalesced rows of one
+    // coordinate); the caller's rows serve the scattered candidate gathers
+    auto coord = [&](uint32_t i, int j) -> float { return xs[(uint64_t)j * stride + base + i]; };
     float x[PPT][D];
     float m[PPT];
-    if (tid < D) cc0[tid] = xs[(uint64_t)tid * stride + base + first];
+    if (tid < D) cc0[tid] = coord(first, tid);
     if (!leader) {
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             const uint32_t i = i0 + p * KC_LA_WPTS;
             const uint32_t ii = i < len ? i : 0;
 #pragma unroll
-            for (int j = 0; j < D; ++j) x[p][j] = xs[(uint64_t)j * stride + base + ii];
+            for (int j = 0; j < D; ++j) x[p][j] = coord(ii, j);
         }
     }
     __syncthreads();
@@ -240,6 +244,7 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                     if (spins > spin_limit) {
                         __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
+                        atomicOr(status, 1u);
                         ab = 1;
                         break;
                     }
@@ -402,21 +407,16 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                 }
                 state = __builtin_amdgcn_readfirstlane(state);
                 if (state == 0) {
-                    // the winner's coordinates, into SGPRs; queued for the
-                    // workers (coordinates first, then the entry's flag: a
-                    // wave's LDS accesses are performed in order)
+                    // queue the winner's slot for the workers; its
+                    // coordinates into SGPRs from the winning lane's copy
                     const int wl = (int)__builtin_ctzll(__ballot(bl == b));
+                    if (lane == 0)
+                        __hip_atomic_store(&sQf[nq], __builtin_amdgcn_readlane(bs, wl) + 1u,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     float cc[D];
 #pragma unroll
                     for (int j = 0; j < D; ++j)
                         cc[j] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bx[j]), wl));
-                    if (lane == 0) {
-#pragma unroll
-                        for (int j = 0; j < D; ++j) sQc[nq][j] = cc[j];
-                        __asm__ volatile("" ::: "memory");
-                        __hip_atomic_store(&sQf[nq], 1u, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                    }
                     ++nq;
                     bl = 0;
                     uint32_t live = 0;
@@ -480,31 +480,32 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
             if (state == 3 && recorder) {
                 keys[t] = 0;
                 __hip_atomic_store(abort_flag, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                atomicOr(status, 1u);
             }
             if (lane == 0)
-                __hip_atomic_store(&sQf[nq], 2u + state, __ATOMIC_RELAXED,
+                __hip_atomic_store(&sQf[nq], KC_LA_END | state, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
             __builtin_amdgcn_s_setprio(0);
         } else {
-            // apply the queued centers in order.  Entry i+1 (flag, then
-            // coordinates: in order, so a set flag means the coordinates read
-            // after it are the center's) is read before center i is applied,
-            // so the LDS latency hides behind the arithmetic.
+            // apply the queued centers in order; entry i+1 and its
+            // coordinates are read before center i is applied, so most of the
+            // LDS latency hides behind the arithmetic
             uint32_t i = 0, f = 0;
             float cv[D];
             for (;;) {
                 if (f == 0) {
                     f = __hip_atomic_load(&sQf[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    __asm__ volatile("" ::: "memory");
-#pragma unroll
-                    for (int j = 0; j < D; ++j) cv[j] = sQc[i < CMAX ? i : CMAX - 1][j];
                     if (f == 0) {
                         __builtin_amdgcn_s_sleep(1);
                         continue;
                     }
+                    if (!(f & KC_LA_END)) {
+#pragma unroll
+                        for (int j = 0; j < D; ++j) cv[j] = sCx[j][f - 1];
+                    }
                 }
-                if (f >= 2) {
-                    state = f - 2;
+                if (f & KC_LA_END) {
+                    state = f & ~KC_LA_END;
                     break;
                 }
                 float cc[D];   // uniform: held in SGPRs
@@ -513,9 +514,10 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                     cc[j] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cv[j])));
                 ++i;
                 f = __hip_atomic_load(&sQf[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                __asm__ volatile("" ::: "memory");
+                if (f != 0 && !(f & KC_LA_END)) {
 #pragma unroll
-                for (int j = 0; j < D; ++j) cv[j] = sQc[i < CMAX ? i : CMAX - 1][j];
+                    for (int j = 0; j < D; ++j) cv[j] = sCx[j][f - 1];
+                }
 #pragma unroll
                 for (int p = 0; p < PPT; ++p) {
                     float s = 0.f;
@@ -533,6 +535,9 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
             const uint32_t i = i0 + p * KC_LA_WPTS;
             if (i < len) mind[base + i] = m[p];
         }
+    } else if (blockIdx.x == 0) {
+        // keys past an early stop (radius 0, or an abort) read as radius 0
+        for (int u = t + (int)lane; u < k; u += 64) keys[u] = 0;
     }
 }
 
@@ -558,12 +563,12 @@ static hipError_t launch_resident(uint32_t G, const float* xs, uint64_t stride,
                                   uint32_t first, int k,
                                   float* mind, u64* keys, u64* xbuf, uint32_t* abort_flag,
                                   uint32_t spin_limit, const float* xa, int64_t lda,
-                                  hipStream_t s)
+                                  uint32_t* status, hipStream_t s)
 {
     void* args[] = {(void*)&xs,    (void*)&stride, (void*)&base, (void*)&len,
                     (void*)&len_ptr, (void*)&first, (void*)&k,      (void*)&mind, (void*)&keys,
                     (void*)&xbuf, (void*)&abort_flag, (void*)&spin_limit, (void*)&xa,
-                    (void*)&lda};
+                    (void*)&lda, (void*)&status};
     return hipLaunchCooperativeKernel((const void*)k_gon_resident<D, PPT>, dim3(G),
                                       dim3(KC_LA_BLOCK), args, 0, s);
 }
@@ -619,14 +624,14 @@ hipError_t kc_gon_resident(int d, uint32_t G, const float* xs, uint64_t stride,
                            uint64_t base, uint32_t len, const uint32_t* len_ptr,
                            uint32_t first, int k, float* mind,
                            u64* keys, u64* slots, uint32_t* abort_flag, uint32_t spin_limit,
-                           const float* xa, int64_t lda, hipStream_t s)
+                           const float* xa, int64_t lda, uint32_t* status, hipStream_t s)
 {
     if (G == 0 || G > KC_LA_GMAX) return hipErrorInvalidValue;
     switch (d) {
 #define KC_CASE(DD, PP)                                                                  \
     case DD:                                                                             \
         return launch_resident<DD, PP>(G, xs, stride, base, len, len_ptr, first, k, mind, keys, \
-                                       slots, abort_flag, spin_limit, xa, lda, s);
+                                       slots, abort_flag, spin_limit, xa, lda, status, s);
         KC_RES_DIMS(KC_CASE)
 #undef KC_CASE
     default:
