@@ -73,17 +73,21 @@ const char* kc_last_error(const kc_handle* h);
 
 /* Options (name, value): "graphs" 0/1 (capture per-step launches in a HIP
  * graph, default 1); "resident" 0/1 (use the register-resident persistent
- * Gonzalez kernel when the points fit, default 1); "timing" 0/1 (record
- * kernel timing events, default 0); "spin_limit" (polls before a persistent
- * kernel's barrier wait gives up, default 2^20).  KC_EINVAL for an unknown
- * name or a value out of range. */
+ * Gonzalez kernel when the points fit, default 1); "resident_blocks" (at
+ * most this many blocks per persistent launch, 0 = as many as are
+ * co-resident, the default; a testing aid: smaller grids hold fewer points,
+ * so more inputs stream and MRG partitions spread over more launches);
+ * "timing" 0/1 (record kernel timing events, default 0); "spin_limit"
+ * (polls before a persistent kernel's barrier wait gives up, default 2^20).
+ * KC_EINVAL for an unknown name or a value out of range. */
 int kc_set_option(kc_handle* h, const char* name, int64_t value);
 
 /* Kernel timing.  With option "timing" = 1 every call records a pair of HIP
  * events on its stream around its dominant kernel or launch sequence, under
  * one of the names "gon_resident" (persistent Gonzalez, 1 launch),
  * "gon_step" (k streaming step launches), "gon_bf16" (BF16 stream steps),
- * "mrg_round1" (MRG first-round step launches), "assign_mfma" (the MFMA
+ * "mrg_round1" (MRG first round: its persistent launches, or its
+ * streaming step launches), "assign_mfma" (the MFMA
  * distance kernel of an assignment), "eim_dist" (EIM distance passes).
  * kc_timing_read synchronises the device, returns the summed milliseconds,
  * the number of kernel launches those intervals cover and the number of

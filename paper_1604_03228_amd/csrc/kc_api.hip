@@ -312,6 +312,99 @@ int kc_run_gon_stream(kc_handle* h, const std::string& key, const KcGonRun& R,
     return h->run_graph(key + ":finish", s, finish);
 }
 
+int kc_run_gon_resident_batch(kc_handle* h, const std::string& key, const KcGonRun& R,
+                              const KcGonHost& H, const std::vector<KcGonJob>& jobs,
+                              const char* span, hipStream_t s, bool* done)
+{
+    *done = false;
+    const int d = R.d;
+    // each segment takes the first variant whose grid for it is co-resident
+    struct Item {
+        uint32_t seg, G;
+    };
+    std::vector<Item> items[2];
+    int gmax[2] = {0, 0};
+    for (size_t q = 0; q < H.segs.size(); ++q) {
+        const KcSeg& sg = H.segs[q];
+        if (sg.len == 0 || sg.ksteps == 0) continue;   // nothing to choose
+        int v = 0;
+        uint32_t G = 0;
+        if (!h->resident_fit(d, sg.len, &v, &G)) return KC_OK;
+        gmax[v] = h->resident_max(d, v);
+        items[v].push_back({(uint32_t)q, G});
+    }
+    // first-fit decreasing into launches of at most gmax blocks; the blocks
+    // of a segment are consecutive in its launch
+    struct Launch {
+        int v;
+        uint32_t G;
+        std::vector<uint32_t> segs;
+    };
+    std::vector<Launch> launches;
+    for (int v = 0; v < 2; ++v) {
+        std::stable_sort(items[v].begin(), items[v].end(),
+                         [](const Item& a, const Item& b) { return a.G > b.G; });
+        const size_t l0 = launches.size();
+        for (const Item& it : items[v]) {
+            size_t l = l0;
+            while (l < launches.size() && launches[l].G + it.G > (uint32_t)gmax[v]) ++l;
+            if (l == launches.size()) launches.push_back({v, 0, {}});
+            launches[l].G += it.G;
+            launches[l].segs.push_back(it.seg);
+        }
+    }
+    if (launches.empty()) return KC_OK;
+    std::vector<uint4> tab;
+    std::vector<size_t> off;
+    for (const Launch& L : launches) {
+        off.push_back(tab.size());
+        uint32_t b0 = 0;
+        for (uint32_t q : L.segs) {
+            const uint32_t gs = kc_resident_blocks_for(d, L.v, H.segs[q].len);
+            for (uint32_t b = 0; b < gs; ++b) tab.push_back(make_uint4(q, b, gs, b0));
+            b0 += gs;
+        }
+    }
+    const uint4* blks = (const uint4*)h->upload(key + ":rblk", tab.data(), sizeof(uint4) * tab.size());
+    // per launch: its exchange words, then its abort flag (one fill clears all)
+    const uint64_t bw = kc_resident_slot_words(0, 0) + 8;
+    u64* bar = (u64*)h->ws(key + ":rbar", sizeof(u64) * bw * launches.size());
+    if (!blks || !bar) return h->fail(KC_ENOMEM, "workspace allocation failed");
+    // the candidate gathers read the caller's rows when every segment has them
+    const float* xa = jobs.empty() ? nullptr : jobs[0].X;
+    for (const KcGonJob& j : jobs)
+        if (j.X != xa || j.ld != jobs[0].ld) xa = nullptr;
+    const int64_t lda = xa ? jobs[0].ld : 0;
+    int rc = h->run_graph(key + ":rprep", s, [&](hipStream_t st) {
+        for (size_t q = 0; q < jobs.size(); ++q)
+            if (jobs[q].X)
+                kc_stage_soa(jobs[q].X, jobs[q].ld, d, jobs[q].row0, jobs[q].len, (float*)R.xs,
+                             R.stride, H.segs[q].base, st);
+        kc_fill_u64(bar, 0ull, bw * launches.size(), st);
+    });
+    if (rc) return rc;
+    hipEvent_t ev = h->span_begin(s);
+    for (size_t l = 0; l < launches.size(); ++l) {
+        const Launch& L = launches[l];
+        u64* slots = bar + bw * l;
+        uint32_t* abort_flag = (uint32_t*)(slots + (bw - 8));
+        hipError_t e = kc_gon_resident(d, L.v, L.G, R.xs, R.stride, 0, 0, nullptr, 0, 0, R.mind,
+                                       R.keys, slots, abort_flag, h->spin_limit, xa, lda,
+                                       h->status_word, R.segs, blks + off[l], s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            if (l == 0) {   // refused before any work: the caller streams
+                if (ev) h->event_pool.push_back(ev);
+                return KC_OK;
+            }
+            return h->fail(KC_EHIP, "resident launch %zu: %s", l, hipGetErrorString(e));
+        }
+    }
+    h->span_end(span, ev, (int64_t)launches.size(), s);
+    *done = true;
+    return KC_OK;
+}
+
 // ---------------------------------------------------------------------------
 // public entry points
 
@@ -379,6 +472,11 @@ int kc_set_option(kc_handle* h, const char* name, int64_t value)
     }
     if (!strcmp(name, "timing")) {
         h->timing = value != 0;
+        return KC_OK;
+    }
+    if (!strcmp(name, "resident_blocks")) {
+        if (value < 0 || value > 0x7FFFFFFF) return h->fail(KC_EINVAL, "resident_blocks range");
+        h->resident_cap = (int)value;
         return KC_OK;
     }
     if (!strcmp(name, "spin_limit")) {
@@ -481,9 +579,9 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
 
     // register-resident persistent kernel when the whole problem fits
     if (h->allow_resident) {
-        const uint32_t G = kc_resident_blocks_for(pts->d, (uint32_t)pts->n);
-        const int Gmax = G ? h->resident_max(pts->d) : 0;
-        if (G > 0 && (int)G <= Gmax) {
+        int v = 0;
+        uint32_t G = 0;
+        if (h->resident_fit(pts->d, (uint64_t)pts->n, &v, &G)) {
             // exchange words, then the abort flag: one fill clears both.  The
             // kernel writes every min-distance and every key (zeros past an
             // early stop); candidate and center gathers read the caller's rows.
@@ -497,10 +595,10 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
             R.xa = pts->f32;
             R.lda = pts->ld;
             hipEvent_t ev = h->span_begin(s);
-            hipError_t e = kc_gon_resident(pts->d, G, R.xs, R.stride, 0, (uint32_t)pts->n, nullptr,
+            hipError_t e = kc_gon_resident(pts->d, v, G, R.xs, R.stride, 0, (uint32_t)pts->n, nullptr,
                                            (uint32_t)first, (int)k, R.mind, R.keys, bar,
                                            abort_flag, h->spin_limit, pts->f32, pts->ld,
-                                           h->status_word, s);
+                                           h->status_word, nullptr, nullptr, s);
             h->span_end("gon_resident", ev, 1, s);
             if (e == hipSuccess) {
                 kc_gon_finish(R, centers, n_chosen, radius_trace, nullptr, nullptr, nullptr, s);
@@ -523,11 +621,29 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
 
 }  // extern "C"
 
-int kc_handle::resident_max(int d)
+int kc_handle::resident_max(int d, int v)
 {
-    auto it = resident_cache.find(d);
-    if (it != resident_cache.end()) return it->second;
-    int v = kc_resident_max_blocks(d);
-    resident_cache[d] = v;
-    return v;
+    const int key = d * 2 + v;
+    int g;
+    auto it = resident_cache.find(key);
+    if (it != resident_cache.end()) {
+        g = it->second;
+    } else {
+        g = kc_resident_max_blocks(d, v);
+        resident_cache[key] = g;
+    }
+    return resident_cap > 0 ? std::min(g, resident_cap) : g;
+}
+
+bool kc_handle::resident_fit(int d, uint64_t len, int* v, uint32_t* G)
+{
+    for (int q = 0; q < 2; ++q) {
+        const uint32_t g = kc_resident_blocks_for(d, q, len);
+        if (g > 0 && (int64_t)g <= (int64_t)resident_max(d, q)) {
+            *v = q;
+            *G = g;
+            return true;
+        }
+    }
+    return false;
 }

@@ -513,17 +513,18 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
     kc_enqueue_gon_prep(RG, HG, jobs, s);
     bool done = false;
     if (h->allow_resident) {
-        const uint32_t G = kc_resident_blocks_for(d, nc);
-        if (G > 0 && (int)G <= h->resident_max(d)) {
+        int v = 0;
+        uint32_t G = 0;
+        if (h->resident_fit(d, nc, &v, &G)) {
             const uint64_t sw = kc_resident_slot_words((int)k, G);
             u64* slots = (u64*)h->ws("e2.slots", 8ull * sw);
             uint32_t* abort_flag = (uint32_t*)h->ws("e2.abort", 64);
             if (!slots || !abort_flag) return h->fail(KC_ENOMEM, "workspace allocation failed");
             kc_fill_u64(slots, 0ull, sw, s);
             kc_fill_u32(abort_flag, 0u, 1, s);
-            if (kc_gon_resident(d, G, RG.xs, RG.stride, 0, nc, nullptr, 0, (int)k, RG.mind,
+            if (kc_gon_resident(d, v, G, RG.xs, RG.stride, 0, nc, nullptr, 0, (int)k, RG.mind,
                                 RG.keys, slots, abort_flag, h->spin_limit, nullptr, 0,
-                                h->status_word, s) == hipSuccess) {
+                                h->status_word, nullptr, nullptr, s) == hipSuccess) {
                 done = true;
             } else {
                 (void)hipGetLastError();

@@ -34,6 +34,7 @@ struct kc_handle {
     std::map<std::string, void*> shadow_ptr;
     std::map<std::string, GraphEntry> graphs;
     std::map<int, int> resident_cache;
+    int resident_cap = 0;             // blocks per resident launch, 0: no cap
     bool timing = false;
     struct TimedSpan {
         hipEvent_t a, b;
@@ -56,7 +57,12 @@ struct kc_handle {
     void* upload(const std::string& name, const void* src, size_t bytes);
     int run_graph(const std::string& key, hipStream_t stream,
                   const std::function<void(hipStream_t)>& enqueue);
-    int resident_max(int d);
+    // Co-resident blocks of resident variant v for dimension d (0: none),
+    // lowered to resident_cap when that is set.
+    int resident_max(int d, int v);
+    // The first resident variant whose grid for `len` points is co-resident:
+    // sets *v and *G and returns true, or returns false.
+    bool resident_fit(int d, uint64_t len, int* v, uint32_t* G);
 };
 
 // One segment of a batched Gonzalez run, as the host describes it.
@@ -87,6 +93,14 @@ int kc_run_gon_stream(kc_handle* h, const std::string& key, const KcGonRun& R,
                       const KcGonHost& H, const std::vector<KcGonJob>& jobs,
                       const char* span, hipStream_t s,
                       const std::function<void(hipStream_t)>& finish);
+// The steps of a planned FP32 run on the resident engine, several segments
+// per cooperative launch.  Sets *done when the keys and min-distances are
+// enqueued; leaves it false, having enqueued nothing that the streaming
+// engine's prep does not redo, when some segment fits no resident grid or
+// a launch is refused.
+int kc_run_gon_resident_batch(kc_handle* h, const std::string& key, const KcGonRun& R,
+                              const KcGonHost& H, const std::vector<KcGonJob>& jobs,
+                              const char* span, hipStream_t s, bool* done);
 // BF16 stream engine (kc_bf16.hip)
 void kc_enqueue_bf16_prep(const KcGonRun& R, const KcBf16Run& B, const KcGonHost& H,
                           const std::vector<KcGonJob>& jobs, hipStream_t s);

@@ -62,17 +62,24 @@ uint64_t kc_resident_slot_words(int k, uint32_t G);
 void kc_gon_step(const float* xs, uint64_t stride, int d, float* mind, u64* part,
                  const KcSeg* segs, const uint32_t* blk_seg, const uint32_t* blk_start,
                  uint32_t nblk, int t, hipStream_t s);
-int kc_resident_max_blocks(int d);
-uint32_t kc_resident_blocks_for(int d, uint32_t len);
+// Resident engine variants (v = 0: balanced, 1: most points per block; a
+// dimension without a kernel of that variant reports 0 points / blocks).
+int kc_resident_max_blocks(int d, int v);
+uint32_t kc_resident_blocks_for(int d, int v, uint64_t len);
+uint32_t kc_resident_block_points(int d, int v);
 // `xa` (nullable): the same points as rows of lda floats (the caller's
 // array), used to gather candidate coordinates; NULL gathers from xs.  A
 // wait that exceeds the spin limit raises abort_flag and bit 0 of *status.
-hipError_t kc_gon_resident(int d, uint32_t G, const float* xs, uint64_t stride,
+// With `blks` (device, one uint4 per block: segment, block within it, blocks
+// of the segment, first block of the segment) the launch runs several
+// segments of `segs` at once and base/len/first/k come from each segment
+// (keys at its keyoff, xa rows from its src).
+hipError_t kc_gon_resident(int d, int v, uint32_t G, const float* xs, uint64_t stride,
                            uint64_t base, uint32_t len, const uint32_t* len_ptr,
                            uint32_t first, int k, float* mind,
                            u64* keys, u64* slots, uint32_t* abort_flag,
                            uint32_t spin_limit, const float* xa, int64_t lda, uint32_t* status,
-                           hipStream_t s);
+                           const KcSeg* segs, const uint4* blks, hipStream_t s);
 void kc_gon_finish(const KcGonRun& R, int64_t* centers, int64_t* n_chosen, double* trace,
                    double* radius_out, const int64_t* report_base, const int64_t* remap,
                    hipStream_t s);

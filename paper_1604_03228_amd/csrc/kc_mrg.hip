@@ -273,7 +273,17 @@ int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int3
             kc_bf16_finish(R1, B1, cent1, nch1, nullptr, rad1, rb, st);
         });
     } else {
-        rc = kc_run_gon_stream(h, key1, R1, H1, jobs, "mrg_round1", s, finish1);
+        // all partitions on the resident engine, packed several per launch,
+        // when each one's points fit a co-resident grid; else streamed
+        bool done = false;
+        if (h->allow_resident) {
+            rc = kc_run_gon_resident_batch(h, key1, R1, H1, jobs, "mrg_round1", s, &done);
+            if (rc) return rc;
+        }
+        if (done)
+            rc = h->run_graph(key1 + ":finish", s, finish1);
+        else
+            rc = kc_run_gon_stream(h, key1, R1, H1, jobs, "mrg_round1", s, finish1);
     }
     if (rc) return rc;
 
@@ -307,17 +317,19 @@ int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int3
     if (rc) return rc;
     bool done = false;
     if (h->allow_resident) {
-        const uint32_t G = kc_resident_blocks_for(d, (uint32_t)cap);
-        if (G > 0 && (int)G <= h->resident_max(d)) {
+        int v = 0;
+        uint32_t G = 0;
+        if (h->resident_fit(d, cap, &v, &G)) {
             const uint64_t sw = kc_resident_slot_words((int)k, G);
             u64* slots = (u64*)h->ws("m2.slots", sizeof(u64) * sw);
             uint32_t* abort_flag = (uint32_t*)h->ws("m2.abort", 64);
             if (!slots || !abort_flag) return h->fail(KC_ENOMEM, "workspace allocation failed");
             kc_fill_u64(slots, 0ull, sw, s);
             kc_fill_u32(abort_flag, 0u, 1, s);
-            hipError_t e = kc_gon_resident(d, G, R2.xs, R2.stride, 0, (uint32_t)cap, len_ptr, 0,
+            hipError_t e = kc_gon_resident(d, v, G, R2.xs, R2.stride, 0, (uint32_t)cap, len_ptr, 0,
                                            (int)k, R2.mind, R2.keys, slots, abort_flag,
-                                           h->spin_limit, nullptr, 0, h->status_word, s);
+                                           h->spin_limit, nullptr, 0, h->status_word, nullptr,
+                                           nullptr, s);
             if (e == hipSuccess) {
                 done = true;
             } else {

@@ -98,12 +98,31 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
     const float* __restrict__ xs, uint64_t stride, uint64_t base, uint32_t len,
     const uint32_t* __restrict__ len_ptr, uint32_t first, int k, float* __restrict__ mind,
     u64* __restrict__ keys, u64* __restrict__ xbuf, uint32_t* __restrict__ abort_flag,
-    uint32_t spin_limit, const float* __restrict__ xa, int64_t lda, uint32_t* __restrict__ status)
+    uint32_t spin_limit, const float* __restrict__ xa, int64_t lda, uint32_t* __restrict__ status,
+    const KcSeg* __restrict__ segs, const uint4* __restrict__ blks)
 {
     static_assert(KC_LA_WPTS * PPT <= KC_LA_NONE, "block-local index must fit in 16 bits");
     constexpr uint32_t CMAX = KcLaCap<PPT>::value;
     constexpr int QL = CMAX / 64;   // candidates per leader lane
     static_assert(CMAX <= KC_LA_BLOCK, "one candidate per thread when gathering");
+    // Several segments per launch: blks[b] = (segment, block within it,
+    // blocks of the segment, first block of the segment); the segment's
+    // blocks are consecutive and exchange only among themselves.  Without
+    // blks the launch is one segment described by the scalar arguments.
+    uint32_t lb = blockIdx.x, gs = gridDim.x, b0 = 0;
+    if (blks) {
+        const uint4 bi = blks[blockIdx.x];
+        const KcSeg sg = segs[bi.x];
+        lb = bi.y;
+        gs = bi.z;
+        b0 = bi.w;
+        base = sg.base;
+        len = sg.len;
+        first = sg.first;
+        k = (int)sg.ksteps;
+        keys += sg.keyoff;
+        if (xa) xa += sg.src * (uint64_t)lda;
+    }
     if (len_ptr) len = min(len, *len_ptr);   // actual length known on the device
     __shared__ u64 sCk[CMAX];                 // candidate keys at the round's start
     __shared__ float sCx[D][CMAX];            // candidate coordinates
@@ -116,13 +135,12 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
     __shared__ uint32_t sWc[KC_LA_WAVES];
     __shared__ u64 sT[KC_LA_WAVES];           // each worker wave's (K+1)-th key
 
-    const uint32_t G = gridDim.x;   // <= KC_LA_GMAX (checked by the host)
-    const uint32_t NWB = G * KC_LA_WPB;     // exchange words of this grid
+    const uint32_t NWB = gs * KC_LA_WPB;    // exchange words of this segment
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
     const bool leader = wave == 0;
-    const uint32_t blk0 = blockIdx.x * (KC_LA_WPTS * PPT);
+    const uint32_t blk0 = lb * (KC_LA_WPTS * PPT);
     const uint32_t i0 = blk0 + (leader ? 0u : (wave - 1) * 64 + lane);
-    const bool recorder = blockIdx.x == 0 && tid == 0;   // the leader of block 0
+    const bool recorder = lb == 0 && tid == 0;   // the leader of the segment's block 0
 
     // the points come from the staging copy (coalesced rows of one
     // coordinate); the caller's rows serve the scattered candidate gathers
@@ -222,8 +240,8 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                 for (int q = 0; q < KC_LA_NPT; ++q) {
                     const uint32_t e = tid_r + q * KC_LA_BLOCK;
                     if (e < NWB && !((have >> q) & 1u)) {
-                        const u64 w = __hip_atomic_load(rb + e, __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
+                        const u64 w = __hip_atomic_load(rb + (uint64_t)b0 * KC_LA_WPB + e,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         if ((((uint32_t)w) >> 16) == tag) {
                             const u64 kw = kc_la_decode<PPT>(w, e / KC_LA_WPB);
                             if (e % KC_LA_WPB == KC_LA_WPB - 1) tl = kc_umax64(tl, kw);
@@ -535,26 +553,38 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
             const uint32_t i = i0 + p * KC_LA_WPTS;
             if (i < len) mind[base + i] = m[p];
         }
-    } else if (blockIdx.x == 0) {
+    } else if (lb == 0) {
         // keys past an early stop (radius 0, or an abort) read as radius 0
         for (int u = t + (int)lane; u < k; u += 64) keys[u] = 0;
     }
 }
 
-// Points per worker lane: the coordinates take at most about 130 VGPRs, so
-// two waves of the 512-thread blocks share each SIMD.
-static int resident_ppt(int d)
+// Points per worker lane, two variants per dimension.  Variant 0 balances
+// the workers' arithmetic per step against the leader's (the coordinates
+// take at most about 130 VGPRs); variant 1 holds as many points as two
+// waves per SIMD allow without spilling and serves inputs too large for
+// variant 0's co-resident grid.
+#define KC_RES_DIMS(X) X(2, 32) X(3, 24) X(8, 12) X(10, 9) X(16, 6) X(32, 3) X(41, 2)
+#define KC_RES_DIMS_BIG(X) X(3, 30) X(8, 15) X(10, 14) X(16, 9)
+
+static int resident_ppt(int d, int v)
 {
-    switch (d) {
-    case 2: return 32;
-    case 3: return 24;
-    case 8: return 12;
-    case 10: return 9;
-    case 16: return 6;
-    case 32: return 3;
-    case 41: return 2;
-    default: return 0;
+#define KC_CASE(DD, PP) \
+    case DD: return PP;
+    if (v == 0) {
+        switch (d) {
+            KC_RES_DIMS(KC_CASE)
+        default: return 0;
+        }
     }
+    if (v == 1) {
+        switch (d) {
+            KC_RES_DIMS_BIG(KC_CASE)
+        default: return 0;
+        }
+    }
+#undef KC_CASE
+    return 0;
 }
 
 template <int D, int PPT>
@@ -563,12 +593,13 @@ static hipError_t launch_resident(uint32_t G, const float* xs, uint64_t stride,
                                   uint32_t first, int k,
                                   float* mind, u64* keys, u64* xbuf, uint32_t* abort_flag,
                                   uint32_t spin_limit, const float* xa, int64_t lda,
-                                  uint32_t* status, hipStream_t s)
+                                  uint32_t* status, const KcSeg* segs, const uint4* blks,
+                                  hipStream_t s)
 {
     void* args[] = {(void*)&xs,    (void*)&stride, (void*)&base, (void*)&len,
                     (void*)&len_ptr, (void*)&first, (void*)&k,      (void*)&mind, (void*)&keys,
                     (void*)&xbuf, (void*)&abort_flag, (void*)&spin_limit, (void*)&xa,
-                    (void*)&lda, (void*)&status};
+                    (void*)&lda, (void*)&status, (void*)&segs, (void*)&blks};
     return hipLaunchCooperativeKernel((const void*)k_gon_resident<D, PPT>, dim3(G),
                                       dim3(KC_LA_BLOCK), args, 0, s);
 }
@@ -589,24 +620,37 @@ static int max_resident_blocks()
     return g < KC_LA_GMAX ? g : KC_LA_GMAX;   // the exchange buffer's capacity
 }
 
-#define KC_RES_DIMS(X) X(2, 32) X(3, 24) X(8, 12) X(10, 9) X(16, 6) X(32, 3) X(41, 2)
-
-int kc_resident_max_blocks(int d)
+int kc_resident_max_blocks(int d, int v)
 {
-    switch (d) {
 #define KC_CASE(DD, PP) \
     case DD: return max_resident_blocks<DD, PP>();
-        KC_RES_DIMS(KC_CASE)
-#undef KC_CASE
-    default: return 0;
+    if (v == 0) {
+        switch (d) {
+            KC_RES_DIMS(KC_CASE)
+        default: return 0;
+        }
     }
+    if (v == 1) {
+        switch (d) {
+            KC_RES_DIMS_BIG(KC_CASE)
+        default: return 0;
+        }
+    }
+#undef KC_CASE
+    return 0;
 }
 
-uint32_t kc_resident_blocks_for(int d, uint32_t len)
+uint32_t kc_resident_block_points(int d, int v)
 {
-    const uint64_t per = (uint64_t)resident_ppt(d) * KC_LA_WPTS;
+    return (uint32_t)resident_ppt(d, v) * KC_LA_WPTS;
+}
+
+uint32_t kc_resident_blocks_for(int d, int v, uint64_t len)
+{
+    const uint64_t per = (uint64_t)resident_ppt(d, v) * KC_LA_WPTS;
     if (per == 0) return 0;
-    return (uint32_t)((len + per - 1) / per);
+    const uint64_t g = (len + per - 1) / per;
+    return g > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)g;
 }
 
 // Exchange buffer of the engine (two rounds), to be zero-filled before each
@@ -620,21 +664,31 @@ uint64_t kc_resident_slot_words(int k, uint32_t G)
 
 // Returns hipSuccess, or an error when the shape has no resident kernel or
 // the grid cannot be co-resident (the caller then streams instead).
-hipError_t kc_gon_resident(int d, uint32_t G, const float* xs, uint64_t stride,
+hipError_t kc_gon_resident(int d, int v, uint32_t G, const float* xs, uint64_t stride,
                            uint64_t base, uint32_t len, const uint32_t* len_ptr,
                            uint32_t first, int k, float* mind,
                            u64* keys, u64* slots, uint32_t* abort_flag, uint32_t spin_limit,
-                           const float* xa, int64_t lda, uint32_t* status, hipStream_t s)
+                           const float* xa, int64_t lda, uint32_t* status, const KcSeg* segs,
+                           const uint4* blks, hipStream_t s)
 {
     if (G == 0 || G > KC_LA_GMAX) return hipErrorInvalidValue;
-    switch (d) {
 #define KC_CASE(DD, PP)                                                                  \
     case DD:                                                                             \
         return launch_resident<DD, PP>(G, xs, stride, base, len, len_ptr, first, k, mind, keys, \
-                                       slots, abort_flag, spin_limit, xa, lda, status, s);
-        KC_RES_DIMS(KC_CASE)
-#undef KC_CASE
-    default:
-        return hipErrorInvalidValue;
+                                       slots, abort_flag, spin_limit, xa, lda, status, segs, \
+                                       blks, s);
+    if (v == 0) {
+        switch (d) {
+            KC_RES_DIMS(KC_CASE)
+        default: return hipErrorInvalidValue;
+        }
     }
+    if (v == 1) {
+        switch (d) {
+            KC_RES_DIMS_BIG(KC_CASE)
+        default: return hipErrorInvalidValue;
+        }
+    }
+#undef KC_CASE
+    return hipErrorInvalidValue;
 }

@@ -110,6 +110,30 @@ def test_resident_candidate_cap(kc, orc):
         assert np.array_equal(tr, otr)
 
 
+# The resident engine's large variant (4,032 points per block at d = 16
+# instead of 2,688) takes inputs beyond the balanced variant's grid: forced
+# by a 4-block cap at 15,000 points, and at 800,000 points by the
+# co-resident grid itself (at most 256 blocks hold 688,128 points).
+@pytest.mark.parametrize("n,cap", [(15_000, 4), (800_000, 0)])
+def test_resident_large_variant(kc, orc, n, cap):
+    rng = np.random.default_rng(n)
+    X = rng.integers(-50, 51, (n, 16)).astype(np.float32)
+    k = 64
+    h = kc.Handle()
+    h.set_option("resident_blocks", cap)
+    h.set_option("timing", 1)
+    Xd = torch.from_numpy(X).cuda()
+    c, tr, nch = kc.gonzalez(Xd, k, 3, handle=h)
+    assert h.device_status() == 0
+    _, la, iv = h.timing_read("gon_resident")
+    assert (la, iv) == (1, 1)
+    oc, otr, og = orc.gon(X, k, 3)
+    assert int(nch.item()) == og
+    assert np.array_equal(c.cpu().numpy(), oc)
+    assert np.array_equal(tr.cpu().numpy(), otr)
+    h.close()
+
+
 def test_config2_prefix(kc):
     X = W.config2(200_000)
     c1, t1, _ = run_gon(kc, X, 100, 0)
