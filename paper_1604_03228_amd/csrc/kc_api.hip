@@ -318,41 +318,56 @@ int kc_run_gon_resident_batch(kc_handle* h, const std::string& key, const KcGonR
 {
     *done = false;
     const int d = R.d;
-    // each segment takes the first variant whose grid for it is co-resident
-    struct Item {
-        uint32_t seg, G;
-    };
-    std::vector<Item> items[2];
-    int gmax[2] = {0, 0};
-    for (size_t q = 0; q < H.segs.size(); ++q) {
-        const KcSeg& sg = H.segs[q];
-        if (sg.len == 0 || sg.ksteps == 0) continue;   // nothing to choose
-        int v = 0;
-        uint32_t G = 0;
-        if (!h->resident_fit(d, sg.len, &v, &G)) return KC_OK;
-        gmax[v] = h->resident_max(d, v);
-        items[v].push_back({(uint32_t)q, G});
-    }
-    // first-fit decreasing into launches of at most gmax blocks; the blocks
-    // of a segment are consecutive in its launch
+    // Two packings: every segment on the first variant whose grid for it is
+    // co-resident, or every segment on the large variant (fewer blocks, so
+    // fewer launches, at more arithmetic per step).  The one with the lower
+    // estimated duration runs.
     struct Launch {
         int v;
         uint32_t G;
         std::vector<uint32_t> segs;
     };
-    std::vector<Launch> launches;
-    for (int v = 0; v < 2; ++v) {
-        std::stable_sort(items[v].begin(), items[v].end(),
-                         [](const Item& a, const Item& b) { return a.G > b.G; });
-        const size_t l0 = launches.size();
-        for (const Item& it : items[v]) {
-            size_t l = l0;
-            while (l < launches.size() && launches[l].G + it.G > (uint32_t)gmax[v]) ++l;
-            if (l == launches.size()) launches.push_back({v, 0, {}});
-            launches[l].G += it.G;
-            launches[l].segs.push_back(it.seg);
+    auto pack = [&](bool large, std::vector<Launch>& out) -> bool {
+        struct Item {
+            uint32_t seg, G;
+        };
+        std::vector<Item> items[2];
+        out.clear();
+        for (size_t q = 0; q < H.segs.size(); ++q) {
+            const KcSeg& sg = H.segs[q];
+            if (sg.len == 0 || sg.ksteps == 0) continue;   // nothing to choose
+            int v = 1;
+            uint32_t G = kc_resident_blocks_for(d, 1, sg.len);
+            if (!large && !h->resident_fit(d, sg.len, &v, &G)) return false;
+            if (large && (G == 0 || (int64_t)G > (int64_t)h->resident_max(d, 1))) return false;
+            items[v].push_back({(uint32_t)q, G});
         }
-    }
+        // first-fit decreasing into launches of at most gmax blocks; the
+        // blocks of a segment are consecutive in its launch
+        for (int v = 0; v < 2; ++v) {
+            const uint32_t gmax = items[v].empty() ? 0u : (uint32_t)h->resident_max(d, v);
+            std::stable_sort(items[v].begin(), items[v].end(),
+                             [](const Item& a, const Item& b) { return a.G > b.G; });
+            const size_t l0 = out.size();
+            for (const Item& it : items[v]) {
+                size_t l = l0;
+                while (l < out.size() && out[l].G + it.G > gmax) ++l;
+                if (l == out.size()) out.push_back({v, 0, {}});
+                out[l].G += it.G;
+                out[l].segs.push_back(it.seg);
+            }
+        }
+        return true;
+    };
+    auto cost = [&](const std::vector<Launch>& L) {
+        double c = 0;
+        for (const Launch& x : L) c += kc_resident_launch_cycles(d, x.v, R.kmax);
+        return c;
+    };
+    std::vector<Launch> launches, alt;
+    const bool fit = pack(false, launches);
+    if (pack(true, alt) && (!fit || cost(alt) < cost(launches))) launches.swap(alt);
+    else if (!fit) return KC_OK;
     if (launches.empty()) return KC_OK;
     std::vector<uint4> tab;
     std::vector<size_t> off;

@@ -293,6 +293,24 @@ __device__ __forceinline__ double kc_hi_bound(double v, double err, double E)
     return r * r * (1.0 + 1e-12);
 }
 
+// Append `val` to list for every lane whose `pred` holds, one atomic per
+// wave.  All 64 lanes must call it together.
+__device__ __forceinline__ void kc_wave_append(bool pred, uint32_t val, uint32_t* list,
+                                               uint32_t* nlist)
+{
+    const u64 b = __ballot(pred);
+    if (b == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __builtin_ctzll(b);
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(nlist, (uint32_t)__builtin_popcountll(b));
+    base = (uint32_t)__shfl((int)base, leader, 64);
+    if (pred) list[base + (uint32_t)__builtin_popcountll(b & ((1ull << lane) - 1ull))] = val;
+}
+
+// With labels == NULL only the radius is wanted: an ambiguous point matters
+// only if its upper bound reaches the largest lower bound, and
+// k_radius_candidates lists exactly those, so ambiguity lists nothing.
 __global__ void k_assign_epilogue(uint32_t n, int d, const int32_t* __restrict__ arg,
                                   const float* __restrict__ m1, const float* __restrict__ m2,
                                   const float* __restrict__ nxv, const float* __restrict__ ex,
@@ -302,6 +320,7 @@ __global__ void k_assign_epilogue(uint32_t n, int d, const int32_t* __restrict__
 {
     const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     float lo_f = 0.f;
+    bool amb = false;
     if (p < n) {
         const double g = (6.0 * d + 32.0) * 5.9604644775390625e-8;
         const double nx = nxv[p];
@@ -310,16 +329,18 @@ __global__ void k_assign_epilogue(uint32_t n, int d, const int32_t* __restrict__
         const double err = g * s * s + 1e-30 * d;
         const double E = ex ? (double)ex[p] + (double)cmax[1] : 0.0;
         const double d1 = nx + (double)m1[p];
-        const double d2 = nx + (double)m2[p];
         const double hi1 = kc_hi_bound(d1, err, E);
         const double lo1 = kc_lo_bound(d1, err, E);
-        const double lo2 = kc_lo_bound(d2, err, E);
-        const bool amb = !(lo2 > hi1);
-        if (labels) labels[p] = amb ? -1 : arg[p];
-        if (amb) list[atomicAdd(nlist, 1u)] = p;
+        if (labels) {
+            const double d2 = nx + (double)m2[p];
+            const double lo2 = kc_lo_bound(d2, err, E);
+            amb = !(lo2 > hi1);
+            labels[p] = amb ? -1 : arg[p];
+        }
         hi_out[p] = (float)hi1 * (1.f + 1e-6f);
         lo_f = (float)lo1 * (1.f - 1e-6f);
     }
+    kc_wave_append(amb, p, list, nlist);
     // block max of the lower bounds, one atomic per block
     __shared__ float red[4];
     float v = lo_f;
@@ -340,8 +361,8 @@ __global__ void k_radius_candidates(uint32_t n, const float* __restrict__ hi,
                                     uint32_t* __restrict__ list, uint32_t* __restrict__ nlist)
 {
     const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    if (hi[p] >= *lo_max) list[atomicAdd(nlist, 1u)] = p;
+    const float L = *lo_max;
+    kc_wave_append(p < n && hi[p] >= L, p, list, nlist);
 }
 
 // One wave per listed point: exact FP64 nearest center (lowest position on

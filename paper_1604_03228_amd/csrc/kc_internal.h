@@ -67,6 +67,7 @@ void kc_gon_step(const float* xs, uint64_t stride, int d, float* mind, u64* part
 int kc_resident_max_blocks(int d, int v);
 uint32_t kc_resident_blocks_for(int d, int v, uint64_t len);
 uint32_t kc_resident_block_points(int d, int v);
+double kc_resident_launch_cycles(int d, int v, uint32_t k);
 // `xa` (nullable): the same points as rows of lda floats (the caller's
 // array), used to gather candidate coordinates; NULL gathers from xs.  A
 // wait that exceeds the spin limit raises abort_flag and bit 0 of *status.

@@ -41,6 +41,8 @@
 // round r+1 words.  Only relaxed device-scope atomics carry data.  Any block
 // whose wait exceeds the spin limit raises abort_flag; every block then
 // leaves its loop.
+#include <algorithm>
+
 #include "kc_device.h"
 #include "kc_internal.h"
 
@@ -651,6 +653,19 @@ uint32_t kc_resident_blocks_for(int d, int v, uint64_t len)
     if (per == 0) return 0;
     const uint64_t g = (len + per - 1) / per;
     return g > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)g;
+}
+
+// Estimated cycles of one launch of variant v for k steps: each step costs
+// the larger of the leader's selection (about 1,600 cycles) and a worker
+// SIMD's arithmetic (two waves, PPT points of 2d+1 VALU instructions, 4
+// cycles each); each lookahead round adds about 16,800 cycles (7 us) of
+// publication and exchange, and clustered inputs certify about 6 steps per
+// round.  Used only to choose between packings of a batch.
+double kc_resident_launch_cycles(int d, int v, uint32_t k)
+{
+    const double ppt = resident_ppt(d, v);
+    const double step = std::max(1600.0, ppt * (2.0 * d + 1.0) * 8.0);
+    return (double)k * step + ((double)k / 6.0) * 16800.0;
 }
 
 // Exchange buffer of the engine (two rounds), to be zero-filled before each
