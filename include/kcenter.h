@@ -137,7 +137,11 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
  * (first center: the partition's first point), all partitions in the same
  * launches; round 2 runs Gonzalez(k) on the union of their centers in
  * ascending index order (first center: the smallest index); the result is
- * assigned to all points for its covering radius.
+ * assigned to all points for its covering radius.  When every partition
+ * fits a register-resident grid, round 1 runs on the resident engine from
+ * the FP32 points in either precision (there is then no stream for BF16 to
+ * shorten); otherwise it streams, in BF16 with exact FP32 rescoring when
+ * pts->prec asks for it.  Both precisions choose the same centers.
  *   offsets   HOST int64 [m+1], 0 = o_0 <= o_1 <= ... <= o_m = n: partition
  *             p is rows [o_p, o_{p+1}); empty partitions are allowed.
  *   m         partitions, 1 <= m.

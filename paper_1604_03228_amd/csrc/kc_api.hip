@@ -271,14 +271,30 @@ int kc_plan_gon(kc_handle* h, const std::string& pre, int d, uint32_t tile,
     return KC_OK;
 }
 
-// Enqueue staging + init of a planned run (streaming engine).
-void kc_enqueue_gon_prep(const KcGonRun& R, const KcGonHost& H,
-                         const std::vector<KcGonJob>& jobs, hipStream_t s)
+// Enqueue the SoA staging of every job with source rows: one launch when all
+// of them read the same array, else one per job.
+void kc_enqueue_stage(const KcGonRun& R, const KcGonHost& H, const std::vector<KcGonJob>& jobs,
+                      hipStream_t s)
 {
+    bool shared = jobs.size() > 1 && jobs[0].X != nullptr;
+    for (const KcGonJob& j : jobs)
+        if (j.X != jobs[0].X || j.ld != jobs[0].ld) shared = false;
+    if (shared) {
+        kc_stage_soa_batch(jobs[0].X, jobs[0].ld, R.d, R.segs, R.blk_seg, R.blk_start, R.nblk,
+                           R.tile, (float*)R.xs, R.stride, s);
+        return;
+    }
     for (size_t q = 0; q < jobs.size(); ++q)
         if (jobs[q].X)
             kc_stage_soa(jobs[q].X, jobs[q].ld, R.d, jobs[q].row0, jobs[q].len, (float*)R.xs,
                          R.stride, H.segs[q].base, s);
+}
+
+// Enqueue staging + init of a planned run (streaming engine).
+void kc_enqueue_gon_prep(const KcGonRun& R, const KcGonHost& H,
+                         const std::vector<KcGonJob>& jobs, hipStream_t s)
+{
+    kc_enqueue_stage(R, H, jobs, s);
     kc_fill_u32((uint32_t*)R.mind, 0x7F800000u, R.stride, s);   // +inf
     kc_fill_u64(R.part, 0ull, R.keysum * KC_PARTS * KC_PSTRIDE, s);
 }
@@ -391,10 +407,7 @@ int kc_run_gon_resident_batch(kc_handle* h, const std::string& key, const KcGonR
         if (j.X != xa || j.ld != jobs[0].ld) xa = nullptr;
     const int64_t lda = xa ? jobs[0].ld : 0;
     int rc = h->run_graph(key + ":rprep", s, [&](hipStream_t st) {
-        for (size_t q = 0; q < jobs.size(); ++q)
-            if (jobs[q].X)
-                kc_stage_soa(jobs[q].X, jobs[q].ld, d, jobs[q].row0, jobs[q].len, (float*)R.xs,
-                             R.stride, H.segs[q].base, st);
+        kc_enqueue_stage(R, H, jobs, st);
         kc_fill_u64(bar, 0ull, bw * launches.size(), st);
     });
     if (rc) return rc;

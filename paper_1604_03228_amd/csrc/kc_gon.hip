@@ -83,6 +83,35 @@ void kc_stage_soa(const float* X, int64_t ld, int d, uint64_t row0, uint32_t len
                        ld, d, row0, len, xs, stride, base, padded);
 }
 
+// Staging of every segment of a planned run in one launch (all segments read
+// the same row-major array): block b covers the tile of `tile` points that
+// starts at blk_start[b] in segment blk_seg[b], padding columns up to the
+// next multiple of 64 repeat the segment's first row.
+__global__ void k_stage_soa_batch(const float* __restrict__ X, int64_t ld, int d,
+                                  const KcSeg* __restrict__ segs,
+                                  const uint32_t* __restrict__ blk_seg,
+                                  const uint32_t* __restrict__ blk_start, uint32_t tile,
+                                  float* __restrict__ xs, uint64_t stride)
+{
+    const KcSeg sg = segs[blk_seg[blockIdx.x]];
+    const uint32_t st = blk_start[blockIdx.x];
+    const uint32_t padded = (sg.len + 63u) & ~63u;
+    const uint32_t end = st + tile < padded ? st + tile : padded;
+    for (uint32_t i = st + threadIdx.x; i < end; i += blockDim.x) {
+        const float* src = X + (sg.src + (i < sg.len ? i : 0)) * (uint64_t)ld;
+        for (int j = 0; j < d; ++j) xs[(uint64_t)j * stride + sg.base + i] = src[j];
+    }
+}
+
+void kc_stage_soa_batch(const float* X, int64_t ld, int d, const KcSeg* segs,
+                        const uint32_t* blk_seg, const uint32_t* blk_start, uint32_t nblk,
+                        uint32_t tile, float* xs, uint64_t stride, hipStream_t s)
+{
+    if (nblk == 0) return;
+    hipLaunchKernelGGL(k_stage_soa_batch, dim3(nblk), dim3(256), 0, s, X, ld, d, segs, blk_seg,
+                       blk_start, tile, xs, stride);
+}
+
 // ---------------------------------------------------------------------------
 // streaming step: one block = 1024 consecutive points of one segment.
 

@@ -2,8 +2,11 @@
 // Gonzalez entry, and the assignment entry point.
 //
 // MRG on the device, without host synchronisation:
-//   round 1   all m partitions are segments of one batched Gonzalez run
-//             (FP32 stream, or BF16 stream + exact FP32 rescoring);
+//   round 1   all m partitions are segments of one batched Gonzalez run:
+//             register-resident, several partitions per cooperative
+//             launch, when every partition fits a co-resident grid (in
+//             either precision), else streamed (FP32, or BF16 + exact FP32
+//             rescoring);
 //   union     k_mrg_union sorts each partition's centers (global indices)
 //             by rank and concatenates them in partition order, which is
 //             ascending global order because partitions are contiguous row
@@ -103,7 +106,9 @@ int kc_bf16_alloc(kc_handle* h, const std::string& pre, const KcGonRun& R, KcBf1
     h->last_bf16_kmax = R.kmax;
     const double u = 5.9604644775390625e-8;
     B.g = (float)((kc_gamma32(R.d) + 16.0 * u) * (1.0 + 1e-6));
-    B.rescore_blocks = 256;
+    // about one listed point per rescoring wave: a wave rescores its kept
+    // points one after another, each a chain of dependent loads
+    B.rescore_blocks = std::min<uint32_t>(2048, std::max<uint32_t>(256, R.nblk / 2));
     return KC_OK;
 }
 
@@ -250,7 +255,7 @@ int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int3
     }
     KcGonRun R1;
     KcGonHost H1;
-    rc = kc_plan_gon(h, "m1.", d, bf ? KC_BF_TILE_PTS : 1024, jobs, R1, H1);
+    rc = kc_plan_gon(h, "m1.", d, 1024, jobs, R1, H1);
     if (rc) return rc;
     const int64_t* rb =
         (const int64_t*)h->upload("m1.rb", offsets, sizeof(int64_t) * (size_t)m);
@@ -260,30 +265,39 @@ int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int3
     if (!rb || !cent1 || !nch1 || !rad1) return h->fail(KC_ENOMEM, "workspace allocation failed");
     const std::string key1 = kc_key("mrg1", {pts->f32, pts->bf16, cent1, rad1},
                                     {pts->n, d, pts->ld, k, m, bf});
-    auto finish1 = [&](hipStream_t st) {
-        kc_fill_u64((u64*)cent1, ~0ull, (uint64_t)m * k, st);
-        kc_gon_finish(R1, cent1, nch1, nullptr, rad1, rb, nullptr, st);
-    };
-    if (bf) {
-        KcBf16Run B1;
-        rc = kc_bf16_alloc(h, "m1b.", R1, B1);
+    // All partitions on the resident engine, packed several per launch, when
+    // each one's points fit a co-resident grid.  This holds in BF16 mode too
+    // (from the full-precision copy): register-resident points are read from
+    // HBM once, so there is no stream for BF16 to halve, and the sequences
+    // are the FP32 path's by construction.  Otherwise the partitions stream,
+    // in BF16 with exact rescoring or in FP32.
+    bool done = false;
+    if (h->allow_resident) {
+        rc = kc_run_gon_resident_batch(h, key1, R1, H1, jobs, "mrg_round1", s, &done);
         if (rc) return rc;
-        rc = kc_run_bf16(h, key1, R1, B1, H1, jobs, "mrg_round1", s, [&](hipStream_t st) {
+    }
+    if (done) {
+        rc = h->run_graph(key1 + ":finish", s, [&](hipStream_t st) {
             kc_fill_u64((u64*)cent1, ~0ull, (uint64_t)m * k, st);
-            kc_bf16_finish(R1, B1, cent1, nch1, nullptr, rad1, rb, st);
+            kc_gon_finish(R1, cent1, nch1, nullptr, rad1, rb, nullptr, st);
+        });
+    } else if (bf) {
+        KcGonRun Rb;
+        KcGonHost Hb;
+        rc = kc_plan_gon(h, "m1s.", d, KC_BF_TILE_PTS, jobs, Rb, Hb);
+        if (rc) return rc;
+        KcBf16Run B1;
+        rc = kc_bf16_alloc(h, "m1b.", Rb, B1);
+        if (rc) return rc;
+        rc = kc_run_bf16(h, key1 + ":bf", Rb, B1, Hb, jobs, "mrg_round1", s, [&](hipStream_t st) {
+            kc_fill_u64((u64*)cent1, ~0ull, (uint64_t)m * k, st);
+            kc_bf16_finish(Rb, B1, cent1, nch1, nullptr, rad1, rb, st);
         });
     } else {
-        // all partitions on the resident engine, packed several per launch,
-        // when each one's points fit a co-resident grid; else streamed
-        bool done = false;
-        if (h->allow_resident) {
-            rc = kc_run_gon_resident_batch(h, key1, R1, H1, jobs, "mrg_round1", s, &done);
-            if (rc) return rc;
-        }
-        if (done)
-            rc = h->run_graph(key1 + ":finish", s, finish1);
-        else
-            rc = kc_run_gon_stream(h, key1, R1, H1, jobs, "mrg_round1", s, finish1);
+        rc = kc_run_gon_stream(h, key1, R1, H1, jobs, "mrg_round1", s, [&](hipStream_t st) {
+            kc_fill_u64((u64*)cent1, ~0ull, (uint64_t)m * k, st);
+            kc_gon_finish(R1, cent1, nch1, nullptr, rad1, rb, nullptr, st);
+        });
     }
     if (rc) return rc;
 
@@ -315,7 +329,7 @@ int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int3
         kc_enqueue_gon_prep(R2, H2, jobs2, st);
     });
     if (rc) return rc;
-    bool done = false;
+    done = false;
     if (h->allow_resident) {
         int v = 0;
         uint32_t G = 0;

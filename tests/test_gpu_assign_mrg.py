@@ -112,13 +112,17 @@ def int_points(n, d, seed):
     return rng.integers(-100, 101, (n, d)).astype(np.float32)
 
 
+# resident = False forces round 1 onto the streaming engines (FP32, or BF16
+# with exact rescoring); with it the partitions are register-resident in
+# either precision
+@pytest.mark.parametrize("resident", [True, False])
 @pytest.mark.parametrize("bf16", [False, True])
-def test_mrg_integer_exact(kc, orc, bf16):
+def test_mrg_integer_exact(kc, orc, bf16, resident):
     X = int_points(60_000, 16, 7)
     off = W.partition_offsets(60_000, 12, 0.5, seed=7)
     off = np.r_[off[:3], off[3], off[3:]]   # an extra empty partition
     k = 25
-    g = gpu_mrg(kc, X, off, k, bf16)
+    g = gpu_mrg(kc, X, off, k, bf16, handle=kc.Handle(resident=resident))
     o = orc.mrg(X, off, k)
     assert np.array_equal(g["round1"], o["round1"])
     assert np.array_equal(g["r1"], o["r1"])
@@ -218,10 +222,11 @@ def test_mrg_gauss_small(kc, orc):
     k = 40
     g = gpu_mrg(kc, X, off, k)
     check_mrg_float(orc, X, off, k, g)
-    gb = gpu_mrg(kc, X, off, k, bf16=True)
-    assert np.array_equal(g["round1"], gb["round1"])
-    assert np.array_equal(g["centers"], gb["centers"])
-    assert g["radius"] == gb["radius"]
+    for resident in (True, False):
+        gb = gpu_mrg(kc, X, off, k, bf16=True, handle=kc.Handle(resident=resident))
+        assert np.array_equal(g["round1"], gb["round1"])
+        assert np.array_equal(g["centers"], gb["centers"])
+        assert g["radius"] == gb["radius"]
 
 
 @pytest.mark.slow
@@ -232,7 +237,9 @@ def test_mrg_config3_full(kc, orc):
     h = kc.Handle()
     g = gpu_mrg(kc, X, off, k, handle=h)
     check_mrg_float(orc, X, off, k, g)
-    gb = gpu_mrg(kc, X, off, k, bf16=True, handle=h)
-    assert np.array_equal(g["centers"], gb["centers"])
-    assert np.array_equal(g["round1"], gb["round1"])
-    assert g["radius"] == gb["radius"]
+    hs = kc.Handle(resident=False)
+    for bf in (False, True):   # both streaming engines
+        gs = gpu_mrg(kc, X, off, k, bf16=bf, handle=hs)
+        assert np.array_equal(g["centers"], gs["centers"])
+        assert np.array_equal(g["round1"], gs["round1"])
+        assert g["radius"] == gs["radius"]
