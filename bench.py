@@ -29,7 +29,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
-FP32_VEC_PEAK_TFS = 157.3    # MI355X FP32 vector (dense)
+# VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane
+# operations per second (a wave64 instruction takes 4 cycles on a SIMD).
+# The quoted 157.3 TFLOP/s FP32 vector peak is this rate x 2 (FMA) x 2
+# (packed FP32); the engines use no packed FP32, so one FP32 instruction per
+# lane and cycle is their ceiling.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -235,13 +240,13 @@ def main():
         kern = "k_gon_resident"
         srcs = ["kc_resident.hip", "kc_device.h"]
         per = res_ms / res_l
-        flops = n * k * 3 * d             # sub + fma per coordinate
-        ach = flops / (per * 1e-3) / 1e12
+        ops = n * k * (2 * d + 1)         # sub + fma per coordinate, one min
+        ach = ops / (per * 1e-3) / 1e12
         roof = {"kernel": kern, "bound": "alu", "achieved": ach,
-                "peak": FP32_VEC_PEAK_TFS, "unit": "TFLOP/s",
-                "frac": ach / FP32_VEC_PEAK_TFS,
+                "peak": VALU_PEAK_TOPS, "unit": "T VALU lane-ops/s",
+                "frac": ach / VALU_PEAK_TOPS,
                 "avg_launch_ms": per, "launches": res_l,
-                "work_per_launch": "%d updates x %d flop" % (n * k, 3 * d)}
+                "work_per_launch": "%d updates x %d VALU ops" % (n * k, 2 * d + 1)}
     else:
         kern = "k_gon_step"
         srcs = ["kc_gon.hip", "kc_device.h"]

@@ -350,7 +350,11 @@ __global__ void k_assign_epilogue(uint32_t n, int d, const int32_t* __restrict__
     if (threadIdx.x == 0) {
         float r = red[0];
         for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmaxf(r, red[w]);
-        kc_atomic_max_f32_nonneg(lo_max, r);
+        // tens of thousands of blocks meet at one word: skip the atomic when
+        // the word already holds as much (a stale read is never larger)
+        const float cur = __uint_as_float(__hip_atomic_load(
+            (const uint32_t*)lo_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (r > cur) kc_atomic_max_f32_nonneg(lo_max, r);
     }
 }
 

@@ -86,17 +86,34 @@ void kc_stage_soa(const float* X, int64_t ld, int d, uint64_t row0, uint32_t len
 // Staging of every segment of a planned run in one launch (all segments read
 // the same row-major array): block b covers the tile of `tile` points that
 // starts at blk_start[b] in segment blk_seg[b], padding columns up to the
-// next multiple of 64 repeat the segment's first row.
+// next multiple of 64 repeat the segment's first row.  vec4: d and ld are
+// multiples of 4 and X is 16-byte aligned.
 __global__ void k_stage_soa_batch(const float* __restrict__ X, int64_t ld, int d,
                                   const KcSeg* __restrict__ segs,
                                   const uint32_t* __restrict__ blk_seg,
                                   const uint32_t* __restrict__ blk_start, uint32_t tile,
-                                  float* __restrict__ xs, uint64_t stride)
+                                  float* __restrict__ xs, uint64_t stride, int vec4)
 {
     const KcSeg sg = segs[blk_seg[blockIdx.x]];
     const uint32_t st = blk_start[blockIdx.x];
     const uint32_t padded = (sg.len + 63u) & ~63u;
     const uint32_t end = st + tile < padded ? st + tile : padded;
+    if (vec4) {
+        // one 16-byte group of a row per thread: consecutive threads read
+        // consecutive groups, so the row-major reads are fully coalesced
+        const uint32_t g4 = (uint32_t)d >> 2, items = (end - st) * g4;
+        for (uint32_t q = threadIdx.x; q < items; q += blockDim.x) {
+            const uint32_t i = st + q / g4, g = q - (q / g4) * g4;
+            const float4 v = *(const float4*)(X + (sg.src + (i < sg.len ? i : 0)) * (uint64_t)ld +
+                                              4 * g);
+            float* dst = xs + (uint64_t)(4 * g) * stride + sg.base + i;
+            dst[0] = v.x;
+            dst[stride] = v.y;
+            dst[2 * stride] = v.z;
+            dst[3 * stride] = v.w;
+        }
+        return;
+    }
     for (uint32_t i = st + threadIdx.x; i < end; i += blockDim.x) {
         const float* src = X + (sg.src + (i < sg.len ? i : 0)) * (uint64_t)ld;
         for (int j = 0; j < d; ++j) xs[(uint64_t)j * stride + sg.base + i] = src[j];
@@ -108,8 +125,9 @@ void kc_stage_soa_batch(const float* X, int64_t ld, int d, const KcSeg* segs,
                         uint32_t tile, float* xs, uint64_t stride, hipStream_t s)
 {
     if (nblk == 0) return;
+    const int vec4 = d % 4 == 0 && ld % 4 == 0 && ((uintptr_t)X & 15) == 0;
     hipLaunchKernelGGL(k_stage_soa_batch, dim3(nblk), dim3(256), 0, s, X, ld, d, segs, blk_seg,
-                       blk_start, tile, xs, stride);
+                       blk_start, tile, xs, stride, vec4);
 }
 
 // ---------------------------------------------------------------------------
