@@ -328,6 +328,22 @@ int kc_run_gon_stream(kc_handle* h, const std::string& key, const KcGonRun& R,
     return h->run_graph(key + ":finish", s, finish);
 }
 
+// A planned FP32 run on the resident engine when every segment fits a
+// co-resident grid (option "resident"), else on the streaming engine; then
+// `finish`.
+int kc_run_gon(kc_handle* h, const std::string& key, const KcGonRun& R, const KcGonHost& H,
+               const std::vector<KcGonJob>& jobs, const char* span, hipStream_t s,
+               const std::function<void(hipStream_t)>& finish)
+{
+    bool done = false;
+    if (h->allow_resident) {
+        const int rc = kc_run_gon_resident_batch(h, key, R, H, jobs, span, s, &done);
+        if (rc) return rc;
+    }
+    if (done) return h->run_graph(key + ":finish", s, finish);
+    return kc_run_gon_stream(h, key, R, H, jobs, span, s, finish);
+}
+
 int kc_run_gon_resident_batch(kc_handle* h, const std::string& key, const KcGonRun& R,
                               const KcGonHost& H, const std::vector<KcGonJob>& jobs,
                               const char* span, hipStream_t s, bool* done)

@@ -3,9 +3,11 @@
 //
 // For every dimension d present:
 //   stage 1  every Gonzalez problem and every partition of every MRG problem
-//            is one segment of a single batched run (segments in descending
+//            is one segment of a single batched run: register-resident,
+//            several segments per cooperative launch, when every segment
+//            fits a co-resident grid, else streamed (segments in descending
 //            order of k, so step t launches only the tiles of segments that
-//            still have centers to choose); one HIP graph per plan;
+//            still have centers to choose; one HIP graph per plan);
 //   stage 2  the MRG unions (built on the device) are the segments of a
 //            second batched run;
 //   stage 3  each MRG problem's covering radius by the MFMA assignment.
@@ -212,7 +214,7 @@ static int run_group(kc_handle* h, const kc_problem* probs, const std::vector<in
         snprintf(b, sizeof b, ":%p:%lld", (const void*)probs[i].pts.f32, (long long)probs[i].k);
         key += b;
     }
-    rc = kc_run_gon_stream(h, key, R, H, sj, "batch_gon", s, [&](hipStream_t sst) {
+    rc = kc_run_gon(h, key, R, H, sj, "batch_gon", s, [&](hipStream_t sst) {
         kc_gon_finish(R, cent, nch, nullptr, rad, rb, nullptr, sst);
         if (!outs.empty())
             hipLaunchKernelGGL(k_batch_out, dim3((unsigned)outs.size()), dim3(256), 0, sst, outs_d,
@@ -296,7 +298,7 @@ static int run_group(kc_handle* h, const kc_problem* probs, const std::vector<in
         }
     });
     if (rc) return rc;
-    rc = kc_run_gon_stream(h, key + ":r2", R2, H2, sj2, "batch_gon", s, [&](hipStream_t sst) {
+    rc = kc_run_gon(h, key + ":r2", R2, H2, sj2, "batch_gon", s, [&](hipStream_t sst) {
         kc_gon_finish(R2, cent2, nch2, nullptr, nullptr, nullptr, uni, sst);
         hipLaunchKernelGGL(k_batch_out, dim3((unsigned)nu), dim3(256), 0, sst, outs2_d, nu, cent2,
                            nch2, (const double*)nullptr);

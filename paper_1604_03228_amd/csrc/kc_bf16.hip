@@ -269,6 +269,7 @@ __global__ __launch_bounds__(KC_BLOCK) void k_gon_step_bf16(
 // cache it), canonical FP32, then the packed key goes to the step's argmax
 // slots.  nresc[t] counts the rescored points.
 #define KC_RESC_SEGS 1024   // segments whose L_t fits the LDS table
+template <int D>
 __global__ __launch_bounds__(256) void k_bf16_rescore(
     const u64* __restrict__ list, const float* __restrict__ list_hi,
     const uint32_t* __restrict__ listcnt, uint32_t region, const uint32_t* __restrict__ lpart,
@@ -356,11 +357,36 @@ __global__ __launch_bounds__(256) void k_bf16_rescore(
             const uint32_t from = exupto[col];
             float best = exm[col];
             __builtin_amdgcn_wave_barrier();
-            for (uint32_t c = from + lane; c <= (uint32_t)t; c += 64) {
-                const float* cj = ccoord + (uint64_t)(sg.keyoff + c) * d;
-                float acc = 0.f;
-                for (int u = 0; u < d; ++u) acc = kc_d32_step(acc, xw[u], cj[u]);
-                best = fminf(best, acc);
+            if (D > 0) {
+                // two centers per lane and pass, every coordinate load of
+                // both issued before the arithmetic: one memory latency per
+                // 128 centers
+                for (uint32_t c = from + lane; c <= (uint32_t)t; c += 128) {
+                    const bool two = c + 64 <= (uint32_t)t;
+                    const float* c0 = ccoord + (uint64_t)(sg.keyoff + c) * D;
+                    const float* c1 = two ? c0 + 64 * D : c0;
+                    float v0[D > 0 ? D : 1], v1[D > 0 ? D : 1];
+#pragma unroll
+                    for (int u = 0; u < D; ++u) {
+                        v0[u] = c0[u];
+                        v1[u] = c1[u];
+                    }
+                    float a0 = 0.f, a1 = 0.f;
+#pragma unroll
+                    for (int u = 0; u < D; ++u) {
+                        a0 = kc_d32_step(a0, xw[u], v0[u]);
+                        a1 = kc_d32_step(a1, xw[u], v1[u]);
+                    }
+                    best = fminf(best, a0);
+                    if (two) best = fminf(best, a1);
+                }
+            } else {
+                for (uint32_t c = from + lane; c <= (uint32_t)t; c += 64) {
+                    const float* cj = ccoord + (uint64_t)(sg.keyoff + c) * d;
+                    float acc = 0.f;
+                    for (int u = 0; u < d; ++u) acc = kc_d32_step(acc, xw[u], cj[u]);
+                    best = fminf(best, acc);
+                }
             }
             __builtin_amdgcn_wave_barrier();
             for (int off = 32; off >= 1; off >>= 1) best = fminf(best, __shfl_xor(best, off, 64));
@@ -429,9 +455,25 @@ void kc_enqueue_bf16_steps(const KcGonRun& R, const KcBf16Run& B, hipStream_t s)
                                R.segs, R.blk_seg, R.blk_start, t, B.g, B.list, B.list_hi,
                                B.listcnt, B.region);
         }
-        hipLaunchKernelGGL(k_bf16_rescore, dim3(B.rescore_blocks), dim3(256), 0, s, B.list,
-                           B.list_hi, B.listcnt, B.region, B.lpart, R.xs, R.stride, R.d,
-                           R.ccoord, R.segs, R.nseg, B.exm, B.exupto, R.part, B.nresc, t);
+        switch (R.d) {
+#define KC_RS_CASE(DD)                                                                        \
+    case DD:                                                                                  \
+        hipLaunchKernelGGL(k_bf16_rescore<DD>, dim3(B.rescore_blocks), dim3(256), 0, s, B.list, \
+                           B.list_hi, B.listcnt, B.region, B.lpart, R.xs, R.stride, R.d,      \
+                           R.ccoord, R.segs, R.nseg, B.exm, B.exupto, R.part, B.nresc, t);    \
+        break;
+            KC_RS_CASE(2)
+            KC_RS_CASE(8)
+            KC_RS_CASE(10)
+            KC_RS_CASE(16)
+            KC_RS_CASE(32)
+            KC_RS_CASE(41)
+#undef KC_RS_CASE
+        default:
+            hipLaunchKernelGGL(k_bf16_rescore<0>, dim3(B.rescore_blocks), dim3(256), 0, s, B.list,
+                               B.list_hi, B.listcnt, B.region, B.lpart, R.xs, R.stride, R.d,
+                               R.ccoord, R.segs, R.nseg, B.exm, B.exupto, R.part, B.nresc, t);
+        }
     }
     kc_part_collect(R.part, R.keys, R.keysum, s);
 }

@@ -100,6 +100,9 @@ int kc_run_gon_stream(kc_handle* h, const std::string& key, const KcGonRun& R,
 // enqueued; leaves it false, having enqueued nothing that the streaming
 // engine's prep does not redo, when some segment fits no resident grid or
 // a launch is refused.
+int kc_run_gon(kc_handle* h, const std::string& key, const KcGonRun& R, const KcGonHost& H,
+               const std::vector<KcGonJob>& jobs, const char* span, hipStream_t s,
+               const std::function<void(hipStream_t)>& finish);
 int kc_run_gon_resident_batch(kc_handle* h, const std::string& key, const KcGonRun& R,
                               const KcGonHost& H, const std::vector<KcGonJob>& jobs,
                               const char* span, hipStream_t s, bool* done);
