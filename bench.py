@@ -61,11 +61,18 @@ def copy_probe():
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(5):
         dst.copy_(src)
+    e1.record()
     torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
     print(json.dumps({"copy_probe_bytes_read": nbytes,
-                      "copy_probe_bytes_written": nbytes, "launches": 5}))
+                      "copy_probe_bytes_written": nbytes, "launches": 5,
+                      "ms_per_copy": ms,
+                      "copy_GBps": 2 * nbytes / (ms * 1e-3) / 1e9}))
 
 
 def kernel_source_hash(files):
