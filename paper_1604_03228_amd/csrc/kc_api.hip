@@ -271,23 +271,25 @@ int kc_plan_gon(kc_handle* h, const std::string& pre, int d, uint32_t tile,
     return KC_OK;
 }
 
-// Enqueue the SoA staging of every job with source rows: one launch when all
-// of them read the same array, else one per job.
+// Enqueue the staging of every job with source rows (FP32 SoA copy, plus the
+// BF16 copy and rounding radii when xb is given): one launch when all of them
+// read the same arrays, else one per job.
 void kc_enqueue_stage(const KcGonRun& R, const KcGonHost& H, const std::vector<KcGonJob>& jobs,
-                      hipStream_t s)
+                      hipStream_t s, uint16_t* xb, float* ex)
 {
     bool shared = jobs.size() > 1 && jobs[0].X != nullptr;
     for (const KcGonJob& j : jobs)
-        if (j.X != jobs[0].X || j.ld != jobs[0].ld) shared = false;
+        if (j.X != jobs[0].X || j.Xb != jobs[0].Xb || j.ld != jobs[0].ld) shared = false;
     if (shared) {
-        kc_stage_soa_batch(jobs[0].X, jobs[0].ld, R.d, R.segs, R.blk_seg, R.blk_start, R.nblk,
-                           R.tile, (float*)R.xs, R.stride, s);
+        kc_stage_rows_batch(jobs[0].X, xb ? jobs[0].Xb : nullptr, jobs[0].ld, R.d, R.segs,
+                            R.blk_seg, R.blk_start, R.nblk, R.tile, (float*)R.xs, xb, ex,
+                            R.stride, s);
         return;
     }
     for (size_t q = 0; q < jobs.size(); ++q)
         if (jobs[q].X)
-            kc_stage_soa(jobs[q].X, jobs[q].ld, R.d, jobs[q].row0, jobs[q].len, (float*)R.xs,
-                         R.stride, H.segs[q].base, s);
+            kc_stage_rows(jobs[q].X, xb ? jobs[q].Xb : nullptr, jobs[q].ld, R.d, jobs[q].row0,
+                          jobs[q].len, (float*)R.xs, xb, ex, R.stride, H.segs[q].base, s);
 }
 
 // Enqueue staging + init of a planned run (streaming engine).

@@ -48,62 +48,6 @@ __device__ __forceinline__ float kc_bf_dec(uint32_t w, int hi)
     return __uint_as_float(hi ? (w & 0xFFFF0000u) : (w << 16));
 }
 
-// SoA BF16 staging of rows [row0, row0+len) plus the per-point rounding
-// radius e_i (FP64, rounded up), indexed like the SoA columns.
-__global__ void k_stage_bf16(const float* __restrict__ X, const uint16_t* __restrict__ Xb,
-                             int64_t ld, int d, uint64_t row0, uint32_t len,
-                             uint16_t* __restrict__ xb, float* __restrict__ ex, uint64_t stride,
-                             uint64_t base, uint32_t padded)
-{
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= padded) return;
-    const uint64_t r = row0 + (i < len ? i : 0);
-    double ee = 0.0;
-    for (int j = 0; j < d; ++j) {
-        const uint16_t h = Xb[r * ld + j];
-        xb[(uint64_t)j * stride + base + i] = h;
-        const double e = (double)__uint_as_float((uint32_t)h << 16) - (double)X[r * ld + j];
-        ee += e * e;
-    }
-    ex[base + i] = (float)(sqrt(ee) * (1.0 + 1e-12)) * (1.f + 1e-6f);
-}
-
-void kc_stage_bf16(const float* X, const uint16_t* Xb, int64_t ld, int d, uint64_t row0,
-                   uint32_t len, uint16_t* xb, float* ex, uint64_t stride, uint64_t base,
-                   hipStream_t s)
-{
-    const uint32_t padded = kc_pad64(len);
-    if (padded == 0) return;
-    hipLaunchKernelGGL(k_stage_bf16, dim3((padded + 255) / 256), dim3(256), 0, s, X, Xb, ld, d,
-                       row0, len, xb, ex, stride, base, padded);
-}
-
-// k_stage_bf16 for every segment of a planned run in one launch (all
-// segments read the same arrays); tiles as in k_stage_soa_batch.
-__global__ void k_stage_bf16_batch(const float* __restrict__ X, const uint16_t* __restrict__ Xb,
-                                   int64_t ld, int d, const KcSeg* __restrict__ segs,
-                                   const uint32_t* __restrict__ blk_seg,
-                                   const uint32_t* __restrict__ blk_start, uint32_t tile,
-                                   uint16_t* __restrict__ xb, float* __restrict__ ex,
-                                   uint64_t stride)
-{
-    const KcSeg sg = segs[blk_seg[blockIdx.x]];
-    const uint32_t st = blk_start[blockIdx.x];
-    const uint32_t padded = (sg.len + 63u) & ~63u;
-    const uint32_t end = st + tile < padded ? st + tile : padded;
-    for (uint32_t i = st + threadIdx.x; i < end; i += blockDim.x) {
-        const uint64_t r = sg.src + (i < sg.len ? i : 0);
-        double ee = 0.0;
-        for (int j = 0; j < d; ++j) {
-            const uint16_t h = Xb[r * ld + j];
-            xb[(uint64_t)j * stride + sg.base + i] = h;
-            const double e = (double)__uint_as_float((uint32_t)h << 16) - (double)X[r * ld + j];
-            ee += e * e;
-        }
-        ex[sg.base + i] = (float)(sqrt(ee) * (1.0 + 1e-12)) * (1.f + 1e-6f);
-    }
-}
-
 // largest-lower-bound partial maxima: lpart[(key * KC_PARTS + slot) * 32]
 // (u32 bits of a non-negative float, one 128-byte line per slot)
 __device__ __forceinline__ uint32_t* kc_lpart(uint32_t* lpart, uint64_t key, uint32_t slot)
@@ -481,19 +425,7 @@ void kc_enqueue_bf16_steps(const KcGonRun& R, const KcBf16Run& B, hipStream_t s)
 void kc_enqueue_bf16_prep(const KcGonRun& R, const KcBf16Run& B, const KcGonHost& H,
                           const std::vector<KcGonJob>& jobs, hipStream_t s)
 {
-    kc_enqueue_stage(R, H, jobs, s);
-    bool shared = jobs.size() > 1;
-    for (const KcGonJob& j : jobs)
-        if (j.X != jobs[0].X || j.Xb != jobs[0].Xb || j.ld != jobs[0].ld) shared = false;
-    if (shared && R.nblk > 0) {
-        hipLaunchKernelGGL(k_stage_bf16_batch, dim3(R.nblk), dim3(256), 0, s, jobs[0].X,
-                           jobs[0].Xb, jobs[0].ld, R.d, R.segs, R.blk_seg, R.blk_start, R.tile,
-                           B.xb, B.ex, R.stride);
-    } else {
-        for (size_t q = 0; q < jobs.size(); ++q)
-            kc_stage_bf16(jobs[q].X, jobs[q].Xb, jobs[q].ld, R.d, jobs[q].row0, jobs[q].len,
-                          B.xb, B.ex, R.stride, H.segs[q].base, s);
-    }
+    kc_enqueue_stage(R, H, jobs, s, B.xb, B.ex);
     kc_fill_u32((uint32_t*)R.mind, 0x7F800000u, R.stride, s);   // +inf
     kc_fill_u32((uint32_t*)B.exm, 0x7F800000u, R.stride, s);
     kc_fill_u32(B.exupto, 0u, R.stride, s);

@@ -60,74 +60,111 @@ void kc_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s)
 
 // ---------------------------------------------------------------------------
 // staging: rows [row0, row0+len) of a caller array [*][ld] -> SoA columns
-// [base, base+len); padding columns up to the next multiple of 64 get a copy
-// of the segment's first point (harmless, they are masked from the argmax).
+// [base, base+len) of the FP32 copy and, when asked, of the BF16 copy with
+// each point's rounding radius e = |bf16(x) - x| (FP64, rounded up).
+// Padding columns up to the next multiple of 64 get a copy of the segment's
+// first point (harmless, they are masked from every argmax).
+//
+// A block moves 64 points at a time through LDS, at most 64 coordinates per
+// pass: the reads walk the rows in memory order and each wave's writes are
+// 64 consecutive columns of one coordinate row, so both sides coalesce.
 
-__global__ void k_stage_soa(const float* __restrict__ X, int64_t ld, int d,
-                            uint64_t row0, uint32_t len, float* __restrict__ xs,
-                            uint64_t stride, uint64_t base, uint32_t padded)
+#define KC_STG_W 64   // coordinates per pass
+
+// Stage the 64 columns [i0, i0+64) of one segment; all threads of the block
+// call it.  sx, sb: LDS of 64 * (KC_STG_W + 1) entries.
+__device__ void kc_stage_tile64(const float* __restrict__ X, const uint16_t* __restrict__ Xb,
+                                int64_t ld, int d, uint64_t row0, uint32_t len, uint32_t i0,
+                                float* __restrict__ xs, uint16_t* __restrict__ xb,
+                                float* __restrict__ ex, uint64_t stride, uint64_t base,
+                                float* sx, uint16_t* sb)
 {
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= padded) return;
-    uint64_t r = row0 + (i < len ? i : 0);
-    const float* src = X + r * (uint64_t)ld;
-    for (int j = 0; j < d; ++j) xs[(uint64_t)j * stride + base + i] = src[j];
+    const bool bf = xb != nullptr && Xb != nullptr;
+    double ee = 0.0;   // thread p < 64: point i0 + p, coordinates in ascending order
+    for (int j0 = 0; j0 < d; j0 += KC_STG_W) {
+        const uint32_t w = (uint32_t)min(KC_STG_W, d - j0);
+        const uint32_t pitch = w | 1u;   // odd: the transposed reads avoid bank conflicts
+        for (uint32_t q = threadIdx.x; q < 64u * w; q += blockDim.x) {
+            const uint32_t p = q / w, j = q - p * w;
+            const uint32_t i = i0 + p;
+            const uint64_t at = (row0 + (i < len ? i : 0)) * (uint64_t)ld + j0 + j;
+            sx[p * pitch + j] = X[at];
+            if (bf) sb[p * pitch + j] = Xb[at];
+        }
+        __syncthreads();
+        for (uint32_t q = threadIdx.x; q < 64u * w; q += blockDim.x) {
+            const uint32_t j = q >> 6, p = q & 63u;
+            const uint64_t at = (uint64_t)(j0 + j) * stride + base + i0 + p;
+            if (xs) xs[at] = sx[p * pitch + j];
+            if (bf) xb[at] = sb[p * pitch + j];
+        }
+        if (bf && threadIdx.x < 64) {
+            for (uint32_t j = 0; j < w; ++j) {
+                const double e = (double)__uint_as_float((uint32_t)sb[threadIdx.x * pitch + j]
+                                                         << 16) -
+                                 (double)sx[threadIdx.x * pitch + j];
+                ee += e * e;
+            }
+        }
+        __syncthreads();
+    }
+    if (bf && threadIdx.x < 64)
+        ex[base + i0 + threadIdx.x] = (float)(sqrt(ee) * (1.0 + 1e-12)) * (1.f + 1e-6f);
+}
+
+// One segment: block b stages columns [64b, 64b + 64).
+__global__ __launch_bounds__(256) void k_stage_rows(
+    const float* __restrict__ X, const uint16_t* __restrict__ Xb, int64_t ld, int d,
+    uint64_t row0, uint32_t len, float* __restrict__ xs, uint16_t* __restrict__ xb,
+    float* __restrict__ ex, uint64_t stride, uint64_t base)
+{
+    __shared__ float sx[64 * (KC_STG_W + 1)];
+    __shared__ uint16_t sb[64 * (KC_STG_W + 1)];
+    kc_stage_tile64(X, Xb, ld, d, row0, len, blockIdx.x * 64u, xs, xb, ex, stride, base, sx, sb);
+}
+
+// Every segment of a planned run (all reading the same arrays): block b
+// stages the `tile` columns from blk_start[b] of segment blk_seg[b].
+__global__ __launch_bounds__(256) void k_stage_rows_batch(
+    const float* __restrict__ X, const uint16_t* __restrict__ Xb, int64_t ld, int d,
+    const KcSeg* __restrict__ segs, const uint32_t* __restrict__ blk_seg,
+    const uint32_t* __restrict__ blk_start, uint32_t tile, float* __restrict__ xs,
+    uint16_t* __restrict__ xb, float* __restrict__ ex, uint64_t stride)
+{
+    __shared__ float sx[64 * (KC_STG_W + 1)];
+    __shared__ uint16_t sb[64 * (KC_STG_W + 1)];
+    const KcSeg sg = segs[blk_seg[blockIdx.x]];
+    const uint32_t st = blk_start[blockIdx.x];
+    const uint32_t padded = (sg.len + 63u) & ~63u;
+    const uint32_t end = st + tile < padded ? st + tile : padded;
+    for (uint32_t i0 = st; i0 < end; i0 += 64)
+        kc_stage_tile64(X, Xb, ld, d, sg.src, sg.len, i0, xs, xb, ex, stride, sg.base, sx, sb);
+}
+
+void kc_stage_rows(const float* X, const uint16_t* Xb, int64_t ld, int d, uint64_t row0,
+                   uint32_t len, float* xs, uint16_t* xb, float* ex, uint64_t stride,
+                   uint64_t base, hipStream_t s)
+{
+    const uint32_t padded = kc_pad64(len);
+    if (padded == 0) return;
+    hipLaunchKernelGGL(k_stage_rows, dim3(padded / 64), dim3(256), 0, s, X, Xb, ld, d, row0, len,
+                       xs, xb, ex, stride, base);
 }
 
 void kc_stage_soa(const float* X, int64_t ld, int d, uint64_t row0, uint32_t len,
                   float* xs, uint64_t stride, uint64_t base, hipStream_t s)
 {
-    uint32_t padded = kc_pad64(len);
-    if (padded == 0) return;
-    hipLaunchKernelGGL(k_stage_soa, dim3((padded + 255) / 256), dim3(256), 0, s, X,
-                       ld, d, row0, len, xs, stride, base, padded);
+    kc_stage_rows(X, nullptr, ld, d, row0, len, xs, nullptr, nullptr, stride, base, s);
 }
 
-// Staging of every segment of a planned run in one launch (all segments read
-// the same row-major array): block b covers the tile of `tile` points that
-// starts at blk_start[b] in segment blk_seg[b], padding columns up to the
-// next multiple of 64 repeat the segment's first row.  vec4: d and ld are
-// multiples of 4 and X is 16-byte aligned.
-__global__ void k_stage_soa_batch(const float* __restrict__ X, int64_t ld, int d,
-                                  const KcSeg* __restrict__ segs,
-                                  const uint32_t* __restrict__ blk_seg,
-                                  const uint32_t* __restrict__ blk_start, uint32_t tile,
-                                  float* __restrict__ xs, uint64_t stride, int vec4)
-{
-    const KcSeg sg = segs[blk_seg[blockIdx.x]];
-    const uint32_t st = blk_start[blockIdx.x];
-    const uint32_t padded = (sg.len + 63u) & ~63u;
-    const uint32_t end = st + tile < padded ? st + tile : padded;
-    if (vec4) {
-        // one 16-byte group of a row per thread: consecutive threads read
-        // consecutive groups, so the row-major reads are fully coalesced
-        const uint32_t g4 = (uint32_t)d >> 2, items = (end - st) * g4;
-        for (uint32_t q = threadIdx.x; q < items; q += blockDim.x) {
-            const uint32_t i = st + q / g4, g = q - (q / g4) * g4;
-            const float4 v = *(const float4*)(X + (sg.src + (i < sg.len ? i : 0)) * (uint64_t)ld +
-                                              4 * g);
-            float* dst = xs + (uint64_t)(4 * g) * stride + sg.base + i;
-            dst[0] = v.x;
-            dst[stride] = v.y;
-            dst[2 * stride] = v.z;
-            dst[3 * stride] = v.w;
-        }
-        return;
-    }
-    for (uint32_t i = st + threadIdx.x; i < end; i += blockDim.x) {
-        const float* src = X + (sg.src + (i < sg.len ? i : 0)) * (uint64_t)ld;
-        for (int j = 0; j < d; ++j) xs[(uint64_t)j * stride + sg.base + i] = src[j];
-    }
-}
-
-void kc_stage_soa_batch(const float* X, int64_t ld, int d, const KcSeg* segs,
-                        const uint32_t* blk_seg, const uint32_t* blk_start, uint32_t nblk,
-                        uint32_t tile, float* xs, uint64_t stride, hipStream_t s)
+void kc_stage_rows_batch(const float* X, const uint16_t* Xb, int64_t ld, int d,
+                         const KcSeg* segs, const uint32_t* blk_seg, const uint32_t* blk_start,
+                         uint32_t nblk, uint32_t tile, float* xs, uint16_t* xb, float* ex,
+                         uint64_t stride, hipStream_t s)
 {
     if (nblk == 0) return;
-    const int vec4 = d % 4 == 0 && ld % 4 == 0 && ((uintptr_t)X & 15) == 0;
-    hipLaunchKernelGGL(k_stage_soa_batch, dim3(nblk), dim3(256), 0, s, X, ld, d, segs, blk_seg,
-                       blk_start, tile, xs, stride, vec4);
+    hipLaunchKernelGGL(k_stage_rows_batch, dim3(nblk), dim3(256), 0, s, X, Xb, ld, d, segs,
+                       blk_seg, blk_start, tile, xs, xb, ex, stride);
 }
 
 // ---------------------------------------------------------------------------

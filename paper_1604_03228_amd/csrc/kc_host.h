@@ -87,7 +87,7 @@ int kc_check_points(kc_handle* h, const kc_points* p, bool need_bf16_if_asked);
 int kc_plan_gon(kc_handle* h, const std::string& pre, int d, uint32_t tile,
                 const std::vector<KcGonJob>& jobs, KcGonRun& R, KcGonHost& H);
 void kc_enqueue_stage(const KcGonRun& R, const KcGonHost& H, const std::vector<KcGonJob>& jobs,
-                      hipStream_t s);
+                      hipStream_t s, uint16_t* xb = nullptr, float* ex = nullptr);
 void kc_enqueue_gon_prep(const KcGonRun& R, const KcGonHost& H,
                          const std::vector<KcGonJob>& jobs, hipStream_t s);
 void kc_enqueue_gon_steps(const KcGonRun& R, hipStream_t s);

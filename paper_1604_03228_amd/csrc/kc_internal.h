@@ -57,9 +57,16 @@ void kc_fill_u64(u64* p, u64 v, uint64_t n, hipStream_t s);
 void kc_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 void kc_stage_soa(const float* X, int64_t ld, int d, uint64_t row0, uint32_t len,
                   float* xs, uint64_t stride, uint64_t base, hipStream_t s);
-void kc_stage_soa_batch(const float* X, int64_t ld, int d, const KcSeg* segs,
-                        const uint32_t* blk_seg, const uint32_t* blk_start, uint32_t nblk,
-                        uint32_t tile, float* xs, uint64_t stride, hipStream_t s);
+// Staging through LDS (kc_gon.hip): FP32 SoA copy (xs) and, with Xb, the
+// BF16 SoA copy (xb) and per-point rounding radius (ex); either output may
+// be NULL.  The batch form stages every segment of a plan from one array.
+void kc_stage_rows(const float* X, const uint16_t* Xb, int64_t ld, int d, uint64_t row0,
+                   uint32_t len, float* xs, uint16_t* xb, float* ex, uint64_t stride,
+                   uint64_t base, hipStream_t s);
+void kc_stage_rows_batch(const float* X, const uint16_t* Xb, int64_t ld, int d,
+                         const KcSeg* segs, const uint32_t* blk_seg, const uint32_t* blk_start,
+                         uint32_t nblk, uint32_t tile, float* xs, uint16_t* xb, float* ex,
+                         uint64_t stride, hipStream_t s);
 void kc_part_collect(const u64* part, u64* keys, uint64_t nkeys, hipStream_t s);
 uint64_t kc_resident_slot_words(int k, uint32_t G);
 void kc_gon_step(const float* xs, uint64_t stride, int d, float* mind, u64* part,

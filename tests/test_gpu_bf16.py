@@ -37,7 +37,8 @@ def run(kc, X, k, first, bf16, h):
     return c.cpu().numpy(), tr.cpu().numpy(), int(nch.item())
 
 
-@pytest.mark.parametrize("d", [2, 5, 16, 41])
+# d = 70 takes the generic-d kernels and stages in two passes of columns
+@pytest.mark.parametrize("d", [2, 5, 16, 41, 70])
 def test_bf16_matches_fp32(kc, orc, d):
     rng = np.random.default_rng(d)
     n = 50_021
