@@ -69,10 +69,20 @@ def copy_probe():
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / 5
+    # read-only reference: torch's sum over the same 1 GiB
+    acc = src.sum()
+    e0.record()
+    for _ in range(5):
+        acc = src.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_r = e0.elapsed_time(e1) / 5
     print(json.dumps({"copy_probe_bytes_read": nbytes,
                       "copy_probe_bytes_written": nbytes, "launches": 5,
                       "ms_per_copy": ms,
-                      "copy_GBps": 2 * nbytes / (ms * 1e-3) / 1e9}))
+                      "copy_GBps": 2 * nbytes / (ms * 1e-3) / 1e9,
+                      "ms_per_sum": ms_r,
+                      "sum_read_GBps": nbytes / (ms_r * 1e-3) / 1e9}))
 
 
 def kernel_source_hash(files):

@@ -86,11 +86,6 @@ __global__ __launch_bounds__(KC_BLOCK) void k_gon_step_bf16(
     const uint64_t col = sg.base + loc;
     const bool live = loc < sg.len;
 
-    uint4 v[D > 0 ? D : 1];
-    if (D > 0 && live) {
-#pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = *(const uint4*)(xb + (uint64_t)j * stride + col);
-    }
     float4 m0 = make_float4(0.f, 0.f, 0.f, 0.f), m1 = m0, e0 = m0, e1 = m0;
     if (live) {
         m0 = *(const float4*)(mind + col);
@@ -98,7 +93,6 @@ __global__ __launch_bounds__(KC_BLOCK) void k_gon_step_bf16(
         e0 = *(const float4*)(ex + col);
         e1 = *(const float4*)(ex + col + 4);
     }
-
     uint32_t c;
     if (t == 0) {
         c = sg.first;
@@ -112,35 +106,34 @@ __global__ __launch_bounds__(KC_BLOCK) void k_gon_step_bf16(
         if ((pv >> 32) == 0) return;   // radius reached 0: segment finished
         c = __builtin_amdgcn_readfirstlane(kc_key_idx(pv));
     }
-    const float* xc = xs + sg.base + c;   // exact FP32 center, uniform
+    const float* xc = xs + sg.base + c;
     if (blk_start[b] == 0) {
-        // the segment's first tile records the center's coordinates
         for (int j = threadIdx.x; j < d; j += KC_BLOCK)
             ccoord[(uint64_t)(sg.keyoff + t) * d + j] = xc[(uint64_t)j * stride];
     }
-
     float s[KC_BF_PTS];
 #pragma unroll
     for (int q = 0; q < KC_BF_PTS; ++q) s[q] = 0.f;
     if (live) {
-        if (D > 0) {
+        constexpr int CH = 2;   // coordinate rows per pass: few VGPRs, many waves
+#pragma unroll 1
+        for (int j0 = 0; j0 < d; j0 += CH) {
+            uint4 w4[CH];
+            float cc[CH];
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                const float cj = xc[(uint64_t)j * stride];
-                const uint32_t w[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
+            for (int u = 0; u < CH; ++u)
+                if (j0 + u < d) {
+                    w4[u] = *(const uint4*)(xb + (uint64_t)(j0 + u) * stride + col);
+                    cc[u] = xc[(uint64_t)(j0 + u) * stride];
+                }
 #pragma unroll
-                for (int q = 0; q < KC_BF_PTS; ++q)
-                    s[q] = kc_d32_step(s[q], kc_bf_dec(w[q >> 1], q & 1), cj);
-            }
-        } else {
-            for (int j = 0; j < d; ++j) {
-                const uint4 u = *(const uint4*)(xb + (uint64_t)j * stride + col);
-                const float cj = xc[(uint64_t)j * stride];
-                const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+            for (int u = 0; u < CH; ++u)
+                if (j0 + u < d) {
+                    const uint32_t w[4] = {w4[u].x, w4[u].y, w4[u].z, w4[u].w};
 #pragma unroll
-                for (int q = 0; q < KC_BF_PTS; ++q)
-                    s[q] = kc_d32_step(s[q], kc_bf_dec(w[q >> 1], q & 1), cj);
-            }
+                    for (int q = 0; q < KC_BF_PTS; ++q)
+                        s[q] = kc_d32_step(s[q], kc_bf_dec(w[q >> 1], q & 1), cc[u]);
+                }
         }
     }
     float lo = 0.f;

@@ -188,18 +188,12 @@ __global__ __launch_bounds__(KC_BLOCK) void k_gon_step(
     const uint64_t col = sg.base + loc;
     const bool live = loc < sg.len;
 
-    // issue this lane's point and min-distance loads before resolving the
-    // center, so their latency overlaps the key reduction
-    float4 v[D > 0 ? D : 1];
+    // The min-distances load first; the center is resolved next (every wave
+    // on its own from the previous step's partial keys, no barrier); the
+    // coordinate rows then stream two at a time, which keeps few VGPRs per
+    // lane and many waves per SIMD in flight.
     float4 m = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (D > 0 && live) {
-#pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = *(const float4*)(xs + (uint64_t)j * stride + col);
-    }
     if (live) m = *(const float4*)(mind + col);
-
-    // newest center: max over the previous step's partial keys, reduced by
-    // every wave on its own (uniform across the block, no barrier needed)
     uint32_t c;
     if (t == 0) {
         c = sg.first;
@@ -213,29 +207,28 @@ __global__ __launch_bounds__(KC_BLOCK) void k_gon_step(
         if ((pv >> 32) == 0) return;   // radius reached 0: segment finished
         c = __builtin_amdgcn_readfirstlane(kc_key_idx(pv));
     }
-    const float* xc = xs + sg.base + c;   // uniform: scalar loads
-
+    const float* xc = xs + sg.base + c;
     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
     if (live) {
-        if (D > 0) {
+        constexpr int CH = 2;   // coordinate rows per pass
+#pragma unroll 1
+        for (int j0 = 0; j0 < d; j0 += CH) {
+            float4 w[CH];
+            float cc[CH];
 #pragma unroll
-            for (int j = 0; j < D; ++j) {
-                const float cj = xc[(uint64_t)j * stride];
-                s0 = kc_d32_step(s0, v[j].x, cj);
-                s1 = kc_d32_step(s1, v[j].y, cj);
-                s2 = kc_d32_step(s2, v[j].z, cj);
-                s3 = kc_d32_step(s3, v[j].w, cj);
-            }
-        } else {
-#pragma unroll 4
-            for (int j = 0; j < d; ++j) {
-                const float4 w = *(const float4*)(xs + (uint64_t)j * stride + col);
-                const float cj = xc[(uint64_t)j * stride];
-                s0 = kc_d32_step(s0, w.x, cj);
-                s1 = kc_d32_step(s1, w.y, cj);
-                s2 = kc_d32_step(s2, w.z, cj);
-                s3 = kc_d32_step(s3, w.w, cj);
-            }
+            for (int u = 0; u < CH; ++u)
+                if (j0 + u < d) {
+                    w[u] = *(const float4*)(xs + (uint64_t)(j0 + u) * stride + col);
+                    cc[u] = xc[(uint64_t)(j0 + u) * stride];
+                }
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+                if (j0 + u < d) {
+                    s0 = kc_d32_step(s0, w[u].x, cc[u]);
+                    s1 = kc_d32_step(s1, w[u].y, cc[u]);
+                    s2 = kc_d32_step(s2, w[u].z, cc[u]);
+                    s3 = kc_d32_step(s3, w[u].w, cc[u]);
+                }
         }
     }
     u64 key = 0;
