@@ -76,7 +76,10 @@ __device__ __forceinline__ float kc_bf16_to_f32(uint16_t h)
 #define KC_MD_PT 2   // point tiles (16 points each) per wave
 
 // BF: BF16 inputs.  KS: MFMA K-steps (K = 4*KS for FP32, 32*KS for BF16).
-template <bool BF, int KS>
+// LAB: keep the best index and the second-best value (labels need them);
+// without it only the smallest value per point is kept (a covering radius or
+// a distance to a set needs nothing else), and out_arg / out_m2 are unused.
+template <bool BF, int KS, bool LAB>
 __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
     const float* __restrict__ X, const uint16_t* __restrict__ Xb, int64_t ld, uint32_t n,
     int d, const float* __restrict__ Cf, const uint16_t* __restrict__ Cb,
@@ -181,27 +184,44 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
                                                                       bb[pt][BF ? ks : 0],
                                                                       acc, 0, 0, 0);
                 }
-                const int ib = (int)(c0 + ct) + grp * 4;
-                kc_best_push(best[pt], __builtin_fmaf(-2.f, acc[0], nc4.x), ib + 0);
-                kc_best_push(best[pt], __builtin_fmaf(-2.f, acc[1], nc4.y), ib + 1);
-                kc_best_push(best[pt], __builtin_fmaf(-2.f, acc[2], nc4.z), ib + 2);
-                kc_best_push(best[pt], __builtin_fmaf(-2.f, acc[3], nc4.w), ib + 3);
+                if (LAB) {
+                    const int ib = (int)(c0 + ct) + grp * 4;
+                    kc_best_push(best[pt], __builtin_fmaf(-2.f, acc[0], nc4.x), ib + 0);
+                    kc_best_push(best[pt], __builtin_fmaf(-2.f, acc[1], nc4.y), ib + 1);
+                    kc_best_push(best[pt], __builtin_fmaf(-2.f, acc[2], nc4.z), ib + 2);
+                    kc_best_push(best[pt], __builtin_fmaf(-2.f, acc[3], nc4.w), ib + 3);
+                } else {
+                    // padding centers have norm +inf, so they never win
+                    float v = fminf(__builtin_fmaf(-2.f, acc[0], nc4.x),
+                                    __builtin_fmaf(-2.f, acc[1], nc4.y));
+                    v = fminf(v, fminf(__builtin_fmaf(-2.f, acc[2], nc4.z),
+                                       __builtin_fmaf(-2.f, acc[3], nc4.w)));
+                    best[pt].m1 = fminf(best[pt].m1, v);
+                }
             }
         }
     }
 
 #pragma unroll
     for (int pt = 0; pt < KC_MD_PT; ++pt) {
-        KcBest b = kc_best_xor(best[pt], 16);
-        b = kc_best_xor(b, 32);
+        KcBest b = best[pt];
+        if (LAB) {
+            b = kc_best_xor(b, 16);
+            b = kc_best_xor(b, 32);
+        } else {
+            b.m1 = fminf(b.m1, __shfl_xor(b.m1, 16, 64));
+            b.m1 = fminf(b.m1, __shfl_xor(b.m1, 32, 64));
+        }
         float nx = nxp[pt];
         nx += __shfl_xor(nx, 16, 64);
         nx += __shfl_xor(nx, 32, 64);
         const uint64_t p = p0 + pt * 16 + col;
         if (grp == 0 && p < n) {
-            out_arg[p] = b.a1;
+            if (LAB) {
+                out_arg[p] = b.a1;
+                out_m2[p] = b.m2;
+            }
             out_m1[p] = b.m1;
-            out_m2[p] = b.m2;
             out_nx[p] = nx;
         }
     }
@@ -458,6 +478,7 @@ void kc_mindist(const float* X, const uint16_t* Xb, int64_t ld, uint32_t n, int 
                 const float* Cf, const uint16_t* Cb, const float* cnorm, uint32_t kpad,
                 int32_t* arg, float* m1, float* m2, float* nx, hipStream_t s)
 {
+    const bool lab = arg != nullptr;
     const bool bf = Xb != nullptr;
     const int ks = kc_mindist_ksteps(d, bf);
     const uint32_t chunk = kc_mindist_chunk(d, bf, kpad);
@@ -469,8 +490,12 @@ void kc_mindist(const float* X, const uint16_t* Xb, int64_t ld, uint32_t n, int 
         switch (ks) {
 #define KC_CASE(K)                                                                       \
     case K:                                                                              \
-        hipLaunchKernelGGL((k_mindist_mfma<false, K>), grid, block, smem, s, X, Xb, ld, n, \
-                           d, Cf, Cb, cnorm, kpad, chunk, arg, m1, m2, nx);              \
+        if (lab)                                                                         \
+            hipLaunchKernelGGL((k_mindist_mfma<false, K, true>), grid, block, smem, s, X, \
+                               Xb, ld, n, d, Cf, Cb, cnorm, kpad, chunk, arg, m1, m2, nx); \
+        else                                                                             \
+            hipLaunchKernelGGL((k_mindist_mfma<false, K, false>), grid, block, smem, s, X, \
+                               Xb, ld, n, d, Cf, Cb, cnorm, kpad, chunk, arg, m1, m2, nx); \
         break;
             KC_MD_CASES_F32(KC_CASE)
 #undef KC_CASE
@@ -479,8 +504,12 @@ void kc_mindist(const float* X, const uint16_t* Xb, int64_t ld, uint32_t n, int 
         switch (ks) {
 #define KC_CASE(K)                                                                       \
     case K:                                                                              \
-        hipLaunchKernelGGL((k_mindist_mfma<true, K>), grid, block, smem, s, X, Xb, ld, n,  \
-                           d, Cf, Cb, cnorm, kpad, chunk, arg, m1, m2, nx);              \
+        if (lab)                                                                         \
+            hipLaunchKernelGGL((k_mindist_mfma<true, K, true>), grid, block, smem, s, X,  \
+                               Xb, ld, n, d, Cf, Cb, cnorm, kpad, chunk, arg, m1, m2, nx); \
+        else                                                                             \
+            hipLaunchKernelGGL((k_mindist_mfma<true, K, false>), grid, block, smem, s, X, \
+                               Xb, ld, n, d, Cf, Cb, cnorm, kpad, chunk, arg, m1, m2, nx); \
         break;
             KC_MD_CASES_BF16(KC_CASE)
 #undef KC_CASE

@@ -436,18 +436,18 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
                 float* Cf = (float*)h->ws("e.cf", 4ull * kpad * dp);
                 float* cn = (float*)h->ws("e.cn", 4ull * kpad);
                 float* cmax = (float*)h->ws("e.cmax", 16);
-                int32_t* arg = (int32_t*)h->ws("e.arg", 4ull * nc);
                 float* m1 = (float*)h->ws("e.m1", 4ull * nc);
                 float* m2 = (float*)h->ws("e.m2", 4ull * nc);
                 float* nx = (float*)h->ws("e.nx", 4ull * nc);
-                if (!XR || !Cf || !cn || !cmax || !arg || !m1 || !m2 || !nx)
+                if (!XR || !Cf || !cn || !cmax || !m1 || !m2 || !nx)
                     return h->fail(KC_ENOMEM, "workspace allocation failed");
                 hipLaunchKernelGGL(k_gather_rows, g1((uint64_t)nc * d), dim3(256), 0, s, X, ld,
                                    d, cand, nc, XR);
                 kc_stage_centers(X, nullptr, ld, d, n, nullptr, S + ns - nds, nds, nullptr,
                                  kpad, dp, Cf, nullptr, cn, cmax, h->status_word, s);
                 hipEvent_t ev = h->span_begin(s);
-                kc_mindist(XR, nullptr, d, nc, d, Cf, nullptr, cn, kpad, arg, m1, m2, nx, s);
+                // d(x, S) needs the smallest value only (no index, no second best)
+                kc_mindist(XR, nullptr, d, nc, d, Cf, nullptr, cn, kpad, nullptr, m1, m2, nx, s);
                 h->span_end("eim_dist", ev, 1, s);
                 hipLaunchKernelGGL(k_eim_bounds, g1(nc), dim3(256), 0, s, nc, d, cand, m1, nx,
                                    cmax, lo, hi);

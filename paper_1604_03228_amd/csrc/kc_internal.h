@@ -121,6 +121,7 @@ struct KcBf16Run {
 // MFMA nearest-center distances (kc_assign.hip)
 int kc_mindist_ksteps(int d, bool bf);
 int kc_mindist_dpad(int d, bool bf);
+// arg == NULL: only m1 (the smallest |c|^2 - 2x.c) and nx are written.
 void kc_mindist(const float* X, const uint16_t* Xb, int64_t ld, uint32_t n, int d,
                 const float* Cf, const uint16_t* Cb, const float* cnorm, uint32_t kpad,
                 int32_t* arg, float* m1, float* m2, float* nx, hipStream_t s);

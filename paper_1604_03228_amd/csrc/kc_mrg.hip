@@ -193,8 +193,9 @@ int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, ui
     if (rc) return rc;
     hipEvent_t ev = h->span_begin(s);
     rc = h->run_graph(key + ":mfma", s, [&](hipStream_t st) {
-        kc_mindist(pts->f32, bf ? pts->bf16 : nullptr, pts->ld, n, d, Cf, Cb, cnorm, kpad, arg, m1,
-                   m2, nx, st);
+        // without labels only the smallest value per point is needed
+        kc_mindist(pts->f32, bf ? pts->bf16 : nullptr, pts->ld, n, d, Cf, Cb, cnorm, kpad,
+                   labels ? arg : nullptr, m1, m2, nx, st);
     });
     h->span_end("assign_mfma", ev, 1, s);
     if (rc) return rc;
