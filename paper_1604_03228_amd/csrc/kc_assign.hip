@@ -73,7 +73,13 @@ __device__ __forceinline__ float kc_bf16_to_f32(uint16_t h)
 }
 
 #define KC_MD_WAVES 4
-#define KC_MD_PT 2   // point tiles (16 points each) per wave
+// Point tiles (16 points each) per wave: four where the B operand is small
+// (more independent MFMA chains per center tile, fewer A reads per point),
+// two where it would crowd the VGPRs.
+__host__ __device__ constexpr int kc_md_pt(bool bf, int ks)
+{
+    return (!bf && ks <= 8) || (bf && ks <= 2) ? 4 : 2;
+}
 
 // BF: BF16 inputs.  KS: MFMA K-steps (K = 4*KS for FP32, 32*KS for BF16).
 // LAB: keep the best index and the second-best value (labels need them);
@@ -88,6 +94,7 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
     float* __restrict__ out_nx)
 {
     constexpr int DP = BF ? KS * 32 : KS * 4;   // padded K
+    constexpr int KC_MD_PT = kc_md_pt(BF, KS);
     extern __shared__ __align__(16) unsigned char kc_smem[];
     float* s_norm = (float*)kc_smem;                          // [chunk]
     void* s_c = (void*)(kc_smem + sizeof(float) * chunk);     // [chunk][DP]
@@ -484,7 +491,7 @@ void kc_mindist(const float* X, const uint16_t* Xb, int64_t ld, uint32_t n, int 
     const uint32_t chunk = kc_mindist_chunk(d, bf, kpad);
     const int dp = kc_mindist_dpad(d, bf);
     const size_t smem = (size_t)chunk * 4 + (size_t)chunk * dp * (bf ? 2 : 4);
-    const uint32_t per_block = KC_MD_WAVES * 16 * KC_MD_PT;
+    const uint32_t per_block = KC_MD_WAVES * 16 * kc_md_pt(bf, ks);
     const dim3 grid((n + per_block - 1) / per_block), block(KC_MD_WAVES * 64);
     if (!bf) {
         switch (ks) {
