@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--engine", choices=["auto", "stream"], default="auto")
     ap.add_argument("--mrg-only", action="store_true",
                     help="only the MRG FP32 vs BF16 comparison")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="time kcenter_batch on the 256-instance mixed batch "
+                         "(GON / MRG / EIM, d in {2, 8, 32}) and exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="copy 1 GiB device-to-device 5 times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -163,6 +166,52 @@ def bench_mrg(kc, torch, steps):
     return out
 
 
+def bench_batch(kc, torch, steps):
+    """kcenter_batch on the 256-instance mixed batch: wall time per call with
+    the points resident in HBM, and the Gonzalez / MRG-round-1 distance
+    updates it performs (EIM instances counted by their final Gonzalez
+    only, as a lower bound)."""
+    from paper_1604_03228_amd import workloads as W
+    insts = W.config5_instances()
+    probs = []
+    upd = 0
+    for inst in insts:
+        X, off = W.config5_points(inst)
+        pr = dict(X=torch.from_numpy(X).cuda(), algo=inst["algo"], k=inst["k"])
+        if off is not None:
+            pr["offsets"] = off
+            upd += int(sum(min(inst["k"], int(b - a)) * int(b - a)
+                           for a, b in zip(off[:-1], off[1:])))
+        elif inst["algo"] == "gon":
+            upd += inst["n"] * inst["k"]
+        if inst["algo"] == "eim":
+            pr.update(eps=inst["eps"], phi=inst["phi"], seed=inst["seed"])
+        probs.append(pr)
+    h = kc.Handle()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        for _ in range(2):
+            kc.batch(probs, handle=h)
+        st.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(steps):
+            kc.batch(probs, handle=h)
+        e1.record(st)
+        st.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    status = h.device_status()
+    h.close()
+    algos = [i["algo"] for i in insts]
+    return {"workload": "batch256_unbalanced_gon_mrg_eim", "ms": ms,
+            "instances": len(insts), "gon": algos.count("gon"),
+            "mrg": algos.count("mrg"), "eim": algos.count("eim"),
+            "points": int(sum(i["n"] for i in insts)),
+            "gon_mrg1_updates": upd,
+            "gon_mrg1_updates_per_s": upd / (ms * 1e-3), "status": status}
+
+
 def bench_gon_bf16(kc, torch, steps):
     """Gonzalez k=500 on the 5,000,000 x 41 mixed-scale workload, FP32 vs
     BF16 stream + exact FP32 rescoring (same centers required)."""
@@ -215,6 +264,9 @@ def main():
     import paper_1604_03228_amd as kc
     from paper_1604_03228_amd import workloads as W
 
+    if a.batch_only:
+        print(json.dumps({"batch": bench_batch(kc, torch, max(2, a.steps))}))
+        return
     if a.mrg_only:
         print(json.dumps({"mrg": bench_mrg(kc, torch, max(2, a.steps)),
                           "gon_bf16": bench_gon_bf16(kc, torch, max(2, a.steps))}))

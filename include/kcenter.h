@@ -98,7 +98,10 @@ int kc_timing_read(kc_handle* h, const char* name, double* ms, int64_t* launches
 /* Work counters of the most recent BF16+rescore Gonzalez run on the handle
  * (synchronises the device): "bf16_listed" is the number of (point, step)
  * pairs listed by the stream as possible candidates, "bf16_rescored" the
- * number rescored exactly in FP32.  KC_EINVAL for an unknown name. */
+ * number rescored exactly in FP32.  "eim_exact": candidates whose keep /
+ * remove decision the most recent kcenter_eim call on the handle made in
+ * exact FP64 (summed over its iterations; a batch counts its last EIM
+ * problem).  KC_EINVAL for an unknown name. */
 int kc_counter_read(kc_handle* h, const char* name, int64_t* value);
 
 /* Synchronises `stream`, then reads and clears the handle's device status

@@ -573,6 +573,9 @@ int kc_counter_read(kc_handle* h, const char* name, int64_t* value)
         every = 32;
     } else if (!strcmp(name, "bf16_rescored")) {
         src = h->last_bf16_nresc;
+    } else if (!strcmp(name, "eim_exact")) {
+        *value = h->eim_exact;
+        return KC_OK;
     } else {
         return h->fail(KC_EINVAL, "unknown counter '%s'", name);
     }

@@ -295,6 +295,68 @@ __global__ void k_eim_exact(const float* __restrict__ X, int64_t ld, int d,
     }
 }
 
+// The same exact pass, tiled: a block takes 64 undecided candidates (their
+// coordinates in LDS) and streams S through LDS in chunks of FP64 rows, so
+// each sample row is read from memory once per 64 candidates instead of once
+// per candidate.  Wave w of the block scores samples w, w+4, ... of a chunk
+// against the 64 candidates (one per lane; the sample row is a broadcast
+// read); the arithmetic is kc_d64_step's, so every value is the one the
+// per-candidate kernel computes.  For d <= KC_EXT_MAXD.
+#define KC_EXT_MAXD 64
+#define KC_EXT_LDS (32 * 1024)   // bytes for the sample chunk
+__global__ __launch_bounds__(256) void k_eim_exact_tiled(
+    const float* __restrict__ X, int64_t ld, int d, const uint32_t* __restrict__ cand,
+    const uint32_t* __restrict__ unsure, const uint32_t* __restrict__ nunsure,
+    const uint32_t* __restrict__ S, uint32_t ns, const double* __restrict__ tau,
+    uint8_t* __restrict__ keep, float* __restrict__ lo, float* __restrict__ hi)
+{
+    __shared__ float sC[64 * (KC_EXT_MAXD + 1)];           // candidates, row pitch d | 1
+    __shared__ double sS[KC_EXT_LDS / sizeof(double)];      // sample chunk, row pitch d
+    __shared__ double sB[4][64];
+    const uint32_t nu = *nunsure;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t pitch = (uint32_t)d | 1u;
+    const uint32_t chunk = (uint32_t)(KC_EXT_LDS / sizeof(double)) / (uint32_t)d;
+    for (uint32_t q0 = blockIdx.x * 64u; q0 < nu; q0 += gridDim.x * 64u) {
+        const uint32_t nq = min(64u, nu - q0);
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < nq * (uint32_t)d; e += blockDim.x) {
+            const uint32_t c = e / (uint32_t)d, j = e - c * (uint32_t)d;
+            sC[c * pitch + j] = X[(uint64_t)cand[unsure[q0 + c]] * ld + j];
+        }
+        double best = __builtin_inf();
+        for (uint32_t i0 = 0; i0 < ns; i0 += chunk) {
+            const uint32_t nsc = min(chunk, ns - i0);
+            __syncthreads();
+            for (uint32_t e = threadIdx.x; e < nsc * (uint32_t)d; e += blockDim.x) {
+                const uint32_t r = e / (uint32_t)d, j = e - r * (uint32_t)d;
+                sS[r * d + j] = (double)X[(uint64_t)S[i0 + r] * ld + j];
+            }
+            __syncthreads();
+            if (lane < nq) {
+                const float* xc = sC + lane * pitch;
+                for (uint32_t r = wave; r < nsc; r += 4) {
+                    const double* sr = sS + r * d;
+                    double a = 0.0;
+                    for (int u = 0; u < d; ++u) a = kc_d64_step(a, (double)xc[u], sr[u]);
+                    best = fmin(best, a);
+                }
+            }
+        }
+        sB[wave][lane] = best;
+        __syncthreads();
+        if (threadIdx.x < nq) {
+            double b = fmin(fmin(sB[0][lane], sB[1][lane]), fmin(sB[2][lane], sB[3][lane]));
+            const uint32_t j = unsure[q0 + lane];
+            const uint32_t x = cand[j];
+            keep[j] = b > *tau;
+            // the exact value is its own interval from now on
+            lo[x] = (float)b * (1.f - 1e-6f);
+            hi[x] = (float)b * (1.f + 1e-6f);
+        }
+    }
+}
+
 __global__ void k_mark(const uint32_t* __restrict__ idx, uint32_t n, uint8_t* __restrict__ f)
 {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -389,6 +451,7 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
         !tau || !cnt || !unsure || !C.blk)
         return h->fail(KC_ENOMEM, "workspace allocation failed");
 
+    h->eim_exact = 0;
     hipLaunchKernelGGL(k_iota, g1(n), dim3(256), 0, s, R, n);
     kc_fill_u32((uint32_t*)lo, 0x7F800000u, n, s);
     kc_fill_u32((uint32_t*)hi, 0x7F800000u, n, s);
@@ -456,14 +519,21 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
             kc_fill_u32(cnt + 4, 0u, 1, s);
             hipLaunchKernelGGL(k_eim_decide, g1(nc), dim3(256), 0, s, nc, cand, lo, hi, tau,
                                keep, unsure, cnt + 4);
-            hipLaunchKernelGGL(k_eim_exact, dim3(2048), dim3(256), 0, s, X, ld, d, cand, unsure,
-                               cnt + 4, S, ns, tau, keep, lo, hi);
+            if (d <= KC_EXT_MAXD)
+                hipLaunchKernelGGL(k_eim_exact_tiled, dim3(1024), dim3(256), 0, s, X, ld, d,
+                                   cand, unsure, cnt + 4, S, ns, tau, keep, lo, hi);
+            else
+                hipLaunchKernelGGL(k_eim_exact, dim3(2048), dim3(256), 0, s, X, ld, d, cand,
+                                   unsure, cnt + 4, S, ns, tau, keep, lo, hi);
             kc_compact(C, keep, cand, nc, R2, cnt + 3, s);
             std::swap(R, R2);
-            if (hipMemcpyAsync(&new_nr, cnt + 3, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            uint32_t rc2[2];
+            if (hipMemcpyAsync(rc2, cnt + 3, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipMemcpyAsync(&tau_h, tau, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess)
                 return h->fail(KC_EHIP, "readback failed");
+            new_nr = rc2[0];
+            h->eim_exact += rc2[1];
         }
         if (iters) {
             kc_eim_iter& rec = iters[it];

@@ -46,6 +46,8 @@ struct kc_handle {
     const uint32_t* last_bf16_listcnt = nullptr;
     const uint32_t* last_bf16_nresc = nullptr;
     uint32_t last_bf16_kmax = 0;
+    // candidates decided by the exact FP64 pass in the most recent EIM call
+    int64_t eim_exact = 0;
 
     ~kc_handle();
     // Record the opening event of a timed span (no-op unless timing is on).
