@@ -36,7 +36,8 @@ def gpu_eim(kc, X, k, eps, phi, seed, max_iters=64):
         assert h.device_status() == 0
     st.synchronize()
     return dict(centers=c.cpu().numpy(), n_centers=int(nc.item()),
-                radius=float(r.item()), sample=smp.cpu().numpy(), iters=its)
+                radius=float(r.item()), sample=smp.cpu().numpy(), iters=its,
+                exact=h.counter("eim_exact"))
 
 
 def check(orc, X, k, eps, phi, seed, g):
@@ -92,11 +93,16 @@ def test_all_duplicates(kc, orc):
     assert len(g["iters"]) == 1 and g["radius"] == 0.0
 
 
-def test_unbalanced_blobs(kc, orc):
+# The unbalanced blobs leave many candidates whose MFMA interval contains
+# tau, so the exact FP64 pass decides them: tiled for d <= 64, one block per
+# candidate above (d = 70).
+@pytest.mark.parametrize("d", [8, 32, 70])
+def test_unbalanced_blobs(kc, orc, d):
     from paper_1604_03228_amd import workloads as W
-    X = W.points_gauss_mixture(100_000, 8, 25, seed=77, heavy=0.9)
+    X = W.points_gauss_mixture(100_000, d, 25, seed=77, heavy=0.9)
     g = gpu_eim(kc, X, 20, 0.1, 4.0, 5 * 2**32 + 1)
     check(orc, X, 20, 0.1, 4.0, 5 * 2**32 + 1, g)
+    assert g["exact"] > 0
 
 
 def test_max_iters_reports_noconv(kc):
