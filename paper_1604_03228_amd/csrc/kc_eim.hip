@@ -238,6 +238,56 @@ __global__ void k_eim_bounds(uint32_t nc, int d, const uint32_t* __restrict__ ca
     hi[x] = fminf(hi[x], (float)u * (1.f + 1e-6f));
 }
 
+// For small d the canonical FP32 distance (one lane per pair, ascending
+// coordinates, relative error at most g = gamma_{d+2}) certifies far more
+// tightly than MFMA's |x|^2 + |c|^2 - 2x.c, whose error scales with the
+// norms: a block takes 256 candidates (one per lane, coordinates in VGPRs)
+// and streams this iteration's samples through LDS.  The interval of
+// d(x,S)^2 narrows to [m / (1 + g), m / (1 - g)] around the smallest FP32
+// value m, widened for rounding and for squares that underflow.
+#define KC_EIM_DIRECT_MAXD 8
+#define KC_EIM_DIRECT_CHUNK 1024
+template <int D>
+__global__ __launch_bounds__(256) void k_eim_direct(const float* __restrict__ X, int64_t ld,
+                                                    const uint32_t* __restrict__ cand,
+                                                    uint32_t nc, const uint32_t* __restrict__ dS,
+                                                    uint32_t nds, double g,
+                                                    float* __restrict__ lo,
+                                                    float* __restrict__ hi)
+{
+    __shared__ float sS[KC_EIM_DIRECT_CHUNK * D];
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = j < nc;
+    const uint32_t x = live ? cand[j] : 0u;
+    float xc[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) xc[u] = live ? X[(uint64_t)x * ld + u] : 0.f;
+    float m = __builtin_inff();
+    for (uint32_t i0 = 0; i0 < nds; i0 += KC_EIM_DIRECT_CHUNK) {
+        const uint32_t cnt = min((uint32_t)KC_EIM_DIRECT_CHUNK, nds - i0);
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < cnt * D; e += blockDim.x) {
+            const uint32_t r = e / D, u = e - r * D;
+            sS[e] = X[(uint64_t)dS[i0 + r] * ld + u];
+        }
+        __syncthreads();
+        for (uint32_t r = 0; r < cnt; ++r) {
+            float a = 0.f;
+#pragma unroll
+            for (int u = 0; u < D; ++u) a = kc_d32_step(a, xc[u], sS[r * D + u]);
+            m = fminf(m, a);
+        }
+    }
+    if (live) {
+        const double mv = (double)m;
+        double l = mv / (1.0 + g) - 1e-37 * D;
+        if (l < 0.0) l = 0.0;
+        const double uu = mv / (1.0 - g) + 1e-37 * D;
+        lo[x] = fminf(lo[x], (float)l * (1.f - 1e-6f));
+        hi[x] = fminf(hi[x], (float)uu * (1.f + 1e-6f));
+    }
+}
+
 // keep iff d(x,S)^2 > tau; interval decides, else the exact pass does
 __global__ void k_eim_decide(uint32_t nc, const uint32_t* __restrict__ cand,
                              const float* __restrict__ lo, const float* __restrict__ hi,
@@ -492,7 +542,28 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
                 kc_fill_u64((u64*)tau, 0xFFF0000000000000ull, 1, s);   // -inf
             }
             // distance pass of the candidates against this iteration's samples
-            if (nds > 0 && nc > 0) {
+            if (nds > 0 && nc > 0 && d <= KC_EIM_DIRECT_MAXD) {
+                const double u32 = 5.9604644775390625e-8, m = d + 2;
+                const double g = m * u32 / (1.0 - m * u32);
+                hipEvent_t ev = h->span_begin(s);
+                switch (d) {
+#define KC_DIR_CASE(DD)                                                                     \
+    case DD:                                                                                \
+        hipLaunchKernelGGL(k_eim_direct<DD>, g1(nc), dim3(256), 0, s, X, ld, cand, nc,      \
+                           S + ns - nds, nds, g, lo, hi);                                   \
+        break;
+                    KC_DIR_CASE(1)
+                    KC_DIR_CASE(2)
+                    KC_DIR_CASE(3)
+                    KC_DIR_CASE(4)
+                    KC_DIR_CASE(5)
+                    KC_DIR_CASE(6)
+                    KC_DIR_CASE(7)
+                    KC_DIR_CASE(8)
+#undef KC_DIR_CASE
+                }
+                h->span_end("eim_dist", ev, 1, s);
+            } else if (nds > 0 && nc > 0) {
                 const int dp = kc_mindist_dpad(d, false);
                 const uint32_t kpad = (nds + 15u) & ~15u;
                 float* XR = (float*)h->ws("e.XR", 4ull * nc * d);

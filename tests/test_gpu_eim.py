@@ -93,16 +93,18 @@ def test_all_duplicates(kc, orc):
     assert len(g["iters"]) == 1 and g["radius"] == 0.0
 
 
-# The unbalanced blobs leave many candidates whose MFMA interval contains
-# tau, so the exact FP64 pass decides them: tiled for d <= 64, one block per
-# candidate above (d = 70).
-@pytest.mark.parametrize("d", [8, 32, 70])
+# d <= 8 runs the distance pass in canonical FP32 (tight relative bounds);
+# above, on MFMA, whose bounds scale with the norms, so the unbalanced blobs
+# leave many candidates whose interval contains tau and the exact FP64 pass
+# decides them: tiled for d <= 64, one block per candidate above (d = 70).
+@pytest.mark.parametrize("d", [2, 8, 32, 70])
 def test_unbalanced_blobs(kc, orc, d):
     from paper_1604_03228_amd import workloads as W
     X = W.points_gauss_mixture(100_000, d, 25, seed=77, heavy=0.9)
     g = gpu_eim(kc, X, 20, 0.1, 4.0, 5 * 2**32 + 1)
     check(orc, X, 20, 0.1, 4.0, 5 * 2**32 + 1, g)
-    assert g["exact"] > 0
+    if d > 8:
+        assert g["exact"] > 0
 
 
 def test_max_iters_reports_noconv(kc):
