@@ -44,7 +44,7 @@ typedef enum {
     KC_EINVAL = -1,        /* invalid argument                              */
     KC_ENOMEM = -2,        /* workspace allocation failed                   */
     KC_EHIP = -3,          /* a HIP runtime call failed                     */
-    KC_ENOCONV = -4,       /* EIM did not converge within max_iters         */
+    KC_ENOCONV = -4,       /* EIM did not converge; an MRG pass kept all    */
     KC_EUNSUPPORTED = -6,  /* valid request this build cannot serve         */
     KC_EDEVICE = -7        /* a device-side check failed (see kc_device_status) */
 } kc_status;
@@ -87,7 +87,7 @@ int kc_set_option(kc_handle* h, const char* name, int64_t value);
  * one of the names "gon_resident" (persistent Gonzalez, 1 launch),
  * "gon_step" (k streaming step launches), "gon_bf16" (BF16 stream steps),
  * "mrg_round1" (MRG first round: its persistent launches, or its
- * streaming step launches), "assign_mfma" (the MFMA
+ * streaming step launches), "mrg_rounds" (each round of kcenter_mrg_rounds), "assign_mfma" (the MFMA
  * distance kernel of an assignment), "eim_dist" (EIM distance passes).
  * kc_timing_read synchronises the device, returns the summed milliseconds,
  * the number of kernel launches those intervals cover and the number of
@@ -162,6 +162,27 @@ int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int3
                 int64_t k, int64_t* centers, int64_t* n_centers, double* radius,
                 int64_t* round1, double* r1, int64_t* uni, int64_t* n_union,
                 double* r2, void* stream);
+
+/*
+ * kcenter_mrg_rounds -- MRG with its loop (Algorithm 1 with machine capacity
+ * c; Lemma 3 and Eq. 1: i passes of the loop then the last round give a
+ * 2(i+1)-approximation).  The sample S starts as all points.  While |S| > c,
+ * S is split into ceil(|S| / c) contiguous blocks of its ascending index
+ * order (sizes differ by at most one), Gonzalez(k) runs on every block
+ * (first center: the block's smallest index) and S becomes the ascending
+ * union of their centers.  Then Gonzalez(k) on S (first center: S[0]), and
+ * the covering radius over all points.  The FP32 points are used in either
+ * precision.  SYNCHRONISES the stream once per pass (to size the next one).
+ *   k          centers, 1 <= k < 2^24.
+ *   capacity   c >= 1; a pass that does not shrink S (k too close to c)
+ *              returns KC_ENOCONV.
+ *   centers    device int64 [k] (-1 padded), n_centers device int64 [1].
+ *   radius     device double [1]: exact FP64 covering radius over all points.
+ *   rounds     HOST int32 [1] or NULL: passes of the loop plus the last round.
+ */
+int kcenter_mrg_rounds(kc_handle* h, const kc_points* pts, int64_t k, int64_t capacity,
+                       int64_t* centers, int64_t* n_centers, double* radius, int32_t* rounds,
+                       void* stream);
 
 /*
  * kcenter_assign -- nearest-center assignment and covering radius (the

@@ -58,7 +58,8 @@ EXPORTS = ["kc_create", "kc_destroy", "kc_strerror", "kc_last_error",
            "kc_set_option", "kc_device_status", "kc_timing_read",
            "kc_counter_read",
            "kcenter_gonzalez",
-           "kcenter_mrg", "kcenter_assign", "kcenter_eim", "kcenter_batch"]
+           "kcenter_mrg", "kcenter_mrg_rounds", "kcenter_assign", "kcenter_eim",
+           "kcenter_batch"]
 
 _lib = None
 
@@ -89,6 +90,8 @@ def load_library(path=LIB_PATH):
                                    _p, _p, _p, _p]
     L.kcenter_mrg.argtypes = [_p, ctypes.POINTER(KcPoints), _p, _i32, _i64,
                               _p, _p, _p, _p, _p, _p, _p, _p, _p]
+    L.kcenter_mrg_rounds.argtypes = [_p, ctypes.POINTER(KcPoints), _i64, _i64,
+                                     _p, _p, _p, ctypes.POINTER(_i32), _p]
     L.kcenter_assign.argtypes = [_p, ctypes.POINTER(KcPoints), _p, _i64, _p,
                                  _p, _p]
     L.kcenter_eim.argtypes = [_p, ctypes.POINTER(KcPoints), _i64,
@@ -98,7 +101,8 @@ def load_library(path=LIB_PATH):
     L.kcenter_batch.argtypes = [_p, _p, _i32, _p]
     for name in ("kc_create", "kc_set_option", "kc_device_status",
                  "kc_timing_read", "kc_counter_read",
-                 "kcenter_gonzalez", "kcenter_mrg", "kcenter_assign",
+                 "kcenter_gonzalez", "kcenter_mrg", "kcenter_mrg_rounds",
+                 "kcenter_assign",
                  "kcenter_eim", "kcenter_batch"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -253,6 +257,23 @@ def mrg(X, offsets, k, bf16=None, handle=None, details=False):
     if details:
         return centers, nc, radius, extra
     return centers, nc, radius
+
+
+def mrg_rounds(X, k, capacity, handle=None):
+    """Multi-round MRG with per-machine capacity.  Returns (centers,
+    n_centers, radius) CUDA tensors and the number of rounds (host int);
+    reads |S| once per pass."""
+    h = handle or default_handle()
+    dev = X.device
+    centers = torch.empty(k, dtype=torch.int64, device=dev)
+    nc = torch.empty(1, dtype=torch.int64, device=dev)
+    radius = torch.empty(1, dtype=torch.float64, device=dev)
+    rounds = _i32(0)
+    p = points(X, None)
+    h._check(load_library().kcenter_mrg_rounds(
+        h._h, ctypes.byref(p), int(k), int(capacity), _ptr(centers), _ptr(nc),
+        _ptr(radius), ctypes.byref(rounds), _stream()))
+    return centers, nc, radius, rounds.value
 
 
 def assign(X, centers, bf16=None, labels=True, handle=None):

@@ -51,6 +51,17 @@ __global__ void k_mrg_union(const int64_t* __restrict__ cent, const int64_t* __r
     }
 }
 
+// Row-major copy of the listed rows: Y[i][*] = X[idx[i]][*] (d columns).
+__global__ void k_gather_rows64(const float* __restrict__ X, int64_t ld, int d,
+                                const int64_t* __restrict__ idx, uint64_t n,
+                                float* __restrict__ Y)
+{
+    const uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (q >= n * (uint64_t)d) return;
+    const uint64_t i = q / (uint64_t)d, j = q - i * (uint64_t)d;
+    Y[q] = X[(uint64_t)idx[i] * (uint64_t)ld + j];
+}
+
 // SoA copy of the listed rows: column i <- row uni[i] (padding repeats uni[0]).
 __global__ void k_gather_soa(const float* __restrict__ X, int64_t ld, int d,
                              const int64_t* __restrict__ uni, const int64_t* __restrict__ nu,
@@ -367,6 +378,111 @@ int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int3
     p32.prec = KC_FP32;
     p32.bf16 = nullptr;
     return kc_assign_run(h, &p32, centers, (uint32_t)k, n_centers, nullptr, radius, s, "m3.");
+}
+
+
+// Multi-round MRG: Algorithm 1 with its while loop (Lemma 3 and Eq. 1 give
+// the factor 2(i+1) after i passes).  The sample S starts as all points; while
+// |S| > capacity it is split into ceil(|S| / capacity) contiguous blocks of
+// its ascending order (sizes differ by at most one) and Gonzalez(k) runs on
+// every block (first center: the block's smallest index), all blocks as the
+// segments of one batched run; S becomes the ascending union of their
+// centers.  Then Gonzalez(k) on S, first center S[0], and the covering radius
+// over all points.  The host reads |S| once per pass.
+int kcenter_mrg_rounds(kc_handle* h, const kc_points* pts, int64_t k, int64_t capacity,
+                       int64_t* centers, int64_t* n_centers, double* radius, int32_t* rounds,
+                       void* stream)
+{
+    if (!h) return KC_EINVAL;
+    int rc = kc_check_points(h, pts, false);
+    if (rc) return rc;
+    if (k < 1 || k >= (1 << 24)) return h->fail(KC_EINVAL, "k=%lld out of range", (long long)k);
+    if (capacity < 1) return h->fail(KC_EINVAL, "capacity must be >= 1");
+    if (!centers || !n_centers || !radius) return h->fail(KC_EINVAL, "outputs NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int d = pts->d;
+    const float* Xc = pts->f32;   // rows of the current sample
+    int64_t ldc = pts->ld;
+    const int64_t* S = nullptr;   // global index of each row of Xc (NULL: identity)
+    int64_t ns = pts->n;
+    int r = 0;
+    while (ns > capacity) {
+        const int64_t mi = (ns + capacity - 1) / capacity;
+        if (mi * k >= (int64_t)0xFFFFFFFFll || mi > (1 << 24))
+            return h->fail(KC_EINVAL, "too many blocks (%lld) for one pass", (long long)mi);
+        std::vector<KcGonJob> jobs((size_t)mi);
+        std::vector<int64_t> base((size_t)mi);
+        for (int64_t p = 0; p < mi; ++p) {
+            const int64_t lo = p * ns / mi, hi = (p + 1) * ns / mi;
+            jobs[p].X = Xc;
+            jobs[p].ld = ldc;
+            jobs[p].row0 = (uint64_t)lo;
+            jobs[p].len = (uint32_t)(hi - lo);
+            jobs[p].first = 0;
+            jobs[p].k = (uint32_t)k;
+            base[p] = lo;
+        }
+        const std::string pre = r & 1 ? "mr1." : "mr0.";
+        KcGonRun R;
+        KcGonHost H;
+        rc = kc_plan_gon(h, pre, d, 1024, jobs, R, H);
+        if (rc) return rc;
+        int64_t* cent = (int64_t*)h->ws("mr.cent", sizeof(int64_t) * (size_t)(mi * k));
+        int64_t* nch = (int64_t*)h->ws("mr.nch", sizeof(int64_t) * (size_t)mi);
+        int64_t* uni = (int64_t*)h->ws(pre + "uni", sizeof(int64_t) * (size_t)(mi * k));
+        int64_t* nu = (int64_t*)h->ws("mr.nu", 16);
+        uint32_t* segl = (uint32_t*)h->ws("mr.segl", 16);
+        const int64_t* rb = S ? nullptr
+                              : (const int64_t*)h->upload("mr.rb", base.data(),
+                                                          sizeof(int64_t) * base.size());
+        if (!cent || !nch || !uni || !nu || !segl || (!S && !rb))
+            return h->fail(KC_ENOMEM, "workspace allocation failed");
+        const std::string key = kc_key("mrr", {pts->f32, cent, Xc, S},
+                                       {pts->n, d, pts->ld, k, capacity, r, ns});
+        rc = kc_run_gon(h, key, R, H, jobs, "mrg_rounds", s, [&](hipStream_t st) {
+            kc_fill_u64((u64*)cent, ~0ull, (uint64_t)(mi * k), st);
+            kc_gon_finish(R, cent, nch, nullptr, nullptr, rb, S, st);
+        });
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_mrg_union, dim3((unsigned)mi), dim3(256), 0, s, cent, nch, (int)mi,
+                           (int)k, uni, nu, segl);
+        int64_t nn = 0;
+        if (hipMemcpyAsync(&nn, nu, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return h->fail(KC_EHIP, "readback failed");
+        ++r;
+        if (nn >= ns)
+            return h->fail(KC_ENOCONV, "pass %d left %lld of %lld points (k too close to the "
+                           "capacity)", r, (long long)nn, (long long)ns);
+        float* Xg = (float*)h->ws(pre + "x", sizeof(float) * (size_t)nn * d);
+        if (!Xg) return h->fail(KC_ENOMEM, "workspace allocation failed");
+        const uint64_t tot = (uint64_t)nn * d;
+        hipLaunchKernelGGL(k_gather_rows64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                           pts->f32, pts->ld, d, uni, (uint64_t)nn, Xg);
+        S = uni;
+        Xc = Xg;
+        ldc = d;
+        ns = nn;
+    }
+    // the last round: Gonzalez(k) on S, first center its smallest index
+    std::vector<KcGonJob> jobs(1);
+    jobs[0] = KcGonJob{Xc, ldc, 0, (uint32_t)ns, 0, (uint32_t)k};
+    KcGonRun R;
+    KcGonHost H;
+    rc = kc_plan_gon(h, "mrf.", d, 1024, jobs, R, H);
+    if (rc) return rc;
+    const std::string key = kc_key("mrf", {pts->f32, Xc, S, centers, n_centers},
+                                   {pts->n, d, pts->ld, k, capacity, r, ns});
+    rc = kc_run_gon(h, key, R, H, jobs, "mrg_rounds", s, [&](hipStream_t st) {
+        kc_gon_finish(R, centers, n_centers, nullptr, nullptr, nullptr, S, st);
+    });
+    if (rc) return rc;
+    ++r;
+    if (rounds) *rounds = r;
+    kc_points p32 = *pts;
+    p32.prec = KC_FP32;
+    p32.bf16 = nullptr;
+    return kc_assign_run(h, &p32, centers, (uint32_t)k, n_centers, nullptr, radius, s, "mra.");
 }
 
 }  // extern "C"
