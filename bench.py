@@ -160,6 +160,25 @@ def bench_mrg(kc, torch, steps):
         h.close()
     out["same_centers"] = bool(all(np.array_equal(cents["fp32"], c)
                                    for c in cents.values()))
+    # Algorithm 1 with its loop: capacity 250,000 points per machine (32
+    # blocks of 250,000, then 32 x 200 = 6,400 centers in one last round)
+    h = kc.Handle()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        for _ in range(2):
+            r = kc.mrg_rounds(Xd, k, 250_000, handle=h)
+        st.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(steps):
+            r = kc.mrg_rounds(Xd, k, 250_000, handle=h)
+        e1.record(st)
+        st.synchronize()
+    out["rounds_c250000_ms"] = e0.elapsed_time(e1) / steps
+    out["rounds_c250000_rounds"] = r[3]
+    out["rounds_c250000_radius"] = float(r[2].item())
+    h.close()
     out["workload"] = "mrg_gauss50_n8000000_d16_m64_k200"
     out["speedup_bf16"] = out["fp32_ms"] / out["bf16_ms"]
     out["speedup_bf16_stream"] = out["fp32_stream_ms"] / out["bf16_stream_ms"]
