@@ -123,13 +123,33 @@ __global__ __launch_bounds__(256) void k_stage_rows(
     kc_stage_tile64(X, Xb, ld, d, row0, len, blockIdx.x * 64u, xs, xb, ex, stride, base, sx, sb);
 }
 
+// FP32 copy only, d and ld multiples of 4 and X 16-byte aligned: one 16-byte
+// group of a row per thread, consecutive threads on consecutive groups (the
+// reads coalesce with no LDS round trip), four scalar stores into four rows.
+__device__ __forceinline__ void kc_stage_vec4(const float* __restrict__ X, int64_t ld, int d,
+                                              uint64_t row0, uint32_t len, uint32_t st,
+                                              uint32_t end, float* __restrict__ xs,
+                                              uint64_t stride, uint64_t base)
+{
+    const uint32_t g4 = (uint32_t)d >> 2, items = (end - st) * g4;
+    for (uint32_t q = threadIdx.x; q < items; q += blockDim.x) {
+        const uint32_t i = st + q / g4, g = q - (q / g4) * g4;
+        const float4 v = *(const float4*)(X + (row0 + (i < len ? i : 0)) * (uint64_t)ld + 4 * g);
+        float* dst = xs + (uint64_t)(4 * g) * stride + base + i;
+        dst[0] = v.x;
+        dst[stride] = v.y;
+        dst[2 * stride] = v.z;
+        dst[3 * stride] = v.w;
+    }
+}
+
 // Every segment of a planned run (all reading the same arrays): block b
 // stages the `tile` columns from blk_start[b] of segment blk_seg[b].
 __global__ __launch_bounds__(256) void k_stage_rows_batch(
     const float* __restrict__ X, const uint16_t* __restrict__ Xb, int64_t ld, int d,
     const KcSeg* __restrict__ segs, const uint32_t* __restrict__ blk_seg,
     const uint32_t* __restrict__ blk_start, uint32_t tile, float* __restrict__ xs,
-    uint16_t* __restrict__ xb, float* __restrict__ ex, uint64_t stride)
+    uint16_t* __restrict__ xb, float* __restrict__ ex, uint64_t stride, int vec4)
 {
     __shared__ float sx[64 * (KC_STG_W + 1)];
     __shared__ uint16_t sb[64 * (KC_STG_W + 1)];
@@ -137,6 +157,10 @@ __global__ __launch_bounds__(256) void k_stage_rows_batch(
     const uint32_t st = blk_start[blockIdx.x];
     const uint32_t padded = (sg.len + 63u) & ~63u;
     const uint32_t end = st + tile < padded ? st + tile : padded;
+    if (vec4 && !xb) {
+        kc_stage_vec4(X, ld, d, sg.src, sg.len, st, end, xs, stride, sg.base);
+        return;
+    }
     for (uint32_t i0 = st; i0 < end; i0 += 64)
         kc_stage_tile64(X, Xb, ld, d, sg.src, sg.len, i0, xs, xb, ex, stride, sg.base, sx, sb);
 }
@@ -163,8 +187,9 @@ void kc_stage_rows_batch(const float* X, const uint16_t* Xb, int64_t ld, int d,
                          uint64_t stride, hipStream_t s)
 {
     if (nblk == 0) return;
+    const int vec4 = d % 4 == 0 && ld % 4 == 0 && ((uintptr_t)X & 15) == 0;
     hipLaunchKernelGGL(k_stage_rows_batch, dim3(nblk), dim3(256), 0, s, X, Xb, ld, d, segs,
-                       blk_seg, blk_start, tile, xs, xb, ex, stride);
+                       blk_seg, blk_start, tile, xs, xb, ex, stride, vec4);
 }
 
 // ---------------------------------------------------------------------------
