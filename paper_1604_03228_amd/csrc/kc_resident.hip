@@ -2,7 +2,9 @@
 // certified lookahead.
 //
 // One cooperative launch runs all k steps of one segment whose points fit in
-// the register file of the grid.  A block has one leader wave and
+// the register file of the grid, or of several segments at once (each on its
+// own consecutive blocks, exchanging only among them: the partitions of an
+// MRG round, or the problems of a batch).  A block has one leader wave and
 // KC_LA_WORKERS worker waves; worker lane (g, w, lane) keeps the coordinates
 // and the running FP32 min-distance of local points
 //     i = g*KC_LA_WPTS*PPT + p*KC_LA_WPTS + w*64 + lane,  p < PPT
@@ -34,8 +36,8 @@
 // on their points remains per step.
 //
 // Exchange words carry their round in the low word, so no word needs a
-// fence: (bits of the FP32 value << 32) | (tag << 12) | wave-local index,
-// index 4095 = "no point" (the leader's words, and waves without points).
+// fence: (bits of the FP32 value << 32) | (tag << 16) | block-local index,
+// index 0xFFFF = "no point" (waves without points), tag = round + 1 mod 2^16.
 // Rounds alternate between two buffers; a block cannot write round r+2
 // before every block has read round r, because it first needs every block's
 // round r+1 words.  Only relaxed device-scope atomics carry data.  Any block
