@@ -206,13 +206,34 @@ __global__ __launch_bounds__(KC_BLOCK) void k_gon_step_bf16(
 // cache it), canonical FP32, then the packed key goes to the step's argmax
 // slots.  nresc[t] counts the rescored points.
 #define KC_RESC_SEGS 1024   // segments whose L_t fits the LDS table
+#define KC_RESC_LT_SEGS 8   // above this many segments L_t comes from k_bf16_lt
+
+// L_t of every segment for step t (the max over its partial slots), one
+// thread per segment, so that the rescoring blocks of a run with many
+// segments read one word per listed point instead of every segment's slots.
+__global__ void k_bf16_lt(const uint32_t* __restrict__ lpart, const KcSeg* __restrict__ segs,
+                          int nseg, int t, float* __restrict__ Lt)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nseg) return;
+    const KcSeg sg = segs[s];
+    uint32_t v = 0;
+    if ((uint32_t)t < sg.ksteps)
+        for (uint32_t p = 0; p < KC_PARTS; ++p) {
+            const uint32_t x = lpart[((uint64_t)(sg.keyoff + t) * KC_PARTS + p) * 32];
+            v = x > v ? x : v;
+        }
+    Lt[s] = __uint_as_float(v);
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_bf16_rescore(
     const u64* __restrict__ list, const float* __restrict__ list_hi,
     const uint32_t* __restrict__ listcnt, uint32_t region, const uint32_t* __restrict__ lpart,
     const float* __restrict__ xs, uint64_t stride, int d, const float* __restrict__ ccoord,
     const KcSeg* __restrict__ segs, int nseg, float* __restrict__ exm,
-    uint32_t* __restrict__ exupto, u64* __restrict__ part, uint32_t* __restrict__ nresc, int t)
+    uint32_t* __restrict__ exupto, u64* __restrict__ part, uint32_t* __restrict__ nresc, int t,
+    const float* __restrict__ Lt)
 {
     __shared__ float sL[KC_RESC_SEGS];
     __shared__ uint32_t sinc[KC_PARTS];
@@ -221,7 +242,7 @@ __global__ __launch_bounds__(256) void k_bf16_rescore(
     const uint32_t waves = gridDim.x * (blockDim.x / 64);
     // L_t per segment (the step's partial slots are final: written by the
     // step kernel that ran before this one); KC_PARTS lanes per segment
-    const int nsl = nseg < KC_RESC_SEGS ? nseg : KC_RESC_SEGS;
+    const int nsl = Lt ? 0 : (nseg < KC_RESC_SEGS ? nseg : KC_RESC_SEGS);
     for (int s0 = 0; s0 < nsl; s0 += (int)blockDim.x / KC_PARTS) {
         const int s = s0 + (int)threadIdx.x / KC_PARTS, p = threadIdx.x % KC_PARTS;
         uint32_t x = 0;
@@ -268,7 +289,9 @@ __global__ __launch_bounds__(256) void k_bf16_rescore(
             e = list[qi];
             const uint32_t sidx = (uint32_t)(e >> 32);
             float L;
-            if (sidx < KC_RESC_SEGS) {
+            if (Lt) {
+                L = Lt[sidx];
+            } else if (sidx < KC_RESC_SEGS) {
                 L = sL[sidx];
             } else {
                 uint32_t v = 0;
@@ -392,12 +415,18 @@ void kc_enqueue_bf16_steps(const KcGonRun& R, const KcBf16Run& B, hipStream_t s)
                                R.segs, R.blk_seg, R.blk_start, t, B.g, B.list, B.list_hi,
                                B.listcnt, B.region);
         }
+        const float* Lt = nullptr;
+        if (R.nseg > KC_RESC_LT_SEGS) {
+            hipLaunchKernelGGL(k_bf16_lt, dim3((R.nseg + 255) / 256), dim3(256), 0, s, B.lpart,
+                               R.segs, R.nseg, t, B.Lt);
+            Lt = B.Lt;
+        }
         switch (R.d) {
 #define KC_RS_CASE(DD)                                                                        \
     case DD:                                                                                  \
         hipLaunchKernelGGL(k_bf16_rescore<DD>, dim3(B.rescore_blocks), dim3(256), 0, s, B.list, \
                            B.list_hi, B.listcnt, B.region, B.lpart, R.xs, R.stride, R.d,      \
-                           R.ccoord, R.segs, R.nseg, B.exm, B.exupto, R.part, B.nresc, t);    \
+                           R.ccoord, R.segs, R.nseg, B.exm, B.exupto, R.part, B.nresc, t, Lt); \
         break;
             KC_RS_CASE(2)
             KC_RS_CASE(8)
@@ -409,7 +438,8 @@ void kc_enqueue_bf16_steps(const KcGonRun& R, const KcBf16Run& B, hipStream_t s)
         default:
             hipLaunchKernelGGL(k_bf16_rescore<0>, dim3(B.rescore_blocks), dim3(256), 0, s, B.list,
                                B.list_hi, B.listcnt, B.region, B.lpart, R.xs, R.stride, R.d,
-                               R.ccoord, R.segs, R.nseg, B.exm, B.exupto, R.part, B.nresc, t);
+                               R.ccoord, R.segs, R.nseg, B.exm, B.exupto, R.part, B.nresc, t,
+                               Lt);
         }
     }
     kc_part_collect(R.part, R.keys, R.keysum, s);

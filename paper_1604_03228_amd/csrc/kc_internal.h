@@ -113,6 +113,7 @@ struct KcBf16Run {
     uint32_t* nresc = nullptr;    // [kmax] rescored points per step
     float* exm = nullptr;         // [stride] cached exact FP32 min-distance
     uint32_t* exupto = nullptr;   // [stride] centers covered by exm
+    float* Lt = nullptr;          // [nseg] L_t of the current step (many-segment runs)
     uint32_t rescore_blocks = 256;
     float g = 0.f;                // gamma_{d+2} + 16u
 };

@@ -109,8 +109,9 @@ int kc_bf16_alloc(kc_handle* h, const std::string& pre, const KcGonRun& R, KcBf1
     B.listcnt = (uint32_t*)h->ws(pre + "listcnt", sizeof(uint32_t) * KC_PARTS * 32 *
                                                       std::max<uint32_t>(R.kmax, 1));
     B.nresc = (uint32_t*)h->ws(pre + "nresc", sizeof(uint32_t) * std::max<uint32_t>(R.kmax, 1));
+    B.Lt = (float*)h->ws(pre + "lt", sizeof(float) * std::max<int>(R.nseg, 1));
     if (!B.xb || !B.ex || !B.lpart || !B.list || !B.list_hi || !B.exm || !B.exupto ||
-        !B.listcnt || !B.nresc)
+        !B.listcnt || !B.nresc || !B.Lt)
         return h->fail(KC_ENOMEM, "workspace allocation failed");
     h->last_bf16_listcnt = B.listcnt;
     h->last_bf16_nresc = B.nresc;
