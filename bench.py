@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--engine", choices=["auto", "stream"], default="auto")
     ap.add_argument("--mrg-only", action="store_true",
                     help="only the MRG FP32 vs BF16 comparison")
+    ap.add_argument("--eim-study", action="store_true",
+                    help="EIM's runtime / solution trade-off over phi and k on "
+                         "Gaussian data (n = 200,000, 25 clusters) and exit")
     ap.add_argument("--batch-only", action="store_true",
                     help="time kcenter_batch on the 256-instance mixed batch "
                          "(GON / MRG / EIM, d in {2, 8, 32}) and exit")
@@ -231,6 +234,47 @@ def bench_batch(kc, torch, steps):
             "gon_mrg1_updates_per_s": upd / (ms * 1e-3), "status": status}
 
 
+def eim_study(kc, torch, seeds=5):
+    """EIM with phi in {1, 4, 6, 8} and k in {2, 5, 10, 25, 50, 100}, eps 0.1,
+    on Gaussian data shaped like the paper's parameter study: n = 200,000,
+    d = 2, 25 clusters with centers uniform in [0, 100]^2 and sigma 0.1.
+    Per (k, phi): mean covering radius, mean wall time per call (the call
+    synchronises once per iteration), mean iterations and sample size over
+    `seeds` data sets; Gonzalez's radius on the same data for reference."""
+    import time
+    from paper_1604_03228_amd import workloads as W
+    ks = (2, 5, 10, 25, 50, 100)
+    phis = (1.0, 4.0, 6.0, 8.0)
+    acc = {}
+    gon = {k: 0.0 for k in ks}
+    h = kc.Handle()
+    for sd in range(seeds):
+        X = W.points_gauss_mixture(200_000, 2, 25, 0.0, 100.0, 0.1, 0.1, seed=600 + sd)
+        Xd = torch.from_numpy(X).cuda()
+        for k in ks:
+            c, tr, nc = kc.gonzalez(Xd, k, 0, handle=h)
+            gon[k] += float(tr[int(nc.item()) - 1].item()) / seeds
+            for phi in phis:
+                kc.eim(Xd, k, 0.1, phi, 7 * 2**32 + sd, handle=h)   # warm
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                c, nc, r, smp, its = kc.eim(Xd, k, 0.1, phi, 7 * 2**32 + sd,
+                                            want_sample=False, handle=h)
+                rr = float(r.item())
+                dt = time.perf_counter() - t0
+                a = acc.setdefault((k, phi), [0.0, 0.0, 0.0, 0.0])
+                a[0] += rr / seeds
+                a[1] += dt * 1e3 / seeds
+                a[2] += len(its) / seeds
+                a[3] += (its[-1]["s_size"] if its else 0) / seeds
+    h.close()
+    rows = [{"k": k, "phi": phi, "radius": v[0], "ms": v[1], "iterations": v[2],
+             "sample_S": v[3], "gon_radius": gon[k]}
+            for (k, phi), v in sorted(acc.items())]
+    return {"workload": "eim_study_gau_n200000_d2_k25clusters_eps0.1",
+            "seeds": seeds, "rows": rows}
+
+
 def bench_gon_bf16(kc, torch, steps):
     """Gonzalez k=500 on the 5,000,000 x 41 mixed-scale workload, FP32 vs
     BF16 stream + exact FP32 rescoring (same centers required)."""
@@ -283,6 +327,9 @@ def main():
     import paper_1604_03228_amd as kc
     from paper_1604_03228_amd import workloads as W
 
+    if a.eim_study:
+        print(json.dumps({"eim_study": eim_study(kc, torch)}))
+        return
     if a.batch_only:
         print(json.dumps({"batch": bench_batch(kc, torch, max(2, a.steps))}))
         return

@@ -11,7 +11,7 @@
 // in VGPRs (KC_LA_WPTS = 64*KC_LA_WORKERS), so applying a center reads
 // nothing from memory but its d coordinates.
 //
-// Gonzalez's traversal (Section 2.1) adds one farthest point per step, and a
+// Gonzalez's traversal (Section 3.1) adds one farthest point per step, and a
 // plain parallel version needs one grid-wide argmax per step.  This engine
 // meets the grid once per *round* of several steps instead:
 //

@@ -112,3 +112,15 @@ def test_max_iters_reports_noconv(kc):
     with pytest.raises(kc.KCenterError) as e:
         gpu_eim(kc, X, 3, 0.1, 8.0, 9, max_iters=1)
     assert e.value.status == -4
+
+
+# The parameter-study shape (Gaussian data, n = 200,000, d = 2, 25 clusters
+# of sigma 0.1 in [0, 100]^2, eps = 0.1): samples, iterations and centers
+# equal the oracle's at the extremes of phi and k.
+@pytest.mark.parametrize("k,phi", [(2, 1.0), (25, 8.0)])
+def test_study_shape(kc, orc, k, phi):
+    from paper_1604_03228_amd import workloads as W
+    X = W.points_gauss_mixture(200_000, 2, 25, 0.0, 100.0, 0.1, 0.1, seed=600)
+    g = gpu_eim(kc, X, k, 0.1, phi, 7 * 2**32)
+    check(orc, X, k, 0.1, phi, 7 * 2**32, g)
+    assert len(g["iters"]) >= 1
