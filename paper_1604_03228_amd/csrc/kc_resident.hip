@@ -381,14 +381,19 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
             uint32_t nv = nc, qn = (nc + 63) / 64;
 #pragma unroll
             for (int q = 0; q < QL; ++q) {
+                // slots past nc hold stale LDS values: their key is taken as 0
+                // (min-distance 0, never live), so their coordinates may be
+                // anything and the loads need no mask (at d = 16 with 9 points
+                // per lane this costs a few spilled VGPRs and is still faster)
                 const uint32_t sl = q * 64 + lane;
                 const bool v = sl < nc;
-                const u64 kq = v ? sCk[sl] : 0ull;
+                const u64 kraw = sCk[sl];
+                const u64 kq = v ? kraw : 0ull;
                 m[q] = kc_key_val(kq);
                 ci[q] = kc_key_idx(kq);
                 os[q] = sl;
 #pragma unroll
-                for (int j = 0; j < D; ++j) x[q][j] = v ? sCx[j][sl] : 0.f;
+                for (int j = 0; j < D; ++j) x[q][j] = sCx[j][sl];
                 if (kq > bl) {   // every key of C is above tau
                     bl = kq;
                     bs = sl;
