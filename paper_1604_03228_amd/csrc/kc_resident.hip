@@ -514,43 +514,117 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
             __builtin_amdgcn_s_setprio(0);
         } else {
-            // apply the queued centers in order; entry i+1 and its
-            // coordinates are read before center i is applied, so most of the
-            // LDS latency hides behind the arithmetic
-            uint32_t i = 0, f = 0;
-            float cv[D];
-            for (;;) {
-                if (f == 0) {
-                    f = __hip_atomic_load(&sQf[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    if (f == 0) {
-                        __builtin_amdgcn_s_sleep(1);
-                        continue;
+            // Two forms of the apply loop: where registers allow, a
+            // double-buffered one (no vector copies between steps); for the
+            // variants whose points leave no room for it (it would spill
+            // VGPRs in this loop), the single-buffer one.
+            constexpr bool kDB = PPT * (D + 1) + 3 * D <= 180;
+            if constexpr (kDB) {
+                // Apply the queued centers in order.  While the center of entry
+                // i is applied, entry i+1 and its coordinates load from LDS; the
+                // coordinates then move into scalar registers (they are
+                // block-uniform), alternating between two scalar sets so that no
+                // vector copies are needed between steps.
+                auto apply = [&](const float(&c)[D]) {
+#pragma unroll
+                    for (int p = 0; p < PPT; ++p) {
+                        float s = 0.f;
+#pragma unroll
+                        for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[p][j], c[j]);
+                        m[p] = kc_fmin_nn(m[p], s);
                     }
-                    if (!(f & KC_LA_END)) {
+                };
+                auto entry = [&](uint32_t at) -> uint32_t {
+                    return __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                        &sQf[at], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                };
+                auto wait_entry = [&](uint32_t at) -> uint32_t {
+                    uint32_t e;
+                    while ((e = entry(at)) == 0) __builtin_amdgcn_s_sleep(1);
+                    return e;
+                };
+                float tv[D];   // coordinates in flight (VGPRs)
+                auto load = [&](uint32_t e) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j) tv[j] = sCx[j][e - 1];
+                };
+                auto uniform = [&](float(&c)[D]) {
+#pragma unroll
+                    for (int j = 0; j < D; ++j)
+                        c[j] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(tv[j])));
+                };
+                float ca[D], cb[D];   // scalar sets
+                uint32_t i = 0;
+                uint32_t f = wait_entry(0);
+                if (!(f & KC_LA_END)) {
+                    load(f);
+                    uniform(ca);
+                }
+                while (!(f & KC_LA_END)) {
+                    // entry i is a center, its coordinates in ca
+                    uint32_t g = entry(++i);
+                    if (g != 0 && !(g & KC_LA_END)) load(g);
+                    apply(ca);
+                    if (g == 0) {
+                        g = wait_entry(i);
+                        if (!(g & KC_LA_END)) load(g);
+                    }
+                    if (g & KC_LA_END) {
+                        f = g;
+                        break;
+                    }
+                    uniform(cb);
+                    // entry i is a center, its coordinates in cb
+                    f = entry(++i);
+                    if (f != 0 && !(f & KC_LA_END)) load(f);
+                    apply(cb);
+                    if (f == 0) {
+                        f = wait_entry(i);
+                        if (!(f & KC_LA_END)) load(f);
+                    }
+                    if (!(f & KC_LA_END)) uniform(ca);
+                }
+                state = f & ~KC_LA_END;
+            } else {
+                // apply the queued centers in order; entry i+1 and its
+                // coordinates are read before center i is applied, so most of
+                // the LDS latency hides behind the arithmetic
+                uint32_t i = 0, f = 0;
+                float cv[D];
+                for (;;) {
+                    if (f == 0) {
+                        f = __hip_atomic_load(&sQf[i], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_WORKGROUP);
+                        if (f == 0) {
+                            __builtin_amdgcn_s_sleep(1);
+                            continue;
+                        }
+                        if (!(f & KC_LA_END)) {
+#pragma unroll
+                            for (int j = 0; j < D; ++j) cv[j] = sCx[j][f - 1];
+                        }
+                    }
+                    if (f & KC_LA_END) {
+                        state = f & ~KC_LA_END;
+                        break;
+                    }
+                    float cc[D];   // uniform: held in SGPRs
+#pragma unroll
+                    for (int j = 0; j < D; ++j)
+                        cc[j] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cv[j])));
+                    ++i;
+                    f = __hip_atomic_load(&sQf[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (f != 0 && !(f & KC_LA_END)) {
 #pragma unroll
                         for (int j = 0; j < D; ++j) cv[j] = sCx[j][f - 1];
                     }
-                }
-                if (f & KC_LA_END) {
-                    state = f & ~KC_LA_END;
-                    break;
-                }
-                float cc[D];   // uniform: held in SGPRs
 #pragma unroll
-                for (int j = 0; j < D; ++j)
-                    cc[j] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cv[j])));
-                ++i;
-                f = __hip_atomic_load(&sQf[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (f != 0 && !(f & KC_LA_END)) {
+                    for (int p = 0; p < PPT; ++p) {
+                        float s = 0.f;
 #pragma unroll
-                    for (int j = 0; j < D; ++j) cv[j] = sCx[j][f - 1];
-                }
-#pragma unroll
-                for (int p = 0; p < PPT; ++p) {
-                    float s = 0.f;
-#pragma unroll
-                    for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[p][j], cc[j]);
-                    m[p] = kc_fmin_nn(m[p], s);
+                        for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[p][j], cc[j]);
+                        m[p] = kc_fmin_nn(m[p], s);
+                    }
                 }
             }
         }
