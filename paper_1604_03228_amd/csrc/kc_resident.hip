@@ -240,12 +240,21 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
             uint32_t have = 0, spins = 0;
             for (;;) {
                 bool all = true;
+                // every word load is issued before any is examined, so one
+                // wait covers them all (a word already taken, or past this
+                // segment's end, is reread from a valid slot and ignored)
+                u64 wr[KC_LA_NPT];
+#pragma unroll
+                for (int q = 0; q < KC_LA_NPT; ++q) {
+                    const uint32_t e = tid_r + q * KC_LA_BLOCK;
+                    wr[q] = __hip_atomic_load(rb + (uint64_t)b0 * KC_LA_WPB + (e < NWB ? e : 0u),
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
 #pragma unroll
                 for (int q = 0; q < KC_LA_NPT; ++q) {
                     const uint32_t e = tid_r + q * KC_LA_BLOCK;
                     if (e < NWB && !((have >> q) & 1u)) {
-                        const u64 w = __hip_atomic_load(rb + (uint64_t)b0 * KC_LA_WPB + e,
-                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const u64 w = wr[q];
                         if ((((uint32_t)w) >> 16) == tag) {
                             const u64 kw = kc_la_decode<PPT>(w, e / KC_LA_WPB);
                             if (e % KC_LA_WPB == KC_LA_WPB - 1) tl = kc_umax64(tl, kw);
