@@ -424,8 +424,14 @@ int kc_run_gon_resident_batch(kc_handle* h, const std::string& key, const KcGonR
     for (const KcGonJob& j : jobs)
         if (j.X != xa || j.ld != jobs[0].ld) xa = nullptr;
     const int64_t lda = xa ? jobs[0].ld : 0;
+    // The points load straight from those rows, with no staging copy, when
+    // the caller's finishing pass reads them there too (R.xa) and the
+    // kernel's row loads allow them.
+    uint64_t rspan = 0;
+    for (const KcSeg& sg : H.segs) rspan = std::max<uint64_t>(rspan, sg.len);
+    const int rows = xa && R.xa == xa && R.lda == lda && kc_resident_rows_ok(d, xa, lda, rspan);
     int rc = h->run_graph(key + ":rprep", s, [&](hipStream_t st) {
-        kc_enqueue_stage(R, H, jobs, st);
+        if (!rows) kc_enqueue_stage(R, H, jobs, st);
         kc_fill_u64(bar, 0ull, bw * launches.size(), st);
     });
     if (rc) return rc;
@@ -435,7 +441,7 @@ int kc_run_gon_resident_batch(kc_handle* h, const std::string& key, const KcGonR
         u64* slots = bar + bw * l;
         uint32_t* abort_flag = (uint32_t*)(slots + (bw - 8));
         hipError_t e = kc_gon_resident(d, L.v, L.G, R.xs, R.stride, 0, 0, nullptr, 0, 0, R.mind,
-                                       R.keys, slots, abort_flag, h->spin_limit, xa, lda,
+                                       R.keys, slots, abort_flag, h->spin_limit, xa, lda, rows,
                                        h->status_word, R.segs, blks + off[l], s);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -638,15 +644,19 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
             u64* bar = (u64*)h->ws("g.bar", sizeof(u64) * (bw + 8));
             if (!bar) return h->fail(KC_ENOMEM, "workspace allocation failed");
             uint32_t* abort_flag = (uint32_t*)(bar + bw);
-            kc_stage_soa(pts->f32, pts->ld, pts->d, 0, (uint32_t)pts->n, (float*)R.xs,
-                         R.stride, 0, s);
+            // points straight from the caller's rows when the kernel's row
+            // loads allow them, else from the SoA staging copy
+            const int rows = kc_resident_rows_ok(pts->d, pts->f32, pts->ld, (uint64_t)pts->n);
+            if (!rows)
+                kc_stage_soa(pts->f32, pts->ld, pts->d, 0, (uint32_t)pts->n, (float*)R.xs,
+                             R.stride, 0, s);
             kc_fill_u64(bar, 0ull, bw + 1, s);
             R.xa = pts->f32;
             R.lda = pts->ld;
             hipEvent_t ev = h->span_begin(s);
             hipError_t e = kc_gon_resident(pts->d, v, G, R.xs, R.stride, 0, (uint32_t)pts->n, nullptr,
                                            (uint32_t)first, (int)k, R.mind, R.keys, bar,
-                                           abort_flag, h->spin_limit, pts->f32, pts->ld,
+                                           abort_flag, h->spin_limit, pts->f32, pts->ld, rows,
                                            h->status_word, nullptr, nullptr, s);
             h->span_end("gon_resident", ev, 1, s);
             if (e == hipSuccess) {

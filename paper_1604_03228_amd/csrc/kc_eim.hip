@@ -664,7 +664,7 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
             kc_fill_u64(slots, 0ull, sw, s);
             kc_fill_u32(abort_flag, 0u, 1, s);
             if (kc_gon_resident(d, v, G, RG.xs, RG.stride, 0, nc, nullptr, 0, (int)k, RG.mind,
-                                RG.keys, slots, abort_flag, h->spin_limit, nullptr, 0,
+                                RG.keys, slots, abort_flag, h->spin_limit, nullptr, 0, 0,
                                 h->status_word, nullptr, nullptr, s) == hipSuccess) {
                 done = true;
             } else {

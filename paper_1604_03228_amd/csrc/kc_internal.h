@@ -78,9 +78,12 @@ int kc_resident_max_blocks(int d, int v);
 uint32_t kc_resident_blocks_for(int d, int v, uint64_t len);
 uint32_t kc_resident_block_points(int d, int v);
 double kc_resident_launch_cycles(int d, int v, uint32_t k);
+bool kc_resident_rows_ok(int d, const float* xa, int64_t lda, uint64_t span);
 // `xa` (nullable): the same points as rows of lda floats (the caller's
-// array), used to gather candidate coordinates; NULL gathers from xs.  A
-// wait that exceeds the spin limit raises abort_flag and bit 0 of *status.
+// array), used to gather candidate coordinates; NULL gathers from xs.  With
+// xa_rows (only where kc_resident_rows_ok holds for the longest segment) the
+// points are loaded from xa too and xs is not read.  A wait that exceeds the
+// spin limit raises abort_flag and bit 0 of *status.
 // With `blks` (device, one uint4 per block: segment, block within it, blocks
 // of the segment, first block of the segment) the launch runs several
 // segments of `segs` at once and base/len/first/k come from each segment
@@ -89,8 +92,9 @@ hipError_t kc_gon_resident(int d, int v, uint32_t G, const float* xs, uint64_t s
                            uint64_t base, uint32_t len, const uint32_t* len_ptr,
                            uint32_t first, int k, float* mind,
                            u64* keys, u64* slots, uint32_t* abort_flag,
-                           uint32_t spin_limit, const float* xa, int64_t lda, uint32_t* status,
-                           const KcSeg* segs, const uint4* blks, hipStream_t s);
+                           uint32_t spin_limit, const float* xa, int64_t lda, int xa_rows,
+                           uint32_t* status, const KcSeg* segs, const uint4* blks,
+                           hipStream_t s);
 void kc_gon_finish(const KcGonRun& R, int64_t* centers, int64_t* n_chosen, double* trace,
                    double* radius_out, const int64_t* report_base, const int64_t* remap,
                    hipStream_t s);

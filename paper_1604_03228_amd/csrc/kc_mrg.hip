@@ -284,6 +284,10 @@ int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int3
     // HBM once, so there is no stream for BF16 to halve, and the sequences
     // are the FP32 path's by construction.  Otherwise the partitions stream,
     // in BF16 with exact rescoring or in FP32.
+    // Round 1's finishing pass reads the caller's rows, so the resident
+    // engine can load its points from them without a staging copy.
+    R1.xa = pts->f32;
+    R1.lda = pts->ld;
     bool done = false;
     if (h->allow_resident) {
         rc = kc_run_gon_resident_batch(h, key1, R1, H1, jobs, "mrg_round1", s, &done);
@@ -355,8 +359,8 @@ int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int3
             kc_fill_u32(abort_flag, 0u, 1, s);
             hipError_t e = kc_gon_resident(d, v, G, R2.xs, R2.stride, 0, (uint32_t)cap, len_ptr, 0,
                                            (int)k, R2.mind, R2.keys, slots, abort_flag,
-                                           h->spin_limit, nullptr, 0, h->status_word, nullptr,
-                                           nullptr, s);
+                                           h->spin_limit, nullptr, 0, 0, h->status_word,
+                                           nullptr, nullptr, s);
             if (e == hipSuccess) {
                 done = true;
             } else {
@@ -440,6 +444,8 @@ int kcenter_mrg_rounds(kc_handle* h, const kc_points* pts, int64_t k, int64_t ca
             return h->fail(KC_ENOMEM, "workspace allocation failed");
         const std::string key = kc_key("mrr", {pts->f32, cent, Xc, S},
                                        {pts->n, d, pts->ld, k, capacity, r, ns});
+        R.xa = Xc;   // the finishing pass reads the rows (no staging copy needed)
+        R.lda = ldc;
         rc = kc_run_gon(h, key, R, H, jobs, "mrg_rounds", s, [&](hipStream_t st) {
             kc_fill_u64((u64*)cent, ~0ull, (uint64_t)(mi * k), st);
             kc_gon_finish(R, cent, nch, nullptr, nullptr, rb, S, st);
@@ -474,6 +480,8 @@ int kcenter_mrg_rounds(kc_handle* h, const kc_points* pts, int64_t k, int64_t ca
     if (rc) return rc;
     const std::string key = kc_key("mrf", {pts->f32, Xc, S, centers, n_centers},
                                    {pts->n, d, pts->ld, k, capacity, r, ns});
+    R.xa = Xc;
+    R.lda = ldc;
     rc = kc_run_gon(h, key, R, H, jobs, "mrg_rounds", s, [&](hipStream_t st) {
         kc_gon_finish(R, centers, n_centers, nullptr, nullptr, nullptr, S, st);
     });

@@ -102,8 +102,8 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
     const float* __restrict__ xs, uint64_t stride, uint64_t base, uint32_t len,
     const uint32_t* __restrict__ len_ptr, uint32_t first, int k, float* __restrict__ mind,
     u64* __restrict__ keys, u64* __restrict__ xbuf, uint32_t* __restrict__ abort_flag,
-    uint32_t spin_limit, const float* __restrict__ xa, int64_t lda, uint32_t* __restrict__ status,
-    const KcSeg* __restrict__ segs, const uint4* __restrict__ blks)
+    uint32_t spin_limit, const float* __restrict__ xa, int64_t lda, int xa_rows,
+    uint32_t* __restrict__ status, const KcSeg* __restrict__ segs, const uint4* __restrict__ blks)
 {
     static_assert(KC_LA_WPTS * PPT <= KC_LA_NONE, "block-local index must fit in 16 bits");
     constexpr uint32_t CMAX = KcLaCap<PPT>::value;
@@ -146,19 +146,54 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
     const uint32_t i0 = blk0 + (leader ? 0u : (wave - 1) * 64 + lane);
     const bool recorder = lb == 0 && tid == 0;   // the leader of the segment's block 0
 
-    // the points come from the staging copy (coalesced rows of one
-    // coordinate); the caller's rows serve the scattered candidate gathers
-    auto coord = [&](uint32_t i, int j) -> float { return xs[(uint64_t)j * stride + base + i]; };
+    // The points come from the caller's rows when xa_rows is set, else from
+    // the SoA staging copy (coalesced per coordinate).  A lane reads its
+    // point's row in vector loads: a wave's 64 rows are contiguous, so every
+    // cache line it touches is used whole across the row's loads.  Rows past
+    // the end read row 0 and are never live.
+    auto coord = [&](uint32_t i, int j) -> float {
+        return xa_rows ? xa[(uint64_t)i * (uint64_t)lda + j] : xs[(uint64_t)j * stride + base + i];
+    };
     float x[PPT][D];
     float m[PPT];
     if (tid < D) cc0[tid] = coord(first, tid);
     if (!leader) {
+        if (xa_rows) {
+            // kc_resident_row_floats(D) floats per load: the host takes this
+            // path only when rows and base are aligned to it and byte
+            // offsets from the segment's first row fit 32 bits, so each load
+            // is the wave-uniform base plus one 32-bit VGPR
+            constexpr int VW = D % 4 == 0 ? 4 : D % 2 == 0 ? 2 : 1;
+            const char* xb = (const char*)xa;
 #pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-            const uint32_t i = i0 + p * KC_LA_WPTS;
-            const uint32_t ii = i < len ? i : 0;
+            for (int p = 0; p < PPT; ++p) {
+                const uint32_t i = i0 + p * KC_LA_WPTS;
+                const uint32_t bo = (i < len ? i : 0u) * (uint32_t)lda * 4u;
 #pragma unroll
-            for (int j = 0; j < D; ++j) x[p][j] = coord(ii, j);
+                for (int j = 0; j < D; j += VW) {
+                    if constexpr (VW == 4) {
+                        const float4 v = *(const float4*)(xb + bo + 4 * j);
+                        x[p][j] = v.x;
+                        x[p][j + 1] = v.y;
+                        x[p][j + 2] = v.z;
+                        x[p][j + 3] = v.w;
+                    } else if constexpr (VW == 2) {
+                        const float2 v = *(const float2*)(xb + bo + 4 * j);
+                        x[p][j] = v.x;
+                        x[p][j + 1] = v.y;
+                    } else {
+                        x[p][j] = *(const float*)(xb + bo + 4 * j);
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                const uint32_t i = i0 + p * KC_LA_WPTS;
+                const uint32_t ii = i < len ? i : 0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) x[p][j] = coord(ii, j);
+            }
         }
     }
     __syncthreads();
@@ -685,13 +720,13 @@ static hipError_t launch_resident(uint32_t G, const float* xs, uint64_t stride,
                                   uint32_t first, int k,
                                   float* mind, u64* keys, u64* xbuf, uint32_t* abort_flag,
                                   uint32_t spin_limit, const float* xa, int64_t lda,
-                                  uint32_t* status, const KcSeg* segs, const uint4* blks,
-                                  hipStream_t s)
+                                  int xa_rows, uint32_t* status, const KcSeg* segs,
+                                  const uint4* blks, hipStream_t s)
 {
     void* args[] = {(void*)&xs,    (void*)&stride, (void*)&base, (void*)&len,
                     (void*)&len_ptr, (void*)&first, (void*)&k,      (void*)&mind, (void*)&keys,
                     (void*)&xbuf, (void*)&abort_flag, (void*)&spin_limit, (void*)&xa,
-                    (void*)&lda, (void*)&status, (void*)&segs, (void*)&blks};
+                    (void*)&lda, (void*)&xa_rows, (void*)&status, (void*)&segs, (void*)&blks};
     return hipLaunchCooperativeKernel((const void*)k_gon_resident<D, PPT>, dim3(G),
                                       dim3(KC_LA_BLOCK), args, 0, s);
 }
@@ -758,6 +793,18 @@ double kc_resident_launch_cycles(int d, int v, uint32_t k)
     return (double)k * step + ((double)k / 6.0) * 16800.0;
 }
 
+// Whether the kernel for dimension d can load its points straight from rows
+// xa of lda floats: its vector loads need the base and the row stride
+// aligned to their width, and byte offsets of up to `span` rows from a
+// segment's first row must fit 32 bits.
+bool kc_resident_rows_ok(int d, const float* xa, int64_t lda, uint64_t span)
+{
+    if (!xa || lda < d) return false;
+    const int vw = d % 4 == 0 ? 4 : d % 2 == 0 ? 2 : 1;   // the kernel's load width
+    if ((uintptr_t)xa % (uintptr_t)(4 * vw) != 0 || lda % vw != 0) return false;
+    return span * (uint64_t)lda * 4ull < (1ull << 32);
+}
+
 // Exchange buffer of the engine (two rounds), to be zero-filled before each
 // launch; independent of k and of the grid size.
 uint64_t kc_resident_slot_words(int k, uint32_t G)
@@ -773,15 +820,16 @@ hipError_t kc_gon_resident(int d, int v, uint32_t G, const float* xs, uint64_t s
                            uint64_t base, uint32_t len, const uint32_t* len_ptr,
                            uint32_t first, int k, float* mind,
                            u64* keys, u64* slots, uint32_t* abort_flag, uint32_t spin_limit,
-                           const float* xa, int64_t lda, uint32_t* status, const KcSeg* segs,
-                           const uint4* blks, hipStream_t s)
+                           const float* xa, int64_t lda, int xa_rows, uint32_t* status,
+                           const KcSeg* segs, const uint4* blks, hipStream_t s)
 {
     if (G == 0 || G > KC_LA_GMAX) return hipErrorInvalidValue;
+    if (xa_rows && !xa) return hipErrorInvalidValue;
 #define KC_CASE(DD, PP)                                                                  \
     case DD:                                                                             \
         return launch_resident<DD, PP>(G, xs, stride, base, len, len_ptr, first, k, mind, keys, \
-                                       slots, abort_flag, spin_limit, xa, lda, status, segs, \
-                                       blks, s);
+                                       slots, abort_flag, spin_limit, xa, lda, xa_rows,      \
+                                       status, segs, blks, s);
     if (v == 0) {
         switch (d) {
             KC_RES_DIMS(KC_CASE)

@@ -192,6 +192,29 @@ def test_mrg_resident_packing(kc, orc, cap, launches):
     h.close()
 
 
+@pytest.mark.parametrize("layout", ["wide", "odd", "shift"])
+def test_mrg_row_layouts(kc, orc, rows_layout, layout):
+    # strided and misaligned rows: round 1 loads the partitions straight from
+    # the rows where their layout allows, else from the staging copy
+    X = int_points(40_000, 16, 11)
+    off = W.partition_offsets(40_000, 9, 0.5, seed=11)
+    k = 18
+    h = kc.Handle()
+    h.set_option("timing", 1)
+    Xd = rows_layout(X, layout)
+    c, nc, r, ex = on_stream(lambda: kc.mrg(Xd, off, k, handle=h, details=True))
+    assert h.device_status() == 0
+    _, la, _ = h.timing_read("mrg_round1")
+    assert la >= 1
+    o = orc.mrg(X, off, k)
+    m = len(off) - 1
+    assert np.array_equal(ex["round1"].cpu().numpy().reshape(m, k), o["round1"])
+    assert np.array_equal(ex["r1"].cpu().numpy(), o["r1"])
+    assert np.array_equal(c.cpu().numpy(), o["centers"])
+    assert float(r.item()) == o["radius"]
+    h.close()
+
+
 def check_mrg_float(orc, X, off, k, g):
     # every partition's round-1 sequence is a certified farthest-first run
     b = band(X.shape[1])

@@ -134,6 +134,29 @@ def test_resident_large_variant(kc, orc, n, cap):
     h.close()
 
 
+@pytest.mark.parametrize("d", [3, 10, 16])
+@pytest.mark.parametrize("layout", ["dense", "wide", "odd", "shift"])
+def test_resident_row_layouts(kc, orc, rows_layout, d, layout):
+    # integer coordinates: centers and trace bit-exact against the oracle;
+    # several tiles per block and a ragged tail
+    rng = np.random.default_rng(7 * d + len(layout))
+    n = 50_037
+    X = rng.integers(-20, 21, (n, d)).astype(np.float32)
+    k = 48
+    h = kc.Handle()
+    h.set_option("timing", 1)
+    Xd = rows_layout(X, layout)
+    c, tr, nch = kc.gonzalez(Xd, k, 5, handle=h)
+    assert h.device_status() == 0
+    _, la, _ = h.timing_read("gon_resident")
+    assert la == 1
+    oc, otr, og = orc.gon(X, k, 5)
+    assert int(nch.item()) == og
+    assert np.array_equal(c.cpu().numpy(), oc)
+    assert np.array_equal(tr.cpu().numpy(), otr)
+    h.close()
+
+
 def test_config2_prefix(kc):
     X = W.config2(200_000)
     c1, t1, _ = run_gon(kc, X, 100, 0)

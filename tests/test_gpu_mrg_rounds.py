@@ -60,6 +60,23 @@ def test_mrg_rounds_integer_exact(kc, orc, n, k, c, resident):
     assert r == o["radius"]
 
 
+@pytest.mark.parametrize("layout", ["wide", "shift"])
+def test_mrg_rounds_row_layouts(kc, orc, rows_layout, layout):
+    # the first pass reads the caller's (strided or misaligned) rows
+    X = int_points(60_000, 10, 13)
+    k, c = 30, 4_000
+    h = kc.Handle()
+    Xd = rows_layout(X, layout)
+    cen, nc, r, rounds = kc.mrg_rounds(Xd, k, c, handle=h)
+    torch.cuda.synchronize()
+    assert h.device_status() == 0
+    o = orc.mrg_rounds(X, k, c)
+    assert int(nc.item()) == o["n_centers"] and rounds == o["rounds"]
+    assert np.array_equal(cen.cpu().numpy()[:o["n_centers"]], o["centers"][:o["n_centers"]])
+    assert float(r.item()) == o["radius"]
+    h.close()
+
+
 def test_mrg_rounds_no_progress(kc, orc):
     # blocks of at most 40 points and k = 50: a pass keeps every point
     X = int_points(5_000, 4, 3)
