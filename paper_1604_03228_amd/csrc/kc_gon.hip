@@ -321,6 +321,93 @@ void kc_gon_step(const float* xs, uint64_t stride, int d, float* mind, u64* part
 // finishing: per segment n_chosen, centers, center coordinates, FP64 trace
 // and exact FP64 radius.
 
+// The finishing kernels are latency-bound (a few hundred waves): every copy
+// keeps eight loads in flight, and every FP64 minimum runs two independent
+// chains per lane.
+
+// dst[j] = src(j) for the d coordinates of one point.
+template <class F>
+__device__ __forceinline__ void kc_copy_coords(float* __restrict__ dst, int d, F src)
+{
+    for (int j0 = 0; j0 < d; j0 += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = j0 + u < d ? src(j0 + u) : 0.f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (j0 + u < d) dst[j0 + u] = v[u];
+    }
+}
+
+// sC[e] = C[e] for e < N, by the whole block.
+__device__ __forceinline__ void kc_fill_lds(float* sC, const float* __restrict__ C, uint32_t N)
+{
+    for (uint32_t e0 = threadIdx.x; e0 < N; e0 += 8 * blockDim.x) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t e = e0 + u * blockDim.x;
+            v[u] = e < N ? C[e] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t e = e0 + u * blockDim.x;
+            if (e < N) sC[e] = v[u];
+        }
+    }
+}
+
+// Wave minimum over rows j < nc of C (d floats each) of the FP64 squared
+// distance from point P: lane l takes rows l, l+64, ..., two rows per pass.
+// Each distance sums separately rounded squares in coordinate order.
+__device__ __forceinline__ double kc_min_d64(const float* P, const float* C, int64_t nc, int d)
+{
+    const int lane = threadIdx.x & 63;
+    double best = __builtin_inf();
+    for (int64_t j = lane; j < nc; j += 128) {
+        const bool two = j + 64 < nc;
+        const float* c0 = C + (uint64_t)j * d;
+        const float* c1 = two ? c0 + 64ull * (uint64_t)d : c0;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll 4
+        for (int u = 0; u < d; ++u) {
+            const double x = (double)P[u];
+            s0 = kc_d64_step(s0, x, (double)c0[u]);
+            s1 = kc_d64_step(s1, x, (double)c1[u]);
+        }
+        best = fmin(best, s0);
+        if (two) best = fmin(best, s1);
+    }
+    return kc_wave_min_f64(best);
+}
+
+// The calling wave copies point `loc` of segment sg (rows xa of lda floats
+// from the segment's src, else the SoA copy xs) into P; then P is readable
+// by every lane of the wave.
+__device__ __forceinline__ void kc_wave_point(float* P, const KcSeg& sg, uint32_t loc,
+                                              const float* __restrict__ xs, uint64_t stride,
+                                              int d, const float* __restrict__ xa, int64_t lda)
+{
+    const int lane = threadIdx.x & 63;
+    float v[KC_MAXD / 64];
+#pragma unroll
+    for (int q = 0; q < KC_MAXD / 64; ++q) {
+        const int u = q * 64 + lane;
+        v[q] = u >= d ? 0.f
+                      : xa ? xa[(sg.src + loc) * (uint64_t)lda + u]
+                           : xs[(uint64_t)u * stride + sg.base + loc];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int q = 0; q < KC_MAXD / 64; ++q)
+        if (q * 64 + lane < d) P[q * 64 + lane] = v[q];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // n_chosen of a segment = 1 + the first step whose key reached radius 0, else
 // ksteps (0 for an empty segment): initialised per segment, then lowered by
 // one thread per (segment, step).  Also clears the exact-radius accumulators.
@@ -401,9 +488,9 @@ __global__ void k_gon_gather_centers(const KcSeg* __restrict__ segs,
     float* dst = ccoord + (uint64_t)(sg.keyoff + t) * d;
     if (xa) {
         const float* row = xa + (sg.src + c) * (uint64_t)lda;
-        for (int j = 0; j < d; ++j) dst[j] = row[j];
+        kc_copy_coords(dst, d, [&](int j) { return row[j]; });
     } else {
-        for (int j = 0; j < d; ++j) dst[j] = xs[(uint64_t)j * stride + sg.base + c];
+        kc_copy_coords(dst, d, [&](int j) { return xs[(uint64_t)j * stride + sg.base + c]; });
     }
 }
 
@@ -420,16 +507,8 @@ __device__ __forceinline__ void kc_trace_wave(const KcSeg& sg, uint32_t t, int64
         if ((int64_t)t >= nch && lane == 0) trace[sg.keyoff + t] = 0.0;
         return;
     }
-    const float* a = ccoord + (uint64_t)(sg.keyoff + t + 1) * d;
-    double best = __builtin_inf();
-#pragma unroll 4
-    for (uint32_t j = lane; j <= t; j += 64) {
-        const float* cj = ccoord + (uint64_t)(sg.keyoff + j) * d;
-        double s = 0.0;
-        for (int u = 0; u < d; ++u) s = kc_d64_step(s, (double)a[u], (double)cj[u]);
-        best = fmin(best, s);
-    }
-    best = kc_wave_min_f64(best);
+    const float* C = ccoord + (uint64_t)sg.keyoff * d;
+    const double best = kc_min_d64(C + (uint64_t)(t + 1) * d, C, (int64_t)t + 1, d);
     if (lane == 0) trace[sg.keyoff + t] = kc_sqrt_rn(best);
 }
 
@@ -524,9 +603,9 @@ __global__ __launch_bounds__(256) void k_gon_fin1_head(
         float* dst = ccoord + (uint64_t)(sg.keyoff + t) * d;
         if (xa) {
             const float* row = xa + (sg.src + c) * (uint64_t)lda;
-            for (int j = 0; j < d; ++j) dst[j] = row[j];
+            kc_copy_coords(dst, d, [&](int j) { return row[j]; });
         } else {
-            for (int j = 0; j < d; ++j) dst[j] = xs[(uint64_t)j * stride + sg.base + c];
+            kc_copy_coords(dst, d, [&](int j) { return xs[(uint64_t)j * stride + sg.base + c]; });
         }
     }
     centers[sg.keyoff + t] = v;
@@ -543,15 +622,7 @@ __device__ __forceinline__ void kc_trace_wave_c(uint32_t t, int64_t nch, int d,
         if ((int64_t)t >= nch && lane == 0) trace[t] = 0.0;
         return;
     }
-    const float* a = C + (uint64_t)(t + 1) * d;
-    double best = __builtin_inf();
-    for (uint32_t j = lane; j <= t; j += 64) {
-        const float* cj = C + (uint64_t)j * d;
-        double s = 0.0;
-        for (int u = 0; u < d; ++u) s = kc_d64_step(s, (double)a[u], (double)cj[u]);
-        best = fmin(best, s);
-    }
-    best = kc_wave_min_f64(best);
+    const double best = kc_min_d64(C + (uint64_t)(t + 1) * d, C, (int64_t)t + 1, d);
     if (lane == 0) trace[t] = kc_sqrt_rn(best);
 }
 
@@ -575,7 +646,7 @@ __global__ __launch_bounds__(KC_BLOCK) void k_gon_fin1_mid(
         if (use_lds) {
             // rows 0..t+1 of this block's last step
             const uint32_t rows = min((uint32_t)nch, (blockIdx.x + 1) * (KC_BLOCK / 64) + 1);
-            for (uint32_t e = threadIdx.x; e < rows * (uint32_t)d; e += KC_BLOCK) sC[e] = C[e];
+            kc_fill_lds(sC, C, rows * (uint32_t)d);
             __syncthreads();
             if (t < sg.ksteps) kc_trace_wave_c<true>(t, nch, d, sC, tr);
         } else if (t < sg.ksteps) {
@@ -599,6 +670,7 @@ __global__ __launch_bounds__(KC_BLOCK) void k_gon_fin1_rescore(
     double* __restrict__ radius_out)
 {
     extern __shared__ float sC[];
+    __shared__ float sP[KC_BLOCK / 64][KC_MAXD];   // each wave's candidate point
     __shared__ int s_last;
     const int lane = threadIdx.x & 63;
     const KcSeg sg = segs[0];
@@ -607,24 +679,15 @@ __global__ __launch_bounds__(KC_BLOCK) void k_gon_fin1_rescore(
     if (nc > cap) nc = cap;
     const float* C = ccoord + (uint64_t)sg.keyoff * d;
     if (use_lds && nc > blockIdx.x * (KC_BLOCK / 64)) {
-        for (uint32_t e = threadIdx.x; e < (uint32_t)nch * (uint32_t)d; e += KC_BLOCK) sC[e] = C[e];
+        kc_fill_lds(sC, C, (uint32_t)nch * (uint32_t)d);
         __syncthreads();
         C = sC;
     }
+    float* P = sP[threadIdx.x >> 6];
     const uint32_t waves = gridDim.x * (KC_BLOCK / 64);
     for (uint32_t q = blockIdx.x * (KC_BLOCK / 64) + (threadIdx.x >> 6); q < nc; q += waves) {
-        const uint32_t loc = (uint32_t)cand[q];
-        double best = __builtin_inf();
-        const float* row = xa ? xa + (sg.src + loc) * (uint64_t)lda : nullptr;
-        for (int64_t j = lane; j < nch; j += 64) {
-            const float* cj = C + (uint64_t)j * d;
-            double s = 0.0;
-            for (int u = 0; u < d; ++u)
-                s = kc_d64_step(s, (double)(row ? row[u] : xs[(uint64_t)u * stride + sg.base + loc]),
-                                (double)cj[u]);
-            best = fmin(best, s);
-        }
-        best = kc_wave_min_f64(best);
+        kc_wave_point(P, sg, (uint32_t)cand[q], xs, stride, d, xa, lda);
+        const double best = kc_min_d64(P, C, nch, d);
         if (lane == 0) kc_atomic_max_f64_nonneg(&radius2[0], best);
     }
     __syncthreads();
@@ -645,7 +708,7 @@ __global__ __launch_bounds__(KC_BLOCK) void k_gon_fin1_rescore(
 
 // One wave per candidate: exact FP64 min over the segment's chosen centers;
 // radius2[seg] = max over candidates (as bits of a non-negative double).
-__global__ void k_gon_radius_rescore(const KcSeg* __restrict__ segs,
+__global__ __launch_bounds__(KC_BLOCK) void k_gon_radius_rescore(const KcSeg* __restrict__ segs,
                                      const u64* __restrict__ cand,
                                      const uint32_t* __restrict__ ncand, uint32_t cap,
                                      const float* __restrict__ xs, uint64_t stride, int d,
@@ -654,28 +717,18 @@ __global__ void k_gon_radius_rescore(const KcSeg* __restrict__ segs,
                                      const float* __restrict__ ccoord,
                                      double* __restrict__ radius2)
 {
+    __shared__ float sP[KC_BLOCK / 64][KC_MAXD];   // each wave's candidate point
     const int lane = threadIdx.x & 63;
     uint32_t nc = *ncand;
     if (nc > cap) nc = cap;
-    const uint32_t waves = gridDim.x * (blockDim.x / 64);
-    for (uint32_t q = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); q < nc;
-         q += waves) {
+    float* P = sP[threadIdx.x >> 6];
+    const uint32_t waves = gridDim.x * (KC_BLOCK / 64);
+    for (uint32_t q = blockIdx.x * (KC_BLOCK / 64) + (threadIdx.x >> 6); q < nc; q += waves) {
         const u64 e = cand[q];
         const uint32_t sidx = (uint32_t)(e >> 32), loc = (uint32_t)e;
         const KcSeg sg = segs[sidx];
-        const int64_t nch = n_chosen[sidx];
-        double best = __builtin_inf();
-        const float* row = xa ? xa + (sg.src + loc) * (uint64_t)lda : nullptr;
-#pragma unroll 4
-        for (int64_t j = lane; j < nch; j += 64) {
-            const float* cj = ccoord + (uint64_t)(sg.keyoff + j) * d;
-            double s = 0.0;
-            for (int u = 0; u < d; ++u)
-                s = kc_d64_step(s, (double)(row ? row[u] : xs[(uint64_t)u * stride + sg.base + loc]),
-                                (double)cj[u]);
-            best = fmin(best, s);
-        }
-        best = kc_wave_min_f64(best);
+        kc_wave_point(P, sg, loc, xs, stride, d, xa, lda);
+        const double best = kc_min_d64(P, ccoord + (uint64_t)sg.keyoff * d, n_chosen[sidx], d);
         if (lane == 0) kc_atomic_max_f64_nonneg(&radius2[sidx], best);
     }
 }
