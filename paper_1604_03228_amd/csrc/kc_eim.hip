@@ -238,6 +238,39 @@ __global__ void k_eim_bounds(uint32_t nc, int d, const uint32_t* __restrict__ ca
     hi[x] = fminf(hi[x], (float)u * (1.f + 1e-6f));
 }
 
+// dst[r * d + j] = X[S[r] * ld + j] (converted to T) for r < cnt, j < d, by
+// the whole block: sixteen elements per thread and pass, the sample indices
+// first and then the coordinates, each group in flight together (an element
+// at a time would wait out two dependent memory latencies per element).
+template <typename T>
+__device__ __forceinline__ void kc_stage_samples(T* dst, const float* __restrict__ X, int64_t ld,
+                                                 int d, const uint32_t* __restrict__ S,
+                                                 uint32_t cnt)
+{
+    constexpr int V = 16;
+    const uint32_t tot = cnt * (uint32_t)d;
+    for (uint32_t e0 = threadIdx.x; e0 < tot; e0 += V * blockDim.x) {
+        uint32_t r[V], idx[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const uint32_t e = e0 + v * blockDim.x;
+            r[v] = e < tot ? e / (uint32_t)d : 0u;
+            idx[v] = e < tot ? S[r[v]] : 0u;
+        }
+        float val[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const uint32_t e = e0 + v * blockDim.x;
+            val[v] = e < tot ? X[(uint64_t)idx[v] * ld + (e - r[v] * (uint32_t)d)] : 0.f;
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const uint32_t e = e0 + v * blockDim.x;
+            if (e < tot) dst[e] = (T)val[v];
+        }
+    }
+}
+
 // For small d the canonical FP32 distance (one lane per pair, ascending
 // coordinates, relative error at most g = gamma_{d+2}) certifies far more
 // tightly than MFMA's |x|^2 + |c|^2 - 2x.c, whose error scales with the
@@ -266,10 +299,7 @@ __global__ __launch_bounds__(256) void k_eim_direct(const float* __restrict__ X,
     for (uint32_t i0 = 0; i0 < nds; i0 += KC_EIM_DIRECT_CHUNK) {
         const uint32_t cnt = min((uint32_t)KC_EIM_DIRECT_CHUNK, nds - i0);
         __syncthreads();
-        for (uint32_t e = threadIdx.x; e < cnt * D; e += blockDim.x) {
-            const uint32_t r = e / D, u = e - r * D;
-            sS[e] = X[(uint64_t)dS[i0 + r] * ld + u];
-        }
+        kc_stage_samples(sS, X, ld, D, dS + i0, cnt);
         __syncthreads();
         for (uint32_t r = 0; r < cnt; ++r) {
             float a = 0.f;
@@ -345,66 +375,79 @@ __global__ void k_eim_exact(const float* __restrict__ X, int64_t ld, int d,
     }
 }
 
-// The same exact pass, tiled: a block takes 64 undecided candidates (their
-// coordinates in LDS) and streams S through LDS in chunks of FP64 rows, so
-// each sample row is read from memory once per 64 candidates instead of once
-// per candidate.  Wave w of the block scores samples w, w+4, ... of a chunk
-// against the 64 candidates (one per lane; the sample row is a broadcast
-// read); the arithmetic is kc_d64_step's, so every value is the one the
-// per-candidate kernel computes.  For d <= KC_EXT_MAXD.
+// The same exact pass, tiled and split: block (x, y) takes undecided
+// candidates 64x .. 64x+63 (their coordinates in LDS) and slice y of S, which
+// it streams through LDS in chunks of FP64 rows, so each sample row is read
+// once per 64 candidates instead of once per candidate, and small candidate
+// counts still spread over the whole chip.  Wave w of the block scores
+// samples w, w+4, ... of a chunk against the 64 candidates (one per lane;
+// the sample row is a broadcast read); the arithmetic is kc_d64_step's, so
+// every value is the one the per-candidate kernel computes.  Each block's
+// minimum goes into exm[q] by an atomic minimum on the bits (non-negative
+// doubles order as integers); k_eim_exact_finish then decides.  For
+// d <= KC_EXT_MAXD.
 #define KC_EXT_MAXD 64
 #define KC_EXT_LDS (32 * 1024)   // bytes for the sample chunk
-__global__ __launch_bounds__(256) void k_eim_exact_tiled(
+__global__ __launch_bounds__(256) void k_eim_exact_split(
     const float* __restrict__ X, int64_t ld, int d, const uint32_t* __restrict__ cand,
-    const uint32_t* __restrict__ unsure, const uint32_t* __restrict__ nunsure,
-    const uint32_t* __restrict__ S, uint32_t ns, const double* __restrict__ tau,
-    uint8_t* __restrict__ keep, float* __restrict__ lo, float* __restrict__ hi)
+    const uint32_t* __restrict__ unsure, uint32_t nu, const uint32_t* __restrict__ S,
+    uint32_t ns, double* __restrict__ exm)
 {
     __shared__ float sC[64 * (KC_EXT_MAXD + 1)];           // candidates, row pitch d | 1
     __shared__ double sS[KC_EXT_LDS / sizeof(double)];      // sample chunk, row pitch d
     __shared__ double sB[4][64];
-    const uint32_t nu = *nunsure;
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t pitch = (uint32_t)d | 1u;
     const uint32_t chunk = (uint32_t)(KC_EXT_LDS / sizeof(double)) / (uint32_t)d;
-    for (uint32_t q0 = blockIdx.x * 64u; q0 < nu; q0 += gridDim.x * 64u) {
-        const uint32_t nq = min(64u, nu - q0);
+    const uint32_t q0 = blockIdx.x * 64u;
+    if (q0 >= nu) return;
+    const uint32_t nq = min(64u, nu - q0);
+    const uint32_t per = (ns + gridDim.y - 1) / gridDim.y;
+    const uint32_t s0 = min(ns, blockIdx.y * per), s1 = min(ns, s0 + per);
+    for (uint32_t e = threadIdx.x; e < nq * (uint32_t)d; e += blockDim.x) {
+        const uint32_t c = e / (uint32_t)d, j = e - c * (uint32_t)d;
+        sC[c * pitch + j] = X[(uint64_t)cand[unsure[q0 + c]] * ld + j];
+    }
+    double best = __builtin_inf();
+    for (uint32_t i0 = s0; i0 < s1; i0 += chunk) {
+        const uint32_t nsc = min(chunk, s1 - i0);
         __syncthreads();
-        for (uint32_t e = threadIdx.x; e < nq * (uint32_t)d; e += blockDim.x) {
-            const uint32_t c = e / (uint32_t)d, j = e - c * (uint32_t)d;
-            sC[c * pitch + j] = X[(uint64_t)cand[unsure[q0 + c]] * ld + j];
-        }
-        double best = __builtin_inf();
-        for (uint32_t i0 = 0; i0 < ns; i0 += chunk) {
-            const uint32_t nsc = min(chunk, ns - i0);
-            __syncthreads();
-            for (uint32_t e = threadIdx.x; e < nsc * (uint32_t)d; e += blockDim.x) {
-                const uint32_t r = e / (uint32_t)d, j = e - r * (uint32_t)d;
-                sS[r * d + j] = (double)X[(uint64_t)S[i0 + r] * ld + j];
-            }
-            __syncthreads();
-            if (lane < nq) {
-                const float* xc = sC + lane * pitch;
-                for (uint32_t r = wave; r < nsc; r += 4) {
-                    const double* sr = sS + r * d;
-                    double a = 0.0;
-                    for (int u = 0; u < d; ++u) a = kc_d64_step(a, (double)xc[u], sr[u]);
-                    best = fmin(best, a);
-                }
-            }
-        }
-        sB[wave][lane] = best;
+        kc_stage_samples(sS, X, ld, d, S + i0, nsc);
         __syncthreads();
-        if (threadIdx.x < nq) {
-            double b = fmin(fmin(sB[0][lane], sB[1][lane]), fmin(sB[2][lane], sB[3][lane]));
-            const uint32_t j = unsure[q0 + lane];
-            const uint32_t x = cand[j];
-            keep[j] = b > *tau;
-            // the exact value is its own interval from now on
-            lo[x] = (float)b * (1.f - 1e-6f);
-            hi[x] = (float)b * (1.f + 1e-6f);
+        if (lane < nq) {
+            const float* xc = sC + lane * pitch;
+            for (uint32_t r = wave; r < nsc; r += 4) {
+                const double* sr = sS + r * d;
+                double a = 0.0;
+                for (int u = 0; u < d; ++u) a = kc_d64_step(a, (double)xc[u], sr[u]);
+                best = fmin(best, a);
+            }
         }
     }
+    sB[wave][lane] = best;
+    __syncthreads();
+    if (threadIdx.x < nq) {
+        const double b = fmin(fmin(sB[0][lane], sB[1][lane]), fmin(sB[2][lane], sB[3][lane]));
+        if (b < __builtin_inf()) atomicMin((u64*)&exm[q0 + lane], (u64)__double_as_longlong(b));
+    }
+}
+
+// keep iff the exact d(x,S)^2 > tau; the exact value is its own interval
+// from now on
+__global__ void k_eim_exact_finish(const uint32_t* __restrict__ cand,
+                                   const uint32_t* __restrict__ unsure, uint32_t nu,
+                                   const double* __restrict__ exm,
+                                   const double* __restrict__ tau, uint8_t* __restrict__ keep,
+                                   float* __restrict__ lo, float* __restrict__ hi)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nu) return;
+    const double b = exm[q];
+    const uint32_t j = unsure[q];
+    const uint32_t x = cand[j];
+    keep[j] = b > *tau;
+    lo[x] = (float)b * (1.f - 1e-6f);
+    hi[x] = (float)b * (1.f + 1e-6f);
 }
 
 __global__ void k_mark(const uint32_t* __restrict__ idx, uint32_t n, uint8_t* __restrict__ f)
@@ -494,11 +537,12 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
     double* tau = (double*)h->ws("e.tau", 16);
     uint32_t* cnt = (uint32_t*)h->ws("e.cnt", 64);   // [0] dS [1] H [2] cand [3] R [4] unsure
     uint32_t* unsure = (uint32_t*)h->ws("e.uns", 4ull * n);
+    double* exm = (double*)h->ws("e.exm", 8ull * n);   // exact minima of the undecided
     KcCompact C;
     C.nb_cap = (n + KC_CMP_ITEMS - 1) / KC_CMP_ITEMS + 1;
     C.blk = (uint32_t*)h->ws("e.blk", 4ull * C.nb_cap);
     if (!R || !R2 || !S || !H || !cand || !fS || !fH || !fK || !keep || !lo || !hi || !dH ||
-        !tau || !cnt || !unsure || !C.blk)
+        !tau || !cnt || !unsure || !exm || !C.blk)
         return h->fail(KC_ENOMEM, "workspace allocation failed");
 
     h->eim_exact = 0;
@@ -590,12 +634,26 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
             kc_fill_u32(cnt + 4, 0u, 1, s);
             hipLaunchKernelGGL(k_eim_decide, g1(nc), dim3(256), 0, s, nc, cand, lo, hi, tau,
                                keep, unsure, cnt + 4);
-            if (d <= KC_EXT_MAXD)
-                hipLaunchKernelGGL(k_eim_exact_tiled, dim3(1024), dim3(256), 0, s, X, ld, d,
-                                   cand, unsure, cnt + 4, S, ns, tau, keep, lo, hi);
-            else
+            if (d <= KC_EXT_MAXD) {
+                // the undecided count sizes the split pass: candidate groups
+                // of 64 times slices of S, about 2048 blocks in all
+                uint32_t nu = 0;
+                rc = kc_read_u32(h, cnt + 4, &nu, s);
+                if (rc) return rc;
+                if (nu > 0) {
+                    const uint32_t gx = (nu + 63) / 64;
+                    const uint32_t gy = std::max<uint32_t>(
+                        1, std::min<uint32_t>({(2048 + gx - 1) / gx, ns / 512, 65535u}));
+                    kc_fill_u64((u64*)exm, 0x7FF0000000000000ull, nu, s);   // +inf
+                    hipLaunchKernelGGL(k_eim_exact_split, dim3(gx, gy), dim3(256), 0, s, X, ld,
+                                       d, cand, unsure, nu, S, ns, exm);
+                    hipLaunchKernelGGL(k_eim_exact_finish, g1(nu), dim3(256), 0, s, cand,
+                                       unsure, nu, exm, tau, keep, lo, hi);
+                }
+            } else {
                 hipLaunchKernelGGL(k_eim_exact, dim3(2048), dim3(256), 0, s, X, ld, d, cand,
                                    unsure, cnt + 4, S, ns, tau, keep, lo, hi);
+            }
             kc_compact(C, keep, cand, nc, R2, cnt + 3, s);
             std::swap(R, R2);
             uint32_t rc2[2];
