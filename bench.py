@@ -52,6 +52,10 @@ def parse():
     ap.add_argument("--eim-study", action="store_true",
                     help="EIM's runtime / solution trade-off over phi and k on "
                          "Gaussian data (n = 200,000, 25 clusters) and exit")
+    ap.add_argument("--quality-sweep", action="store_true",
+                    help="covering radius of MRG (m = 50), EIM (eps 0.1, "
+                         "phi 6) and Gonzalez over k on the Unif / Gau / UnB "
+                         "graph types and exit")
     ap.add_argument("--batch-only", action="store_true",
                     help="time kcenter_batch on the 256-instance mixed batch "
                          "(GON / MRG / EIM, d in {2, 8, 32}) and exit")
@@ -275,6 +279,61 @@ def eim_study(kc, torch, seeds=5):
             "seeds": seeds, "rows": rows}
 
 
+def quality_sweep(kc, torch, sets=3):
+    """The solution-value comparison of the paper's Tables 2-4 on seeded
+    stand-ins: for each graph type (Unif n = 100,000; Gau n = 1,000,000 and
+    UnB n = 200,000, 25 clusters) and k in {2, 5, 10, 25, 50, 100}, the mean
+    covering radius of MRG (m = 50 equal partitions), EIM (eps = 0.1,
+    phi = 6; two Philox seeds per data set) and Gonzalez (first center 0)
+    over `sets` data sets, with the wall time per call."""
+    import time
+    from paper_1604_03228_amd import workloads as W
+    ks = (2, 5, 10, 25, 50, 100)
+    h = kc.Handle()
+    out = {}
+    for kind in ("gau", "unif", "unb"):
+        acc = {}
+        for sd in range(sets):
+            X = W.quality_points(kind, 900 + sd)
+            n = len(X)
+            Xd = torch.from_numpy(X).cuda()
+            off = W.equal_offsets(n, 50)
+            for k in ks:
+                runs = [("gon", lambda: kc.gonzalez(Xd, k, 0, handle=h)),
+                        ("mrg", lambda: kc.mrg(Xd, off, k, handle=h))]
+                for e in range(2):
+                    runs.append(("eim", lambda e=e: kc.eim(
+                        Xd, k, 0.1, 6.0, 9 * 2**32 + 2 * sd + e,
+                        want_sample=False, handle=h)))
+                for name, fn in runs:
+                    fn()   # warm
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    r = fn()
+                    if name == "gon":
+                        rad = float(r[1][int(r[2].item()) - 1].item())
+                    else:
+                        rad = float(r[2].item())
+                    dt = (time.perf_counter() - t0) * 1e3
+                    a = acc.setdefault((k, name), [0.0, 0.0, 0])
+                    a[0] += rad
+                    a[1] += dt
+                    a[2] += 1
+        rows = []
+        for k in ks:
+            row = {"k": k}
+            for name in ("mrg", "eim", "gon"):
+                a = acc[(k, name)]
+                row[name] = a[0] / a[2]
+                row[name + "_ms"] = a[1] / a[2]
+            row["mrg_over_gon"] = row["mrg"] / row["gon"]
+            row["eim_over_gon"] = row["eim"] / row["gon"]
+            rows.append(row)
+        out[kind] = {"n": int(W.QUALITY_SETS[kind]), "sets": sets, "rows": rows}
+    h.close()
+    return out
+
+
 def bench_gon_bf16(kc, torch, steps):
     """Gonzalez k=500 on the 5,000,000 x 41 mixed-scale workload, FP32 vs
     BF16 stream + exact FP32 rescoring (same centers required)."""
@@ -329,6 +388,9 @@ def main():
 
     if a.eim_study:
         print(json.dumps({"eim_study": eim_study(kc, torch)}))
+        return
+    if a.quality_sweep:
+        print(json.dumps({"quality": quality_sweep(kc, torch)}))
         return
     if a.batch_only:
         print(json.dumps({"batch": bench_batch(kc, torch, max(2, a.steps))}))

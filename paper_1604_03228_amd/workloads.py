@@ -128,6 +128,31 @@ def config1(n=20000):
     return points_uniform(n, 2, seed=1)
 
 
+# The three synthetic graph types of the paper's comparison (Section 8.1,
+# Tables 2-4), 2-D, at the scale the printed radii imply: Unif uniform in
+# [0, 100)^2; Gau 25 clusters with centers uniform in [0, 100]^2 and
+# sigma 0.1, points spread evenly; UnB the same with about half the points
+# in cluster 0.
+QUALITY_SETS = {"unif": 100_000, "gau": 1_000_000, "unb": 200_000}
+
+
+def quality_points(kind, seed, n=None):
+    """One data set of graph type `kind` ('unif', 'gau', 'unb'); n defaults
+    to the paper's size for that type."""
+    n = QUALITY_SETS[kind] if n is None else n
+    if kind == "unif":
+        rng = np.random.default_rng(seed)
+        return (rng.random((n, 2)) * 100.0).astype(np.float32)
+    heavy = 0.5 if kind == "unb" else None
+    return points_gauss_mixture(n, 2, 25, 0.0, 100.0, 0.1, 0.1, seed=seed, heavy=heavy)
+
+
+def equal_offsets(n, m):
+    """Offsets [m+1] of m contiguous partitions of sizes differing by at most
+    one (the points are i.i.d., so contiguous blocks are random subsets)."""
+    return np.array([p * n // m for p in range(m + 1)], np.int64)
+
+
 def config2(n=1_000_000):
     return points_int_grid(n, seed=2)
 
