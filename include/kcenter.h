@@ -88,7 +88,8 @@ int kc_set_option(kc_handle* h, const char* name, int64_t value);
  * "gon_step" (k streaming step launches), "gon_bf16" (BF16 stream steps),
  * "mrg_round1" (MRG first round: its persistent launches, or its
  * streaming step launches), "mrg_rounds" (each round of kcenter_mrg_rounds), "assign_mfma" (the MFMA
- * distance kernel of an assignment), "eim_dist" (EIM distance passes).
+ * distance kernel of an assignment), "assign_direct" (a radius-only assignment at d <= 8: canonical
+ * FP32 distances, candidate listing and the exact FP64 pass), "eim_dist" (EIM distance passes).
  * kc_timing_read synchronises the device, returns the summed milliseconds,
  * the number of kernel launches those intervals cover and the number of
  * intervals, for one name, and forgets them.  KC_EINVAL for NULL args. */
@@ -191,7 +192,9 @@ int kcenter_mrg_rounds(kc_handle* h, const kc_points* pts, int64_t k, int64_t ca
  * as |x|^2 + |c|^2 - 2 x.c on MFMA (FP32, or BF16 when pts->prec is
  * KC_BF16_RESCORE); every point whose nearest center is not certified by the
  * a-priori error bound, and every point that may attain the maximum, is
- * rescored exactly in FP64.
+ * rescored exactly in FP64.  With labels NULL, FP32 points and d <= 8 the
+ * distances are instead the canonical FP32 ones (relative error at most
+ * gamma_{d+2}), whose tighter bound leaves fewer points to rescore.
  *   centers  device int64 [k], point indices, 1 <= k <= 4096.
  *   labels   device int32 [n] or NULL: position in centers of the nearest.
  *   radius   device double [1]: exact FP64 covering radius.

@@ -439,6 +439,79 @@ __global__ void k_rescore_f64(const float* __restrict__ X, int64_t ld, int d,
     }
 }
 
+// Covering radius only, small d: the canonical FP32 distance to every
+// center (one lane per point, coordinates in VGPRs, the centers streamed
+// through LDS).  Its relative error is at most g = gamma_{d+2}, so the
+// exact min-distance lies in [m / (1 + g), m / (1 - g)] around the smallest
+// FP32 value m (widened for rounding and for squares that underflow): far
+// tighter than the MFMA bound, whose error scales with the norms, so only
+// a handful of points reach the largest lower bound and go to the exact
+// FP64 pass.  Writes hi_out[p] and the maximum lower bound into lo_max.
+#define KC_RD_MAXD 8
+#define KC_RD_CHUNK 1024
+template <int D>
+__global__ __launch_bounds__(256) void k_radius_direct(const float* __restrict__ X, int64_t ld,
+                                                       uint32_t n, const float* __restrict__ Cf,
+                                                       int dp, uint32_t k,
+                                                       const int64_t* __restrict__ k_dev,
+                                                       double g, float* __restrict__ hi_out,
+                                                       float* __restrict__ lo_max)
+{
+    __shared__ float sC[KC_RD_CHUNK * D];
+    __shared__ float red[4];
+    if (k_dev && (int64_t)k > *k_dev) k = (uint32_t)(*k_dev < 0 ? 0 : *k_dev);
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = p < n;
+    float xc[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) xc[u] = live ? X[(uint64_t)p * ld + u] : 0.f;
+    float m = __builtin_inff();
+    for (uint32_t j0 = 0; j0 < k; j0 += KC_RD_CHUNK) {
+        const uint32_t cnt = min((uint32_t)KC_RD_CHUNK, k - j0);
+        __syncthreads();
+        for (uint32_t e0 = threadIdx.x; e0 < cnt * D; e0 += 8 * blockDim.x) {
+            float v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t e = e0 + q * blockDim.x, r = e / D, u = e - r * D;
+                v[q] = e < cnt * D ? Cf[(uint64_t)(j0 + r) * dp + u] : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t e = e0 + q * blockDim.x;
+                if (e < cnt * D) sC[e] = v[q];
+            }
+        }
+        __syncthreads();
+        for (uint32_t r = 0; r < cnt; ++r) {
+            float a = 0.f;
+#pragma unroll
+            for (int u = 0; u < D; ++u) a = kc_d32_step(a, xc[u], sC[r * D + u]);
+            m = fminf(m, a);
+        }
+    }
+    float lo_f = 0.f;
+    if (live) {
+        const double mv = (double)m;
+        double l = mv / (1.0 + g) - 1e-37 * D;
+        if (l < 0.0) l = 0.0;
+        const double u = mv / (1.0 - g) + 1e-37 * D;
+        hi_out[p] = (float)u * (1.f + 1e-6f);
+        lo_f = (float)l * (1.f - 1e-6f);
+    }
+    float v = lo_f;
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float r = red[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmaxf(r, red[w]);
+        const float cur = __uint_as_float(__hip_atomic_load(
+            (const uint32_t*)lo_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (r > cur) kc_atomic_max_f32_nonneg(lo_max, r);
+    }
+}
+
 __global__ void k_sqrt_out(const double* __restrict__ r2, double* __restrict__ out)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *out = kc_sqrt_rn(*r2);
@@ -538,6 +611,41 @@ void kc_bf16_err(const float* X, const uint16_t* Xb, int64_t ld, int d, uint32_t
                  hipStream_t s)
 {
     hipLaunchKernelGGL(k_bf16_err, dim3((n + 255) / 256), dim3(256), 0, s, X, Xb, ld, d, n, ex);
+}
+
+bool kc_radius_direct(uint32_t n, int d, const float* X, int64_t ld, const float* Cf, int dp,
+                      uint32_t k, const int64_t* k_dev, float* hi, uint32_t* list,
+                      uint32_t* nlist, float* lo_max, double* radius2, double* radius_out,
+                      hipStream_t s)
+{
+    if (d < 1 || d > KC_RD_MAXD) return false;
+    const double u32 = 5.9604644775390625e-8, m = d + 2;
+    const double g = m * u32 / (1.0 - m * u32);
+    kc_fill_u32(nlist, 0u, 1, s);
+    kc_fill_u32((uint32_t*)lo_max, 0u, 1, s);
+    kc_fill_u64((u64*)radius2, 0ull, 1, s);
+    const dim3 gr((n + 255) / 256);
+    switch (d) {
+#define KC_RD_CASE(DD)                                                                      \
+    case DD:                                                                                \
+        hipLaunchKernelGGL(k_radius_direct<DD>, gr, dim3(256), 0, s, X, ld, n, Cf, dp, k,    \
+                           k_dev, g, hi, lo_max);                                           \
+        break;
+        KC_RD_CASE(1)
+        KC_RD_CASE(2)
+        KC_RD_CASE(3)
+        KC_RD_CASE(4)
+        KC_RD_CASE(5)
+        KC_RD_CASE(6)
+        KC_RD_CASE(7)
+        KC_RD_CASE(8)
+#undef KC_RD_CASE
+    }
+    hipLaunchKernelGGL(k_radius_candidates, gr, dim3(256), 0, s, n, hi, lo_max, list, nlist);
+    hipLaunchKernelGGL(k_rescore_f64, dim3(2048), dim3(256), 0, s, X, ld, d, Cf, dp, k, k_dev,
+                       list, nlist, 2 * n, nullptr, radius2);
+    hipLaunchKernelGGL(k_sqrt_out, dim3(1), dim3(64), 0, s, radius2, radius_out);
+    return true;
 }
 
 void kc_assign_finish(uint32_t n, int d, const float* X, int64_t ld, const float* Cf, int dp,

@@ -136,6 +136,14 @@ void kc_stage_centers(const float* X, const uint16_t* Xb, int64_t ld, int d, uin
                       float* cnorm, float* cmax, uint32_t* status, hipStream_t s);
 void kc_bf16_err(const float* X, const uint16_t* Xb, int64_t ld, int d, uint32_t n, float* ex,
                  hipStream_t s);
+// Covering radius only (no labels), FP32 points, d <= 8: canonical FP32
+// distances to the staged centers Cf (rows of dp floats), then the exact
+// FP64 pass over the points that may attain the radius.  Returns false
+// (nothing enqueued) for other d.
+bool kc_radius_direct(uint32_t n, int d, const float* X, int64_t ld, const float* Cf, int dp,
+                      uint32_t k, const int64_t* k_dev, float* hi, uint32_t* list,
+                      uint32_t* nlist, float* lo_max, double* radius2, double* radius_out,
+                      hipStream_t s);
 void kc_assign_finish(uint32_t n, int d, const float* X, int64_t ld, const float* Cf, int dp,
                       uint32_t k, const int64_t* k_dev, const int32_t* arg, const float* m1,
                       const float* m2, const float* nx, const float* ex, const float* cmax,

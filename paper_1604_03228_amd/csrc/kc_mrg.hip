@@ -203,6 +203,17 @@ int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, ui
                          k_dev, kpad, dp, Cf, Cb, cnorm, cmax, h->status_word, st);
     });
     if (rc) return rc;
+    if (!labels && !bf && d <= 8) {
+        // radius only at small d: canonical FP32 distances bound each
+        // point's min-distance tightly, so few points need FP64
+        hipEvent_t ev = h->span_begin(s);
+        rc = h->run_graph(key + ":direct", s, [&](hipStream_t st) {
+            kc_radius_direct(n, d, pts->f32, pts->ld, Cf, dp, k, k_dev, hi, list, nlist, lo_max,
+                             r2, radius, st);
+        });
+        h->span_end("assign_direct", ev, 1, s);
+        return rc;
+    }
     hipEvent_t ev = h->span_begin(s);
     rc = h->run_graph(key + ":mfma", s, [&](hipStream_t st) {
         // without labels only the smallest value per point is needed

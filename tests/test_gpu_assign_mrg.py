@@ -82,6 +82,40 @@ def test_assign_radius_equals_gon(kc, orc):
     assert R == tr[-1]
 
 
+# Radius only (no labels): at d <= 8 the canonical FP32 distances bound each
+# point's min-distance tightly (the direct pass); above, the MFMA bound.
+# Data far from the origin with small clusters makes the MFMA bound loose;
+# k = 1500 spans two chunks of the direct pass's staged centers.
+@pytest.mark.parametrize("d", [1, 2, 5, 8, 16])
+@pytest.mark.parametrize("k", [1, 7, 200, 1500])
+def test_radius_only_far_from_origin(kc, orc, d, k):
+    X = W.points_gauss_mixture(20_011, d, 25, 0.0, 100.0, 0.1, 0.1, seed=31 + d)
+    C = np.random.default_rng(k + d).choice(len(X), k, replace=False)
+    h = kc.Handle()
+    h.set_option("timing", 1)
+    Xd = torch.from_numpy(X).cuda()
+    lab, r = on_stream(lambda: kc.assign(Xd, torch.from_numpy(C), labels=False, handle=h))
+    assert lab is None and h.device_status() == 0
+    _, la, _ = h.timing_read("assign_direct")
+    assert la == (1 if d <= 8 else 0)
+    _, oR = orc.assign(X, C)
+    assert float(r.item()) == oR
+
+
+def test_mrg_fewer_centers_than_k_small_d(kc, orc):
+    # 13 distinct points, repeated: fewer than k centers exist, and the
+    # covering radius (direct pass, d = 2) sees the device-side center count
+    base = np.random.default_rng(8).integers(0, 50, (13, 2)).astype(np.float32)
+    X = np.repeat(base, 500, axis=0)[np.random.default_rng(9).permutation(6500)]
+    off = W.partition_offsets(len(X), 5, 0.5, seed=9)
+    k = 20
+    g = gpu_mrg(kc, X, off, k)
+    o = orc.mrg(X, off, k)
+    assert g["n_centers"] == 13
+    assert np.array_equal(g["centers"], o["centers"])
+    assert g["radius"] == o["radius"] == 0.0
+
+
 def test_assign_bad_center_is_reported(kc):
     h = kc.Handle()
     X = np.random.default_rng(3).random((1000, 3)).astype(np.float32)
