@@ -432,7 +432,53 @@ __global__ __launch_bounds__(256) void k_eim_exact_split(
     }
 }
 
-// keep iff the exact d(x,S)^2 > tau; the exact value is its own interval
+// The same split pass for a dimension known at compile time: each lane
+// holds its candidate's coordinates as doubles in VGPRs, so a pair costs a
+// broadcast LDS read and three FP64 operations per coordinate (no per-pair
+// conversion or candidate read); the values are kc_d64_step's, as above.
+template <int D>
+__global__ __launch_bounds__(256) void k_eim_exact_split_d(
+    const float* __restrict__ X, int64_t ld, const uint32_t* __restrict__ cand,
+    const uint32_t* __restrict__ unsure, uint32_t nu, const uint32_t* __restrict__ S,
+    uint32_t ns, double* __restrict__ exm)
+{
+    constexpr uint32_t CH = (uint32_t)(KC_EXT_LDS / sizeof(double)) / D;   // samples per chunk
+    __shared__ double sS[CH * D];
+    __shared__ double sB[4][64];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t q0 = blockIdx.x * 64u;
+    if (q0 >= nu) return;
+    const uint32_t nq = min(64u, nu - q0);
+    const uint32_t per = (ns + gridDim.y - 1) / gridDim.y;
+    const uint32_t s0 = min(ns, blockIdx.y * per), s1 = min(ns, s0 + per);
+    const bool live = lane < nq;
+    const uint32_t x = live ? cand[unsure[q0 + lane]] : 0u;
+    double xd[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) xd[u] = (double)(live ? X[(uint64_t)x * ld + u] : 0.f);
+    double best = __builtin_inf();
+    for (uint32_t i0 = s0; i0 < s1; i0 += CH) {
+        const uint32_t nsc = min(CH, s1 - i0);
+        __syncthreads();
+        kc_stage_samples(sS, X, ld, D, S + i0, nsc);
+        __syncthreads();
+        for (uint32_t r = wave; r < nsc; r += 4) {
+            const double* sr = sS + r * D;
+            double a = 0.0;
+#pragma unroll
+            for (int u = 0; u < D; ++u) a = kc_d64_step(a, xd[u], sr[u]);
+            best = fmin(best, a);
+        }
+    }
+    sB[wave][lane] = best;
+    __syncthreads();
+    if (threadIdx.x < nq) {
+        const double b = fmin(fmin(sB[0][lane], sB[1][lane]), fmin(sB[2][lane], sB[3][lane]));
+        if (b < __builtin_inf()) atomicMin((u64*)&exm[q0 + lane], (u64)__double_as_longlong(b));
+    }
+}
+
+// keep iff the exact d(x,S)^2 > tau; the exact value is its own interval// keep iff the exact d(x,S)^2 > tau; the exact value is its own interval
 // from now on
 __global__ void k_eim_exact_finish(const uint32_t* __restrict__ cand,
                                    const uint32_t* __restrict__ unsure, uint32_t nu,
@@ -645,8 +691,20 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
                     const uint32_t gy = std::max<uint32_t>(
                         1, std::min<uint32_t>({(2048 + gx - 1) / gx, ns / 512, 65535u}));
                     kc_fill_u64((u64*)exm, 0x7FF0000000000000ull, nu, s);   // +inf
-                    hipLaunchKernelGGL(k_eim_exact_split, dim3(gx, gy), dim3(256), 0, s, X, ld,
-                                       d, cand, unsure, nu, S, ns, exm);
+                    switch (d) {
+#define KC_EXS_CASE(DD)                                                                     \
+    case DD:                                                                                \
+        hipLaunchKernelGGL(k_eim_exact_split_d<DD>, dim3(gx, gy), dim3(256), 0, s, X, ld, cand, \
+                           unsure, nu, S, ns, exm);                                         \
+        break;
+                        KC_EXS_CASE(10)
+                        KC_EXS_CASE(16)
+                        KC_EXS_CASE(32)
+#undef KC_EXS_CASE
+                    default:
+                        hipLaunchKernelGGL(k_eim_exact_split, dim3(gx, gy), dim3(256), 0, s, X,
+                                           ld, d, cand, unsure, nu, S, ns, exm);
+                    }
                     hipLaunchKernelGGL(k_eim_exact_finish, g1(nu), dim3(256), 0, s, cand,
                                        unsure, nu, exm, tau, keep, lo, hi);
                 }
