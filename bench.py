@@ -375,7 +375,7 @@ def bench_gon_bf16(kc, torch, steps):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py: this build measures one GPU only (the hot path runs "
+        print("bench.py: measures one GPU only (the hot path runs "
               "on a single MI355X); --gpus %d is not supported" % a.gpus,
               file=sys.stderr)
         sys.exit(2)

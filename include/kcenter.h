@@ -45,7 +45,7 @@ typedef enum {
     KC_ENOMEM = -2,        /* workspace allocation failed                   */
     KC_EHIP = -3,          /* a HIP runtime call failed                     */
     KC_ENOCONV = -4,       /* EIM did not converge; an MRG pass kept all    */
-    KC_EUNSUPPORTED = -6,  /* valid request this build cannot serve         */
+    KC_EUNSUPPORTED = -6,  /* valid request this library cannot serve       */
     KC_EDEVICE = -7        /* a device-side check failed (see kc_device_status) */
 } kc_status;
 
