@@ -195,7 +195,8 @@ int kcenter_mrg_rounds(kc_handle* h, const kc_points* pts, int64_t k, int64_t ca
  * rescored exactly in FP64.  With labels NULL, FP32 points and d <= 8 the
  * distances are instead the canonical FP32 ones (relative error at most
  * gamma_{d+2}), whose tighter bound leaves fewer points to rescore.
- *   centers  device int64 [k], point indices, 1 <= k <= 4096.
+ *   centers  device int64 [k], point indices, 1 <= k < 2^24 (streamed
+ *            through LDS in chunks, so k is limited only by that check).
  *   labels   device int32 [n] or NULL: position in centers of the nearest.
  *   radius   device double [1]: exact FP64 covering radius.
  */
