@@ -102,6 +102,23 @@ def test_radius_only_far_from_origin(kc, orc, d, k):
     assert float(r.item()) == oR
 
 
+# more centers than one LDS chunk holds, in both passes and with labels
+@pytest.mark.parametrize("d", [2, 16])
+@pytest.mark.parametrize("labels", [True, False])
+def test_assign_many_centers(kc, orc, d, labels):
+    rng = np.random.default_rng(50 + d)
+    X = (rng.normal(size=(20_000, d)) * 10.0).astype(np.float32)
+    C = rng.choice(len(X), 5_000, replace=False)
+    h = kc.Handle()
+    Xd = torch.from_numpy(X).cuda()
+    lab, r = on_stream(lambda: kc.assign(Xd, torch.from_numpy(C), labels=labels, handle=h))
+    assert h.device_status() == 0
+    olab, oR = orc.assign(X, C)
+    assert float(r.item()) == oR
+    if labels:
+        assert np.array_equal(lab.cpu().numpy(), olab)
+
+
 def test_mrg_fewer_centers_than_k_small_d(kc, orc):
     # 13 distinct points, repeated: fewer than k centers exist, and the
     # covering radius (direct pass, d = 2) sees the device-side center count
