@@ -62,7 +62,10 @@ def lib():
                               _i64, _p, _p, _p, _p, _p, _p, _p]
         L.orc_mrg.restype = _f64
         L.orc_mrg_rounds.argtypes = [_p, _i64, ctypes.c_int, _i64, _i64, _i64,
-                                     _p, _p, _p]
+                                     _p, _p, _p, _p, _p]
+        L.orc_gon_resume.argtypes = [_p, _i64, ctypes.c_int, _i64, _i64, _p,
+                                     _i64, _p, _p]
+        L.orc_gon_resume.restype = _i64
         L.orc_mrg_rounds.restype = _f64
         L.orc_philox4x64_10.argtypes = [_p, _p, _p]
         L.orc_philox4x64_10.restype = None
@@ -159,15 +162,33 @@ def mrg(X, offsets, k):
 
 
 def mrg_rounds(X, k, capacity):
-    """Multi-round MRG (Algorithm 1 with its loop, Lemma 3)."""
+    """Multi-round MRG (Algorithm 1 with its loop, Lemma 3).  `sample` is the
+    set S the last round runs on."""
     X, n, d = _pts(X)
     centers = np.full(k, -1, np.int64)
     nc = ctypes.c_int64(0)
     rounds = ctypes.c_int(0)
+    s_out = np.zeros(n, np.int64)
+    ns = ctypes.c_int64(0)
     R = lib().orc_mrg_rounds(_ptr(X), n, d, d, k, capacity, _ptr(centers),
-                             ctypes.byref(nc), ctypes.byref(rounds))
+                             ctypes.byref(nc), ctypes.byref(rounds),
+                             _ptr(s_out), ctypes.byref(ns))
     return dict(centers=centers, n_centers=int(nc.value), radius=R,
-                rounds=rounds.value)
+                rounds=rounds.value, sample=s_out[:ns.value].copy())
+
+
+def gon_resume(X, k, prefix):
+    """Gonzalez with centers 0..p-1 forced to `prefix`, then continued to k.
+    Returns (centers[k], trace[k], n_chosen); raises on an invalid prefix."""
+    X, n, d = _pts(X)
+    prefix = np.ascontiguousarray(prefix, dtype=np.int64)
+    centers = np.full(k, -1, np.int64)
+    trace = np.zeros(k, np.float64)
+    got = lib().orc_gon_resume(_ptr(X), n, d, d, k, _ptr(prefix), len(prefix),
+                               _ptr(centers), _ptr(trace))
+    if got < 0:
+        raise ValueError("oracle gon_resume: invalid prefix")
+    return centers, trace, int(got)
 
 
 def philox4x64_10(ctr, key):

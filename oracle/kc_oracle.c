@@ -23,6 +23,11 @@
  *   orc_gon_replay   the same traversal, forced along a given sequence,
  *                    checking each forced choice is a farthest point up to a
  *                    relative band (used to accept certified FP32 ties).
+ *   orc_gon_resume   the traversal with its first p centers given (a saved
+ *                    prefix), continued by farthest points to k centers;
+ *                    Section 3.1's traversal adds one center per step from
+ *                    the current set alone, so a prefix of a run extends to
+ *                    the longer run.
  *   orc_assign       nearest-center assignment and covering radius, the
  *                    k-center definition in Section 1.1.
  *   orc_mrg          two-round MRG, Algorithm 1 with one pass of its loop.
@@ -170,6 +175,58 @@ int64_t orc_gon_replay(const float *X, int64_t n, int d, int64_t ld,
     return bad;
 }
 
+/* Gonzalez with a forced prefix (Section 3.1).  Centers c_0..c_{p-1} are
+ * prefix[0..p-1]; every later center is a farthest point (lowest index on
+ * ties) from the centers so far.  Step t applies c_t to every point's squared
+ * min-distance m_i and picks the next center (the forced one while t+1 < p).
+ * The traversal ends after k centers, or at step t when the next center is
+ * already at distance 0 from c_0..c_t (for a free step: every point is
+ * covered).
+ * trace out [k]: for a step t that is followed by another center,
+ *   sqrt(m of that center), its distance to c_0..c_t; for the last chosen
+ *   step, sqrt(max_i m_i), the covering radius of all chosen centers; 0
+ *   after the end.  Along a free step both readings are the same value.
+ * centers out [k] (-1 padded).  Returns the number of centers chosen, or -1
+ * when the prefix is invalid (p < 1, p > k, an index out of range). */
+int64_t orc_gon_resume(const float *X, int64_t n, int d, int64_t ld, int64_t k,
+                       const int64_t *prefix, int64_t p, int64_t *centers,
+                       double *trace)
+{
+    if (p < 1 || p > k) return -1;
+    for (int64_t t = 0; t < p; ++t)
+        if (prefix[t] < 0 || prefix[t] >= n) return -1;
+    double *mind = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!mind) return -1;
+    for (int64_t i = 0; i < n; ++i) mind[i] = INFINITY;
+    for (int64_t t = 0; t < k; ++t) { centers[t] = -1; trace[t] = 0.0; }
+
+    int64_t c = prefix[0];
+    int64_t chosen = 0;
+    for (int64_t t = 0; t < k; ++t) {
+        centers[t] = c;
+        chosen = t + 1;
+        const float *xc = X + c * ld;
+#pragma omp parallel for num_threads(g_threads) schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double dd = dist2(X + i * ld, xc, d);
+            if (dd < mind[i]) mind[i] = dd;
+        }
+        double M = -1.0;
+        int64_t a = -1;
+        for (int64_t i = 0; i < n; ++i)
+            if (mind[i] > M) { M = mind[i]; a = i; }
+        int64_t next = (t + 1 < p) ? prefix[t + 1] : a;
+        if (t == k - 1 || mind[next] == 0.0) {
+            trace[t] = sqrt(M);   /* covering radius of the chosen centers */
+            break;
+        }
+        trace[t] = sqrt(mind[next]);
+        c = next;
+    }
+    free(mind);
+    return chosen;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Assignment (Section 1.1): every point goes to its nearest center; the
  * solution value is the largest such distance (the covering radius).
@@ -272,11 +329,14 @@ double orc_mrg(const float *X, int64_t n, int d, int64_t ld,
  * block; S becomes the union of their centers.  Then one machine runs
  * Gonzalez(k) on S (first center = smallest index).
  * *rounds counts all rounds including the last (i+1 in Lemma 3's terms).
+ * s_out (optional, [n]) and *n_s_out receive the sample S the last round
+ * runs on (ascending).
  * Returns the covering radius over X, or -1 if the loop cannot shrink S
  * (when every block already has at most k points). */
 double orc_mrg_rounds(const float *X, int64_t n, int d, int64_t ld,
                       int64_t k, int64_t c, int64_t *centers,
-                      int64_t *n_centers, int *rounds)
+                      int64_t *n_centers, int *rounds, int64_t *s_out,
+                      int64_t *n_s_out)
 {
     int64_t *S = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     int64_t *T = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
@@ -301,6 +361,8 @@ double orc_mrg_rounds(const float *X, int64_t n, int d, int64_t ld,
         ns = nt;
     }
     {
+        if (s_out) memcpy(s_out, S, sizeof(int64_t) * (size_t)ns);
+        if (n_s_out) *n_s_out = ns;
         int64_t got = gon_subset(X, d, ld, S, ns, k, centers, tr);
         *n_centers = got;
         ++*rounds;

@@ -178,3 +178,72 @@ def test_replay_accepts_certified_tie(orc):
     bad, ties, _ = orc.gon_replay(X, 2, np.array([0, 2]), band)
     assert bad == -1 and ties == 1
     assert orc.gon_replay(X, 2, np.array([0, 2]), 0.0)[0] == 1
+
+
+def test_resume_single_first_is_gon(orc):
+    X = np.random.default_rng(41).normal(size=(800, 4)).astype(np.float32)
+    for first in (0, 313):
+        c, tr, got = orc.gon_resume(X, 25, [first])
+        c2, tr2, got2 = orc.gon(X, 25, first)
+        assert got == got2 and np.array_equal(c, c2) and np.array_equal(tr, tr2)
+
+
+def test_resume_from_own_prefix_is_longer_run(orc):
+    # the traversal adds one center per step from the current set alone, so a
+    # saved prefix extends to the longer run (Section 3.1)
+    X = np.random.default_rng(42).normal(size=(1500, 3)).astype(np.float32)
+    c, tr, got = orc.gon(X, 60, 7)
+    for p in (2, 17, 59, 60):
+        cr, trr, gr = orc.gon_resume(X, 60, c[:p])
+        assert gr == got and np.array_equal(cr, c) and np.array_equal(trr, tr)
+
+
+def test_resume_arbitrary_prefix_by_library_distances(orc):
+    # an arbitrary prefix (not a traversal's): the prefix is kept, every
+    # later center is the lowest-index farthest point by library distances,
+    # trace[t] is the next center's distance to centers 0..t and the last
+    # entry is the covering radius (integer coordinates: all exact)
+    rng = np.random.default_rng(43)
+    for trial in range(20):
+        n = int(rng.integers(5, 60))
+        X = rng.integers(0, 9, (n, 2)).astype(np.float32)
+        k = int(rng.integers(1, 12))
+        p = int(rng.integers(1, k + 1))
+        pre = rng.choice(n, min(p, n), replace=False)
+        p = len(pre)
+        if p > k:
+            continue
+        c, tr, got = orc.gon_resume(X, k, pre)
+        D = cdist(X.astype(np.float64), X.astype(np.float64), "sqeuclidean")
+        assert np.array_equal(c[:min(p, got)], pre[:min(p, got)])
+        m = np.full(n, np.inf)
+        for t in range(got):
+            m = np.minimum(m, D[c[t]])
+            if t + 1 < got:
+                nxt = c[t + 1]
+                if t + 1 >= p:
+                    assert nxt == int(np.flatnonzero(m == m.max())[0])
+                assert m[nxt] > 0 and tr[t] == np.sqrt(m[nxt])
+            else:
+                assert tr[t] == np.sqrt(m.max())
+                # ended at k, or the next center was already covered
+                if got < k:
+                    nxt = pre[t + 1] if t + 1 < p else int(np.argmax(m))
+                    assert m[nxt] == 0
+        assert np.all(c[got:] == -1) and np.all(tr[got:] == 0)
+
+
+def test_resume_covered_prefix_center_ends(orc):
+    # a forced center at distance 0 from the centers before it ends the run
+    X = np.array([[0, 0], [5, 0], [0, 0], [9, 9]], np.float32)
+    c, tr, got = orc.gon_resume(X, 4, [0, 1, 2])
+    assert got == 2 and c.tolist() == [0, 1, -1, -1]
+    # covering radius of {0, 1}: point 3 at (9, 9) is nearest to (5, 0)
+    assert tr[1] == np.sqrt(4 * 4 + 9 * 9) and tr[0] == 5.0
+
+
+def test_resume_rejects_bad_prefix(orc):
+    X = np.zeros((10, 2), np.float32)
+    for pre, k in (([], 3), ([0, 1, 2, 3], 3), ([10], 3), ([-1], 3)):
+        with pytest.raises(ValueError):
+            orc.gon_resume(X, k, pre)

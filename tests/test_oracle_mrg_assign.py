@@ -154,3 +154,85 @@ def test_multi_round_capacity_above_n_is_gon(orc):
     r = orc.mrg_rounds(X, 9, 400)
     c, tr, got = orc.gon(X, 9, 0)
     assert r["rounds"] == 1 and np.array_equal(r["centers"], c)
+
+
+def test_min_dist2_to_set_matches_library(orc):
+    # d(x, S) of the EIM distance pass and of Select: squared FP64 distance to
+    # the nearest listed point and the lowest list position attaining it
+    rng = np.random.default_rng(38)
+    for d in (1, 2, 8, 32):
+        X = rng.normal(size=(400, d)).astype(np.float32)
+        for trial in range(6):
+            S = rng.choice(400, int(rng.integers(1, 60)), replace=False)
+            x = int(rng.integers(0, 400))
+            v, a = orc.min_dist2_to_set(X, x, S)
+            D = cdist(X[x:x + 1].astype(np.float64), X[S].astype(np.float64),
+                      "sqeuclidean")[0]
+            assert v == pytest.approx(D.min(), rel=1e-12, abs=0)
+            assert D[a] <= D.min() * (1 + 1e-12)
+            # integer coordinates: every distance exact, so value and the
+            # lowest position are exact too
+            Xi = rng.integers(-20, 21, (400, d)).astype(np.float32)
+            v, a = orc.min_dist2_to_set(Xi, x, S)
+            Di = cdist(Xi[x:x + 1].astype(np.float64), Xi[S].astype(np.float64),
+                       "sqeuclidean")[0]
+            assert v == Di.min() and a == int(np.flatnonzero(Di == Di.min())[0])
+    # a repeated member ties with itself: the first position wins
+    X = np.array([[0, 0], [3, 4], [3, 4], [6, 8]], np.float32)
+    assert orc.min_dist2_to_set(X, 0, np.array([3, 2, 1])) == (25.0, 1)
+    assert orc.min_dist2_to_set(X, 3, np.array([0])) == (100.0, 0)
+    # the empty set is at infinite distance
+    v, a = orc.min_dist2_to_set(X, 0, np.array([], np.int64))
+    assert v == np.inf and a == -1
+
+
+@pytest.mark.parametrize("n,c,k", [(3001, 1000, 40), (2500, 700, 25), (999, 250, 12)])
+def test_multi_round_one_pass_equals_two_round(orc, n, c, k):
+    # one pass of the loop (Algorithm 1) is two-round MRG on the blocks of
+    # the ascending order, whose sizes differ by at most one: partition p is
+    # [p*n // mi, (p+1)*n // mi) with mi = ceil(n / c).  Clustered data, so
+    # that block boundaries and first centers change the result.
+    X = np.random.default_rng(39).normal(size=(n, 3)).astype(np.float32)
+    X[: n // 3] += 40.0
+    X[n // 3: n // 2] -= 25.0
+    mi = -(-n // c)
+    off = np.array([p * n // mi for p in range(mi + 1)], np.int64)
+    assert np.diff(off).max() - np.diff(off).min() <= 1
+    r = orc.mrg_rounds(X, k, c)
+    q = orc.mrg(X, off, k)
+    assert r["rounds"] == 2
+    assert np.array_equal(r["centers"], q["centers"])
+    assert r["n_centers"] == q["n_centers"] and r["radius"] == q["radius"]
+    # the union is ascending and is exactly the blocks' Gonzalez centers, each
+    # block started at its smallest index (computed here block by block)
+    S = r["sample"]
+    assert np.all(np.diff(S) > 0)
+    blocks = []
+    for p in range(mi):
+        cc, _, got = orc.gon(X[off[p]:off[p + 1]], k, 0)
+        blocks.append(cc[:got] + off[p])
+    assert np.array_equal(S, np.sort(np.concatenate(blocks)))
+    assert np.array_equal(S, q["union"])
+    # the last round starts from the smallest index of S
+    assert r["centers"][0] == S[0]
+
+
+def test_multi_round_two_passes_compose(orc):
+    # two passes of the loop: the second pass splits the first pass's union
+    # (ascending) into ceil(|S|/c) blocks and runs Gonzalez on each
+    n, c, k = 4000, 250, 20
+    X = np.random.default_rng(40).normal(size=(n, 2)).astype(np.float32)
+    r = orc.mrg_rounds(X, k, c)
+    assert r["rounds"] == 3
+    S = np.arange(n)
+    for _ in range(2):
+        mi = -(-len(S) // c)
+        nxt = []
+        for p in range(mi):
+            blk = S[p * len(S) // mi:(p + 1) * len(S) // mi]
+            cc, _, got = orc.gon(X[blk], k, 0)
+            nxt.append(blk[cc[:got]])
+        S = np.sort(np.concatenate(nxt))
+    assert np.array_equal(r["sample"], S)
+    cc, tr, got = orc.gon(X[S], k, 0)
+    assert np.array_equal(r["centers"][:got], S[cc[:got]])
