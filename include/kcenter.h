@@ -21,6 +21,11 @@
  *           owns only its workspace (held by the handle, grown on demand with
  *           hipMalloc, freed by kc_destroy) and never frees caller memory.
  *           Calls on one handle must not overlap (one stream at a time).
+ *           Small host tables (partition and tile lists) reach the device by
+ *           copies ordered on the call's stream, from pinned staging buffers
+ *           the handle owns; a call whose tables are unchanged copies none.
+ *           Destroy every handle before the process exits (while the HIP
+ *           runtime is still up).
  * Errors.   Every entry point returns KC_OK or a negative kc_status.  All
  *           argument checks happen on the host before any device work; a
  *           failed check enqueues nothing.  kc_last_error() gives the text of
@@ -261,10 +266,12 @@ typedef struct {
 /*
  * kcenter_batch -- solve `count` independent problems of mixed n, d, k and
  * algorithm.  Gonzalez problems and MRG first rounds of equal d share the
- * same step launches (one tile list over all of them, a HIP graph per plan);
- * MRG second rounds likewise; EIM problems run their sampling loop (which
- * synchronises the stream per iteration) and join the shared launches for
- * their final Gonzalez.  Outputs as for the single-problem calls.
+ * same launches (register-resident, several per cooperative launch, when
+ * every one fits a co-resident grid, else one streamed tile list over all of
+ * them with a HIP graph per plan); MRG second rounds likewise.  EIM problems,
+ * and problems streamed in BF16, run one after another through their
+ * single-problem entry points (kcenter_eim synchronises the stream once per
+ * iteration).  Outputs as for the single-problem calls.
  */
 int kcenter_batch(kc_handle* h, const kc_problem* probs, int32_t count, void* stream);
 

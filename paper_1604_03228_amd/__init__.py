@@ -8,8 +8,10 @@ current HIP stream) go to the C ABI of ``libkcenter.so``
 in the library's HIP kernels.  If the library is missing the import of any
 entry point raises -- there is no CPU fallback.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import torch
 
@@ -117,6 +119,31 @@ def _ptr(t):
     return _p(t.data_ptr()) if t is not None else None
 
 
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    """Release every live handle while the HIP runtime is still up.  Python's
+    exit handlers run before the C runtime's; a handle still holding
+    instantiated graphs, events and device buffers when the runtime (or a
+    profiler wrapping it) tears down would otherwise be released after the
+    library's code objects are gone."""
+    hs = list(_live)
+    if not hs:
+        return
+    try:
+        if torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+    for h in hs:
+        try:
+            h.close()
+        except Exception:
+            pass
+
+
 class Handle:
     """Owns a kc_handle (workspace, captured graphs) on the current device."""
 
@@ -127,13 +154,14 @@ class Handle:
         if rc != 0:
             raise KCenterError(rc, L.kc_strerror(rc).decode())
         self._h = h
+        _live.add(self)
         self.set_option("graphs", int(graphs))
         self.set_option("resident", int(resident))
 
     def close(self):
         if getattr(self, "_h", None):
-            load_library().kc_destroy(self._h)
-            self._h = None
+            h, self._h = self._h, None
+            load_library().kc_destroy(h)
 
     def __del__(self):
         try:

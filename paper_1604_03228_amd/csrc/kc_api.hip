@@ -27,6 +27,10 @@ kc_handle::~kc_handle()
             hipEventDestroy(sp.b);
         }
     for (hipEvent_t e : event_pool) hipEventDestroy(e);
+    for (auto& kv : staging) {
+        if (kv.second.done) hipEventDestroy(kv.second.done);
+        if (kv.second.p) hipHostFree(kv.second.p);
+    }
     for (auto& kv : bufs) hipFree(kv.second.p);
     if (status_word) hipFree(status_word);
 }
@@ -104,10 +108,13 @@ void* kc_handle::ws(const std::string& name, size_t bytes)
     return p;
 }
 
-// Upload a host table to a named workspace buffer, skipping the copy when the
-// same bytes were uploaded last time (so repeated identical calls stay free
-// of host-device synchronisation).
-void* kc_handle::upload(const std::string& name, const void* src, size_t bytes)
+// Upload a host table to a named workspace buffer.  The copy is ordered on
+// stream s after the work already queued there (which may still read the
+// buffer's previous contents): it reads a pinned host staging buffer of the
+// same name, and the staging bytes are rewritten only once the previous copy
+// from them has completed.  The copy is skipped when the same bytes were
+// uploaded last time, so repeated identical calls stay free of host waits.
+void* kc_handle::upload(const std::string& name, const void* src, size_t bytes, hipStream_t s)
 {
     void* p = ws(name, bytes);
     if (!p) return nullptr;
@@ -115,9 +122,36 @@ void* kc_handle::upload(const std::string& name, const void* src, size_t bytes)
     if (shadow.size() == bytes && bytes > 0 && memcmp(shadow.data(), src, bytes) == 0 &&
         shadow_ptr[name] == p)
         return p;
-    if (bytes > 0 && hipMemcpy(p, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
+    if (bytes > 0) {
+        Staging& st = staging[name];
+        if (st.done && hipEventSynchronize(st.done) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        if (st.cap < bytes) {
+            if (st.p) hipHostFree(st.p);
+            st.p = nullptr;
+            st.cap = 0;
+            const size_t cap = (bytes + 4095) & ~(size_t)4095;
+            if (hipHostMalloc(&st.p, cap, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                st.p = nullptr;
+                return nullptr;
+            }
+            st.cap = cap;
+        }
+        if (!st.done && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            st.done = nullptr;
+            return nullptr;
+        }
+        memcpy(st.p, src, bytes);
+        if (hipMemcpyAsync(p, st.p, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipEventRecord(st.done, s) != hipSuccess) {
+            (void)hipGetLastError();
+            shadow.clear();
+            return nullptr;
+        }
     }
     shadow.assign((const char*)src, (const char*)src + bytes);
     shadow_ptr[name] = p;
@@ -183,7 +217,7 @@ int kc_check_points(kc_handle* h, const kc_points* p, bool need_bf16_if_asked)
 // batched Gonzalez planning
 
 int kc_plan_gon(kc_handle* h, const std::string& pre, int d, uint32_t tile,
-                const std::vector<KcGonJob>& jobs, KcGonRun& R, KcGonHost& H)
+                const std::vector<KcGonJob>& jobs, KcGonRun& R, KcGonHost& H, hipStream_t s)
 {
     const int nseg = (int)jobs.size();
     H.segs.assign(nseg, KcSeg{});
@@ -240,11 +274,11 @@ int kc_plan_gon(kc_handle* h, const std::string& pre, int d, uint32_t tile,
     if (!R.xs || !R.mind || !R.keys || !R.part || !R.ccoord || !R.radius2 || !R.cand ||
         !R.ncand)
         return h->fail(KC_ENOMEM, "workspace allocation failed");
-    R.segs = (KcSeg*)h->upload(pre + "segs", H.segs.data(), sizeof(KcSeg) * nseg);
-    R.blk_seg = (uint32_t*)h->upload(pre + "blk_seg", H.blk_seg.data(), 4 * H.blk_seg.size());
-    R.blk_start = (uint32_t*)h->upload(pre + "blk_start", H.blk_start.data(), 4 * H.blk_start.size());
-    R.pairs_seg = (uint32_t*)h->upload(pre + "pairs_seg", H.pairs_seg.data(), 4 * H.pairs_seg.size());
-    R.pairs_t = (uint32_t*)h->upload(pre + "pairs_t", H.pairs_t.data(), 4 * H.pairs_t.size());
+    R.segs = (KcSeg*)h->upload(pre + "segs", H.segs.data(), sizeof(KcSeg) * nseg, s);
+    R.blk_seg = (uint32_t*)h->upload(pre + "blk_seg", H.blk_seg.data(), 4 * H.blk_seg.size(), s);
+    R.blk_start = (uint32_t*)h->upload(pre + "blk_start", H.blk_start.data(), 4 * H.blk_start.size(), s);
+    R.pairs_seg = (uint32_t*)h->upload(pre + "pairs_seg", H.pairs_seg.data(), 4 * H.pairs_seg.size(), s);
+    R.pairs_t = (uint32_t*)h->upload(pre + "pairs_t", H.pairs_t.data(), 4 * H.pairs_t.size(), s);
     if (!R.segs || !R.blk_seg || !R.blk_start || !R.pairs_seg || !R.pairs_t)
         return h->fail(KC_ENOMEM, "plan upload failed");
     R.keysum = keyoff;
@@ -268,6 +302,13 @@ int kc_plan_gon(kc_handle* h, const std::string& pre, int d, uint32_t tile,
         }
         R.nblk_at = H.nblk_at.data();
     }
+    // Graphs captured from this plan embed its grids and loop counts (tiles,
+    // steps, active tiles per step): their keys carry this signature.
+    uint64_t hsh = kc_hash_bytes(&d, sizeof d);
+    hsh = kc_hash_bytes(&tile, sizeof tile, hsh);
+    hsh = kc_hash_vec(H.segs, hsh);
+    hsh = kc_hash_vec(H.nblk_at, hsh);
+    R.plan_hash = hsh;
     return KC_OK;
 }
 
@@ -315,11 +356,12 @@ void kc_enqueue_gon_steps(const KcGonRun& R, hipStream_t s)
 
 // Prep, steps and finish of a streaming run as three cached graphs; the
 // steps graph is bracketed by a timing span called `span`.
-int kc_run_gon_stream(kc_handle* h, const std::string& key, const KcGonRun& R,
+int kc_run_gon_stream(kc_handle* h, const std::string& key0, const KcGonRun& R,
                       const KcGonHost& H, const std::vector<KcGonJob>& jobs,
                       const char* span, hipStream_t s,
                       const std::function<void(hipStream_t)>& finish)
 {
+    const std::string key = key0 + kc_hash_str(R.plan_hash);
     int rc = h->run_graph(key + ":prep", s,
                           [&](hipStream_t st) { kc_enqueue_gon_prep(R, H, jobs, st); });
     if (rc) return rc;
@@ -342,15 +384,16 @@ int kc_run_gon(kc_handle* h, const std::string& key, const KcGonRun& R, const Kc
         const int rc = kc_run_gon_resident_batch(h, key, R, H, jobs, span, s, &done);
         if (rc) return rc;
     }
-    if (done) return h->run_graph(key + ":finish", s, finish);
+    if (done) return h->run_graph(key + kc_hash_str(R.plan_hash) + ":rfinish", s, finish);
     return kc_run_gon_stream(h, key, R, H, jobs, span, s, finish);
 }
 
-int kc_run_gon_resident_batch(kc_handle* h, const std::string& key, const KcGonRun& R,
+int kc_run_gon_resident_batch(kc_handle* h, const std::string& key0, const KcGonRun& R,
                               const KcGonHost& H, const std::vector<KcGonJob>& jobs,
                               const char* span, hipStream_t s, bool* done)
 {
     *done = false;
+    const std::string key = key0 + kc_hash_str(R.plan_hash);
     const int d = R.d;
     // Two packings: every segment on the first variant whose grid for it is
     // co-resident, or every segment on the large variant (fewer blocks, so
@@ -414,10 +457,11 @@ int kc_run_gon_resident_batch(kc_handle* h, const std::string& key, const KcGonR
             b0 += gs;
         }
     }
-    const uint4* blks = (const uint4*)h->upload(key + ":rblk", tab.data(), sizeof(uint4) * tab.size());
+    const uint4* blks =
+        (const uint4*)h->upload(key0 + ":rblk", tab.data(), sizeof(uint4) * tab.size(), s);
     // per launch: its exchange words, then its abort flag (one fill clears all)
     const uint64_t bw = kc_resident_slot_words(0, 0) + 8;
-    u64* bar = (u64*)h->ws(key + ":rbar", sizeof(u64) * bw * launches.size());
+    u64* bar = (u64*)h->ws(key0 + ":rbar", sizeof(u64) * bw * launches.size());
     if (!blks || !bar) return h->fail(KC_ENOMEM, "workspace allocation failed");
     // the candidate gathers read the caller's rows when every segment has them
     const float* xa = jobs.empty() ? nullptr : jobs[0].X;
@@ -629,7 +673,7 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
     jobs[0] = KcGonJob{pts->f32, pts->ld, 0, (uint32_t)pts->n, (uint32_t)first, (uint32_t)k};
     KcGonRun R;
     KcGonHost H;
-    rc = kc_plan_gon(h, "g.", pts->d, 1024, jobs, R, H);
+    rc = kc_plan_gon(h, "g.", pts->d, 1024, jobs, R, H, s);
     if (rc) return rc;
 
     // register-resident persistent kernel when the whole problem fits

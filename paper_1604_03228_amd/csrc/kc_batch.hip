@@ -186,10 +186,10 @@ static int run_group(kc_handle* h, const kc_problem* probs, const std::vector<in
     }
     KcGonRun R;
     KcGonHost H;
-    int rc = kc_plan_gon(h, P + "1.", d, 1024, sj, R, H);
+    int rc = kc_plan_gon(h, P + "1.", d, 1024, sj, R, H, s);
     if (rc) return rc;
     const int nseg = (int)sj.size();
-    const int64_t* rb = (const int64_t*)h->upload(P + "1.rb", sr.data(), 8 * sr.size());
+    const int64_t* rb = (const int64_t*)h->upload(P + "1.rb", sr.data(), 8 * sr.size(), s);
     int64_t* cent = (int64_t*)h->ws(P + "1.cent", 8 * std::max<uint64_t>(R.keysum, 1));
     int64_t* nch = (int64_t*)h->ws(P + "1.nch", 8 * (size_t)nseg);
     double* rad = (double*)h->ws(P + "1.rad", 8 * (size_t)nseg);
@@ -207,11 +207,18 @@ static int run_group(kc_handle* h, const kc_problem* probs, const std::vector<in
             first_seg[t.prob] = q;
     }
     const KcBatchOut* outs_d = outs.empty() ? nullptr
-        : (const KcBatchOut*)h->upload(P + "1.outs", outs.data(), sizeof(KcBatchOut) * outs.size());
+        : (const KcBatchOut*)h->upload(P + "1.outs", outs.data(), sizeof(KcBatchOut) * outs.size(), s);
     std::string key = P + "run1";
+    // every problem's arrays, sizes and algorithm (the graphs embed their
+    // pointers, strides and grids; the partition offsets enter through the
+    // plans' signatures)
     for (int i : ids) {
-        char b[64];
-        snprintf(b, sizeof b, ":%p:%lld", (const void*)probs[i].pts.f32, (long long)probs[i].k);
+        char b[160];
+        const kc_problem& p = probs[i];
+        snprintf(b, sizeof b, ":%p:%lld:%lld:%lld:%d:%lld:%d:%p:%p:%p", (const void*)p.pts.f32,
+                 (long long)p.pts.n, (long long)p.pts.ld, (long long)p.k, p.algo,
+                 (long long)p.first, p.m, (void*)p.centers, (void*)p.n_centers,
+                 (void*)p.radius);
         key += b;
     }
     rc = kc_run_gon(h, key, R, H, sj, "batch_gon", s, [&](hipStream_t sst) {
@@ -265,16 +272,16 @@ static int run_group(kc_handle* h, const kc_problem* probs, const std::vector<in
     }
     KcGonRun R2;
     KcGonHost H2;
-    rc = kc_plan_gon(h, P + "2.", d, 1024, sj2, R2, H2);
+    rc = kc_plan_gon(h, P + "2.", d, 1024, sj2, R2, H2, s);
     if (rc) return rc;
     const int nu = (int)uj.size();
     int64_t* uni = (int64_t*)h->ws(P + "2.uni", 8 * (size_t)std::max<int64_t>(uoff, 1));
     int64_t* nuni = (int64_t*)h->ws(P + "2.nu", 8 * (size_t)nu);
     int64_t* cent2 = (int64_t*)h->ws(P + "2.cent", 8 * std::max<uint64_t>(R2.keysum, 1));
     int64_t* nch2 = (int64_t*)h->ws(P + "2.nch", 8 * (size_t)nu);
-    const KcUnionJob* uj_d = (const KcUnionJob*)h->upload(P + "2.uj", uj.data(), sizeof(KcUnionJob) * nu);
-    const int32_t* bj_d = (const int32_t*)h->upload(P + "2.bj", blk_job.data(), 4 * blk_job.size());
-    const int32_t* bp_d = (const int32_t*)h->upload(P + "2.bp", blk_part.data(), 4 * blk_part.size());
+    const KcUnionJob* uj_d = (const KcUnionJob*)h->upload(P + "2.uj", uj.data(), sizeof(KcUnionJob) * nu, s);
+    const int32_t* bj_d = (const int32_t*)h->upload(P + "2.bj", blk_job.data(), 4 * blk_job.size(), s);
+    const int32_t* bp_d = (const int32_t*)h->upload(P + "2.bp", blk_part.data(), 4 * blk_part.size(), s);
     if (!uni || !nuni || !cent2 || !nch2 || !uj_d || !bj_d || !bp_d)
         return h->fail(KC_ENOMEM, "workspace allocation failed");
     std::vector<KcBatchOut> outs2;
@@ -283,9 +290,12 @@ static int run_group(kc_handle* h, const kc_problem* probs, const std::vector<in
         outs2.push_back({(int64_t)H2.segs[q].keyoff, p.k, q, p.centers, p.n_centers, nullptr});
     }
     const KcBatchOut* outs2_d =
-        (const KcBatchOut*)h->upload(P + "2.outs", outs2.data(), sizeof(KcBatchOut) * nu);
+        (const KcBatchOut*)h->upload(P + "2.outs", outs2.data(), sizeof(KcBatchOut) * nu, s);
     if (!outs2_d) return h->fail(KC_ENOMEM, "workspace allocation failed");
-    rc = h->run_graph(key + ":u", s, [&](hipStream_t sst) {
+    // the union graph's grids follow the union jobs and round 2's plan
+    uint64_t uh = kc_hash_vec(uj, R2.plan_hash);
+    uh = kc_hash_vec(blk_job, uh);
+    rc = h->run_graph(key + kc_hash_str(uh) + ":u", s, [&](hipStream_t sst) {
         hipLaunchKernelGGL(k_batch_union, dim3((unsigned)blk_job.size()), dim3(256), 0, sst, uj_d,
                            bj_d, bp_d, cent, nch, uni, nuni, R2.segs);
         for (int q = 0; q < nu; ++q) {

@@ -762,7 +762,7 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
     jobs[0].k = (uint32_t)k;
     KcGonRun RG;
     KcGonHost HG;
-    rc = kc_plan_gon(h, "e2.", d, 1024, jobs, RG, HG);
+    rc = kc_plan_gon(h, "e2.", d, 1024, jobs, RG, HG, s);
     if (rc) return rc;
     const uint32_t padded = kc_pad64(nc);
     hipLaunchKernelGGL(k_gather_soa32, g1(padded), dim3(256), 0, s, X, ld, d, Cidx, nc, padded,

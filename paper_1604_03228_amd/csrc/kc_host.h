@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <stdio.h>
+
 #include <functional>
 #include <map>
 #include <string>
@@ -21,6 +23,36 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
 };
 
+// Pinned host staging of one uploaded table: the bytes a stream-ordered copy
+// reads, and an event recorded after that copy (the staging bytes are not
+// rewritten before it has completed).
+struct Staging {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+
+// FNV-1a over bytes, chained through `h` (plan signatures in graph keys).
+static inline uint64_t kc_hash_bytes(const void* p, size_t n, uint64_t h = 1469598103934665603ull)
+{
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    return h;
+}
+template <class T>
+static inline uint64_t kc_hash_vec(const std::vector<T>& v, uint64_t h)
+{
+    const uint64_t n = v.size();
+    h = kc_hash_bytes(&n, sizeof n, h);
+    return v.empty() ? h : kc_hash_bytes(v.data(), sizeof(T) * v.size(), h);
+}
+static inline std::string kc_hash_str(uint64_t h)
+{
+    char b[24];
+    snprintf(b, sizeof b, ":#%016llx", (unsigned long long)h);
+    return b;
+}
+
 struct kc_handle {
     int device = 0;
     int num_cu = 0;
@@ -32,6 +64,7 @@ struct kc_handle {
     std::map<std::string, DevBuf> bufs;
     std::map<std::string, std::vector<char>> shadows;
     std::map<std::string, void*> shadow_ptr;
+    std::map<std::string, Staging> staging;
     std::map<std::string, GraphEntry> graphs;
     std::map<int, int> resident_cache;
     int resident_cap = 0;             // blocks per resident launch, 0: no cap
@@ -56,7 +89,9 @@ struct kc_handle {
     void clear_graphs();
     int fail(int code, const char* fmt, ...);
     void* ws(const std::string& name, size_t bytes);
-    void* upload(const std::string& name, const void* src, size_t bytes);
+    // Copy a host table into a named workspace buffer, ordered on stream s
+    // after the work already queued there (see kc_api.hip).
+    void* upload(const std::string& name, const void* src, size_t bytes, hipStream_t s);
     int run_graph(const std::string& key, hipStream_t stream,
                   const std::function<void(hipStream_t)>& enqueue);
     // Co-resident blocks of resident variant v for dimension d (0: none),
@@ -86,8 +121,11 @@ struct KcGonHost {
 };
 
 int kc_check_points(kc_handle* h, const kc_points* p, bool need_bf16_if_asked);
+// Plans a batched run: workspace, and the segment / tile / step tables
+// uploaded in order on stream s.  R.plan_hash identifies the plan's geometry
+// (every graph key built from a plan includes it).
 int kc_plan_gon(kc_handle* h, const std::string& pre, int d, uint32_t tile,
-                const std::vector<KcGonJob>& jobs, KcGonRun& R, KcGonHost& H);
+                const std::vector<KcGonJob>& jobs, KcGonRun& R, KcGonHost& H, hipStream_t s);
 void kc_enqueue_stage(const KcGonRun& R, const KcGonHost& H, const std::vector<KcGonJob>& jobs,
                       hipStream_t s, uint16_t* xb = nullptr, float* ex = nullptr);
 void kc_enqueue_gon_prep(const KcGonRun& R, const KcGonHost& H,

@@ -51,6 +51,7 @@ struct KcGonRun {
     // host [kmax]: blocks still active at step t when segments are ordered by
     // descending k (their tiles then form a prefix); NULL: all blocks
     const uint32_t* nblk_at = nullptr;
+    uint64_t plan_hash = 0;     // geometry of the plan (host), part of graph keys
 };
 
 void kc_fill_u64(u64* p, u64 v, uint64_t n, hipStream_t s);

@@ -125,10 +125,11 @@ int kc_bf16_alloc(kc_handle* h, const std::string& pre, const KcGonRun& R, KcBf1
 }
 
 // prep / steps (timed under `span`) / finish graphs of a BF16 run
-int kc_run_bf16(kc_handle* h, const std::string& key, const KcGonRun& R, const KcBf16Run& B,
+int kc_run_bf16(kc_handle* h, const std::string& key0, const KcGonRun& R, const KcBf16Run& B,
                 const KcGonHost& H, const std::vector<KcGonJob>& jobs, const char* span,
                 hipStream_t s, const std::function<void(hipStream_t)>& finish)
 {
+    const std::string key = key0 + kc_hash_str(R.plan_hash);
     int rc = h->run_graph(key + ":prep", s,
                           [&](hipStream_t st) { kc_enqueue_bf16_prep(R, B, H, jobs, st); });
     if (rc) return rc;
@@ -152,7 +153,7 @@ int kc_gonzalez_bf16(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
     jobs[0].k = (uint32_t)k;
     KcGonRun R;
     KcGonHost H;
-    int rc = kc_plan_gon(h, "g.", pts->d, KC_BF_TILE_PTS, jobs, R, H);
+    int rc = kc_plan_gon(h, "g.", pts->d, KC_BF_TILE_PTS, jobs, R, H, s);
     if (rc) return rc;
     KcBf16Run B;
     rc = kc_bf16_alloc(h, "gb.", R, B);
@@ -195,8 +196,8 @@ int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, ui
         !nlist || !lo_max || !r2 || (bf && !ex))
         return h->fail(KC_ENOMEM, "workspace allocation failed");
     const std::string key =
-        kc_key("assign", {pts->f32, pts->bf16, centers, k_dev, labels, radius},
-               {pts->n, d, pts->ld, k, bf, (long long)(pre.size() ? pre[0] : 0)});
+        kc_key(("assign:" + pre).c_str(), {pts->f32, pts->bf16, centers, k_dev, labels, radius},
+               {pts->n, d, pts->ld, k, bf});
     int rc = h->run_graph(key + ":stage", s, [&](hipStream_t st) {
         if (bf) kc_bf16_err(pts->f32, pts->bf16, pts->ld, d, n, ex, st);
         kc_stage_centers(pts->f32, bf ? pts->bf16 : nullptr, pts->ld, d, n, centers, nullptr, k,
@@ -279,10 +280,10 @@ int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int3
     }
     KcGonRun R1;
     KcGonHost H1;
-    rc = kc_plan_gon(h, "m1.", d, 1024, jobs, R1, H1);
+    rc = kc_plan_gon(h, "m1.", d, 1024, jobs, R1, H1, s);
     if (rc) return rc;
     const int64_t* rb =
-        (const int64_t*)h->upload("m1.rb", offsets, sizeof(int64_t) * (size_t)m);
+        (const int64_t*)h->upload("m1.rb", offsets, sizeof(int64_t) * (size_t)m, s);
     int64_t* cent1 = round1 ? round1 : (int64_t*)h->ws("m1.cent", sizeof(int64_t) * m * k);
     int64_t* nch1 = (int64_t*)h->ws("m1.nch", sizeof(int64_t) * m);
     double* rad1 = r1 ? r1 : (double*)h->ws("m1.rad", sizeof(double) * m);
@@ -305,14 +306,14 @@ int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int3
         if (rc) return rc;
     }
     if (done) {
-        rc = h->run_graph(key1 + ":finish", s, [&](hipStream_t st) {
+        rc = h->run_graph(key1 + kc_hash_str(R1.plan_hash) + ":finish", s, [&](hipStream_t st) {
             kc_fill_u64((u64*)cent1, ~0ull, (uint64_t)m * k, st);
             kc_gon_finish(R1, cent1, nch1, nullptr, rad1, rb, nullptr, st);
         });
     } else if (bf) {
         KcGonRun Rb;
         KcGonHost Hb;
-        rc = kc_plan_gon(h, "m1s.", d, KC_BF_TILE_PTS, jobs, Rb, Hb);
+        rc = kc_plan_gon(h, "m1s.", d, KC_BF_TILE_PTS, jobs, Rb, Hb, s);
         if (rc) return rc;
         KcBf16Run B1;
         rc = kc_bf16_alloc(h, "m1b.", Rb, B1);
@@ -339,7 +340,7 @@ int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int3
     jobs2[0].k = (uint32_t)k;
     KcGonRun R2;
     KcGonHost H2;
-    rc = kc_plan_gon(h, "m2.", d, 1024, jobs2, R2, H2);
+    rc = kc_plan_gon(h, "m2.", d, 1024, jobs2, R2, H2, s);
     if (rc) return rc;
     int64_t* uni_b = uni ? uni : (int64_t*)h->ws("m2.uni", sizeof(int64_t) * cap);
     int64_t* nu = n_union ? n_union : (int64_t*)h->ws("m2.nu", 16);
@@ -347,7 +348,8 @@ int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int3
     if (!uni_b || !nu || !r2b) return h->fail(KC_ENOMEM, "workspace allocation failed");
     uint32_t* len_ptr = (uint32_t*)((char*)R2.segs + offsetof(KcSeg, len));
     const std::string key2 = kc_key("mrg2", {pts->f32, cent1, uni_b, nu, centers, n_centers, r2b},
-                                    {pts->n, d, pts->ld, k, m});
+                                    {pts->n, d, pts->ld, k, m}) +
+                             kc_hash_str(R2.plan_hash);
     rc = h->run_graph(key2 + ":prep", s, [&](hipStream_t st) {
         hipLaunchKernelGGL(k_mrg_union, dim3(m), dim3(256), 0, st, cent1, nch1, m, (int)k, uni_b,
                            nu, len_ptr);
@@ -441,7 +443,7 @@ int kcenter_mrg_rounds(kc_handle* h, const kc_points* pts, int64_t k, int64_t ca
         const std::string pre = r & 1 ? "mr1." : "mr0.";
         KcGonRun R;
         KcGonHost H;
-        rc = kc_plan_gon(h, pre, d, 1024, jobs, R, H);
+        rc = kc_plan_gon(h, pre, d, 1024, jobs, R, H, s);
         if (rc) return rc;
         int64_t* cent = (int64_t*)h->ws("mr.cent", sizeof(int64_t) * (size_t)(mi * k));
         int64_t* nch = (int64_t*)h->ws("mr.nch", sizeof(int64_t) * (size_t)mi);
@@ -450,7 +452,7 @@ int kcenter_mrg_rounds(kc_handle* h, const kc_points* pts, int64_t k, int64_t ca
         uint32_t* segl = (uint32_t*)h->ws("mr.segl", 16);
         const int64_t* rb = S ? nullptr
                               : (const int64_t*)h->upload("mr.rb", base.data(),
-                                                          sizeof(int64_t) * base.size());
+                                                          sizeof(int64_t) * base.size(), s);
         if (!cent || !nch || !uni || !nu || !segl || (!S && !rb))
             return h->fail(KC_ENOMEM, "workspace allocation failed");
         const std::string key = kc_key("mrr", {pts->f32, cent, Xc, S},
@@ -487,7 +489,7 @@ int kcenter_mrg_rounds(kc_handle* h, const kc_points* pts, int64_t k, int64_t ca
     jobs[0] = KcGonJob{Xc, ldc, 0, (uint32_t)ns, 0, (uint32_t)k};
     KcGonRun R;
     KcGonHost H;
-    rc = kc_plan_gon(h, "mrf.", d, 1024, jobs, R, H);
+    rc = kc_plan_gon(h, "mrf.", d, 1024, jobs, R, H, s);
     if (rc) return rc;
     const std::string key = kc_key("mrf", {pts->f32, Xc, S, centers, n_centers},
                                    {pts->n, d, pts->ld, k, capacity, r, ns});
