@@ -69,8 +69,9 @@ typedef struct {
     int32_t prec;          /* kc_precision                                   */
 } kc_points;
 
-/* Handle life cycle.  kc_create binds the handle to the current HIP device.
- * Returns KC_OK, KC_EINVAL (out == NULL), KC_ENOMEM or KC_EHIP. */
+/* Handle life cycle.  kc_create binds the handle to the current HIP device
+ * (and looks up that device's address of the no-allocation array, once per
+ * device).  Returns KC_OK, KC_EINVAL (out == NULL), KC_ENOMEM or KC_EHIP. */
 int kc_create(kc_handle** out);
 void kc_destroy(kc_handle* h);
 const char* kc_strerror(int status);
@@ -246,6 +247,26 @@ typedef struct {
 int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k, const kc_eim_params* prm,
                 int64_t* centers, int64_t* n_centers, double* radius, int64_t* sample,
                 int64_t* n_sample, kc_eim_iter* iters, int32_t* n_iters, void* stream);
+
+/*
+ * kcenter_gonzalez_noalloc -- kcenter_gonzalez for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and kernels as
+ * kcenter_gonzalez with FP32 points; it calls no hipMalloc, hipFree or
+ * allocating library routine and uploads no host table.  Its workspace is
+ * one 32 MiB device array per GPU, held until the process ends: the points'
+ * min-distances (4 B per point, padded to 64), radius candidates (8 B per
+ * point), per center 8 + 4d B plus, when the points stream instead of
+ * fitting the register-resident grid, 2 KiB per center and a 4d-byte SoA
+ * copy per point (also taken when the rows' layout does not suit the
+ * resident kernel's vector loads).  A request that needs more returns
+ * KC_EINVAL (stating the size) before any work; BF16 points return
+ * KC_EUNSUPPORTED.  Every call on a GPU uses that GPU's array: calls that
+ * overlap on one GPU (on other streams or handles) race.
+ */
+int kcenter_gonzalez_noalloc(kc_handle* h, const kc_points* pts, int64_t k, int64_t first,
+                             int64_t* centers, double* radius_trace, int64_t* n_chosen,
+                             void* stream);
 
 typedef enum { KC_ALGO_GON = 0, KC_ALGO_MRG = 1, KC_ALGO_EIM = 2 } kc_algo;
 

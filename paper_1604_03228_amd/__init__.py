@@ -59,7 +59,7 @@ class KCenterError(RuntimeError):
 EXPORTS = ["kc_create", "kc_destroy", "kc_strerror", "kc_last_error",
            "kc_set_option", "kc_device_status", "kc_timing_read",
            "kc_counter_read",
-           "kcenter_gonzalez",
+           "kcenter_gonzalez", "kcenter_gonzalez_noalloc",
            "kcenter_mrg", "kcenter_mrg_rounds", "kcenter_assign", "kcenter_eim",
            "kcenter_batch"]
 
@@ -90,6 +90,8 @@ def load_library(path=LIB_PATH):
     L.kc_counter_read.argtypes = [_p, ctypes.c_char_p, ctypes.POINTER(_i64)]
     L.kcenter_gonzalez.argtypes = [_p, ctypes.POINTER(KcPoints), _i64, _i64,
                                    _p, _p, _p, _p]
+    L.kcenter_gonzalez_noalloc.argtypes = [_p, ctypes.POINTER(KcPoints),
+                                           _i64, _i64, _p, _p, _p, _p]
     L.kcenter_mrg.argtypes = [_p, ctypes.POINTER(KcPoints), _p, _i32, _i64,
                               _p, _p, _p, _p, _p, _p, _p, _p, _p]
     L.kcenter_mrg_rounds.argtypes = [_p, ctypes.POINTER(KcPoints), _i64, _i64,
@@ -103,7 +105,8 @@ def load_library(path=LIB_PATH):
     L.kcenter_batch.argtypes = [_p, _p, _i32, _p]
     for name in ("kc_create", "kc_set_option", "kc_device_status",
                  "kc_timing_read", "kc_counter_read",
-                 "kcenter_gonzalez", "kcenter_mrg", "kcenter_mrg_rounds",
+                 "kcenter_gonzalez", "kcenter_gonzalez_noalloc",
+                 "kcenter_mrg", "kcenter_mrg_rounds",
                  "kcenter_assign",
                  "kcenter_eim", "kcenter_batch"):
         getattr(L, name).restype = ctypes.c_int
@@ -251,6 +254,25 @@ def gonzalez(X, k, first=0, bf16=None, handle=None, out=None):
     centers, trace, nch = out
     p = points(X, bf16)
     h._check(load_library().kcenter_gonzalez(
+        h._h, ctypes.byref(p), int(k), int(first), _ptr(centers),
+        _ptr(trace), _ptr(nch), _stream()))
+    return centers, trace, nch
+
+
+def gonzalez_noalloc(X, k, first=0, handle=None, out=None):
+    """Gonzalez's traversal through the entry point that allocates no device
+    memory (its workspace is the library's fixed per-GPU array).  `out`, if
+    given, is (centers int64[k], trace f64[k], n_chosen int64[1]); with it
+    the call allocates nothing.  Returns those tensors (asynchronous)."""
+    h = handle or default_handle()
+    dev = X.device
+    if out is None:
+        out = (torch.empty(k, dtype=torch.int64, device=dev),
+               torch.empty(k, dtype=torch.float64, device=dev),
+               torch.empty(1, dtype=torch.int64, device=dev))
+    centers, trace, nch = out
+    p = points(X, None)
+    h._check(load_library().kcenter_gonzalez_noalloc(
         h._h, ctypes.byref(p), int(k), int(first), _ptr(centers),
         _ptr(trace), _ptr(nch), _stream()))
     return centers, trace, nch

@@ -525,6 +525,11 @@ int kc_create(kc_handle** out)
         delete h;
         return KC_ENOMEM;
     }
+    // the no-allocation entry point's array on this device
+    if (kc_noalloc_setup(h->device, &h->scratch) != hipSuccess) {
+        delete h;
+        return KC_EHIP;
+    }
     *out = h;
     return KC_OK;
 }

@@ -60,6 +60,7 @@ struct kc_handle {
     bool allow_resident = true;
     uint32_t spin_limit = 1u << 20;   // polls before a barrier wait gives up
     uint32_t* status_word = nullptr;  // device, see kc_device_status
+    void* scratch = nullptr;          // device address of the no-allocation array
     std::string last_error;
     std::map<std::string, DevBuf> bufs;
     std::map<std::string, std::vector<char>> shadows;
@@ -121,6 +122,9 @@ struct KcGonHost {
 };
 
 int kc_check_points(kc_handle* h, const kc_points* p, bool need_bf16_if_asked);
+// Device address of the no-allocation scratch array on `device` (current),
+// looked up once per device (kc_noalloc.hip).
+hipError_t kc_noalloc_setup(int device, void** out);
 // Plans a batched run: workspace, and the segment / tile / step tables
 // uploaded in order on stream s.  R.plan_hash identifies the plan's geometry
 // (every graph key built from a plan includes it).
