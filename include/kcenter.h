@@ -142,6 +142,32 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
                      void* stream);
 
 /*
+ * kcenter_gonzalez_resume -- Gonzalez's traversal continued from a saved
+ * prefix of centers (checkpoint / resume).  The traversal of Section 3.1
+ * picks each center from the centers chosen so far alone, so with
+ * prefix = the first p centers of an earlier run (same points, same or
+ * smaller k) the result is exactly the run with k centers.  Centers
+ * 0..p-1 are prefix[0..p-1], all kept as given; every later center is a
+ * farthest point (lowest index on ties) from the centers so far, until k
+ * are chosen or, after the prefix, every point coincides with a center.
+ * Runs on the FP32 points in either precision.
+ *   prefix        HOST int64 [p]: distinct indices in [0, n); 1 <= p <= k.
+ *                 Out-of-range or repeated indices, or p outside [1, k],
+ *                 return KC_EINVAL before any work.
+ *   k             centers wanted, 1 <= k < 2^24.
+ *   centers       device int64 [k] (-1 after an early stop), n_chosen
+ *                 device int64 [1].
+ *   radius_trace  device double [k] or NULL: entry t < n_chosen-1 is the FP64
+ *                 distance of center t+1 to its nearest of centers 0..t (for
+ *                 a free step: the covering radius after t+1 centers, as in
+ *                 kcenter_gonzalez); the last chosen entry is the exact FP64
+ *                 covering radius of all chosen centers; 0 after it.
+ */
+int kcenter_gonzalez_resume(kc_handle* h, const kc_points* pts, const int64_t* prefix,
+                            int64_t p, int64_t k, int64_t* centers, double* radius_trace,
+                            int64_t* n_chosen, void* stream);
+
+/*
  * kcenter_mrg -- two-round MRG (Algorithm 1 with one pass of its loop;
  * Lemma 2 gives the factor 4).  Round 1 runs Gonzalez(k) on each partition
  * (first center: the partition's first point), all partitions in the same

@@ -179,9 +179,9 @@ int64_t orc_gon_replay(const float *X, int64_t n, int d, int64_t ld,
  * prefix[0..p-1]; every later center is a farthest point (lowest index on
  * ties) from the centers so far.  Step t applies c_t to every point's squared
  * min-distance m_i and picks the next center (the forced one while t+1 < p).
- * The traversal ends after k centers, or at step t when the next center is
- * already at distance 0 from c_0..c_t (for a free step: every point is
- * covered).
+ * The forced centers are all kept (a saved prefix is taken as given); the
+ * traversal ends after k centers, or at a step t >= p-1 whose farthest
+ * point is already at distance 0 from c_0..c_t (every point is covered).
  * trace out [k]: for a step t that is followed by another center,
  *   sqrt(m of that center), its distance to c_0..c_t; for the last chosen
  *   step, sqrt(max_i m_i), the covering radius of all chosen centers; 0
@@ -216,7 +216,7 @@ int64_t orc_gon_resume(const float *X, int64_t n, int d, int64_t ld, int64_t k,
         for (int64_t i = 0; i < n; ++i)
             if (mind[i] > M) { M = mind[i]; a = i; }
         int64_t next = (t + 1 < p) ? prefix[t + 1] : a;
-        if (t == k - 1 || mind[next] == 0.0) {
+        if (t == k - 1 || (t + 1 >= p && mind[next] == 0.0)) {
             trace[t] = sqrt(M);   /* covering radius of the chosen centers */
             break;
         }

@@ -60,6 +60,7 @@ EXPORTS = ["kc_create", "kc_destroy", "kc_strerror", "kc_last_error",
            "kc_set_option", "kc_device_status", "kc_timing_read",
            "kc_counter_read",
            "kcenter_gonzalez", "kcenter_gonzalez_noalloc",
+           "kcenter_gonzalez_resume",
            "kcenter_mrg", "kcenter_mrg_rounds", "kcenter_assign", "kcenter_eim",
            "kcenter_batch"]
 
@@ -92,6 +93,8 @@ def load_library(path=LIB_PATH):
                                    _p, _p, _p, _p]
     L.kcenter_gonzalez_noalloc.argtypes = [_p, ctypes.POINTER(KcPoints),
                                            _i64, _i64, _p, _p, _p, _p]
+    L.kcenter_gonzalez_resume.argtypes = [_p, ctypes.POINTER(KcPoints), _p,
+                                          _i64, _i64, _p, _p, _p, _p]
     L.kcenter_mrg.argtypes = [_p, ctypes.POINTER(KcPoints), _p, _i32, _i64,
                               _p, _p, _p, _p, _p, _p, _p, _p, _p]
     L.kcenter_mrg_rounds.argtypes = [_p, ctypes.POINTER(KcPoints), _i64, _i64,
@@ -106,6 +109,7 @@ def load_library(path=LIB_PATH):
     for name in ("kc_create", "kc_set_option", "kc_device_status",
                  "kc_timing_read", "kc_counter_read",
                  "kcenter_gonzalez", "kcenter_gonzalez_noalloc",
+           "kcenter_gonzalez_resume",
                  "kcenter_mrg", "kcenter_mrg_rounds",
                  "kcenter_assign",
                  "kcenter_eim", "kcenter_batch"):
@@ -257,6 +261,25 @@ def gonzalez(X, k, first=0, bf16=None, handle=None, out=None):
         h._h, ctypes.byref(p), int(k), int(first), _ptr(centers),
         _ptr(trace), _ptr(nch), _stream()))
     return centers, trace, nch
+
+
+def gonzalez_resume(X, prefix, k, handle=None):
+    """Gonzalez's traversal with its first centers forced to `prefix` (a host
+    sequence of distinct indices, e.g. the first p centers of an earlier
+    run), continued to k centers.  Returns (centers int64[k], trace f64[k],
+    n_chosen int64[1]) as CUDA tensors (asynchronous)."""
+    import numpy as np
+    h = handle or default_handle()
+    dev = X.device
+    pre = np.ascontiguousarray(np.asarray(prefix, dtype=np.int64))
+    out = (torch.empty(k, dtype=torch.int64, device=dev),
+           torch.empty(k, dtype=torch.float64, device=dev),
+           torch.empty(1, dtype=torch.int64, device=dev))
+    p = points(X, None)
+    h._check(load_library().kcenter_gonzalez_resume(
+        h._h, ctypes.byref(p), pre.ctypes.data_as(_p), len(pre), int(k),
+        _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _stream()))
+    return out
 
 
 def gonzalez_noalloc(X, k, first=0, handle=None, out=None):

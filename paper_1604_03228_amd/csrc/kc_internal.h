@@ -85,6 +85,8 @@ bool kc_resident_rows_ok(int d, const float* xa, int64_t lda, uint64_t span);
 // xa_rows (only where kc_resident_rows_ok holds for the longest segment) the
 // points are loaded from xa too and xs is not read.  A wait that exceeds the
 // spin limit raises abort_flag and bit 0 of *status.
+// With `mind_in` (nullable, indexed like `mind`) every point's min-distance
+// starts as its value there (a run resumed after earlier centers).
 // With `blks` (device, one uint4 per block: segment, block within it, blocks
 // of the segment, first block of the segment) the launch runs several
 // segments of `segs` at once and base/len/first/k come from each segment
@@ -95,7 +97,7 @@ hipError_t kc_gon_resident(int d, int v, uint32_t G, const float* xs, uint64_t s
                            u64* keys, u64* slots, uint32_t* abort_flag,
                            uint32_t spin_limit, const float* xa, int64_t lda, int xa_rows,
                            uint32_t* status, const KcSeg* segs, const uint4* blks,
-                           hipStream_t s);
+                           hipStream_t s, const float* mind_in = nullptr);
 void kc_gon_finish(const KcGonRun& R, int64_t* centers, int64_t* n_chosen, double* trace,
                    double* radius_out, const int64_t* report_base, const int64_t* remap,
                    hipStream_t s);

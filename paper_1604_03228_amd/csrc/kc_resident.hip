@@ -103,7 +103,8 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
     const uint32_t* __restrict__ len_ptr, uint32_t first, int k, float* __restrict__ mind,
     u64* __restrict__ keys, u64* __restrict__ xbuf, uint32_t* __restrict__ abort_flag,
     uint32_t spin_limit, const float* __restrict__ xa, int64_t lda, int xa_rows,
-    uint32_t* __restrict__ status, const KcSeg* __restrict__ segs, const uint4* __restrict__ blks)
+    uint32_t* __restrict__ status, const KcSeg* __restrict__ segs, const uint4* __restrict__ blks,
+    const float* mind_in)
 {
     static_assert(KC_LA_WPTS * PPT <= KC_LA_NONE, "block-local index must fit in 16 bits");
     constexpr uint32_t CMAX = KcLaCap<PPT>::value;
@@ -204,6 +205,15 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
 #pragma unroll
             for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[p][j], cc0[j]);
             m[p] = s;
+        }
+        if (mind_in) {
+            // resumed run: the min-distances to the centers chosen before
+            // `first` (read by the lane that later writes them back)
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                const uint32_t i = i0 + p * KC_LA_WPTS;
+                if (i < len) m[p] = kc_fmin_nn(m[p], mind_in[base + i]);
+            }
         }
     }
 
@@ -721,12 +731,13 @@ static hipError_t launch_resident(uint32_t G, const float* xs, uint64_t stride,
                                   float* mind, u64* keys, u64* xbuf, uint32_t* abort_flag,
                                   uint32_t spin_limit, const float* xa, int64_t lda,
                                   int xa_rows, uint32_t* status, const KcSeg* segs,
-                                  const uint4* blks, hipStream_t s)
+                                  const uint4* blks, const float* mind_in, hipStream_t s)
 {
     void* args[] = {(void*)&xs,    (void*)&stride, (void*)&base, (void*)&len,
                     (void*)&len_ptr, (void*)&first, (void*)&k,      (void*)&mind, (void*)&keys,
                     (void*)&xbuf, (void*)&abort_flag, (void*)&spin_limit, (void*)&xa,
-                    (void*)&lda, (void*)&xa_rows, (void*)&status, (void*)&segs, (void*)&blks};
+                    (void*)&lda, (void*)&xa_rows, (void*)&status, (void*)&segs, (void*)&blks,
+                    (void*)&mind_in};
     return hipLaunchCooperativeKernel((const void*)k_gon_resident<D, PPT>, dim3(G),
                                       dim3(KC_LA_BLOCK), args, 0, s);
 }
@@ -821,7 +832,8 @@ hipError_t kc_gon_resident(int d, int v, uint32_t G, const float* xs, uint64_t s
                            uint32_t first, int k, float* mind,
                            u64* keys, u64* slots, uint32_t* abort_flag, uint32_t spin_limit,
                            const float* xa, int64_t lda, int xa_rows, uint32_t* status,
-                           const KcSeg* segs, const uint4* blks, hipStream_t s)
+                           const KcSeg* segs, const uint4* blks, hipStream_t s,
+                           const float* mind_in)
 {
     if (G == 0 || G > KC_LA_GMAX) return hipErrorInvalidValue;
     if (xa_rows && !xa) return hipErrorInvalidValue;
@@ -829,7 +841,7 @@ hipError_t kc_gon_resident(int d, int v, uint32_t G, const float* xs, uint64_t s
     case DD:                                                                             \
         return launch_resident<DD, PP>(G, xs, stride, base, len, len_ptr, first, k, mind, keys, \
                                        slots, abort_flag, spin_limit, xa, lda, xa_rows,      \
-                                       status, segs, blks, s);
+                                       status, segs, blks, mind_in, s);
     if (v == 0) {
         switch (d) {
             KC_RES_DIMS(KC_CASE)

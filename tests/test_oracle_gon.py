@@ -223,23 +223,28 @@ def test_resume_arbitrary_prefix_by_library_distances(orc):
                 nxt = c[t + 1]
                 if t + 1 >= p:
                     assert nxt == int(np.flatnonzero(m == m.max())[0])
-                assert m[nxt] > 0 and tr[t] == np.sqrt(m[nxt])
+                assert (m[nxt] > 0 or t + 1 < p) and tr[t] == np.sqrt(m[nxt])
             else:
                 assert tr[t] == np.sqrt(m.max())
-                # ended at k, or the next center was already covered
+                # ended at k, or after the prefix with every point covered
                 if got < k:
-                    nxt = pre[t + 1] if t + 1 < p else int(np.argmax(m))
-                    assert m[nxt] == 0
+                    assert got >= p and m.max() == 0
         assert np.all(c[got:] == -1) and np.all(tr[got:] == 0)
 
 
-def test_resume_covered_prefix_center_ends(orc):
-    # a forced center at distance 0 from the centers before it ends the run
+def test_resume_covered_prefix_center_is_kept(orc):
+    # a forced center at distance 0 from the centers before it is still a
+    # center (the prefix is taken as given); the run stops only at a free
+    # step whose farthest point is covered
     X = np.array([[0, 0], [5, 0], [0, 0], [9, 9]], np.float32)
     c, tr, got = orc.gon_resume(X, 4, [0, 1, 2])
-    assert got == 2 and c.tolist() == [0, 1, -1, -1]
-    # covering radius of {0, 1}: point 3 at (9, 9) is nearest to (5, 0)
-    assert tr[1] == np.sqrt(4 * 4 + 9 * 9) and tr[0] == 5.0
+    assert got == 4 and c.tolist() == [0, 1, 2, 3]
+    # trace: next center's distance to the centers before it, then the
+    # covering radius (0: every point is a center)
+    assert tr.tolist() == [5.0, 0.0, np.sqrt(4 * 4 + 9 * 9), 0.0]
+    c, tr, got = orc.gon_resume(X, 6, [0, 2, 1])
+    assert got == 4 and c.tolist() == [0, 2, 1, 3, -1, -1]
+    assert tr.tolist() == [0.0, 5.0, np.sqrt(4 * 4 + 9 * 9), 0.0, 0.0, 0.0]
 
 
 def test_resume_rejects_bad_prefix(orc):
