@@ -5,17 +5,24 @@
 Workload (one "step"): Gonzalez's traversal with k = 1000 on n = 1,000,000
 synthetic integer-grid points in d = 10 (five coordinates uniform in {1..4},
 five in {1..13}, stored FP32), first center 0, through kcenter_gonzalez:
-staging, all k steps, the FP64 radius trace and the exact FP64 radius.  The
-points are resident in HBM before the timed region.
+all k steps, the FP64 radius trace and the exact FP64 radius.  The points
+are resident in HBM before the timed region.
 
 Prints ONE JSON line: value = n*k distance updates per second over the K
 timed steps, plus
   roofline      the dominant kernel (live HIP-event timing from the library,
                 on the stream it launches on) against its MI355X peak;
-  cpu_baseline  the FP64 oracle on the host cores (same workload);
+  cpu_baseline  the FP64 oracle on the host cores, 1 thread and all cores;
+  configs       the other workloads: c1 (Gonzalez, 20,000 uniform 2-D
+                points, k = 20: microseconds per call), c2_k100 (the step's
+                workload at k = 100), c4_assign (the n x k assignment of the
+                5,000,000 x 41 workload against its BF16 MFMA peak), c5_batch
+                (the 256-instance mixed batch);
   mrg           two-round MRG on n = 8,000,000, d = 16, m = 64 Dirichlet
                 partitions, k = 200: FP32 vs BF16+rescore wall time and
-                whether the centers agree (when --no-mrg is not given).
+                whether the centers agree;
+  gon_bf16      Gonzalez k = 500 on the 5,000,000 x 41 workload, FP32 vs
+                BF16 stream + exact FP32 rescoring.
 """
 import argparse
 import json
@@ -29,11 +36,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak (dense)
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
 # VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane
 # operations per second (a wave64 instruction takes 4 cycles on a SIMD).
 # The quoted 157.3 TFLOP/s FP32 vector peak is this rate x 2 (FMA) x 2
 # (packed FP32); the engines use no packed FP32, so one FP32 instruction per
-# lane and cycle is their ceiling.
+# lane and cycle is their issue ceiling (reported beside the FLOP fraction).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -46,6 +56,8 @@ def parse():
     ap.add_argument("--k", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mrg", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip configs 1, 2 (k = 100), 4's assignment and 5")
     ap.add_argument("--engine", choices=["auto", "stream"], default="auto")
     ap.add_argument("--mrg-only", action="store_true",
                     help="only the MRG FP32 vs BF16 comparison")
@@ -104,17 +116,41 @@ def kernel_source_hash(files):
     return h.hexdigest()[:16]
 
 
+def _median_time(fn, runs=3, cap_s=60.0):
+    """Median wall time of `runs` calls (one call when it exceeds cap_s)."""
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+        if ts[-1] > cap_s:
+            break
+    return float(np.median(ts)), len(ts)
+
+
 def cpu_baseline(X, k):
+    """The FP64 oracle's Gonzalez on the step's points: on all host cores
+    (OpenMP over the per-point update loop) for the full k, and on one thread
+    for the first 100 centers (a bounded sample, the paper's sequential
+    setting); each the median of 3 runs."""
     import oracle
     cores = len(os.sched_getaffinity(0))
     used = oracle.set_threads(cores)
-    t0 = time.perf_counter()
-    oracle.gon(X, k, 0)
-    dt = time.perf_counter() - t0
-    return {"value": len(X) * k / dt, "unit": "dist-updates/s",
-            "cores": used, "kind": "oracle",
-            "sample": "full workload (n=%d, d=%d, k=%d), one run, %.1f s"
-                      % (len(X), X.shape[1], k, dt)}
+    dt, runs = _median_time(lambda: oracle.gon(X, k, 0))
+    out = {"value": len(X) * k / dt, "unit": "dist-updates/s",
+           "cores": used, "kind": "oracle",
+           "sample": "full workload (n=%d, d=%d, k=%d), median of %d runs, "
+                     "%.2f s each" % (len(X), X.shape[1], k, runs, dt)}
+    k1 = min(k, 100)
+    oracle.set_threads(1)
+    dt1, runs1 = _median_time(lambda: oracle.gon(X, k1, 0))
+    out["one_thread"] = {"value": len(X) * k1 / dt1, "unit": "dist-updates/s",
+                         "cores": 1,
+                         "sample": "n=%d, d=%d, first %d centers, median of %d "
+                                   "runs, %.2f s each" % (len(X), X.shape[1],
+                                                          k1, runs1, dt1)}
+    oracle.set_threads(used)
+    return out
 
 
 def stored_traffic(kernel, workload, sources):
@@ -187,6 +223,10 @@ def bench_mrg(kc, torch, steps):
     out["rounds_c250000_radius"] = float(r[2].item())
     h.close()
     out["workload"] = "mrg_gauss50_n8000000_d16_m64_k200"
+    # every partition fits the register-resident grid, so round 1 runs the
+    # same FP32 resident kernel in both modes: the BF16 comparison proper is
+    # the streamed pair
+    out["resident_rows_same_kernel"] = True
     out["speedup_bf16"] = out["fp32_ms"] / out["bf16_ms"]
     out["speedup_bf16_stream"] = out["fp32_stream_ms"] / out["bf16_stream_ms"]
     return out
@@ -334,9 +374,57 @@ def quality_sweep(kc, torch, sets=3):
     return out
 
 
-def bench_gon_bf16(kc, torch, steps):
+def bench_assign(kc, torch, Xd, B, centers, steps):
+    """kcenter_assign (labels and exact radius) of every point to `centers`,
+    in FP32 and with BF16 MFMA distances: ms per call, and the MFMA distance
+    kernel's time from the library's own timing spans."""
+    n, d = Xd.shape
+    k = centers.numel()
+    out = {}
+    labs = {}
+    for mode, bf in (("bf16", B), ("fp32", None)):
+        h = kc.Handle()
+        h.set_option("timing", 1)
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            for _ in range(2):
+                kc.assign(Xd, centers, bf16=bf, handle=h)
+            st.synchronize()
+            h.timing_read("assign_mfma")
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(steps):
+                lab, rad = kc.assign(Xd, centers, bf16=bf, handle=h)
+            e1.record(st)
+            st.synchronize()
+        kms, kl, _ = h.timing_read("assign_mfma")
+        out[mode + "_rescored_fp64"] = h.counter("assign_rescored")
+        out[mode + "_ms"] = e0.elapsed_time(e1) / steps
+        out[mode + "_mfma_kernel_ms"] = kms / max(kl, 1)
+        out[mode + "_radius"] = float(rad.item())
+        labs[mode] = lab.cpu().numpy()
+        h.close()
+    flops = 2.0 * n * k * d
+    per = out["bf16_mfma_kernel_ms"]
+    ach = flops / (per * 1e-3) / 1e12
+    kpad = -(-d // 32) * 32          # BF16 16x16x32 MFMA: K padded to 32
+    out.update({"n": n, "k": k, "d": d, "same_labels": bool(
+        np.array_equal(labs["bf16"], labs["fp32"])),
+        "roofline": {"kernel": "k_mindist_mfma (BF16 16x16x32)", "bound": "mfma",
+                     "achieved": ach, "peak": BF16_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": ach / BF16_MFMA_PEAK_TFLOPS,
+                     "work_per_launch": "2*n*k*d = %.4g flop (%.4g with K "
+                                        "padded to %d)" % (flops, 2.0 * n * k * kpad, kpad),
+                     "avg_launch_ms": per}})
+    return out
+
+
+def bench_gon_bf16(kc, torch, steps, cfg=None):
     """Gonzalez k=500 on the 5,000,000 x 41 mixed-scale workload, FP32 vs
-    BF16 stream + exact FP32 rescoring (same centers required)."""
+    BF16 stream + exact FP32 rescoring (same centers required); with `cfg`,
+    also the n x k assignment to those centers (cfg["c4_assign"])."""
     from paper_1604_03228_amd import workloads as W
     X, Xb = W.config4()
     Xd = torch.from_numpy(X).cuda()
@@ -369,7 +457,101 @@ def bench_gon_bf16(kc, torch, steps):
     out["same_centers"] = bool(np.array_equal(cents["fp32"], cents["bf16"]))
     out["speedup_bf16"] = out["fp32_ms"] / out["bf16_ms"]
     out["dist_updates_per_s_bf16"] = len(X) * k / (out["bf16_ms"] * 1e-3)
+    if cfg is not None:
+        a = bench_assign(kc, torch, Xd, B, torch.from_numpy(cents["fp32"]).cuda(), steps)
+        a["workload"] = "assign_mixed41_n5000000_k500"
+        a["radius_matches_gonzalez"] = a["bf16_radius"] == out["fp32_radius"]
+        cfg["c4_assign"] = a
     return out
+
+
+def time_gon(kc, torch, Xd, k, steps, warmup, resident=True):
+    """kcenter_gonzalez on the HBM-resident points Xd, timed over `steps`
+    calls on a non-default stream (so the library's HIP graphs apply), with
+    the library's own timing spans of the dominant kernel."""
+    h = kc.Handle(resident=resident)
+    h.set_option("timing", 1)
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    with torch.cuda.stream(st):
+        for _ in range(warmup):
+            kc.gonzalez(Xd, k, 0, handle=h)
+        st.synchronize()
+        for name in ("gon_resident", "gon_step"):
+            h.timing_read(name)           # drop warm-up spans
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record(st)
+        for _ in range(steps):
+            kc.gonzalez(Xd, k, 0, handle=h)
+        e1.record(st)
+        st.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+    status = h.device_status()
+    if status:
+        raise SystemExit("device status 0x%x" % status)
+    out = {"ms": e0.elapsed_time(e1) / steps, "wall": wall}
+    res_ms, res_l, _ = h.timing_read("gon_resident")
+    stp_ms, stp_l, _ = h.timing_read("gon_step")
+    if res_l > 0:
+        out.update(engine="k_gon_resident", kern_ms=res_ms, launches=res_l,
+                   sources=["kc_resident.hip", "kc_device.h"])
+    else:
+        out.update(engine="k_gon_step", kern_ms=stp_ms, launches=stp_l,
+                   sources=["kc_gon.hip", "kc_device.h"])
+    h.close()
+    return out
+
+
+def gon_roofline(n, d, k, g):
+    """Roofline of the dominant Gonzalez kernel.  Register-resident: bound by
+    FP32 vector arithmetic, 3d flop per update (a subtraction and a fused
+    multiply-add per coordinate) against the 157.3 TFLOP/s FP32 peak, with
+    the VALU issue-rate fraction beside it (2d + 1 instructions per update,
+    one integer min).  Streamed: bound by HBM, 4d + 8 bytes per point and
+    step against 8 TB/s."""
+    kern = g["engine"]
+    if kern == "k_gon_resident":
+        per = g["kern_ms"] / g["launches"]
+        flops = n * k * 3 * d
+        ach = flops / (per * 1e-3) / 1e12
+        ops = n * k * (2 * d + 1)
+        issue = ops / (per * 1e-3) / 1e12
+        roof = {"kernel": kern, "bound": "alu", "achieved": ach,
+                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP32_PEAK_TFLOPS,
+                "avg_launch_ms": per, "launches": g["launches"],
+                "work_per_launch": "%d updates x %d flop" % (n * k, 3 * d),
+                "issue_rate": {"achieved": issue, "peak": VALU_PEAK_TOPS,
+                               "unit": "T VALU lane-ops/s",
+                               "frac": issue / VALU_PEAK_TOPS,
+                               "ops_per_update": 2 * d + 1}}
+    else:
+        per = g["kern_ms"] / g["launches"]
+        byt = n * (4 * d + 8)             # read d coords + mind, write mind
+        ach = byt / (per * 1e-3) / 1e9
+        roof = {"kernel": kern, "bound": "hbm", "achieved": ach,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS,
+                "avg_launch_ms": per, "launches": g["launches"],
+                "work_per_launch": "%d points x %d B" % (n, 4 * d + 8)}
+    return kern, roof
+
+
+def bench_c1(kc, torch, W, steps=200):
+    """Gonzalez on 20,000 uniform 2-D points, k = 20 (latency-bound: report
+    microseconds per call and per step)."""
+    X = W.config1()
+    Xd = torch.from_numpy(X).cuda()
+    g = time_gon(kc, torch, Xd, 20, steps, 10)
+    return {"workload": "gon_uniform_n20000_d2_k20", "engine": g["engine"],
+            "us_per_call": g["ms"] * 1e3, "us_per_step": g["ms"] * 1e3 / 20,
+            "kernel_us_per_call": g["kern_ms"] / g["launches"] * 1e3,
+            "dist_updates_per_s": len(X) * 20 / (g["ms"] * 1e-3)}
 
 
 def main():
@@ -403,60 +585,12 @@ def main():
     n, d, k = 1_000_000, 10, a.k
     X = W.config2(n)
     Xd = torch.from_numpy(X).cuda()
-    h = kc.Handle(resident=(a.engine == "auto"))
-    h.set_option("timing", 1)
-    st = torch.cuda.Stream()
-    st.wait_stream(torch.cuda.current_stream())
-    torch.cuda.synchronize()
-    with torch.cuda.stream(st):
-        for _ in range(a.warmup):
-            c, tr, nch = kc.gonzalez(Xd, k, 0, handle=h)
-        st.synchronize()
-        for name in ("gon_resident", "gon_step"):
-            h.timing_read(name)           # drop warm-up spans
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        w0 = time.perf_counter()
-        e0.record(st)
-        for _ in range(a.steps):
-            c, tr, nch = kc.gonzalez(Xd, k, 0, handle=h)
-        e1.record(st)
-        st.synchronize()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - w0
-    ms = e0.elapsed_time(e1) / a.steps
-    status = h.device_status()
-    if status:
-        raise SystemExit("device status 0x%x" % status)
+    g = time_gon(kc, torch, Xd, k, a.steps, a.warmup, resident=(a.engine == "auto"))
+    ms, wall = g["ms"], g["wall"]
     value = n * k / (ms * 1e-3)
-
-    res_ms, res_l, _ = h.timing_read("gon_resident")
-    stp_ms, stp_l, _ = h.timing_read("gon_step")
-    if res_l > 0:
-        kern = "k_gon_resident"
-        srcs = ["kc_resident.hip", "kc_device.h"]
-        per = res_ms / res_l
-        ops = n * k * (2 * d + 1)         # sub + fma per coordinate, one min
-        ach = ops / (per * 1e-3) / 1e12
-        roof = {"kernel": kern, "bound": "alu", "achieved": ach,
-                "peak": VALU_PEAK_TOPS, "unit": "T VALU lane-ops/s",
-                "frac": ach / VALU_PEAK_TOPS,
-                "avg_launch_ms": per, "launches": res_l,
-                "work_per_launch": "%d updates x %d VALU ops" % (n * k, 2 * d + 1)}
-    else:
-        kern = "k_gon_step"
-        srcs = ["kc_gon.hip", "kc_device.h"]
-        per = stp_ms / stp_l
-        byt = n * (4 * d + 8)             # read d coords + mind, write mind
-        ach = byt / (per * 1e-3) / 1e9
-        roof = {"kernel": kern, "bound": "hbm", "achieved": ach,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS,
-                "avg_launch_ms": per, "launches": stp_l,
-                "work_per_launch": "%d points x %d B" % (n, 4 * d + 8)}
+    kern, roof = gon_roofline(n, d, k, g)
     roof["traffic"] = stored_traffic(kern, "gon_intgrid_n1000000_d10_k%d" % k,
-                                     srcs)
+                                     g["sources"])
 
     line = {"metric": "n*k dist-updates/s (Gonzalez, 1 GPU)",
             "value": value, "unit": "dist-updates/s", "n_gpus": 1,
@@ -469,13 +603,28 @@ def main():
                        "n": n, "d": d, "k": k, "first": 0,
                        "engine": kern},
             "roofline": roof}
-    h.close()
+    cfg = {}
+    if not a.no_configs:
+        cfg["c1"] = bench_c1(kc, torch, W)
+        g100 = time_gon(kc, torch, Xd, 100, a.steps, a.warmup)
+        kern100, roof100 = gon_roofline(n, d, 100, g100)
+        cfg["c2_k100"] = {"workload": "gon_intgrid_n1000000_d10_k100",
+                          "ms": g100["ms"],
+                          "dist_updates_per_s": n * 100 / (g100["ms"] * 1e-3),
+                          "roofline": roof100}
+    del Xd
     if not a.no_mrg:
         try:
             line["mrg"] = bench_mrg(kc, torch, max(2, min(a.steps, 5)))
-            line["gon_bf16"] = bench_gon_bf16(kc, torch, max(2, min(a.steps, 5)))
+            line["gon_bf16"] = bench_gon_bf16(kc, torch, max(2, min(a.steps, 5)),
+                                              cfg if not a.no_configs else None)
         except kc.KCenterError as e:
             line["mrg"] = {"error": str(e)}
+    if not a.no_configs:
+        b = bench_batch(kc, torch, 3)
+        cfg["c5_batch"] = b
+    if cfg:
+        line["configs"] = cfg
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(X, k)
     print(json.dumps(line))

@@ -108,7 +108,10 @@ int kc_timing_read(kc_handle* h, const char* name, double* ms, int64_t* launches
  * number rescored exactly in FP32.  "eim_exact": candidates whose keep /
  * remove decision the most recent kcenter_eim call on the handle made in
  * exact FP64 (summed over its iterations; a batch counts its last EIM
- * problem).  KC_EINVAL for an unknown name. */
+ * problem).  "assign_rescored": points the most recent assignment on the
+ * handle rescored in FP64 (uncertified nearest center, or a possible
+ * maximiser of the radius; a point may count twice).  KC_EINVAL for an
+ * unknown name. */
 int kc_counter_read(kc_handle* h, const char* name, int64_t* value);
 
 /* Synchronises `stream`, then reads and clears the handle's device status

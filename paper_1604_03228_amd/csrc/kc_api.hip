@@ -631,6 +631,9 @@ int kc_counter_read(kc_handle* h, const char* name, int64_t* value)
     } else if (!strcmp(name, "eim_exact")) {
         *value = h->eim_exact;
         return KC_OK;
+    } else if (!strcmp(name, "assign_rescored")) {
+        src = h->last_assign_nlist;   // one count
+        words = 1;
     } else {
         return h->fail(KC_EINVAL, "unknown counter '%s'", name);
     }

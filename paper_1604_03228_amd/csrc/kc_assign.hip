@@ -11,50 +11,60 @@
 // v_mfma_f32_16x16x32_bf16 (K = 32), both accumulating in FP32.  Centers are
 // staged through LDS in chunks; points stream from the caller's array.
 //
-// Certification (used by the assignment and by EIM's distance pass): with
-//     g = (6d + 32) u,  err = g (|x| + max_i |c_i|)^2
-// every exact squared distance lies within err of |x|^2 + v_i (BF16 inputs
-// add the rounding radius E = e_x + max e_c in the square-root domain).  A
-// point whose second-best lower bound exceeds its best upper bound has a
+// Certification (used by the assignment, the covering radius and EIM's
+// distance pass), per pair of a point x and a center c, with a = |x| and
+// b = |c| of the values fed to the MFMA:
+//     |(|x|^2 + v) - D^| <= g (a + b)^2,   g = (6d + 40) u
+// where D^ is their exact squared distance, and for BF16 inputs the exact
+// distance D of the FP32 points satisfies |sqrt(D) - sqrt(D^)| <= E = e_x +
+// e_c (their rounding radii), hence
+//     D >= |x|^2 + v - g (a + b)^2 - 2 E (a + b).
+// This lower bound is linear in per-center constants, so the kernel keeps,
+// per point, the best v with its lowest center index and the smallest lower
+// bound over every other center (three FMAs per pair).  A point whose
+// smallest other lower bound exceeds the best center's upper bound has a
 // certified nearest center; every other point is rescored exactly in FP64.
+// Bounds per pair, not through the largest center norm: Gonzalez's centers
+// include the data's outliers, whose norms would otherwise swamp the bound
+// of every ordinary point.
 #include "kc_device.h"
 #include "kc_internal.h"
 
 typedef float kc_v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 kc_v8bf __attribute__((ext_vector_type(8)));
 
+// Per point and lane: the best v with its center index, the lower-bound
+// term w of that center, and the smallest w over every other center (LAB),
+// or over all centers (without LAB).
 struct KcBest {
     float m1;
     int a1;
-    float m2;
+    float wb;
+    float l2;
 };
 
-__device__ __forceinline__ void kc_best_push(KcBest& b, float v, int idx)
+// Labels pass: push center idx with its v and w.
+__device__ __forceinline__ void kc_best_push(KcBest& b, float v, float w, int idx)
 {
     // centers arrive in ascending index order per lane: strict < keeps the
-    // lower index on ties, and a tie leaves m2 == m1 (ambiguous)
+    // lower index on ties, and a tied center's w (below its v) then stays in
+    // l2, leaving the point uncertified
     if (v < b.m1) {
-        b.m2 = b.m1;
+        b.l2 = fminf(b.l2, b.wb);
         b.m1 = v;
         b.a1 = idx;
+        b.wb = w;
     } else {
-        b.m2 = fminf(b.m2, v);
+        b.l2 = fminf(b.l2, w);
     }
 }
 
 __device__ __forceinline__ KcBest kc_best_merge(KcBest a, KcBest o)
 {
     const bool take_o = (o.m1 < a.m1) || (o.m1 == a.m1 && o.a1 < a.a1);
-    KcBest r;
-    if (take_o) {
-        r.m1 = o.m1;
-        r.a1 = o.a1;
-        r.m2 = fminf(o.m2, a.m1);
-    } else {
-        r.m1 = a.m1;
-        r.a1 = a.a1;
-        r.m2 = fminf(a.m2, o.m1);
-    }
+    KcBest r = take_o ? o : a;
+    const float lw = take_o ? a.wb : o.wb;
+    r.l2 = fminf(fminf(a.l2, o.l2), lw);
     return r;
 }
 
@@ -63,7 +73,8 @@ __device__ __forceinline__ KcBest kc_best_xor(KcBest b, int mask)
     KcBest o;
     o.m1 = __shfl_xor(b.m1, mask, 64);
     o.a1 = __shfl_xor(b.a1, mask, 64);
-    o.m2 = __shfl_xor(b.m2, mask, 64);
+    o.wb = __shfl_xor(b.wb, mask, 64);
+    o.l2 = __shfl_xor(b.l2, mask, 64);
     return kc_best_merge(b, o);
 }
 
@@ -82,22 +93,27 @@ __host__ __device__ constexpr int kc_md_pt(bool bf, int ks)
 }
 
 // BF: BF16 inputs.  KS: MFMA K-steps (K = 4*KS for FP32, 32*KS for BF16).
-// LAB: keep the best index and the second-best value (labels need them);
-// without it only the smallest value per point is kept (a covering radius or
-// a distance to a set needs nothing else), and out_arg / out_m2 are unused.
+// LAB: labels pass, per point the best center's index (arg), its v (m1),
+// its lower-bound term (lob) and the smallest one of the other centers
+// (lo2); without LAB (a covering radius, a distance to a set) only the
+// smallest v (m1).  Always |x|^2 of the MFMA inputs (nx).  FP32 passes with
+// a local origin C.mu subtract it from points and centers as they load.
 template <bool BF, int KS, bool LAB>
 __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
-    const float* __restrict__ X, const uint16_t* __restrict__ Xb, int64_t ld, uint32_t n,
-    int d, const float* __restrict__ Cf, const uint16_t* __restrict__ Cb,
-    const float* __restrict__ cnorm, uint32_t kpad, uint32_t chunk,
-    int32_t* __restrict__ out_arg, float* __restrict__ out_m1, float* __restrict__ out_m2,
-    float* __restrict__ out_nx)
+    const float* __restrict__ X, const uint16_t* __restrict__ Xb, const float* __restrict__ ex,
+    int64_t ld, uint32_t n, int d, float gm, KcCenters C, uint32_t chunk, KcMinOut O)
 {
     constexpr int DP = BF ? KS * 32 : KS * 4;   // padded K
     constexpr int KC_MD_PT = kc_md_pt(BF, KS);
     extern __shared__ __align__(16) unsigned char kc_smem[];
-    float* s_norm = (float*)kc_smem;                          // [chunk]
-    void* s_c = (void*)(kc_smem + sizeof(float) * chunk);     // [chunk][DP]
+    float* s_norm = (float*)kc_smem;                          // [chunk] cn
+    float* s_cnl = s_norm + chunk;                            // [chunk] cnl
+    float* s_len = s_cnl + chunk;                             // [chunk] |c|
+    float* s_cer = s_len + chunk;                             // [chunk] e_c (BF16)
+    void* s_c = (void*)(s_cer + (BF ? chunk : 0));            // [chunk][DP]
+    const float* __restrict__ Cf = C.mu ? C.Ct : C.Cf;
+    const uint16_t* __restrict__ Cb = C.Cb;
+    const uint32_t kpad = C.kpad;
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -119,6 +135,7 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
             for (int ks = 0; ks < KS; ++ks) {
                 const int kk = ks * 4 + grp;
                 float v = (ok && kk < d) ? X[p * ld + kk] : 0.f;
+                if (C.mu && kk < d) v = ok ? v - C.mu[kk] : 0.f;
                 bf[pt][BF ? 0 : ks] = v;
                 nxp[pt] = __builtin_fmaf(v, v, nxp[pt]);
             }
@@ -139,18 +156,44 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
         }
     }
 
+    // |x|^2 over the four lane groups, then the point's coefficients of the
+    // per-pair lower bound: P1 multiplies |c|, P2 multiplies e_c
+    float P1[KC_MD_PT], P2[KC_MD_PT];
+#pragma unroll
+    for (int pt = 0; pt < KC_MD_PT; ++pt) {
+        float nx = nxp[pt];
+        nx += __shfl_xor(nx, 16, 64);
+        nx += __shfl_xor(nx, 32, 64);
+        nxp[pt] = nx;
+        if (LAB) {
+            const uint64_t p = p0 + pt * 16 + col;
+            const float a = sqrtf(nx) * (1.f + (float)(d + 4) * 5.9604645e-8f) * (1.f + 1e-6f);
+            const float e = (BF && ex && p < n) ? ex[p] : 0.f;
+            P1[pt] = (2.f * gm * a + 2.f * e) * (1.f + 1e-6f);
+            P2[pt] = 2.f * a * (1.f + 1e-6f);
+        }
+    }
+
     KcBest best[KC_MD_PT];
 #pragma unroll
     for (int pt = 0; pt < KC_MD_PT; ++pt) {
         best[pt].m1 = __builtin_inff();
-        best[pt].m2 = __builtin_inff();
         best[pt].a1 = 0x7FFFFFFF;
+        best[pt].wb = __builtin_inff();
+        best[pt].l2 = __builtin_inff();
     }
 
     for (uint32_t c0 = 0; c0 < kpad; c0 += chunk) {
         const uint32_t cn = min(chunk, kpad - c0);
         __syncthreads();
-        for (uint32_t q = threadIdx.x; q < cn; q += blockDim.x) s_norm[q] = cnorm[c0 + q];
+        for (uint32_t q = threadIdx.x; q < cn; q += blockDim.x) {
+            s_norm[q] = C.cn[c0 + q];
+            if (LAB) {
+                s_cnl[q] = C.cnl[c0 + q];
+                s_len[q] = C.clen[c0 + q];
+                if (BF) s_cer[q] = C.cerr[c0 + q];
+            }
+        }
         if (!BF) {
             const float4* src = (const float4*)(Cf + (uint64_t)c0 * DP);
             float4* dst = (float4*)s_c;
@@ -177,6 +220,12 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
                     ab[BF ? ks : 0] = *(const kc_v8bf*)(cs + ks * 32 + grp * 8);
             }
             const float4 nc4 = *(const float4*)(s_norm + ct + grp * 4);
+            float4 nl4 = make_float4(0.f, 0.f, 0.f, 0.f), cb4 = nl4, ce4 = nl4;
+            if (LAB) {
+                nl4 = *(const float4*)(s_cnl + ct + grp * 4);
+                cb4 = *(const float4*)(s_len + ct + grp * 4);
+                if (BF) ce4 = *(const float4*)(s_cer + ct + grp * 4);
+            }
 #pragma unroll
             for (int pt = 0; pt < KC_MD_PT; ++pt) {
                 kc_v4f acc = {0.f, 0.f, 0.f, 0.f};
@@ -191,14 +240,24 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
                                                                       bb[pt][BF ? ks : 0],
                                                                       acc, 0, 0, 0);
                 }
+                // v = |c|^2 - 2 x.c; labels: w = v - (g b^2 + 2 e_c b) - P1 b
+                // - P2 e_c (padding centers have cn = cnl = +inf, so they
+                // never count)
                 if (LAB) {
                     const int ib = (int)(c0 + ct) + grp * 4;
-                    kc_best_push(best[pt], __builtin_fmaf(-2.f, acc[0], nc4.x), ib + 0);
-                    kc_best_push(best[pt], __builtin_fmaf(-2.f, acc[1], nc4.y), ib + 1);
-                    kc_best_push(best[pt], __builtin_fmaf(-2.f, acc[2], nc4.z), ib + 2);
-                    kc_best_push(best[pt], __builtin_fmaf(-2.f, acc[3], nc4.w), ib + 3);
+                    const float q1 = P1[pt], q2 = P2[pt];
+                    auto pair = [&](float a, float cnv, float cnlv, float bv, float ev, int idx) {
+                        const float v = __builtin_fmaf(-2.f, a, cnv);
+                        float w = __builtin_fmaf(-2.f, a, cnlv);
+                        w = __builtin_fmaf(-q1, bv, w);
+                        if (BF) w = __builtin_fmaf(-q2, ev, w);
+                        kc_best_push(best[pt], v, w, idx);
+                    };
+                    pair(acc[0], nc4.x, nl4.x, cb4.x, ce4.x, ib + 0);
+                    pair(acc[1], nc4.y, nl4.y, cb4.y, ce4.y, ib + 1);
+                    pair(acc[2], nc4.z, nl4.z, cb4.z, ce4.z, ib + 2);
+                    pair(acc[3], nc4.w, nl4.w, cb4.w, ce4.w, ib + 3);
                 } else {
-                    // padding centers have norm +inf, so they never win
                     float v = fminf(__builtin_fmaf(-2.f, acc[0], nc4.x),
                                     __builtin_fmaf(-2.f, acc[1], nc4.y));
                     v = fminf(v, fminf(__builtin_fmaf(-2.f, acc[2], nc4.z),
@@ -219,17 +278,15 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
             b.m1 = fminf(b.m1, __shfl_xor(b.m1, 16, 64));
             b.m1 = fminf(b.m1, __shfl_xor(b.m1, 32, 64));
         }
-        float nx = nxp[pt];
-        nx += __shfl_xor(nx, 16, 64);
-        nx += __shfl_xor(nx, 32, 64);
         const uint64_t p = p0 + pt * 16 + col;
         if (grp == 0 && p < n) {
             if (LAB) {
-                out_arg[p] = b.a1;
-                out_m2[p] = b.m2;
+                O.arg[p] = b.a1;
+                O.lo2[p] = b.l2;
+                O.lob[p] = b.wb;
             }
-            out_m1[p] = b.m1;
-            out_nx[p] = nx;
+            O.m1[p] = b.m1;
+            O.nx[p] = nxp[pt];
         }
     }
 }
@@ -241,12 +298,12 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
 __global__ void k_stage_centers(const float* __restrict__ X, const uint16_t* __restrict__ Xb,
                                 int64_t ld, int d, uint32_t n, const int64_t* __restrict__ idx,
                                 const uint32_t* __restrict__ idx32, uint32_t k,
-                                const int64_t* __restrict__ k_dev, uint32_t kpad, int dp,
-                                float* __restrict__ Cf, uint16_t* __restrict__ Cb,
-                                float* __restrict__ cnorm, float* __restrict__ cmax,
+                                const int64_t* __restrict__ k_dev, KcCenters C,
                                 uint32_t* __restrict__ status)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t kpad = C.kpad;
+    const int dp = C.dp;
     if (i >= kpad) return;
     if (k_dev && (int64_t)k > *k_dev) k = (uint32_t)(*k_dev < 0 ? 0 : *k_dev);
     int64_t ri = 0;
@@ -259,89 +316,138 @@ __global__ void k_stage_centers(const float* __restrict__ X, const uint16_t* __r
     }
     if (i >= k) {
         for (int j = 0; j < dp; ++j) {
-            if (Cf) Cf[(uint64_t)i * dp + j] = 0.f;
-            if (Cb) Cb[(uint64_t)i * dp + j] = 0;
+            if (C.Cf) C.Cf[(uint64_t)i * dp + j] = 0.f;
+            if (C.Ct) C.Ct[(uint64_t)i * dp + j] = 0.f;
+            if (C.Cb) C.Cb[(uint64_t)i * dp + j] = 0;
         }
-        cnorm[i] = __builtin_inff();
+        C.cn[i] = __builtin_inff();
+        C.cnl[i] = __builtin_inff();
+        C.clen[i] = 0.f;
+        if (C.cerr) C.cerr[i] = 0.f;
         return;
     }
     const uint64_t r = (uint64_t)ri;
-    double nn = 0.0, ee = 0.0;
+    double nn = 0.0, ee = 0.0, nb = 0.0;
     float nf = 0.f;
     for (int j = 0; j < dp; ++j) {
         const float v = j < d ? X[r * ld + j] : 0.f;
-        if (Cf) Cf[(uint64_t)i * dp + j] = v;
-        if (Cb) {
+        if (C.Cf) C.Cf[(uint64_t)i * dp + j] = v;
+        if (C.Ct) C.Ct[(uint64_t)i * dp + j] = (C.mu && j < d) ? v - C.mu[j] : v;
+        if (C.Cb) {
             const uint16_t h = j < d ? Xb[r * ld + j] : (uint16_t)0;
-            Cb[(uint64_t)i * dp + j] = h;
+            C.Cb[(uint64_t)i * dp + j] = h;
             const float f = kc_bf16_to_f32(h);
             nf = __builtin_fmaf(f, f, nf);
+            nb += (double)f * (double)f;
             const double e = (double)f - (double)v;
             ee += e * e;
+        } else {
+            // the value the MFMA pass loads: translated to the local origin
+            const float t = (C.mu && j < d) ? v - C.mu[j] : v;
+            nf = __builtin_fmaf(t, t, nf);
+            nn += (double)t * (double)t;
         }
-        nn += (double)v * (double)v;
     }
-    // norm used in v_i: of the values fed to the MFMA
-    cnorm[i] = Cb ? nf : (float)nn;
-    const float len = Cb ? sqrtf(nf) : (float)sqrt(nn);
-    kc_atomic_max_f32_nonneg(&cmax[0], len * (1.f + 1e-6f));
-    if (Cb) kc_atomic_max_f32_nonneg(&cmax[1], (float)(sqrt(ee) * (1.0 + 1e-12)) * (1.f + 1e-6f));
+    // the norm used in v: of the values fed to the MFMA, in FP32 as the
+    // kernel's error bound assumes; |c| and e_c rounded up
+    const double b = sqrt(C.Cb ? nb : nn) * (1.0 + 1e-6);
+    const double e = C.Cb ? sqrt(ee) * (1.0 + 1e-6) : 0.0;
+    const double g = kc_md_gamma(d);
+    C.cn[i] = nf;
+    C.cnl[i] = (float)((double)nf - (g * b * b + 2.0 * e * b));
+    C.clen[i] = (float)b * (1.f + 1e-6f);
+    if (C.cerr) C.cerr[i] = (float)e * (1.f + 1e-6f);
+    kc_atomic_max_f32_nonneg(&C.cmax[0], (float)b * (1.f + 1e-6f));
+    if (C.Cb) kc_atomic_max_f32_nonneg(&C.cmax[1], (float)e * (1.f + 1e-6f));
 }
 
-// Per-point BF16 rounding radius e_x = |bf16(x) - x| (FP64, rounded up).
-__global__ void k_bf16_err(const float* __restrict__ X, const uint16_t* __restrict__ Xb,
-                           int64_t ld, int d, uint32_t n, float* __restrict__ ex)
+// mu[j] = the median (the lower middle value) of coordinate j over m points
+// spread evenly over the n rows: block j ranks its m values by counting.
+#define KC_LO_SAMPLE 1024
+__global__ __launch_bounds__(256) void k_local_origin(const float* __restrict__ X, int64_t ld,
+                                                      uint32_t n, float* __restrict__ mu)
 {
-    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    double ee = 0.0;
-    for (int j = 0; j < d; ++j) {
-        const double e = (double)kc_bf16_to_f32(Xb[(uint64_t)p * ld + j]) -
-                         (double)X[(uint64_t)p * ld + j];
-        ee += e * e;
+    __shared__ float sv[KC_LO_SAMPLE];
+    const int j = blockIdx.x;
+    const uint32_t m = n < KC_LO_SAMPLE ? n : KC_LO_SAMPLE;
+    const uint32_t want = (m - 1) / 2;
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x)
+        sv[i] = X[((uint64_t)i * n / m) * (uint64_t)ld + j];
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+        const float v = sv[i];
+        uint32_t below = 0, equal = 0;
+        for (uint32_t q = 0; q < m; ++q) {
+            below += sv[q] < v;
+            equal += sv[q] == v;
+        }
+        if (below <= want && want < below + equal) mu[j] = v;   // all writers agree
     }
-    ex[p] = (float)(sqrt(ee) * (1.0 + 1e-12)) * (1.f + 1e-6f);
+}
+
+// Per-point BF16 rounding radius e_x = |bf16(x) - x| (FP64, rounded up).  A
+// block takes 64 points, reads their rows through LDS (consecutive threads
+// on consecutive elements, so the reads coalesce), 64 coordinates per pass,
+// and thread i sums point i's squared differences in coordinate order.
+__global__ __launch_bounds__(256) void k_bf16_err(const float* __restrict__ X,
+                                                  const uint16_t* __restrict__ Xb, int64_t ld,
+                                                  int d, uint32_t n, float* __restrict__ ex)
+{
+    __shared__ double se[64][65];
+    const uint32_t p0 = blockIdx.x * 64u;
+    double acc = 0.0;
+    for (int j0 = 0; j0 < d; j0 += 64) {
+        const uint32_t w = (uint32_t)min(64, d - j0);
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < 64u * w; e += blockDim.x) {
+            const uint32_t i = e / w, j = e - i * w;
+            double v = 0.0;
+            if (p0 + i < n) {
+                const uint64_t at = (uint64_t)(p0 + i) * (uint64_t)ld + (uint64_t)(j0 + j);
+                v = (double)kc_bf16_to_f32(Xb[at]) - (double)X[at];
+                v = v * v;
+            }
+            se[i][j] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < 64)
+            for (uint32_t j = 0; j < w; ++j) acc += se[threadIdx.x][j];
+    }
+    if (threadIdx.x < 64 && p0 + threadIdx.x < n)
+        ex[p0 + threadIdx.x] = (float)(sqrt(acc) * (1.0 + 1e-12)) * (1.f + 1e-6f);
 }
 
 // ---------------------------------------------------------------------------
 // assignment epilogue: certify, collect ambiguous points, radius lower bound
 
-__device__ __forceinline__ double kc_lo_bound(double v, double err, double E)
+// Append `val` to list for every thread whose `pred` holds, one atomic per
+// block (hundreds of thousands of appends from every wave of the grid would
+// otherwise queue at one word).  Every thread of the block must call it.
+__device__ __forceinline__ void kc_block_append(bool pred, uint32_t val, uint32_t* list,
+                                                uint32_t* nlist)
 {
-    double a = v - err;
-    if (a < 0.0) a = 0.0;
-    double r = sqrt(a) - E;
-    if (r < 0.0) r = 0.0;
-    return r * r * (1.0 - 1e-12);
-}
-__device__ __forceinline__ double kc_hi_bound(double v, double err, double E)
-{
-    const double r = sqrt(v + err) + E;
-    return r * r * (1.0 + 1e-12);
-}
-
-// Append `val` to list for every lane whose `pred` holds, one atomic per
-// wave.  All 64 lanes must call it together.
-__device__ __forceinline__ void kc_wave_append(bool pred, uint32_t val, uint32_t* list,
-                                               uint32_t* nlist)
-{
+    __shared__ uint32_t s_cnt[16];
+    __shared__ uint32_t s_base;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const u64 b = __ballot(pred);
-    if (b == 0) return;
-    const int lane = threadIdx.x & 63;
-    const int leader = __builtin_ctzll(b);
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(nlist, (uint32_t)__builtin_popcountll(b));
-    base = (uint32_t)__shfl((int)base, leader, 64);
-    if (pred) list[base + (uint32_t)__builtin_popcountll(b & ((1ull << lane) - 1ull))] = val;
+    if (lane == 0) s_cnt[wave] = (uint32_t)__builtin_popcountll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += s_cnt[w];
+        s_base = tot ? atomicAdd(nlist, tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t off = s_base;
+    for (int w = 0; w < wave; ++w) off += s_cnt[w];
+    if (pred) list[off + (uint32_t)__builtin_popcountll(b & ((1ull << lane) - 1ull))] = val;
 }
 
 // With labels == NULL only the radius is wanted: an ambiguous point matters
 // only if its upper bound reaches the largest lower bound, and
 // k_radius_candidates lists exactly those, so ambiguity lists nothing.
-__global__ void k_assign_epilogue(uint32_t n, int d, const int32_t* __restrict__ arg,
-                                  const float* __restrict__ m1, const float* __restrict__ m2,
-                                  const float* __restrict__ nxv, const float* __restrict__ ex,
-                                  const float* __restrict__ cmax, int32_t* __restrict__ labels,
+__global__ void k_assign_epilogue(uint32_t n, int d, KcMinOut O, const float* __restrict__ ex,
+                                  KcCenters C, int32_t* __restrict__ labels,
                                   float* __restrict__ hi_out, uint32_t* __restrict__ list,
                                   uint32_t* __restrict__ nlist, float* __restrict__ lo_max)
 {
@@ -349,25 +455,15 @@ __global__ void k_assign_epilogue(uint32_t n, int d, const int32_t* __restrict__
     float lo_f = 0.f;
     bool amb = false;
     if (p < n) {
-        const double g = (6.0 * d + 32.0) * 5.9604644775390625e-8;
-        const double nx = nxv[p];
-        const double xl = sqrt(nx) * (1.0 + 1e-6);
-        const double s = xl + (double)cmax[0];
-        const double err = g * s * s + 1e-30 * d;
-        const double E = ex ? (double)ex[p] + (double)cmax[1] : 0.0;
-        const double d1 = nx + (double)m1[p];
-        const double hi1 = kc_hi_bound(d1, err, E);
-        const double lo1 = kc_lo_bound(d1, err, E);
+        const KcMdBounds B = kc_md_bounds(O, p, ex, C, d, labels != nullptr);
         if (labels) {
-            const double d2 = nx + (double)m2[p];
-            const double lo2 = kc_lo_bound(d2, err, E);
-            amb = !(lo2 > hi1);
-            labels[p] = amb ? -1 : arg[p];
+            amb = !(B.lo_other > B.hi);
+            labels[p] = amb ? -1 : O.arg[p];
         }
-        hi_out[p] = (float)hi1 * (1.f + 1e-6f);
-        lo_f = (float)lo1 * (1.f - 1e-6f);
+        hi_out[p] = (float)B.hi * (1.f + 1e-6f);
+        lo_f = (float)B.lo_min * (1.f - 1e-6f);
     }
-    kc_wave_append(amb, p, list, nlist);
+    kc_block_append(amb, p, list, nlist);
     // block max of the lower bounds, one atomic per block
     __shared__ float red[4];
     float v = lo_f;
@@ -393,49 +489,129 @@ __global__ void k_radius_candidates(uint32_t n, const float* __restrict__ hi,
 {
     const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     const float L = *lo_max;
-    kc_wave_append(p < n && hi[p] >= L, p, list, nlist);
+    kc_block_append(p < n && hi[p] >= L, p, list, nlist);
 }
 
-// One wave per listed point: exact FP64 nearest center (lowest position on
-// ties) over all k centers; label and radius^2 (as bits of a double).
-__global__ void k_rescore_f64(const float* __restrict__ X, int64_t ld, int d,
-                              const float* __restrict__ Cf, int dp, uint32_t k,
-                              const int64_t* __restrict__ k_dev,
-                              const uint32_t* __restrict__ list,
-                              const uint32_t* __restrict__ nlist, uint32_t cap,
-                              int32_t* __restrict__ labels, double* __restrict__ radius2)
+// Exact FP64 nearest center (lowest position on ties) of every listed point,
+// with its label and radius^2 (as bits of a double).  A block takes 16 listed
+// points at a time (four per wave, one after another, each held in VGPRs)
+// and streams the k centers through LDS, rows at an odd pitch so the 64 lanes of a
+// wave, each on its own center, read distinct banks; a wave reduces its lanes' minima
+// per point, and the per-point minima carry over LDS chunks.  The distance
+// sums separately rounded squares in coordinate order, as the FP64
+// reference does.
+#define KC_RS_FLOATS 12288   // 48 KiB of center coordinates per LDS chunk
+#define KC_RS_PTS 16         // listed points per block pass
+template <int D>
+__global__ __launch_bounds__(256) void k_rescore_f64(const float* __restrict__ X, int64_t ld,
+                                                     int d_rt, const float* __restrict__ Cf,
+                                                     int dp, uint32_t k,
+                                                     const int64_t* __restrict__ k_dev,
+                                                     const uint32_t* __restrict__ list,
+                                                     const uint32_t* __restrict__ nlist,
+                                                     uint32_t cap, int32_t* __restrict__ labels,
+                                                     double* __restrict__ radius2)
 {
-    const int lane = threadIdx.x & 63;
+    const int d = D > 0 ? D : d_rt;
+    const uint32_t pitch = (uint32_t)d | 1u;
+    __shared__ float sC[KC_RS_FLOATS];
+    __shared__ float sP[KC_RS_PTS][KC_MAXD];
+    __shared__ double sBest[KC_RS_PTS];
+    __shared__ int sArg[KC_RS_PTS];
     if (k_dev && (int64_t)k > *k_dev) k = (uint32_t)(*k_dev < 0 ? 0 : *k_dev);
     uint32_t nl = *nlist;
     if (nl > cap) nl = cap;
-    const uint32_t waves = gridDim.x * (blockDim.x / 64);
-    for (uint32_t q = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); q < nl; q += waves) {
-        const uint64_t p = list[q];
-        const float* xp = X + p * ld;
-        double best = __builtin_inf();
-        int bj = 0x7FFFFFFF;
-        for (uint32_t j = lane; j < k; j += 64) {
-            const float* cj = Cf + (uint64_t)j * dp;
-            double s = 0.0;
-            for (int u = 0; u < d; ++u) s = kc_d64_step(s, (double)xp[u], (double)cj[u]);
-            if (s < best) {
-                best = s;
-                bj = (int)j;
+    const uint32_t per = KC_RS_FLOATS / pitch;   // centers per chunk
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (uint32_t b0 = blockIdx.x * KC_RS_PTS; b0 < nl; b0 += gridDim.x * KC_RS_PTS) {
+        const uint32_t np = min((uint32_t)KC_RS_PTS, nl - b0);
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < np * (uint32_t)d; e += blockDim.x) {
+            const uint32_t q = e / (uint32_t)d, u = e - q * (uint32_t)d;
+            sP[q][u] = X[(uint64_t)list[b0 + q] * (uint64_t)ld + u];
+        }
+        if (threadIdx.x < KC_RS_PTS) {
+            sBest[threadIdx.x] = __builtin_inf();
+            sArg[threadIdx.x] = 0x7FFFFFFF;
+        }
+        for (uint32_t c0 = 0; c0 < k; c0 += per) {
+            const uint32_t cn = min(per, k - c0);
+            __syncthreads();
+            for (uint32_t e = threadIdx.x; e < cn * (uint32_t)d; e += blockDim.x) {
+                const uint32_t c = e / (uint32_t)d, u = e - c * (uint32_t)d;
+                sC[c * pitch + u] = Cf[(uint64_t)(c0 + c) * dp + u];
+            }
+            __syncthreads();
+            for (uint32_t q = wave; q < np; q += blockDim.x >> 6) {
+                const float* P = sP[q];
+                float xr[D > 0 ? D : 1];   // the point, as FP32 (exact) in VGPRs
+                if constexpr (D > 0) {
+#pragma unroll
+                    for (int u = 0; u < D; ++u) xr[u] = P[u];
+                }
+                double best = __builtin_inf();
+                int bj = 0x7FFFFFFF;
+                for (uint32_t c = lane; c < cn; c += 64) {
+                    const float* cc = sC + c * pitch;
+                    double a = 0.0;
+                    if constexpr (D > 0) {
+#pragma unroll
+                        for (int u = 0; u < D; ++u)
+                            a = kc_d64_step(a, (double)xr[u], (double)cc[u]);
+                    } else {
+                        for (int u = 0; u < d; ++u) a = kc_d64_step(a, (double)P[u], (double)cc[u]);
+                    }
+                    if (a < best) {   // a lane's centers ascend: ties keep the lowest
+                        best = a;
+                        bj = (int)(c0 + c);
+                    }
+                }
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const double ob = __shfl_xor(best, off, 64);
+                    const int oj = __shfl_xor(bj, off, 64);
+                    if (ob < best || (ob == best && oj < bj)) {
+                        best = ob;
+                        bj = oj;
+                    }
+                }
+                if (lane == 0 && best < sBest[q]) {   // later chunks hold higher positions
+                    sBest[q] = best;
+                    sArg[q] = bj;
+                }
             }
         }
-        for (int off = 32; off >= 1; off >>= 1) {
-            const double ob = __shfl_xor(best, off, 64);
-            const int oj = __shfl_xor(bj, off, 64);
-            if (ob < best || (ob == best && oj < bj)) {
-                best = ob;
-                bj = oj;
-            }
+        __syncthreads();
+        if (threadIdx.x < np) {
+            const uint32_t q = threadIdx.x;
+            if (labels) labels[list[b0 + q]] = sArg[q];
+            kc_atomic_max_f64_nonneg(radius2, sBest[q]);
         }
-        if (lane == 0) {
-            if (labels) labels[p] = bj;
-            kc_atomic_max_f64_nonneg(radius2, best);
-        }
+    }
+}
+
+static void kc_rescore_f64(const float* X, int64_t ld, int d, const float* Cf, int dp,
+                           uint32_t k, const int64_t* k_dev, const uint32_t* list,
+                           const uint32_t* nlist, uint32_t cap, int32_t* labels,
+                           double* radius2, hipStream_t s)
+{
+    const dim3 g(2048), b(256);
+    switch (d) {
+#define KC_RS_CASE(DD)                                                                      \
+    case DD:                                                                                \
+        hipLaunchKernelGGL(k_rescore_f64<DD>, g, b, 0, s, X, ld, d, Cf, dp, k, k_dev, list,  \
+                           nlist, cap, labels, radius2);                                    \
+        break;
+        KC_RS_CASE(2)
+        KC_RS_CASE(3)
+        KC_RS_CASE(8)
+        KC_RS_CASE(10)
+        KC_RS_CASE(16)
+        KC_RS_CASE(32)
+        KC_RS_CASE(41)
+#undef KC_RS_CASE
+    default:
+        hipLaunchKernelGGL(k_rescore_f64<0>, g, b, 0, s, X, ld, d, Cf, dp, k, k_dev, list, nlist,
+                           cap, labels, radius2);
     }
 }
 
@@ -548,34 +724,33 @@ int kc_mindist_dpad(int d, bool bf)
 uint32_t kc_mindist_chunk(int d, bool bf, uint32_t kpad)
 {
     const uint32_t dp = (uint32_t)kc_mindist_dpad(d, bf);
-    const uint32_t per = dp * (bf ? 2 : 4) + 4;
+    const uint32_t per = dp * (bf ? 2 : 4) + (bf ? 16 : 12);
     uint32_t c = (64u * 1024u / per) & ~15u;
     if (c < 16) c = 16;
     return c < kpad ? c : kpad;
 }
 
-void kc_mindist(const float* X, const uint16_t* Xb, int64_t ld, uint32_t n, int d,
-                const float* Cf, const uint16_t* Cb, const float* cnorm, uint32_t kpad,
-                int32_t* arg, float* m1, float* m2, float* nx, hipStream_t s)
+void kc_mindist(const float* X, const uint16_t* Xb, const float* ex, int64_t ld, uint32_t n,
+                int d, const KcCenters& C, const KcMinOut& O, bool lab, hipStream_t s)
 {
-    const bool lab = arg != nullptr;
     const bool bf = Xb != nullptr;
     const int ks = kc_mindist_ksteps(d, bf);
-    const uint32_t chunk = kc_mindist_chunk(d, bf, kpad);
+    const uint32_t chunk = kc_mindist_chunk(d, bf, C.kpad);
     const int dp = kc_mindist_dpad(d, bf);
-    const size_t smem = (size_t)chunk * 4 + (size_t)chunk * dp * (bf ? 2 : 4);
+    const size_t smem = (size_t)chunk * (bf ? 16 : 12) + (size_t)chunk * dp * (bf ? 2 : 4);
     const uint32_t per_block = KC_MD_WAVES * 16 * kc_md_pt(bf, ks);
     const dim3 grid((n + per_block - 1) / per_block), block(KC_MD_WAVES * 64);
+    const float gm = (float)kc_md_gamma(d);
     if (!bf) {
         switch (ks) {
 #define KC_CASE(K)                                                                       \
     case K:                                                                              \
         if (lab)                                                                         \
             hipLaunchKernelGGL((k_mindist_mfma<false, K, true>), grid, block, smem, s, X, \
-                               Xb, ld, n, d, Cf, Cb, cnorm, kpad, chunk, arg, m1, m2, nx); \
+                               Xb, ex, ld, n, d, gm, C, chunk, O);                        \
         else                                                                             \
             hipLaunchKernelGGL((k_mindist_mfma<false, K, false>), grid, block, smem, s, X, \
-                               Xb, ld, n, d, Cf, Cb, cnorm, kpad, chunk, arg, m1, m2, nx); \
+                               Xb, ex, ld, n, d, gm, C, chunk, O);                        \
         break;
             KC_MD_CASES_F32(KC_CASE)
 #undef KC_CASE
@@ -586,10 +761,10 @@ void kc_mindist(const float* X, const uint16_t* Xb, int64_t ld, uint32_t n, int 
     case K:                                                                              \
         if (lab)                                                                         \
             hipLaunchKernelGGL((k_mindist_mfma<true, K, true>), grid, block, smem, s, X,  \
-                               Xb, ld, n, d, Cf, Cb, cnorm, kpad, chunk, arg, m1, m2, nx); \
+                               Xb, ex, ld, n, d, gm, C, chunk, O);                        \
         else                                                                             \
             hipLaunchKernelGGL((k_mindist_mfma<true, K, false>), grid, block, smem, s, X, \
-                               Xb, ld, n, d, Cf, Cb, cnorm, kpad, chunk, arg, m1, m2, nx); \
+                               Xb, ex, ld, n, d, gm, C, chunk, O);                        \
         break;
             KC_MD_CASES_BF16(KC_CASE)
 #undef KC_CASE
@@ -599,18 +774,22 @@ void kc_mindist(const float* X, const uint16_t* Xb, int64_t ld, uint32_t n, int 
 
 void kc_stage_centers(const float* X, const uint16_t* Xb, int64_t ld, int d, uint32_t n,
                       const int64_t* idx, const uint32_t* idx32, uint32_t k,
-                      const int64_t* k_dev, uint32_t kpad, int dp, float* Cf, uint16_t* Cb,
-                      float* cnorm, float* cmax, uint32_t* status, hipStream_t s)
+                      const int64_t* k_dev, const KcCenters& C, uint32_t* status, hipStream_t s)
 {
-    kc_fill_u32((uint32_t*)cmax, 0u, 2, s);
-    hipLaunchKernelGGL(k_stage_centers, dim3((kpad + 255) / 256), dim3(256), 0, s, X, Xb, ld, d,
-                       n, idx, idx32, k, k_dev, kpad, dp, Cf, Cb, cnorm, cmax, status);
+    kc_fill_u32((uint32_t*)C.cmax, 0u, 2, s);
+    hipLaunchKernelGGL(k_stage_centers, dim3((C.kpad + 255) / 256), dim3(256), 0, s, X, Xb, ld,
+                       d, n, idx, idx32, k, k_dev, C, status);
+}
+
+void kc_local_origin(const float* X, int64_t ld, int d, uint32_t n, float* mu, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_local_origin, dim3(d), dim3(256), 0, s, X, ld, n, mu);
 }
 
 void kc_bf16_err(const float* X, const uint16_t* Xb, int64_t ld, int d, uint32_t n, float* ex,
                  hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bf16_err, dim3((n + 255) / 256), dim3(256), 0, s, X, Xb, ld, d, n, ex);
+    hipLaunchKernelGGL(k_bf16_err, dim3((n + 63) / 64), dim3(256), 0, s, X, Xb, ld, d, n, ex);
 }
 
 bool kc_radius_direct(uint32_t n, int d, const float* X, int64_t ld, const float* Cf, int dp,
@@ -642,15 +821,13 @@ bool kc_radius_direct(uint32_t n, int d, const float* X, int64_t ld, const float
 #undef KC_RD_CASE
     }
     hipLaunchKernelGGL(k_radius_candidates, gr, dim3(256), 0, s, n, hi, lo_max, list, nlist);
-    hipLaunchKernelGGL(k_rescore_f64, dim3(2048), dim3(256), 0, s, X, ld, d, Cf, dp, k, k_dev,
-                       list, nlist, 2 * n, nullptr, radius2);
+    kc_rescore_f64(X, ld, d, Cf, dp, k, k_dev, list, nlist, 2 * n, nullptr, radius2, s);
     hipLaunchKernelGGL(k_sqrt_out, dim3(1), dim3(64), 0, s, radius2, radius_out);
     return true;
 }
 
-void kc_assign_finish(uint32_t n, int d, const float* X, int64_t ld, const float* Cf, int dp,
-                      uint32_t k, const int64_t* k_dev, const int32_t* arg, const float* m1,
-                      const float* m2, const float* nx, const float* ex, const float* cmax,
+void kc_assign_finish(uint32_t n, int d, const float* X, int64_t ld, const KcCenters& C,
+                      uint32_t k, const int64_t* k_dev, const KcMinOut& O, const float* ex,
                       int32_t* labels, float* hi, uint32_t* list, uint32_t* nlist,
                       float* lo_max, double* radius2, double* radius_out, hipStream_t s)
 {
@@ -658,10 +835,9 @@ void kc_assign_finish(uint32_t n, int d, const float* X, int64_t ld, const float
     kc_fill_u32((uint32_t*)lo_max, 0u, 1, s);
     kc_fill_u64((u64*)radius2, 0ull, 1, s);
     const dim3 g((n + 255) / 256);
-    hipLaunchKernelGGL(k_assign_epilogue, g, dim3(256), 0, s, n, d, arg, m1, m2, nx, ex, cmax,
-                       labels, hi, list, nlist, lo_max);
+    hipLaunchKernelGGL(k_assign_epilogue, g, dim3(256), 0, s, n, d, O, ex, C, labels, hi, list,
+                       nlist, lo_max);
     hipLaunchKernelGGL(k_radius_candidates, g, dim3(256), 0, s, n, hi, lo_max, list, nlist);
-    hipLaunchKernelGGL(k_rescore_f64, dim3(2048), dim3(256), 0, s, X, ld, d, Cf, dp, k, k_dev,
-                       list, nlist, 2 * n, labels, radius2);
+    kc_rescore_f64(X, ld, d, C.Cf, C.dp, k, k_dev, list, nlist, 2 * n, labels, radius2, s);
     hipLaunchKernelGGL(k_sqrt_out, dim3(1), dim3(64), 0, s, radius2, radius_out);
 }

@@ -217,25 +217,17 @@ __global__ void k_gather_rows(const float* __restrict__ X, int64_t ld, int d,
     out[q] = X[(uint64_t)idx[j] * ld + u];
 }
 
-// Narrow [lo, hi] of d(x,S)^2 with this iteration's new samples (MFMA values).
-__global__ void k_eim_bounds(uint32_t nc, int d, const uint32_t* __restrict__ cand,
-                             const float* __restrict__ m1, const float* __restrict__ nxv,
-                             const float* __restrict__ cmax, float* __restrict__ lo,
-                             float* __restrict__ hi)
+// Narrow [lo, hi] of d(x,S)^2 with this iteration's new samples (certified
+// bounds of the MFMA pass, per pair; see kc_md_bounds).
+__global__ void k_eim_bounds(uint32_t nc, int d, const uint32_t* __restrict__ cand, KcMinOut O,
+                             KcCenters C, float* __restrict__ lo, float* __restrict__ hi)
 {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nc) return;
     const uint32_t x = cand[j];
-    const double g = (6.0 * d + 32.0) * 5.9604644775390625e-8;
-    const double nx = nxv[j];
-    const double s = sqrt(nx) * (1.0 + 1e-6) + (double)cmax[0];
-    const double err = g * s * s + 1e-30 * d;
-    const double v = nx + (double)m1[j];
-    double l = (v - err) * (1.0 - 1e-12);
-    if (l < 0.0) l = 0.0;
-    const double u = (v + err) * (1.0 + 1e-12);
-    lo[x] = fminf(lo[x], (float)l * (1.f - 1e-6f));
-    hi[x] = fminf(hi[x], (float)u * (1.f + 1e-6f));
+    const KcMdBounds B = kc_md_bounds(O, j, nullptr, C, d, false);
+    lo[x] = fminf(lo[x], (float)B.lo_min * (1.f - 1e-6f));
+    hi[x] = fminf(hi[x], (float)B.hi * (1.f + 1e-6f));
 }
 
 // dst[r * d + j] = X[S[r] * ld + j] (converted to T) for r < cnt, j < d, by
@@ -591,6 +583,11 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
         !tau || !cnt || !unsure || !exm || !C.blk)
         return h->fail(KC_ENOMEM, "workspace allocation failed");
 
+    // local origin of the points for the MFMA distance passes (d > 8): their
+    // error bound scales with the norms, measured from it
+    float* mu = (float*)h->ws("e.mu", 4ull * d);
+    if (!mu) return h->fail(KC_ENOMEM, "workspace allocation failed");
+    if (d > KC_EIM_DIRECT_MAXD) kc_local_origin(X, ld, d, n, mu, s);
     h->eim_exact = 0;
     hipLaunchKernelGGL(k_iota, g1(n), dim3(256), 0, s, R, n);
     kc_fill_u32((uint32_t*)lo, 0x7F800000u, n, s);
@@ -657,24 +654,34 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
                 const int dp = kc_mindist_dpad(d, false);
                 const uint32_t kpad = (nds + 15u) & ~15u;
                 float* XR = (float*)h->ws("e.XR", 4ull * nc * d);
-                float* Cf = (float*)h->ws("e.cf", 4ull * kpad * dp);
-                float* cn = (float*)h->ws("e.cn", 4ull * kpad);
-                float* cmax = (float*)h->ws("e.cmax", 16);
-                float* m1 = (float*)h->ws("e.m1", 4ull * nc);
-                float* m2 = (float*)h->ws("e.m2", 4ull * nc);
-                float* nx = (float*)h->ws("e.nx", 4ull * nc);
-                if (!XR || !Cf || !cn || !cmax || !m1 || !m2 || !nx)
+                KcCenters Cs;
+                Cs.kpad = kpad;
+                Cs.dp = dp;
+                Cs.Cf = (float*)h->ws("e.cf", 4ull * kpad * dp);
+                Cs.cn = (float*)h->ws("e.cn", 4ull * kpad);
+                Cs.cnl = (float*)h->ws("e.cnl", 4ull * kpad);
+                Cs.clen = (float*)h->ws("e.clen", 4ull * kpad);
+                Cs.cmax = (float*)h->ws("e.cmax", 16);
+                Cs.mu = mu;
+                Cs.Ct = (float*)h->ws("e.ct", 4ull * kpad * dp);
+                KcMinOut O;
+                O.arg = (int32_t*)h->ws("e.arg", 4ull * nc);
+                O.m1 = (float*)h->ws("e.m1", 4ull * nc);
+                O.lo2 = (float*)h->ws("e.m2", 4ull * nc);
+                O.nx = (float*)h->ws("e.nx", 4ull * nc);
+                if (!XR || !Cs.Cf || !Cs.Ct || !Cs.cn || !Cs.cnl || !Cs.clen || !Cs.cmax || !O.arg ||
+                    !O.m1 || !O.lo2 || !O.nx)
                     return h->fail(KC_ENOMEM, "workspace allocation failed");
                 hipLaunchKernelGGL(k_gather_rows, g1((uint64_t)nc * d), dim3(256), 0, s, X, ld,
                                    d, cand, nc, XR);
-                kc_stage_centers(X, nullptr, ld, d, n, nullptr, S + ns - nds, nds, nullptr,
-                                 kpad, dp, Cf, nullptr, cn, cmax, h->status_word, s);
+                kc_stage_centers(X, nullptr, ld, d, n, nullptr, S + ns - nds, nds, nullptr, Cs,
+                                 h->status_word, s);
                 hipEvent_t ev = h->span_begin(s);
-                // d(x, S) needs the smallest value only (no index, no second best)
-                kc_mindist(XR, nullptr, d, nc, d, Cf, nullptr, cn, kpad, nullptr, m1, m2, nx, s);
+                // d(x, S) needs the smallest distance's bounds only
+                kc_mindist(XR, nullptr, nullptr, d, nc, d, Cs, O, false, s);
                 h->span_end("eim_dist", ev, 1, s);
-                hipLaunchKernelGGL(k_eim_bounds, g1(nc), dim3(256), 0, s, nc, d, cand, m1, nx,
-                                   cmax, lo, hi);
+                hipLaunchKernelGGL(k_eim_bounds, g1(nc), dim3(256), 0, s, nc, d, cand, O, Cs,
+                                   lo, hi);
             }
             // keep / remove
             kc_fill_u32(cnt + 4, 0u, 1, s);

@@ -82,6 +82,8 @@ struct kc_handle {
     uint32_t last_bf16_kmax = 0;
     // candidates decided by the exact FP64 pass in the most recent EIM call
     int64_t eim_exact = 0;
+    // list count (device) of the most recent assignment's FP64 rescoring
+    const uint32_t* last_assign_nlist = nullptr;
 
     ~kc_handle();
     // Record the opening event of a timed span (no-op unless timing is on).

@@ -127,16 +127,111 @@ struct KcBf16Run {
 #define KC_BF_TILE_PTS (KC_BLOCK * 8)
 
 // MFMA nearest-center distances (kc_assign.hip)
+
+// Staged centers of an MFMA distance pass (device arrays of kpad entries,
+// padding entries with cn = cnl = +inf).
+struct KcCenters {
+    float* Cf = nullptr;     // [kpad][dp] FP32 coordinates
+    float* Ct = nullptr;     // [kpad][dp] the same translated to mu (FP32
+                             // passes with a local origin; the MFMA reads it)
+    uint16_t* Cb = nullptr;  // [kpad][dp] BF16 bits (BF16 passes)
+    float* cn = nullptr;     // |c|^2 of the MFMA inputs, in FP32
+    float* cnl = nullptr;    // cn - (g |c|^2 + 2 e_c |c|)
+    float* clen = nullptr;   // |c| of the MFMA inputs, rounded up
+    float* cerr = nullptr;   // BF16 rounding radius e_c, rounded up (BF16 passes)
+    float* cmax = nullptr;   // [2]: the largest clen and cerr
+    const float* mu = nullptr;  // FP32 passes: local origin subtracted from
+                                // points and centers before the MFMA (or NULL)
+    uint32_t kpad = 0;
+    int dp = 0;
+};
+
+// Per-point outputs of an MFMA distance pass (device arrays of n entries).
+struct KcMinOut {
+    int32_t* arg = nullptr;  // best center (smallest v, lowest index on ties)
+    float* m1 = nullptr;     // its v = |c|^2 - 2 x.c
+    float* lo2 = nullptr;    // smallest lower-bound term w over the other
+                             // centers (labels pass)
+    float* lob = nullptr;    // the best center's w (labels pass)
+    float* nx = nullptr;     // |x|^2 of the MFMA inputs
+};
+
+// Relative error constant of the MFMA distance: (6d + 44) u, u = 2^-24
+// (including the rounding of a translation to the local origin).
+__host__ __device__ inline double kc_md_gamma(int d)
+{
+    return (6.0 * d + 44.0) * 5.9604644775390625e-8;
+}
+
+struct KcMdBounds {
+    double hi;        // >= the exact squared distance to the best center
+    double lo_min;    // <= the exact squared distance to every center
+    double lo_other;  // <= the exact squared distance to every other center
+                      // (labels pass; +inf when there is no other)
+};
+
+// Certified bounds of point p from an MFMA pass (see kc_assign.hip): with
+// a = |x|, b = |c| (of the translated values when a local origin is used),
+// E = e_x + e_c,
+//   D <= (sqrt(|x|^2 + v + g (a+b)^2) + E)^2,
+//   D >= (sqrt(max(0, |x|^2 + v - g (a+b)^2)) - E)^2  (for the best center),
+//   D >= |x|^2 - (g a^2 + 2 e_x a) + w                 (labels pass, any center).
+// Without labels the kernel keeps the smallest v only, and b, e_c are the
+// largest over the centers.
+__device__ inline KcMdBounds kc_md_bounds(const KcMinOut& O, uint32_t p,
+                                          const float* __restrict__ ex, const KcCenters& C,
+                                          int d, bool lab)
+{
+    KcMdBounds B;
+    const double g = kc_md_gamma(d);
+    const double nx = O.nx[p];
+    const double a = sqrt(nx) * (1.0 + (d + 4) * 5.9604644775390625e-8) * (1.0 + 1e-6);
+    const double e_x = (C.Cb && ex) ? (double)ex[p] : 0.0;
+    const double P0 = (g * a * a + 2.0 * e_x * a) * (1.0 + 1e-12);
+    const int32_t a1 = lab ? O.arg[p] : 0;
+    if (a1 < 0 || (uint32_t)a1 >= C.kpad) {
+        B.hi = __builtin_inf();
+        B.lo_min = 0.0;
+        B.lo_other = 0.0;
+        return B;
+    }
+    const double b1 = lab ? (double)C.clen[a1] : (double)C.cmax[0];
+    const double E = e_x + (C.cerr ? (double)(lab ? C.cerr[a1] : C.cmax[1]) : 0.0);
+    const double s = a + b1;
+    const double err = g * s * s + 1e-30 * d;
+    const double d1 = nx + (double)O.m1[p];
+    const double rh = sqrt(d1 + err) + E;
+    B.hi = rh * rh * (1.0 + 1e-12);
+    double l = d1 - err;
+    l = l > 0.0 ? sqrt(l) - E : 0.0;
+    l = l > 0.0 ? l * l * (1.0 - 1e-12) : 0.0;
+    if (lab) {
+        const double lo2 = nx - P0 + (double)O.lo2[p];
+        const double lb = nx - P0 + (double)O.lob[p];
+        if (lb > l) l = lb;
+        B.lo_other = lo2;
+        B.lo_min = lo2 < l ? lo2 : l;
+    } else {
+        B.lo_other = __builtin_inf();
+        B.lo_min = l;
+    }
+    if (!(B.lo_min > 0.0)) B.lo_min = 0.0;
+    return B;
+}
+
 int kc_mindist_ksteps(int d, bool bf);
 int kc_mindist_dpad(int d, bool bf);
-// arg == NULL: only m1 (the smallest |c|^2 - 2x.c) and nx are written.
-void kc_mindist(const float* X, const uint16_t* Xb, int64_t ld, uint32_t n, int d,
-                const float* Cf, const uint16_t* Cb, const float* cnorm, uint32_t kpad,
-                int32_t* arg, float* m1, float* m2, float* nx, hipStream_t s);
+// One MFMA pass of every point against the staged centers (lab: labels
+// pass); ex: the points' BF16 rounding radii (BF16 passes).
+void kc_mindist(const float* X, const uint16_t* Xb, const float* ex, int64_t ld, uint32_t n,
+                int d, const KcCenters& C, const KcMinOut& O, bool lab, hipStream_t s);
 void kc_stage_centers(const float* X, const uint16_t* Xb, int64_t ld, int d, uint32_t n,
                       const int64_t* idx, const uint32_t* idx32, uint32_t k,
-                      const int64_t* k_dev, uint32_t kpad, int dp, float* Cf, uint16_t* Cb,
-                      float* cnorm, float* cmax, uint32_t* status, hipStream_t s);
+                      const int64_t* k_dev, const KcCenters& C, uint32_t* status, hipStream_t s);
+// mu[j] = the median of coordinate j over up to 1024 points spread evenly
+// over X (a local origin for FP32 MFMA passes: translating to it shrinks the
+// norms the error bound scales with); d <= KC_MAXD.
+void kc_local_origin(const float* X, int64_t ld, int d, uint32_t n, float* mu, hipStream_t s);
 void kc_bf16_err(const float* X, const uint16_t* Xb, int64_t ld, int d, uint32_t n, float* ex,
                  hipStream_t s);
 // Covering radius only (no labels), FP32 points, d <= 8: canonical FP32
@@ -147,8 +242,7 @@ bool kc_radius_direct(uint32_t n, int d, const float* X, int64_t ld, const float
                       uint32_t k, const int64_t* k_dev, float* hi, uint32_t* list,
                       uint32_t* nlist, float* lo_max, double* radius2, double* radius_out,
                       hipStream_t s);
-void kc_assign_finish(uint32_t n, int d, const float* X, int64_t ld, const float* Cf, int dp,
-                      uint32_t k, const int64_t* k_dev, const int32_t* arg, const float* m1,
-                      const float* m2, const float* nx, const float* ex, const float* cmax,
+void kc_assign_finish(uint32_t n, int d, const float* X, int64_t ld, const KcCenters& C,
+                      uint32_t k, const int64_t* k_dev, const KcMinOut& O, const float* ex,
                       int32_t* labels, float* hi, uint32_t* list, uint32_t* nlist,
                       float* lo_max, double* radius2, double* radius_out, hipStream_t s);

@@ -177,31 +177,46 @@ int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, ui
     const int d = pts->d;
     const int dp = kc_mindist_dpad(d, bf);
     const uint32_t kpad = (k + 15u) & ~15u;
-    float* Cf = (float*)h->ws(pre + "cf", sizeof(float) * (size_t)kpad * dp);
-    uint16_t* Cb = bf ? (uint16_t*)h->ws(pre + "cb", sizeof(uint16_t) * (size_t)kpad * dp)
-                      : nullptr;
-    float* cnorm = (float*)h->ws(pre + "cn", sizeof(float) * kpad);
-    float* cmax = (float*)h->ws(pre + "cmax", 16);
-    int32_t* arg = (int32_t*)h->ws(pre + "arg", sizeof(int32_t) * n);
-    float* m1 = (float*)h->ws(pre + "m1", sizeof(float) * n);
-    float* m2 = (float*)h->ws(pre + "m2", sizeof(float) * n);
-    float* nx = (float*)h->ws(pre + "nx", sizeof(float) * n);
+    KcCenters C;
+    C.kpad = kpad;
+    C.dp = dp;
+    C.Cf = (float*)h->ws(pre + "cf", sizeof(float) * (size_t)kpad * dp);
+    C.Cb = bf ? (uint16_t*)h->ws(pre + "cb", sizeof(uint16_t) * (size_t)kpad * dp) : nullptr;
+    C.cn = (float*)h->ws(pre + "cn", sizeof(float) * kpad);
+    C.cnl = (float*)h->ws(pre + "cnl", sizeof(float) * kpad);
+    C.clen = (float*)h->ws(pre + "clen", sizeof(float) * kpad);
+    C.cerr = bf ? (float*)h->ws(pre + "cerr", sizeof(float) * kpad) : nullptr;
+    C.cmax = (float*)h->ws(pre + "cmax", 16);
+    // FP32 passes measure from a local origin of the points (smaller norms,
+    // tighter bounds); BF16 inputs are used as stored
+    float* mu = bf ? nullptr : (float*)h->ws(pre + "mu", sizeof(float) * (size_t)d);
+    C.mu = mu;
+    C.Ct = bf ? nullptr : (float*)h->ws(pre + "ct", sizeof(float) * (size_t)kpad * dp);
+    KcMinOut O;
+    O.arg = (int32_t*)h->ws(pre + "arg", sizeof(int32_t) * n);
+    O.m1 = (float*)h->ws(pre + "m1", sizeof(float) * n);
+    O.lo2 = (float*)h->ws(pre + "lo2", sizeof(float) * n);
+    O.lob = (float*)h->ws(pre + "lob", sizeof(float) * n);
+    O.nx = (float*)h->ws(pre + "nx", sizeof(float) * n);
     float* hi = (float*)h->ws(pre + "hi", sizeof(float) * n);
     uint32_t* list = (uint32_t*)h->ws(pre + "list", sizeof(uint32_t) * 2 * (size_t)n);
     uint32_t* nlist = (uint32_t*)h->ws(pre + "nlist", 16);
     float* lo_max = (float*)h->ws(pre + "lomax", 16);
     double* r2 = (double*)h->ws(pre + "r2", 16);
     float* ex = bf ? (float*)h->ws(pre + "ex", sizeof(float) * n) : nullptr;
-    if (!Cf || (bf && !Cb) || !cnorm || !cmax || !arg || !m1 || !m2 || !nx || !hi || !list ||
-        !nlist || !lo_max || !r2 || (bf && !ex))
+    if (!C.Cf || (bf && (!C.Cb || !C.cerr)) || (!bf && (!mu || !C.Ct)) || !C.cmax || !C.cn || !C.cnl ||
+        !C.clen || !O.arg || !O.m1 ||
+        !O.lo2 || !O.lob || !O.nx || !hi || !list || !nlist || !lo_max || !r2 || (bf && !ex))
         return h->fail(KC_ENOMEM, "workspace allocation failed");
+    h->last_assign_nlist = nlist;
     const std::string key =
         kc_key(("assign:" + pre).c_str(), {pts->f32, pts->bf16, centers, k_dev, labels, radius},
                {pts->n, d, pts->ld, k, bf});
     int rc = h->run_graph(key + ":stage", s, [&](hipStream_t st) {
         if (bf) kc_bf16_err(pts->f32, pts->bf16, pts->ld, d, n, ex, st);
+        if (mu) kc_local_origin(pts->f32, pts->ld, d, n, mu, st);
         kc_stage_centers(pts->f32, bf ? pts->bf16 : nullptr, pts->ld, d, n, centers, nullptr, k,
-                         k_dev, kpad, dp, Cf, Cb, cnorm, cmax, h->status_word, st);
+                         k_dev, C, h->status_word, st);
     });
     if (rc) return rc;
     if (!labels && !bf && d <= 8) {
@@ -209,23 +224,22 @@ int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, ui
         // point's min-distance tightly, so few points need FP64
         hipEvent_t ev = h->span_begin(s);
         rc = h->run_graph(key + ":direct", s, [&](hipStream_t st) {
-            kc_radius_direct(n, d, pts->f32, pts->ld, Cf, dp, k, k_dev, hi, list, nlist, lo_max,
-                             r2, radius, st);
+            kc_radius_direct(n, d, pts->f32, pts->ld, C.Cf, dp, k, k_dev, hi, list, nlist,
+                             lo_max, r2, radius, st);
         });
         h->span_end("assign_direct", ev, 1, s);
         return rc;
     }
     hipEvent_t ev = h->span_begin(s);
     rc = h->run_graph(key + ":mfma", s, [&](hipStream_t st) {
-        // without labels only the smallest value per point is needed
-        kc_mindist(pts->f32, bf ? pts->bf16 : nullptr, pts->ld, n, d, Cf, Cb, cnorm, kpad,
-                   labels ? arg : nullptr, m1, m2, nx, st);
+        kc_mindist(pts->f32, bf ? pts->bf16 : nullptr, ex, pts->ld, n, d, C, O,
+                   labels != nullptr, st);
     });
     h->span_end("assign_mfma", ev, 1, s);
     if (rc) return rc;
     return h->run_graph(key + ":finish", s, [&](hipStream_t st) {
-        kc_assign_finish(n, d, pts->f32, pts->ld, Cf, dp, k, k_dev, arg, m1, m2, nx, ex, cmax,
-                         labels, hi, list, nlist, lo_max, r2, radius, st);
+        kc_assign_finish(n, d, pts->f32, pts->ld, C, k, k_dev, O, ex, labels, hi, list, nlist,
+                         lo_max, r2, radius, st);
     });
 }
 

@@ -84,6 +84,21 @@ def test_config4_full(kc, orc):
     assert np.array_equal(c32, cbf) and np.array_equal(t32, tbf)
     bad, _, otr = orc.gon_replay(X, k, c32, band(41))
     assert bad == -1
-    _, R = orc.assign(X, c32)
+    olab, R = orc.assign(X, c32)
     assert t32[-1] == R
     assert abs(t32[-1] - otr[-1]) <= 1e-6 * otr[-1]
+    # the n x k assignment of the objective (Section 1.1) at full shape:
+    # BF16 MFMA distances with certified labels, FP64 rescoring of the rest;
+    # labels equal the oracle's and the radius is the exact FP64 one
+    Xd = torch.from_numpy(X).cuda()
+    B = torch.from_numpy(W.to_bf16_rne(X).view(np.int16)).cuda()
+    cd = torch.from_numpy(c32).cuda()
+    for bf in (B, None):
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            lab, rad = kc.assign(Xd, cd, bf16=bf, handle=h)
+            assert h.device_status() == 0
+        st.synchronize()
+        assert np.array_equal(lab.cpu().numpy(), olab)
+        assert float(rad.item()) == R
