@@ -75,6 +75,9 @@ def lib():
         L.orc_eim_uniform_pair.argtypes = [ctypes.c_uint64, _i64,
                                            ctypes.c_int, _p]
         L.orc_eim_uniform_pair.restype = None
+        L.orc_eim_draw_flags.argtypes = [ctypes.c_uint64, ctypes.c_int, _p,
+                                         _i64, _f64, _f64, _p]
+        L.orc_eim_draw_flags.restype = _i64
         L.orc_min_dist2_to_set.argtypes = [_p, ctypes.c_int, _i64, _i64, _p,
                                            _i64, _p]
         L.orc_min_dist2_to_set.restype = _f64
@@ -233,6 +236,16 @@ def eim_uniform_pair(seed, x, it):
     lib().orc_eim_uniform_pair(ctypes.c_uint64(seed), int(x), int(it),
                                _ptr(out))
     return float(out[0]), float(out[1])
+
+
+def eim_draw_flags(seed, it, R, p_s, p_h):
+    """EIM's draws of iteration `it` for the listed points R: uint8 flags
+    (bit 0 into S, bit 1 into H)."""
+    R = np.ascontiguousarray(R, dtype=np.int64)
+    f = np.zeros(max(len(R), 1), np.uint8)
+    lib().orc_eim_draw_flags(ctypes.c_uint64(seed), int(it), _ptr(R), len(R),
+                             float(p_s), float(p_h), _ptr(f))
+    return f[:len(R)]
 
 
 def min_dist2_to_set(X, x, idx):

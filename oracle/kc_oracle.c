@@ -587,6 +587,23 @@ void orc_eim_uniform_pair(uint64_t seed, int64_t x, int it, double out[2])
     eim_uniforms(seed, x, it, &out[0], &out[1]);
 }
 
+/* EIM's draws of one iteration for the listed points R[0..nr-1]: flags[j]
+ * bit 0 when R[j] joins S (u_S < pS), bit 1 when it joins H (u_H < pH),
+ * with the uniforms of orc_eim_uniform_pair.  Returns the number drawn
+ * into S. */
+int64_t orc_eim_draw_flags(uint64_t seed, int it, const int64_t *R, int64_t nr,
+                           double pS, double pH, uint8_t *flags)
+{
+    int64_t ns = 0;
+    for (int64_t j = 0; j < nr; ++j) {
+        double uS, uH;
+        eim_uniforms(seed, R[j], it, &uS, &uH);
+        flags[j] = (uint8_t)((uS < pS ? 1 : 0) | (uH < pH ? 2 : 0));
+        ns += uS < pS;
+    }
+    return ns;
+}
+
 /* min over the listed points s of D(x, s) (squared, FP64) and the lowest
  * list position attaining it; +inf and -1 for an empty list. */
 double orc_min_dist2_to_set(const float *X, int d, int64_t ld, int64_t x,

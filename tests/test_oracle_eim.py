@@ -140,3 +140,17 @@ def test_sample_sizes_binomial(orc):
         for cnt, p in ((it["ds_size"], it["p_s"]), (it["h_size"], it["p_h"])):
             mu, sd = n * p, math.sqrt(n * p * (1 - p))
             assert abs(cnt - mu) <= 6 * sd
+
+
+def test_draw_flags_match_uniform_pairs(orc):
+    # the vectorised draws are the per-point uniforms compared with p_S, p_H
+    rng = np.random.default_rng(44)
+    for it in (0, 3):
+        R = np.sort(rng.choice(10**6, 500, replace=False))
+        seed = 5 * 2**32 + 17
+        f = orc.eim_draw_flags(seed, it, R, 0.3, 0.05)
+        for j, x in enumerate(R):
+            uS, uH = orc.eim_uniform_pair(seed, int(x), it)
+            assert bool(f[j] & 1) == (uS < 0.3) and bool(f[j] & 2) == (uH < 0.05)
+    # probability 1 draws everything, 0 nothing
+    assert np.all(orc.eim_draw_flags(1, 0, np.arange(100), 1.0, 0.0) == 1)
