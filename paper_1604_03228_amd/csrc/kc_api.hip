@@ -571,6 +571,10 @@ int kc_set_option(kc_handle* h, const char* name, int64_t value)
         h->allow_resident = value != 0;
         return KC_OK;
     }
+    if (!strcmp(name, "mfma_split")) {
+        h->mfma_split = value != 0;
+        return KC_OK;
+    }
     if (!strcmp(name, "timing")) {
         h->timing = value != 0;
         return KC_OK;

@@ -84,33 +84,61 @@ __device__ __forceinline__ float kc_bf16_to_f32(uint16_t h)
 }
 
 #define KC_MD_WAVES 4
+// Input modes of the distance pass: FP32 on v_mfma_f32_16x16x4f32; BF16
+// inputs (the caller's BF16 copy) on v_mfma_f32_16x16x32_bf16; FP32 inputs
+// split into BF16 high and low parts, x = h + l + r with h = bf16(x),
+// l = bf16(x - h), |r| <= 2^-18 |x|, on three BF16 MFMAs (h.h' + h.l' + l.h').
+// The split's products are exact in the FP32 accumulator and the dropped
+// terms (l.l', and the r's) are below 3.01 * 2^-18 |x| |c|, so its error
+// bound is the FP32 one plus 3.1 * 2^-18 (a + b)^2, at 3/16 of the FP32
+// MFMA's issue cost.
+#define KC_MD_F32 0
+#define KC_MD_BF16 1
+#define KC_MD_SPLIT 2
 // Point tiles (16 points each) per wave: four where the B operand is small
 // (more independent MFMA chains per center tile, fewer A reads per point),
 // two where it would crowd the VGPRs.
-__host__ __device__ constexpr int kc_md_pt(bool bf, int ks)
+__host__ __device__ constexpr int kc_md_pt(int mode, int ks)
 {
-    return (!bf && ks <= 8) || (bf && ks <= 2) ? 4 : 2;
+    return (mode == KC_MD_F32 && ks <= 8) || (mode != KC_MD_F32 && ks <= 2) ? 4 : 2;
 }
 
-// BF: BF16 inputs.  KS: MFMA K-steps (K = 4*KS for FP32, 32*KS for BF16).
-// LAB: labels pass, per point the best center's index (arg), its v (m1),
-// its lower-bound term (lob) and the smallest one of the other centers
-// (lo2); without LAB (a covering radius, a distance to a set) only the
-// smallest v (m1).  Always |x|^2 of the MFMA inputs (nx).  FP32 passes with
-// a local origin C.mu subtract it from points and centers as they load.
-template <bool BF, int KS, bool LAB>
+__device__ __forceinline__ uint16_t kc_f32_to_bf16_rne(float t)
+{
+    const uint32_t b = __float_as_uint(t);
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+
+// MODE: KC_MD_F32, KC_MD_BF16 or KC_MD_SPLIT.  KS: MFMA K-steps (K = 4*KS
+// for FP32, 32*KS otherwise).  LAB: labels pass, per point the best center's
+// index (arg), its v (m1), its lower-bound term (lob) and the smallest one of
+// the other centers (lo2).  Without LAB (a covering radius, a distance to a
+// set): with FP32 inputs, bounds of min_j |x|^2 + v_j taken per LDS chunk of
+// centers with that chunk's largest |c| -- the smallest v of the chunk
+// plus (m1) and minus (lo2) g (a + b_chunk)^2 -- so centers ordered by norm
+// give nearly per-center bounds at no cost per pair; with BF16 inputs the
+// smallest v (m1).  Always |x|^2 of the values fed to the MFMA (nx; of the
+// FP32 values in the split mode).  FP32 inputs with a local origin C.mu have
+// it subtracted as they load; the centers come translated.
+template <int MODE, int KS, bool LAB>
 __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
     const float* __restrict__ X, const uint16_t* __restrict__ Xb, const float* __restrict__ ex,
     int64_t ld, uint32_t n, int d, float gm, KcCenters C, uint32_t chunk, KcMinOut O)
 {
-    constexpr int DP = BF ? KS * 32 : KS * 4;   // padded K
-    constexpr int KC_MD_PT = kc_md_pt(BF, KS);
+    constexpr bool BF = MODE != KC_MD_F32;     // BF16 MFMA instructions
+    constexpr bool SP = MODE == KC_MD_SPLIT;   // high and low parts
+    constexpr bool RB = MODE == KC_MD_BF16;    // inputs carry rounding radii
+    constexpr int DP = BF ? KS * 32 : KS * 4;  // padded K
+    constexpr int KC_MD_PT = kc_md_pt(MODE, KS);
+    constexpr bool CB = !LAB && !RB;            // per-chunk bounds
+    __shared__ float s_bmax;
     extern __shared__ __align__(16) unsigned char kc_smem[];
     float* s_norm = (float*)kc_smem;                          // [chunk] cn
     float* s_cnl = s_norm + chunk;                            // [chunk] cnl
     float* s_len = s_cnl + chunk;                             // [chunk] |c|
     float* s_cer = s_len + chunk;                             // [chunk] e_c (BF16)
-    void* s_c = (void*)(s_cer + (BF ? chunk : 0));            // [chunk][DP]
+    void* s_c = (void*)(s_cer + (RB ? chunk : 0));            // [chunk][DP]
+    uint16_t* s_cl = (uint16_t*)s_c + (SP ? (size_t)chunk * DP : 0);   // low parts
     const float* __restrict__ Cf = C.mu ? C.Ct : C.Cf;
     const uint16_t* __restrict__ Cb = C.Cb;
     const uint32_t kpad = C.kpad;
@@ -124,13 +152,14 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
     // B operand (points) for all point tiles and K-steps, kept in registers
     float bf[KC_MD_PT][BF ? 1 : KS];
     kc_v8bf bb[KC_MD_PT][BF ? KS : 1];
+    kc_v8bf bl[KC_MD_PT][SP ? KS : 1];
     float nxp[KC_MD_PT];
 #pragma unroll
     for (int pt = 0; pt < KC_MD_PT; ++pt) {
         const uint64_t p = p0 + pt * 16 + col;
         const bool ok = p < n;
         nxp[pt] = 0.f;
-        if (!BF) {
+        if (MODE == KC_MD_F32) {
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
                 const int kk = ks * 4 + grp;
@@ -139,7 +168,7 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
                 bf[pt][BF ? 0 : ks] = v;
                 nxp[pt] = __builtin_fmaf(v, v, nxp[pt]);
             }
-        } else {
+        } else if (MODE == KC_MD_BF16) {
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
                 kc_v8bf w;
@@ -153,24 +182,45 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
                 }
                 bb[pt][BF ? ks : 0] = w;
             }
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                kc_v8bf wh, wl;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int kk = ks * 32 + grp * 8 + e;
+                    float v = (ok && kk < d) ? X[p * ld + kk] : 0.f;
+                    if (C.mu && kk < d) v = ok ? v - C.mu[kk] : 0.f;
+                    nxp[pt] = __builtin_fmaf(v, v, nxp[pt]);
+                    const float fh = kc_bf16_to_f32(kc_f32_to_bf16_rne(v));
+                    const float fl = kc_bf16_to_f32(kc_f32_to_bf16_rne(v - fh));
+                    wh[e] = (__bf16)fh;   // exact: both are BF16 values
+                    wl[e] = (__bf16)fl;
+                }
+                bb[pt][BF ? ks : 0] = wh;
+                bl[pt][SP ? ks : 0] = wl;
+            }
         }
     }
 
     // |x|^2 over the four lane groups, then the point's coefficients of the
     // per-pair lower bound: P1 multiplies |c|, P2 multiplies e_c
-    float P1[KC_MD_PT], P2[KC_MD_PT];
+    float P1[KC_MD_PT], P2[KC_MD_PT], ap[KC_MD_PT];
+    float wt[KC_MD_PT], ut[KC_MD_PT];   // per-chunk bounds: lower and upper terms
 #pragma unroll
     for (int pt = 0; pt < KC_MD_PT; ++pt) {
         float nx = nxp[pt];
         nx += __shfl_xor(nx, 16, 64);
         nx += __shfl_xor(nx, 32, 64);
         nxp[pt] = nx;
+        ap[pt] = sqrtf(nx) * (1.f + (float)(d + 4) * 5.9604645e-8f) * (1.f + 1e-6f);
+        wt[pt] = __builtin_inff();
+        ut[pt] = __builtin_inff();
         if (LAB) {
             const uint64_t p = p0 + pt * 16 + col;
-            const float a = sqrtf(nx) * (1.f + (float)(d + 4) * 5.9604645e-8f) * (1.f + 1e-6f);
-            const float e = (BF && ex && p < n) ? ex[p] : 0.f;
-            P1[pt] = (2.f * gm * a + 2.f * e) * (1.f + 1e-6f);
-            P2[pt] = 2.f * a * (1.f + 1e-6f);
+            const float e = (RB && ex && p < n) ? ex[p] : 0.f;
+            P1[pt] = (2.f * gm * ap[pt] + 2.f * e) * (1.f + 1e-6f);
+            P2[pt] = 2.f * ap[pt] * (1.f + 1e-6f);
         }
     }
 
@@ -188,10 +238,10 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
         __syncthreads();
         for (uint32_t q = threadIdx.x; q < cn; q += blockDim.x) {
             s_norm[q] = C.cn[c0 + q];
+            if (LAB || CB) s_len[q] = C.clen[c0 + q];
             if (LAB) {
                 s_cnl[q] = C.cnl[c0 + q];
-                s_len[q] = C.clen[c0 + q];
-                if (BF) s_cer[q] = C.cerr[c0 + q];
+                if (RB) s_cer[q] = C.cerr[c0 + q];
             }
         }
         if (!BF) {
@@ -202,13 +252,29 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
             const uint4* src = (const uint4*)(Cb + (uint64_t)c0 * DP);
             uint4* dst = (uint4*)s_c;
             for (uint32_t q = threadIdx.x; q < cn * DP / 8; q += blockDim.x) dst[q] = src[q];
+            if (SP) {
+                const uint4* srl = (const uint4*)(C.Cbl + (uint64_t)c0 * DP);
+                uint4* dsl = (uint4*)s_cl;
+                for (uint32_t q = threadIdx.x; q < cn * DP / 8; q += blockDim.x) dsl[q] = srl[q];
+            }
         }
         __syncthreads();
+        if (CB) {
+            // the chunk's largest |c| (wave 0; read after the next barrier)
+            if (wave == 0) {
+                float bm = 0.f;
+                for (uint32_t q = lane; q < cn; q += 64) bm = fmaxf(bm, s_len[q]);
+                for (int off = 32; off >= 1; off >>= 1) bm = fmaxf(bm, __shfl_xor(bm, off, 64));
+                if (lane == 0) s_bmax = bm;
+            }
+            __syncthreads();
+        }
 
         for (uint32_t ct = 0; ct < cn; ct += 16) {
             // A operand: centers ct + col, K slice of this lane group
             float af[BF ? 1 : KS];
             kc_v8bf ab[BF ? KS : 1];
+            kc_v8bf al[SP ? KS : 1];
             if (!BF) {
                 const float* cs = (const float*)s_c + (uint64_t)(ct + col) * DP;
 #pragma unroll
@@ -218,27 +284,40 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks)
                     ab[BF ? ks : 0] = *(const kc_v8bf*)(cs + ks * 32 + grp * 8);
+                if (SP) {
+                    const uint16_t* cl = s_cl + (uint64_t)(ct + col) * DP;
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks)
+                        al[SP ? ks : 0] = *(const kc_v8bf*)(cl + ks * 32 + grp * 8);
+                }
             }
             const float4 nc4 = *(const float4*)(s_norm + ct + grp * 4);
             float4 nl4 = make_float4(0.f, 0.f, 0.f, 0.f), cb4 = nl4, ce4 = nl4;
             if (LAB) {
                 nl4 = *(const float4*)(s_cnl + ct + grp * 4);
                 cb4 = *(const float4*)(s_len + ct + grp * 4);
-                if (BF) ce4 = *(const float4*)(s_cer + ct + grp * 4);
+                if (RB) ce4 = *(const float4*)(s_cer + ct + grp * 4);
             }
 #pragma unroll
             for (int pt = 0; pt < KC_MD_PT; ++pt) {
                 kc_v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
-                    if (!BF)
+                    if (!BF) {
                         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[BF ? 0 : ks],
                                                                    bf[pt][BF ? 0 : ks], acc,
                                                                    0, 0, 0);
-                    else
+                    } else {
                         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab[BF ? ks : 0],
                                                                       bb[pt][BF ? ks : 0],
                                                                       acc, 0, 0, 0);
+                        if (SP) {
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                ab[BF ? ks : 0], bl[pt][SP ? ks : 0], acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                al[SP ? ks : 0], bb[pt][BF ? ks : 0], acc, 0, 0, 0);
+                        }
+                    }
                 }
                 // v = |c|^2 - 2 x.c; labels: w = v - (g b^2 + 2 e_c b) - P1 b
                 // - P2 e_c (padding centers have cn = cnl = +inf, so they
@@ -250,7 +329,7 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
                         const float v = __builtin_fmaf(-2.f, a, cnv);
                         float w = __builtin_fmaf(-2.f, a, cnlv);
                         w = __builtin_fmaf(-q1, bv, w);
-                        if (BF) w = __builtin_fmaf(-q2, ev, w);
+                        if (RB) w = __builtin_fmaf(-q2, ev, w);
                         kc_best_push(best[pt], v, w, idx);
                     };
                     pair(acc[0], nc4.x, nl4.x, cb4.x, ce4.x, ib + 0);
@@ -266,6 +345,18 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
                 }
             }
         }
+        if (CB) {
+            // this chunk's bounds: its smallest v -/+ g (a + b_chunk)^2
+            const float bc = s_bmax;
+#pragma unroll
+            for (int pt = 0; pt < KC_MD_PT; ++pt) {
+                const float sb = ap[pt] + bc;
+                const float e = gm * sb * sb * (1.f + 1e-6f);
+                wt[pt] = fminf(wt[pt], best[pt].m1 - e);
+                ut[pt] = fminf(ut[pt], best[pt].m1 + e);
+                best[pt].m1 = __builtin_inff();
+            }
+        }
     }
 
 #pragma unroll
@@ -274,6 +365,11 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
         if (LAB) {
             b = kc_best_xor(b, 16);
             b = kc_best_xor(b, 32);
+        } else if (CB) {
+            b.m1 = fminf(ut[pt], __shfl_xor(ut[pt], 16, 64));
+            b.m1 = fminf(b.m1, __shfl_xor(b.m1, 32, 64));
+            b.l2 = fminf(wt[pt], __shfl_xor(wt[pt], 16, 64));
+            b.l2 = fminf(b.l2, __shfl_xor(b.l2, 32, 64));
         } else {
             b.m1 = fminf(b.m1, __shfl_xor(b.m1, 16, 64));
             b.m1 = fminf(b.m1, __shfl_xor(b.m1, 32, 64));
@@ -285,6 +381,7 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
                 O.lo2[p] = b.l2;
                 O.lob[p] = b.wb;
             }
+            if (CB) O.lo2[p] = b.l2;
             O.m1[p] = b.m1;
             O.nx[p] = nxp[pt];
         }
@@ -319,6 +416,7 @@ __global__ void k_stage_centers(const float* __restrict__ X, const uint16_t* __r
             if (C.Cf) C.Cf[(uint64_t)i * dp + j] = 0.f;
             if (C.Ct) C.Ct[(uint64_t)i * dp + j] = 0.f;
             if (C.Cb) C.Cb[(uint64_t)i * dp + j] = 0;
+            if (C.Cbl) C.Cbl[(uint64_t)i * dp + j] = 0;
         }
         C.cn[i] = __builtin_inff();
         C.cnl[i] = __builtin_inff();
@@ -329,11 +427,20 @@ __global__ void k_stage_centers(const float* __restrict__ X, const uint16_t* __r
     const uint64_t r = (uint64_t)ri;
     double nn = 0.0, ee = 0.0, nb = 0.0;
     float nf = 0.f;
+    const bool split = C.Cbl != nullptr;
     for (int j = 0; j < dp; ++j) {
         const float v = j < d ? X[r * ld + j] : 0.f;
         if (C.Cf) C.Cf[(uint64_t)i * dp + j] = v;
         if (C.Ct) C.Ct[(uint64_t)i * dp + j] = (C.mu && j < d) ? v - C.mu[j] : v;
-        if (C.Cb) {
+        if (split) {
+            // high and low BF16 parts of the translated value
+            const float t = (C.mu && j < d) ? v - C.mu[j] : v;
+            const uint16_t hh = kc_f32_to_bf16_rne(t);
+            C.Cb[(uint64_t)i * dp + j] = hh;
+            C.Cbl[(uint64_t)i * dp + j] = kc_f32_to_bf16_rne(t - kc_bf16_to_f32(hh));
+            nf = __builtin_fmaf(t, t, nf);
+            nn += (double)t * (double)t;
+        } else if (C.Cb) {
             const uint16_t h = j < d ? Xb[r * ld + j] : (uint16_t)0;
             C.Cb[(uint64_t)i * dp + j] = h;
             const float f = kc_bf16_to_f32(h);
@@ -350,15 +457,16 @@ __global__ void k_stage_centers(const float* __restrict__ X, const uint16_t* __r
     }
     // the norm used in v: of the values fed to the MFMA, in FP32 as the
     // kernel's error bound assumes; |c| and e_c rounded up
-    const double b = sqrt(C.Cb ? nb : nn) * (1.0 + 1e-6);
-    const double e = C.Cb ? sqrt(ee) * (1.0 + 1e-6) : 0.0;
-    const double g = kc_md_gamma(d);
+    const bool bf_in = C.Cb && !split;
+    const double b = sqrt(bf_in ? nb : nn) * (1.0 + 1e-6);
+    const double e = bf_in ? sqrt(ee) * (1.0 + 1e-6) : 0.0;
+    const double g = kc_md_gamma(d, split);
     C.cn[i] = nf;
     C.cnl[i] = (float)((double)nf - (g * b * b + 2.0 * e * b));
     C.clen[i] = (float)b * (1.f + 1e-6f);
     if (C.cerr) C.cerr[i] = (float)e * (1.f + 1e-6f);
     kc_atomic_max_f32_nonneg(&C.cmax[0], (float)b * (1.f + 1e-6f));
-    if (C.Cb) kc_atomic_max_f32_nonneg(&C.cmax[1], (float)e * (1.f + 1e-6f));
+    if (bf_in) kc_atomic_max_f32_nonneg(&C.cmax[1], (float)e * (1.f + 1e-6f));
 }
 
 // mu[j] = the median (the lower middle value) of coordinate j over m points
@@ -721,10 +829,10 @@ int kc_mindist_dpad(int d, bool bf)
 }
 
 // Largest center chunk (multiple of 16) whose LDS copy fits in 64 KiB.
-uint32_t kc_mindist_chunk(int d, bool bf, uint32_t kpad)
+static uint32_t kc_mindist_chunk(int d, int mode, uint32_t kpad)
 {
-    const uint32_t dp = (uint32_t)kc_mindist_dpad(d, bf);
-    const uint32_t per = dp * (bf ? 2 : 4) + (bf ? 16 : 12);
+    const uint32_t dp = (uint32_t)kc_mindist_dpad(d, mode != KC_MD_F32);
+    const uint32_t per = dp * (mode == KC_MD_BF16 ? 2 : 4) + (mode == KC_MD_BF16 ? 16 : 12);
     uint32_t c = (64u * 1024u / per) & ~15u;
     if (c < 16) c = 16;
     return c < kpad ? c : kpad;
@@ -733,43 +841,49 @@ uint32_t kc_mindist_chunk(int d, bool bf, uint32_t kpad)
 void kc_mindist(const float* X, const uint16_t* Xb, const float* ex, int64_t ld, uint32_t n,
                 int d, const KcCenters& C, const KcMinOut& O, bool lab, hipStream_t s)
 {
-    const bool bf = Xb != nullptr;
+    const int mode = Xb ? KC_MD_BF16 : C.Cbl ? KC_MD_SPLIT : KC_MD_F32;
+    const bool bf = mode != KC_MD_F32;
     const int ks = kc_mindist_ksteps(d, bf);
-    const uint32_t chunk = kc_mindist_chunk(d, bf, C.kpad);
+    const uint32_t chunk = kc_mindist_chunk(d, mode, C.kpad);
     const int dp = kc_mindist_dpad(d, bf);
-    const size_t smem = (size_t)chunk * (bf ? 16 : 12) + (size_t)chunk * dp * (bf ? 2 : 4);
-    const uint32_t per_block = KC_MD_WAVES * 16 * kc_md_pt(bf, ks);
+    const size_t smem = (size_t)chunk * (mode == KC_MD_BF16 ? 16 : 12) +
+                        (size_t)chunk * dp * (mode == KC_MD_BF16 ? 2 : 4);
+    const uint32_t per_block = KC_MD_WAVES * 16 * kc_md_pt(mode, ks);
     const dim3 grid((n + per_block - 1) / per_block), block(KC_MD_WAVES * 64);
-    const float gm = (float)kc_md_gamma(d);
-    if (!bf) {
+    const float gm = (float)kc_md_gamma(d, mode == KC_MD_SPLIT);
+#define KC_LAUNCH(M, K)                                                                 \
+    if (lab)                                                                            \
+        hipLaunchKernelGGL((k_mindist_mfma<M, K, true>), grid, block, smem, s, X, Xb, ex, \
+                           ld, n, d, gm, C, chunk, O);                                  \
+    else                                                                                \
+        hipLaunchKernelGGL((k_mindist_mfma<M, K, false>), grid, block, smem, s, X, Xb,   \
+                           ex, ld, n, d, gm, C, chunk, O);
+    if (mode == KC_MD_F32) {
         switch (ks) {
-#define KC_CASE(K)                                                                       \
-    case K:                                                                              \
-        if (lab)                                                                         \
-            hipLaunchKernelGGL((k_mindist_mfma<false, K, true>), grid, block, smem, s, X, \
-                               Xb, ex, ld, n, d, gm, C, chunk, O);                        \
-        else                                                                             \
-            hipLaunchKernelGGL((k_mindist_mfma<false, K, false>), grid, block, smem, s, X, \
-                               Xb, ex, ld, n, d, gm, C, chunk, O);                        \
-        break;
+#define KC_CASE(K) \
+    case K:        \
+        KC_LAUNCH(KC_MD_F32, K) break;
             KC_MD_CASES_F32(KC_CASE)
+#undef KC_CASE
+        }
+    } else if (mode == KC_MD_BF16) {
+        switch (ks) {
+#define KC_CASE(K) \
+    case K:        \
+        KC_LAUNCH(KC_MD_BF16, K) break;
+            KC_MD_CASES_BF16(KC_CASE)
 #undef KC_CASE
         }
     } else {
         switch (ks) {
-#define KC_CASE(K)                                                                       \
-    case K:                                                                              \
-        if (lab)                                                                         \
-            hipLaunchKernelGGL((k_mindist_mfma<true, K, true>), grid, block, smem, s, X,  \
-                               Xb, ex, ld, n, d, gm, C, chunk, O);                        \
-        else                                                                             \
-            hipLaunchKernelGGL((k_mindist_mfma<true, K, false>), grid, block, smem, s, X, \
-                               Xb, ex, ld, n, d, gm, C, chunk, O);                        \
-        break;
+#define KC_CASE(K) \
+    case K:        \
+        KC_LAUNCH(KC_MD_SPLIT, K) break;
             KC_MD_CASES_BF16(KC_CASE)
 #undef KC_CASE
         }
     }
+#undef KC_LAUNCH
 }
 
 void kc_stage_centers(const float* X, const uint16_t* Xb, int64_t ld, int d, uint32_t n,

@@ -23,6 +23,8 @@
 
 #include <algorithm>
 
+#include <hipcub/hipcub.hpp>
+
 #include "kc_host.h"
 
 // ---------------------------------------------------------------------------
@@ -215,6 +217,27 @@ __global__ void k_gather_rows(const float* __restrict__ X, int64_t ld, int d,
     if (q >= (uint64_t)n * d) return;
     const uint64_t j = q / d, u = q % d;
     out[q] = X[(uint64_t)idx[j] * ld + u];
+}
+
+// Sort keys of this iteration's samples for the MFMA pass: the FP32 squared
+// norm of the translated coordinates (its bits order as unsigned integers),
+// with the sample's index.  Centers ordered by norm make the pass's
+// per-chunk bounds nearly per-center ones.
+__global__ void k_sample_norm_keys(const float* __restrict__ X, int64_t ld, int d,
+                                   const uint32_t* __restrict__ idx, uint32_t cnt,
+                                   const float* __restrict__ mu, uint32_t* __restrict__ key,
+                                   uint32_t* __restrict__ val)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    const uint32_t r = idx[i];
+    float s = 0.f;
+    for (int j = 0; j < d; ++j) {
+        const float t = X[(uint64_t)r * ld + j] - mu[j];
+        s = __builtin_fmaf(t, t, s);
+    }
+    key[i] = __float_as_uint(s);
+    val[i] = r;
 }
 
 // Narrow [lo, hi] of d(x,S)^2 with this iteration's new samples (certified
@@ -651,7 +674,10 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
                 }
                 h->span_end("eim_dist", ev, 1, s);
             } else if (nds > 0 && nc > 0) {
-                const int dp = kc_mindist_dpad(d, false);
+                // split BF16 MFMAs (option mfma_split) or the FP32 MFMA, on
+                // the points translated to the local origin
+                const bool split = h->mfma_split;
+                const int dp = kc_mindist_dpad(d, split);
                 const uint32_t kpad = (nds + 15u) & ~15u;
                 float* XR = (float*)h->ws("e.XR", 4ull * nc * d);
                 KcCenters Cs;
@@ -663,18 +689,42 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
                 Cs.clen = (float*)h->ws("e.clen", 4ull * kpad);
                 Cs.cmax = (float*)h->ws("e.cmax", 16);
                 Cs.mu = mu;
-                Cs.Ct = (float*)h->ws("e.ct", 4ull * kpad * dp);
+                if (split) {
+                    Cs.Cb = (uint16_t*)h->ws("e.cbh", 2ull * kpad * dp);
+                    Cs.Cbl = (uint16_t*)h->ws("e.cbl", 2ull * kpad * dp);
+                } else {
+                    Cs.Ct = (float*)h->ws("e.ct", 4ull * kpad * dp);
+                }
                 KcMinOut O;
                 O.arg = (int32_t*)h->ws("e.arg", 4ull * nc);
                 O.m1 = (float*)h->ws("e.m1", 4ull * nc);
                 O.lo2 = (float*)h->ws("e.m2", 4ull * nc);
                 O.nx = (float*)h->ws("e.nx", 4ull * nc);
-                if (!XR || !Cs.Cf || !Cs.Ct || !Cs.cn || !Cs.cnl || !Cs.clen || !Cs.cmax || !O.arg ||
+                if (!XR || !Cs.Cf || (!split && !Cs.Ct) || (split && (!Cs.Cb || !Cs.Cbl)) || !Cs.cn ||
+                    !Cs.cnl || !Cs.clen || !Cs.cmax || !O.arg ||
                     !O.m1 || !O.lo2 || !O.nx)
                     return h->fail(KC_ENOMEM, "workspace allocation failed");
                 hipLaunchKernelGGL(k_gather_rows, g1((uint64_t)nc * d), dim3(256), 0, s, X, ld,
                                    d, cand, nc, XR);
-                kc_stage_centers(X, nullptr, ld, d, n, nullptr, S + ns - nds, nds, nullptr, Cs,
+                // the new samples in ascending order of norm, then staged
+                uint32_t* kin = (uint32_t*)h->ws("e.skey", 4ull * nds);
+                uint32_t* kout = (uint32_t*)h->ws("e.skey2", 4ull * nds);
+                uint32_t* vin = (uint32_t*)h->ws("e.sval", 4ull * nds);
+                uint32_t* vout = (uint32_t*)h->ws("e.sval2", 4ull * nds);
+                size_t tbytes = 0;
+                hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, kin, kout, vin, vout,
+                                                   (int)nds, 0, 32, s);
+                void* tmp = h->ws("e.sorttmp", tbytes);
+                if (!kin || !kout || !vin || !vout || !tmp)
+                    return h->fail(KC_ENOMEM, "workspace allocation failed");
+                hipLaunchKernelGGL(k_sample_norm_keys, g1(nds), dim3(256), 0, s, X, ld, d,
+                                   S + ns - nds, nds, mu, kin, vin);
+                if (hipcub::DeviceRadixSort::SortPairs(tmp, tbytes, kin, kout, vin, vout,
+                                                       (int)nds, 0, 32, s) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return h->fail(KC_EHIP, "sample sort failed");
+                }
+                kc_stage_centers(X, nullptr, ld, d, n, nullptr, vout, nds, nullptr, Cs,
                                  h->status_word, s);
                 hipEvent_t ev = h->span_begin(s);
                 // d(x, S) needs the smallest distance's bounds only

@@ -58,6 +58,7 @@ struct kc_handle {
     int num_cu = 0;
     bool use_graphs = true;
     bool allow_resident = true;
+    bool mfma_split = true;           // FP32 distance passes on split BF16 MFMAs
     uint32_t spin_limit = 1u << 20;   // polls before a barrier wait gives up
     uint32_t* status_word = nullptr;  // device, see kc_device_status
     void* scratch = nullptr;          // device address of the no-allocation array

@@ -134,7 +134,10 @@ struct KcCenters {
     float* Cf = nullptr;     // [kpad][dp] FP32 coordinates
     float* Ct = nullptr;     // [kpad][dp] the same translated to mu (FP32
                              // passes with a local origin; the MFMA reads it)
-    uint16_t* Cb = nullptr;  // [kpad][dp] BF16 bits (BF16 passes)
+    uint16_t* Cb = nullptr;  // [kpad][dp] BF16 bits (BF16 passes), or the
+                             // high parts of the translated FP32 values
+    uint16_t* Cbl = nullptr; // [kpad][dp] their low parts (split passes:
+                             // FP32 inputs on three BF16 MFMAs)
     float* cn = nullptr;     // |c|^2 of the MFMA inputs, in FP32
     float* cnl = nullptr;    // cn - (g |c|^2 + 2 e_c |c|)
     float* clen = nullptr;   // |c| of the MFMA inputs, rounded up
@@ -151,16 +154,19 @@ struct KcMinOut {
     int32_t* arg = nullptr;  // best center (smallest v, lowest index on ties)
     float* m1 = nullptr;     // its v = |c|^2 - 2 x.c
     float* lo2 = nullptr;    // smallest lower-bound term w over the other
-                             // centers (labels pass)
+                             // centers (labels pass), or the per-chunk lower
+                             // term (radius passes on FP32 inputs)
     float* lob = nullptr;    // the best center's w (labels pass)
     float* nx = nullptr;     // |x|^2 of the MFMA inputs
 };
 
 // Relative error constant of the MFMA distance: (6d + 44) u, u = 2^-24
-// (including the rounding of a translation to the local origin).
-__host__ __device__ inline double kc_md_gamma(int d)
+// (including the rounding of a translation to the local origin), plus
+// 3.1 * 2^-18 for FP32 inputs split into BF16 high and low parts (the
+// dropped products of the split, kc_assign.hip).
+__host__ __device__ inline double kc_md_gamma(int d, bool split = false)
 {
-    return (6.0 * d + 44.0) * 5.9604644775390625e-8;
+    return (6.0 * d + 44.0) * 5.9604644775390625e-8 + (split ? 3.1 * 3.814697265625e-6 : 0.0);
 }
 
 struct KcMdBounds {
@@ -176,17 +182,25 @@ struct KcMdBounds {
 //   D <= (sqrt(|x|^2 + v + g (a+b)^2) + E)^2,
 //   D >= (sqrt(max(0, |x|^2 + v - g (a+b)^2)) - E)^2  (for the best center),
 //   D >= |x|^2 - (g a^2 + 2 e_x a) + w                 (labels pass, any center).
-// Without labels the kernel keeps the smallest v only, and b, e_c are the
-// largest over the centers.
+// Without labels, FP32 inputs: the kernel's per-chunk terms, min_j D_j in
+// [|x|^2 + lo2, |x|^2 + m1]; BF16 inputs: the smallest v, with b and e_c
+// the largest over the centers.
 __device__ inline KcMdBounds kc_md_bounds(const KcMinOut& O, uint32_t p,
                                           const float* __restrict__ ex, const KcCenters& C,
                                           int d, bool lab)
 {
     KcMdBounds B;
-    const double g = kc_md_gamma(d);
+    const double g = kc_md_gamma(d, C.Cbl != nullptr);
     const double nx = O.nx[p];
+    if (!lab && !(C.Cb && !C.Cbl)) {
+        B.hi = (nx + (double)O.m1[p]) * (1.0 + 1e-12) + 1e-30 * d;
+        const double l = (nx + (double)O.lo2[p]) * (1.0 - 1e-12) - 1e-30 * d;
+        B.lo_min = l > 0.0 ? l : 0.0;
+        B.lo_other = __builtin_inf();
+        return B;
+    }
     const double a = sqrt(nx) * (1.0 + (d + 4) * 5.9604644775390625e-8) * (1.0 + 1e-6);
-    const double e_x = (C.Cb && ex) ? (double)ex[p] : 0.0;
+    const double e_x = (C.Cb && !C.Cbl && ex) ? (double)ex[p] : 0.0;
     const double P0 = (g * a * a + 2.0 * e_x * a) * (1.0 + 1e-12);
     const int32_t a1 = lab ? O.arg[p] : 0;
     if (a1 < 0 || (uint32_t)a1 >= C.kpad) {

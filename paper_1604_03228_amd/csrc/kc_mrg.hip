@@ -173,9 +173,12 @@ int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, ui
                   const std::string& pre)
 {
     const bool bf = pts->prec == KC_BF16_RESCORE;
+    // FP32 inputs run the distance pass on split BF16 MFMAs (option
+    // mfma_split) or on the FP32 MFMA; every staged row has the MFMA's K
+    const bool split = !bf && h->mfma_split;
     const uint32_t n = (uint32_t)pts->n;
     const int d = pts->d;
-    const int dp = kc_mindist_dpad(d, bf);
+    const int dp = kc_mindist_dpad(d, bf || split);
     const uint32_t kpad = (k + 15u) & ~15u;
     KcCenters C;
     C.kpad = kpad;
@@ -191,7 +194,13 @@ int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, ui
     // tighter bounds); BF16 inputs are used as stored
     float* mu = bf ? nullptr : (float*)h->ws(pre + "mu", sizeof(float) * (size_t)d);
     C.mu = mu;
-    C.Ct = bf ? nullptr : (float*)h->ws(pre + "ct", sizeof(float) * (size_t)kpad * dp);
+    // FP32 inputs: the translated copy for the FP32 MFMA, or its BF16 high
+    // and low parts for the split MFMAs
+    C.Ct = (bf || split) ? nullptr : (float*)h->ws(pre + "ct", sizeof(float) * (size_t)kpad * dp);
+    if (split) {
+        C.Cb = (uint16_t*)h->ws(pre + "cb", sizeof(uint16_t) * (size_t)kpad * dp);
+        C.Cbl = (uint16_t*)h->ws(pre + "cbl", sizeof(uint16_t) * (size_t)kpad * dp);
+    }
     KcMinOut O;
     O.arg = (int32_t*)h->ws(pre + "arg", sizeof(int32_t) * n);
     O.m1 = (float*)h->ws(pre + "m1", sizeof(float) * n);
@@ -204,14 +213,15 @@ int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, ui
     float* lo_max = (float*)h->ws(pre + "lomax", 16);
     double* r2 = (double*)h->ws(pre + "r2", 16);
     float* ex = bf ? (float*)h->ws(pre + "ex", sizeof(float) * n) : nullptr;
-    if (!C.Cf || (bf && (!C.Cb || !C.cerr)) || (!bf && (!mu || !C.Ct)) || !C.cmax || !C.cn || !C.cnl ||
+    if (!C.Cf || (bf && (!C.Cb || !C.cerr)) || (!bf && !mu) || (!bf && !split && !C.Ct) ||
+        (split && (!C.Cb || !C.Cbl)) || !C.cmax || !C.cn || !C.cnl ||
         !C.clen || !O.arg || !O.m1 ||
         !O.lo2 || !O.lob || !O.nx || !hi || !list || !nlist || !lo_max || !r2 || (bf && !ex))
         return h->fail(KC_ENOMEM, "workspace allocation failed");
     h->last_assign_nlist = nlist;
     const std::string key =
         kc_key(("assign:" + pre).c_str(), {pts->f32, pts->bf16, centers, k_dev, labels, radius},
-               {pts->n, d, pts->ld, k, bf});
+               {pts->n, d, pts->ld, k, bf, split});
     int rc = h->run_graph(key + ":stage", s, [&](hipStream_t st) {
         if (bf) kc_bf16_err(pts->f32, pts->bf16, pts->ld, d, n, ex, st);
         if (mu) kc_local_origin(pts->f32, pts->ld, d, n, mu, st);

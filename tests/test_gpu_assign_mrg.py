@@ -50,27 +50,36 @@ def gpu_assign(kc, X, C, bf16=False, handle=None):
     return lab.cpu().numpy(), float(r.item())
 
 
+def mode_handle(kc, mode):
+    """FP32 inputs run the distance pass on split BF16 MFMAs by default, or on
+    the FP32 MFMA (option mfma_split = 0); "bf16" passes a BF16 copy."""
+    h = kc.Handle()
+    if mode == "fp32":
+        h.set_option("mfma_split", 0)
+    return h
+
+
 @pytest.mark.parametrize("d", [1, 2, 5, 16, 41, 70])
 @pytest.mark.parametrize("k", [1, 7, 200])
-@pytest.mark.parametrize("bf16", [False, True])
-def test_assign_random(kc, orc, d, k, bf16):
+@pytest.mark.parametrize("mode", ["split", "fp32", "bf16"])
+def test_assign_random(kc, orc, d, k, mode):
     rng = np.random.default_rng(1000 * d + k)
     n = 9_999
     X = (rng.normal(size=(n, d)) * rng.uniform(0.1, 50, d)).astype(np.float32)
     C = rng.choice(n, k, replace=False)
-    lab, R = gpu_assign(kc, X, C, bf16)
+    lab, R = gpu_assign(kc, X, C, mode == "bf16", handle=mode_handle(kc, mode))
     olab, oR = orc.assign(X, C)
     assert np.array_equal(lab, olab)
     assert R == oR
 
 
-@pytest.mark.parametrize("bf16", [False, True])
-def test_assign_ties_and_duplicates(kc, orc, bf16):
+@pytest.mark.parametrize("mode", ["split", "fp32", "bf16"])
+def test_assign_ties_and_duplicates(kc, orc, mode):
     # integer grid: many exactly equal distances; duplicate centers too
     X = W.config2(30_000)
     c, _, _ = orc.gon(X, 64, 0)
     C = np.r_[c, c[:5], c[10:12]]
-    lab, R = gpu_assign(kc, X, C, bf16)
+    lab, R = gpu_assign(kc, X, C, mode == "bf16", handle=mode_handle(kc, mode))
     olab, oR = orc.assign(X, C)
     assert np.array_equal(lab, olab) and R == oR
 

@@ -26,8 +26,9 @@ def kc():
     return kc
 
 
-def gpu_eim(kc, X, k, eps, phi, seed, max_iters=64):
+def gpu_eim(kc, X, k, eps, phi, seed, max_iters=64, split=True):
     h = kc.Handle()
+    h.set_option("mfma_split", int(split))
     Xd = torch.from_numpy(X).cuda()
     st = torch.cuda.Stream()
     st.wait_stream(torch.cuda.current_stream())
@@ -97,11 +98,12 @@ def test_all_duplicates(kc, orc):
 # above, on MFMA, whose bounds scale with the norms, so the unbalanced blobs
 # leave many candidates whose interval contains tau and the exact FP64 pass
 # decides them: tiled for d <= 64, one block per candidate above (d = 70).
-@pytest.mark.parametrize("d", [2, 8, 32, 70])
-def test_unbalanced_blobs(kc, orc, d):
+@pytest.mark.parametrize("d,split", [(2, True), (8, True), (32, True), (32, False),
+                                     (70, True)])
+def test_unbalanced_blobs(kc, orc, d, split):
     from paper_1604_03228_amd import workloads as W
     X = W.points_gauss_mixture(100_000, d, 25, seed=77, heavy=0.9)
-    g = gpu_eim(kc, X, 20, 0.1, 4.0, 5 * 2**32 + 1)
+    g = gpu_eim(kc, X, 20, 0.1, 4.0, 5 * 2**32 + 1, split=split)
     check(orc, X, 20, 0.1, 4.0, 5 * 2**32 + 1, g)
     if d > 8:
         assert g["exact"] > 0
