@@ -302,6 +302,18 @@ int kc_plan_gon(kc_handle* h, const std::string& pre, int d, uint32_t tile,
         }
         R.nblk_at = H.nblk_at.data();
     }
+    // Segments reading different arrays stage from a table of their sources
+    // (one launch for all of them)
+    R.srcs = nullptr;
+    bool shared = true;
+    for (const KcGonJob& j : jobs)
+        if (j.X != jobs[0].X || j.Xb != jobs[0].Xb || j.ld != jobs[0].ld) shared = false;
+    if (!shared && nseg > 1) {
+        std::vector<KcSrc> src(nseg);
+        for (int q = 0; q < nseg; ++q) src[q] = KcSrc{jobs[q].X, jobs[q].Xb, jobs[q].ld, 0};
+        R.srcs = (const KcSrc*)h->upload(pre + "srcs", src.data(), sizeof(KcSrc) * nseg, s);
+        if (!R.srcs) return h->fail(KC_ENOMEM, "plan upload failed");
+    }
     // Graphs captured from this plan embed its grids and loop counts (tiles,
     // steps, active tiles per step): their keys carry this signature.
     uint64_t hsh = kc_hash_bytes(&d, sizeof d);
@@ -318,6 +330,11 @@ int kc_plan_gon(kc_handle* h, const std::string& pre, int d, uint32_t tile,
 void kc_enqueue_stage(const KcGonRun& R, const KcGonHost& H, const std::vector<KcGonJob>& jobs,
                       hipStream_t s, uint16_t* xb, float* ex)
 {
+    if (R.srcs) {   // segments with their own arrays: one launch from the table
+        kc_stage_rows_src(R.srcs, xb != nullptr, R.d, R.segs, R.blk_seg, R.blk_start, R.nblk,
+                          R.tile, (float*)R.xs, xb, ex, R.stride, s);
+        return;
+    }
     bool shared = jobs.size() > 1 && jobs[0].X != nullptr;
     for (const KcGonJob& j : jobs)
         if (j.X != jobs[0].X || j.Xb != jobs[0].Xb || j.ld != jobs[0].ld) shared = false;

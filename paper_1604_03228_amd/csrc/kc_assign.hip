@@ -471,7 +471,7 @@ __global__ void k_stage_centers(const float* __restrict__ X, const uint16_t* __r
 
 // mu[j] = the median (the lower middle value) of coordinate j over m points
 // spread evenly over the n rows: block j ranks its m values by counting.
-#define KC_LO_SAMPLE 1024
+#define KC_LO_SAMPLE 256
 __global__ __launch_bounds__(256) void k_local_origin(const float* __restrict__ X, int64_t ld,
                                                       uint32_t n, float* __restrict__ mu)
 {

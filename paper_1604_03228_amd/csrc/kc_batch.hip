@@ -1,7 +1,9 @@
 // kc_batch.hip -- many independent k-center problems of mixed n, d, k and
 // algorithm in shared launches.
 //
-// For every dimension d present:
+// For every dimension d present, the problems whose points fit a
+// co-resident register-resident grid (every partition, for MRG) and the
+// others form two groups; for each group:
 //   stage 1  every Gonzalez problem and every partition of every MRG problem
 //            is one segment of a single batched run: register-resident,
 //            several segments per cooperative launch, when every segment
@@ -134,10 +136,10 @@ struct SegTag {
 };
 
 static int run_group(kc_handle* h, const kc_problem* probs, const std::vector<int>& ids, int d,
-                     hipStream_t s)
+                     const char* tag, hipStream_t s)
 {
     char pre[32];
-    snprintf(pre, sizeof pre, "b%d.", d);
+    snprintf(pre, sizeof pre, "b%d%s.", d, tag);
     const std::string P(pre);
 
     // ---- stage 1: one run over all Gonzalez problems and MRG partitions
@@ -347,9 +349,33 @@ extern "C" int kcenter_batch(kc_handle* h, const kc_problem* probs, int32_t coun
         else
             others.push_back(i);
     }
+    // Each dimension's problems in two runs: those whose points (every
+    // partition, for MRG) fit a co-resident register-resident grid, and the
+    // others, which stream; one problem too large for the register file
+    // then leaves the others on the resident engine.
     for (auto& g : groups) {
-        int rc = run_group(h, probs, g.second, g.first, s);
-        if (rc) return rc;
+        const int d = g.first;
+        std::vector<int> fit, other;
+        for (int i : g.second) {
+            const kc_problem& p = probs[i];
+            bool ok = h->allow_resident;
+            int v = 0;
+            uint32_t G = 0;
+            if (ok && p.algo == KC_ALGO_GON) ok = h->resident_fit(d, (uint64_t)p.pts.n, &v, &G);
+            for (int q = 0; ok && p.algo == KC_ALGO_MRG && q < p.m; ++q) {
+                const uint64_t len = (uint64_t)(p.offsets[q + 1] - p.offsets[q]);
+                ok = len == 0 || h->resident_fit(d, len, &v, &G);
+            }
+            (ok ? fit : other).push_back(i);
+        }
+        if (!fit.empty()) {
+            int rc = run_group(h, probs, fit, d, "r", s);
+            if (rc) return rc;
+        }
+        if (!other.empty()) {
+            int rc = run_group(h, probs, other, d, "s", s);
+            if (rc) return rc;
+        }
     }
     for (int i : others) {
         const kc_problem& p = probs[i];

@@ -165,6 +165,38 @@ __global__ __launch_bounds__(256) void k_stage_rows_batch(
         kc_stage_tile64(X, Xb, ld, d, sg.src, sg.len, i0, xs, xb, ex, stride, sg.base, sx, sb);
 }
 
+// Every segment of a planned run from its own source rows: block b stages
+// the `tile` columns from blk_start[b] of segment blk_seg[b] (segments with
+// no source are skipped).
+__global__ __launch_bounds__(256) void k_stage_rows_src(
+    const KcSrc* __restrict__ srcs, int bf, int d, const KcSeg* __restrict__ segs,
+    const uint32_t* __restrict__ blk_seg, const uint32_t* __restrict__ blk_start, uint32_t tile,
+    float* __restrict__ xs, uint16_t* __restrict__ xb, float* __restrict__ ex, uint64_t stride)
+{
+    __shared__ float sx[64 * (KC_STG_W + 1)];
+    __shared__ uint16_t sb[64 * (KC_STG_W + 1)];
+    const uint32_t q = blk_seg[blockIdx.x];
+    const KcSrc src = srcs[q];
+    if (!src.X) return;
+    const KcSeg sg = segs[q];
+    const uint32_t st = blk_start[blockIdx.x];
+    const uint32_t padded = (sg.len + 63u) & ~63u;
+    const uint32_t end = st + tile < padded ? st + tile : padded;
+    for (uint32_t i0 = st; i0 < end; i0 += 64)
+        kc_stage_tile64(src.X, bf ? src.Xb : nullptr, src.ld, d, sg.src, sg.len, i0, xs,
+                        bf ? xb : nullptr, ex, stride, sg.base, sx, sb);
+}
+
+void kc_stage_rows_src(const KcSrc* srcs, bool bf, int d, const KcSeg* segs,
+                       const uint32_t* blk_seg, const uint32_t* blk_start, uint32_t nblk,
+                       uint32_t tile, float* xs, uint16_t* xb, float* ex, uint64_t stride,
+                       hipStream_t s)
+{
+    if (nblk == 0) return;
+    hipLaunchKernelGGL(k_stage_rows_src, dim3(nblk), dim3(256), 0, s, srcs, (int)bf, d, segs,
+                       blk_seg, blk_start, tile, xs, xb, ex, stride);
+}
+
 void kc_stage_rows(const float* X, const uint16_t* Xb, int64_t ld, int d, uint64_t row0,
                    uint32_t len, float* xs, uint16_t* xb, float* ex, uint64_t stride,
                    uint64_t base, hipStream_t s)

@@ -19,6 +19,16 @@ static inline double kc_gamma32(int d)
     return m * u / (1.0 - m * u);
 }
 
+// Source rows of one segment of a run (device table, one per segment, when
+// the segments read different arrays): X NULL when the segment is filled
+// otherwise (a gathered union).
+struct KcSrc {
+    const float* X;
+    const uint16_t* Xb;
+    int64_t ld;
+    int64_t pad;
+};
+
 // Everything the step engines and the finishing kernels of one batched
 // Gonzalez run need (device pointers unless noted).
 struct KcGonRun {
@@ -52,6 +62,7 @@ struct KcGonRun {
     // descending k (their tiles then form a prefix); NULL: all blocks
     const uint32_t* nblk_at = nullptr;
     uint64_t plan_hash = 0;     // geometry of the plan (host), part of graph keys
+    const KcSrc* srcs = nullptr;  // per-segment sources, when they differ
 };
 
 void kc_fill_u64(u64* p, u64 v, uint64_t n, hipStream_t s);
@@ -68,6 +79,11 @@ void kc_stage_rows_batch(const float* X, const uint16_t* Xb, int64_t ld, int d,
                          const KcSeg* segs, const uint32_t* blk_seg, const uint32_t* blk_start,
                          uint32_t nblk, uint32_t tile, float* xs, uint16_t* xb, float* ex,
                          uint64_t stride, hipStream_t s);
+// The same with each segment's own source rows (srcs[segment]).
+void kc_stage_rows_src(const KcSrc* srcs, bool bf, int d, const KcSeg* segs,
+                       const uint32_t* blk_seg, const uint32_t* blk_start, uint32_t nblk,
+                       uint32_t tile, float* xs, uint16_t* xb, float* ex, uint64_t stride,
+                       hipStream_t s);
 void kc_part_collect(const u64* part, u64* keys, uint64_t nkeys, hipStream_t s);
 uint64_t kc_resident_slot_words(int k, uint32_t G);
 void kc_gon_step(const float* xs, uint64_t stride, int d, float* mind, u64* part,
@@ -242,7 +258,7 @@ void kc_mindist(const float* X, const uint16_t* Xb, const float* ex, int64_t ld,
 void kc_stage_centers(const float* X, const uint16_t* Xb, int64_t ld, int d, uint32_t n,
                       const int64_t* idx, const uint32_t* idx32, uint32_t k,
                       const int64_t* k_dev, const KcCenters& C, uint32_t* status, hipStream_t s);
-// mu[j] = the median of coordinate j over up to 1024 points spread evenly
+// mu[j] = the median of coordinate j over up to 256 points spread evenly
 // over X (a local origin for FP32 MFMA passes: translating to it shrinks the
 // norms the error bound scales with); d <= KC_MAXD.
 void kc_local_origin(const float* X, int64_t ld, int d, uint32_t n, float* mu, hipStream_t s);
