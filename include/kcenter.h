@@ -84,9 +84,29 @@ const char* kc_last_error(const kc_handle* h);
  * co-resident, the default; a testing aid: smaller grids hold fewer points,
  * so more inputs stream and MRG partitions spread over more launches);
  * "timing" 0/1 (record kernel timing events, default 0); "spin_limit"
- * (polls before a persistent kernel's barrier wait gives up, default 2^20).
+ * (polls before a persistent kernel's barrier wait gives up, default 2^20);
+ * "mfma_split" 0/1 (FP32 distance passes of assignments and EIM on split
+ * BF16 MFMAs -- each FP32 operand as a sum of two BF16 values, three
+ * products -- instead of the FP32 MFMA, default 1; results are identical,
+ * only the certified bounds and so the speed differ); "autotune" 0/1
+ * (default 1: the first call of a shape bucket -- dimension, and n, k or
+ * sample size rounded to half powers of two -- times every feasible variant
+ * of its engine once and the handle keeps the fastest; the variants give
+ * identical results; a call made during stream capture never tunes).
  * KC_EINVAL for an unknown name or a value out of range. */
 int kc_set_option(kc_handle* h, const char* name, int64_t value);
+
+/* The autotuner's choices on this handle as text: one line per shape
+ * bucket, "<key> <chosen variant> <ms of variant 0> <ms of variant 1> ...",
+ * -1 for a variant that could not run.  Keys: "gon/d/a/b/rows" (Gonzalez,
+ * a = floor(2 log2 n), b = floor(2 log2 k); variants resident v0, resident
+ * v1, streaming), "eim/d/a/b" (EIM distance pass, a and b of the candidate
+ * and new-sample counts; variants direct VALU for d <= 8, FP32 MFMA, split
+ * MFMA).  Writes at most `cap` bytes (NUL-terminated) to the host buffer
+ * `buf` and the needed size to *need; with cap = 0 (buf may be NULL) it
+ * only sets *need.  KC_EINVAL for a NULL handle or need, or when 0 < cap <
+ * *need (nothing written). */
+int kc_tune_report(kc_handle* h, char* buf, int64_t cap, int64_t* need);
 
 /* Kernel timing.  With option "timing" = 1 every call records a pair of HIP
  * events on its stream around its dominant kernel or launch sequence, under

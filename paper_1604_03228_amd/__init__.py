@@ -58,7 +58,7 @@ class KCenterError(RuntimeError):
 
 EXPORTS = ["kc_create", "kc_destroy", "kc_strerror", "kc_last_error",
            "kc_set_option", "kc_device_status", "kc_timing_read",
-           "kc_counter_read",
+           "kc_counter_read", "kc_tune_report",
            "kcenter_gonzalez", "kcenter_gonzalez_noalloc",
            "kcenter_gonzalez_resume",
            "kcenter_mrg", "kcenter_mrg_rounds", "kcenter_assign", "kcenter_eim",
@@ -89,6 +89,8 @@ def load_library(path=LIB_PATH):
                                  ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
     L.kc_counter_read.argtypes = [_p, ctypes.c_char_p, ctypes.POINTER(_i64)]
+    L.kc_tune_report.argtypes = [_p, ctypes.c_char_p, _i64,
+                                 ctypes.POINTER(_i64)]
     L.kcenter_gonzalez.argtypes = [_p, ctypes.POINTER(KcPoints), _i64, _i64,
                                    _p, _p, _p, _p]
     L.kcenter_gonzalez_noalloc.argtypes = [_p, ctypes.POINTER(KcPoints),
@@ -107,9 +109,9 @@ def load_library(path=LIB_PATH):
                               ctypes.POINTER(_i32), _p]
     L.kcenter_batch.argtypes = [_p, _p, _i32, _p]
     for name in ("kc_create", "kc_set_option", "kc_device_status",
-                 "kc_timing_read", "kc_counter_read",
+                 "kc_timing_read", "kc_counter_read", "kc_tune_report",
                  "kcenter_gonzalez", "kcenter_gonzalez_noalloc",
-           "kcenter_gonzalez_resume",
+                 "kcenter_gonzalez_resume",
                  "kcenter_mrg", "kcenter_mrg_rounds",
                  "kcenter_assign",
                  "kcenter_eim", "kcenter_batch"):
@@ -202,6 +204,19 @@ class Handle:
         self._check(load_library().kc_counter_read(self._h, name.encode(),
                                                    ctypes.byref(v)))
         return v.value
+
+    def tune_report(self):
+        """The autotuner's choices: {key: (variant, [ms per variant])}."""
+        L = load_library()
+        need = _i64(0)
+        L.kc_tune_report(self._h, None, 0, ctypes.byref(need))
+        buf = ctypes.create_string_buffer(max(int(need.value), 1))
+        self._check(L.kc_tune_report(self._h, buf, len(buf), ctypes.byref(need)))
+        out = {}
+        for line in buf.value.decode().splitlines():
+            f = line.split()
+            out[f[0]] = (int(f[1]), [float(x) for x in f[2:]])
+        return out
 
     def device_status(self):
         """Synchronise the current stream and read/clear the status word."""

@@ -194,6 +194,59 @@ int kc_handle::run_graph(const std::string& key, hipStream_t stream,
     return e == hipSuccess ? KC_OK : fail(KC_EHIP, "graph launch: %s", hipGetErrorString(e));
 }
 
+int kc_handle::tune(const std::string& key, int nvar, const bool* feasible, hipStream_t s,
+                    const std::function<int(int)>& run)
+{
+    int first = -1, nfeas = 0;
+    for (int v = 0; v < nvar; ++v)
+        if (feasible[v]) {
+            if (first < 0) first = v;
+            ++nfeas;
+        }
+    if (first < 0) return fail(KC_EUNSUPPORTED, "no feasible variant for %s", key.c_str());
+    auto it = tuned.find(key);
+    if (it != tuned.end() && feasible[it->second]) return run(it->second);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        cs = hipStreamCaptureStatusActive;
+    }
+    if (!autotune || nfeas == 1 || cs != hipStreamCaptureStatusNone) return run(first);
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) {
+        (void)hipGetLastError();
+        if (ea) hipEventDestroy(ea);
+        return run(first);
+    }
+    std::vector<float> ms(nvar, -1.f);
+    int best = first, rc = KC_OK;
+    const bool timing_was = timing;   // measured runs stay out of the spans
+    timing = false;
+    for (int v = 0; v < nvar && rc == KC_OK; ++v) {
+        if (!feasible[v]) continue;
+        rc = run(v);   // warm: caches, captured graphs
+        if (rc) break;
+        hipEventRecord(ea, s);
+        rc = run(v);
+        hipEventRecord(eb, s);
+        if (rc) break;
+        float t = 0.f;
+        if (hipEventSynchronize(eb) != hipSuccess || hipEventElapsedTime(&t, ea, eb) != hipSuccess) {
+            (void)hipGetLastError();
+            t = 1e30f;
+        }
+        ms[v] = t;
+        if (ms[best] < 0.f || t < ms[best]) best = v;
+    }
+    timing = timing_was;
+    hipEventDestroy(ea);
+    hipEventDestroy(eb);
+    if (rc) return rc;
+    tuned[key] = best;
+    tune_ms[key] = ms;
+    return run(best);   // the call's results and spans: the chosen variant's
+}
+
 // ---------------------------------------------------------------------------
 // argument checks
 
@@ -592,6 +645,10 @@ int kc_set_option(kc_handle* h, const char* name, int64_t value)
         h->mfma_split = value != 0;
         return KC_OK;
     }
+    if (!strcmp(name, "autotune")) {
+        h->autotune = value != 0;
+        return KC_OK;
+    }
     if (!strcmp(name, "timing")) {
         h->timing = value != 0;
         return KC_OK;
@@ -607,6 +664,30 @@ int kc_set_option(kc_handle* h, const char* name, int64_t value)
         return KC_OK;
     }
     return h->fail(KC_EINVAL, "unknown option '%s'", name);
+}
+
+int kc_tune_report(kc_handle* h, char* buf, int64_t cap, int64_t* need)
+{
+    if (!h || !need || cap < 0 || (cap > 0 && !buf)) return KC_EINVAL;
+    std::string out;
+    char num[32];
+    for (auto& kv : h->tuned) {
+        out += kv.first;
+        snprintf(num, sizeof num, " %d", kv.second);
+        out += num;
+        auto it = h->tune_ms.find(kv.first);
+        if (it != h->tune_ms.end())
+            for (float t : it->second) {
+                snprintf(num, sizeof num, " %.4f", (double)t);
+                out += num;
+            }
+        out += '\n';
+    }
+    *need = (int64_t)out.size() + 1;
+    if (cap == 0) return KC_OK;   // a size query
+    if (cap < *need) return h->fail(KC_EINVAL, "tune report needs %lld bytes", (long long)*need);
+    memcpy(buf, out.c_str(), out.size() + 1);
+    return KC_OK;
 }
 
 int kc_timing_read(kc_handle* h, const char* name, double* ms, int64_t* launches,
@@ -705,50 +786,60 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
     rc = kc_plan_gon(h, "g.", pts->d, 1024, jobs, R, H, s);
     if (rc) return rc;
 
-    // register-resident persistent kernel when the whole problem fits
-    if (h->allow_resident) {
-        int v = 0;
-        uint32_t G = 0;
-        if (h->resident_fit(pts->d, (uint64_t)pts->n, &v, &G)) {
-            // exchange words, then the abort flag: one fill clears both.  The
-            // kernel writes every min-distance and every key (zeros past an
-            // early stop); candidate and center gathers read the caller's rows.
-            const uint64_t bw = kc_resident_slot_words((int)k, G);
-            u64* bar = (u64*)h->ws("g.bar", sizeof(u64) * (bw + 8));
-            if (!bar) return h->fail(KC_ENOMEM, "workspace allocation failed");
-            uint32_t* abort_flag = (uint32_t*)(bar + bw);
-            // points straight from the caller's rows when the kernel's row
-            // loads allow them, else from the SoA staging copy
-            const int rows = kc_resident_rows_ok(pts->d, pts->f32, pts->ld, (uint64_t)pts->n);
-            if (!rows)
-                kc_stage_soa(pts->f32, pts->ld, pts->d, 0, (uint32_t)pts->n, (float*)R.xs,
-                             R.stride, 0, s);
-            kc_fill_u64(bar, 0ull, bw + 1, s);
-            R.xa = pts->f32;
-            R.lda = pts->ld;
-            hipEvent_t ev = h->span_begin(s);
-            hipError_t e = kc_gon_resident(pts->d, v, G, R.xs, R.stride, 0, (uint32_t)pts->n, nullptr,
-                                           (uint32_t)first, (int)k, R.mind, R.keys, bar,
-                                           abort_flag, h->spin_limit, pts->f32, pts->ld, rows,
-                                           h->status_word, nullptr, nullptr, s);
-            h->span_end("gon_resident", ev, 1, s);
-            if (e == hipSuccess) {
-                kc_gon_finish(R, centers, n_chosen, radius_trace, nullptr, nullptr, nullptr, s);
-                e = hipGetLastError();
-                return e == hipSuccess ? KC_OK
-                                       : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
-            }
-            (void)hipGetLastError();   // not co-resident: fall back to streaming
-        }
-    }
-
+    // Engines: the register-resident persistent kernel in either variant
+    // when the points fit its co-resident grid, or the streaming steps; the
+    // autotuner measures the feasible ones once per shape bucket.
     char key[256];
     snprintf(key, sizeof key, "gon:%p:%lld:%d:%lld:%lld:%lld:%p:%p:%p", (const void*)pts->f32,
              (long long)pts->n, pts->d, (long long)pts->ld, (long long)k, (long long)first,
              (void*)centers, (void*)radius_trace, (void*)n_chosen);
-    return kc_run_gon_stream(h, key, R, H, jobs, "gon_step", s, [&](hipStream_t st) {
-        kc_gon_finish(R, centers, n_chosen, radius_trace, nullptr, nullptr, nullptr, st);
-    });
+    auto stream_run = [&]() {
+        return kc_run_gon_stream(h, key, R, H, jobs, "gon_step", s, [&](hipStream_t st) {
+            kc_gon_finish(R, centers, n_chosen, radius_trace, nullptr, nullptr, nullptr, st);
+        });
+    };
+    const int rows = kc_resident_rows_ok(pts->d, pts->f32, pts->ld, (uint64_t)pts->n);
+    auto run = [&](int var) -> int {
+        if (var == 2) return stream_run();
+        const uint32_t G = kc_resident_blocks_for(pts->d, var, (uint64_t)pts->n);
+        // exchange words, then the abort flag: one fill clears both.  The
+        // kernel writes every min-distance and every key (zeros past an early
+        // stop); candidate and center gathers read the caller's rows.
+        const uint64_t bw = kc_resident_slot_words((int)k, G);
+        u64* bar = (u64*)h->ws("g.bar", sizeof(u64) * (bw + 8));
+        if (!bar) return h->fail(KC_ENOMEM, "workspace allocation failed");
+        uint32_t* abort_flag = (uint32_t*)(bar + bw);
+        // points straight from the caller's rows when the kernel's row loads
+        // allow them, else from the SoA staging copy
+        if (!rows)
+            kc_stage_soa(pts->f32, pts->ld, pts->d, 0, (uint32_t)pts->n, (float*)R.xs, R.stride,
+                         0, s);
+        kc_fill_u64(bar, 0ull, bw + 1, s);
+        R.xa = pts->f32;
+        R.lda = pts->ld;
+        hipEvent_t ev = h->span_begin(s);
+        hipError_t e = kc_gon_resident(pts->d, var, G, R.xs, R.stride, 0, (uint32_t)pts->n,
+                                       nullptr, (uint32_t)first, (int)k, R.mind, R.keys, bar,
+                                       abort_flag, h->spin_limit, pts->f32, pts->ld, rows,
+                                       h->status_word, nullptr, nullptr, s);
+        h->span_end("gon_resident", ev, 1, s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();   // not co-resident: stream instead
+            return stream_run();
+        }
+        kc_gon_finish(R, centers, n_chosen, radius_trace, nullptr, nullptr, nullptr, s);
+        e = hipGetLastError();
+        return e == hipSuccess ? KC_OK : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
+    };
+    bool feas[3] = {false, false, true};
+    for (int v = 0; v < 2; ++v) {
+        const uint32_t G = kc_resident_blocks_for(pts->d, v, (uint64_t)pts->n);
+        feas[v] = h->allow_resident && G > 0 && (int64_t)G <= (int64_t)h->resident_max(pts->d, v);
+    }
+    char tkey[96];
+    snprintf(tkey, sizeof tkey, "gon/%d/%d/%d/%d", pts->d, (int)floor(2.0 * log2((double)pts->n)),
+             (int)floor(2.0 * log2((double)k)), rows);
+    return h->tune(tkey, 3, feas, s, run);
 }
 
 }  // extern "C"

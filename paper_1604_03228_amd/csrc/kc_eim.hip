@@ -651,124 +651,153 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
             } else {
                 kc_fill_u64((u64*)tau, 0xFFF0000000000000ull, 1, s);   // -inf
             }
-            // distance pass of the candidates against this iteration's samples
-            if (nds > 0 && nc > 0 && d <= KC_EIM_DIRECT_MAXD) {
-                const double u32 = 5.9604644775390625e-8, m = d + 2;
-                const double g = m * u32 / (1.0 - m * u32);
-                hipEvent_t ev = h->span_begin(s);
-                switch (d) {
+            // Distance pass of the candidates against this iteration's
+            // samples, then the keep / remove decisions: variant 0 computes
+            // canonical FP32 distances on the VALU (d <= 8), 1 the FP32 MFMA,
+            // 2 split BF16 MFMAs (option mfma_split), both on the points
+            // translated to the local origin.  All decide exactly alike; the
+            // autotuner measures them once per shape bucket (with the
+            // intervals restored before each of its runs).
+            auto pass = [&](int var) -> int {
+                if (nds > 0 && nc > 0 && var == 0) {
+                    const double u32 = 5.9604644775390625e-8, m = d + 2;
+                    const double g = m * u32 / (1.0 - m * u32);
+                    hipEvent_t ev = h->span_begin(s);
+                    switch (d) {
 #define KC_DIR_CASE(DD)                                                                     \
     case DD:                                                                                \
         hipLaunchKernelGGL(k_eim_direct<DD>, g1(nc), dim3(256), 0, s, X, ld, cand, nc,      \
                            S + ns - nds, nds, g, lo, hi);                                   \
         break;
-                    KC_DIR_CASE(1)
-                    KC_DIR_CASE(2)
-                    KC_DIR_CASE(3)
-                    KC_DIR_CASE(4)
-                    KC_DIR_CASE(5)
-                    KC_DIR_CASE(6)
-                    KC_DIR_CASE(7)
-                    KC_DIR_CASE(8)
+                        KC_DIR_CASE(1)
+                        KC_DIR_CASE(2)
+                        KC_DIR_CASE(3)
+                        KC_DIR_CASE(4)
+                        KC_DIR_CASE(5)
+                        KC_DIR_CASE(6)
+                        KC_DIR_CASE(7)
+                        KC_DIR_CASE(8)
 #undef KC_DIR_CASE
-                }
-                h->span_end("eim_dist", ev, 1, s);
-            } else if (nds > 0 && nc > 0) {
-                // split BF16 MFMAs (option mfma_split) or the FP32 MFMA, on
-                // the points translated to the local origin
-                const bool split = h->mfma_split;
-                const int dp = kc_mindist_dpad(d, split);
-                const uint32_t kpad = (nds + 15u) & ~15u;
-                float* XR = (float*)h->ws("e.XR", 4ull * nc * d);
-                KcCenters Cs;
-                Cs.kpad = kpad;
-                Cs.dp = dp;
-                Cs.Cf = (float*)h->ws("e.cf", 4ull * kpad * dp);
-                Cs.cn = (float*)h->ws("e.cn", 4ull * kpad);
-                Cs.cnl = (float*)h->ws("e.cnl", 4ull * kpad);
-                Cs.clen = (float*)h->ws("e.clen", 4ull * kpad);
-                Cs.cmax = (float*)h->ws("e.cmax", 16);
-                Cs.mu = mu;
-                if (split) {
-                    Cs.Cb = (uint16_t*)h->ws("e.cbh", 2ull * kpad * dp);
-                    Cs.Cbl = (uint16_t*)h->ws("e.cbl", 2ull * kpad * dp);
-                } else {
-                    Cs.Ct = (float*)h->ws("e.ct", 4ull * kpad * dp);
-                }
-                KcMinOut O;
-                O.arg = (int32_t*)h->ws("e.arg", 4ull * nc);
-                O.m1 = (float*)h->ws("e.m1", 4ull * nc);
-                O.lo2 = (float*)h->ws("e.m2", 4ull * nc);
-                O.nx = (float*)h->ws("e.nx", 4ull * nc);
-                if (!XR || !Cs.Cf || (!split && !Cs.Ct) || (split && (!Cs.Cb || !Cs.Cbl)) || !Cs.cn ||
-                    !Cs.cnl || !Cs.clen || !Cs.cmax || !O.arg ||
-                    !O.m1 || !O.lo2 || !O.nx)
-                    return h->fail(KC_ENOMEM, "workspace allocation failed");
-                hipLaunchKernelGGL(k_gather_rows, g1((uint64_t)nc * d), dim3(256), 0, s, X, ld,
-                                   d, cand, nc, XR);
-                // the new samples in ascending order of norm, then staged
-                uint32_t* kin = (uint32_t*)h->ws("e.skey", 4ull * nds);
-                uint32_t* kout = (uint32_t*)h->ws("e.skey2", 4ull * nds);
-                uint32_t* vin = (uint32_t*)h->ws("e.sval", 4ull * nds);
-                uint32_t* vout = (uint32_t*)h->ws("e.sval2", 4ull * nds);
-                size_t tbytes = 0;
-                hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, kin, kout, vin, vout,
-                                                   (int)nds, 0, 32, s);
-                void* tmp = h->ws("e.sorttmp", tbytes);
-                if (!kin || !kout || !vin || !vout || !tmp)
-                    return h->fail(KC_ENOMEM, "workspace allocation failed");
-                hipLaunchKernelGGL(k_sample_norm_keys, g1(nds), dim3(256), 0, s, X, ld, d,
-                                   S + ns - nds, nds, mu, kin, vin);
-                if (hipcub::DeviceRadixSort::SortPairs(tmp, tbytes, kin, kout, vin, vout,
-                                                       (int)nds, 0, 32, s) != hipSuccess) {
-                    (void)hipGetLastError();
-                    return h->fail(KC_EHIP, "sample sort failed");
-                }
-                kc_stage_centers(X, nullptr, ld, d, n, nullptr, vout, nds, nullptr, Cs,
-                                 h->status_word, s);
-                hipEvent_t ev = h->span_begin(s);
-                // d(x, S) needs the smallest distance's bounds only
-                kc_mindist(XR, nullptr, nullptr, d, nc, d, Cs, O, false, s);
-                h->span_end("eim_dist", ev, 1, s);
-                hipLaunchKernelGGL(k_eim_bounds, g1(nc), dim3(256), 0, s, nc, d, cand, O, Cs,
-                                   lo, hi);
-            }
-            // keep / remove
-            kc_fill_u32(cnt + 4, 0u, 1, s);
-            hipLaunchKernelGGL(k_eim_decide, g1(nc), dim3(256), 0, s, nc, cand, lo, hi, tau,
-                               keep, unsure, cnt + 4);
-            if (d <= KC_EXT_MAXD) {
-                // the undecided count sizes the split pass: candidate groups
-                // of 64 times slices of S, about 2048 blocks in all
-                uint32_t nu = 0;
-                rc = kc_read_u32(h, cnt + 4, &nu, s);
-                if (rc) return rc;
-                if (nu > 0) {
-                    const uint32_t gx = (nu + 63) / 64;
-                    const uint32_t gy = std::max<uint32_t>(
-                        1, std::min<uint32_t>({(2048 + gx - 1) / gx, ns / 512, 65535u}));
-                    kc_fill_u64((u64*)exm, 0x7FF0000000000000ull, nu, s);   // +inf
-                    switch (d) {
-#define KC_EXS_CASE(DD)                                                                     \
-    case DD:                                                                                \
-        hipLaunchKernelGGL(k_eim_exact_split_d<DD>, dim3(gx, gy), dim3(256), 0, s, X, ld, cand, \
-                           unsure, nu, S, ns, exm);                                         \
-        break;
-                        KC_EXS_CASE(10)
-                        KC_EXS_CASE(16)
-                        KC_EXS_CASE(32)
-#undef KC_EXS_CASE
-                    default:
-                        hipLaunchKernelGGL(k_eim_exact_split, dim3(gx, gy), dim3(256), 0, s, X,
-                                           ld, d, cand, unsure, nu, S, ns, exm);
                     }
-                    hipLaunchKernelGGL(k_eim_exact_finish, g1(nu), dim3(256), 0, s, cand,
-                                       unsure, nu, exm, tau, keep, lo, hi);
+                    h->span_end("eim_dist", ev, 1, s);
+                } else if (nds > 0 && nc > 0) {
+                    const bool split = var == 2;
+                    const int dp = kc_mindist_dpad(d, split);
+                    const uint32_t kpad = (nds + 15u) & ~15u;
+                    float* XR = (float*)h->ws("e.XR", 4ull * nc * d);
+                    KcCenters Cs;
+                    Cs.kpad = kpad;
+                    Cs.dp = dp;
+                    Cs.Cf = (float*)h->ws("e.cf", 4ull * kpad * dp);
+                    Cs.cn = (float*)h->ws("e.cn", 4ull * kpad);
+                    Cs.cnl = (float*)h->ws("e.cnl", 4ull * kpad);
+                    Cs.clen = (float*)h->ws("e.clen", 4ull * kpad);
+                    Cs.cmax = (float*)h->ws("e.cmax", 16);
+                    Cs.mu = mu;
+                    if (split) {
+                        Cs.Cb = (uint16_t*)h->ws("e.cbh", 2ull * kpad * dp);
+                        Cs.Cbl = (uint16_t*)h->ws("e.cbl", 2ull * kpad * dp);
+                    } else {
+                        Cs.Ct = (float*)h->ws("e.ct", 4ull * kpad * dp);
+                    }
+                    KcMinOut O;
+                    O.arg = (int32_t*)h->ws("e.arg", 4ull * nc);
+                    O.m1 = (float*)h->ws("e.m1", 4ull * nc);
+                    O.lo2 = (float*)h->ws("e.m2", 4ull * nc);
+                    O.nx = (float*)h->ws("e.nx", 4ull * nc);
+                    // the new samples in ascending order of norm, then staged
+                    uint32_t* kin = (uint32_t*)h->ws("e.skey", 4ull * nds);
+                    uint32_t* kout = (uint32_t*)h->ws("e.skey2", 4ull * nds);
+                    uint32_t* vin = (uint32_t*)h->ws("e.sval", 4ull * nds);
+                    uint32_t* vout = (uint32_t*)h->ws("e.sval2", 4ull * nds);
+                    size_t tbytes = 0;
+                    hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, kin, kout, vin, vout,
+                                                       (int)nds, 0, 32, s);
+                    void* tmp = h->ws("e.sorttmp", tbytes);
+                    if (!XR || !Cs.Cf || (!split && !Cs.Ct) || (split && (!Cs.Cb || !Cs.Cbl)) ||
+                        !Cs.cn || !Cs.cnl || !Cs.clen || !Cs.cmax || !O.arg || !O.m1 || !O.lo2 ||
+                        !O.nx || !kin || !kout || !vin || !vout || !tmp)
+                        return h->fail(KC_ENOMEM, "workspace allocation failed");
+                    hipLaunchKernelGGL(k_gather_rows, g1((uint64_t)nc * d), dim3(256), 0, s, X,
+                                       ld, d, cand, nc, XR);
+                    hipLaunchKernelGGL(k_sample_norm_keys, g1(nds), dim3(256), 0, s, X, ld, d,
+                                       S + ns - nds, nds, mu, kin, vin);
+                    if (hipcub::DeviceRadixSort::SortPairs(tmp, tbytes, kin, kout, vin, vout,
+                                                           (int)nds, 0, 32, s) != hipSuccess) {
+                        (void)hipGetLastError();
+                        return h->fail(KC_EHIP, "sample sort failed");
+                    }
+                    kc_stage_centers(X, nullptr, ld, d, n, nullptr, vout, nds, nullptr, Cs,
+                                     h->status_word, s);
+                    hipEvent_t ev = h->span_begin(s);
+                    // d(x, S) needs the smallest distance's bounds only
+                    kc_mindist(XR, nullptr, nullptr, d, nc, d, Cs, O, false, s);
+                    h->span_end("eim_dist", ev, 1, s);
+                    hipLaunchKernelGGL(k_eim_bounds, g1(nc), dim3(256), 0, s, nc, d, cand, O,
+                                       Cs, lo, hi);
                 }
+                // keep / remove
+                kc_fill_u32(cnt + 4, 0u, 1, s);
+                hipLaunchKernelGGL(k_eim_decide, g1(nc), dim3(256), 0, s, nc, cand, lo, hi, tau,
+                                   keep, unsure, cnt + 4);
+                if (d <= KC_EXT_MAXD) {
+                    // the undecided count sizes the split pass: candidate
+                    // groups of 64 times slices of S, about 2048 blocks in all
+                    uint32_t nu = 0;
+                    int rc3 = kc_read_u32(h, cnt + 4, &nu, s);
+                    if (rc3) return rc3;
+                    if (nu > 0) {
+                        const uint32_t gx = (nu + 63) / 64;
+                        const uint32_t gy = std::max<uint32_t>(
+                            1, std::min<uint32_t>({(2048 + gx - 1) / gx, ns / 512, 65535u}));
+                        kc_fill_u64((u64*)exm, 0x7FF0000000000000ull, nu, s);   // +inf
+                        switch (d) {
+#define KC_EXS_CASE(DD)                                                                       \
+    case DD:                                                                                  \
+        hipLaunchKernelGGL(k_eim_exact_split_d<DD>, dim3(gx, gy), dim3(256), 0, s, X, ld, cand, \
+                           unsure, nu, S, ns, exm);                                           \
+        break;
+                            KC_EXS_CASE(10)
+                            KC_EXS_CASE(16)
+                            KC_EXS_CASE(32)
+#undef KC_EXS_CASE
+                        default:
+                            hipLaunchKernelGGL(k_eim_exact_split, dim3(gx, gy), dim3(256), 0, s,
+                                               X, ld, d, cand, unsure, nu, S, ns, exm);
+                        }
+                        hipLaunchKernelGGL(k_eim_exact_finish, g1(nu), dim3(256), 0, s, cand,
+                                           unsure, nu, exm, tau, keep, lo, hi);
+                    }
+                } else {
+                    hipLaunchKernelGGL(k_eim_exact, dim3(2048), dim3(256), 0, s, X, ld, d, cand,
+                                       unsure, cnt + 4, S, ns, tau, keep, lo, hi);
+                }
+                const hipError_t e = hipGetLastError();
+                return e == hipSuccess ? KC_OK
+                                       : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
+            };
+            const bool feas[3] = {d <= KC_EIM_DIRECT_MAXD, true, h->mfma_split};
+            char tkey[96];
+            snprintf(tkey, sizeof tkey, "eim/%d/%d/%d", d, (int)floor(2.0 * log2((double)nc + 1)),
+                     (int)floor(2.0 * log2((double)nds + 1)));
+            const bool tuning = h->autotune && nds > 0 && nc > 0 && !h->tuned.count(tkey);
+            if (tuning) {   // the intervals every measured run starts from
+                float* lo0 = (float*)h->ws("e.lo0", 4ull * n);
+                float* hi0 = (float*)h->ws("e.hi0", 4ull * n);
+                if (!lo0 || !hi0) return h->fail(KC_ENOMEM, "workspace allocation failed");
+                hipMemcpyAsync(lo0, lo, 4ull * n, hipMemcpyDeviceToDevice, s);
+                hipMemcpyAsync(hi0, hi, 4ull * n, hipMemcpyDeviceToDevice, s);
+                rc = h->tune(tkey, 3, feas, s, [&](int var) {
+                    hipMemcpyAsync(lo, lo0, 4ull * n, hipMemcpyDeviceToDevice, s);
+                    hipMemcpyAsync(hi, hi0, 4ull * n, hipMemcpyDeviceToDevice, s);
+                    return pass(var);
+                });
+            } else if (nds > 0 && nc > 0) {
+                rc = h->tune(tkey, 3, feas, s, pass);
             } else {
-                hipLaunchKernelGGL(k_eim_exact, dim3(2048), dim3(256), 0, s, X, ld, d, cand,
-                                   unsure, cnt + 4, S, ns, tau, keep, lo, hi);
+                rc = pass(1);
             }
+            if (rc) return rc;
             kc_compact(C, keep, cand, nc, R2, cnt + 3, s);
             std::swap(R, R2);
             uint32_t rc2[2];

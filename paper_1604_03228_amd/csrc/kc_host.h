@@ -59,6 +59,9 @@ struct kc_handle {
     bool use_graphs = true;
     bool allow_resident = true;
     bool mfma_split = true;           // FP32 distance passes on split BF16 MFMAs
+    bool autotune = true;             // measured choice of engine variants
+    std::map<std::string, int> tuned;  // key -> chosen variant
+    std::map<std::string, std::vector<float>> tune_ms;   // key -> measured ms per variant
     uint32_t spin_limit = 1u << 20;   // polls before a barrier wait gives up
     uint32_t* status_word = nullptr;  // device, see kc_device_status
     void* scratch = nullptr;          // device address of the no-allocation array
@@ -98,6 +101,16 @@ struct kc_handle {
     void* upload(const std::string& name, const void* src, size_t bytes, hipStream_t s);
     int run_graph(const std::string& key, hipStream_t stream,
                   const std::function<void(hipStream_t)>& enqueue);
+    // Measured choice among variants 0..nvar-1 of one operation that all
+    // give the same result (feasible[v] says which may run).  With autotune
+    // on and `key` not yet seen, every feasible variant runs twice on `s`,
+    // the second run timed between events (the host waits for them), with
+    // the timing spans off; the fastest is cached for `key` and runs once
+    // more, which gives the call's results and spans.  Otherwise the cached
+    // choice runs (or, untuned, the first feasible variant).  Returns
+    // run()'s status.
+    int tune(const std::string& key, int nvar, const bool* feasible, hipStream_t s,
+             const std::function<int(int)>& run);
     // Co-resident blocks of resident variant v for dimension d (0: none),
     // lowered to resident_cap when that is set.
     int resident_max(int d, int v);

@@ -121,6 +121,7 @@ def test_resident_large_variant(kc, orc, n, cap):
     k = 64
     h = kc.Handle()
     h.set_option("resident_blocks", cap)
+    h.set_option("autotune", 0)   # the resident engine, not a measured choice
     h.set_option("timing", 1)
     Xd = torch.from_numpy(X).cuda()
     c, tr, nch = kc.gonzalez(Xd, k, 3, handle=h)
@@ -144,6 +145,7 @@ def test_resident_row_layouts(kc, orc, rows_layout, d, layout):
     X = rng.integers(-20, 21, (n, d)).astype(np.float32)
     k = 48
     h = kc.Handle()
+    h.set_option("autotune", 0)   # the resident engine, not a measured choice
     h.set_option("timing", 1)
     Xd = rows_layout(X, layout)
     c, tr, nch = kc.gonzalez(Xd, k, 5, handle=h)
