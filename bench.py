@@ -39,12 +39,12 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector peak (dense)
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
-# VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane
-# operations per second (a wave64 instruction takes 4 cycles on a SIMD).
-# The quoted 157.3 TFLOP/s FP32 vector peak is this rate x 2 (FMA) x 2
-# (packed FP32); the engines use no packed FP32, so one FP32 instruction per
-# lane and cycle is their issue ceiling (reported beside the FLOP fraction).
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU issue ceiling of MI355X: the FP32 vector peak of 157.3 TFLOP/s is
+# 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz FMA lane-operations x 2 flop, so
+# one FP32 VALU instruction retires at most 32 lanes per cycle per SIMD
+# (measured: sub/FMA distance chains reach 0.75 of this with 8 waves per
+# SIMD, 0.57 with 2).  Reported beside the FLOP fraction.
+VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 

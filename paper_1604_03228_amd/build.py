@@ -4,7 +4,9 @@
 
 Each .hip source under csrc/ is compiled to an object in _build/ and the
 objects are linked into paper_1604_03228_amd/libkcenter.so.  Packed FP32
-instructions are disabled (the compiler must not form v_pk_*_f32).
+instructions are disabled (the compiler must not form v_pk_*_f32); MFMA
+results go to ordinary VGPRs (the distance passes' epilogues read them
+directly instead of copying them out of accumulation registers).
 """
 import concurrent.futures as cf
 import os
@@ -22,6 +24,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-ffp-contract=off", "-fno-fast-math",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wno-unused-result"]
 
 

@@ -83,7 +83,8 @@ __device__ __forceinline__ float kc_bf16_to_f32(uint16_t h)
     return __uint_as_float((uint32_t)h << 16);
 }
 
-#define KC_MD_WAVES 4
+// Waves per block of the distance pass: 4, or 8 (twice the points share
+// each LDS copy of a center chunk; for large n).
 // Input modes of the distance pass: FP32 on v_mfma_f32_16x16x4f32; BF16
 // inputs (the caller's BF16 copy) on v_mfma_f32_16x16x32_bf16; FP32 inputs
 // split into BF16 high and low parts, x = h + l + r with h = bf16(x),
@@ -102,6 +103,17 @@ __host__ __device__ constexpr int kc_md_pt(int mode, int ks)
 {
     return (mode == KC_MD_F32 && ks <= 8) || (mode != KC_MD_F32 && ks <= 2) ? 4 : 2;
 }
+// LDS row pitch of a staged center, in elements: the padded K plus 16
+// bytes, so the 16 rows one A-operand read touches start in distinct banks.
+__host__ __device__ constexpr int kc_md_pitch(int mode, int dp)
+{
+    return mode == KC_MD_F32 ? dp + 4 : dp + 8;
+}
+
+__device__ __forceinline__ float kc_max3(float a, float b, float c)
+{
+    return fmaxf(fmaxf(a, b), c);
+}
 
 __device__ __forceinline__ uint16_t kc_f32_to_bf16_rne(float t)
 {
@@ -119,9 +131,12 @@ __device__ __forceinline__ uint16_t kc_f32_to_bf16_rne(float t)
 // give nearly per-center bounds at no cost per pair; with BF16 inputs the
 // smallest v (m1).  Always |x|^2 of the values fed to the MFMA (nx; of the
 // FP32 values in the split mode).  FP32 inputs with a local origin C.mu have
-// it subtracted as they load; the centers come translated.
-template <int MODE, int KS, bool LAB>
-__global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
+// it subtracted as they load; the centers come translated.  The passes
+// without labels start each MFMA chain from -|c|^2/2 and keep the largest
+// -|c|^2/2 + x.c, which is -v/2 (scaling by 2 is exact), so their epilogue
+// is one max per output.
+template <int MODE, int KS, bool LAB, int W>
+__global__ __launch_bounds__(W * 64) void k_mindist_mfma(
     const float* __restrict__ X, const uint16_t* __restrict__ Xb, const float* __restrict__ ex,
     int64_t ld, uint32_t n, int d, float gm, KcCenters C, uint32_t chunk, KcMinOut O)
 {
@@ -131,6 +146,7 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
     constexpr int DP = BF ? KS * 32 : KS * 4;  // padded K
     constexpr int KC_MD_PT = kc_md_pt(MODE, KS);
     constexpr bool CB = !LAB && !RB;            // per-chunk bounds
+    constexpr int PITCH = kc_md_pitch(MODE, DP);
     __shared__ float s_bmax;
     extern __shared__ __align__(16) unsigned char kc_smem[];
     float* s_norm = (float*)kc_smem;                          // [chunk] cn
@@ -138,7 +154,7 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
     float* s_len = s_cnl + chunk;                             // [chunk] |c|
     float* s_cer = s_len + chunk;                             // [chunk] e_c (BF16)
     void* s_c = (void*)(s_cer + (RB ? chunk : 0));            // [chunk][DP]
-    uint16_t* s_cl = (uint16_t*)s_c + (SP ? (size_t)chunk * DP : 0);   // low parts
+    uint16_t* s_cl = (uint16_t*)s_c + (SP ? (size_t)chunk * PITCH : 0);   // low parts
     const float* __restrict__ Cf = C.mu ? C.Ct : C.Cf;
     const uint16_t* __restrict__ Cb = C.Cb;
     const uint32_t kpad = C.kpad;
@@ -147,7 +163,7 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
     const int wave = threadIdx.x >> 6;
     const int col = lane & 15, grp = lane >> 4;
     const uint64_t p0 =
-        ((uint64_t)blockIdx.x * KC_MD_WAVES + wave) * (16 * KC_MD_PT);
+        ((uint64_t)blockIdx.x * W + wave) * (16 * KC_MD_PT);
 
     // B operand (points) for all point tiles and K-steps, kept in registers
     float bf[KC_MD_PT][BF ? 1 : KS];
@@ -227,7 +243,7 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
     KcBest best[KC_MD_PT];
 #pragma unroll
     for (int pt = 0; pt < KC_MD_PT; ++pt) {
-        best[pt].m1 = __builtin_inff();
+        best[pt].m1 = LAB ? __builtin_inff() : -__builtin_inff();
         best[pt].a1 = 0x7FFFFFFF;
         best[pt].wb = __builtin_inff();
         best[pt].l2 = __builtin_inff();
@@ -237,7 +253,7 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
         const uint32_t cn = min(chunk, kpad - c0);
         __syncthreads();
         for (uint32_t q = threadIdx.x; q < cn; q += blockDim.x) {
-            s_norm[q] = C.cn[c0 + q];
+            s_norm[q] = LAB ? C.cn[c0 + q] : -0.5f * C.cn[c0 + q];
             if (LAB || CB) s_len[q] = C.clen[c0 + q];
             if (LAB) {
                 s_cnl[q] = C.cnl[c0 + q];
@@ -247,15 +263,19 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
         if (!BF) {
             const float4* src = (const float4*)(Cf + (uint64_t)c0 * DP);
             float4* dst = (float4*)s_c;
-            for (uint32_t q = threadIdx.x; q < cn * DP / 4; q += blockDim.x) dst[q] = src[q];
+            for (uint32_t q = threadIdx.x; q < cn * DP / 4; q += blockDim.x) {
+                const uint32_t r = q / (DP / 4), w = q - r * (DP / 4);
+                dst[r * (PITCH / 4) + w] = src[q];
+            }
         } else {
             const uint4* src = (const uint4*)(Cb + (uint64_t)c0 * DP);
             uint4* dst = (uint4*)s_c;
-            for (uint32_t q = threadIdx.x; q < cn * DP / 8; q += blockDim.x) dst[q] = src[q];
-            if (SP) {
-                const uint4* srl = (const uint4*)(C.Cbl + (uint64_t)c0 * DP);
-                uint4* dsl = (uint4*)s_cl;
-                for (uint32_t q = threadIdx.x; q < cn * DP / 8; q += blockDim.x) dsl[q] = srl[q];
+            const uint4* srl = (const uint4*)(C.Cbl + (uint64_t)c0 * DP);
+            uint4* dsl = (uint4*)s_cl;
+            for (uint32_t q = threadIdx.x; q < cn * DP / 8; q += blockDim.x) {
+                const uint32_t r = q / (DP / 8), w = q - r * (DP / 8);
+                dst[r * (PITCH / 8) + w] = src[q];
+                if (SP) dsl[r * (PITCH / 8) + w] = srl[q];
             }
         }
         __syncthreads();
@@ -270,28 +290,44 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
             __syncthreads();
         }
 
+        // A operand: centers ct + col, K slice of this lane group; the next
+        // tile's operands load while this tile's MFMAs run
+        float naf[BF ? 1 : KS];
+        kc_v8bf nab[BF ? KS : 1];
+        kc_v8bf nal[SP ? KS : 1];
+        float4 nnc;
+        auto load_a = [&](uint32_t ct) {
+            if (!BF) {
+                const float* cs = (const float*)s_c + (uint64_t)(ct + col) * PITCH;
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) naf[BF ? 0 : ks] = cs[ks * 4 + grp];
+            } else {
+                const uint16_t* cs = (const uint16_t*)s_c + (uint64_t)(ct + col) * PITCH;
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks)
+                    nab[BF ? ks : 0] = *(const kc_v8bf*)(cs + ks * 32 + grp * 8);
+                if (SP) {
+                    const uint16_t* cl = s_cl + (uint64_t)(ct + col) * PITCH;
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks)
+                        nal[SP ? ks : 0] = *(const kc_v8bf*)(cl + ks * 32 + grp * 8);
+                }
+            }
+            nnc = *(const float4*)(s_norm + ct + grp * 4);
+        };
+        load_a(0);
         for (uint32_t ct = 0; ct < cn; ct += 16) {
-            // A operand: centers ct + col, K slice of this lane group
             float af[BF ? 1 : KS];
             kc_v8bf ab[BF ? KS : 1];
             kc_v8bf al[SP ? KS : 1];
-            if (!BF) {
-                const float* cs = (const float*)s_c + (uint64_t)(ct + col) * DP;
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks) af[BF ? 0 : ks] = cs[ks * 4 + grp];
-            } else {
-                const uint16_t* cs = (const uint16_t*)s_c + (uint64_t)(ct + col) * DP;
+            for (int ks = 0; ks < (BF ? 1 : KS); ++ks) af[ks] = naf[ks];
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks)
-                    ab[BF ? ks : 0] = *(const kc_v8bf*)(cs + ks * 32 + grp * 8);
-                if (SP) {
-                    const uint16_t* cl = s_cl + (uint64_t)(ct + col) * DP;
+            for (int ks = 0; ks < (BF ? KS : 1); ++ks) ab[ks] = nab[ks];
 #pragma unroll
-                    for (int ks = 0; ks < KS; ++ks)
-                        al[SP ? ks : 0] = *(const kc_v8bf*)(cl + ks * 32 + grp * 8);
-                }
-            }
-            const float4 nc4 = *(const float4*)(s_norm + ct + grp * 4);
+            for (int ks = 0; ks < (SP ? KS : 1); ++ks) al[ks] = nal[ks];
+            const float4 nc4 = nnc;
+            if (ct + 16 < cn) load_a(ct + 16);
             float4 nl4 = make_float4(0.f, 0.f, 0.f, 0.f), cb4 = nl4, ce4 = nl4;
             if (LAB) {
                 nl4 = *(const float4*)(s_cnl + ct + grp * 4);
@@ -301,6 +337,7 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
 #pragma unroll
             for (int pt = 0; pt < KC_MD_PT; ++pt) {
                 kc_v4f acc = {0.f, 0.f, 0.f, 0.f};
+                if (!LAB) acc = kc_v4f{nc4.x, nc4.y, nc4.z, nc4.w};   // -|c|^2/2
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
                     if (!BF) {
@@ -336,12 +373,8 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
                     pair(acc[1], nc4.y, nl4.y, cb4.y, ce4.y, ib + 1);
                     pair(acc[2], nc4.z, nl4.z, cb4.z, ce4.z, ib + 2);
                     pair(acc[3], nc4.w, nl4.w, cb4.w, ce4.w, ib + 3);
-                } else {
-                    float v = fminf(__builtin_fmaf(-2.f, acc[0], nc4.x),
-                                    __builtin_fmaf(-2.f, acc[1], nc4.y));
-                    v = fminf(v, fminf(__builtin_fmaf(-2.f, acc[2], nc4.z),
-                                       __builtin_fmaf(-2.f, acc[3], nc4.w)));
-                    best[pt].m1 = fminf(best[pt].m1, v);
+                } else {   // m1 holds the largest -v/2 here
+                    best[pt].m1 = kc_max3(kc_max3(best[pt].m1, acc[0], acc[1]), acc[2], acc[3]);
                 }
             }
         }
@@ -352,9 +385,10 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
             for (int pt = 0; pt < KC_MD_PT; ++pt) {
                 const float sb = ap[pt] + bc;
                 const float e = gm * sb * sb * (1.f + 1e-6f);
-                wt[pt] = fminf(wt[pt], best[pt].m1 - e);
-                ut[pt] = fminf(ut[pt], best[pt].m1 + e);
-                best[pt].m1 = __builtin_inff();
+                const float m1 = -2.f * best[pt].m1;   // the chunk's smallest v
+                wt[pt] = fminf(wt[pt], m1 - e);
+                ut[pt] = fminf(ut[pt], m1 + e);
+                best[pt].m1 = -__builtin_inff();
             }
         }
     }
@@ -371,8 +405,8 @@ __global__ __launch_bounds__(KC_MD_WAVES * 64) void k_mindist_mfma(
             b.l2 = fminf(wt[pt], __shfl_xor(wt[pt], 16, 64));
             b.l2 = fminf(b.l2, __shfl_xor(b.l2, 32, 64));
         } else {
-            b.m1 = fminf(b.m1, __shfl_xor(b.m1, 16, 64));
-            b.m1 = fminf(b.m1, __shfl_xor(b.m1, 32, 64));
+            b.m1 = fmaxf(b.m1, __shfl_xor(b.m1, 16, 64));
+            b.m1 = -2.f * fmaxf(b.m1, __shfl_xor(b.m1, 32, 64));
         }
         const uint64_t p = p0 + pt * 16 + col;
         if (grp == 0 && p < n) {
@@ -831,7 +865,7 @@ int kc_mindist_dpad(int d, bool bf)
 // Largest center chunk (multiple of 16) whose LDS copy fits in 64 KiB.
 static uint32_t kc_mindist_chunk(int d, int mode, uint32_t kpad)
 {
-    const uint32_t dp = (uint32_t)kc_mindist_dpad(d, mode != KC_MD_F32);
+    const uint32_t dp = (uint32_t)kc_md_pitch(mode, kc_mindist_dpad(d, mode != KC_MD_F32));
     const uint32_t per = dp * (mode == KC_MD_BF16 ? 2 : 4) + (mode == KC_MD_BF16 ? 16 : 12);
     uint32_t c = (64u * 1024u / per) & ~15u;
     if (c < 16) c = 16;
@@ -839,25 +873,32 @@ static uint32_t kc_mindist_chunk(int d, int mode, uint32_t kpad)
 }
 
 void kc_mindist(const float* X, const uint16_t* Xb, const float* ex, int64_t ld, uint32_t n,
-                int d, const KcCenters& C, const KcMinOut& O, bool lab, hipStream_t s)
+                int d, const KcCenters& C, const KcMinOut& O, bool lab, hipStream_t s, int waves)
 {
+    if (waves != 8) waves = 4;
     const int mode = Xb ? KC_MD_BF16 : C.Cbl ? KC_MD_SPLIT : KC_MD_F32;
     const bool bf = mode != KC_MD_F32;
     const int ks = kc_mindist_ksteps(d, bf);
     const uint32_t chunk = kc_mindist_chunk(d, mode, C.kpad);
-    const int dp = kc_mindist_dpad(d, bf);
+    const int dp = kc_md_pitch(mode, kc_mindist_dpad(d, bf));
     const size_t smem = (size_t)chunk * (mode == KC_MD_BF16 ? 16 : 12) +
                         (size_t)chunk * dp * (mode == KC_MD_BF16 ? 2 : 4);
-    const uint32_t per_block = KC_MD_WAVES * 16 * kc_md_pt(mode, ks);
-    const dim3 grid((n + per_block - 1) / per_block), block(KC_MD_WAVES * 64);
+    const uint32_t per_block = (uint32_t)waves * 16 * kc_md_pt(mode, ks);
+    const dim3 grid((n + per_block - 1) / per_block), block(waves * 64);
     const float gm = (float)kc_md_gamma(d, mode == KC_MD_SPLIT);
-#define KC_LAUNCH(M, K)                                                                 \
-    if (lab)                                                                            \
-        hipLaunchKernelGGL((k_mindist_mfma<M, K, true>), grid, block, smem, s, X, Xb, ex, \
-                           ld, n, d, gm, C, chunk, O);                                  \
-    else                                                                                \
-        hipLaunchKernelGGL((k_mindist_mfma<M, K, false>), grid, block, smem, s, X, Xb,   \
+#define KC_LAUNCH_W(M, K, WW)                                                              \
+    if (lab)                                                                               \
+        hipLaunchKernelGGL((k_mindist_mfma<M, K, true, WW>), grid, block, smem, s, X, Xb, ex, \
+                           ld, n, d, gm, C, chunk, O);                                     \
+    else                                                                                   \
+        hipLaunchKernelGGL((k_mindist_mfma<M, K, false, WW>), grid, block, smem, s, X, Xb,  \
                            ex, ld, n, d, gm, C, chunk, O);
+#define KC_LAUNCH(M, K)         \
+    if (waves == 8) {           \
+        KC_LAUNCH_W(M, K, 8)    \
+    } else {                    \
+        KC_LAUNCH_W(M, K, 4)    \
+    }
     if (mode == KC_MD_F32) {
         switch (ks) {
 #define KC_CASE(K) \
@@ -884,6 +925,7 @@ void kc_mindist(const float* X, const uint16_t* Xb, const float* ex, int64_t ld,
         }
     }
 #undef KC_LAUNCH
+#undef KC_LAUNCH_W
 }
 
 void kc_stage_centers(const float* X, const uint16_t* Xb, int64_t ld, int d, uint32_t n,

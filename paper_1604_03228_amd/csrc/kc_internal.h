@@ -252,9 +252,11 @@ __device__ inline KcMdBounds kc_md_bounds(const KcMinOut& O, uint32_t p,
 int kc_mindist_ksteps(int d, bool bf);
 int kc_mindist_dpad(int d, bool bf);
 // One MFMA pass of every point against the staged centers (lab: labels
-// pass); ex: the points' BF16 rounding radii (BF16 passes).
+// pass); ex: the points' BF16 rounding radii (BF16 passes); waves: 4 or 8
+// waves per block (the results do not depend on it).
 void kc_mindist(const float* X, const uint16_t* Xb, const float* ex, int64_t ld, uint32_t n,
-                int d, const KcCenters& C, const KcMinOut& O, bool lab, hipStream_t s);
+                int d, const KcCenters& C, const KcMinOut& O, bool lab, hipStream_t s,
+                int waves = 4);
 void kc_stage_centers(const float* X, const uint16_t* Xb, int64_t ld, int d, uint32_t n,
                       const int64_t* idx, const uint32_t* idx32, uint32_t k,
                       const int64_t* k_dev, const KcCenters& C, uint32_t* status, hipStream_t s);

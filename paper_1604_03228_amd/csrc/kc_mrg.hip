@@ -240,12 +240,20 @@ int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, ui
         h->span_end("assign_direct", ev, 1, s);
         return rc;
     }
-    hipEvent_t ev = h->span_begin(s);
-    rc = h->run_graph(key + ":mfma", s, [&](hipStream_t st) {
-        kc_mindist(pts->f32, bf ? pts->bf16 : nullptr, ex, pts->ld, n, d, C, O,
-                   labels != nullptr, st);
+    // the MFMA pass with 4 or 8 waves per block, a measured choice per shape
+    const bool feas[2] = {true, true};
+    char tkey[96];
+    snprintf(tkey, sizeof tkey, "assign/%d/%d/%d/%d/%d", d, (int)floor(2.0 * log2((double)n + 1)),
+             (int)floor(2.0 * log2((double)k + 1)), labels != nullptr, bf ? 1 : split ? 2 : 0);
+    rc = h->tune(tkey, 2, feas, s, [&](int var) {
+        hipEvent_t ev = h->span_begin(s);
+        const int r = h->run_graph(key + (var ? ":mfma8" : ":mfma"), s, [&](hipStream_t st) {
+            kc_mindist(pts->f32, bf ? pts->bf16 : nullptr, ex, pts->ld, n, d, C, O,
+                       labels != nullptr, st, var ? 8 : 4);
+        });
+        h->span_end("assign_mfma", ev, 1, s);
+        return r;
     });
-    h->span_end("assign_mfma", ev, 1, s);
     if (rc) return rc;
     return h->run_graph(key + ":finish", s, [&](hipStream_t st) {
         kc_assign_finish(n, d, pts->f32, pts->ld, C, k, k_dev, O, ex, labels, hi, list, nlist,
