@@ -267,10 +267,23 @@ def bench_batch(kc, torch, steps):
         e1.record(st)
         st.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    # the same batch planned once (kcenter_batch_plan) and run repeatedly
+    plan = kc.BatchPlan(probs, handle=h)
+    with torch.cuda.stream(st):
+        for _ in range(2):
+            plan.run()
+        st.synchronize()
+        e0.record(st)
+        for _ in range(steps):
+            plan.run()
+        e1.record(st)
+        st.synchronize()
+    plan_ms = e0.elapsed_time(e1) / steps
+    plan.close()
     status = h.device_status()
     h.close()
     algos = [i["algo"] for i in insts]
-    return {"workload": "batch256_unbalanced_gon_mrg_eim", "ms": ms,
+    return {"workload": "batch256_unbalanced_gon_mrg_eim", "ms": ms, "plan_run_ms": plan_ms,
             "instances": len(insts), "gon": algos.count("gon"),
             "mrg": algos.count("mrg"), "eim": algos.count("eim"),
             "points": int(sum(i["n"] for i in insts)),

@@ -345,6 +345,37 @@ typedef struct {
  */
 int kcenter_batch(kc_handle* h, const kc_problem* probs, int32_t count, void* stream);
 
+/*
+ * A batch planned once and run many times (the same problems; the points'
+ * values may change between runs, their arrays, sizes and the other fields
+ * may not).
+ *
+ * kcenter_batch_plan -- check the problems as kcenter_batch does, copy them
+ * (MRG offsets included) and decide their grouping.  The plan owns a private
+ * workspace on the handle's device: its tables, buffers and captured graphs
+ * are never reallocated or evicted by other calls.  No GPU work; *plan is
+ * NULL on error.  KC_EINVAL / KC_ENOMEM / KC_EHIP.
+ *
+ * kcenter_batch_run -- run the plan on `stream`: the first run builds and
+ * uploads every group's launch plan and captures the graphs of the streamed
+ * steps and of the finishing passes; later runs only launch (cached graphs;
+ * the register-resident engine's cooperative launches are issued directly,
+ * since a graph carries no co-residency guarantee).  EIM and BF16 problems
+ * run through their single-problem paths on the plan's workspace
+ * (kcenter_eim synchronises the stream once per iteration).  The plan's
+ * device status is folded into `h`'s (see kc_device_status).  Outputs, as
+ * for kcenter_batch, land in the arrays the problems name.  Runs of one plan
+ * must not overlap.
+ *
+ * kcenter_batch_free -- synchronise the device and release the plan (NULL:
+ * no-op).
+ */
+typedef struct kc_batch_plan kc_batch_plan;
+int kcenter_batch_plan(kc_handle* h, const kc_problem* probs, int32_t count,
+                       kc_batch_plan** plan);
+int kcenter_batch_run(kc_handle* h, kc_batch_plan* plan, void* stream);
+void kcenter_batch_free(kc_batch_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -62,7 +62,8 @@ EXPORTS = ["kc_create", "kc_destroy", "kc_strerror", "kc_last_error",
            "kcenter_gonzalez", "kcenter_gonzalez_noalloc",
            "kcenter_gonzalez_resume",
            "kcenter_mrg", "kcenter_mrg_rounds", "kcenter_assign", "kcenter_eim",
-           "kcenter_batch"]
+           "kcenter_batch", "kcenter_batch_plan", "kcenter_batch_run",
+           "kcenter_batch_free"]
 
 _lib = None
 
@@ -108,13 +109,18 @@ def load_library(path=LIB_PATH):
                               ctypes.POINTER(_i64), _p,
                               ctypes.POINTER(_i32), _p]
     L.kcenter_batch.argtypes = [_p, _p, _i32, _p]
+    L.kcenter_batch_plan.argtypes = [_p, _p, _i32, ctypes.POINTER(_p)]
+    L.kcenter_batch_run.argtypes = [_p, _p, _p]
+    L.kcenter_batch_free.argtypes = [_p]
+    L.kcenter_batch_free.restype = None
     for name in ("kc_create", "kc_set_option", "kc_device_status",
                  "kc_timing_read", "kc_counter_read", "kc_tune_report",
                  "kcenter_gonzalez", "kcenter_gonzalez_noalloc",
                  "kcenter_gonzalez_resume",
                  "kcenter_mrg", "kcenter_mrg_rounds",
                  "kcenter_assign",
-                 "kcenter_eim", "kcenter_batch"):
+                 "kcenter_eim", "kcenter_batch", "kcenter_batch_plan",
+                 "kcenter_batch_run"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -409,13 +415,10 @@ def eim(X, k, eps, phi, seed, max_iters=64, bf16=None, want_sample=True,
     return centers, nc, radius, sample, recs
 
 
-def batch(problems, handle=None):
-    """Solve independent problems.  Each entry is a dict with X (CUDA
-    FP32), algo ('gon' | 'mrg' | 'eim'), k, and first / offsets / eps,
-    phi, seed as the algorithm needs.  Returns a list of (centers,
-    n_centers, radius) CUDA tensors."""
+def _problem_array(problems):
+    """The kc_problem array of a list of problem dicts, the output tensors
+    and the host arrays the array points into."""
     import numpy as np
-    h = handle or default_handle()
     arr = (KcProblem * len(problems))()
     keep = []
     outs = []
@@ -443,6 +446,50 @@ def batch(problems, handle=None):
         q.centers = c.data_ptr()
         q.n_centers = nc.data_ptr()
         q.radius = r.data_ptr()
+    return arr, outs, keep
+
+
+def batch(problems, handle=None):
+    """Solve independent problems.  Each entry is a dict with X (CUDA
+    FP32), algo ('gon' | 'mrg' | 'eim'), k, and first / offsets / eps,
+    phi, seed as the algorithm needs.  Returns a list of (centers,
+    n_centers, radius) CUDA tensors."""
+    h = handle or default_handle()
+    arr, outs, keep = _problem_array(problems)
     h._check(load_library().kcenter_batch(h._h, ctypes.cast(arr, _p),
                                           len(problems), _stream()))
     return outs
+
+
+class BatchPlan:
+    """A batch planned once (kcenter_batch_plan) and run many times
+    (kcenter_batch_run on the current stream).  `outs` holds the (centers,
+    n_centers, radius) tensors every run writes; the problems' point tensors
+    must stay alive and unchanged in shape."""
+
+    def __init__(self, problems, handle=None):
+        self.handle = handle or default_handle()
+        arr, self.outs, _ = _problem_array(problems)
+        self._points = [pr["X"] for pr in problems]
+        pl = _p()
+        self.handle._check(load_library().kcenter_batch_plan(
+            self.handle._h, ctypes.cast(arr, _p), len(problems),
+            ctypes.byref(pl)))
+        self._plan = pl
+        _live.add(self)
+
+    def run(self):
+        self.handle._check(load_library().kcenter_batch_run(
+            self.handle._h, self._plan, _stream()))
+        return self.outs
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            pl, self._plan = self._plan, None
+            load_library().kcenter_batch_free(pl)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -175,7 +175,7 @@ int kc_handle::run_graph(const std::string& key, hipStream_t stream,
     }
     auto it = graphs.find(key);
     if (it == graphs.end()) {
-        if (graphs.size() >= 32) clear_graphs();
+        if (graph_cap && graphs.size() >= graph_cap) clear_graphs();
         hipGraph_t g = nullptr;
         hipGraphExec_t ex = nullptr;
         hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);

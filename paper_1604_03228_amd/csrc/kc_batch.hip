@@ -135,12 +135,50 @@ struct SegTag {
     int part;   // partition (MRG) or -1 (GON)
 };
 
-static int run_group(kc_handle* h, const kc_problem* probs, const std::vector<int>& ids, int d,
-                     const char* tag, hipStream_t s)
+// One group's prepared launches: the plans, tables and workspace of its
+// stages, built by group_prepare and run (any number of times, while the
+// problems' sizes stay those it was built for) by group_execute.
+struct KcBatchGroup {
+    int d = 0;
+    std::string P, key;
+    std::vector<int> ids;
+    // stage 1
+    std::vector<KcGonJob> sj;
+    KcGonRun R;
+    KcGonHost H;
+    const int64_t* rb = nullptr;
+    int64_t* cent = nullptr;
+    int64_t* nch = nullptr;
+    double* rad = nullptr;
+    std::vector<KcBatchOut> outs;
+    const KcBatchOut* outs_d = nullptr;
+    // stage 2 (MRG problems)
+    std::vector<KcUnionJob> uj;
+    std::vector<int32_t> blk_job, blk_part;
+    std::vector<int> o2, mrg_ids;
+    std::vector<KcGonJob> sj2;
+    KcGonRun R2;
+    KcGonHost H2;
+    int64_t* uni = nullptr;
+    int64_t* nuni = nullptr;
+    int64_t* cent2 = nullptr;
+    int64_t* nch2 = nullptr;
+    const KcUnionJob* uj_d = nullptr;
+    const int32_t* bj_d = nullptr;
+    const int32_t* bp_d = nullptr;
+    const KcBatchOut* outs2_d = nullptr;
+    uint64_t uh = 0;
+};
+
+static int group_prepare(kc_handle* h, const kc_problem* probs, const std::vector<int>& ids, int d,
+                         const char* tag, hipStream_t s, KcBatchGroup& G)
 {
     char pre[32];
     snprintf(pre, sizeof pre, "b%d%s.", d, tag);
-    const std::string P(pre);
+    G.d = d;
+    G.P = pre;
+    G.ids = ids;
+    const std::string& P = G.P;
 
     // ---- stage 1: one run over all Gonzalez problems and MRG partitions
     std::vector<KcGonJob> jobs;
@@ -178,39 +216,40 @@ static int run_group(kc_handle* h, const kc_problem* probs, const std::vector<in
     std::vector<int> ord(jobs.size());
     std::iota(ord.begin(), ord.end(), 0);
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return jobs[a].k > jobs[b].k; });
-    std::vector<KcGonJob> sj;
     std::vector<SegTag> st;
     std::vector<int64_t> sr;
     for (int q : ord) {
-        sj.push_back(jobs[q]);
+        G.sj.push_back(jobs[q]);
         st.push_back(tags[q]);
         sr.push_back(rbase[q]);
     }
-    KcGonRun R;
-    KcGonHost H;
-    int rc = kc_plan_gon(h, P + "1.", d, 1024, sj, R, H, s);
+    int rc = kc_plan_gon(h, P + "1.", d, 1024, G.sj, G.R, G.H, s);
     if (rc) return rc;
-    const int nseg = (int)sj.size();
-    const int64_t* rb = (const int64_t*)h->upload(P + "1.rb", sr.data(), 8 * sr.size(), s);
-    int64_t* cent = (int64_t*)h->ws(P + "1.cent", 8 * std::max<uint64_t>(R.keysum, 1));
-    int64_t* nch = (int64_t*)h->ws(P + "1.nch", 8 * (size_t)nseg);
-    double* rad = (double*)h->ws(P + "1.rad", 8 * (size_t)nseg);
-    if (!rb || !cent || !nch || !rad) return h->fail(KC_ENOMEM, "workspace allocation failed");
+    const int nseg = (int)G.sj.size();
+    G.rb = (const int64_t*)h->upload(P + "1.rb", sr.data(), 8 * sr.size(), s);
+    G.cent = (int64_t*)h->ws(P + "1.cent", 8 * std::max<uint64_t>(G.R.keysum, 1));
+    G.nch = (int64_t*)h->ws(P + "1.nch", 8 * (size_t)nseg);
+    G.rad = (double*)h->ws(P + "1.rad", 8 * (size_t)nseg);
+    if (!G.rb || !G.cent || !G.nch || !G.rad)
+        return h->fail(KC_ENOMEM, "workspace allocation failed");
 
     // outputs of the Gonzalez problems; layout of the MRG problems
-    std::vector<KcBatchOut> outs;
     std::map<int, int> first_seg;   // MRG problem -> its first segment
     for (int q = 0; q < nseg; ++q) {
         const SegTag& t = st[q];
         const kc_problem& p = probs[t.prob];
         if (t.part < 0)
-            outs.push_back({(int64_t)H.segs[q].keyoff, p.k, q, p.centers, p.n_centers, p.radius});
+            G.outs.push_back(
+                {(int64_t)G.H.segs[q].keyoff, p.k, q, p.centers, p.n_centers, p.radius});
         else if (t.part == 0)
             first_seg[t.prob] = q;
     }
-    const KcBatchOut* outs_d = outs.empty() ? nullptr
-        : (const KcBatchOut*)h->upload(P + "1.outs", outs.data(), sizeof(KcBatchOut) * outs.size(), s);
-    std::string key = P + "run1";
+    if (!G.outs.empty()) {
+        G.outs_d = (const KcBatchOut*)h->upload(P + "1.outs", G.outs.data(),
+                                                sizeof(KcBatchOut) * G.outs.size(), s);
+        if (!G.outs_d) return h->fail(KC_ENOMEM, "workspace allocation failed");
+    }
+    G.key = P + "run1";
     // every problem's arrays, sizes and algorithm (the graphs embed their
     // pointers, strides and grids; the partition offsets enter through the
     // plans' signatures)
@@ -221,38 +260,28 @@ static int run_group(kc_handle* h, const kc_problem* probs, const std::vector<in
                  (long long)p.pts.n, (long long)p.pts.ld, (long long)p.k, p.algo,
                  (long long)p.first, p.m, (void*)p.centers, (void*)p.n_centers,
                  (void*)p.radius);
-        key += b;
+        G.key += b;
     }
-    rc = kc_run_gon(h, key, R, H, sj, "batch_gon", s, [&](hipStream_t sst) {
-        kc_gon_finish(R, cent, nch, nullptr, rad, rb, nullptr, sst);
-        if (!outs.empty())
-            hipLaunchKernelGGL(k_batch_out, dim3((unsigned)outs.size()), dim3(256), 0, sst, outs_d,
-                               (int)outs.size(), cent, nch, rad);
-    });
-    if (rc) return rc;
     if (first_seg.empty()) return KC_OK;
 
     // ---- stage 2: MRG second rounds as the segments of one run
-    std::vector<KcUnionJob> uj;
-    std::vector<int32_t> blk_job, blk_part;
     std::vector<KcGonJob> j2;
-    std::vector<int> mrg_ids;
     int64_t uoff = 0;
     for (auto& kv : first_seg) {
         const kc_problem& p = probs[kv.first];
         const int64_t cap = std::min<int64_t>((int64_t)p.m * p.k, p.pts.n);
         KcUnionJob J;
-        J.keyoff = H.segs[kv.second].keyoff;
+        J.keyoff = G.H.segs[kv.second].keyoff;
         J.seg0 = kv.second;
         J.m = p.m;
         J.k = p.k;
         J.uoff = uoff;
         J.seg2 = 0;   // set after the round-2 order is known
         for (int q = 0; q < p.m; ++q) {
-            blk_job.push_back((int32_t)uj.size());
-            blk_part.push_back(q);
+            G.blk_job.push_back((int32_t)G.uj.size());
+            G.blk_part.push_back(q);
         }
-        uj.push_back(J);
+        G.uj.push_back(J);
         KcGonJob g;
         g.X = nullptr;   // gathered
         g.ld = p.pts.ld;
@@ -261,64 +290,76 @@ static int run_group(kc_handle* h, const kc_problem* probs, const std::vector<in
         g.first = 0;
         g.k = (uint32_t)p.k;
         j2.push_back(g);
-        mrg_ids.push_back(kv.first);
+        G.mrg_ids.push_back(kv.first);
         uoff += cap;
     }
-    std::vector<int> o2(j2.size());
-    std::iota(o2.begin(), o2.end(), 0);
-    std::stable_sort(o2.begin(), o2.end(), [&](int a, int b) { return j2[a].k > j2[b].k; });
-    std::vector<KcGonJob> sj2;
-    for (int q = 0; q < (int)o2.size(); ++q) {
-        sj2.push_back(j2[o2[q]]);
-        uj[o2[q]].seg2 = q;
+    G.o2.resize(j2.size());
+    std::iota(G.o2.begin(), G.o2.end(), 0);
+    std::stable_sort(G.o2.begin(), G.o2.end(), [&](int a, int b) { return j2[a].k > j2[b].k; });
+    for (int q = 0; q < (int)G.o2.size(); ++q) {
+        G.sj2.push_back(j2[G.o2[q]]);
+        G.uj[G.o2[q]].seg2 = q;
     }
-    KcGonRun R2;
-    KcGonHost H2;
-    rc = kc_plan_gon(h, P + "2.", d, 1024, sj2, R2, H2, s);
+    rc = kc_plan_gon(h, P + "2.", d, 1024, G.sj2, G.R2, G.H2, s);
     if (rc) return rc;
-    const int nu = (int)uj.size();
-    int64_t* uni = (int64_t*)h->ws(P + "2.uni", 8 * (size_t)std::max<int64_t>(uoff, 1));
-    int64_t* nuni = (int64_t*)h->ws(P + "2.nu", 8 * (size_t)nu);
-    int64_t* cent2 = (int64_t*)h->ws(P + "2.cent", 8 * std::max<uint64_t>(R2.keysum, 1));
-    int64_t* nch2 = (int64_t*)h->ws(P + "2.nch", 8 * (size_t)nu);
-    const KcUnionJob* uj_d = (const KcUnionJob*)h->upload(P + "2.uj", uj.data(), sizeof(KcUnionJob) * nu, s);
-    const int32_t* bj_d = (const int32_t*)h->upload(P + "2.bj", blk_job.data(), 4 * blk_job.size(), s);
-    const int32_t* bp_d = (const int32_t*)h->upload(P + "2.bp", blk_part.data(), 4 * blk_part.size(), s);
-    if (!uni || !nuni || !cent2 || !nch2 || !uj_d || !bj_d || !bp_d)
+    const int nu = (int)G.uj.size();
+    G.uni = (int64_t*)h->ws(P + "2.uni", 8 * (size_t)std::max<int64_t>(uoff, 1));
+    G.nuni = (int64_t*)h->ws(P + "2.nu", 8 * (size_t)nu);
+    G.cent2 = (int64_t*)h->ws(P + "2.cent", 8 * std::max<uint64_t>(G.R2.keysum, 1));
+    G.nch2 = (int64_t*)h->ws(P + "2.nch", 8 * (size_t)nu);
+    G.uj_d = (const KcUnionJob*)h->upload(P + "2.uj", G.uj.data(), sizeof(KcUnionJob) * nu, s);
+    G.bj_d = (const int32_t*)h->upload(P + "2.bj", G.blk_job.data(), 4 * G.blk_job.size(), s);
+    G.bp_d = (const int32_t*)h->upload(P + "2.bp", G.blk_part.data(), 4 * G.blk_part.size(), s);
+    if (!G.uni || !G.nuni || !G.cent2 || !G.nch2 || !G.uj_d || !G.bj_d || !G.bp_d)
         return h->fail(KC_ENOMEM, "workspace allocation failed");
     std::vector<KcBatchOut> outs2;
     for (int q = 0; q < nu; ++q) {
-        const kc_problem& p = probs[mrg_ids[o2[q]]];
-        outs2.push_back({(int64_t)H2.segs[q].keyoff, p.k, q, p.centers, p.n_centers, nullptr});
+        const kc_problem& p = probs[G.mrg_ids[G.o2[q]]];
+        outs2.push_back({(int64_t)G.H2.segs[q].keyoff, p.k, q, p.centers, p.n_centers, nullptr});
     }
-    const KcBatchOut* outs2_d =
+    G.outs2_d =
         (const KcBatchOut*)h->upload(P + "2.outs", outs2.data(), sizeof(KcBatchOut) * nu, s);
-    if (!outs2_d) return h->fail(KC_ENOMEM, "workspace allocation failed");
+    if (!G.outs2_d) return h->fail(KC_ENOMEM, "workspace allocation failed");
     // the union graph's grids follow the union jobs and round 2's plan
-    uint64_t uh = kc_hash_vec(uj, R2.plan_hash);
-    uh = kc_hash_vec(blk_job, uh);
-    rc = h->run_graph(key + kc_hash_str(uh) + ":u", s, [&](hipStream_t sst) {
-        hipLaunchKernelGGL(k_batch_union, dim3((unsigned)blk_job.size()), dim3(256), 0, sst, uj_d,
-                           bj_d, bp_d, cent, nch, uni, nuni, R2.segs);
+    G.uh = kc_hash_vec(G.blk_job, kc_hash_vec(G.uj, G.R2.plan_hash));
+    return KC_OK;
+}
+
+static int group_execute(kc_handle* h, const kc_problem* probs, const KcBatchGroup& G,
+                         hipStream_t s)
+{
+    const int d = G.d;
+    const std::string& P = G.P;
+    int rc = kc_run_gon(h, G.key, G.R, G.H, G.sj, "batch_gon", s, [&](hipStream_t sst) {
+        kc_gon_finish(G.R, G.cent, G.nch, nullptr, G.rad, G.rb, nullptr, sst);
+        if (!G.outs.empty())
+            hipLaunchKernelGGL(k_batch_out, dim3((unsigned)G.outs.size()), dim3(256), 0, sst,
+                               G.outs_d, (int)G.outs.size(), G.cent, G.nch, G.rad);
+    });
+    if (rc || G.mrg_ids.empty()) return rc;
+    const int nu = (int)G.uj.size();
+    rc = h->run_graph(G.key + kc_hash_str(G.uh) + ":u", s, [&](hipStream_t sst) {
+        hipLaunchKernelGGL(k_batch_union, dim3((unsigned)G.blk_job.size()), dim3(256), 0, sst,
+                           G.uj_d, G.bj_d, G.bp_d, G.cent, G.nch, G.uni, G.nuni, G.R2.segs);
         for (int q = 0; q < nu; ++q) {
-            const KcUnionJob& J = uj[o2[q]];
-            const kc_problem& p = probs[mrg_ids[o2[q]]];
-            const uint32_t padded = kc_pad64(sj2[q].len);
+            const KcUnionJob& J = G.uj[G.o2[q]];
+            const kc_problem& p = probs[G.mrg_ids[G.o2[q]]];
+            const uint32_t padded = kc_pad64(G.sj2[q].len);
             hipLaunchKernelGGL(k_batch_gather, dim3((padded + 255) / 256), dim3(256), 0, sst,
-                               p.pts.f32, p.pts.ld, d, uni, J.uoff, nuni + o2[q], padded,
-                               (float*)R2.xs, R2.stride, H2.segs[q].base);
+                               p.pts.f32, p.pts.ld, d, G.uni, J.uoff, G.nuni + G.o2[q], padded,
+                               (float*)G.R2.xs, G.R2.stride, G.H2.segs[q].base);
         }
     });
     if (rc) return rc;
-    rc = kc_run_gon(h, key + ":r2", R2, H2, sj2, "batch_gon", s, [&](hipStream_t sst) {
-        kc_gon_finish(R2, cent2, nch2, nullptr, nullptr, nullptr, uni, sst);
-        hipLaunchKernelGGL(k_batch_out, dim3((unsigned)nu), dim3(256), 0, sst, outs2_d, nu, cent2,
-                           nch2, (const double*)nullptr);
+    rc = kc_run_gon(h, G.key + ":r2", G.R2, G.H2, G.sj2, "batch_gon", s, [&](hipStream_t sst) {
+        kc_gon_finish(G.R2, G.cent2, G.nch2, nullptr, nullptr, nullptr, G.uni, sst);
+        hipLaunchKernelGGL(k_batch_out, dim3((unsigned)nu), dim3(256), 0, sst, G.outs2_d, nu,
+                           G.cent2, G.nch2, (const double*)nullptr);
     });
     if (rc) return rc;
 
     // ---- stage 3: covering radius of every MRG problem (FP32 MFMA)
-    for (int i : mrg_ids) {
+    for (int i : G.mrg_ids) {
         const kc_problem& p = probs[i];
         kc_points p32 = p.pts;
         p32.prec = KC_FP32;
@@ -330,30 +371,28 @@ static int run_group(kc_handle* h, const kc_problem* probs, const std::vector<in
     return KC_OK;
 }
 
-extern "C" int kcenter_batch(kc_handle* h, const kc_problem* probs, int32_t count, void* stream)
+// The problems' grouping: per dimension, the FP32 Gonzalez and MRG problems
+// whose points (every partition, for MRG) fit a co-resident register-resident
+// grid ("r"), and the others ("s"), which stream -- one problem too large for
+// the register file then leaves the others on the resident engine; EIM
+// problems and BF16 problems run alone (`single`).
+struct KcBatchLayout {
+    std::vector<std::pair<int, std::vector<int>>> groups;   // (d, ids), tag r then s
+    std::vector<const char*> tags;
+    std::vector<int> single;
+};
+
+static void batch_layout(kc_handle* h, const kc_problem* probs, int count, KcBatchLayout& L)
 {
-    if (!h) return KC_EINVAL;
-    if (count < 0 || (count > 0 && !probs)) return h->fail(KC_EINVAL, "bad problem list");
-    for (int i = 0; i < count; ++i) {
-        int rc = check_problem(h, probs[i], i);
-        if (rc) return rc;
-    }
-    hipStream_t s = (hipStream_t)stream;
-    std::map<int, std::vector<int>> groups;
-    std::vector<int> others;
+    std::map<int, std::vector<int>> byd;
     for (int i = 0; i < count; ++i) {
         const kc_problem& p = probs[i];
-        const bool fp32 = p.pts.prec == KC_FP32;
-        if (p.algo != KC_ALGO_EIM && fp32)
-            groups[p.pts.d].push_back(i);
+        if (p.algo != KC_ALGO_EIM && p.pts.prec == KC_FP32)
+            byd[p.pts.d].push_back(i);
         else
-            others.push_back(i);
+            L.single.push_back(i);
     }
-    // Each dimension's problems in two runs: those whose points (every
-    // partition, for MRG) fit a co-resident register-resident grid, and the
-    // others, which stream; one problem too large for the register file
-    // then leaves the others on the resident engine.
-    for (auto& g : groups) {
+    for (auto& g : byd) {
         const int d = g.first;
         std::vector<int> fit, other;
         for (int i : g.second) {
@@ -369,36 +408,162 @@ extern "C" int kcenter_batch(kc_handle* h, const kc_problem* probs, int32_t coun
             (ok ? fit : other).push_back(i);
         }
         if (!fit.empty()) {
-            int rc = run_group(h, probs, fit, d, "r", s);
-            if (rc) return rc;
+            L.groups.push_back({d, fit});
+            L.tags.push_back("r");
         }
         if (!other.empty()) {
-            int rc = run_group(h, probs, other, d, "s", s);
-            if (rc) return rc;
+            L.groups.push_back({d, other});
+            L.tags.push_back("s");
         }
     }
-    for (int i : others) {
-        const kc_problem& p = probs[i];
-        int rc;
-        if (p.algo == KC_ALGO_EIM) {
-            int64_t ns = 0;
-            int32_t ni = 0;
-            rc = kcenter_eim(h, &p.pts, p.k, &p.eim, p.centers, p.n_centers, p.radius, nullptr, &ns,
-                             nullptr, &ni, s);
-        } else if (p.algo == KC_ALGO_GON) {
-            double* tr = (double*)h->ws("bo.trace", 8 * (size_t)p.k);
-            if (!tr) return h->fail(KC_ENOMEM, "workspace allocation failed");
-            rc = kcenter_gonzalez(h, &p.pts, p.k, p.first, p.centers, tr, p.n_centers, s);
-            if (!rc) {
-                // radius: the last chosen entry of the trace, via the assignment
-                rc = kc_assign_run(h, &p.pts, p.centers, (uint32_t)p.k, p.n_centers, nullptr,
-                                   p.radius, s, "bo.a.");
-            }
-        } else {
-            rc = kcenter_mrg(h, &p.pts, p.offsets, p.m, p.k, p.centers, p.n_centers, p.radius,
-                             nullptr, nullptr, nullptr, nullptr, nullptr, s);
+}
+
+static int run_single(kc_handle* h, const kc_problem& p, int i, hipStream_t s)
+{
+    int rc;
+    if (p.algo == KC_ALGO_EIM) {
+        int64_t ns = 0;
+        int32_t ni = 0;
+        rc = kcenter_eim(h, &p.pts, p.k, &p.eim, p.centers, p.n_centers, p.radius, nullptr, &ns,
+                         nullptr, &ni, s);
+    } else if (p.algo == KC_ALGO_GON) {
+        double* tr = (double*)h->ws("bo.trace", 8 * (size_t)p.k);
+        if (!tr) return h->fail(KC_ENOMEM, "workspace allocation failed");
+        rc = kcenter_gonzalez(h, &p.pts, p.k, p.first, p.centers, tr, p.n_centers, s);
+        if (!rc) {
+            // radius: the last chosen entry of the trace, via the assignment
+            rc = kc_assign_run(h, &p.pts, p.centers, (uint32_t)p.k, p.n_centers, nullptr,
+                               p.radius, s, "bo.a.");
         }
-        if (rc) return h->fail(rc, "problem %d: %s", i, h->last_error.c_str());
+    } else {
+        rc = kcenter_mrg(h, &p.pts, p.offsets, p.m, p.k, p.centers, p.n_centers, p.radius,
+                         nullptr, nullptr, nullptr, nullptr, nullptr, s);
+    }
+    if (rc) return h->fail(rc, "problem %d: %s", i, h->last_error.c_str());
+    return KC_OK;
+}
+
+extern "C" int kcenter_batch(kc_handle* h, const kc_problem* probs, int32_t count, void* stream)
+{
+    if (!h) return KC_EINVAL;
+    if (count < 0 || (count > 0 && !probs)) return h->fail(KC_EINVAL, "bad problem list");
+    for (int i = 0; i < count; ++i) {
+        int rc = check_problem(h, probs[i], i);
+        if (rc) return rc;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    KcBatchLayout L;
+    batch_layout(h, probs, count, L);
+    for (size_t g = 0; g < L.groups.size(); ++g) {
+        KcBatchGroup G;
+        int rc = group_prepare(h, probs, L.groups[g].second, L.groups[g].first, L.tags[g], s, G);
+        if (!rc) rc = group_execute(h, probs, G, s);
+        if (rc) return rc;
+    }
+    for (int i : L.single) {
+        int rc = run_single(h, probs[i], i, s);
+        if (rc) return rc;
     }
     return KC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// a batch planned once and run many times
+
+struct kc_batch_plan {
+    kc_handle* sub = nullptr;             // private workspace, tables and graphs
+    std::vector<kc_problem> probs;        // the problems, offsets copied
+    std::vector<std::vector<int64_t>> offsets;
+    KcBatchLayout layout;
+    std::vector<KcBatchGroup> groups;     // prepared on the first run
+    bool prepared = false;
+};
+
+__global__ void k_status_fold(uint32_t* __restrict__ dst, uint32_t* __restrict__ src)
+{
+    if (threadIdx.x == 0) {
+        const uint32_t v = *src;
+        if (v) {
+            atomicOr(dst, v);
+            *src = 0u;
+        }
+    }
+}
+
+extern "C" int kcenter_batch_plan(kc_handle* h, const kc_problem* probs, int32_t count,
+                                  kc_batch_plan** plan)
+{
+    if (!h) return KC_EINVAL;
+    if (!plan) return h->fail(KC_EINVAL, "plan NULL");
+    *plan = nullptr;
+    if (count < 0 || (count > 0 && !probs)) return h->fail(KC_EINVAL, "bad problem list");
+    for (int i = 0; i < count; ++i) {
+        int rc = check_problem(h, probs[i], i);
+        if (rc) return rc;
+    }
+    kc_batch_plan* B = new (std::nothrow) kc_batch_plan();
+    if (!B) return h->fail(KC_ENOMEM, "plan allocation failed");
+    int rc = kc_create(&B->sub);
+    if (rc) {
+        delete B;
+        return h->fail(rc, "plan handle: %s", kc_strerror(rc));
+    }
+    kc_handle* S = B->sub;
+    S->use_graphs = h->use_graphs;
+    S->allow_resident = h->allow_resident;
+    S->mfma_split = h->mfma_split;
+    S->autotune = h->autotune;
+    S->tuned = h->tuned;
+    S->tune_ms = h->tune_ms;
+    S->spin_limit = h->spin_limit;
+    S->resident_cap = h->resident_cap;
+    S->graph_cap = 0;   // a plan keeps every graph it captures
+    B->probs.assign(probs, probs + count);
+    B->offsets.resize(count);
+    for (int i = 0; i < count; ++i)
+        if (probs[i].algo == KC_ALGO_MRG) {
+            B->offsets[i].assign(probs[i].offsets, probs[i].offsets + probs[i].m + 1);
+            B->probs[i].offsets = B->offsets[i].data();
+        }
+    batch_layout(S, B->probs.data(), count, B->layout);
+    *plan = B;
+    return KC_OK;
+}
+
+extern "C" int kcenter_batch_run(kc_handle* h, kc_batch_plan* plan, void* stream)
+{
+    if (!h) return KC_EINVAL;
+    if (!plan) return h->fail(KC_EINVAL, "plan NULL");
+    kc_handle* S = plan->sub;
+    hipStream_t s = (hipStream_t)stream;
+    const kc_problem* probs = plan->probs.data();
+    const KcBatchLayout& L = plan->layout;
+    int rc = KC_OK;
+    if (!plan->prepared) {
+        plan->groups.resize(L.groups.size());
+        for (size_t g = 0; g < L.groups.size() && !rc; ++g)
+            rc = group_prepare(S, probs, L.groups[g].second, L.groups[g].first, L.tags[g], s,
+                               plan->groups[g]);
+        if (rc) {
+            plan->groups.clear();
+            return h->fail(rc, "%s", S->last_error.c_str());
+        }
+        plan->prepared = true;
+    }
+    for (size_t g = 0; g < plan->groups.size() && !rc; ++g)
+        rc = group_execute(S, probs, plan->groups[g], s);
+    for (size_t q = 0; q < L.single.size() && !rc; ++q)
+        rc = run_single(S, probs[L.single[q]], L.single[q], s);
+    // the plan's device status joins the caller's handle
+    hipLaunchKernelGGL(k_status_fold, dim3(1), dim3(64), 0, s, h->status_word, S->status_word);
+    if (rc) return h->fail(rc, "%s", S->last_error.c_str());
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? KC_OK : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
+}
+
+extern "C" void kcenter_batch_free(kc_batch_plan* plan)
+{
+    if (!plan) return;
+    kc_destroy(plan->sub);   // synchronises the device first
+    delete plan;
 }

@@ -71,6 +71,7 @@ struct kc_handle {
     std::map<std::string, void*> shadow_ptr;
     std::map<std::string, Staging> staging;
     std::map<std::string, GraphEntry> graphs;
+    size_t graph_cap = 512;           // cached graphs before the cache is cleared (0: no limit)
     std::map<int, int> resident_cache;
     int resident_cap = 0;             // blocks per resident launch, 0: no cap
     bool timing = false;
