@@ -92,7 +92,10 @@ const char* kc_last_error(const kc_handle* h);
  * (default 1: the first call of a shape bucket -- dimension, and n, k or
  * sample size rounded to half powers of two -- times every feasible variant
  * of its engine once and the handle keeps the fastest; the variants give
- * identical results; a call made during stream capture never tunes).
+ * identical results; a call made during stream capture never tunes);
+ * "tune_force" (-1 default; v >= 0: every tuned operation runs its variant v
+ * where that is feasible, else its first feasible one -- a testing aid that
+ * reaches each variant; the variants are listed with kc_tune_report).
  * KC_EINVAL for an unknown name or a value out of range. */
 int kc_set_option(kc_handle* h, const char* name, int64_t value);
 
@@ -102,9 +105,12 @@ int kc_set_option(kc_handle* h, const char* name, int64_t value);
  * a = floor(2 log2 n), b = floor(2 log2 k); variants resident v0, resident
  * v1, streaming), "eim/d/a/b" (EIM distance pass, a and b of the candidate
  * and new-sample counts; variants direct VALU for d <= 8, FP32 MFMA, split
- * MFMA).  Writes at most `cap` bytes (NUL-terminated) to the host buffer
- * `buf` and the needed size to *need; with cap = 0 (buf may be NULL) it
- * only sets *need.  KC_EINVAL for a NULL handle or need, or when 0 < cap <
+ * MFMA with 4 and with 8 waves per block; an MFMA pass's undecided
+ * candidates are refined in canonical FP32 before FP64), "assign/d/a/b/l/m"
+ * (the assignment's MFMA pass, a and b of n and k, l = labels, m = input
+ * mode; variants 4 and 8 waves per block).  Writes at most `cap` bytes
+ * (NUL-terminated) to the host buffer `buf` and the needed size to *need;
+ * with cap = 0 (buf may be NULL) it only sets *need.  KC_EINVAL for a NULL handle or need, or when 0 < cap <
  * *need (nothing written). */
 int kc_tune_report(kc_handle* h, char* buf, int64_t cap, int64_t* need);
 
@@ -125,7 +131,10 @@ int kc_timing_read(kc_handle* h, const char* name, double* ms, int64_t* launches
 /* Work counters of the most recent BF16+rescore Gonzalez run on the handle
  * (synchronises the device): "bf16_listed" is the number of (point, step)
  * pairs listed by the stream as possible candidates, "bf16_rescored" the
- * number rescored exactly in FP32.  "eim_exact": candidates whose keep /
+ * number rescored exactly in FP32.  "eim_refined": candidates an MFMA
+ * distance pass of the most recent kcenter_eim call left undecided, which
+ * were then bounded in canonical FP32 (summed over its iterations).
+ * "eim_exact": candidates whose keep /
  * remove decision the most recent kcenter_eim call on the handle made in
  * exact FP64 (summed over its iterations; a batch counts its last EIM
  * problem).  "assign_rescored": points the most recent assignment on the

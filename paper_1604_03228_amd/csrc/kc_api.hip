@@ -204,6 +204,7 @@ int kc_handle::tune(const std::string& key, int nvar, const bool* feasible, hipS
             ++nfeas;
         }
     if (first < 0) return fail(KC_EUNSUPPORTED, "no feasible variant for %s", key.c_str());
+    if (tune_force >= 0) return run(tune_force < nvar && feasible[tune_force] ? tune_force : first);
     auto it = tuned.find(key);
     if (it != tuned.end() && feasible[it->second]) return run(it->second);
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -649,6 +650,11 @@ int kc_set_option(kc_handle* h, const char* name, int64_t value)
         h->autotune = value != 0;
         return KC_OK;
     }
+    if (!strcmp(name, "tune_force")) {
+        if (value < -1 || value > 63) return h->fail(KC_EINVAL, "tune_force range");
+        h->tune_force = (int)value;
+        return KC_OK;
+    }
     if (!strcmp(name, "timing")) {
         h->timing = value != 0;
         return KC_OK;
@@ -732,6 +738,9 @@ int kc_counter_read(kc_handle* h, const char* name, int64_t* value)
         src = h->last_bf16_nresc;
     } else if (!strcmp(name, "eim_exact")) {
         *value = h->eim_exact;
+        return KC_OK;
+    } else if (!strcmp(name, "eim_refined")) {
+        *value = h->eim_refined;
         return KC_OK;
     } else if (!strcmp(name, "assign_rescored")) {
         src = h->last_assign_nlist;   // one count

@@ -511,6 +511,94 @@ __global__ void k_eim_exact_finish(const uint32_t* __restrict__ cand,
     hi[x] = (float)b * (1.f + 1e-6f);
 }
 
+// Refinement of the candidates an MFMA pass left undecided, before any
+// FP64: the canonical FP32 d(x,S)^2 over all of S (relative error at most
+// g = gamma_{d+2}, as in the direct pass), laid out like the split exact
+// pass -- blocks of 64 candidates times slices of S, partial minima by an
+// atomic min on the bits (non-negative floats order as integers).
+template <int D>
+__global__ __launch_bounds__(256) void k_eim_refine_split(
+    const float* __restrict__ X, int64_t ld, int d_rt, const uint32_t* __restrict__ cand,
+    const uint32_t* __restrict__ unsure, uint32_t nu, const uint32_t* __restrict__ S,
+    uint32_t ns, uint32_t* __restrict__ rmin)
+{
+    const int d = D > 0 ? D : d_rt;
+    constexpr uint32_t LDSF = KC_EXT_LDS / sizeof(float);
+    __shared__ float sS[LDSF];
+    __shared__ float sB[4][64];
+    const uint32_t CH = LDSF / (uint32_t)d;   // samples per chunk
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t q0 = blockIdx.x * 64u;
+    if (q0 >= nu) return;
+    const uint32_t nq = min(64u, nu - q0);
+    const uint32_t per = (ns + gridDim.y - 1) / gridDim.y;
+    const uint32_t s0 = min(ns, blockIdx.y * per), s1 = min(ns, s0 + per);
+    const bool live = lane < nq;
+    const uint32_t x = live ? cand[unsure[q0 + lane]] : 0u;
+    const float* xp = X + (uint64_t)x * ld;
+    float xr[D > 0 ? D : 1];
+    if constexpr (D > 0) {
+#pragma unroll
+        for (int u = 0; u < D; ++u) xr[u] = live ? xp[u] : 0.f;
+    }
+    float best = __builtin_inff();
+    for (uint32_t i0 = s0; i0 < s1; i0 += CH) {
+        const uint32_t nsc = min(CH, s1 - i0);
+        __syncthreads();
+        kc_stage_samples(sS, X, ld, d, S + i0, nsc);
+        __syncthreads();
+        if (live) {
+            for (uint32_t r = wave; r < nsc; r += 4) {
+                const float* sr = sS + r * (uint32_t)d;
+                float a = 0.f;
+                if constexpr (D > 0) {
+#pragma unroll
+                    for (int u = 0; u < D; ++u) a = kc_d32_step(a, xr[u], sr[u]);
+                } else {
+                    for (int u = 0; u < d; ++u) a = kc_d32_step(a, xp[u], sr[u]);
+                }
+                best = fminf(best, a);
+            }
+        }
+    }
+    sB[wave][lane] = best;
+    __syncthreads();
+    if (threadIdx.x < nq) {
+        const float b = fminf(fminf(sB[0][lane], sB[1][lane]), fminf(sB[2][lane], sB[3][lane]));
+        atomicMin(&rmin[q0 + lane], __float_as_uint(b));
+    }
+}
+
+// The refined interval [m / (1 + g), m / (1 - g)] (widened as in the direct
+// pass) bounds d(x,S)^2 over all of S, so it replaces the MFMA one; keep /
+// remove where it decides, else the candidate joins the FP64 list.
+__global__ void k_eim_refine_finish(const uint32_t* __restrict__ cand,
+                                    const uint32_t* __restrict__ unsure, uint32_t nu,
+                                    const uint32_t* __restrict__ rmin, double g, int d,
+                                    const double* __restrict__ tau, uint8_t* __restrict__ keep,
+                                    float* __restrict__ lo, float* __restrict__ hi,
+                                    uint32_t* __restrict__ unsure2, uint32_t* __restrict__ n2)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nu) return;
+    const uint32_t j = unsure[q];
+    const uint32_t x = cand[j];
+    const double mv = (double)__uint_as_float(rmin[q]);
+    double l = mv / (1.0 + g) - 1e-37 * d;
+    if (l < 0.0) l = 0.0;
+    const double u = mv / (1.0 - g) + 1e-37 * d;
+    const float lf = (float)l * (1.f - 1e-6f), uf = (float)u * (1.f + 1e-6f);
+    lo[x] = lf;
+    hi[x] = uf;
+    const double t = *tau;
+    if ((double)lf > t) {
+        keep[j] = 1;
+    } else {
+        keep[j] = 0;
+        if (!((double)uf <= t)) unsure2[atomicAdd(n2, 1u)] = j;
+    }
+}
+
 __global__ void k_mark(const uint32_t* __restrict__ idx, uint32_t n, uint8_t* __restrict__ f)
 {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -596,7 +684,7 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
     float* hi = (float*)h->ws("e.hi", 4ull * n);
     double* dH = (double*)h->ws("e.dH", 8ull * n);
     double* tau = (double*)h->ws("e.tau", 16);
-    uint32_t* cnt = (uint32_t*)h->ws("e.cnt", 64);   // [0] dS [1] H [2] cand [3] R [4] unsure
+    uint32_t* cnt = (uint32_t*)h->ws("e.cnt", 64);   // [0] dS [1] H [2] cand [3] R [4] FP64 [5] refined-undecided
     uint32_t* unsure = (uint32_t*)h->ws("e.uns", 4ull * n);
     double* exm = (double*)h->ws("e.exm", 8ull * n);   // exact minima of the undecided
     KcCompact C;
@@ -612,6 +700,7 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
     if (!mu) return h->fail(KC_ENOMEM, "workspace allocation failed");
     if (d > KC_EIM_DIRECT_MAXD) kc_local_origin(X, ld, d, n, mu, s);
     h->eim_exact = 0;
+    h->eim_refined = 0;
     hipLaunchKernelGGL(k_iota, g1(n), dim3(256), 0, s, R, n);
     kc_fill_u32((uint32_t*)lo, 0x7F800000u, n, s);
     kc_fill_u32((uint32_t*)hi, 0x7F800000u, n, s);
@@ -659,7 +748,9 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
             // origin.  All decide exactly alike; the
             // autotuner measures them once per shape bucket (with the
             // intervals restored before each of its runs).
+            uint32_t refined_it = 0;
             auto pass = [&](int var) -> int {
+                refined_it = 0;
                 if (nds > 0 && nc > 0 && var == 0) {
                     const double u32 = 5.9604644775390625e-8, m = d + 2;
                     const double g = m * u32 / (1.0 - m * u32);
@@ -748,6 +839,45 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
                     uint32_t nu = 0;
                     int rc3 = kc_read_u32(h, cnt + 4, &nu, s);
                     if (rc3) return rc3;
+                    const uint32_t* uns = unsure;
+                    if (var > 0 && nu > 0 && (uint64_t)nu * ns >= (1ull << 22)) {
+                        // the MFMA pass's undecided: canonical FP32 first
+                        refined_it = nu;   // the last run's count stands
+                        uint32_t* rmin = (uint32_t*)h->ws("e.rmin", 4ull * nu);
+                        uint32_t* uns2 = (uint32_t*)h->ws("e.uns2", 4ull * nu);
+                        if (!rmin || !uns2) return h->fail(KC_ENOMEM, "workspace allocation failed");
+                        const uint32_t gx = (nu + 63) / 64;
+                        const uint32_t gy = std::max<uint32_t>(
+                            1, std::min<uint32_t>({(2048 + gx - 1) / gx, ns / 512, 65535u}));
+                        kc_fill_u32(rmin, 0x7F800000u, nu, s);   // +inf
+                        kc_fill_u32(cnt + 5, 0u, 1, s);
+                        switch (d) {
+#define KC_RFS_CASE(DD)                                                                        \
+    case DD:                                                                                   \
+        hipLaunchKernelGGL(k_eim_refine_split<DD>, dim3(gx, gy), dim3(256), 0, s, X, ld, d,     \
+                           cand, unsure, nu, S, ns, rmin);                                     \
+        break;
+                            KC_RFS_CASE(2)
+                            KC_RFS_CASE(3)
+                            KC_RFS_CASE(8)
+                            KC_RFS_CASE(10)
+                            KC_RFS_CASE(16)
+                            KC_RFS_CASE(32)
+#undef KC_RFS_CASE
+                        default:
+                            hipLaunchKernelGGL(k_eim_refine_split<0>, dim3(gx, gy), dim3(256), 0,
+                                               s, X, ld, d, cand, unsure, nu, S, ns, rmin);
+                        }
+                        const double u32 = 5.9604644775390625e-8, m = d + 2;
+                        hipLaunchKernelGGL(k_eim_refine_finish, g1(nu), dim3(256), 0, s, cand,
+                                           unsure, nu, rmin, m * u32 / (1.0 - m * u32), d, tau,
+                                           keep, lo, hi, uns2, cnt + 5);
+                        // the FP64 pass takes what is still undecided
+                        hipMemcpyAsync(cnt + 4, cnt + 5, 4, hipMemcpyDeviceToDevice, s);
+                        rc3 = kc_read_u32(h, cnt + 5, &nu, s);
+                        if (rc3) return rc3;
+                        uns = uns2;
+                    }
                     if (nu > 0) {
                         const uint32_t gx = (nu + 63) / 64;
                         const uint32_t gy = std::max<uint32_t>(
@@ -757,7 +887,7 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
 #define KC_EXS_CASE(DD)                                                                       \
     case DD:                                                                                  \
         hipLaunchKernelGGL(k_eim_exact_split_d<DD>, dim3(gx, gy), dim3(256), 0, s, X, ld, cand, \
-                           unsure, nu, S, ns, exm);                                           \
+                           uns, nu, S, ns, exm);                                              \
         break;
                             KC_EXS_CASE(10)
                             KC_EXS_CASE(16)
@@ -765,10 +895,10 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
 #undef KC_EXS_CASE
                         default:
                             hipLaunchKernelGGL(k_eim_exact_split, dim3(gx, gy), dim3(256), 0, s,
-                                               X, ld, d, cand, unsure, nu, S, ns, exm);
+                                               X, ld, d, cand, uns, nu, S, ns, exm);
                         }
                         hipLaunchKernelGGL(k_eim_exact_finish, g1(nu), dim3(256), 0, s, cand,
-                                           unsure, nu, exm, tau, keep, lo, hi);
+                                           uns, nu, exm, tau, keep, lo, hi);
                     }
                 } else {
                     hipLaunchKernelGGL(k_eim_exact, dim3(2048), dim3(256), 0, s, X, ld, d, cand,
@@ -801,6 +931,7 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
                 rc = pass(1);
             }
             if (rc) return rc;
+            h->eim_refined += refined_it;
             kc_compact(C, keep, cand, nc, R2, cnt + 3, s);
             std::swap(R, R2);
             uint32_t rc2[2];

@@ -60,6 +60,7 @@ struct kc_handle {
     bool allow_resident = true;
     bool mfma_split = true;           // FP32 distance passes on split BF16 MFMAs
     bool autotune = true;             // measured choice of engine variants
+    int tune_force = -1;              // >= 0: always that variant where feasible
     std::map<std::string, int> tuned;  // key -> chosen variant
     std::map<std::string, std::vector<float>> tune_ms;   // key -> measured ms per variant
     uint32_t spin_limit = 1u << 20;   // polls before a barrier wait gives up
@@ -87,6 +88,8 @@ struct kc_handle {
     uint32_t last_bf16_kmax = 0;
     // candidates decided by the exact FP64 pass in the most recent EIM call
     int64_t eim_exact = 0;
+    // candidates refined in canonical FP32 after an MFMA pass (same call)
+    int64_t eim_refined = 0;
     // list count (device) of the most recent assignment's FP64 rescoring
     const uint32_t* last_assign_nlist = nullptr;
 

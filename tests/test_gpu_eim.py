@@ -26,9 +26,10 @@ def kc():
     return kc
 
 
-def gpu_eim(kc, X, k, eps, phi, seed, max_iters=64, split=True):
+def gpu_eim(kc, X, k, eps, phi, seed, max_iters=64, split=True, force=-1):
     h = kc.Handle()
     h.set_option("mfma_split", int(split))
+    h.set_option("tune_force", force)
     Xd = torch.from_numpy(X).cuda()
     st = torch.cuda.Stream()
     st.wait_stream(torch.cuda.current_stream())
@@ -38,7 +39,7 @@ def gpu_eim(kc, X, k, eps, phi, seed, max_iters=64, split=True):
     st.synchronize()
     return dict(centers=c.cpu().numpy(), n_centers=int(nc.item()),
                 radius=float(r.item()), sample=smp.cpu().numpy(), iters=its,
-                exact=h.counter("eim_exact"))
+                exact=h.counter("eim_exact"), refined=h.counter("eim_refined"))
 
 
 def check(orc, X, k, eps, phi, seed, g):
@@ -106,7 +107,22 @@ def test_unbalanced_blobs(kc, orc, d, split):
     g = gpu_eim(kc, X, 20, 0.1, 4.0, 5 * 2**32 + 1, split=split)
     check(orc, X, 20, 0.1, 4.0, 5 * 2**32 + 1, g)
     if d > 8:
-        assert g["exact"] > 0
+        assert g["exact"] + g["refined"] > 0
+
+
+# Every variant of the distance pass (tune_force): 0 the direct canonical
+# FP32 pass (d <= 8; elsewhere the first feasible variant), 1 the FP32 MFMA,
+# 2 and 3 the split MFMA with 4 and 8 waves per block; the MFMA variants'
+# undecided candidates go through the canonical FP32 refinement, then FP64.
+# Samples, records and the final Gonzalez equal the oracle's in every one.
+@pytest.mark.parametrize("d", [2, 8, 32])
+@pytest.mark.parametrize("var", [0, 1, 2, 3])
+def test_forced_variants(kc, orc, d, var):
+    from paper_1604_03228_amd import workloads as W
+    X = W.points_gauss_mixture(60_000, d, 25, seed=91 + d, heavy=0.9)
+    g = gpu_eim(kc, X, 12, 0.1, 4.0, 3 * 2**32 + d, force=var)
+    check(orc, X, 12, 0.1, 4.0, 3 * 2**32 + d, g)
+    assert len(g["iters"]) >= 1
 
 
 def test_max_iters_reports_noconv(kc):
