@@ -282,13 +282,70 @@ def bench_batch(kc, torch, steps):
     plan.close()
     status = h.device_status()
     h.close()
+    eim_pass = bench_eim_pass(kc, torch, insts, probs)
     algos = [i["algo"] for i in insts]
     return {"workload": "batch256_unbalanced_gon_mrg_eim", "ms": ms, "plan_run_ms": plan_ms,
+            "eim_pass": eim_pass,
             "instances": len(insts), "gon": algos.count("gon"),
             "mrg": algos.count("mrg"), "eim": algos.count("eim"),
             "points": int(sum(i["n"] for i in insts)),
             "gon_mrg1_updates": upd,
             "gon_mrg1_updates_per_s": upd / (ms * 1e-3), "status": status}
+
+
+def bench_eim_pass(kc, torch, insts, probs):
+    """EIM's distance pass on the batch's largest d = 32 instance, alone on a
+    tuned handle: the pass's kernel time (timing spans), the MFMA work it
+    does (K padded to 32; three products per pair in the split mode) against
+    the peak of the chosen MFMA, and how many candidates needed the canonical
+    FP32 refinement and FP64; plus the same counts over every d = 32 EIM
+    instance of the batch."""
+    big = max((i for i, t in enumerate(insts) if t["algo"] == "eim" and t["d"] == 32),
+              key=lambda i: insts[i]["n"])
+    pr = probs[big]
+    h = kc.Handle()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        for _ in range(2):   # tune, warm
+            kc.eim(pr["X"], pr["k"], pr["eps"], pr["phi"], pr["seed"], handle=h)
+        st.synchronize()
+        h.set_option("timing", 1)
+        res = kc.eim(pr["X"], pr["k"], pr["eps"], pr["phi"], pr["seed"], handle=h)
+        st.synchronize()
+    dist_ms, launches, _ = h.timing_read("eim_dist")
+    its = res[4]
+    rep = h.tune_report()
+    var = [v[0] for key, v in rep.items() if key.startswith("eim/32/")]
+    split = bool(var) and var[-1] >= 2
+    pairs = sum((it["r_size"] - it["ds_size"]) * it["ds_size"] for it in its)
+    flop = 2.0 * pairs * 32 * (3 if split else 1)
+    peak = BF16_MFMA_PEAK_TFLOPS if split else FP32_MFMA_PEAK_TFLOPS
+    achieved = flop / (dist_ms * 1e-3) / 1e12 if dist_ms > 0 else None
+    out = {"workload": "eim_gauss25_n%d_d32_k%d" % (insts[big]["n"], insts[big]["k"]),
+           "iterations": len(its), "pairs": pairs, "dist_ms": dist_ms,
+           "dist_launches": launches,
+           "kernel": "k_mindist_mfma (%s)" % ("split BF16 16x16x32, 3 products" if split
+                                               else "FP32 16x16x4"),
+           "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
+                        "unit": "TFLOP/s", "frac": achieved / peak if achieved else None},
+           "refined_fp32": h.counter("eim_refined"), "decided_fp64": h.counter("eim_exact")}
+    h.close()
+    # every d = 32 EIM instance: candidates refined and decided in FP64
+    ref = exact = cands = 0
+    h = kc.Handle()
+    with torch.cuda.stream(st):
+        for i, t in enumerate(insts):
+            if t["algo"] != "eim" or t["d"] != 32:
+                continue
+            p = probs[i]
+            r = kc.eim(p["X"], p["k"], p["eps"], p["phi"], p["seed"], handle=h)
+            st.synchronize()
+            ref += h.counter("eim_refined")
+            exact += h.counter("eim_exact")
+            cands += sum(it["r_size"] - it["ds_size"] for it in r[4])
+    h.close()
+    out["d32_instances"] = {"candidates": cands, "refined_fp32": ref, "decided_fp64": exact}
+    return out
 
 
 def eim_study(kc, torch, seeds=5):

@@ -144,7 +144,7 @@ def _mrg_check(kc, orc, X, off, k, h):
 
 def _eim_first_iteration(kc, orc, X, inst, h):
     """A larger EIM instance: its first iteration's draws (sizes), threshold
-    over all of H, and 2,000 seeded keep / remove decisions equal the
+    over all of H, and 10,000 seeded keep / remove decisions equal the
     oracle's; the final Gonzalez is replayed on the sample."""
     n, k = len(X), inst["k"]
     Xd = torch.from_numpy(X).cuda()
@@ -169,11 +169,16 @@ def _eim_first_iteration(kc, orc, X, inst, h):
     # removed in the first is still outside it)
     assert np.all(np.isin(S, smp))
     rest = np.setdiff1d(np.arange(n), S)
-    pick = np.random.default_rng(inst["id"]).choice(rest, 2_000, replace=False)
-    for x in pick:
-        keep = orc.min_dist2_to_set(X, int(x), S)[0] > it0["tau"]
+    pick = np.random.default_rng(inst["id"]).choice(rest, min(10_000, len(rest)), replace=False)
+    # d(x, S)^2 of the picked points: the oracle's assignment of [X[pick];
+    # X[S]] to the S rows (its per-point minimum, FP64)
+    Y = np.concatenate([X[pick], X[S]])
+    _, _, md = orc.assign(Y, np.arange(len(pick), len(Y)), want_mind=True)
+    in_smp = np.isin(pick, smp)
+    for x, dm, got in zip(pick, md[:len(pick)], in_smp):
+        keep = dm > it0["tau"]
         if len(its) == 1 or not keep:
-            assert keep == bool(np.isin(x, smp)), x
+            assert keep == bool(got), x
     # the final Gonzalez on the sample, replayed; exact radius
     nc = int(nc.item())
     cc = c.cpu().numpy()[:nc]
