@@ -620,7 +620,8 @@ def bench_c1(kc, torch, W, steps=200):
     g = time_gon(kc, torch, Xd, 20, steps, 10)
     return {"workload": "gon_uniform_n20000_d2_k20", "engine": g["engine"],
             "us_per_call": g["ms"] * 1e3, "us_per_step": g["ms"] * 1e3 / 20,
-            "kernel_us_per_call": g["kern_ms"] / g["launches"] * 1e3,
+            "kernel_us_per_call": g["kern_ms"] / steps * 1e3,
+            "launches_per_call": g["launches"] / steps,
             "dist_updates_per_s": len(X) * 20 / (g["ms"] * 1e-3)}
 
 

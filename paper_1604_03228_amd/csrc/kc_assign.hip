@@ -802,9 +802,7 @@ __global__ __launch_bounds__(256) void k_radius_direct(const float* __restrict__
         }
         __syncthreads();
         for (uint32_t r = 0; r < cnt; ++r) {
-            float a = 0.f;
-#pragma unroll
-            for (int u = 0; u < D; ++u) a = kc_d32_step(a, xc[u], sC[r * D + u]);
+            const float a = kc_d32_dist<D>(xc, sC + r * D);
             m = fminf(m, a);
         }
     }

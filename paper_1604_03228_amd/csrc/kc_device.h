@@ -39,6 +39,20 @@ __device__ __forceinline__ float kc_d32_step(float s, float x, float c)
     return __builtin_fmaf(diff, diff, s);
 }
 
+// The canonical distance over D coordinates.  Its first step, fmaf(t, t,
+// +0), equals t * t for every t (one rounding of the exact square, never
+// -0), so it is written as the multiply: a two-operand instruction, which
+// the VALU issues at a higher rate than the three-operand FMA.
+template <int D, class A, class B>
+__device__ __forceinline__ float kc_d32_dist(const A& x, const B& c)
+{
+    const float t = x[0] - c[0];
+    float s = t * t;
+#pragma unroll
+    for (int j = 1; j < D; ++j) s = kc_d32_step(s, x[j], c[j]);
+    return s;
+}
+
 // Minimum of two non-negative FP32 values (squared distances, +inf) as
 // their bit patterns order: one integer instruction, no NaN quieting.
 __device__ __forceinline__ float kc_fmin_nn(float a, float b)

@@ -317,9 +317,7 @@ __global__ __launch_bounds__(256) void k_eim_direct(const float* __restrict__ X,
         kc_stage_samples(sS, X, ld, D, dS + i0, cnt);
         __syncthreads();
         for (uint32_t r = 0; r < cnt; ++r) {
-            float a = 0.f;
-#pragma unroll
-            for (int u = 0; u < D; ++u) a = kc_d32_step(a, xc[u], sS[r * D + u]);
+            const float a = kc_d32_dist<D>(xc, sS + r * D);
             m = fminf(m, a);
         }
     }
@@ -552,8 +550,7 @@ __global__ __launch_bounds__(256) void k_eim_refine_split(
                 const float* sr = sS + r * (uint32_t)d;
                 float a = 0.f;
                 if constexpr (D > 0) {
-#pragma unroll
-                    for (int u = 0; u < D; ++u) a = kc_d32_step(a, xr[u], sr[u]);
+                    a = kc_d32_dist<D>(xr, sr);
                 } else {
                     for (int u = 0; u < d; ++u) a = kc_d32_step(a, xp[u], sr[u]);
                 }

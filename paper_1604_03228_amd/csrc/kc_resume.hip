@@ -51,8 +51,7 @@ __global__ __launch_bounds__(256) void k_prefix_apply(const float* __restrict__ 
                 const float* cc = sC + c * (uint32_t)d;
                 float s = 0.f;
                 if constexpr (D > 0) {
-#pragma unroll
-                    for (int j = 0; j < D; ++j) s = kc_d32_step(s, xr[j], cc[j]);
+                    s = kc_d32_dist<D>(xr, cc);
                 } else {
                     for (int j = 0; j < d; ++j) s = kc_d32_step(s, xi[j], cc[j]);
                 }
