@@ -691,11 +691,12 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
         !tau || !cnt || !unsure || !exm || !C.blk)
         return h->fail(KC_ENOMEM, "workspace allocation failed");
 
-    // local origin of the points for the MFMA distance passes (d > 8): their
-    // error bound scales with the norms, measured from it
+    // local origin of the points for the MFMA distance passes (every d: the
+    // MFMA variants can run at d <= 8 too): their error bound scales with
+    // the norms, measured from it
     float* mu = (float*)h->ws("e.mu", 4ull * d);
     if (!mu) return h->fail(KC_ENOMEM, "workspace allocation failed");
-    if (d > KC_EIM_DIRECT_MAXD) kc_local_origin(X, ld, d, n, mu, s);
+    kc_local_origin(X, ld, d, n, mu, s);
     h->eim_exact = 0;
     h->eim_refined = 0;
     hipLaunchKernelGGL(k_iota, g1(n), dim3(256), 0, s, R, n);
