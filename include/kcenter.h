@@ -104,14 +104,16 @@ int kc_set_option(kc_handle* h, const char* name, int64_t value);
  * -1 for a variant that could not run.  Keys: "gon/d/a/b/rows" (Gonzalez,
  * a = floor(2 log2 n), b = floor(2 log2 k); variants resident v0, resident
  * v1, streaming), "eim/d/a/b" (EIM distance pass, a and b of the candidate
- * and new-sample counts; variants direct VALU for d <= 8, FP32 MFMA, split
- * MFMA with 4 and with 8 waves per block; an MFMA pass's undecided
- * candidates are refined in canonical FP32 before FP64), "assign/d/a/b/l/m"
- * (the assignment's MFMA pass, a and b of n and k, l = labels, m = input
- * mode; variants 4 and 8 waves per block).  Writes at most `cap` bytes
- * (NUL-terminated) to the host buffer `buf` and the needed size to *need;
- * with cap = 0 (buf may be NULL) it only sets *need.  KC_EINVAL for a NULL handle or need, or when 0 < cap <
- * *need (nothing written). */
+ * and new-sample counts; variants 0 direct VALU for d <= 8, 1 FP32 MFMA,
+ * 2-5 split MFMA with 4 / 8 waves per block and 64 KiB of staged samples,
+ * then 8 / 4 waves with 32 KiB; an MFMA pass's undecided candidates are
+ * refined in canonical FP32 before FP64), "assign/d/a/b/l/m" (the
+ * assignment's MFMA pass, a and b of n and k, l = labels, m = input mode;
+ * variants 0-3: 4 / 8 waves per block with 64 KiB of staged centers, then
+ * 4 / 8 waves with 32 KiB).  Writes at most `cap` bytes (NUL-terminated) to
+ * the host buffer `buf` and the needed size to *need; with cap = 0 (buf may
+ * be NULL) it only sets *need.  KC_EINVAL for a NULL handle or need, or
+ * when 0 < cap < *need (nothing written). */
 int kc_tune_report(kc_handle* h, char* buf, int64_t cap, int64_t* need);
 
 /* Kernel timing.  With option "timing" = 1 every call records a pair of HIP

@@ -860,24 +860,26 @@ int kc_mindist_dpad(int d, bool bf)
     return bf ? kc_mindist_ksteps(d, true) * 32 : kc_mindist_ksteps(d, false) * 4;
 }
 
-// Largest center chunk (multiple of 16) whose LDS copy fits in 64 KiB.
-static uint32_t kc_mindist_chunk(int d, int mode, uint32_t kpad)
+// Largest center chunk (multiple of 16) whose LDS copy fits in `kib` KiB.
+static uint32_t kc_mindist_chunk(int d, int mode, uint32_t kpad, uint32_t kib)
 {
     const uint32_t dp = (uint32_t)kc_md_pitch(mode, kc_mindist_dpad(d, mode != KC_MD_F32));
     const uint32_t per = dp * (mode == KC_MD_BF16 ? 2 : 4) + (mode == KC_MD_BF16 ? 16 : 12);
-    uint32_t c = (64u * 1024u / per) & ~15u;
+    uint32_t c = (kib * 1024u / per) & ~15u;
     if (c < 16) c = 16;
     return c < kpad ? c : kpad;
 }
 
 void kc_mindist(const float* X, const uint16_t* Xb, const float* ex, int64_t ld, uint32_t n,
-                int d, const KcCenters& C, const KcMinOut& O, bool lab, hipStream_t s, int waves)
+                int d, const KcCenters& C, const KcMinOut& O, bool lab, hipStream_t s, int waves,
+                int lds_kib)
 {
+    if (lds_kib != 32) lds_kib = 64;
     if (waves != 8) waves = 4;
     const int mode = Xb ? KC_MD_BF16 : C.Cbl ? KC_MD_SPLIT : KC_MD_F32;
     const bool bf = mode != KC_MD_F32;
     const int ks = kc_mindist_ksteps(d, bf);
-    const uint32_t chunk = kc_mindist_chunk(d, mode, C.kpad);
+    const uint32_t chunk = kc_mindist_chunk(d, mode, C.kpad, (uint32_t)lds_kib);
     const int dp = kc_md_pitch(mode, kc_mindist_dpad(d, bf));
     const size_t smem = (size_t)chunk * (mode == KC_MD_BF16 ? 16 : 12) +
                         (size_t)chunk * dp * (mode == KC_MD_BF16 ? 2 : 4);

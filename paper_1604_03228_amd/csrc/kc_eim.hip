@@ -741,8 +741,9 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
             // Distance pass of the candidates against this iteration's
             // samples, then the keep / remove decisions: variant 0 computes
             // canonical FP32 distances on the VALU (d <= 8), 1 the FP32 MFMA,
-            // 2 and 3 split BF16 MFMAs (option mfma_split) with 4 or 8 waves
-            // per block, all MFMA ones on the points translated to the local
+            // 2 to 5 split BF16 MFMAs (option mfma_split): 4 or 8 waves per
+            // block with 64 KiB of staged samples, then 8 or 4 waves with 32
+            // KiB; all MFMA ones on the points translated to the local
             // origin.  All decide exactly alike; the
             // autotuner measures them once per shape bucket (with the
             // intervals restored before each of its runs).
@@ -822,7 +823,7 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
                     hipEvent_t ev = h->span_begin(s);
                     // d(x, S) needs the smallest distance's bounds only
                     kc_mindist(XR, nullptr, nullptr, d, nc, d, Cs, O, false, s,
-                               var == 3 ? 8 : 4);
+                               (var == 3 || var == 4) ? 8 : 4, var >= 4 ? 32 : 64);
                     h->span_end("eim_dist", ev, 1, s);
                     hipLaunchKernelGGL(k_eim_bounds, g1(nc), dim3(256), 0, s, nc, d, cand, O,
                                        Cs, lo, hi);
@@ -906,8 +907,8 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
                 return e == hipSuccess ? KC_OK
                                        : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
             };
-            const bool feas[4] = {d <= KC_EIM_DIRECT_MAXD, true, h->mfma_split,
-                                  h->mfma_split};
+            const bool feas[6] = {d <= KC_EIM_DIRECT_MAXD, true, h->mfma_split,
+                                  h->mfma_split, h->mfma_split, h->mfma_split};
             char tkey[96];
             snprintf(tkey, sizeof tkey, "eim/%d/%d/%d", d, (int)floor(2.0 * log2((double)nc + 1)),
                      (int)floor(2.0 * log2((double)nds + 1)));
@@ -918,13 +919,13 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
                 if (!lo0 || !hi0) return h->fail(KC_ENOMEM, "workspace allocation failed");
                 hipMemcpyAsync(lo0, lo, 4ull * n, hipMemcpyDeviceToDevice, s);
                 hipMemcpyAsync(hi0, hi, 4ull * n, hipMemcpyDeviceToDevice, s);
-                rc = h->tune(tkey, 4, feas, s, [&](int var) {
+                rc = h->tune(tkey, 6, feas, s, [&](int var) {
                     hipMemcpyAsync(lo, lo0, 4ull * n, hipMemcpyDeviceToDevice, s);
                     hipMemcpyAsync(hi, hi0, 4ull * n, hipMemcpyDeviceToDevice, s);
                     return pass(var);
                 });
             } else if (nds > 0 && nc > 0) {
-                rc = h->tune(tkey, 4, feas, s, pass);
+                rc = h->tune(tkey, 6, feas, s, pass);
             } else {
                 rc = pass(1);
             }

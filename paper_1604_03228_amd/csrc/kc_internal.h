@@ -253,10 +253,11 @@ int kc_mindist_ksteps(int d, bool bf);
 int kc_mindist_dpad(int d, bool bf);
 // One MFMA pass of every point against the staged centers (lab: labels
 // pass); ex: the points' BF16 rounding radii (BF16 passes); waves: 4 or 8
-// waves per block (the results do not depend on it).
+// waves per block; lds_kib: 64 or 32 KiB of staged centers per block (more
+// blocks per CU, more chunks); the results depend on neither.
 void kc_mindist(const float* X, const uint16_t* Xb, const float* ex, int64_t ld, uint32_t n,
                 int d, const KcCenters& C, const KcMinOut& O, bool lab, hipStream_t s,
-                int waves = 4);
+                int waves = 4, int lds_kib = 64);
 void kc_stage_centers(const float* X, const uint16_t* Xb, int64_t ld, int d, uint32_t n,
                       const int64_t* idx, const uint32_t* idx32, uint32_t k,
                       const int64_t* k_dev, const KcCenters& C, uint32_t* status, hipStream_t s);

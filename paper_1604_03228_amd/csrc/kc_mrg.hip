@@ -240,16 +240,19 @@ int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, ui
         h->span_end("assign_direct", ev, 1, s);
         return rc;
     }
-    // the MFMA pass with 4 or 8 waves per block, a measured choice per shape
-    const bool feas[2] = {true, true};
+    // the MFMA pass with 4 or 8 waves per block and 64 or 32 KiB of staged
+    // centers, a measured choice per shape
+    const bool feas[4] = {true, true, true, true};
     char tkey[96];
     snprintf(tkey, sizeof tkey, "assign/%d/%d/%d/%d/%d", d, (int)floor(2.0 * log2((double)n + 1)),
              (int)floor(2.0 * log2((double)k + 1)), labels != nullptr, bf ? 1 : split ? 2 : 0);
-    rc = h->tune(tkey, 2, feas, s, [&](int var) {
+    rc = h->tune(tkey, 4, feas, s, [&](int var) {
         hipEvent_t ev = h->span_begin(s);
-        const int r = h->run_graph(key + (var ? ":mfma8" : ":mfma"), s, [&](hipStream_t st) {
+        char vk[16];
+        snprintf(vk, sizeof vk, ":mfma%d", var);
+        const int r = h->run_graph(key + vk, s, [&](hipStream_t st) {
             kc_mindist(pts->f32, bf ? pts->bf16 : nullptr, ex, pts->ld, n, d, C, O,
-                       labels != nullptr, st, var ? 8 : 4);
+                       labels != nullptr, st, (var & 1) ? 8 : 4, var >= 2 ? 32 : 64);
         });
         h->span_end("assign_mfma", ev, 1, s);
         return r;

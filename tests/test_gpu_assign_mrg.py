@@ -111,14 +111,18 @@ def test_radius_only_far_from_origin(kc, orc, d, k):
     assert float(r.item()) == oR
 
 
-# more centers than one LDS chunk holds, in both passes and with labels
-@pytest.mark.parametrize("d", [2, 16])
+# more centers than one LDS chunk holds, in both passes and with labels, in
+# every block shape of the MFMA pass (tune_force: 4 / 8 waves per block with
+# 64 KiB of staged centers, then with 32 KiB)
+@pytest.mark.parametrize("d", [2, 16, 41])
 @pytest.mark.parametrize("labels", [True, False])
-def test_assign_many_centers(kc, orc, d, labels):
+@pytest.mark.parametrize("var", [0, 1, 2, 3])
+def test_assign_many_centers(kc, orc, d, labels, var):
     rng = np.random.default_rng(50 + d)
     X = (rng.normal(size=(20_000, d)) * 10.0).astype(np.float32)
     C = rng.choice(len(X), 5_000, replace=False)
     h = kc.Handle()
+    h.set_option("tune_force", var)
     Xd = torch.from_numpy(X).cuda()
     lab, r = on_stream(lambda: kc.assign(Xd, torch.from_numpy(C), labels=labels, handle=h))
     assert h.device_status() == 0

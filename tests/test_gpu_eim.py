@@ -112,11 +112,12 @@ def test_unbalanced_blobs(kc, orc, d, split):
 
 # Every variant of the distance pass (tune_force): 0 the direct canonical
 # FP32 pass (d <= 8; elsewhere the first feasible variant), 1 the FP32 MFMA,
-# 2 and 3 the split MFMA with 4 and 8 waves per block; the MFMA variants'
-# undecided candidates go through the canonical FP32 refinement, then FP64.
+# 2-5 the split MFMA with 4 / 8 waves per block and 64 KiB of staged
+# samples, then 8 / 4 waves with 32 KiB; the MFMA variants' undecided
+# candidates go through the canonical FP32 refinement, then FP64.
 # Samples, records and the final Gonzalez equal the oracle's in every one.
 @pytest.mark.parametrize("d", [2, 8, 32])
-@pytest.mark.parametrize("var", [0, 1, 2, 3])
+@pytest.mark.parametrize("var", [0, 1, 2, 3, 4, 5])
 def test_forced_variants(kc, orc, d, var):
     from paper_1604_03228_amd import workloads as W
     X = W.points_gauss_mixture(60_000, d, 25, seed=91 + d, heavy=0.9)
