@@ -730,9 +730,36 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
             // Select: tau over H (exact FP64 against all of S)
             if (nh > 0) {
                 kc_fill_u64((u64*)dH, 0x7FF0000000000000ull, nh, s);   // +inf
-                const uint32_t splits = std::max<uint32_t>(1, std::min<uint32_t>(64, ns / 4096));
-                hipLaunchKernelGGL(k_eim_dist_h, dim3((nh + 3) / 4, splits), dim3(256), 0, s, X,
-                                   ld, d, H, nh, S, ns, dH);
+                if (d <= KC_EXT_MAXD) {
+                    // the exact pass's tiling: 64 points of H per block, held
+                    // as doubles, S streamed through LDS in slices (the same
+                    // FP64 arithmetic, so the same values)
+                    uint32_t* iota = (uint32_t*)h->ws("e.iota", 4ull * nh);
+                    if (!iota) return h->fail(KC_ENOMEM, "workspace allocation failed");
+                    hipLaunchKernelGGL(k_iota, g1(nh), dim3(256), 0, s, iota, nh);
+                    const uint32_t gx = (nh + 63) / 64;
+                    const uint32_t gy = std::max<uint32_t>(
+                        1, std::min<uint32_t>({(2048 + gx - 1) / gx, ns / 512, 65535u}));
+                    switch (d) {
+#define KC_EXH_CASE(DD)                                                                        \
+    case DD:                                                                                   \
+        hipLaunchKernelGGL(k_eim_exact_split_d<DD>, dim3(gx, gy), dim3(256), 0, s, X, ld, H,     \
+                           iota, nh, S, ns, dH);                                               \
+        break;
+                        KC_EXH_CASE(10)
+                        KC_EXH_CASE(16)
+                        KC_EXH_CASE(32)
+#undef KC_EXH_CASE
+                    default:
+                        hipLaunchKernelGGL(k_eim_exact_split, dim3(gx, gy), dim3(256), 0, s, X,
+                                           ld, d, H, iota, nh, S, ns, dH);
+                    }
+                } else {
+                    const uint32_t splits =
+                        std::max<uint32_t>(1, std::min<uint32_t>(64, ns / 4096));
+                    hipLaunchKernelGGL(k_eim_dist_h, dim3((nh + 3) / 4, splits), dim3(256), 0, s,
+                                       X, ld, d, H, nh, S, ns, dH);
+                }
                 const uint32_t rr = (uint32_t)std::min<int64_t>(rsel, nh);
                 hipLaunchKernelGGL(k_eim_select, dim3(1), dim3(1024), 0, s, dH, nh, rr, tau);
             } else {
