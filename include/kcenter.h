@@ -349,9 +349,12 @@ typedef struct {
  * algorithm.  Gonzalez problems and MRG first rounds of equal d share the
  * same launches (register-resident, several per cooperative launch, when
  * every one fits a co-resident grid, else one streamed tile list over all of
- * them with a HIP graph per plan); MRG second rounds likewise.  EIM problems,
- * and problems streamed in BF16, run one after another through their
- * single-problem entry points (kcenter_eim synchronises the stream once per
+ * them with a HIP graph per plan); MRG second rounds likewise.  An EIM
+ * problem whose n does not exceed Algorithm 2's threshold (4/eps) k n^eps
+ * ln n never samples, so its result is Gonzalez's from point 0 with the
+ * covering radius, and it joins those launches as such.  The other EIM
+ * problems, and problems streamed in BF16, run one after another through
+ * their single-problem entry points (kcenter_eim reads counts back in each
  * iteration).  Outputs as for the single-problem calls.
  */
 int kcenter_batch(kc_handle* h, const kc_problem* probs, int32_t count, void* stream);

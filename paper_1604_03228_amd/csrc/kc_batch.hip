@@ -13,9 +13,12 @@
 //   stage 2  the MRG unions (built on the device) are the segments of a
 //            second batched run;
 //   stage 3  each MRG problem's covering radius by the MFMA assignment.
-// EIM problems run their sampling loop (which synchronises per iteration)
-// and finish on the single-problem path; problems streamed in BF16 also take
-// their single-problem entry point.
+// EIM problems that never sample (n at most Algorithm 2's threshold) are
+// Gonzalez problems from point 0 and join stage 1; the others run their
+// sampling loop (which synchronises per iteration) and finish on the
+// single-problem path; problems streamed in BF16 also take their
+// single-problem entry point.
+#include <math.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -130,6 +133,24 @@ static int check_problem(kc_handle* h, const kc_problem& p, int i)
     }
 }
 
+// An EIM problem whose n does not exceed Algorithm 2's threshold
+// (4/eps) k n^eps ln n never samples: its sample is all of V and its result
+// Gonzalez's traversal from V's smallest index, 0, with the covering radius
+// -- exactly a Gonzalez problem with first = 0, which the batch runs in the
+// shared launches (the same constants and comparison as kcenter_eim).
+static bool eim_as_gon(const kc_problem& p)
+{
+    if (p.algo != KC_ALGO_EIM) return false;
+    const double n = (double)p.pts.n;
+    const double thr = (4.0 / p.eim.eps) * (double)p.k * pow(n, p.eim.eps) * log(n);
+    return !(n > thr);
+}
+
+static bool gon_like(const kc_problem& p)
+{
+    return p.algo == KC_ALGO_GON || eim_as_gon(p);
+}
+
 struct SegTag {
     int prob;   // problem index
     int part;   // partition (MRG) or -1 (GON)
@@ -186,13 +207,13 @@ static int group_prepare(kc_handle* h, const kc_problem* probs, const std::vecto
     std::vector<int64_t> rbase;
     for (int i : ids) {
         const kc_problem& p = probs[i];
-        if (p.algo == KC_ALGO_GON) {
+        if (gon_like(p)) {
             KcGonJob j;
             j.X = p.pts.f32;
             j.ld = p.pts.ld;
             j.row0 = 0;
             j.len = (uint32_t)p.pts.n;
-            j.first = (uint32_t)p.first;
+            j.first = p.algo == KC_ALGO_GON ? (uint32_t)p.first : 0u;
             j.k = (uint32_t)p.k;
             jobs.push_back(j);
             tags.push_back({i, -1});
@@ -387,7 +408,7 @@ static void batch_layout(kc_handle* h, const kc_problem* probs, int count, KcBat
     std::map<int, std::vector<int>> byd;
     for (int i = 0; i < count; ++i) {
         const kc_problem& p = probs[i];
-        if (p.algo != KC_ALGO_EIM && p.pts.prec == KC_FP32)
+        if ((p.algo != KC_ALGO_EIM || eim_as_gon(p)) && p.pts.prec == KC_FP32)
             byd[p.pts.d].push_back(i);
         else
             L.single.push_back(i);
@@ -400,7 +421,7 @@ static void batch_layout(kc_handle* h, const kc_problem* probs, int count, KcBat
             bool ok = h->allow_resident;
             int v = 0;
             uint32_t G = 0;
-            if (ok && p.algo == KC_ALGO_GON) ok = h->resident_fit(d, (uint64_t)p.pts.n, &v, &G);
+            if (ok && gon_like(p)) ok = h->resident_fit(d, (uint64_t)p.pts.n, &v, &G);
             for (int q = 0; ok && p.algo == KC_ALGO_MRG && q < p.m; ++q) {
                 const uint64_t len = (uint64_t)(p.offsets[q + 1] - p.offsets[q]);
                 ok = len == 0 || h->resident_fit(d, len, &v, &G);
