@@ -105,6 +105,20 @@ __global__ void k_batch_gather(const float* __restrict__ X, int64_t ld, int d,
     for (int j = 0; j < d; ++j) xs[(uint64_t)j * stride + base + i] = X[r * ld + j];
 }
 
+// SoA columns [base, base+padded) <- rows idx[i] of X (padding repeats the
+// first row), and the segment's remap entries map[off + i] = idx[i]
+__global__ void k_batch_gather_u32(const float* __restrict__ X, int64_t ld, int d,
+                                   const uint32_t* __restrict__ idx, uint32_t n, uint32_t padded,
+                                   float* __restrict__ xs, uint64_t stride, uint64_t base,
+                                   int64_t* __restrict__ map, uint64_t off)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= padded) return;
+    const uint64_t r = idx[i < n ? i : 0];
+    if (i < n) map[off + i] = (int64_t)r;
+    for (int j = 0; j < d; ++j) xs[(uint64_t)j * stride + base + i] = X[r * ld + j];
+}
+
 static int check_problem(kc_handle* h, const kc_problem& p, int i)
 {
     int rc = kc_check_points(h, &p.pts, true);
@@ -400,6 +414,7 @@ static int group_execute(kc_handle* h, const kc_problem* probs, const KcBatchGro
 struct KcBatchLayout {
     std::vector<std::pair<int, std::vector<int>>> groups;   // (d, ids), tag r then s
     std::vector<const char*> tags;
+    std::vector<int> eim;      // EIM problems that sample
     std::vector<int> single;
 };
 
@@ -410,6 +425,8 @@ static void batch_layout(kc_handle* h, const kc_problem* probs, int count, KcBat
         const kc_problem& p = probs[i];
         if ((p.algo != KC_ALGO_EIM || eim_as_gon(p)) && p.pts.prec == KC_FP32)
             byd[p.pts.d].push_back(i);
+        else if (p.algo == KC_ALGO_EIM)
+            L.eim.push_back(i);
         else
             L.single.push_back(i);
     }
@@ -437,6 +454,105 @@ static void batch_layout(kc_handle* h, const kc_problem* probs, int count, KcBat
             L.tags.push_back("s");
         }
     }
+}
+
+// The EIM problems that sample: each runs Algorithm 2's loop (one after
+// another: the loop reads counts back), keeping its sample C; then, per
+// dimension, the final Gonzalez of every problem on its C runs as the
+// segments of one shared run (C's rows gathered, first center C's smallest
+// index), and each problem's covering radius by the assignment.
+static int run_eim_group(kc_handle* h, const kc_problem* probs, const std::vector<int>& ids,
+                         hipStream_t s)
+{
+    if (ids.empty()) return KC_OK;
+    std::vector<uint32_t*> keep(ids.size());
+    std::vector<uint32_t> ncs(ids.size());
+    for (size_t q = 0; q < ids.size(); ++q) {
+        const kc_problem& p = probs[ids[q]];
+        char nm[32];
+        snprintf(nm, sizeof nm, "bE%zu.C", q);
+        keep[q] = (uint32_t*)h->ws(nm, 4ull * (uint64_t)p.pts.n);
+        if (!keep[q]) return h->fail(KC_ENOMEM, "workspace allocation failed");
+        int64_t ns = 0;
+        int32_t ni = 0;
+        const int rc = kc_eim_run(h, &p.pts, p.k, &p.eim, p.centers, p.n_centers, p.radius,
+                                  nullptr, &ns, nullptr, &ni, s, keep[q], &ncs[q]);
+        if (rc) return h->fail(rc, "problem %d: %s", ids[q], h->last_error.c_str());
+    }
+    std::map<int, std::vector<size_t>> byd;
+    for (size_t q = 0; q < ids.size(); ++q) byd[probs[ids[q]].pts.d].push_back(q);
+    for (auto& g : byd) {
+        const int d = g.first;
+        std::vector<size_t> ord = g.second;   // descending k, stable
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+            return probs[ids[a]].k > probs[ids[b]].k;
+        });
+        std::vector<KcGonJob> jobs;
+        uint64_t off = 0;
+        for (size_t q : ord) {
+            const kc_problem& p = probs[ids[q]];
+            KcGonJob j;
+            j.X = nullptr;   // gathered
+            j.ld = p.pts.ld;
+            j.row0 = off;    // its entries of the remap
+            j.len = ncs[q];
+            j.first = 0;
+            j.k = (uint32_t)p.k;
+            jobs.push_back(j);
+            off += ncs[q];
+        }
+        char pre[32];
+        snprintf(pre, sizeof pre, "bE%d.", d);
+        const std::string P(pre);
+        KcGonRun R;
+        KcGonHost H;
+        int rc = kc_plan_gon(h, P, d, 1024, jobs, R, H, s);
+        if (rc) return rc;
+        int64_t* map = (int64_t*)h->ws(P + "map", 8 * std::max<uint64_t>(off, 1));
+        int64_t* cent = (int64_t*)h->ws(P + "cent", 8 * std::max<uint64_t>(R.keysum, 1));
+        int64_t* nch = (int64_t*)h->ws(P + "nch", 8 * jobs.size());
+        std::vector<KcBatchOut> outs;
+        for (size_t q = 0; q < ord.size(); ++q) {
+            const kc_problem& p = probs[ids[ord[q]]];
+            outs.push_back({(int64_t)H.segs[q].keyoff, p.k, (int64_t)q, p.centers, p.n_centers,
+                            nullptr});
+        }
+        const KcBatchOut* outs_d =
+            (const KcBatchOut*)h->upload(P + "outs", outs.data(), sizeof(KcBatchOut) * outs.size(), s);
+        if (!map || !cent || !nch || !outs_d)
+            return h->fail(KC_ENOMEM, "workspace allocation failed");
+        for (size_t q = 0; q < ord.size(); ++q) {
+            const kc_problem& p = probs[ids[ord[q]]];
+            const uint32_t padded = kc_pad64(ncs[ord[q]]);
+            hipLaunchKernelGGL(k_batch_gather_u32, dim3((padded + 255) / 256), dim3(256), 0, s,
+                               p.pts.f32, p.pts.ld, d, keep[ord[q]], ncs[ord[q]], padded,
+                               (float*)R.xs, R.stride, H.segs[q].base, map, jobs[q].row0);
+        }
+        std::string key = P + "run";
+        for (size_t q : ord) {
+            char b[96];
+            const kc_problem& p = probs[ids[q]];
+            snprintf(b, sizeof b, ":%p:%lld:%p:%p", (const void*)p.pts.f32, (long long)p.k,
+                     (void*)p.centers, (void*)p.n_centers);
+            key += b;
+        }
+        rc = kc_run_gon(h, key, R, H, jobs, "batch_gon", s, [&](hipStream_t sst) {
+            kc_gon_finish(R, cent, nch, nullptr, nullptr, nullptr, map, sst);
+            hipLaunchKernelGGL(k_batch_out, dim3((unsigned)outs.size()), dim3(256), 0, sst,
+                               outs_d, (int)outs.size(), cent, nch, (const double*)nullptr);
+        });
+        if (rc) return rc;
+        for (size_t q : ord) {
+            const kc_problem& p = probs[ids[q]];
+            kc_points p32 = p.pts;
+            p32.prec = KC_FP32;
+            p32.bf16 = nullptr;
+            rc = kc_assign_run(h, &p32, p.centers, (uint32_t)p.k, p.n_centers, nullptr,
+                               p.radius, s, P + "a.");
+            if (rc) return rc;
+        }
+    }
+    return KC_OK;
 }
 
 static int run_single(kc_handle* h, const kc_problem& p, int i, hipStream_t s)
@@ -479,6 +595,10 @@ extern "C" int kcenter_batch(kc_handle* h, const kc_problem* probs, int32_t coun
         KcBatchGroup G;
         int rc = group_prepare(h, probs, L.groups[g].second, L.groups[g].first, L.tags[g], s, G);
         if (!rc) rc = group_execute(h, probs, G, s);
+        if (rc) return rc;
+    }
+    {
+        const int rc = run_eim_group(h, probs, L.eim, s);
         if (rc) return rc;
     }
     for (int i : L.single) {
@@ -573,6 +693,7 @@ extern "C" int kcenter_batch_run(kc_handle* h, kc_batch_plan* plan, void* stream
     }
     for (size_t g = 0; g < plan->groups.size() && !rc; ++g)
         rc = group_execute(S, probs, plan->groups[g], s);
+    if (!rc) rc = run_eim_group(S, probs, L.eim, s);
     for (size_t q = 0; q < L.single.size() && !rc; ++q)
         rc = run_single(S, probs[L.single[q]], L.single[q], s);
     // the plan's device status joins the caller's handle

@@ -653,7 +653,16 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
     if (prm->max_iters < 1) return h->fail(KC_EINVAL, "max_iters must be >= 1");
     if (k < 1 || k >= (1 << 24)) return h->fail(KC_EINVAL, "k out of range");
     if (!centers || !n_centers || !radius) return h->fail(KC_EINVAL, "outputs NULL");
-    hipStream_t s = (hipStream_t)stream;
+    return kc_eim_run(h, pts, k, prm, centers, n_centers, radius, sample, n_sample, iters,
+                      n_iters, (hipStream_t)stream, nullptr, nullptr);
+}
+
+int kc_eim_run(kc_handle* h, const kc_points* pts, int64_t k, const kc_eim_params* prm,
+               int64_t* centers, int64_t* n_centers, double* radius, int64_t* sample,
+               int64_t* n_sample, kc_eim_iter* iters, int32_t* n_iters, hipStream_t s,
+               uint32_t* c_keep, uint32_t* nc_keep)
+{
+    int rc = KC_OK;
     const uint32_t n = (uint32_t)pts->n;
     const int d = pts->d;
     const float* X = pts->f32;
@@ -994,6 +1003,12 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
     rc = kc_read_u32(h, cnt + 5, &nc, s);
     if (rc) return rc;
     if (n_sample) *n_sample = nc;
+    if (c_keep) {   // the caller runs the final Gonzalez (a batch's shared launches)
+        hipMemcpyAsync(c_keep, Cidx, 4ull * nc, hipMemcpyDeviceToDevice, s);
+        *nc_keep = nc;
+        const hipError_t e = hipGetLastError();
+        return e == hipSuccess ? KC_OK : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
+    }
     int64_t* C64 = sample ? sample : (int64_t*)h->ws("e.C64", 8ull * nc);
     if (!C64) return h->fail(KC_ENOMEM, "workspace allocation failed");
     hipLaunchKernelGGL(k_u32_to_i64, g1(nc), dim3(256), 0, s, Cidx, nc, C64);

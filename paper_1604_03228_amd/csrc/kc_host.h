@@ -188,3 +188,12 @@ int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, ui
 int kc_gonzalez_bf16(kc_handle* h, const kc_points* pts, int64_t k, int64_t first,
                      int64_t* centers, double* radius_trace, int64_t* n_chosen,
                      hipStream_t s);
+
+// EIM (Algorithm 2 with Select, then Gonzalez on the sample C and the
+// covering radius), arguments checked by the caller.  With c_keep (device,
+// n entries) it stops once C is formed: C's indices, ascending, go to
+// c_keep and |C| to *nc_keep, and centers / radius are not written.
+int kc_eim_run(kc_handle* h, const kc_points* pts, int64_t k, const kc_eim_params* prm,
+               int64_t* centers, int64_t* n_centers, double* radius, int64_t* sample,
+               int64_t* n_sample, kc_eim_iter* iters, int32_t* n_iters, hipStream_t s,
+               uint32_t* c_keep, uint32_t* nc_keep);
