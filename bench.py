@@ -548,7 +548,7 @@ def time_gon(kc, torch, Xd, k, steps, warmup, resident=True):
         for _ in range(warmup):
             kc.gonzalez(Xd, k, 0, handle=h)
         st.synchronize()
-        for name in ("gon_resident", "gon_step"):
+        for name in ("gon_resident", "gon_step", "gon_block"):
             h.timing_read(name)           # drop warm-up spans
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -567,7 +567,11 @@ def time_gon(kc, torch, Xd, k, steps, warmup, resident=True):
     out = {"ms": e0.elapsed_time(e1) / steps, "wall": wall}
     res_ms, res_l, _ = h.timing_read("gon_resident")
     stp_ms, stp_l, _ = h.timing_read("gon_step")
-    if res_l > 0:
+    blk_ms, blk_l, _ = h.timing_read("gon_block")
+    if blk_l > 0:
+        out.update(engine="k_gon_block", kern_ms=blk_ms, launches=blk_l,
+                   sources=["kc_block.hip", "kc_device.h"])
+    elif res_l > 0:
         out.update(engine="k_gon_resident", kern_ms=res_ms, launches=res_l,
                    sources=["kc_resident.hip", "kc_device.h"])
     else:
@@ -585,7 +589,7 @@ def gon_roofline(n, d, k, g):
     one integer min).  Streamed: bound by HBM, 4d + 8 bytes per point and
     step against 8 TB/s."""
     kern = g["engine"]
-    if kern == "k_gon_resident":
+    if kern in ("k_gon_resident", "k_gon_block"):
         per = g["kern_ms"] / g["launches"]
         flops = n * k * 3 * d
         ach = flops / (per * 1e-3) / 1e12

@@ -796,8 +796,9 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
     if (rc) return rc;
 
     // Engines: the register-resident persistent kernel in either variant
-    // when the points fit its co-resident grid, or the streaming steps; the
-    // autotuner measures the feasible ones once per shape bucket.
+    // when the points fit its co-resident grid, the streaming steps, or one
+    // workgroup when the points fit its lanes; the autotuner measures the
+    // feasible ones once per shape bucket.
     char key[256];
     snprintf(key, sizeof key, "gon:%p:%lld:%d:%lld:%lld:%lld:%p:%p:%p", (const void*)pts->f32,
              (long long)pts->n, pts->d, (long long)pts->ld, (long long)k, (long long)first,
@@ -810,6 +811,19 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
     const int rows = kc_resident_rows_ok(pts->d, pts->f32, pts->ld, (uint64_t)pts->n);
     auto run = [&](int var) -> int {
         if (var == 2) return stream_run();
+        if (var == 3) {   // one workgroup: small inputs
+            R.xa = pts->f32;
+            R.lda = pts->ld;
+            hipEvent_t ev = h->span_begin(s);
+            hipError_t e = kc_gon_block(pts->d, pts->f32, pts->ld, (uint32_t)pts->n,
+                                        (uint32_t)first, (int)k, R.mind, R.keys, s);
+            h->span_end("gon_block", ev, 1, s);
+            if (e != hipSuccess)
+                return h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
+            kc_gon_finish(R, centers, n_chosen, radius_trace, nullptr, nullptr, nullptr, s);
+            e = hipGetLastError();
+            return e == hipSuccess ? KC_OK : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
+        }
         const uint32_t G = kc_resident_blocks_for(pts->d, var, (uint64_t)pts->n);
         // exchange words, then the abort flag: one fill clears both.  The
         // kernel writes every min-distance and every key (zeros past an early
@@ -840,7 +854,9 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
         e = hipGetLastError();
         return e == hipSuccess ? KC_OK : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
     };
-    bool feas[3] = {false, false, true};
+    // (the one-workgroup engine is register-resident too: option resident)
+    bool feas[4] = {false, false, true,
+                    h->allow_resident && kc_gon_block_fits(pts->d, (uint64_t)pts->n)};
     for (int v = 0; v < 2; ++v) {
         const uint32_t G = kc_resident_blocks_for(pts->d, v, (uint64_t)pts->n);
         feas[v] = h->allow_resident && G > 0 && (int64_t)G <= (int64_t)h->resident_max(pts->d, v);
@@ -848,7 +864,7 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
     char tkey[96];
     snprintf(tkey, sizeof tkey, "gon/%d/%d/%d/%d", pts->d, (int)floor(2.0 * log2((double)pts->n)),
              (int)floor(2.0 * log2((double)k)), rows);
-    return h->tune(tkey, 3, feas, s, run);
+    return h->tune(tkey, 4, feas, s, run);
 }
 
 }  // extern "C"

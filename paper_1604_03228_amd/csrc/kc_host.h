@@ -197,3 +197,10 @@ int kc_eim_run(kc_handle* h, const kc_points* pts, int64_t k, const kc_eim_param
                int64_t* centers, int64_t* n_centers, double* radius, int64_t* sample,
                int64_t* n_sample, kc_eim_iter* iters, int32_t* n_iters, hipStream_t s,
                uint32_t* c_keep, uint32_t* nc_keep);
+
+// Gonzalez in one workgroup (kc_block.hip): whether d has an instantiation
+// and n points fit its lanes; the launch (keys and min-distances as the
+// resident engine writes them).
+bool kc_gon_block_fits(int d, uint64_t n);
+hipError_t kc_gon_block(int d, const float* X, int64_t ld, uint32_t n, uint32_t first, int k,
+                        float* mind, u64* keys, hipStream_t s);

@@ -235,3 +235,43 @@ def test_invalid_arguments(kc):
         kc.gonzalez(X, 3, -1, handle=h)
     with pytest.raises(ValueError):
         kc.gonzalez(X.t(), 3, 0, handle=h)
+
+
+# The one-workgroup engine (tune_force = 3; it holds up to 1,024 lanes x
+# 20 / 16 / 8 / 7 / 4 points at d = 2 / 3 / 8 / 10 / 16): integer
+# coordinates, centers, trace and count bit-exact against the oracle, at
+# ragged sizes up to its capacity, with k = 1, early stops and a first
+# center past the middle.
+@pytest.mark.parametrize("d,n", [(2, 1), (2, 1025), (2, 20_000), (2, 20_480), (3, 16_384),
+                                 (8, 5_000), (10, 7_168), (16, 4_096)])
+@pytest.mark.parametrize("k", [1, 7, 200])
+def test_block_engine(kc, orc, d, n, k):
+    X = np.random.default_rng(n + d).integers(-30, 31, (n, d)).astype(np.float32)
+    h = kc.Handle()
+    h.set_option("tune_force", 3)
+    h.set_option("timing", 1)
+    Xd = torch.from_numpy(X).cuda()
+    first = (2 * n) // 3
+    c, tr, nch = kc.gonzalez(Xd, k, first, handle=h)
+    assert h.device_status() == 0
+    _, la, _ = h.timing_read("gon_block")
+    assert la == 1
+    oc, otr, og = orc.gon(X, k, first)
+    assert int(nch.item()) == og
+    assert np.array_equal(c.cpu().numpy(), oc)
+    assert np.array_equal(tr.cpu().numpy(), otr)
+    h.close()
+
+
+def test_block_engine_early_stop(kc, orc):
+    base = np.random.default_rng(9).integers(0, 9, (11, 2)).astype(np.float32)
+    base = np.unique(base, axis=0)
+    X = np.repeat(base, 700, axis=0)
+    h = kc.Handle()
+    h.set_option("tune_force", 3)
+    c, tr, nch = kc.gonzalez(torch.from_numpy(X).cuda(), 40, 0, handle=h)
+    oc, otr, og = orc.gon(X, 40, 0)
+    got = int(nch.item())
+    assert got == og == len(base)
+    assert np.array_equal(c.cpu().numpy(), oc) and np.array_equal(tr.cpu().numpy(), otr)
+    h.close()
