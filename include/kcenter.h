@@ -78,8 +78,9 @@ const char* kc_strerror(int status);
 const char* kc_last_error(const kc_handle* h);
 
 /* Options (name, value): "graphs" 0/1 (capture per-step launches in a HIP
- * graph, default 1); "resident" 0/1 (use the register-resident persistent
- * Gonzalez kernel when the points fit, default 1); "resident_blocks" (at
+ * graph, default 1); "resident" 0/1 (use the register-resident Gonzalez
+ * engines -- the persistent grid, or one workgroup for small inputs -- when
+ * the points fit, default 1); "resident_blocks" (at
  * most this many blocks per persistent launch, 0 = as many as are
  * co-resident, the default; a testing aid: smaller grids hold fewer points,
  * so more inputs stream and MRG partitions spread over more launches);
@@ -103,7 +104,7 @@ int kc_set_option(kc_handle* h, const char* name, int64_t value);
  * bucket, "<key> <chosen variant> <ms of variant 0> <ms of variant 1> ...",
  * -1 for a variant that could not run.  Keys: "gon/d/a/b/rows" (Gonzalez,
  * a = floor(2 log2 n), b = floor(2 log2 k); variants resident v0, resident
- * v1, streaming), "eim/d/a/b" (EIM distance pass, a and b of the candidate
+ * v1, streaming, one workgroup for small n), "eim/d/a/b" (EIM distance pass, a and b of the candidate
  * and new-sample counts; variants 0 direct VALU for d <= 8, 1 FP32 MFMA,
  * 2-5 split MFMA with 4 / 8 waves per block and 64 KiB of staged samples,
  * then 8 / 4 waves with 32 KiB; an MFMA pass's undecided candidates are
