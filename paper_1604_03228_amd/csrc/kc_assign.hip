@@ -93,15 +93,24 @@ __device__ __forceinline__ float kc_bf16_to_f32(uint16_t h)
 // terms (l.l', and the r's) are below 3.01 * 2^-18 |x| |c|, so its error
 // bound is the FP32 one plus 3.1 * 2^-18 (a + b)^2, at 3/16 of the FP32
 // MFMA's issue cost.
+// Where 3d is well below 3 * 32 * ceil(d/32), the packed split lays the
+// three products along one K range instead: points [h | h | l], centers
+// [h' | l' | h'] (each part d long, zero padding after), one MFMA chain of
+// ceil(3d/32) K-steps; the products and their count are the split's, so is
+// the bound.
 #define KC_MD_F32 0
 #define KC_MD_BF16 1
 #define KC_MD_SPLIT 2
+#define KC_MD_SPLITP 3
 // Point tiles (16 points each) per wave: four where the B operand is small
 // (more independent MFMA chains per center tile, fewer A reads per point),
 // two where it would crowd the VGPRs.
 __host__ __device__ constexpr int kc_md_pt(int mode, int ks)
 {
-    return (mode == KC_MD_F32 && ks <= 8) || (mode != KC_MD_F32 && ks <= 2) ? 4 : 2;
+    return (mode == KC_MD_F32 && ks <= 8) || (mode == KC_MD_SPLITP && ks <= 4) ||
+                   (mode != KC_MD_F32 && ks <= 2)
+               ? 4
+               : 2;
 }
 // LDS row pitch of a staged center, in elements: the padded K plus 16
 // bytes, so the 16 rows one A-operand read touches start in distinct banks.
@@ -121,7 +130,7 @@ __device__ __forceinline__ uint16_t kc_f32_to_bf16_rne(float t)
     return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
 }
 
-// MODE: KC_MD_F32, KC_MD_BF16 or KC_MD_SPLIT.  KS: MFMA K-steps (K = 4*KS
+// MODE: KC_MD_F32, KC_MD_BF16, KC_MD_SPLIT or KC_MD_SPLITP.  KS: MFMA K-steps (K = 4*KS
 // for FP32, 32*KS otherwise).  LAB: labels pass, per point the best center's
 // index (arg), its v (m1), its lower-bound term (lob) and the smallest one of
 // the other centers (lo2).  Without LAB (a covering radius, a distance to a
@@ -197,6 +206,25 @@ __global__ __launch_bounds__(W * 64) void k_mindist_mfma(
                     nxp[pt] = __builtin_fmaf(f, f, nxp[pt]);
                 }
                 bb[pt][BF ? ks : 0] = w;
+            }
+        } else if (MODE == KC_MD_SPLITP) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                kc_v8bf w;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    // packed K position: part 0 and 1 take h, part 2 takes l
+                    const int kk = ks * 32 + grp * 8 + e;
+                    const int part = kk < d ? 0 : kk < 2 * d ? 1 : kk < 3 * d ? 2 : 3;
+                    const int j = kk - part * d;
+                    float v = (ok && part < 3) ? X[p * ld + j] : 0.f;
+                    if (C.mu && part < 3) v = ok ? v - C.mu[j] : 0.f;
+                    if (part == 0) nxp[pt] = __builtin_fmaf(v, v, nxp[pt]);
+                    const float fh = kc_bf16_to_f32(kc_f32_to_bf16_rne(v));
+                    const float fl = kc_bf16_to_f32(kc_f32_to_bf16_rne(v - fh));
+                    w[e] = (__bf16)(part == 2 ? fl : fh);
+                }
+                bb[pt][ks] = w;
             }
         } else {
 #pragma unroll
@@ -461,12 +489,26 @@ __global__ void k_stage_centers(const float* __restrict__ X, const uint16_t* __r
     const uint64_t r = (uint64_t)ri;
     double nn = 0.0, ee = 0.0, nb = 0.0;
     float nf = 0.f;
-    const bool split = C.Cbl != nullptr;
+    const bool split = C.Cbl != nullptr || C.pk;
     for (int j = 0; j < dp; ++j) {
         const float v = j < d ? X[r * ld + j] : 0.f;
         if (C.Cf) C.Cf[(uint64_t)i * dp + j] = v;
         if (C.Ct) C.Ct[(uint64_t)i * dp + j] = (C.mu && j < d) ? v - C.mu[j] : v;
-        if (split) {
+        if (C.pk) {
+            // packed row [h | l | h | 0]: position j takes part j / d of
+            // coordinate j mod d
+            const int part = j < d ? 0 : j < 2 * d ? 1 : j < 3 * d ? 2 : 3;
+            const int jj = j - part * d;
+            const float u = part < 3 ? X[r * ld + jj] : 0.f;
+            const float t = (C.mu && part < 3) ? u - C.mu[jj] : u;
+            const uint16_t hh = kc_f32_to_bf16_rne(t);
+            C.Cb[(uint64_t)i * dp + j] =
+                part == 1 ? kc_f32_to_bf16_rne(t - kc_bf16_to_f32(hh)) : hh;
+            if (part == 0) {
+                nf = __builtin_fmaf(t, t, nf);
+                nn += (double)t * (double)t;
+            }
+        } else if (split) {
             // high and low BF16 parts of the translated value
             const float t = (C.mu && j < d) ? v - C.mu[j] : v;
             const uint16_t hh = kc_f32_to_bf16_rne(t);
@@ -838,6 +880,7 @@ __global__ void k_sqrt_out(const double* __restrict__ r2, double* __restrict__ o
 
 #define KC_MD_CASES_F32(X) X(1) X(2) X(3) X(4) X(8) X(11) X(16) X(32) X(64)
 #define KC_MD_CASES_BF16(X) X(1) X(2) X(4) X(8)
+#define KC_MD_CASES_PK(X) X(1) X(2) X(4) X(5)
 
 int kc_mindist_ksteps(int d, bool bf)
 {
@@ -860,11 +903,40 @@ int kc_mindist_dpad(int d, bool bf)
     return bf ? kc_mindist_ksteps(d, true) * 32 : kc_mindist_ksteps(d, false) * 4;
 }
 
-// Largest center chunk (multiple of 16) whose LDS copy fits in `kib` KiB.
-static uint32_t kc_mindist_chunk(int d, int mode, uint32_t kpad, uint32_t kib)
+int kc_split_packed_ksteps(int d)
 {
-    const uint32_t dp = (uint32_t)kc_md_pitch(mode, kc_mindist_dpad(d, mode != KC_MD_F32));
-    const uint32_t per = dp * (mode == KC_MD_BF16 ? 2 : 4) + (mode == KC_MD_BF16 ? 16 : 12);
+    const int ks = (3 * d + 31) / 32;
+    const int opts[] = {1, 2, 4, 5};   // d <= 53 (longer rows spill at 8 waves)
+    for (int o : opts)
+        if (ks <= o) return o < 3 * kc_mindist_ksteps(d, true) ? o : 0;
+    return 0;
+}
+
+bool kc_split_use_packed(int d, uint32_t kpad)
+{
+    // the packed operands cost a point about 3d scattered loads and roundings
+    // up front, which fewer MFMAs repay only over many centers
+    return kpad >= 2048 && kc_split_packed_ksteps(d) > 0;
+}
+
+int kc_mindist_dpad_split(int d, uint32_t kpad)
+{
+    return kc_split_use_packed(d, kpad) ? kc_split_packed_ksteps(d) * 32
+                                        : kc_mindist_dpad(d, true);
+}
+
+// Bytes per staged center element in LDS (the split keeps two parts).
+static uint32_t kc_md_elem_bytes(int mode)
+{
+    return mode == KC_MD_BF16 || mode == KC_MD_SPLITP ? 2 : 4;
+}
+
+// Largest center chunk (multiple of 16) whose LDS copy fits in `kib` KiB
+// (dp: the staged rows' padded K).
+static uint32_t kc_mindist_chunk(int dp_rows, int mode, uint32_t kpad, uint32_t kib)
+{
+    const uint32_t dp = (uint32_t)kc_md_pitch(mode, dp_rows);
+    const uint32_t per = dp * kc_md_elem_bytes(mode) + (mode == KC_MD_BF16 ? 16 : 12);
     uint32_t c = (kib * 1024u / per) & ~15u;
     if (c < 16) c = 16;
     return c < kpad ? c : kpad;
@@ -876,16 +948,20 @@ void kc_mindist(const float* X, const uint16_t* Xb, const float* ex, int64_t ld,
 {
     if (lds_kib != 32) lds_kib = 64;
     if (waves != 8) waves = 4;
-    const int mode = Xb ? KC_MD_BF16 : C.Cbl ? KC_MD_SPLIT : KC_MD_F32;
+    const int mode = Xb     ? KC_MD_BF16
+                     : C.pk  ? KC_MD_SPLITP
+                     : C.Cbl ? KC_MD_SPLIT
+                             : KC_MD_F32;
     const bool bf = mode != KC_MD_F32;
-    const int ks = kc_mindist_ksteps(d, bf);
-    const uint32_t chunk = kc_mindist_chunk(d, mode, C.kpad, (uint32_t)lds_kib);
-    const int dp = kc_md_pitch(mode, kc_mindist_dpad(d, bf));
+    const int rows = mode == KC_MD_SPLITP ? C.dp : kc_mindist_dpad(d, bf);
+    const int ks = mode == KC_MD_SPLITP ? C.dp / 32 : kc_mindist_ksteps(d, bf);
+    const uint32_t chunk = kc_mindist_chunk(rows, mode, C.kpad, (uint32_t)lds_kib);
+    const int dp = kc_md_pitch(mode, rows);
     const size_t smem = (size_t)chunk * (mode == KC_MD_BF16 ? 16 : 12) +
-                        (size_t)chunk * dp * (mode == KC_MD_BF16 ? 2 : 4);
+                        (size_t)chunk * dp * kc_md_elem_bytes(mode);
     const uint32_t per_block = (uint32_t)waves * 16 * kc_md_pt(mode, ks);
     const dim3 grid((n + per_block - 1) / per_block), block(waves * 64);
-    const float gm = (float)kc_md_gamma(d, mode == KC_MD_SPLIT);
+    const float gm = (float)kc_md_gamma(d, mode == KC_MD_SPLIT || mode == KC_MD_SPLITP);
 #define KC_LAUNCH_W(M, K, WW)                                                              \
     if (lab)                                                                               \
         hipLaunchKernelGGL((k_mindist_mfma<M, K, true, WW>), grid, block, smem, s, X, Xb, ex, \
@@ -915,12 +991,20 @@ void kc_mindist(const float* X, const uint16_t* Xb, const float* ex, int64_t ld,
             KC_MD_CASES_BF16(KC_CASE)
 #undef KC_CASE
         }
-    } else {
+    } else if (mode == KC_MD_SPLIT) {
         switch (ks) {
 #define KC_CASE(K) \
     case K:        \
         KC_LAUNCH(KC_MD_SPLIT, K) break;
             KC_MD_CASES_BF16(KC_CASE)
+#undef KC_CASE
+        }
+    } else {
+        switch (ks) {
+#define KC_CASE(K) \
+    case K:        \
+        KC_LAUNCH(KC_MD_SPLITP, K) break;
+            KC_MD_CASES_PK(KC_CASE)
 #undef KC_CASE
         }
     }

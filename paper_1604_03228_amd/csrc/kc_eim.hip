@@ -809,8 +809,10 @@ int kc_eim_run(kc_handle* h, const kc_points* pts, int64_t k, const kc_eim_param
                     h->span_end("eim_dist", ev, 1, s);
                 } else if (nds > 0 && nc > 0) {
                     const bool split = var >= 2;
-                    const int dp = kc_mindist_dpad(d, split);
                     const uint32_t kpad = (nds + 15u) & ~15u;
+                    const int dp =
+                        split ? kc_mindist_dpad_split(d, kpad) : kc_mindist_dpad(d, false);
+                    const bool packed = split && kc_split_use_packed(d, kpad);
                     float* XR = (float*)h->ws("e.XR", 4ull * nc * d);
                     KcCenters Cs;
                     Cs.kpad = kpad;
@@ -823,7 +825,10 @@ int kc_eim_run(kc_handle* h, const kc_points* pts, int64_t k, const kc_eim_param
                     Cs.mu = mu;
                     if (split) {
                         Cs.Cb = (uint16_t*)h->ws("e.cbh", 2ull * kpad * dp);
-                        Cs.Cbl = (uint16_t*)h->ws("e.cbl", 2ull * kpad * dp);
+                        if (packed)
+                            Cs.pk = true;
+                        else
+                            Cs.Cbl = (uint16_t*)h->ws("e.cbl", 2ull * kpad * dp);
                     } else {
                         Cs.Ct = (float*)h->ws("e.ct", 4ull * kpad * dp);
                     }
@@ -841,7 +846,8 @@ int kc_eim_run(kc_handle* h, const kc_points* pts, int64_t k, const kc_eim_param
                     hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, kin, kout, vin, vout,
                                                        (int)nds, 0, 32, s);
                     void* tmp = h->ws("e.sorttmp", tbytes);
-                    if (!XR || !Cs.Cf || (!split && !Cs.Ct) || (split && (!Cs.Cb || !Cs.Cbl)) ||
+                    if (!XR || !Cs.Cf || (!split && !Cs.Ct) ||
+                        (split && (!Cs.Cb || (!packed && !Cs.Cbl))) ||
                         !Cs.cn || !Cs.cnl || !Cs.clen || !Cs.cmax || !O.arg || !O.m1 || !O.lo2 ||
                         !O.nx || !kin || !kout || !vin || !vout || !tmp)
                         return h->fail(KC_ENOMEM, "workspace allocation failed");

@@ -154,6 +154,8 @@ struct KcCenters {
                              // high parts of the translated FP32 values
     uint16_t* Cbl = nullptr; // [kpad][dp] their low parts (split passes:
                              // FP32 inputs on three BF16 MFMAs)
+    bool pk = false;         // packed split: Cb holds [h | l | h] rows of dp
+                             // (kc_split_packed_ksteps), Cbl unused
     float* cn = nullptr;     // |c|^2 of the MFMA inputs, in FP32
     float* cnl = nullptr;    // cn - (g |c|^2 + 2 e_c |c|)
     float* clen = nullptr;   // |c| of the MFMA inputs, rounded up
@@ -206,9 +208,10 @@ __device__ inline KcMdBounds kc_md_bounds(const KcMinOut& O, uint32_t p,
                                           int d, bool lab)
 {
     KcMdBounds B;
-    const double g = kc_md_gamma(d, C.Cbl != nullptr);
+    const bool bf_in = C.Cb && !C.Cbl && !C.pk;   // BF16 inputs (not a split)
+    const double g = kc_md_gamma(d, C.Cbl != nullptr || C.pk);
     const double nx = O.nx[p];
-    if (!lab && !(C.Cb && !C.Cbl)) {
+    if (!lab && !bf_in) {
         B.hi = (nx + (double)O.m1[p]) * (1.0 + 1e-12) + 1e-30 * d;
         const double l = (nx + (double)O.lo2[p]) * (1.0 - 1e-12) - 1e-30 * d;
         B.lo_min = l > 0.0 ? l : 0.0;
@@ -216,7 +219,7 @@ __device__ inline KcMdBounds kc_md_bounds(const KcMinOut& O, uint32_t p,
         return B;
     }
     const double a = sqrt(nx) * (1.0 + (d + 4) * 5.9604644775390625e-8) * (1.0 + 1e-6);
-    const double e_x = (C.Cb && !C.Cbl && ex) ? (double)ex[p] : 0.0;
+    const double e_x = (bf_in && ex) ? (double)ex[p] : 0.0;
     const double P0 = (g * a * a + 2.0 * e_x * a) * (1.0 + 1e-12);
     const int32_t a1 = lab ? O.arg[p] : 0;
     if (a1 < 0 || (uint32_t)a1 >= C.kpad) {
@@ -251,6 +254,12 @@ __device__ inline KcMdBounds kc_md_bounds(const KcMinOut& O, uint32_t p,
 
 int kc_mindist_ksteps(int d, bool bf);
 int kc_mindist_dpad(int d, bool bf);
+// K-steps of the packed split for dimension d (0: it would not use fewer
+// MFMAs than the three-chain split); whether a split pass over kpad centers
+// packs; and its staged row length (packed or not).
+int kc_split_packed_ksteps(int d);
+bool kc_split_use_packed(int d, uint32_t kpad);
+int kc_mindist_dpad_split(int d, uint32_t kpad);
 // One MFMA pass of every point against the staged centers (lab: labels
 // pass); ex: the points' BF16 rounding radii (BF16 passes); waves: 4 or 8
 // waves per block; lds_kib: 64 or 32 KiB of staged centers per block (more

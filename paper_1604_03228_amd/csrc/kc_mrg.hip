@@ -178,8 +178,9 @@ int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, ui
     const bool split = !bf && h->mfma_split;
     const uint32_t n = (uint32_t)pts->n;
     const int d = pts->d;
-    const int dp = kc_mindist_dpad(d, bf || split);
     const uint32_t kpad = (k + 15u) & ~15u;
+    const int dp = split ? kc_mindist_dpad_split(d, kpad) : kc_mindist_dpad(d, bf);
+    const bool packed = split && kc_split_use_packed(d, kpad);
     KcCenters C;
     C.kpad = kpad;
     C.dp = dp;
@@ -199,7 +200,10 @@ int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, ui
     C.Ct = (bf || split) ? nullptr : (float*)h->ws(pre + "ct", sizeof(float) * (size_t)kpad * dp);
     if (split) {
         C.Cb = (uint16_t*)h->ws(pre + "cb", sizeof(uint16_t) * (size_t)kpad * dp);
-        C.Cbl = (uint16_t*)h->ws(pre + "cbl", sizeof(uint16_t) * (size_t)kpad * dp);
+        if (packed)
+            C.pk = true;
+        else
+            C.Cbl = (uint16_t*)h->ws(pre + "cbl", sizeof(uint16_t) * (size_t)kpad * dp);
     }
     KcMinOut O;
     O.arg = (int32_t*)h->ws(pre + "arg", sizeof(int32_t) * n);
@@ -214,7 +218,7 @@ int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, ui
     double* r2 = (double*)h->ws(pre + "r2", 16);
     float* ex = bf ? (float*)h->ws(pre + "ex", sizeof(float) * n) : nullptr;
     if (!C.Cf || (bf && (!C.Cb || !C.cerr)) || (!bf && !mu) || (!bf && !split && !C.Ct) ||
-        (split && (!C.Cb || !C.Cbl)) || !C.cmax || !C.cn || !C.cnl ||
+        (split && (!C.Cb || (!packed && !C.Cbl))) || !C.cmax || !C.cn || !C.cnl ||
         !C.clen || !O.arg || !O.m1 ||
         !O.lo2 || !O.lob || !O.nx || !hi || !list || !nlist || !lo_max || !r2 || (bf && !ex))
         return h->fail(KC_ENOMEM, "workspace allocation failed");

@@ -132,6 +132,27 @@ def test_assign_many_centers(kc, orc, d, labels, var):
         assert np.array_equal(lab.cpu().numpy(), olab)
 
 
+# the split pass over 2,048 or more centers packs its three products along
+# one K range where that saves MFMAs (d <= 21 and 33..53): the part
+# boundaries at d, 2d, 3d fall in every place of the 32-wide K steps; 2,032
+# centers and d = 22, 54 keep three chains
+@pytest.mark.parametrize("d,k", [(3, 2048), (10, 2048), (11, 2048), (21, 2048), (22, 2048),
+                                 (33, 2048), (43, 2048), (53, 2048), (54, 2048), (16, 2032)])
+def test_assign_packed_split(kc, orc, d, k):
+    rng = np.random.default_rng(70 + d)
+    X = (rng.normal(size=(6_000, d)) * 4.0 + 300.0).astype(np.float32)
+    C = rng.choice(len(X), k, replace=False)
+    Xd = torch.from_numpy(X).cuda()
+    olab, oR = orc.assign(X, C)
+    for labels in (True, False):
+        h = kc.Handle()
+        lab, r = on_stream(lambda: kc.assign(Xd, torch.from_numpy(C), labels=labels, handle=h))
+        assert h.device_status() == 0
+        assert float(r.item()) == oR
+        if labels:
+            assert np.array_equal(lab.cpu().numpy(), olab)
+
+
 def test_mrg_fewer_centers_than_k_small_d(kc, orc):
     # 13 distinct points, repeated: fewer than k centers exist, and the
     # covering radius (direct pass, d = 2) sees the device-side center count
