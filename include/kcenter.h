@@ -135,12 +135,13 @@ int kc_timing_read(kc_handle* h, const char* name, double* ms, int64_t* launches
  * (synchronises the device): "bf16_listed" is the number of (point, step)
  * pairs listed by the stream as possible candidates, "bf16_rescored" the
  * number rescored exactly in FP32.  "eim_refined": candidates an MFMA
- * distance pass of the most recent kcenter_eim call left undecided, which
- * were then bounded in canonical FP32 (summed over its iterations).
+ * distance pass of the most recent kcenter_eim call (or batch) left
+ * undecided, which were then bounded in canonical FP32 (summed over its
+ * iterations).
  * "eim_exact": candidates whose keep /
  * remove decision the most recent kcenter_eim call on the handle made in
- * exact FP64 (summed over its iterations; a batch counts its last EIM
- * problem).  "assign_rescored": points the most recent assignment on the
+ * exact FP64 (summed over its iterations; a batch sums over its EIM
+ * problems that sample).  "assign_rescored": points the most recent assignment on the
  * handle rescored in FP64 (uncertified nearest center, or a possible
  * maximiser of the radius; a point may count twice).  KC_EINVAL for an
  * unknown name. */
@@ -354,9 +355,14 @@ typedef struct {
  * problem whose n does not exceed Algorithm 2's threshold (4/eps) k n^eps
  * ln n never samples, so its result is Gonzalez's from point 0 with the
  * covering radius, and it joins those launches as such.  The other EIM
- * problems, and problems streamed in BF16, run one after another through
- * their single-problem entry points (kcenter_eim reads counts back in each
- * iteration).  Outputs as for the single-problem calls.
+ * problems run their sampling loops in lockstep: each phase of an iteration
+ * (draws and compactions; Select, distance pass and decisions; FP32
+ * refinement; FP64 decisions and R's compaction) is queued for every one of
+ * them before one wait, whose readback sizes the next phase.  Then, per d,
+ * the final Gonzalez of all of them runs as the segments of one run on
+ * their samples C, and each covering radius by the assignment.  Gonzalez
+ * and MRG problems in BF16 run one after another through their
+ * single-problem entry points.  Outputs as for the single-problem calls.
  */
 int kcenter_batch(kc_handle* h, const kc_problem* probs, int32_t count, void* stream);
 

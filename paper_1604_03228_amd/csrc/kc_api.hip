@@ -248,6 +248,49 @@ int kc_handle::tune(const std::string& key, int nvar, const bool* feasible, hipS
     return run(best);   // the call's results and spans: the chosen variant's
 }
 
+int kc_handle::choice(const std::string& key, int nvar, const bool* feasible, hipStream_t s,
+                      bool* measure)
+{
+    *measure = false;
+    int first = -1, nfeas = 0;
+    for (int v = 0; v < nvar; ++v)
+        if (feasible[v]) {
+            if (first < 0) first = v;
+            ++nfeas;
+        }
+    if (first < 0) return -1;
+    if (tune_force >= 0) return tune_force < nvar && feasible[tune_force] ? tune_force : first;
+    auto it = tuned.find(key);
+    if (it != tuned.end() && feasible[it->second]) return it->second;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        cs = hipStreamCaptureStatusActive;
+    }
+    *measure = autotune && nfeas > 1 && cs == hipStreamCaptureStatusNone;
+    return first;
+}
+
+void* kc_handle::pinned(const std::string& name, size_t bytes)
+{
+    Staging& st = staging["pinned:" + name];
+    if (st.cap >= bytes && st.p) return st.p;
+    if (st.p) {
+        hipDeviceSynchronize();   // no queued copy may still target it
+        hipHostFree(st.p);
+    }
+    st.p = nullptr;
+    st.cap = 0;
+    const size_t cap = (bytes + 4095) & ~(size_t)4095;
+    if (hipHostMalloc(&st.p, cap, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        st.p = nullptr;
+        return nullptr;
+    }
+    st.cap = cap;
+    return st.p;
+}
+
 // ---------------------------------------------------------------------------
 // argument checks
 

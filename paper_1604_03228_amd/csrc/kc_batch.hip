@@ -410,7 +410,8 @@ static int group_execute(kc_handle* h, const kc_problem* probs, const KcBatchGro
 // whose points (every partition, for MRG) fit a co-resident register-resident
 // grid ("r"), and the others ("s"), which stream -- one problem too large for
 // the register file then leaves the others on the resident engine; EIM
-// problems and BF16 problems run alone (`single`).
+// problems that sample run their loops in lockstep (`eim`); Gonzalez and MRG
+// problems in BF16 run alone (`single`).
 struct KcBatchLayout {
     std::vector<std::pair<int, std::vector<int>>> groups;   // (d, ids), tag r then s
     std::vector<const char*> tags;
@@ -456,8 +457,8 @@ static void batch_layout(kc_handle* h, const kc_problem* probs, int count, KcBat
     }
 }
 
-// The EIM problems that sample: each runs Algorithm 2's loop (one after
-// another: the loop reads counts back), keeping its sample C; then, per
+// The EIM problems that sample: their Algorithm 2 loops run in lockstep (one
+// wait per phase for all of them), each keeping its sample C; then, per
 // dimension, the final Gonzalez of every problem on its C runs as the
 // segments of one shared run (C's rows gathered, first center C's smallest
 // index), and each problem's covering radius by the assignment.
@@ -465,20 +466,10 @@ static int run_eim_group(kc_handle* h, const kc_problem* probs, const std::vecto
                          hipStream_t s)
 {
     if (ids.empty()) return KC_OK;
-    std::vector<uint32_t*> keep(ids.size());
-    std::vector<uint32_t> ncs(ids.size());
-    for (size_t q = 0; q < ids.size(); ++q) {
-        const kc_problem& p = probs[ids[q]];
-        char nm[32];
-        snprintf(nm, sizeof nm, "bE%zu.C", q);
-        keep[q] = (uint32_t*)h->ws(nm, 4ull * (uint64_t)p.pts.n);
-        if (!keep[q]) return h->fail(KC_ENOMEM, "workspace allocation failed");
-        int64_t ns = 0;
-        int32_t ni = 0;
-        const int rc = kc_eim_run(h, &p.pts, p.k, &p.eim, p.centers, p.n_centers, p.radius,
-                                  nullptr, &ns, nullptr, &ni, s, keep[q], &ncs[q]);
-        if (rc) return h->fail(rc, "problem %d: %s", ids[q], h->last_error.c_str());
-    }
+    std::vector<const uint32_t*> keep;
+    std::vector<uint32_t> ncs;
+    int rc0 = kc_eim_sample_many(h, probs, ids, keep, ncs, s);
+    if (rc0) return rc0;
     std::map<int, std::vector<size_t>> byd;
     for (size_t q = 0; q < ids.size(); ++q) byd[probs[ids[q]].pts.d].push_back(q);
     for (auto& g : byd) {

@@ -626,15 +626,565 @@ __global__ void k_gather_soa32(const float* __restrict__ X, int64_t ld, int d,
 
 // ---------------------------------------------------------------------------
 // host driver
+//
+// Algorithm 2's loop runs as phases that only enqueue work; between phases
+// the host reads the few counts that size the next phase's launches, from
+// pinned words that every problem in flight fills before one wait.
+// kc_eim_loops drives one problem (kcenter_eim) or a batch's in lockstep:
+// per iteration the draws and compactions of every problem, a wait; Select,
+// the distance pass and the decisions, a wait; the FP32 refinement where it
+// applies, a wait; the FP64 decisions and R's compaction, a wait.  Each
+// problem's arithmetic and order of operations are those of a run alone.
 
 static inline dim3 g1(uint64_t n, int b = 256) { return dim3((unsigned)((n + b - 1) / b)); }
 
-static int kc_read_u32(kc_handle* h, const uint32_t* dev, uint32_t* out, hipStream_t s)
+// One problem's loop state.  Buffers named with `pre` are the problem's own
+// (they live across phases); the distance pass's scratch is shared, since a
+// problem's use of it starts and ends within one phase on the one stream.
+struct KcEimLoop {
+    int id = 0;
+    const float* X = nullptr;
+    int64_t ld = 0;
+    uint32_t n = 0;
+    int d = 0;
+    int64_t k = 0;
+    const kc_eim_params* prm = nullptr;
+    kc_eim_iter* iters = nullptr;
+    std::string pre;
+    double A_S = 0.0, A_H = 0.0, thr = 0.0;
+    int64_t rsel = 1;
+    uint32_t *R = nullptr, *R2 = nullptr, *S = nullptr, *H = nullptr, *cand = nullptr;
+    uint32_t *unsure = nullptr, *uns2 = nullptr, *cnt = nullptr;
+    uint8_t *fS = nullptr, *fH = nullptr, *fK = nullptr, *keep = nullptr;
+    float *lo = nullptr, *hi = nullptr, *mu = nullptr;
+    double* tau = nullptr;
+    KcCompact C;
+    // pinned: [0..2] |dS| |H| |cand|, [3] undecided, [4] |R'|, [5] FP64-decided,
+    // [6..7] tau (a double)
+    uint32_t* hw = nullptr;
+    uint32_t nr = 0, ns = 0;
+    int it = 0;
+    bool done = false;
+    // the current iteration
+    double pS = 0.0, pH = 0.0;
+    uint32_t nds = 0, nh = 0, nc = 0, nu = 0, refined_it = 0;
+    int var = 1;
+    bool passed = false;   // S is not empty: distance pass and decisions
+    bool whole = false;    // the tuner ran the pass to its end
+    bool refine = false;   // FP32 refinement this iteration
+};
+
+static int kc_eim_init(kc_handle* h, KcEimLoop& P, const kc_points* pts, int64_t k,
+                       const kc_eim_params* prm, kc_eim_iter* iters, hipStream_t s)
 {
-    if (hipMemcpyAsync(out, dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
-        hipError_t e = hipGetLastError();
+    P.X = pts->f32;
+    P.ld = pts->ld;
+    P.n = (uint32_t)pts->n;
+    P.d = pts->d;
+    P.k = k;
+    P.prm = prm;
+    P.iters = iters;
+    const uint32_t n = P.n;
+    // constants of Algorithm 2 and Select, in FP64 on the host (natural log)
+    const double L = log((double)n);
+    const double ne = pow((double)n, prm->eps);
+    P.A_S = 9.0 * (double)k * ne * L;
+    P.A_H = 4.0 * ne * L;
+    P.thr = (4.0 / prm->eps) * (double)k * ne * L;
+    P.rsel = (int64_t)ceil(prm->phi * L);
+    if (P.rsel < 1) P.rsel = 1;
+    const std::string& p = P.pre;
+    P.R = (uint32_t*)h->ws(p + "R", 4ull * n);
+    P.R2 = (uint32_t*)h->ws(p + "R2", 4ull * n);
+    P.S = (uint32_t*)h->ws(p + "S", 4ull * n);
+    P.H = (uint32_t*)h->ws(p + "H", 4ull * n);
+    P.cand = (uint32_t*)h->ws(p + "cand", 4ull * n);
+    P.fS = (uint8_t*)h->ws(p + "fS", n);
+    P.fH = (uint8_t*)h->ws(p + "fH", n);
+    P.fK = (uint8_t*)h->ws(p + "fK", n);
+    P.keep = (uint8_t*)h->ws(p + "keep", n);
+    P.lo = (float*)h->ws(p + "lo", 4ull * n);
+    P.hi = (float*)h->ws(p + "hi", 4ull * n);
+    P.tau = (double*)h->ws(p + "tau", 16);
+    // [0] dS [1] H [2] cand [3] R [4] FP64 [5] refined-undecided
+    P.cnt = (uint32_t*)h->ws(p + "cnt", 64);
+    P.unsure = (uint32_t*)h->ws(p + "uns", 4ull * n);
+    P.uns2 = (uint32_t*)h->ws(p + "uns2", 4ull * n);
+    P.C.nb_cap = (n + KC_CMP_ITEMS - 1) / KC_CMP_ITEMS + 1;
+    P.C.blk = (uint32_t*)h->ws(p + "blk", 4ull * P.C.nb_cap);
+    // local origin of the points for the MFMA distance passes (every d: the
+    // MFMA variants can run at d <= 8 too): their error bound scales with
+    // the norms, measured from it
+    P.mu = (float*)h->ws(p + "mu", 4ull * P.d);
+    if (!P.R || !P.R2 || !P.S || !P.H || !P.cand || !P.fS || !P.fH || !P.fK || !P.keep ||
+        !P.lo || !P.hi || !P.tau || !P.cnt || !P.unsure || !P.uns2 || !P.C.blk || !P.mu)
+        return h->fail(KC_ENOMEM, "workspace allocation failed");
+    kc_local_origin(P.X, P.ld, P.d, n, P.mu, s);
+    hipLaunchKernelGGL(k_iota, g1(n), dim3(256), 0, s, P.R, n);
+    kc_fill_u32((uint32_t*)P.lo, 0x7F800000u, n, s);
+    kc_fill_u32((uint32_t*)P.hi, 0x7F800000u, n, s);
+    P.nr = n;
+    P.ns = 0;
+    P.it = 0;
+    P.done = false;
+    return KC_OK;
+}
+
+// Phase 1: the loop test, the draws and the split of R into dS, H and the
+// candidates; their sizes go to hw[0..2].
+static int kc_eim_draw_phase(kc_handle* h, KcEimLoop& P, hipStream_t s)
+{
+    if ((double)P.nr <= P.thr) {
+        P.done = true;
+        return KC_OK;
+    }
+    if (P.it >= P.prm->max_iters)
+        return h->fail(KC_ENOCONV, "R still has %u points after %d iterations", P.nr, P.it);
+    P.pS = P.A_S / (double)P.nr;
+    if (P.pS > 1.0) P.pS = 1.0;
+    P.pH = P.A_H / (double)P.nr;
+    if (P.pH > 1.0) P.pH = 1.0;
+    hipLaunchKernelGGL(k_eim_draw, g1(P.nr), dim3(256), 0, s, P.R, P.nr, P.prm->seed, P.it,
+                       P.pS, P.pH, P.fS, P.fH, P.fK);
+    kc_compact(P.C, P.fS, P.R, P.nr, P.S + P.ns, P.cnt + 0, s);
+    kc_compact(P.C, P.fH, P.R, P.nr, P.H, P.cnt + 1, s);
+    kc_compact(P.C, P.fK, P.R, P.nr, P.cand, P.cnt + 2, s);
+    if (hipMemcpyAsync(P.hw, P.cnt, 12, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return h->fail(KC_EHIP, "readback failed");
+    return KC_OK;
+}
+
+// Select (Algorithm 3): tau over H, exact FP64 against all of S.
+static int kc_eim_select(kc_handle* h, KcEimLoop& P, hipStream_t s)
+{
+    const uint32_t nh = P.nh, ns = P.ns;
+    const int d = P.d;
+    if (nh == 0) {
+        kc_fill_u64((u64*)P.tau, 0xFFF0000000000000ull, 1, s);   // -inf
+        return KC_OK;
+    }
+    double* dH = (double*)h->ws("e.dH", 8ull * nh);
+    if (!dH) return h->fail(KC_ENOMEM, "workspace allocation failed");
+    kc_fill_u64((u64*)dH, 0x7FF0000000000000ull, nh, s);   // +inf
+    if (d <= KC_EXT_MAXD) {
+        // the exact pass's tiling: 64 points of H per block, held as
+        // doubles, S streamed through LDS in slices (the same FP64
+        // arithmetic, so the same values)
+        uint32_t* iota = (uint32_t*)h->ws("e.iota", 4ull * nh);
+        if (!iota) return h->fail(KC_ENOMEM, "workspace allocation failed");
+        hipLaunchKernelGGL(k_iota, g1(nh), dim3(256), 0, s, iota, nh);
+        const uint32_t gx = (nh + 63) / 64;
+        const uint32_t gy = std::max<uint32_t>(
+            1, std::min<uint32_t>({(2048 + gx - 1) / gx, ns / 512, 65535u}));
+        switch (d) {
+#define KC_EXH_CASE(DD)                                                                        \
+    case DD:                                                                                   \
+        hipLaunchKernelGGL(k_eim_exact_split_d<DD>, dim3(gx, gy), dim3(256), 0, s, P.X, P.ld,  \
+                           P.H, iota, nh, P.S, ns, dH);                                        \
+        break;
+            KC_EXH_CASE(10)
+            KC_EXH_CASE(16)
+            KC_EXH_CASE(32)
+#undef KC_EXH_CASE
+        default:
+            hipLaunchKernelGGL(k_eim_exact_split, dim3(gx, gy), dim3(256), 0, s, P.X, P.ld, d,
+                               P.H, iota, nh, P.S, ns, dH);
+        }
+    } else {
+        const uint32_t splits = std::max<uint32_t>(1, std::min<uint32_t>(64, ns / 4096));
+        hipLaunchKernelGGL(k_eim_dist_h, dim3((nh + 3) / 4, splits), dim3(256), 0, s, P.X, P.ld,
+                           d, P.H, nh, P.S, ns, dH);
+    }
+    const uint32_t rr = (uint32_t)std::min<int64_t>(P.rsel, nh);
+    hipLaunchKernelGGL(k_eim_select, dim3(1), dim3(1024), 0, s, dH, nh, rr, P.tau);
+    return KC_OK;
+}
+
+// The distance pass of the candidates against this iteration's samples and
+// the keep / remove decisions by the intervals.  Variant 0 computes
+// canonical FP32 distances on the VALU (d <= 8), 1 the FP32 MFMA, 2 to 5
+// split BF16 MFMAs (option mfma_split): 4 or 8 waves per block with 64 KiB
+// of staged samples, then 8 or 4 waves with 32 KiB; all MFMA ones on the
+// points translated to the local origin.  All decide exactly alike.  With
+// d <= KC_EXT_MAXD the undecided count goes to hw[3] (it sizes the next
+// phase); above, the exact FP64 decisions follow here.
+static int kc_eim_pass_front(kc_handle* h, KcEimLoop& P, int var, hipStream_t s)
+{
+    const uint32_t nds = P.nds, nc = P.nc, ns = P.ns;
+    const int d = P.d;
+    P.refined_it = 0;
+    P.refine = false;
+    if (nds > 0 && nc > 0 && var == 0) {
+        const double u32 = 5.9604644775390625e-8, m = d + 2;
+        const double g = m * u32 / (1.0 - m * u32);
+        hipEvent_t ev = h->span_begin(s);
+        switch (d) {
+#define KC_DIR_CASE(DD)                                                                     \
+    case DD:                                                                                \
+        hipLaunchKernelGGL(k_eim_direct<DD>, g1(nc), dim3(256), 0, s, P.X, P.ld, P.cand, nc,  \
+                           P.S + ns - nds, nds, g, P.lo, P.hi);                             \
+        break;
+            KC_DIR_CASE(1)
+            KC_DIR_CASE(2)
+            KC_DIR_CASE(3)
+            KC_DIR_CASE(4)
+            KC_DIR_CASE(5)
+            KC_DIR_CASE(6)
+            KC_DIR_CASE(7)
+            KC_DIR_CASE(8)
+#undef KC_DIR_CASE
+        }
+        h->span_end("eim_dist", ev, 1, s);
+    } else if (nds > 0 && nc > 0) {
+        const bool split = var >= 2;
+        const uint32_t kpad = (nds + 15u) & ~15u;
+        const int dp = split ? kc_mindist_dpad_split(d, kpad) : kc_mindist_dpad(d, false);
+        const bool packed = split && kc_split_use_packed(d, kpad);
+        float* XR = (float*)h->ws("e.XR", 4ull * nc * d);
+        KcCenters Cs;
+        Cs.kpad = kpad;
+        Cs.dp = dp;
+        Cs.Cf = (float*)h->ws("e.cf", 4ull * kpad * dp);
+        Cs.cn = (float*)h->ws("e.cn", 4ull * kpad);
+        Cs.cnl = (float*)h->ws("e.cnl", 4ull * kpad);
+        Cs.clen = (float*)h->ws("e.clen", 4ull * kpad);
+        Cs.cmax = (float*)h->ws("e.cmax", 16);
+        Cs.mu = P.mu;
+        if (split) {
+            Cs.Cb = (uint16_t*)h->ws("e.cbh", 2ull * kpad * dp);
+            if (packed)
+                Cs.pk = true;
+            else
+                Cs.Cbl = (uint16_t*)h->ws("e.cbl", 2ull * kpad * dp);
+        } else {
+            Cs.Ct = (float*)h->ws("e.ct", 4ull * kpad * dp);
+        }
+        KcMinOut O;
+        O.arg = (int32_t*)h->ws("e.arg", 4ull * nc);
+        O.m1 = (float*)h->ws("e.m1", 4ull * nc);
+        O.lo2 = (float*)h->ws("e.m2", 4ull * nc);
+        O.nx = (float*)h->ws("e.nx", 4ull * nc);
+        // the new samples in ascending order of norm, then staged
+        uint32_t* kin = (uint32_t*)h->ws("e.skey", 4ull * nds);
+        uint32_t* kout = (uint32_t*)h->ws("e.skey2", 4ull * nds);
+        uint32_t* vin = (uint32_t*)h->ws("e.sval", 4ull * nds);
+        uint32_t* vout = (uint32_t*)h->ws("e.sval2", 4ull * nds);
+        size_t tbytes = 0;
+        hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, kin, kout, vin, vout, (int)nds, 0,
+                                           32, s);
+        void* tmp = h->ws("e.sorttmp", tbytes);
+        if (!XR || !Cs.Cf || (!split && !Cs.Ct) || (split && (!Cs.Cb || (!packed && !Cs.Cbl))) ||
+            !Cs.cn || !Cs.cnl || !Cs.clen || !Cs.cmax || !O.arg || !O.m1 || !O.lo2 || !O.nx ||
+            !kin || !kout || !vin || !vout || !tmp)
+            return h->fail(KC_ENOMEM, "workspace allocation failed");
+        hipLaunchKernelGGL(k_gather_rows, g1((uint64_t)nc * d), dim3(256), 0, s, P.X, P.ld, d,
+                           P.cand, nc, XR);
+        hipLaunchKernelGGL(k_sample_norm_keys, g1(nds), dim3(256), 0, s, P.X, P.ld, d,
+                           P.S + ns - nds, nds, P.mu, kin, vin);
+        if (hipcub::DeviceRadixSort::SortPairs(tmp, tbytes, kin, kout, vin, vout, (int)nds, 0, 32,
+                                               s) != hipSuccess) {
+            (void)hipGetLastError();
+            return h->fail(KC_EHIP, "sample sort failed");
+        }
+        kc_stage_centers(P.X, nullptr, P.ld, d, P.n, nullptr, vout, nds, nullptr, Cs,
+                         h->status_word, s);
+        hipEvent_t ev = h->span_begin(s);
+        // d(x, S) needs the smallest distance's bounds only
+        kc_mindist(XR, nullptr, nullptr, d, nc, d, Cs, O, false, s,
+                   (var == 3 || var == 4) ? 8 : 4, var >= 4 ? 32 : 64);
+        h->span_end("eim_dist", ev, 1, s);
+        hipLaunchKernelGGL(k_eim_bounds, g1(nc), dim3(256), 0, s, nc, d, P.cand, O, Cs, P.lo,
+                           P.hi);
+    }
+    // keep / remove
+    kc_fill_u32(P.cnt + 4, 0u, 1, s);
+    hipLaunchKernelGGL(k_eim_decide, g1(nc), dim3(256), 0, s, nc, P.cand, P.lo, P.hi, P.tau,
+                       P.keep, P.unsure, P.cnt + 4);
+    if (d <= KC_EXT_MAXD) {
+        if (hipMemcpyAsync(P.hw + 3, P.cnt + 4, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+            return h->fail(KC_EHIP, "readback failed");
+    } else {
+        hipLaunchKernelGGL(k_eim_exact, dim3(2048), dim3(256), 0, s, P.X, P.ld, d, P.cand,
+                           P.unsure, P.cnt + 4, P.S, ns, P.tau, P.keep, P.lo, P.hi);
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? KC_OK : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
+}
+
+// The MFMA pass's undecided (hw[3] of the front phase), when there are
+// enough of them against S: canonical FP32 over all of S first; what it
+// leaves undecided goes to hw[3].
+static int kc_eim_pass_refine(kc_handle* h, KcEimLoop& P, int var, hipStream_t s)
+{
+    P.nu = P.hw[3];
+    const uint32_t nu = P.nu, ns = P.ns;
+    const int d = P.d;
+    if (!(var > 0 && nu > 0 && (uint64_t)nu * ns >= (1ull << 22))) return KC_OK;
+    P.refine = true;
+    P.refined_it = nu;
+    uint32_t* rmin = (uint32_t*)h->ws("e.rmin", 4ull * nu);
+    if (!rmin) return h->fail(KC_ENOMEM, "workspace allocation failed");
+    const uint32_t gx = (nu + 63) / 64;
+    const uint32_t gy =
+        std::max<uint32_t>(1, std::min<uint32_t>({(2048 + gx - 1) / gx, ns / 512, 65535u}));
+    kc_fill_u32(rmin, 0x7F800000u, nu, s);   // +inf
+    kc_fill_u32(P.cnt + 5, 0u, 1, s);
+    switch (d) {
+#define KC_RFS_CASE(DD)                                                                        \
+    case DD:                                                                                   \
+        hipLaunchKernelGGL(k_eim_refine_split<DD>, dim3(gx, gy), dim3(256), 0, s, P.X, P.ld, d, \
+                           P.cand, P.unsure, nu, P.S, ns, rmin);                               \
+        break;
+        KC_RFS_CASE(2)
+        KC_RFS_CASE(3)
+        KC_RFS_CASE(8)
+        KC_RFS_CASE(10)
+        KC_RFS_CASE(16)
+        KC_RFS_CASE(32)
+#undef KC_RFS_CASE
+    default:
+        hipLaunchKernelGGL(k_eim_refine_split<0>, dim3(gx, gy), dim3(256), 0, s, P.X, P.ld, d,
+                           P.cand, P.unsure, nu, P.S, ns, rmin);
+    }
+    const double u32 = 5.9604644775390625e-8, m = d + 2;
+    hipLaunchKernelGGL(k_eim_refine_finish, g1(nu), dim3(256), 0, s, P.cand, P.unsure, nu, rmin,
+                       m * u32 / (1.0 - m * u32), d, P.tau, P.keep, P.lo, P.hi, P.uns2,
+                       P.cnt + 5);
+    // the FP64 pass takes what is still undecided
+    hipMemcpyAsync(P.cnt + 4, P.cnt + 5, 4, hipMemcpyDeviceToDevice, s);
+    if (hipMemcpyAsync(P.hw + 3, P.cnt + 5, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return h->fail(KC_EHIP, "readback failed");
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? KC_OK : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
+}
+
+// Exact FP64 decisions of what is still undecided (hw[3]).
+static int kc_eim_pass_exact(kc_handle* h, KcEimLoop& P, hipStream_t s)
+{
+    if (P.refine) P.nu = P.hw[3];
+    const uint32_t nu = P.nu, ns = P.ns;
+    const int d = P.d;
+    if (nu == 0) return KC_OK;
+    const uint32_t* uns = P.refine ? P.uns2 : P.unsure;
+    double* exm = (double*)h->ws("e.exm", 8ull * nu);   // exact minima of the undecided
+    if (!exm) return h->fail(KC_ENOMEM, "workspace allocation failed");
+    const uint32_t gx = (nu + 63) / 64;
+    const uint32_t gy =
+        std::max<uint32_t>(1, std::min<uint32_t>({(2048 + gx - 1) / gx, ns / 512, 65535u}));
+    kc_fill_u64((u64*)exm, 0x7FF0000000000000ull, nu, s);   // +inf
+    switch (d) {
+#define KC_EXS_CASE(DD)                                                                       \
+    case DD:                                                                                  \
+        hipLaunchKernelGGL(k_eim_exact_split_d<DD>, dim3(gx, gy), dim3(256), 0, s, P.X, P.ld,  \
+                           P.cand, uns, nu, P.S, ns, exm);                                    \
+        break;
+        KC_EXS_CASE(10)
+        KC_EXS_CASE(16)
+        KC_EXS_CASE(32)
+#undef KC_EXS_CASE
+    default:
+        hipLaunchKernelGGL(k_eim_exact_split, dim3(gx, gy), dim3(256), 0, s, P.X, P.ld, d,
+                           P.cand, uns, nu, P.S, ns, exm);
+    }
+    hipLaunchKernelGGL(k_eim_exact_finish, g1(nu), dim3(256), 0, s, P.cand, uns, nu, exm, P.tau,
+                       P.keep, P.lo, P.hi);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? KC_OK : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
+}
+
+static int kc_eim_wait(kc_handle* h, hipStream_t s)
+{
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        const hipError_t e = hipGetLastError();
         return h->fail(KC_EHIP, "readback: %s", hipGetErrorString(e));
+    }
+    return KC_OK;
+}
+
+// The whole pass with its own waits (the tuner's unit of measurement).
+static int kc_eim_pass_whole(kc_handle* h, KcEimLoop& P, int var, hipStream_t s)
+{
+    int rc = kc_eim_pass_front(h, P, var, s);
+    if (rc || P.d > KC_EXT_MAXD) return rc;
+    if ((rc = kc_eim_wait(h, s))) return rc;
+    if ((rc = kc_eim_pass_refine(h, P, var, s))) return rc;
+    if (P.refine && (rc = kc_eim_wait(h, s))) return rc;
+    return kc_eim_pass_exact(h, P, s);
+}
+
+// Phase 2: Select and the front of the distance pass.  An untuned shape
+// bucket is measured here: every feasible variant runs whole (the intervals
+// restored before each run), and the chosen one's results stand.
+static int kc_eim_front_phase(kc_handle* h, KcEimLoop& P, hipStream_t s)
+{
+    P.nds = P.hw[0];
+    P.nh = P.hw[1];
+    P.nc = P.hw[2];
+    P.ns += P.nds;
+    P.passed = P.ns > 0;
+    P.whole = false;
+    P.refine = false;
+    P.nu = 0;
+    P.refined_it = 0;
+    if (!P.passed) return KC_OK;
+    int rc = kc_eim_select(h, P, s);
+    if (rc) return rc;
+    const int d = P.d;
+    if (!(P.nds > 0 && P.nc > 0)) {
+        P.var = 1;
+        return kc_eim_pass_front(h, P, 1, s);
+    }
+    const bool feas[6] = {d <= KC_EIM_DIRECT_MAXD, true, h->mfma_split,
+                          h->mfma_split, h->mfma_split, h->mfma_split};
+    char tkey[96];
+    snprintf(tkey, sizeof tkey, "eim/%d/%d/%d", d, (int)floor(2.0 * log2((double)P.nc + 1)),
+             (int)floor(2.0 * log2((double)P.nds + 1)));
+    bool measure = false;
+    P.var = h->choice(tkey, 6, feas, s, &measure);
+    if (P.var < 0) return h->fail(KC_EUNSUPPORTED, "no feasible variant for %s", tkey);
+    if (!measure) return kc_eim_pass_front(h, P, P.var, s);
+    // the intervals every measured run starts from
+    const uint32_t n = P.n;
+    float* lo0 = (float*)h->ws("e.lo0", 4ull * n);
+    float* hi0 = (float*)h->ws("e.hi0", 4ull * n);
+    if (!lo0 || !hi0) return h->fail(KC_ENOMEM, "workspace allocation failed");
+    hipMemcpyAsync(lo0, P.lo, 4ull * n, hipMemcpyDeviceToDevice, s);
+    hipMemcpyAsync(hi0, P.hi, 4ull * n, hipMemcpyDeviceToDevice, s);
+    P.whole = true;
+    return h->tune(tkey, 6, feas, s, [&](int v) {
+        hipMemcpyAsync(P.lo, lo0, 4ull * n, hipMemcpyDeviceToDevice, s);
+        hipMemcpyAsync(P.hi, hi0, 4ull * n, hipMemcpyDeviceToDevice, s);
+        P.var = v;
+        return kc_eim_pass_whole(h, P, v, s);
+    });
+}
+
+// Phase 4: the rest of the decisions, then R' = the kept candidates; |R'|,
+// the FP64-decided count and tau go to hw[4..7].
+static int kc_eim_keep_phase(kc_handle* h, KcEimLoop& P, hipStream_t s)
+{
+    if (!P.passed) return KC_OK;
+    if (!P.whole && P.d <= KC_EXT_MAXD) {
+        const int rc = kc_eim_pass_exact(h, P, s);
+        if (rc) return rc;
+    }
+    h->eim_refined += P.refined_it;
+    kc_compact(P.C, P.keep, P.cand, P.nc, P.R2, P.cnt + 3, s);
+    std::swap(P.R, P.R2);
+    if (hipMemcpyAsync(P.hw + 4, P.cnt + 3, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(P.hw + 6, P.tau, 8, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return h->fail(KC_EHIP, "readback failed");
+    return KC_OK;
+}
+
+// Phase 5 (host): the iteration's record; R' becomes R.
+static void kc_eim_end_iter(kc_handle* h, KcEimLoop& P)
+{
+    double tau_h = -INFINITY;
+    uint32_t new_nr = P.nr;
+    if (P.passed) {
+        new_nr = P.hw[4];
+        h->eim_exact += P.hw[5];
+        memcpy(&tau_h, P.hw + 6, 8);
+    }
+    if (P.iters) {
+        kc_eim_iter& rec = P.iters[P.it];
+        rec.r_size = P.nr;
+        rec.ds_size = P.nds;
+        rec.h_size = P.nh;
+        rec.s_size = P.ns;
+        rec.tau = tau_h;
+        rec.p_s = P.pS;
+        rec.p_h = P.pH;
+    }
+    P.nr = new_nr;
+    ++P.it;
+}
+
+// C = S u R in ascending order into P.H; its size goes to hw[0].
+static int kc_eim_form_c(kc_handle* h, KcEimLoop& P, hipStream_t s)
+{
+    uint8_t* mark = P.fS;
+    hipMemsetAsync(mark, 0, P.n, s);
+    if (P.ns) hipLaunchKernelGGL(k_mark, g1(P.ns), dim3(256), 0, s, P.S, P.ns, mark);
+    if (P.nr) hipLaunchKernelGGL(k_mark, g1(P.nr), dim3(256), 0, s, P.R, P.nr, mark);
+    kc_compact(P.C, mark, nullptr, P.n, P.H, P.cnt + 5, s);
+    if (hipMemcpyAsync(P.hw, P.cnt + 5, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return h->fail(KC_EHIP, "readback failed");
+    return KC_OK;
+}
+
+// Drive every loop to its end in lockstep, then form each C (its size in
+// hw[0], its indices in H).  A problem that fails stops the call.
+static int kc_eim_loops(kc_handle* h, std::vector<KcEimLoop>& L, hipStream_t s)
+{
+    int rc;
+    auto fail_at = [&](const KcEimLoop& P, int code) {
+        return L.size() > 1 ? h->fail(code, "problem %d: %s", P.id, h->last_error.c_str())
+                            : code;
+    };
+    for (;;) {
+        bool any = false;
+        for (KcEimLoop& P : L)
+            if (!P.done) {
+                if ((rc = kc_eim_draw_phase(h, P, s))) return fail_at(P, rc);
+                any = any || !P.done;
+            }
+        if (!any) break;
+        if ((rc = kc_eim_wait(h, s))) return rc;
+        bool wait_nu = false;
+        for (KcEimLoop& P : L)
+            if (!P.done) {
+                if ((rc = kc_eim_front_phase(h, P, s))) return fail_at(P, rc);
+                wait_nu = wait_nu || (P.passed && !P.whole && P.d <= KC_EXT_MAXD);
+            }
+        if (wait_nu) {
+            if ((rc = kc_eim_wait(h, s))) return rc;
+            bool wait_ref = false;
+            for (KcEimLoop& P : L)
+                if (!P.done && P.passed && !P.whole && P.d <= KC_EXT_MAXD) {
+                    if ((rc = kc_eim_pass_refine(h, P, P.var, s))) return fail_at(P, rc);
+                    wait_ref = wait_ref || P.refine;
+                }
+            if (wait_ref && (rc = kc_eim_wait(h, s))) return rc;
+        }
+        for (KcEimLoop& P : L)
+            if (!P.done && (rc = kc_eim_keep_phase(h, P, s))) return fail_at(P, rc);
+        if ((rc = kc_eim_wait(h, s))) return rc;
+        for (KcEimLoop& P : L)
+            if (!P.done) kc_eim_end_iter(h, P);
+    }
+    for (KcEimLoop& P : L)
+        if ((rc = kc_eim_form_c(h, P, s))) return fail_at(P, rc);
+    return kc_eim_wait(h, s);
+}
+
+int kc_eim_sample_many(kc_handle* h, const kc_problem* probs, const std::vector<int>& ids,
+                       std::vector<const uint32_t*>& C, std::vector<uint32_t>& nc,
+                       hipStream_t s)
+{
+    std::vector<KcEimLoop> L(ids.size());
+    uint32_t* hw = (uint32_t*)h->pinned("eim.hw", 32 * std::max<size_t>(ids.size(), 1));
+    if (!hw) return h->fail(KC_ENOMEM, "pinned host allocation failed");
+    h->eim_exact = 0;
+    h->eim_refined = 0;
+    for (size_t q = 0; q < ids.size(); ++q) {
+        const kc_problem& p = probs[ids[q]];
+        char pre[32];
+        snprintf(pre, sizeof pre, "bL%zu.", q);
+        L[q].id = ids[q];
+        L[q].pre = pre;
+        L[q].hw = hw + 8 * q;
+        const int rc = kc_eim_init(h, L[q], &p.pts, p.k, &p.eim, nullptr, s);
+        if (rc) return h->fail(rc, "problem %d: %s", ids[q], h->last_error.c_str());
+    }
+    const int rc = kc_eim_loops(h, L, s);
+    if (rc) return rc;
+    C.resize(ids.size());
+    nc.resize(ids.size());
+    for (size_t q = 0; q < ids.size(); ++q) {
+        C[q] = L[q].H;
+        nc[q] = L[q].hw[0];
     }
     return KC_OK;
 }
@@ -653,368 +1203,25 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
     if (prm->max_iters < 1) return h->fail(KC_EINVAL, "max_iters must be >= 1");
     if (k < 1 || k >= (1 << 24)) return h->fail(KC_EINVAL, "k out of range");
     if (!centers || !n_centers || !radius) return h->fail(KC_EINVAL, "outputs NULL");
-    return kc_eim_run(h, pts, k, prm, centers, n_centers, radius, sample, n_sample, iters,
-                      n_iters, (hipStream_t)stream, nullptr, nullptr);
-}
-
-int kc_eim_run(kc_handle* h, const kc_points* pts, int64_t k, const kc_eim_params* prm,
-               int64_t* centers, int64_t* n_centers, double* radius, int64_t* sample,
-               int64_t* n_sample, kc_eim_iter* iters, int32_t* n_iters, hipStream_t s,
-               uint32_t* c_keep, uint32_t* nc_keep)
-{
-    int rc = KC_OK;
+    const hipStream_t s = (hipStream_t)stream;
     const uint32_t n = (uint32_t)pts->n;
     const int d = pts->d;
     const float* X = pts->f32;
     const int64_t ld = pts->ld;
 
-    // constants of Algorithm 2 and Select, in FP64 on the host (natural log)
-    const double L = log((double)n);
-    const double ne = pow((double)n, prm->eps);
-    const double A_S = 9.0 * (double)k * ne * L;
-    const double A_H = 4.0 * ne * L;
-    const double thr = (4.0 / prm->eps) * (double)k * ne * L;
-    int64_t rsel = (int64_t)ceil(prm->phi * L);
-    if (rsel < 1) rsel = 1;
-
-    uint32_t* R = (uint32_t*)h->ws("e.R", 4ull * n);
-    uint32_t* R2 = (uint32_t*)h->ws("e.R2", 4ull * n);
-    uint32_t* S = (uint32_t*)h->ws("e.S", 4ull * n);
-    uint32_t* H = (uint32_t*)h->ws("e.H", 4ull * n);
-    uint32_t* cand = (uint32_t*)h->ws("e.cand", 4ull * n);
-    uint8_t* fS = (uint8_t*)h->ws("e.fS", n);
-    uint8_t* fH = (uint8_t*)h->ws("e.fH", n);
-    uint8_t* fK = (uint8_t*)h->ws("e.fK", n);
-    uint8_t* keep = (uint8_t*)h->ws("e.keep", n);
-    float* lo = (float*)h->ws("e.lo", 4ull * n);
-    float* hi = (float*)h->ws("e.hi", 4ull * n);
-    double* dH = (double*)h->ws("e.dH", 8ull * n);
-    double* tau = (double*)h->ws("e.tau", 16);
-    uint32_t* cnt = (uint32_t*)h->ws("e.cnt", 64);   // [0] dS [1] H [2] cand [3] R [4] FP64 [5] refined-undecided
-    uint32_t* unsure = (uint32_t*)h->ws("e.uns", 4ull * n);
-    double* exm = (double*)h->ws("e.exm", 8ull * n);   // exact minima of the undecided
-    KcCompact C;
-    C.nb_cap = (n + KC_CMP_ITEMS - 1) / KC_CMP_ITEMS + 1;
-    C.blk = (uint32_t*)h->ws("e.blk", 4ull * C.nb_cap);
-    if (!R || !R2 || !S || !H || !cand || !fS || !fH || !fK || !keep || !lo || !hi || !dH ||
-        !tau || !cnt || !unsure || !exm || !C.blk)
-        return h->fail(KC_ENOMEM, "workspace allocation failed");
-
-    // local origin of the points for the MFMA distance passes (every d: the
-    // MFMA variants can run at d <= 8 too): their error bound scales with
-    // the norms, measured from it
-    float* mu = (float*)h->ws("e.mu", 4ull * d);
-    if (!mu) return h->fail(KC_ENOMEM, "workspace allocation failed");
-    kc_local_origin(X, ld, d, n, mu, s);
+    std::vector<KcEimLoop> L(1);
+    L[0].pre = "e.";
+    L[0].hw = (uint32_t*)h->pinned("eim.hw", 32);
+    if (!L[0].hw) return h->fail(KC_ENOMEM, "pinned host allocation failed");
     h->eim_exact = 0;
     h->eim_refined = 0;
-    hipLaunchKernelGGL(k_iota, g1(n), dim3(256), 0, s, R, n);
-    kc_fill_u32((uint32_t*)lo, 0x7F800000u, n, s);
-    kc_fill_u32((uint32_t*)hi, 0x7F800000u, n, s);
-    uint32_t nr = n, ns = 0;
-    int it = 0;
-    while ((double)nr > thr) {
-        if (it >= prm->max_iters) {
-            if (n_iters) *n_iters = it;
-            return h->fail(KC_ENOCONV, "R still has %u points after %d iterations", nr, it);
-        }
-        double pS = A_S / (double)nr;
-        if (pS > 1.0) pS = 1.0;
-        double pH = A_H / (double)nr;
-        if (pH > 1.0) pH = 1.0;
-        hipLaunchKernelGGL(k_eim_draw, g1(nr), dim3(256), 0, s, R, nr, prm->seed, it, pS, pH,
-                           fS, fH, fK);
-        kc_compact(C, fS, R, nr, S + ns, cnt + 0, s);
-        kc_compact(C, fH, R, nr, H, cnt + 1, s);
-        kc_compact(C, fK, R, nr, cand, cnt + 2, s);
-        uint32_t hc[3];
-        if (hipMemcpyAsync(hc, cnt, 12, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return h->fail(KC_EHIP, "readback failed");
-        const uint32_t nds = hc[0], nh = hc[1], nc = hc[2];
-        ns += nds;
-        double tau_h = -INFINITY;
-        uint32_t new_nr = nr;
-        if (ns > 0) {
-            // Select: tau over H (exact FP64 against all of S)
-            if (nh > 0) {
-                kc_fill_u64((u64*)dH, 0x7FF0000000000000ull, nh, s);   // +inf
-                if (d <= KC_EXT_MAXD) {
-                    // the exact pass's tiling: 64 points of H per block, held
-                    // as doubles, S streamed through LDS in slices (the same
-                    // FP64 arithmetic, so the same values)
-                    uint32_t* iota = (uint32_t*)h->ws("e.iota", 4ull * nh);
-                    if (!iota) return h->fail(KC_ENOMEM, "workspace allocation failed");
-                    hipLaunchKernelGGL(k_iota, g1(nh), dim3(256), 0, s, iota, nh);
-                    const uint32_t gx = (nh + 63) / 64;
-                    const uint32_t gy = std::max<uint32_t>(
-                        1, std::min<uint32_t>({(2048 + gx - 1) / gx, ns / 512, 65535u}));
-                    switch (d) {
-#define KC_EXH_CASE(DD)                                                                        \
-    case DD:                                                                                   \
-        hipLaunchKernelGGL(k_eim_exact_split_d<DD>, dim3(gx, gy), dim3(256), 0, s, X, ld, H,     \
-                           iota, nh, S, ns, dH);                                               \
-        break;
-                        KC_EXH_CASE(10)
-                        KC_EXH_CASE(16)
-                        KC_EXH_CASE(32)
-#undef KC_EXH_CASE
-                    default:
-                        hipLaunchKernelGGL(k_eim_exact_split, dim3(gx, gy), dim3(256), 0, s, X,
-                                           ld, d, H, iota, nh, S, ns, dH);
-                    }
-                } else {
-                    const uint32_t splits =
-                        std::max<uint32_t>(1, std::min<uint32_t>(64, ns / 4096));
-                    hipLaunchKernelGGL(k_eim_dist_h, dim3((nh + 3) / 4, splits), dim3(256), 0, s,
-                                       X, ld, d, H, nh, S, ns, dH);
-                }
-                const uint32_t rr = (uint32_t)std::min<int64_t>(rsel, nh);
-                hipLaunchKernelGGL(k_eim_select, dim3(1), dim3(1024), 0, s, dH, nh, rr, tau);
-            } else {
-                kc_fill_u64((u64*)tau, 0xFFF0000000000000ull, 1, s);   // -inf
-            }
-            // Distance pass of the candidates against this iteration's
-            // samples, then the keep / remove decisions: variant 0 computes
-            // canonical FP32 distances on the VALU (d <= 8), 1 the FP32 MFMA,
-            // 2 to 5 split BF16 MFMAs (option mfma_split): 4 or 8 waves per
-            // block with 64 KiB of staged samples, then 8 or 4 waves with 32
-            // KiB; all MFMA ones on the points translated to the local
-            // origin.  All decide exactly alike; the
-            // autotuner measures them once per shape bucket (with the
-            // intervals restored before each of its runs).
-            uint32_t refined_it = 0;
-            auto pass = [&](int var) -> int {
-                refined_it = 0;
-                if (nds > 0 && nc > 0 && var == 0) {
-                    const double u32 = 5.9604644775390625e-8, m = d + 2;
-                    const double g = m * u32 / (1.0 - m * u32);
-                    hipEvent_t ev = h->span_begin(s);
-                    switch (d) {
-#define KC_DIR_CASE(DD)                                                                     \
-    case DD:                                                                                \
-        hipLaunchKernelGGL(k_eim_direct<DD>, g1(nc), dim3(256), 0, s, X, ld, cand, nc,      \
-                           S + ns - nds, nds, g, lo, hi);                                   \
-        break;
-                        KC_DIR_CASE(1)
-                        KC_DIR_CASE(2)
-                        KC_DIR_CASE(3)
-                        KC_DIR_CASE(4)
-                        KC_DIR_CASE(5)
-                        KC_DIR_CASE(6)
-                        KC_DIR_CASE(7)
-                        KC_DIR_CASE(8)
-#undef KC_DIR_CASE
-                    }
-                    h->span_end("eim_dist", ev, 1, s);
-                } else if (nds > 0 && nc > 0) {
-                    const bool split = var >= 2;
-                    const uint32_t kpad = (nds + 15u) & ~15u;
-                    const int dp =
-                        split ? kc_mindist_dpad_split(d, kpad) : kc_mindist_dpad(d, false);
-                    const bool packed = split && kc_split_use_packed(d, kpad);
-                    float* XR = (float*)h->ws("e.XR", 4ull * nc * d);
-                    KcCenters Cs;
-                    Cs.kpad = kpad;
-                    Cs.dp = dp;
-                    Cs.Cf = (float*)h->ws("e.cf", 4ull * kpad * dp);
-                    Cs.cn = (float*)h->ws("e.cn", 4ull * kpad);
-                    Cs.cnl = (float*)h->ws("e.cnl", 4ull * kpad);
-                    Cs.clen = (float*)h->ws("e.clen", 4ull * kpad);
-                    Cs.cmax = (float*)h->ws("e.cmax", 16);
-                    Cs.mu = mu;
-                    if (split) {
-                        Cs.Cb = (uint16_t*)h->ws("e.cbh", 2ull * kpad * dp);
-                        if (packed)
-                            Cs.pk = true;
-                        else
-                            Cs.Cbl = (uint16_t*)h->ws("e.cbl", 2ull * kpad * dp);
-                    } else {
-                        Cs.Ct = (float*)h->ws("e.ct", 4ull * kpad * dp);
-                    }
-                    KcMinOut O;
-                    O.arg = (int32_t*)h->ws("e.arg", 4ull * nc);
-                    O.m1 = (float*)h->ws("e.m1", 4ull * nc);
-                    O.lo2 = (float*)h->ws("e.m2", 4ull * nc);
-                    O.nx = (float*)h->ws("e.nx", 4ull * nc);
-                    // the new samples in ascending order of norm, then staged
-                    uint32_t* kin = (uint32_t*)h->ws("e.skey", 4ull * nds);
-                    uint32_t* kout = (uint32_t*)h->ws("e.skey2", 4ull * nds);
-                    uint32_t* vin = (uint32_t*)h->ws("e.sval", 4ull * nds);
-                    uint32_t* vout = (uint32_t*)h->ws("e.sval2", 4ull * nds);
-                    size_t tbytes = 0;
-                    hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, kin, kout, vin, vout,
-                                                       (int)nds, 0, 32, s);
-                    void* tmp = h->ws("e.sorttmp", tbytes);
-                    if (!XR || !Cs.Cf || (!split && !Cs.Ct) ||
-                        (split && (!Cs.Cb || (!packed && !Cs.Cbl))) ||
-                        !Cs.cn || !Cs.cnl || !Cs.clen || !Cs.cmax || !O.arg || !O.m1 || !O.lo2 ||
-                        !O.nx || !kin || !kout || !vin || !vout || !tmp)
-                        return h->fail(KC_ENOMEM, "workspace allocation failed");
-                    hipLaunchKernelGGL(k_gather_rows, g1((uint64_t)nc * d), dim3(256), 0, s, X,
-                                       ld, d, cand, nc, XR);
-                    hipLaunchKernelGGL(k_sample_norm_keys, g1(nds), dim3(256), 0, s, X, ld, d,
-                                       S + ns - nds, nds, mu, kin, vin);
-                    if (hipcub::DeviceRadixSort::SortPairs(tmp, tbytes, kin, kout, vin, vout,
-                                                           (int)nds, 0, 32, s) != hipSuccess) {
-                        (void)hipGetLastError();
-                        return h->fail(KC_EHIP, "sample sort failed");
-                    }
-                    kc_stage_centers(X, nullptr, ld, d, n, nullptr, vout, nds, nullptr, Cs,
-                                     h->status_word, s);
-                    hipEvent_t ev = h->span_begin(s);
-                    // d(x, S) needs the smallest distance's bounds only
-                    kc_mindist(XR, nullptr, nullptr, d, nc, d, Cs, O, false, s,
-                               (var == 3 || var == 4) ? 8 : 4, var >= 4 ? 32 : 64);
-                    h->span_end("eim_dist", ev, 1, s);
-                    hipLaunchKernelGGL(k_eim_bounds, g1(nc), dim3(256), 0, s, nc, d, cand, O,
-                                       Cs, lo, hi);
-                }
-                // keep / remove
-                kc_fill_u32(cnt + 4, 0u, 1, s);
-                hipLaunchKernelGGL(k_eim_decide, g1(nc), dim3(256), 0, s, nc, cand, lo, hi, tau,
-                                   keep, unsure, cnt + 4);
-                if (d <= KC_EXT_MAXD) {
-                    // the undecided count sizes the split pass: candidate
-                    // groups of 64 times slices of S, about 2048 blocks in all
-                    uint32_t nu = 0;
-                    int rc3 = kc_read_u32(h, cnt + 4, &nu, s);
-                    if (rc3) return rc3;
-                    const uint32_t* uns = unsure;
-                    if (var > 0 && nu > 0 && (uint64_t)nu * ns >= (1ull << 22)) {
-                        // the MFMA pass's undecided: canonical FP32 first
-                        refined_it = nu;   // the last run's count stands
-                        uint32_t* rmin = (uint32_t*)h->ws("e.rmin", 4ull * nu);
-                        uint32_t* uns2 = (uint32_t*)h->ws("e.uns2", 4ull * nu);
-                        if (!rmin || !uns2) return h->fail(KC_ENOMEM, "workspace allocation failed");
-                        const uint32_t gx = (nu + 63) / 64;
-                        const uint32_t gy = std::max<uint32_t>(
-                            1, std::min<uint32_t>({(2048 + gx - 1) / gx, ns / 512, 65535u}));
-                        kc_fill_u32(rmin, 0x7F800000u, nu, s);   // +inf
-                        kc_fill_u32(cnt + 5, 0u, 1, s);
-                        switch (d) {
-#define KC_RFS_CASE(DD)                                                                        \
-    case DD:                                                                                   \
-        hipLaunchKernelGGL(k_eim_refine_split<DD>, dim3(gx, gy), dim3(256), 0, s, X, ld, d,     \
-                           cand, unsure, nu, S, ns, rmin);                                     \
-        break;
-                            KC_RFS_CASE(2)
-                            KC_RFS_CASE(3)
-                            KC_RFS_CASE(8)
-                            KC_RFS_CASE(10)
-                            KC_RFS_CASE(16)
-                            KC_RFS_CASE(32)
-#undef KC_RFS_CASE
-                        default:
-                            hipLaunchKernelGGL(k_eim_refine_split<0>, dim3(gx, gy), dim3(256), 0,
-                                               s, X, ld, d, cand, unsure, nu, S, ns, rmin);
-                        }
-                        const double u32 = 5.9604644775390625e-8, m = d + 2;
-                        hipLaunchKernelGGL(k_eim_refine_finish, g1(nu), dim3(256), 0, s, cand,
-                                           unsure, nu, rmin, m * u32 / (1.0 - m * u32), d, tau,
-                                           keep, lo, hi, uns2, cnt + 5);
-                        // the FP64 pass takes what is still undecided
-                        hipMemcpyAsync(cnt + 4, cnt + 5, 4, hipMemcpyDeviceToDevice, s);
-                        rc3 = kc_read_u32(h, cnt + 5, &nu, s);
-                        if (rc3) return rc3;
-                        uns = uns2;
-                    }
-                    if (nu > 0) {
-                        const uint32_t gx = (nu + 63) / 64;
-                        const uint32_t gy = std::max<uint32_t>(
-                            1, std::min<uint32_t>({(2048 + gx - 1) / gx, ns / 512, 65535u}));
-                        kc_fill_u64((u64*)exm, 0x7FF0000000000000ull, nu, s);   // +inf
-                        switch (d) {
-#define KC_EXS_CASE(DD)                                                                       \
-    case DD:                                                                                  \
-        hipLaunchKernelGGL(k_eim_exact_split_d<DD>, dim3(gx, gy), dim3(256), 0, s, X, ld, cand, \
-                           uns, nu, S, ns, exm);                                              \
-        break;
-                            KC_EXS_CASE(10)
-                            KC_EXS_CASE(16)
-                            KC_EXS_CASE(32)
-#undef KC_EXS_CASE
-                        default:
-                            hipLaunchKernelGGL(k_eim_exact_split, dim3(gx, gy), dim3(256), 0, s,
-                                               X, ld, d, cand, uns, nu, S, ns, exm);
-                        }
-                        hipLaunchKernelGGL(k_eim_exact_finish, g1(nu), dim3(256), 0, s, cand,
-                                           uns, nu, exm, tau, keep, lo, hi);
-                    }
-                } else {
-                    hipLaunchKernelGGL(k_eim_exact, dim3(2048), dim3(256), 0, s, X, ld, d, cand,
-                                       unsure, cnt + 4, S, ns, tau, keep, lo, hi);
-                }
-                const hipError_t e = hipGetLastError();
-                return e == hipSuccess ? KC_OK
-                                       : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
-            };
-            const bool feas[6] = {d <= KC_EIM_DIRECT_MAXD, true, h->mfma_split,
-                                  h->mfma_split, h->mfma_split, h->mfma_split};
-            char tkey[96];
-            snprintf(tkey, sizeof tkey, "eim/%d/%d/%d", d, (int)floor(2.0 * log2((double)nc + 1)),
-                     (int)floor(2.0 * log2((double)nds + 1)));
-            const bool tuning = h->autotune && nds > 0 && nc > 0 && !h->tuned.count(tkey);
-            if (tuning) {   // the intervals every measured run starts from
-                float* lo0 = (float*)h->ws("e.lo0", 4ull * n);
-                float* hi0 = (float*)h->ws("e.hi0", 4ull * n);
-                if (!lo0 || !hi0) return h->fail(KC_ENOMEM, "workspace allocation failed");
-                hipMemcpyAsync(lo0, lo, 4ull * n, hipMemcpyDeviceToDevice, s);
-                hipMemcpyAsync(hi0, hi, 4ull * n, hipMemcpyDeviceToDevice, s);
-                rc = h->tune(tkey, 6, feas, s, [&](int var) {
-                    hipMemcpyAsync(lo, lo0, 4ull * n, hipMemcpyDeviceToDevice, s);
-                    hipMemcpyAsync(hi, hi0, 4ull * n, hipMemcpyDeviceToDevice, s);
-                    return pass(var);
-                });
-            } else if (nds > 0 && nc > 0) {
-                rc = h->tune(tkey, 6, feas, s, pass);
-            } else {
-                rc = pass(1);
-            }
-            if (rc) return rc;
-            h->eim_refined += refined_it;
-            kc_compact(C, keep, cand, nc, R2, cnt + 3, s);
-            std::swap(R, R2);
-            uint32_t rc2[2];
-            if (hipMemcpyAsync(rc2, cnt + 3, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipMemcpyAsync(&tau_h, tau, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess)
-                return h->fail(KC_EHIP, "readback failed");
-            new_nr = rc2[0];
-            h->eim_exact += rc2[1];
-        }
-        if (iters) {
-            kc_eim_iter& rec = iters[it];
-            rec.r_size = nr;
-            rec.ds_size = nds;
-            rec.h_size = nh;
-            rec.s_size = ns;
-            rec.tau = tau_h;
-            rec.p_s = pS;
-            rec.p_h = pH;
-        }
-        nr = new_nr;
-        ++it;
-    }
-    if (n_iters) *n_iters = it;
-
-    // C = S u R, ascending: mark and compact the index range
-    uint8_t* mark = fS;
-    uint32_t* Cidx = H;
-    hipMemsetAsync(mark, 0, n, s);
-    if (ns) hipLaunchKernelGGL(k_mark, g1(ns), dim3(256), 0, s, S, ns, mark);
-    if (nr) hipLaunchKernelGGL(k_mark, g1(nr), dim3(256), 0, s, R, nr, mark);
-    kc_compact(C, mark, nullptr, n, Cidx, cnt + 5, s);
-    uint32_t nc = 0;
-    rc = kc_read_u32(h, cnt + 5, &nc, s);
+    if ((rc = kc_eim_init(h, L[0], pts, k, prm, iters, s))) return rc;
+    rc = kc_eim_loops(h, L, s);
+    if (n_iters) *n_iters = L[0].it;
     if (rc) return rc;
+    const uint32_t nc = L[0].hw[0];
+    const uint32_t* Cidx = L[0].H;
     if (n_sample) *n_sample = nc;
-    if (c_keep) {   // the caller runs the final Gonzalez (a batch's shared launches)
-        hipMemcpyAsync(c_keep, Cidx, 4ull * nc, hipMemcpyDeviceToDevice, s);
-        *nc_keep = nc;
-        const hipError_t e = hipGetLastError();
-        return e == hipSuccess ? KC_OK : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
-    }
     int64_t* C64 = sample ? sample : (int64_t*)h->ws("e.C64", 8ull * nc);
     if (!C64) return h->fail(KC_ENOMEM, "workspace allocation failed");
     hipLaunchKernelGGL(k_u32_to_i64, g1(nc), dim3(256), 0, s, Cidx, nc, C64);
@@ -1059,5 +1266,6 @@ int kc_eim_run(kc_handle* h, const kc_points* pts, int64_t k, const kc_eim_param
     kc_gon_finish(RG, centers, n_centers, nullptr, nullptr, nullptr, C64, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
+    (void)n;
     return kc_assign_run(h, pts, centers, (uint32_t)k, n_centers, nullptr, radius, s, "e3.");
 }

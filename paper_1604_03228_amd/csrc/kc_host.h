@@ -115,6 +115,15 @@ struct kc_handle {
     // run()'s status.
     int tune(const std::string& key, int nvar, const bool* feasible, hipStream_t s,
              const std::function<int(int)>& run);
+    // The variant tune() would run for `key` without measuring anything
+    // (forced, cached or first feasible; -1 if none is feasible); *measure is
+    // set when tune() would measure the variants first.
+    int choice(const std::string& key, int nvar, const bool* feasible, hipStream_t s,
+               bool* measure);
+    // Pinned host memory of at least `bytes` under `name` (hipHostMalloc),
+    // for readbacks that several queued copies fill before one wait.
+    // Growing it waits for the device first.  NULL on failure.
+    void* pinned(const std::string& name, size_t bytes);
     // Co-resident blocks of resident variant v for dimension d (0: none),
     // lowered to resident_cap when that is set.
     int resident_max(int d, int v);
@@ -189,14 +198,14 @@ int kc_gonzalez_bf16(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
                      int64_t* centers, double* radius_trace, int64_t* n_chosen,
                      hipStream_t s);
 
-// EIM (Algorithm 2 with Select, then Gonzalez on the sample C and the
-// covering radius), arguments checked by the caller.  With c_keep (device,
-// n entries) it stops once C is formed: C's indices, ascending, go to
-// c_keep and |C| to *nc_keep, and centers / radius are not written.
-int kc_eim_run(kc_handle* h, const kc_points* pts, int64_t k, const kc_eim_params* prm,
-               int64_t* centers, int64_t* n_centers, double* radius, int64_t* sample,
-               int64_t* n_sample, kc_eim_iter* iters, int32_t* n_iters, hipStream_t s,
-               uint32_t* c_keep, uint32_t* nc_keep);
+// EIM's sampling loops (Algorithm 2 with Select) of the problems probs[ids[q]]
+// (arguments checked by the caller), in lockstep: one wait per phase for all
+// of them.  On return C[q] (device, in the handle's workspace until its next
+// EIM call) holds problem q's sample C = S u R in ascending order and nc[q]
+// its size; the handle's eim_exact / eim_refined count over all of them.
+int kc_eim_sample_many(kc_handle* h, const kc_problem* probs, const std::vector<int>& ids,
+                       std::vector<const uint32_t*>& C, std::vector<uint32_t>& nc,
+                       hipStream_t s);
 
 // Gonzalez in one workgroup (kc_block.hip): whether d has an instantiation
 // and n points fit its lanes; the launch (keys and min-distances as the
