@@ -147,7 +147,8 @@ __device__ __forceinline__ uint16_t kc_f32_to_bf16_rne(float t)
 template <int MODE, int KS, bool LAB, int W>
 __global__ __launch_bounds__(W * 64) void k_mindist_mfma(
     const float* __restrict__ X, const uint16_t* __restrict__ Xb, const float* __restrict__ ex,
-    int64_t ld, uint32_t n, int d, float gm, KcCenters C, uint32_t chunk, KcMinOut O)
+    int64_t ld, uint32_t n, int d, float gm, KcCenters C, uint32_t chunk, KcMinOut O,
+    const uint32_t* __restrict__ rows, const uint32_t* __restrict__ n_dev)
 {
     constexpr bool BF = MODE != KC_MD_F32;     // BF16 MFMA instructions
     constexpr bool SP = MODE == KC_MD_SPLIT;   // high and low parts
@@ -168,6 +169,11 @@ __global__ __launch_bounds__(W * 64) void k_mindist_mfma(
     const uint16_t* __restrict__ Cb = C.Cb;
     const uint32_t kpad = C.kpad;
 
+    if (n_dev) {   // a device-side count (a pass over listed rows)
+        const uint32_t nd = *n_dev;
+        n = nd < n ? nd : n;
+        if ((uint64_t)blockIdx.x * W * 16 * KC_MD_PT >= n) return;   // the whole block
+    }
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int col = lane & 15, grp = lane >> 4;
@@ -181,8 +187,9 @@ __global__ __launch_bounds__(W * 64) void k_mindist_mfma(
     float nxp[KC_MD_PT];
 #pragma unroll
     for (int pt = 0; pt < KC_MD_PT; ++pt) {
-        const uint64_t p = p0 + pt * 16 + col;
-        const bool ok = p < n;
+        const uint64_t p0r = p0 + pt * 16 + col;
+        const bool ok = p0r < n;
+        const uint64_t p = (rows && ok) ? (uint64_t)rows[p0r] : p0r;   // the row read
         nxp[pt] = 0.f;
         if (MODE == KC_MD_F32) {
 #pragma unroll
@@ -262,7 +269,7 @@ __global__ __launch_bounds__(W * 64) void k_mindist_mfma(
         ut[pt] = __builtin_inff();
         if (LAB) {
             const uint64_t p = p0 + pt * 16 + col;
-            const float e = (RB && ex && p < n) ? ex[p] : 0.f;
+            const float e = (RB && ex && p < n) ? ex[rows ? (uint64_t)rows[p] : p] : 0.f;
             P1[pt] = (2.f * gm * ap[pt] + 2.f * e) * (1.f + 1e-6f);
             P2[pt] = 2.f * ap[pt] * (1.f + 1e-6f);
         }
@@ -454,46 +461,48 @@ __global__ __launch_bounds__(W * 64) void k_mindist_mfma(
 // center staging: compact FP32 / BF16 rows [kpad][DP], norms (+inf padding),
 // and the maxima |c| and e_c used by the error bound.
 
-__global__ void k_stage_centers(const float* __restrict__ X, const uint16_t* __restrict__ Xb,
-                                int64_t ld, int d, uint32_t n, const int64_t* __restrict__ idx,
-                                const uint32_t* __restrict__ idx32, uint32_t k,
-                                const int64_t* __restrict__ k_dev, KcCenters C,
-                                uint32_t* __restrict__ status)
+// One wave per center: lanes over the row's K positions, the norms reduced
+// over the wave (any order: the bounds cover FP32 sums in any order).
+__global__ __launch_bounds__(256) void k_stage_centers(
+    const float* __restrict__ X, const uint16_t* __restrict__ Xb, int64_t ld, int d, uint32_t n,
+    const int64_t* __restrict__ idx, const uint32_t* __restrict__ idx32, uint32_t k,
+    const int64_t* __restrict__ k_dev, KcCenters C, uint32_t* __restrict__ status)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const uint32_t kpad = C.kpad;
     const int dp = C.dp;
-    if (i >= kpad) return;
+    if (i >= kpad) return;   // the whole wave
     if (k_dev && (int64_t)k > *k_dev) k = (uint32_t)(*k_dev < 0 ? 0 : *k_dev);
-    int64_t ri = 0;
-    if (i < k) {
-        ri = idx ? idx[i] : (int64_t)idx32[i];
-        if (ri < 0 || ri >= (int64_t)n) {   // invalid index: report, stay in bounds
-            atomicOr(status, 4u);
-            ri = 0;
-        }
-    }
+    const uint64_t row = (uint64_t)i * dp;
     if (i >= k) {
-        for (int j = 0; j < dp; ++j) {
-            if (C.Cf) C.Cf[(uint64_t)i * dp + j] = 0.f;
-            if (C.Ct) C.Ct[(uint64_t)i * dp + j] = 0.f;
-            if (C.Cb) C.Cb[(uint64_t)i * dp + j] = 0;
-            if (C.Cbl) C.Cbl[(uint64_t)i * dp + j] = 0;
+        for (int j = lane; j < dp; j += 64) {
+            if (C.Cf) C.Cf[row + j] = 0.f;
+            if (C.Ct) C.Ct[row + j] = 0.f;
+            if (C.Cb) C.Cb[row + j] = 0;
+            if (C.Cbl) C.Cbl[row + j] = 0;
         }
-        C.cn[i] = __builtin_inff();
-        C.cnl[i] = __builtin_inff();
-        C.clen[i] = 0.f;
-        if (C.cerr) C.cerr[i] = 0.f;
+        if (lane == 0) {
+            C.cn[i] = __builtin_inff();
+            C.cnl[i] = __builtin_inff();
+            C.clen[i] = 0.f;
+            if (C.cerr) C.cerr[i] = 0.f;
+        }
         return;
+    }
+    int64_t ri = idx ? idx[i] : (int64_t)idx32[i];
+    if (ri < 0 || ri >= (int64_t)n) {   // invalid index: report, stay in bounds
+        if (lane == 0) atomicOr(status, 4u);
+        ri = 0;
     }
     const uint64_t r = (uint64_t)ri;
     double nn = 0.0, ee = 0.0, nb = 0.0;
     float nf = 0.f;
     const bool split = C.Cbl != nullptr || C.pk;
-    for (int j = 0; j < dp; ++j) {
+    for (int j = lane; j < dp; j += 64) {
         const float v = j < d ? X[r * ld + j] : 0.f;
-        if (C.Cf) C.Cf[(uint64_t)i * dp + j] = v;
-        if (C.Ct) C.Ct[(uint64_t)i * dp + j] = (C.mu && j < d) ? v - C.mu[j] : v;
+        if (C.Cf) C.Cf[row + j] = v;
+        if (C.Ct) C.Ct[row + j] = (C.mu && j < d) ? v - C.mu[j] : v;
         if (C.pk) {
             // packed row [h | l | h | 0]: position j takes part j / d of
             // coordinate j mod d
@@ -502,8 +511,7 @@ __global__ void k_stage_centers(const float* __restrict__ X, const uint16_t* __r
             const float u = part < 3 ? X[r * ld + jj] : 0.f;
             const float t = (C.mu && part < 3) ? u - C.mu[jj] : u;
             const uint16_t hh = kc_f32_to_bf16_rne(t);
-            C.Cb[(uint64_t)i * dp + j] =
-                part == 1 ? kc_f32_to_bf16_rne(t - kc_bf16_to_f32(hh)) : hh;
+            C.Cb[row + j] = part == 1 ? kc_f32_to_bf16_rne(t - kc_bf16_to_f32(hh)) : hh;
             if (part == 0) {
                 nf = __builtin_fmaf(t, t, nf);
                 nn += (double)t * (double)t;
@@ -512,13 +520,13 @@ __global__ void k_stage_centers(const float* __restrict__ X, const uint16_t* __r
             // high and low BF16 parts of the translated value
             const float t = (C.mu && j < d) ? v - C.mu[j] : v;
             const uint16_t hh = kc_f32_to_bf16_rne(t);
-            C.Cb[(uint64_t)i * dp + j] = hh;
-            C.Cbl[(uint64_t)i * dp + j] = kc_f32_to_bf16_rne(t - kc_bf16_to_f32(hh));
+            C.Cb[row + j] = hh;
+            C.Cbl[row + j] = kc_f32_to_bf16_rne(t - kc_bf16_to_f32(hh));
             nf = __builtin_fmaf(t, t, nf);
             nn += (double)t * (double)t;
         } else if (C.Cb) {
             const uint16_t h = j < d ? Xb[r * ld + j] : (uint16_t)0;
-            C.Cb[(uint64_t)i * dp + j] = h;
+            C.Cb[row + j] = h;
             const float f = kc_bf16_to_f32(h);
             nf = __builtin_fmaf(f, f, nf);
             nb += (double)f * (double)f;
@@ -531,6 +539,13 @@ __global__ void k_stage_centers(const float* __restrict__ X, const uint16_t* __r
             nn += (double)t * (double)t;
         }
     }
+    for (int off = 32; off >= 1; off >>= 1) {
+        nf += __shfl_xor(nf, off, 64);
+        nn += __shfl_xor(nn, off, 64);
+        nb += __shfl_xor(nb, off, 64);
+        ee += __shfl_xor(ee, off, 64);
+    }
+    if (lane != 0) return;
     // the norm used in v: of the values fed to the MFMA, in FP32 as the
     // kernel's error bound assumes; |c| and e_c rounded up
     const bool bf_in = C.Cb && !split;
@@ -674,6 +689,64 @@ __global__ void k_radius_candidates(uint32_t n, const float* __restrict__ hi,
     const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     const float L = *lo_max;
     kc_block_append(p < n && hi[p] >= L, p, list, nlist);
+}
+
+// Second pass of an assignment on BF16 inputs, over the points the first
+// one listed (entry q: row list[q]): the MFMA pass on their FP32 rows (O2,
+// C2) bounds them again, without the BF16 rounding radii.  A label it
+// certifies is written; an uncertain one lists the row for FP64.  Its lower
+// bounds raise lo_max (still a lower bound of the radius).
+__global__ void k_assign_refine_epilogue(const uint32_t* __restrict__ list,
+                                         const uint32_t* __restrict__ nlist, uint32_t cap, int d,
+                                         KcMinOut O2, KcCenters C2, int32_t* __restrict__ labels,
+                                         float* __restrict__ hi2, uint32_t* __restrict__ list2,
+                                         uint32_t* __restrict__ nlist2, float* __restrict__ lo_max)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nq = min(*nlist, cap);
+    if ((uint64_t)blockIdx.x * blockDim.x >= nq) return;   // the whole block
+    float lo_f = 0.f;
+    bool need = false;
+    uint32_t p = 0;
+    if (q < nq) {
+        p = list[q];
+        const KcMdBounds B = kc_md_bounds(O2, q, nullptr, C2, d, labels != nullptr);
+        if (labels) {
+            if (B.lo_other > B.hi) labels[p] = O2.arg[q];
+            else need = true;
+        }
+        hi2[q] = (float)B.hi * (1.f + 1e-6f);
+        lo_f = (float)B.lo_min * (1.f - 1e-6f);
+    }
+    kc_block_append(need, p, list2, nlist2);
+    __shared__ float red[4];
+    float v = lo_f;
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float r = red[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmaxf(r, red[w]);
+        const float cur = __uint_as_float(__hip_atomic_load(
+            (const uint32_t*)lo_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (r > cur) kc_atomic_max_f32_nonneg(lo_max, r);
+    }
+}
+
+// listed rows whose second-pass upper bound reaches the raised lower bound
+// may attain the radius: FP64 for them; every point not listed by the first
+// pass already has an upper bound below it
+__global__ void k_assign_refine_radius(const uint32_t* __restrict__ list,
+                                       const uint32_t* __restrict__ nlist, uint32_t cap,
+                                       const float* __restrict__ hi2,
+                                       const float* __restrict__ lo_max,
+                                       uint32_t* __restrict__ list2, uint32_t* __restrict__ nlist2)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nq = min(*nlist, cap);
+    if ((uint64_t)blockIdx.x * blockDim.x >= nq) return;
+    const float L = *lo_max;
+    kc_block_append(q < nq && hi2[q] >= L, q < nq ? list[q] : 0u, list2, nlist2);
 }
 
 // Exact FP64 nearest center (lowest position on ties) of every listed point,
@@ -944,7 +1017,7 @@ static uint32_t kc_mindist_chunk(int dp_rows, int mode, uint32_t kpad, uint32_t 
 
 void kc_mindist(const float* X, const uint16_t* Xb, const float* ex, int64_t ld, uint32_t n,
                 int d, const KcCenters& C, const KcMinOut& O, bool lab, hipStream_t s, int waves,
-                int lds_kib)
+                int lds_kib, const uint32_t* rows, const uint32_t* n_dev)
 {
     if (lds_kib != 32) lds_kib = 64;
     if (waves != 8) waves = 4;
@@ -953,10 +1026,10 @@ void kc_mindist(const float* X, const uint16_t* Xb, const float* ex, int64_t ld,
                      : C.Cbl ? KC_MD_SPLIT
                              : KC_MD_F32;
     const bool bf = mode != KC_MD_F32;
-    const int rows = mode == KC_MD_SPLITP ? C.dp : kc_mindist_dpad(d, bf);
+    const int klen = mode == KC_MD_SPLITP ? C.dp : kc_mindist_dpad(d, bf);   // staged row
     const int ks = mode == KC_MD_SPLITP ? C.dp / 32 : kc_mindist_ksteps(d, bf);
-    const uint32_t chunk = kc_mindist_chunk(rows, mode, C.kpad, (uint32_t)lds_kib);
-    const int dp = kc_md_pitch(mode, rows);
+    const uint32_t chunk = kc_mindist_chunk(klen, mode, C.kpad, (uint32_t)lds_kib);
+    const int dp = kc_md_pitch(mode, klen);
     const size_t smem = (size_t)chunk * (mode == KC_MD_BF16 ? 16 : 12) +
                         (size_t)chunk * dp * kc_md_elem_bytes(mode);
     const uint32_t per_block = (uint32_t)waves * 16 * kc_md_pt(mode, ks);
@@ -965,10 +1038,10 @@ void kc_mindist(const float* X, const uint16_t* Xb, const float* ex, int64_t ld,
 #define KC_LAUNCH_W(M, K, WW)                                                              \
     if (lab)                                                                               \
         hipLaunchKernelGGL((k_mindist_mfma<M, K, true, WW>), grid, block, smem, s, X, Xb, ex, \
-                           ld, n, d, gm, C, chunk, O);                                     \
+                           ld, n, d, gm, C, chunk, O, rows, n_dev);                        \
     else                                                                                   \
         hipLaunchKernelGGL((k_mindist_mfma<M, K, false, WW>), grid, block, smem, s, X, Xb,  \
-                           ex, ld, n, d, gm, C, chunk, O);
+                           ex, ld, n, d, gm, C, chunk, O, rows, n_dev);
 #define KC_LAUNCH(M, K)         \
     if (waves == 8) {           \
         KC_LAUNCH_W(M, K, 8)    \
@@ -1017,8 +1090,8 @@ void kc_stage_centers(const float* X, const uint16_t* Xb, int64_t ld, int d, uin
                       const int64_t* k_dev, const KcCenters& C, uint32_t* status, hipStream_t s)
 {
     kc_fill_u32((uint32_t*)C.cmax, 0u, 2, s);
-    hipLaunchKernelGGL(k_stage_centers, dim3((C.kpad + 255) / 256), dim3(256), 0, s, X, Xb, ld,
-                       d, n, idx, idx32, k, k_dev, C, status);
+    hipLaunchKernelGGL(k_stage_centers, dim3((C.kpad + 3) / 4), dim3(256), 0, s, X, Xb, ld, d, n,
+                       idx, idx32, k, k_dev, C, status);
 }
 
 void kc_local_origin(const float* X, int64_t ld, int d, uint32_t n, float* mu, hipStream_t s)
@@ -1069,7 +1142,8 @@ bool kc_radius_direct(uint32_t n, int d, const float* X, int64_t ld, const float
 void kc_assign_finish(uint32_t n, int d, const float* X, int64_t ld, const KcCenters& C,
                       uint32_t k, const int64_t* k_dev, const KcMinOut& O, const float* ex,
                       int32_t* labels, float* hi, uint32_t* list, uint32_t* nlist,
-                      float* lo_max, double* radius2, double* radius_out, hipStream_t s)
+                      float* lo_max, double* radius2, double* radius_out, hipStream_t s,
+                      const KcAssignRefine* R2)
 {
     kc_fill_u32(nlist, 0u, 1, s);
     kc_fill_u32((uint32_t*)lo_max, 0u, 1, s);
@@ -1078,6 +1152,22 @@ void kc_assign_finish(uint32_t n, int d, const float* X, int64_t ld, const KcCen
     hipLaunchKernelGGL(k_assign_epilogue, g, dim3(256), 0, s, n, d, O, ex, C, labels, hi, list,
                        nlist, lo_max);
     hipLaunchKernelGGL(k_radius_candidates, g, dim3(256), 0, s, n, hi, lo_max, list, nlist);
-    kc_rescore_f64(X, ld, d, C.Cf, C.dp, k, k_dev, list, nlist, 2 * n, labels, radius2, s);
+    if (!R2) {
+        kc_rescore_f64(X, ld, d, C.Cf, C.dp, k, k_dev, list, nlist, 2 * n, labels, radius2, s);
+    } else {
+        // the listed points again, on their FP32 rows (up to 2n entries: a
+        // point can be listed as ambiguous and as a radius candidate)
+        const uint32_t cap = 2 * n;
+        const dim3 g2((cap + 255) / 256);
+        kc_fill_u32(R2->nlist, 0u, 1, s);
+        kc_mindist(X, nullptr, nullptr, ld, cap, d, R2->C, R2->O, labels != nullptr, s, 4, 64,
+                   list, nlist);
+        hipLaunchKernelGGL(k_assign_refine_epilogue, g2, dim3(256), 0, s, list, nlist, cap, d,
+                           R2->O, R2->C, labels, R2->hi, R2->list, R2->nlist, lo_max);
+        hipLaunchKernelGGL(k_assign_refine_radius, g2, dim3(256), 0, s, list, nlist, cap, R2->hi,
+                           lo_max, R2->list, R2->nlist);
+        kc_rescore_f64(X, ld, d, C.Cf, C.dp, k, k_dev, R2->list, R2->nlist, 2 * cap, labels,
+                       radius2, s);
+    }
     hipLaunchKernelGGL(k_sqrt_out, dim3(1), dim3(64), 0, s, radius2, radius_out);
 }

@@ -264,9 +264,13 @@ int kc_mindist_dpad_split(int d, uint32_t kpad);
 // pass); ex: the points' BF16 rounding radii (BF16 passes); waves: 4 or 8
 // waves per block; lds_kib: 64 or 32 KiB of staged centers per block (more
 // blocks per CU, more chunks); the results depend on neither.
+// With `rows`, output entry p reads row rows[p]; with `n_dev`, the entries
+// are min(n, *n_dev) (a device-side count: the grid covers n, blocks past
+// the count leave at once).
 void kc_mindist(const float* X, const uint16_t* Xb, const float* ex, int64_t ld, uint32_t n,
                 int d, const KcCenters& C, const KcMinOut& O, bool lab, hipStream_t s,
-                int waves = 4, int lds_kib = 64);
+                int waves = 4, int lds_kib = 64, const uint32_t* rows = nullptr,
+                const uint32_t* n_dev = nullptr);
 void kc_stage_centers(const float* X, const uint16_t* Xb, int64_t ld, int d, uint32_t n,
                       const int64_t* idx, const uint32_t* idx32, uint32_t k,
                       const int64_t* k_dev, const KcCenters& C, uint32_t* status, hipStream_t s);
@@ -284,7 +288,19 @@ bool kc_radius_direct(uint32_t n, int d, const float* X, int64_t ld, const float
                       uint32_t k, const int64_t* k_dev, float* hi, uint32_t* list,
                       uint32_t* nlist, float* lo_max, double* radius2, double* radius_out,
                       hipStream_t s);
+// Second pass of an assignment on BF16 inputs: the points the first pass
+// lists (labels it cannot certify, possible maximisers of the radius) run
+// the MFMA pass again on their FP32 rows, without the BF16 rounding radii;
+// only what that leaves uncertain goes to FP64.
+struct KcAssignRefine {
+    KcCenters C;            // the centers staged from their FP32 rows
+    KcMinOut O;             // per list entry (2n)
+    float* hi = nullptr;    // per list entry (2n)
+    uint32_t* list = nullptr;    // rows for FP64 (4n)
+    uint32_t* nlist = nullptr;
+};
 void kc_assign_finish(uint32_t n, int d, const float* X, int64_t ld, const KcCenters& C,
                       uint32_t k, const int64_t* k_dev, const KcMinOut& O, const float* ex,
                       int32_t* labels, float* hi, uint32_t* list, uint32_t* nlist,
-                      float* lo_max, double* radius2, double* radius_out, hipStream_t s);
+                      float* lo_max, double* radius2, double* radius_out, hipStream_t s,
+                      const KcAssignRefine* R2 = nullptr);

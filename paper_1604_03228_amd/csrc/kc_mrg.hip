@@ -222,15 +222,62 @@ int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, ui
         !C.clen || !O.arg || !O.m1 ||
         !O.lo2 || !O.lob || !O.nx || !hi || !list || !nlist || !lo_max || !r2 || (bf && !ex))
         return h->fail(KC_ENOMEM, "workspace allocation failed");
-    h->last_assign_nlist = nlist;
+    // BF16 inputs: the points their pass lists run again on their FP32 rows
+    // (split BF16 MFMAs, or the FP32 MFMA) against the centers staged from
+    // their FP32 rows, measured from a local origin; FP64 takes the rest
+    KcAssignRefine R2;
+    float* mu2 = nullptr;
+    if (bf) {
+        const bool sp2 = h->mfma_split;
+        const int dp2 = sp2 ? kc_mindist_dpad_split(d, kpad) : kc_mindist_dpad(d, false);
+        const bool pk2 = sp2 && kc_split_use_packed(d, kpad);
+        KcCenters& C2 = R2.C;
+        C2.kpad = kpad;
+        C2.dp = dp2;
+        C2.Cf = (float*)h->ws(pre + "2cf", sizeof(float) * (size_t)kpad * dp2);
+        C2.cn = (float*)h->ws(pre + "2cn", sizeof(float) * kpad);
+        C2.cnl = (float*)h->ws(pre + "2cnl", sizeof(float) * kpad);
+        C2.clen = (float*)h->ws(pre + "2clen", sizeof(float) * kpad);
+        C2.cmax = (float*)h->ws(pre + "2cmax", 16);
+        mu2 = (float*)h->ws(pre + "mu", sizeof(float) * (size_t)d);
+        C2.mu = mu2;
+        if (sp2) {
+            C2.Cb = (uint16_t*)h->ws(pre + "2cb", sizeof(uint16_t) * (size_t)kpad * dp2);
+            if (pk2)
+                C2.pk = true;
+            else
+                C2.Cbl = (uint16_t*)h->ws(pre + "2cbl", sizeof(uint16_t) * (size_t)kpad * dp2);
+        } else {
+            C2.Ct = (float*)h->ws(pre + "2ct", sizeof(float) * (size_t)kpad * dp2);
+        }
+        const size_t cap = 2 * (size_t)n;
+        R2.O.arg = (int32_t*)h->ws(pre + "2arg", sizeof(int32_t) * cap);
+        R2.O.m1 = (float*)h->ws(pre + "2m1", sizeof(float) * cap);
+        R2.O.lo2 = (float*)h->ws(pre + "2lo2", sizeof(float) * cap);
+        R2.O.lob = (float*)h->ws(pre + "2lob", sizeof(float) * cap);
+        R2.O.nx = (float*)h->ws(pre + "2nx", sizeof(float) * cap);
+        R2.hi = (float*)h->ws(pre + "2hi", sizeof(float) * cap);
+        R2.list = (uint32_t*)h->ws(pre + "2list", sizeof(uint32_t) * 2 * cap);
+        R2.nlist = (uint32_t*)h->ws(pre + "2nlist", 16);
+        if (!C2.Cf || !C2.cn || !C2.cnl || !C2.clen || !C2.cmax || !C2.mu ||
+            (sp2 && (!C2.Cb || (!pk2 && !C2.Cbl))) || (!sp2 && !C2.Ct) || !R2.O.arg ||
+            !R2.O.m1 || !R2.O.lo2 || !R2.O.lob || !R2.O.nx || !R2.hi || !R2.list || !R2.nlist)
+            return h->fail(KC_ENOMEM, "workspace allocation failed");
+    }
+    h->last_assign_nlist = bf ? R2.nlist : nlist;
     const std::string key =
         kc_key(("assign:" + pre).c_str(), {pts->f32, pts->bf16, centers, k_dev, labels, radius},
-               {pts->n, d, pts->ld, k, bf, split});
+               {pts->n, d, pts->ld, k, bf, split, h->mfma_split});
     int rc = h->run_graph(key + ":stage", s, [&](hipStream_t st) {
         if (bf) kc_bf16_err(pts->f32, pts->bf16, pts->ld, d, n, ex, st);
         if (mu) kc_local_origin(pts->f32, pts->ld, d, n, mu, st);
         kc_stage_centers(pts->f32, bf ? pts->bf16 : nullptr, pts->ld, d, n, centers, nullptr, k,
                          k_dev, C, h->status_word, st);
+        if (bf) {
+            kc_local_origin(pts->f32, pts->ld, d, n, mu2, st);
+            kc_stage_centers(pts->f32, nullptr, pts->ld, d, n, centers, nullptr, k, k_dev, R2.C,
+                             h->status_word, st);
+        }
     });
     if (rc) return rc;
     if (!labels && !bf && d <= 8) {
@@ -264,7 +311,7 @@ int kc_assign_run(kc_handle* h, const kc_points* pts, const int64_t* centers, ui
     if (rc) return rc;
     return h->run_graph(key + ":finish", s, [&](hipStream_t st) {
         kc_assign_finish(n, d, pts->f32, pts->ld, C, k, k_dev, O, ex, labels, hi, list, nlist,
-                         lo_max, r2, radius, st);
+                         lo_max, r2, radius, st, bf ? &R2 : nullptr);
     });
 }
 

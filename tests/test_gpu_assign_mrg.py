@@ -84,6 +84,28 @@ def test_assign_ties_and_duplicates(kc, orc, mode):
     assert np.array_equal(lab, olab) and R == oR
 
 
+# BF16 inputs: the points whose label or radius bound the BF16 pass leaves
+# open run a second MFMA pass on their FP32 rows (split, packed at 2,048
+# centers, or the FP32 MFMA), FP64 after that; with and without labels
+@pytest.mark.parametrize("d,k", [(3, 100), (16, 2048), (41, 500)])
+@pytest.mark.parametrize("split", [1, 0])
+@pytest.mark.parametrize("labels", [True, False])
+def test_assign_bf16_second_pass(kc, orc, d, k, split, labels):
+    X = W.points_gauss_mixture(12_000, d, 25, 0.0, 100.0, 0.2, 1.0, seed=60 + d)
+    C = np.random.default_rng(d + k).choice(len(X), k, replace=False)
+    h = kc.Handle()
+    h.set_option("mfma_split", split)
+    Xd = torch.from_numpy(X).cuda()
+    B = torch.from_numpy(W.to_bf16_rne(X).view(np.int16)).cuda()
+    lab, r = on_stream(lambda: kc.assign(Xd, torch.from_numpy(C), labels=labels, bf16=B,
+                                         handle=h))
+    assert h.device_status() == 0
+    olab, oR = orc.assign(X, C)
+    assert float(r.item()) == oR
+    if labels:
+        assert np.array_equal(lab.cpu().numpy(), olab)
+
+
 def test_assign_radius_equals_gon(kc, orc):
     X = W.config1()
     c, tr, got = orc.gon(X, 20, 0)
