@@ -1,7 +1,8 @@
 // kc_eim.hip -- the EIM sampling pass (Algorithm 2 with Select, Algorithm 3,
 // and the Section 4.1 changes) on gfx950, followed by Gonzalez on the sample.
 //
-// Per iteration (host-driven, one synchronisation to size the next one):
+// Per iteration (host-driven: phases that only queue work, each followed by
+// one wait whose readback sizes the next; kc_eim_loops below):
 //   k_eim_draw        Philox4x64-10 Bernoulli draws for every x in R: into
 //                     S with probability p_S, into H with probability p_H
 //                     (one counter-based block per point and iteration);
