@@ -325,44 +325,34 @@ __global__ __launch_bounds__(W * 64) void k_mindist_mfma(
             __syncthreads();
         }
 
-        // A operand: centers ct + col, K slice of this lane group; the next
-        // tile's operands load while this tile's MFMAs run
-        float naf[BF ? 1 : KS];
-        kc_v8bf nab[BF ? KS : 1];
-        kc_v8bf nal[SP ? KS : 1];
-        float4 nnc;
-        auto load_a = [&](uint32_t ct) {
+        // A operand: centers ct + col, K slice of this lane group.  Two sets
+        // of registers take turns: the next tile's operands load into one
+        // while the other's MFMAs run (no copies between them)
+        float afA[BF ? 1 : KS], afB[BF ? 1 : KS];
+        kc_v8bf abA[BF ? KS : 1], abB[BF ? KS : 1];
+        kc_v8bf alA[SP ? KS : 1], alB[SP ? KS : 1];
+        float4 ncA, ncB;
+        auto load_a = [&](uint32_t ct, float* af, kc_v8bf* ab, kc_v8bf* al, float4& nc) {
             if (!BF) {
                 const float* cs = (const float*)s_c + (uint64_t)(ct + col) * PITCH;
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks) naf[BF ? 0 : ks] = cs[ks * 4 + grp];
+                for (int ks = 0; ks < KS; ++ks) af[BF ? 0 : ks] = cs[ks * 4 + grp];
             } else {
                 const uint16_t* cs = (const uint16_t*)s_c + (uint64_t)(ct + col) * PITCH;
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks)
-                    nab[BF ? ks : 0] = *(const kc_v8bf*)(cs + ks * 32 + grp * 8);
+                    ab[BF ? ks : 0] = *(const kc_v8bf*)(cs + ks * 32 + grp * 8);
                 if (SP) {
                     const uint16_t* cl = s_cl + (uint64_t)(ct + col) * PITCH;
 #pragma unroll
                     for (int ks = 0; ks < KS; ++ks)
-                        nal[SP ? ks : 0] = *(const kc_v8bf*)(cl + ks * 32 + grp * 8);
+                        al[SP ? ks : 0] = *(const kc_v8bf*)(cl + ks * 32 + grp * 8);
                 }
             }
-            nnc = *(const float4*)(s_norm + ct + grp * 4);
+            nc = *(const float4*)(s_norm + ct + grp * 4);
         };
-        load_a(0);
-        for (uint32_t ct = 0; ct < cn; ct += 16) {
-            float af[BF ? 1 : KS];
-            kc_v8bf ab[BF ? KS : 1];
-            kc_v8bf al[SP ? KS : 1];
-#pragma unroll
-            for (int ks = 0; ks < (BF ? 1 : KS); ++ks) af[ks] = naf[ks];
-#pragma unroll
-            for (int ks = 0; ks < (BF ? KS : 1); ++ks) ab[ks] = nab[ks];
-#pragma unroll
-            for (int ks = 0; ks < (SP ? KS : 1); ++ks) al[ks] = nal[ks];
-            const float4 nc4 = nnc;
-            if (ct + 16 < cn) load_a(ct + 16);
+        auto tile = [&](uint32_t ct, const float* af, const kc_v8bf* ab, const kc_v8bf* al,
+                        const float4 nc4) {
             float4 nl4 = make_float4(0.f, 0.f, 0.f, 0.f), cb4 = nl4, ce4 = nl4;
             if (LAB) {
                 nl4 = *(const float4*)(s_cnl + ct + grp * 4);
@@ -412,6 +402,14 @@ __global__ __launch_bounds__(W * 64) void k_mindist_mfma(
                     best[pt].m1 = kc_max3(kc_max3(best[pt].m1, acc[0], acc[1]), acc[2], acc[3]);
                 }
             }
+        };
+        load_a(0, afA, abA, alA, ncA);
+        for (uint32_t ct = 0; ct < cn; ct += 32) {
+            if (ct + 16 < cn) load_a(ct + 16, afB, abB, alB, ncB);
+            tile(ct, afA, abA, alA, ncA);
+            if (ct + 16 >= cn) break;
+            if (ct + 32 < cn) load_a(ct + 32, afA, abA, alA, ncA);
+            tile(ct + 16, afB, abB, alB, ncB);
         }
         if (CB) {
             // this chunk's bounds: its smallest v -/+ g (a + b_chunk)^2
