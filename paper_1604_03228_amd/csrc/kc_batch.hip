@@ -187,6 +187,8 @@ struct KcBatchGroup {
     double* rad = nullptr;
     std::vector<KcBatchOut> outs;
     const KcBatchOut* outs_d = nullptr;
+    bool bf = false;   // streamed on a BF16 copy the library rounds, exact rescoring
+    KcBf16Run B;
     // stage 2 (MRG problems)
     std::vector<KcUnionJob> uj;
     std::vector<int32_t> blk_job, blk_part;
@@ -258,8 +260,18 @@ static int group_prepare(kc_handle* h, const kc_problem* probs, const std::vecto
         st.push_back(tags[q]);
         sr.push_back(rbase[q]);
     }
-    int rc = kc_plan_gon(h, P + "1.", d, 1024, G.sj, G.R, G.H, s);
+    // A group that streams reads every point at every step: with enough
+    // points the stream runs on a BF16 copy rounded from the FP32 rows (half
+    // the bytes per coordinate) with exact FP32 rescoring of the candidates,
+    // whose centers are the FP32 stream's.  The rescoring adds a fixed cost
+    // per step (about 10 us: at 5 TB/s the bytes of 5e7 / 2 coordinates), so
+    // it pays from n d = 2.5e7 on.
+    uint64_t nd = 0;
+    for (const KcGonJob& j : G.sj) nd += (uint64_t)j.len * (uint64_t)d;
+    G.bf = !strcmp(tag, "s") && nd >= 25000000ull;
+    int rc = kc_plan_gon(h, P + "1.", d, G.bf ? KC_BF_TILE_PTS : 1024, G.sj, G.R, G.H, s);
     if (rc) return rc;
+    if (G.bf && (rc = kc_bf16_alloc(h, P + "1b.", G.R, G.B))) return rc;
     const int nseg = (int)G.sj.size();
     G.rb = (const int64_t*)h->upload(P + "1.rb", sr.data(), 8 * sr.size(), s);
     G.cent = (int64_t*)h->ws(P + "1.cent", 8 * std::max<uint64_t>(G.R.keysum, 1));
@@ -365,12 +377,17 @@ static int group_execute(kc_handle* h, const kc_problem* probs, const KcBatchGro
 {
     const int d = G.d;
     const std::string& P = G.P;
-    int rc = kc_run_gon(h, G.key, G.R, G.H, G.sj, "batch_gon", s, [&](hipStream_t sst) {
-        kc_gon_finish(G.R, G.cent, G.nch, nullptr, G.rad, G.rb, nullptr, sst);
+    auto finish1 = [&](hipStream_t sst) {
+        if (G.bf)
+            kc_bf16_finish(G.R, G.B, G.cent, G.nch, nullptr, G.rad, G.rb, sst);
+        else
+            kc_gon_finish(G.R, G.cent, G.nch, nullptr, G.rad, G.rb, nullptr, sst);
         if (!G.outs.empty())
             hipLaunchKernelGGL(k_batch_out, dim3((unsigned)G.outs.size()), dim3(256), 0, sst,
                                G.outs_d, (int)G.outs.size(), G.cent, G.nch, G.rad);
-    });
+    };
+    int rc = G.bf ? kc_run_bf16(h, G.key + ":bf", G.R, G.B, G.H, G.sj, "batch_gon", s, finish1)
+                  : kc_run_gon(h, G.key, G.R, G.H, G.sj, "batch_gon", s, finish1);
     if (rc || G.mrg_ids.empty()) return rc;
     const int nu = (int)G.uj.size();
     rc = h->run_graph(G.key + kc_hash_str(G.uh) + ":u", s, [&](hipStream_t sst) {

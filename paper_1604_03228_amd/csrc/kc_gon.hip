@@ -73,13 +73,22 @@ void kc_fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s)
 
 // Stage the 64 columns [i0, i0+64) of one segment; all threads of the block
 // call it.  sx, sb: LDS of 64 * (KC_STG_W + 1) entries.
+// BF16 bits of x rounded to nearest, ties to even (finite x).
+__device__ __forceinline__ uint16_t kc_stage_bf16_rne(float x)
+{
+    const uint32_t b = __float_as_uint(x);
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+
+// With xb and no Xb the BF16 copy is the FP32 rows rounded to nearest even
+// (a library-made copy for the BF16 stream).
 __device__ void kc_stage_tile64(const float* __restrict__ X, const uint16_t* __restrict__ Xb,
                                 int64_t ld, int d, uint64_t row0, uint32_t len, uint32_t i0,
                                 float* __restrict__ xs, uint16_t* __restrict__ xb,
                                 float* __restrict__ ex, uint64_t stride, uint64_t base,
                                 float* sx, uint16_t* sb)
 {
-    const bool bf = xb != nullptr && Xb != nullptr;
+    const bool bf = xb != nullptr;
     double ee = 0.0;   // thread p < 64: point i0 + p, coordinates in ascending order
     for (int j0 = 0; j0 < d; j0 += KC_STG_W) {
         const uint32_t w = (uint32_t)min(KC_STG_W, d - j0);
@@ -88,8 +97,9 @@ __device__ void kc_stage_tile64(const float* __restrict__ X, const uint16_t* __r
             const uint32_t p = q / w, j = q - p * w;
             const uint32_t i = i0 + p;
             const uint64_t at = (row0 + (i < len ? i : 0)) * (uint64_t)ld + j0 + j;
-            sx[p * pitch + j] = X[at];
-            if (bf) sb[p * pitch + j] = Xb[at];
+            const float v = X[at];
+            sx[p * pitch + j] = v;
+            if (bf) sb[p * pitch + j] = Xb ? Xb[at] : kc_stage_bf16_rne(v);
         }
         __syncthreads();
         for (uint32_t q = threadIdx.x; q < 64u * w; q += blockDim.x) {

@@ -128,6 +128,37 @@ def test_batch_integer_exact(kc, orc):
             assert np.array_equal(c, o["centers"]) and r == o["radius"]
 
 
+def test_batch_streamed_group_on_bf16_copy(kc, orc):
+    # option resident = 0 streams every group; a streamed group of n d >=
+    # 2.5e7 runs on a BF16 copy the library rounds, with exact rescoring:
+    # its centers and radii equal the FP32 single calls' (both streamed)
+    rng = np.random.default_rng(77)
+    probs = []
+    for i, (n, algo, k) in enumerate([(420_000, "gon", 60), (300_000, "mrg", 40),
+                                      (150_000, "gon", 25)]):
+        X = W.points_gauss_mixture(n, 32, 30, seed=500 + i)
+        pr = dict(X=torch.from_numpy(X).cuda(), Xh=X, algo=algo, k=k)
+        if algo == "mrg":
+            pr["offsets"] = W.partition_offsets(n, 8, 0.5, seed=i)
+        else:
+            pr["first"] = int(rng.integers(0, n))
+        probs.append(pr)
+    h = kc.Handle(resident=False)
+    outs = on_stream(lambda: kc.batch(probs, handle=h))
+    assert h.device_status() == 0
+    for pr, (c, nc, r) in zip(probs, outs):
+        ref = on_stream(lambda: single(kc, pr, h))
+        g = int(nc.item())
+        assert g == ref[1]
+        assert np.array_equal(c.cpu().numpy()[:g], ref[0][:g])
+        assert float(r.item()) == ref[2]
+    # the smallest against the oracle: a replay of its traversal
+    pr, (c, nc, _) = probs[2], outs[2]
+    g = int(nc.item())
+    bad, _, _ = orc.gon_replay(pr["Xh"], pr["k"], c.cpu().numpy()[:g], band(32))
+    assert bad == -1
+
+
 @pytest.mark.slow
 def test_batch_config5_full(kc, orc):
     orc.set_threads(16)
