@@ -3,10 +3,11 @@
 //
 // Per iteration (host-driven: phases that only queue work, each followed by
 // one wait whose readback sizes the next; kc_eim_loops below):
-//   k_eim_draw        Philox4x64-10 Bernoulli draws for every x in R: into
+//   k_eim_split_*     Philox4x64-10 Bernoulli draws for every x in R: into
 //                     S with probability p_S, into H with probability p_H
-//                     (one counter-based block per point and iteration);
-//   compaction        stable scans split R into dS (new samples), H and the
+//                     (one counter-based block per point and iteration,
+//                     recomputed rather than stored); count, scan and
+//                     scatter split R stably into dS (new samples), H and the
 //                     points that stay candidates (not sampled);
 //   k_eim_dist_h      exact FP64 d(h,S)^2 for h in H (split over S, min via
 //                     64-bit atomics on the bits of non-negative doubles);
@@ -51,23 +52,6 @@ __device__ __forceinline__ void kc_philox4x64_10(uint64_t c[4], uint64_t k0, uin
         c[2] = n2;
         c[3] = lo0;
     }
-}
-
-// flags: bit 0 = drawn into S, bit 1 = drawn into H
-__global__ void k_eim_draw(const uint32_t* __restrict__ R, uint32_t nr, uint64_t seed, int it,
-                           double pS, double pH, uint8_t* __restrict__ fS,
-                           uint8_t* __restrict__ fH, uint8_t* __restrict__ fKeep)
-{
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nr) return;
-    uint64_t c[4] = {(uint64_t)R[j], (uint64_t)it, 0ull, 0ull};
-    kc_philox4x64_10(c, seed, 0ull);
-    const double uS = (double)(c[0] >> 11) * 0x1.0p-53;
-    const double uH = (double)(c[1] >> 11) * 0x1.0p-53;
-    const bool s = uS < pS;
-    fS[j] = s;
-    fH[j] = uH < pH;
-    fKeep[j] = !s;   // sampled points always leave R
 }
 
 // ---------------------------------------------------------------------------
@@ -147,9 +131,129 @@ __global__ void k_cmp_scatter(const uint8_t* __restrict__ f, const uint32_t* __r
 }
 
 struct KcCompact {
-    uint32_t* blk = nullptr;   // [nblocks]
+    uint32_t* blk = nullptr;   // [3][nb_cap] block counts / offsets
     uint32_t nb_cap = 0;
 };
+
+// ---------------------------------------------------------------------------
+// An iteration's draws and the split of R in three launches: the draws of
+// a point (counter-based) are recomputed where they are needed instead of
+// stored, and dS, H and the candidates (the points not sampled) are each
+// compacted in R's order.
+
+__device__ __forceinline__ void kc_eim_flags(uint32_t x, uint64_t seed, int it, double pS,
+                                             double pH, bool& s, bool& hh)
+{
+    uint64_t c[4] = {(uint64_t)x, (uint64_t)it, 0ull, 0ull};
+    kc_philox4x64_10(c, seed, 0ull);
+    s = (double)(c[0] >> 11) * 0x1.0p-53 < pS;
+    hh = (double)(c[1] >> 11) * 0x1.0p-53 < pH;
+}
+
+__global__ __launch_bounds__(256) void k_eim_split_count(const uint32_t* __restrict__ R,
+                                                         uint32_t nr, uint64_t seed, int it,
+                                                         double pS, double pH,
+                                                         uint32_t* __restrict__ blk3, uint32_t nb)
+{
+    __shared__ uint32_t red[3][4];
+    const uint32_t base = blockIdx.x * KC_CMP_ITEMS;
+    uint32_t c[3] = {0u, 0u, 0u};
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t i = base + q * 256 + threadIdx.x;
+        if (i < nr) {
+            bool sm, hm;
+            kc_eim_flags(R[i], seed, it, pS, pH, sm, hm);
+            c[0] += sm;
+            c[1] += hm;
+            c[2] += !sm;   // sampled points always leave R
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        for (int off = 32; off >= 1; off >>= 1) c[f] += __shfl_xor(c[f], off, 64);
+        if ((threadIdx.x & 63) == 0) red[f][threadIdx.x >> 6] = c[f];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const uint32_t f = threadIdx.x;
+        blk3[(uint64_t)f * nb + blockIdx.x] = red[f][0] + red[f][1] + red[f][2] + red[f][3];
+    }
+}
+
+// one block of 1024: the three exclusive scans; totals -> count3[0..2]
+__global__ __launch_bounds__(1024) void k_eim_split_scan(uint32_t* __restrict__ blk3,
+                                                         uint32_t nb,
+                                                         uint32_t* __restrict__ count3)
+{
+    __shared__ uint32_t carry;
+    __shared__ uint32_t wsum[16];
+    const int lane = threadIdx.x & 63;
+    for (int f = 0; f < 3; ++f) {
+        uint32_t* blk = blk3 + (uint64_t)f * nb;
+        if (threadIdx.x == 0) carry = 0;
+        __syncthreads();
+        for (uint32_t b0 = 0; b0 < nb; b0 += blockDim.x) {
+            const uint32_t i = b0 + threadIdx.x;
+            const uint32_t v = i < nb ? blk[i] : 0u;
+            uint32_t x = v;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(x, off, 64);
+                if (lane >= off) x += y;
+            }
+            if (lane == 63) wsum[threadIdx.x >> 6] = x;
+            __syncthreads();
+            uint32_t wpre = 0;
+            for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wpre += wsum[w];
+            const uint32_t excl = carry + wpre + x - v;
+            __syncthreads();
+            if (i < nb) blk[i] = excl;
+            if (threadIdx.x == blockDim.x - 1) carry = excl + v;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) count3[f] = carry;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_eim_split_scatter(
+    const uint32_t* __restrict__ R, uint32_t nr, uint64_t seed, int it, double pS, double pH,
+    const uint32_t* __restrict__ blk3, uint32_t nb, uint32_t* __restrict__ outS,
+    uint32_t* __restrict__ outH, uint32_t* __restrict__ outK)
+{
+    __shared__ uint32_t wcnt[3][4];
+    const uint32_t base = blockIdx.x * KC_CMP_ITEMS;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t run[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) run[f] = blk3[(uint64_t)f * nb + blockIdx.x];
+    uint32_t* out[3] = {outS, outH, outK};
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t i = base + q * 256 + threadIdx.x;
+        bool on[3] = {false, false, false};
+        uint32_t x = 0;
+        if (i < nr) {
+            x = R[i];
+            kc_eim_flags(x, seed, it, pS, pH, on[0], on[1]);
+            on[2] = !on[0];
+        }
+        u64 mask[3];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            mask[f] = __ballot(on[f]);
+            if (lane == 0) wcnt[f][w] = __popcll(mask[f]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            uint32_t wpre = 0;
+            for (int v = 0; v < w; ++v) wpre += wcnt[f][v];
+            if (on[f])
+                out[f][run[f] + wpre + __popcll(mask[f] & ((1ull << lane) - 1ull))] = x;
+            run[f] += wcnt[f][0] + wcnt[f][1] + wcnt[f][2] + wcnt[f][3];
+        }
+        __syncthreads();
+    }
+}
 
 static void kc_compact(const KcCompact& C, const uint8_t* f, const uint32_t* in, uint32_t n,
                        uint32_t* out, uint32_t* count, hipStream_t s)
@@ -656,7 +760,7 @@ struct KcEimLoop {
     int64_t rsel = 1;
     uint32_t *R = nullptr, *R2 = nullptr, *S = nullptr, *H = nullptr, *cand = nullptr;
     uint32_t *unsure = nullptr, *uns2 = nullptr, *cnt = nullptr;
-    uint8_t *fS = nullptr, *fH = nullptr, *fK = nullptr, *keep = nullptr;
+    uint8_t *fS = nullptr, *keep = nullptr;   // fS: marks when C is formed
     float *lo = nullptr, *hi = nullptr, *mu = nullptr;
     double* tau = nullptr;
     KcCompact C;
@@ -701,8 +805,6 @@ static int kc_eim_init(kc_handle* h, KcEimLoop& P, const kc_points* pts, int64_t
     P.H = (uint32_t*)h->ws(p + "H", 4ull * n);
     P.cand = (uint32_t*)h->ws(p + "cand", 4ull * n);
     P.fS = (uint8_t*)h->ws(p + "fS", n);
-    P.fH = (uint8_t*)h->ws(p + "fH", n);
-    P.fK = (uint8_t*)h->ws(p + "fK", n);
     P.keep = (uint8_t*)h->ws(p + "keep", n);
     P.lo = (float*)h->ws(p + "lo", 4ull * n);
     P.hi = (float*)h->ws(p + "hi", 4ull * n);
@@ -712,12 +814,12 @@ static int kc_eim_init(kc_handle* h, KcEimLoop& P, const kc_points* pts, int64_t
     P.unsure = (uint32_t*)h->ws(p + "uns", 4ull * n);
     P.uns2 = (uint32_t*)h->ws(p + "uns2", 4ull * n);
     P.C.nb_cap = (n + KC_CMP_ITEMS - 1) / KC_CMP_ITEMS + 1;
-    P.C.blk = (uint32_t*)h->ws(p + "blk", 4ull * P.C.nb_cap);
+    P.C.blk = (uint32_t*)h->ws(p + "blk", 3 * 4ull * P.C.nb_cap);
     // local origin of the points for the MFMA distance passes (every d: the
     // MFMA variants can run at d <= 8 too): their error bound scales with
     // the norms, measured from it
     P.mu = (float*)h->ws(p + "mu", 4ull * P.d);
-    if (!P.R || !P.R2 || !P.S || !P.H || !P.cand || !P.fS || !P.fH || !P.fK || !P.keep ||
+    if (!P.R || !P.R2 || !P.S || !P.H || !P.cand || !P.fS || !P.keep ||
         !P.lo || !P.hi || !P.tau || !P.cnt || !P.unsure || !P.uns2 || !P.C.blk || !P.mu)
         return h->fail(KC_ENOMEM, "workspace allocation failed");
     kc_local_origin(P.X, P.ld, P.d, n, P.mu, s);
@@ -745,11 +847,12 @@ static int kc_eim_draw_phase(kc_handle* h, KcEimLoop& P, hipStream_t s)
     if (P.pS > 1.0) P.pS = 1.0;
     P.pH = P.A_H / (double)P.nr;
     if (P.pH > 1.0) P.pH = 1.0;
-    hipLaunchKernelGGL(k_eim_draw, g1(P.nr), dim3(256), 0, s, P.R, P.nr, P.prm->seed, P.it,
-                       P.pS, P.pH, P.fS, P.fH, P.fK);
-    kc_compact(P.C, P.fS, P.R, P.nr, P.S + P.ns, P.cnt + 0, s);
-    kc_compact(P.C, P.fH, P.R, P.nr, P.H, P.cnt + 1, s);
-    kc_compact(P.C, P.fK, P.R, P.nr, P.cand, P.cnt + 2, s);
+    const uint32_t nb = (P.nr + KC_CMP_ITEMS - 1) / KC_CMP_ITEMS;
+    hipLaunchKernelGGL(k_eim_split_count, dim3(nb), dim3(256), 0, s, P.R, P.nr, P.prm->seed,
+                       P.it, P.pS, P.pH, P.C.blk, nb);
+    hipLaunchKernelGGL(k_eim_split_scan, dim3(1), dim3(1024), 0, s, P.C.blk, nb, P.cnt);
+    hipLaunchKernelGGL(k_eim_split_scatter, dim3(nb), dim3(256), 0, s, P.R, P.nr, P.prm->seed,
+                       P.it, P.pS, P.pH, P.C.blk, nb, P.S + P.ns, P.H, P.cand);
     if (hipMemcpyAsync(P.hw, P.cnt, 12, hipMemcpyDeviceToHost, s) != hipSuccess)
         return h->fail(KC_EHIP, "readback failed");
     return KC_OK;
