@@ -31,7 +31,8 @@
  *           failed check enqueues nothing.  kc_last_error() gives the text of
  *           the last failure on a handle.  Nothing aborts or throws.
  * Inputs.   Non-finite coordinates give unspecified (but memory-safe)
- *           results.  n must be below 2^32 - 1 and d at most 256.
+ *           results; option "validate" flags them in the device status
+ *           word.  n must be below 2^32 - 1 and d at most 256.
  */
 #ifndef KCENTER_H
 #define KCENTER_H
@@ -96,7 +97,11 @@ const char* kc_last_error(const kc_handle* h);
  * identical results; a call made during stream capture never tunes);
  * "tune_force" (-1 default; v >= 0: every tuned operation runs its variant v
  * where that is feasible, else its first feasible one -- a testing aid that
- * reaches each variant; the variants are listed with kc_tune_report).
+ * reaches each variant; the variants are listed with kc_tune_report);
+ * "validate" 0/1 (default 0: every call first scans its points, and the BF16
+ * copy when one is used, for non-finite values on the device and sets bit 3
+ * of the device status word when it finds one; no host wait -- read it with
+ * kc_device_status).
  * KC_EINVAL for an unknown name or a value out of range. */
 int kc_set_option(kc_handle* h, const char* name, int64_t value);
 
@@ -148,9 +153,11 @@ int kc_timing_read(kc_handle* h, const char* name, double* ms, int64_t* launches
 int kc_counter_read(kc_handle* h, const char* name, int64_t* value);
 
 /* Synchronises `stream`, then reads and clears the handle's device status
- * word (bit 0: a persistent kernel's grid barrier timed out; bit 1: a
- * candidate buffer overflowed).  *status receives the word.  Returns KC_OK,
- * or KC_EDEVICE when the word was non-zero. */
+ * word (bit 0: a persistent kernel's grid barrier timed out; bit 2: a center
+ * index passed to an assignment is out of range (it is read as point 0);
+ * bit 3: a non-finite input coordinate, with option "validate").  *status
+ * receives the word.  Returns KC_OK, or KC_EDEVICE when the word was
+ * non-zero. */
 int kc_device_status(kc_handle* h, void* stream, uint32_t* status);
 
 /*
@@ -384,9 +391,10 @@ int kcenter_batch(kc_handle* h, const kc_problem* probs, int32_t count, void* st
  * uploads every group's launch plan and captures the graphs of the streamed
  * steps and of the finishing passes; later runs only launch (cached graphs;
  * the register-resident engine's cooperative launches are issued directly,
- * since a graph carries no co-residency guarantee).  EIM and BF16 problems
- * run through their single-problem paths on the plan's workspace
- * (kcenter_eim synchronises the stream once per iteration).  The plan's
+ * since a graph carries no co-residency guarantee).  EIM problems run as in
+ * kcenter_batch (lockstep loops, one wait per phase) and BF16 Gonzalez and
+ * MRG problems through their single-problem paths, on the plan's
+ * workspace.  The plan's
  * device status is folded into `h`'s (see kc_device_status).  Outputs, as
  * for kcenter_batch, land in the arrays the problems name.  Runs of one plan
  * must not overlap.

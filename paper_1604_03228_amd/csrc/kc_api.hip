@@ -618,6 +618,44 @@ int kc_run_gon_resident_batch(kc_handle* h, const std::string& key0, const KcGon
 // ---------------------------------------------------------------------------
 // public entry points
 
+// Option "validate": any non-finite coordinate of the n x d points (FP32,
+// and the BF16 copy when one is given) sets KC_STATUS_NONFINITE in the
+// device status word.  Rows are walked with a grid stride; a contiguous
+// array is read in memory order.
+__global__ __launch_bounds__(256) void k_check_finite(const float* __restrict__ X,
+                                                      const uint16_t* __restrict__ Xb,
+                                                      int64_t ld, int d, uint64_t n,
+                                                      uint32_t* __restrict__ status)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    if (ld == d) {
+        const uint64_t total = n * (uint64_t)d;
+        for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < total; e += stride) {
+            bad |= (__float_as_uint(X[e]) & 0x7F800000u) == 0x7F800000u;
+            if (Xb) bad |= (Xb[e] & 0x7F80u) == 0x7F80u;
+        }
+    } else {
+        for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += stride)
+            for (int j = 0; j < d; ++j) {
+                const uint64_t at = i * (uint64_t)ld + j;
+                bad |= (__float_as_uint(X[at]) & 0x7F800000u) == 0x7F800000u;
+                if (Xb) bad |= (Xb[at] & 0x7F80u) == 0x7F80u;
+            }
+    }
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(status, KC_STATUS_NONFINITE);
+}
+
+void kc_validate_points(kc_handle* h, const kc_points* p, hipStream_t s)
+{
+    if (!h->validate) return;
+    const uint64_t work = p->ld == p->d ? (uint64_t)p->n * p->d : (uint64_t)p->n;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>(2048, (work + 255) / 256);
+    hipLaunchKernelGGL(k_check_finite, dim3(blocks), dim3(256), 0, s, p->f32,
+                       p->prec == KC_BF16_RESCORE ? p->bf16 : nullptr, p->ld, p->d,
+                       (uint64_t)p->n, h->status_word);
+}
+
 extern "C" {
 
 int kc_create(kc_handle** out)
@@ -691,6 +729,11 @@ int kc_set_option(kc_handle* h, const char* name, int64_t value)
     }
     if (!strcmp(name, "autotune")) {
         h->autotune = value != 0;
+        return KC_OK;
+    }
+    if (!strcmp(name, "validate")) {
+        if (value != 0 && value != 1) return h->fail(KC_EINVAL, "validate must be 0 or 1");
+        h->validate = value != 0;
         return KC_OK;
     }
     if (!strcmp(name, "tune_force")) {
@@ -828,6 +871,7 @@ int kcenter_gonzalez(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
     if (first < 0 || first >= pts->n) return h->fail(KC_EINVAL, "first out of range");
     if (!centers || !n_chosen) return h->fail(KC_EINVAL, "centers/n_chosen NULL");
     hipStream_t s = (hipStream_t)stream;
+    kc_validate_points(h, pts, s);
     if (pts->prec == KC_BF16_RESCORE)
         return kc_gonzalez_bf16(h, pts, k, first, centers, radius_trace, n_chosen, s);
 

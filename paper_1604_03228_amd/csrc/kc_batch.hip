@@ -597,6 +597,7 @@ extern "C" int kcenter_batch(kc_handle* h, const kc_problem* probs, int32_t coun
         if (rc) return rc;
     }
     hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < count; ++i) kc_validate_points(h, &probs[i].pts, s);
     KcBatchLayout L;
     batch_layout(h, probs, count, L);
     for (size_t g = 0; g < L.groups.size(); ++g) {
@@ -665,6 +666,7 @@ extern "C" int kcenter_batch_plan(kc_handle* h, const kc_problem* probs, int32_t
     S->tuned = h->tuned;
     S->tune_ms = h->tune_ms;
     S->spin_limit = h->spin_limit;
+    S->validate = h->validate;
     S->resident_cap = h->resident_cap;
     S->graph_cap = 0;   // a plan keeps every graph it captures
     B->probs.assign(probs, probs + count);
@@ -688,6 +690,7 @@ extern "C" int kcenter_batch_run(kc_handle* h, kc_batch_plan* plan, void* stream
     const kc_problem* probs = plan->probs.data();
     const KcBatchLayout& L = plan->layout;
     int rc = KC_OK;
+    for (const kc_problem& p : plan->probs) kc_validate_points(S, &p.pts, s);
     if (!plan->prepared) {
         plan->groups.resize(L.groups.size());
         for (size_t g = 0; g < L.groups.size() && !rc; ++g)

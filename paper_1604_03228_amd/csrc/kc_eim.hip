@@ -1308,6 +1308,7 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
     if (k < 1 || k >= (1 << 24)) return h->fail(KC_EINVAL, "k out of range");
     if (!centers || !n_centers || !radius) return h->fail(KC_EINVAL, "outputs NULL");
     const hipStream_t s = (hipStream_t)stream;
+    kc_validate_points(h, pts, s);
     const uint32_t n = (uint32_t)pts->n;
     const int d = pts->d;
     const float* X = pts->f32;

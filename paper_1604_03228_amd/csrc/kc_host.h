@@ -61,6 +61,7 @@ struct kc_handle {
     bool mfma_split = true;           // FP32 distance passes on split BF16 MFMAs
     bool autotune = true;             // measured choice of engine variants
     int tune_force = -1;              // >= 0: always that variant where feasible
+    bool validate = false;            // scan inputs for non-finite values
     std::map<std::string, int> tuned;  // key -> chosen variant
     std::map<std::string, std::vector<float>> tune_ms;   // key -> measured ms per variant
     uint32_t spin_limit = 1u << 20;   // polls before a barrier wait gives up
@@ -203,6 +204,9 @@ int kc_gonzalez_bf16(kc_handle* h, const kc_points* pts, int64_t k, int64_t firs
 // of them.  On return C[q] (device, in the handle's workspace until its next
 // EIM call) holds problem q's sample C = S u R in ascending order and nc[q]
 // its size; the handle's eim_exact / eim_refined count over all of them.
+// Option "validate": enqueue the non-finite scan of the points (kc_api.hip).
+void kc_validate_points(kc_handle* h, const kc_points* p, hipStream_t s);
+
 int kc_eim_sample_many(kc_handle* h, const kc_problem* probs, const std::vector<int>& ids,
                        std::vector<const uint32_t*>& C, std::vector<uint32_t>& nc,
                        hipStream_t s);

@@ -253,6 +253,8 @@ __device__ inline KcMdBounds kc_md_bounds(const KcMinOut& O, uint32_t p,
 }
 
 int kc_mindist_ksteps(int d, bool bf);
+// Status bit of a non-finite input coordinate (option "validate").
+#define KC_STATUS_NONFINITE 8u
 int kc_mindist_dpad(int d, bool bf);
 // K-steps of the packed split for dimension d (0: it would not use fewer
 // MFMAs than the three-chain split); whether a split pass over kpad centers

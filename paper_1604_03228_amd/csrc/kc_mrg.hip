@@ -328,6 +328,7 @@ int kcenter_assign(kc_handle* h, const kc_points* pts, const int64_t* centers, i
     if (rc) return rc;
     if (k < 1 || k >= (1 << 24)) return h->fail(KC_EINVAL, "k=%lld out of range", (long long)k);
     if (!centers || !radius) return h->fail(KC_EINVAL, "centers/radius NULL");
+    kc_validate_points(h, pts, (hipStream_t)stream);
     return kc_assign_run(h, pts, centers, (uint32_t)k, nullptr, labels, radius,
                          (hipStream_t)stream, "a.");
 }
@@ -350,6 +351,7 @@ int kcenter_mrg(kc_handle* h, const kc_points* pts, const int64_t* offsets, int3
     if ((int64_t)m * k >= (int64_t)0xFFFFFFFFll) return h->fail(KC_EINVAL, "m*k too large");
     if (!centers || !n_centers || !radius) return h->fail(KC_EINVAL, "outputs NULL");
     hipStream_t s = (hipStream_t)stream;
+    kc_validate_points(h, pts, s);
     const bool bf = pts->prec == KC_BF16_RESCORE;
     const int d = pts->d;
 
@@ -504,6 +506,7 @@ int kcenter_mrg_rounds(kc_handle* h, const kc_points* pts, int64_t k, int64_t ca
     if (capacity < 1) return h->fail(KC_EINVAL, "capacity must be >= 1");
     if (!centers || !n_centers || !radius) return h->fail(KC_EINVAL, "outputs NULL");
     hipStream_t s = (hipStream_t)stream;
+    kc_validate_points(h, pts, s);
     const int d = pts->d;
     const float* Xc = pts->f32;   // rows of the current sample
     int64_t ldc = pts->ld;

@@ -168,6 +168,7 @@ extern "C" int kcenter_gonzalez_noalloc(kc_handle* h, const kc_points* pts, int6
     R.xa = pts->f32;   // center and candidate gathers read the caller's rows
     R.lda = pts->ld;
 
+    kc_validate_points(h, pts, s);
     const uint32_t ng = std::max<uint32_t>(std::max(nblk, kk), 1);
     hipLaunchKernelGGL(k_plan_one, dim3((ng + 255) / 256), dim3(256), 0, s, R.segs, R.blk_seg,
                        R.blk_start, nblk, R.pairs_seg, R.pairs_t, kk, n, (uint32_t)first, tile);

@@ -142,6 +142,7 @@ extern "C" int kcenter_gonzalez_resume(kc_handle* h, const kc_points* pts,
                 return h->fail(KC_EINVAL, "prefix repeats point %lld", (long long)srt[t]);
     }
     hipStream_t s = (hipStream_t)stream;
+    kc_validate_points(h, pts, s);
     const int d = pts->d;
     const uint32_t n = (uint32_t)pts->n, kk = (uint32_t)k, pp = (uint32_t)p;
     const uint32_t ks = kk - pp + 1;   // engine steps: p-1 .. k-1
