@@ -358,10 +358,10 @@ typedef struct {
  * algorithm.  Gonzalez problems and MRG first rounds of equal d share the
  * same launches (register-resident, several per cooperative launch, when
  * every one fits a co-resident grid, else one streamed tile list over all of
- * them with a HIP graph per plan; a streamed list whose n d reaches 2.5e7
- * streams a BF16 copy the library rounds from the FP32 rows, with exact FP32
- * rescoring, which gives the FP32 stream's centers); MRG second rounds
- * likewise.  An EIM
+ * them with a HIP graph per plan; a streamed list of n points with
+ * n (2d - 4) >= 1e8 streams a BF16 copy the library rounds from the FP32
+ * rows, with exact FP32 rescoring, which gives the FP32 stream's centers);
+ * MRG second rounds likewise.  An EIM
  * problem whose n does not exceed Algorithm 2's threshold (4/eps) k n^eps
  * ln n never samples, so its result is Gonzalez's from point 0 with the
  * covering radius, and it joins those launches as such.  The other EIM

@@ -459,8 +459,104 @@ __global__ __launch_bounds__(W * 64) void k_mindist_mfma(
 // center staging: compact FP32 / BF16 rows [kpad][DP], norms (+inf padding),
 // and the maxima |c| and e_c used by the error bound.
 
+// One thread per center: for many centers (an EIM pass stages its samples),
+// where a wave per center would spend most of its time on the reductions.
+__global__ void k_stage_centers_thread(const float* __restrict__ X,
+                                       const uint16_t* __restrict__ Xb, int64_t ld, int d,
+                                       uint32_t n, const int64_t* __restrict__ idx,
+                                       const uint32_t* __restrict__ idx32, uint32_t k,
+                                       const int64_t* __restrict__ k_dev, KcCenters C,
+                                       uint32_t* __restrict__ status)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t kpad = C.kpad;
+    const int dp = C.dp;
+    if (i >= kpad) return;
+    if (k_dev && (int64_t)k > *k_dev) k = (uint32_t)(*k_dev < 0 ? 0 : *k_dev);
+    int64_t ri = 0;
+    if (i < k) {
+        ri = idx ? idx[i] : (int64_t)idx32[i];
+        if (ri < 0 || ri >= (int64_t)n) {   // invalid index: report, stay in bounds
+            atomicOr(status, 4u);
+            ri = 0;
+        }
+    }
+    if (i >= k) {
+        for (int j = 0; j < dp; ++j) {
+            if (C.Cf) C.Cf[(uint64_t)i * dp + j] = 0.f;
+            if (C.Ct) C.Ct[(uint64_t)i * dp + j] = 0.f;
+            if (C.Cb) C.Cb[(uint64_t)i * dp + j] = 0;
+            if (C.Cbl) C.Cbl[(uint64_t)i * dp + j] = 0;
+        }
+        C.cn[i] = __builtin_inff();
+        C.cnl[i] = __builtin_inff();
+        C.clen[i] = 0.f;
+        if (C.cerr) C.cerr[i] = 0.f;
+        return;
+    }
+    const uint64_t r = (uint64_t)ri;
+    double nn = 0.0, ee = 0.0, nb = 0.0;
+    float nf = 0.f;
+    const bool split = C.Cbl != nullptr || C.pk;
+    for (int j = 0; j < dp; ++j) {
+        const float v = j < d ? X[r * ld + j] : 0.f;
+        if (C.Cf) C.Cf[(uint64_t)i * dp + j] = v;
+        if (C.Ct) C.Ct[(uint64_t)i * dp + j] = (C.mu && j < d) ? v - C.mu[j] : v;
+        if (C.pk) {
+            // packed row [h | l | h | 0]: position j takes part j / d of
+            // coordinate j mod d
+            const int part = j < d ? 0 : j < 2 * d ? 1 : j < 3 * d ? 2 : 3;
+            const int jj = j - part * d;
+            const float u = part < 3 ? X[r * ld + jj] : 0.f;
+            const float t = (C.mu && part < 3) ? u - C.mu[jj] : u;
+            const uint16_t hh = kc_f32_to_bf16_rne(t);
+            C.Cb[(uint64_t)i * dp + j] =
+                part == 1 ? kc_f32_to_bf16_rne(t - kc_bf16_to_f32(hh)) : hh;
+            if (part == 0) {
+                nf = __builtin_fmaf(t, t, nf);
+                nn += (double)t * (double)t;
+            }
+        } else if (split) {
+            // high and low BF16 parts of the translated value
+            const float t = (C.mu && j < d) ? v - C.mu[j] : v;
+            const uint16_t hh = kc_f32_to_bf16_rne(t);
+            C.Cb[(uint64_t)i * dp + j] = hh;
+            C.Cbl[(uint64_t)i * dp + j] = kc_f32_to_bf16_rne(t - kc_bf16_to_f32(hh));
+            nf = __builtin_fmaf(t, t, nf);
+            nn += (double)t * (double)t;
+        } else if (C.Cb) {
+            const uint16_t h = j < d ? Xb[r * ld + j] : (uint16_t)0;
+            C.Cb[(uint64_t)i * dp + j] = h;
+            const float f = kc_bf16_to_f32(h);
+            nf = __builtin_fmaf(f, f, nf);
+            nb += (double)f * (double)f;
+            const double e = (double)f - (double)v;
+            ee += e * e;
+        } else {
+            // the value the MFMA pass loads: translated to the local origin
+            const float t = (C.mu && j < d) ? v - C.mu[j] : v;
+            nf = __builtin_fmaf(t, t, nf);
+            nn += (double)t * (double)t;
+        }
+    }
+    // the norm used in v: of the values fed to the MFMA, in FP32 as the
+    // kernel's error bound assumes; |c| and e_c rounded up
+    const bool bf_in = C.Cb && !split;
+    const double b = sqrt(bf_in ? nb : nn) * (1.0 + 1e-6);
+    const double e = bf_in ? sqrt(ee) * (1.0 + 1e-6) : 0.0;
+    const double g = kc_md_gamma(d, split);
+    C.cn[i] = nf;
+    C.cnl[i] = (float)((double)nf - (g * b * b + 2.0 * e * b));
+    C.clen[i] = (float)b * (1.f + 1e-6f);
+    if (C.cerr) C.cerr[i] = (float)e * (1.f + 1e-6f);
+    kc_atomic_max_f32_nonneg(&C.cmax[0], (float)b * (1.f + 1e-6f));
+    if (bf_in) kc_atomic_max_f32_nonneg(&C.cmax[1], (float)e * (1.f + 1e-6f));
+}
+
 // One wave per center: lanes over the row's K positions, the norms reduced
-// over the wave (any order: the bounds cover FP32 sums in any order).
+// over the wave (any order: the bounds cover FP32 sums in any order); for
+// few centers (an assignment's), where one thread per center would leave
+// the launch a handful of long serial loops.
 __global__ __launch_bounds__(256) void k_stage_centers(
     const float* __restrict__ X, const uint16_t* __restrict__ Xb, int64_t ld, int d, uint32_t n,
     const int64_t* __restrict__ idx, const uint32_t* __restrict__ idx32, uint32_t k,
@@ -1088,8 +1184,12 @@ void kc_stage_centers(const float* X, const uint16_t* Xb, int64_t ld, int d, uin
                       const int64_t* k_dev, const KcCenters& C, uint32_t* status, hipStream_t s)
 {
     kc_fill_u32((uint32_t*)C.cmax, 0u, 2, s);
-    hipLaunchKernelGGL(k_stage_centers, dim3((C.kpad + 3) / 4), dim3(256), 0, s, X, Xb, ld, d, n,
-                       idx, idx32, k, k_dev, C, status);
+    if (C.kpad >= 2048)
+        hipLaunchKernelGGL(k_stage_centers_thread, dim3((C.kpad + 255) / 256), dim3(256), 0, s,
+                           X, Xb, ld, d, n, idx, idx32, k, k_dev, C, status);
+    else
+        hipLaunchKernelGGL(k_stage_centers, dim3((C.kpad + 3) / 4), dim3(256), 0, s, X, Xb, ld, d,
+                           n, idx, idx32, k, k_dev, C, status);
 }
 
 void kc_local_origin(const float* X, int64_t ld, int d, uint32_t n, float* mu, hipStream_t s)

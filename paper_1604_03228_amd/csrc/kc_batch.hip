@@ -261,14 +261,16 @@ static int group_prepare(kc_handle* h, const kc_problem* probs, const std::vecto
         sr.push_back(rbase[q]);
     }
     // A group that streams reads every point at every step: with enough
-    // points the stream runs on a BF16 copy rounded from the FP32 rows (half
-    // the bytes per coordinate) with exact FP32 rescoring of the candidates,
-    // whose centers are the FP32 stream's.  The rescoring adds a fixed cost
-    // per step (about 10 us: at 5 TB/s the bytes of 5e7 / 2 coordinates), so
-    // it pays from n d = 2.5e7 on.
-    uint64_t nd = 0;
-    for (const KcGonJob& j : G.sj) nd += (uint64_t)j.len * (uint64_t)d;
-    G.bf = !strcmp(tag, "s") && nd >= 25000000ull;
+    // points the stream runs on a BF16 copy rounded from the FP32 rows (2d
+    // bytes less per point and step, 4 more for its rounding radius) with
+    // exact FP32 rescoring of the candidates, whose centers are the FP32
+    // stream's.  The rescoring adds about 10 us per step (5e7 bytes at
+    // 5 TB/s), so it runs from twice that in saved bytes: n (2d - 4) >= 1e8
+    // (a d = 32 group of 1.7e6 points, a d = 8 group of 8.3e6).
+    const uint64_t per = 2 * d > 4 ? (uint64_t)(2 * d - 4) : 0u;
+    uint64_t saved = 0;
+    for (const KcGonJob& j : G.sj) saved += (uint64_t)j.len * per;
+    G.bf = !strcmp(tag, "s") && saved >= 100000000ull;
     int rc = kc_plan_gon(h, P + "1.", d, G.bf ? KC_BF_TILE_PTS : 1024, G.sj, G.R, G.H, s);
     if (rc) return rc;
     if (G.bf && (rc = kc_bf16_alloc(h, P + "1b.", G.R, G.B))) return rc;

@@ -129,13 +129,14 @@ def test_batch_integer_exact(kc, orc):
 
 
 def test_batch_streamed_group_on_bf16_copy(kc, orc):
-    # option resident = 0 streams every group; a streamed group of n d >=
-    # 2.5e7 runs on a BF16 copy the library rounds, with exact rescoring:
-    # its centers and radii equal the FP32 single calls' (both streamed)
+    # option resident = 0 streams every group; a streamed group of n points
+    # with n (2d - 4) >= 1e8 runs on a BF16 copy the library rounds, with
+    # exact rescoring: its centers and radii equal the FP32 single calls'
+    # (both streamed); here 1.8e6 points at d = 32
     rng = np.random.default_rng(77)
     probs = []
-    for i, (n, algo, k) in enumerate([(420_000, "gon", 60), (300_000, "mrg", 40),
-                                      (150_000, "gon", 25)]):
+    for i, (n, algo, k) in enumerate([(900_000, "gon", 60), (600_000, "mrg", 40),
+                                      (300_000, "gon", 25)]):
         X = W.points_gauss_mixture(n, 32, 30, seed=500 + i)
         pr = dict(X=torch.from_numpy(X).cuda(), Xh=X, algo=algo, k=k)
         if algo == "mrg":
@@ -146,6 +147,7 @@ def test_batch_streamed_group_on_bf16_copy(kc, orc):
     h = kc.Handle(resident=False)
     outs = on_stream(lambda: kc.batch(probs, handle=h))
     assert h.device_status() == 0
+    assert h.counter("bf16_listed") > 0    # the group did run the BF16 stream
     for pr, (c, nc, r) in zip(probs, outs):
         ref = on_stream(lambda: single(kc, pr, h))
         g = int(nc.item())
