@@ -1309,7 +1309,6 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
     if (!centers || !n_centers || !radius) return h->fail(KC_EINVAL, "outputs NULL");
     const hipStream_t s = (hipStream_t)stream;
     kc_validate_points(h, pts, s);
-    const uint32_t n = (uint32_t)pts->n;
     const int d = pts->d;
     const float* X = pts->f32;
     const int64_t ld = pts->ld;
@@ -1371,6 +1370,5 @@ extern "C" int kcenter_eim(kc_handle* h, const kc_points* pts, int64_t k,
     kc_gon_finish(RG, centers, n_centers, nullptr, nullptr, nullptr, C64, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
-    (void)n;
     return kc_assign_run(h, pts, centers, (uint32_t)k, n_centers, nullptr, radius, s, "e3.");
 }
