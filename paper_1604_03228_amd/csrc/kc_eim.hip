@@ -8,7 +8,8 @@
 //                     (one counter-based block per point and iteration,
 //                     recomputed rather than stored); count, scan and
 //                     scatter split R stably into dS (new samples), H and the
-//                     points that stay candidates (not sampled);
+//                     points that stay candidates (not sampled) -- three
+//                     launches shared by every problem still looping;
 //   k_eim_dist_h      exact FP64 d(h,S)^2 for h in H (split over S, min via
 //                     64-bit atomics on the bits of non-negative doubles);
 //   k_eim_select      tau = the min(r,|H|)-th largest d(h,S)^2 (rank count);
@@ -150,19 +151,47 @@ __device__ __forceinline__ void kc_eim_flags(uint32_t x, uint64_t seed, int it, 
     hh = (double)(c[1] >> 11) * 0x1.0p-53 < pH;
 }
 
-__global__ __launch_bounds__(256) void k_eim_split_count(const uint32_t* __restrict__ R,
-                                                         uint32_t nr, uint64_t seed, int it,
-                                                         double pS, double pH,
-                                                         uint32_t* __restrict__ blk3, uint32_t nb)
+// One problem's share of a shared split launch (the problems of a batch in
+// lockstep, or one): its R, outputs, block counts [3][nb] and draw
+// parameters; its blocks are blk0 .. blk0 + nb - 1 of the launch.
+struct KcEimSplitJob {
+    const uint32_t* R;
+    uint32_t* outS;   // S + |S| before the draws
+    uint32_t* outH;
+    uint32_t* outK;   // the candidates
+    uint32_t* blk;    // [3][nb]
+    uint64_t seed;
+    double pS, pH;
+    uint32_t nr, nb, blk0;
+    int32_t it;
+};
+
+// the job whose blocks contain block b (jobs in ascending blk0)
+__device__ __forceinline__ const KcEimSplitJob& kc_split_job(const KcEimSplitJob* __restrict__ J,
+                                                             int nj, uint32_t b)
+{
+    int lo = 0, hi = nj - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (J[mid].blk0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return J[lo];
+}
+
+__global__ __launch_bounds__(256) void k_eim_split_count(const KcEimSplitJob* __restrict__ J,
+                                                         int nj)
 {
     __shared__ uint32_t red[3][4];
-    const uint32_t base = blockIdx.x * KC_CMP_ITEMS;
+    const KcEimSplitJob& jb = kc_split_job(J, nj, blockIdx.x);
+    const uint32_t lb = blockIdx.x - jb.blk0;
+    const uint32_t base = lb * KC_CMP_ITEMS, nr = jb.nr;
     uint32_t c[3] = {0u, 0u, 0u};
     for (int q = 0; q < 4; ++q) {
         const uint32_t i = base + q * 256 + threadIdx.x;
         if (i < nr) {
             bool sm, hm;
-            kc_eim_flags(R[i], seed, it, pS, pH, sm, hm);
+            kc_eim_flags(jb.R[i], jb.seed, jb.it, jb.pS, jb.pH, sm, hm);
             c[0] += sm;
             c[1] += hm;
             c[2] += !sm;   // sampled points always leave R
@@ -176,20 +205,22 @@ __global__ __launch_bounds__(256) void k_eim_split_count(const uint32_t* __restr
     __syncthreads();
     if (threadIdx.x < 3) {
         const uint32_t f = threadIdx.x;
-        blk3[(uint64_t)f * nb + blockIdx.x] = red[f][0] + red[f][1] + red[f][2] + red[f][3];
+        jb.blk[(uint64_t)f * jb.nb + lb] = red[f][0] + red[f][1] + red[f][2] + red[f][3];
     }
 }
 
-// one block of 1024: the three exclusive scans; totals -> count3[0..2]
-__global__ __launch_bounds__(1024) void k_eim_split_scan(uint32_t* __restrict__ blk3,
-                                                         uint32_t nb,
+// block j (1024 threads): job j's three exclusive scans; its totals ->
+// count3[3j .. 3j+2]
+__global__ __launch_bounds__(1024) void k_eim_split_scan(const KcEimSplitJob* __restrict__ J,
                                                          uint32_t* __restrict__ count3)
 {
     __shared__ uint32_t carry;
     __shared__ uint32_t wsum[16];
+    const KcEimSplitJob& jb = J[blockIdx.x];
+    const uint32_t nb = jb.nb;
     const int lane = threadIdx.x & 63;
     for (int f = 0; f < 3; ++f) {
-        uint32_t* blk = blk3 + (uint64_t)f * nb;
+        uint32_t* blk = jb.blk + (uint64_t)f * nb;
         if (threadIdx.x == 0) carry = 0;
         __syncthreads();
         for (uint32_t b0 = 0; b0 < nb; b0 += blockDim.x) {
@@ -210,30 +241,30 @@ __global__ __launch_bounds__(1024) void k_eim_split_scan(uint32_t* __restrict__ 
             if (threadIdx.x == blockDim.x - 1) carry = excl + v;
             __syncthreads();
         }
-        if (threadIdx.x == 0) count3[f] = carry;
+        if (threadIdx.x == 0) count3[3 * blockIdx.x + f] = carry;
         __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(256) void k_eim_split_scatter(
-    const uint32_t* __restrict__ R, uint32_t nr, uint64_t seed, int it, double pS, double pH,
-    const uint32_t* __restrict__ blk3, uint32_t nb, uint32_t* __restrict__ outS,
-    uint32_t* __restrict__ outH, uint32_t* __restrict__ outK)
+__global__ __launch_bounds__(256) void k_eim_split_scatter(const KcEimSplitJob* __restrict__ J,
+                                                           int nj)
 {
     __shared__ uint32_t wcnt[3][4];
-    const uint32_t base = blockIdx.x * KC_CMP_ITEMS;
+    const KcEimSplitJob& jb = kc_split_job(J, nj, blockIdx.x);
+    const uint32_t lb = blockIdx.x - jb.blk0;
+    const uint32_t base = lb * KC_CMP_ITEMS, nr = jb.nr;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t run[3];
 #pragma unroll
-    for (int f = 0; f < 3; ++f) run[f] = blk3[(uint64_t)f * nb + blockIdx.x];
-    uint32_t* out[3] = {outS, outH, outK};
+    for (int f = 0; f < 3; ++f) run[f] = jb.blk[(uint64_t)f * jb.nb + lb];
+    uint32_t* out[3] = {jb.outS, jb.outH, jb.outK};
     for (int q = 0; q < 4; ++q) {
         const uint32_t i = base + q * 256 + threadIdx.x;
         bool on[3] = {false, false, false};
         uint32_t x = 0;
         if (i < nr) {
-            x = R[i];
-            kc_eim_flags(x, seed, it, pS, pH, on[0], on[1]);
+            x = jb.R[i];
+            kc_eim_flags(x, jb.seed, jb.it, jb.pS, jb.pH, on[0], on[1]);
             on[2] = !on[0];
         }
         u64 mask[3];
@@ -833,9 +864,9 @@ static int kc_eim_init(kc_handle* h, KcEimLoop& P, const kc_points* pts, int64_t
     return KC_OK;
 }
 
-// Phase 1: the loop test, the draws and the split of R into dS, H and the
-// candidates; their sizes go to hw[0..2].
-static int kc_eim_draw_phase(kc_handle* h, KcEimLoop& P, hipStream_t s)
+// Phase 1 for one problem: the loop test; an iteration that runs gets its
+// draw probabilities and its job in the shared split launches.
+static int kc_eim_begin_iter(kc_handle* h, KcEimLoop& P)
 {
     if ((double)P.nr <= P.thr) {
         P.done = true;
@@ -847,15 +878,46 @@ static int kc_eim_draw_phase(kc_handle* h, KcEimLoop& P, hipStream_t s)
     if (P.pS > 1.0) P.pS = 1.0;
     P.pH = P.A_H / (double)P.nr;
     if (P.pH > 1.0) P.pH = 1.0;
-    const uint32_t nb = (P.nr + KC_CMP_ITEMS - 1) / KC_CMP_ITEMS;
-    hipLaunchKernelGGL(k_eim_split_count, dim3(nb), dim3(256), 0, s, P.R, P.nr, P.prm->seed,
-                       P.it, P.pS, P.pH, P.C.blk, nb);
-    hipLaunchKernelGGL(k_eim_split_scan, dim3(1), dim3(1024), 0, s, P.C.blk, nb, P.cnt);
-    hipLaunchKernelGGL(k_eim_split_scatter, dim3(nb), dim3(256), 0, s, P.R, P.nr, P.prm->seed,
-                       P.it, P.pS, P.pH, P.C.blk, nb, P.S + P.ns, P.H, P.cand);
-    if (hipMemcpyAsync(P.hw, P.cnt, 12, hipMemcpyDeviceToHost, s) != hipSuccess)
-        return h->fail(KC_EHIP, "readback failed");
     return KC_OK;
+}
+
+// Phase 1 for every problem still looping, in three shared launches: the
+// draws and the split of each R into dS, H and the candidates; the sizes go
+// to each problem's hw[0..2] (through one readback).
+static int kc_eim_split_phase(kc_handle* h, std::vector<KcEimLoop*>& act, hipStream_t s)
+{
+    std::vector<KcEimSplitJob> jobs(act.size());
+    uint32_t total = 0;
+    for (size_t q = 0; q < act.size(); ++q) {
+        KcEimLoop& P = *act[q];
+        KcEimSplitJob& j = jobs[q];
+        j.R = P.R;
+        j.outS = P.S + P.ns;
+        j.outH = P.H;
+        j.outK = P.cand;
+        j.blk = P.C.blk;
+        j.seed = P.prm->seed;
+        j.pS = P.pS;
+        j.pH = P.pH;
+        j.nr = P.nr;
+        j.nb = (P.nr + KC_CMP_ITEMS - 1) / KC_CMP_ITEMS;
+        j.blk0 = total;
+        j.it = P.it;
+        total += j.nb;
+    }
+    const int nj = (int)jobs.size();
+    const KcEimSplitJob* J =
+        (const KcEimSplitJob*)h->upload("eim.jobs", jobs.data(), sizeof(KcEimSplitJob) * nj, s);
+    uint32_t* c3 = (uint32_t*)h->ws("eim.c3", 12ull * nj);
+    uint32_t* c3h = (uint32_t*)h->pinned("eim.c3", 12ull * nj);
+    if (!J || !c3 || !c3h) return h->fail(KC_ENOMEM, "workspace allocation failed");
+    hipLaunchKernelGGL(k_eim_split_count, dim3(total), dim3(256), 0, s, J, nj);
+    hipLaunchKernelGGL(k_eim_split_scan, dim3(nj), dim3(1024), 0, s, J, c3);
+    hipLaunchKernelGGL(k_eim_split_scatter, dim3(total), dim3(256), 0, s, J, nj);
+    if (hipMemcpyAsync(c3h, c3, 12ull * nj, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return h->fail(KC_EHIP, "readback failed");
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? KC_OK : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
 }
 
 // Select (Algorithm 3): tau over H, exact FP64 against all of S.
@@ -1227,15 +1289,22 @@ static int kc_eim_loops(kc_handle* h, std::vector<KcEimLoop>& L, hipStream_t s)
         return L.size() > 1 ? h->fail(code, "problem %d: %s", P.id, h->last_error.c_str())
                             : code;
     };
+    std::vector<KcEimLoop*> act;
     for (;;) {
-        bool any = false;
+        act.clear();
         for (KcEimLoop& P : L)
             if (!P.done) {
-                if ((rc = kc_eim_draw_phase(h, P, s))) return fail_at(P, rc);
-                any = any || !P.done;
+                if ((rc = kc_eim_begin_iter(h, P))) return fail_at(P, rc);
+                if (!P.done) act.push_back(&P);
             }
-        if (!any) break;
+        if (act.empty()) break;
+        if ((rc = kc_eim_split_phase(h, act, s))) return rc;
         if ((rc = kc_eim_wait(h, s))) return rc;
+        {
+            const uint32_t* c3h = (const uint32_t*)h->pinned("eim.c3", 12ull * act.size());
+            for (size_t q = 0; q < act.size(); ++q)
+                for (int f = 0; f < 3; ++f) act[q]->hw[f] = c3h[3 * q + f];
+        }
         bool wait_nu = false;
         for (KcEimLoop& P : L)
             if (!P.done) {
