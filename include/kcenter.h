@@ -366,10 +366,10 @@ typedef struct {
  * ln n never samples, so its result is Gonzalez's from point 0 with the
  * covering radius, and it joins those launches as such.  The other EIM
  * problems run their sampling loops in lockstep: each phase of an iteration
- * (draws and compactions -- three launches shared by all of them; Select,
- * distance pass and decisions; FP32 refinement; FP64 decisions and R's
- * compaction) is queued for every one of them before one wait, whose
- * readback sizes the next phase.  Then, per d,
+ * (draws and splits -- three launches shared by all of them; Select,
+ * distance pass and decisions; FP32 refinement; FP64 decisions, then R's
+ * compaction -- again three shared launches) is queued for every one of
+ * them before one wait, whose readback sizes the next phase.  Then, per d,
  * the final Gonzalez of all of them runs as the segments of one run on
  * their samples C, and each covering radius by the assignment.  Gonzalez
  * and MRG problems in BF16 run one after another through their

@@ -167,8 +167,8 @@ struct KcEimSplitJob {
 };
 
 // the job whose blocks contain block b (jobs in ascending blk0)
-__device__ __forceinline__ const KcEimSplitJob& kc_split_job(const KcEimSplitJob* __restrict__ J,
-                                                             int nj, uint32_t b)
+template <class JT>
+__device__ __forceinline__ const JT& kc_split_job(const JT* __restrict__ J, int nj, uint32_t b)
 {
     int lo = 0, hi = nj - 1;
     while (lo < hi) {
@@ -209,39 +209,113 @@ __global__ __launch_bounds__(256) void k_eim_split_count(const KcEimSplitJob* __
     }
 }
 
+// One block of 1024 threads: the exclusive scan of nb block counts in
+// place; returns the total (to every thread).
+__device__ uint32_t kc_scan_block_counts(uint32_t* __restrict__ blk, uint32_t nb)
+{
+    __shared__ uint32_t carry;
+    __shared__ uint32_t wsum[16];
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t b0 = 0; b0 < nb; b0 += blockDim.x) {
+        const uint32_t i = b0 + threadIdx.x;
+        const uint32_t v = i < nb ? blk[i] : 0u;
+        uint32_t x = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[threadIdx.x >> 6] = x;
+        __syncthreads();
+        uint32_t wpre = 0;
+        for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wpre += wsum[w];
+        const uint32_t excl = carry + wpre + x - v;
+        __syncthreads();
+        if (i < nb) blk[i] = excl;
+        if (threadIdx.x == blockDim.x - 1) carry = excl + v;
+        __syncthreads();
+    }
+    const uint32_t tot = carry;
+    __syncthreads();
+    return tot;
+}
+
 // block j (1024 threads): job j's three exclusive scans; its totals ->
 // count3[3j .. 3j+2]
 __global__ __launch_bounds__(1024) void k_eim_split_scan(const KcEimSplitJob* __restrict__ J,
                                                          uint32_t* __restrict__ count3)
 {
-    __shared__ uint32_t carry;
-    __shared__ uint32_t wsum[16];
     const KcEimSplitJob& jb = J[blockIdx.x];
-    const uint32_t nb = jb.nb;
-    const int lane = threadIdx.x & 63;
     for (int f = 0; f < 3; ++f) {
-        uint32_t* blk = jb.blk + (uint64_t)f * nb;
-        if (threadIdx.x == 0) carry = 0;
+        const uint32_t tot = kc_scan_block_counts(jb.blk + (uint64_t)f * jb.nb, jb.nb);
+        if (threadIdx.x == 0) count3[3 * blockIdx.x + f] = tot;
+    }
+}
+
+// R' = the kept candidates of every problem that decided this iteration,
+// in three shared launches (stable compaction of the keep flags); per
+// problem out4[4j ..] = |R'|, its FP64-decided count and tau's two words.
+struct KcKeepJob {
+    const uint8_t* f;          // keep flags, per candidate
+    const uint32_t* in;        // the candidates
+    uint32_t* out;             // R'
+    uint32_t* blk;             // [nb]
+    const uint32_t* nexact;    // FP64-decided count of the iteration
+    const double* tau;
+    uint32_t n, nb, blk0, pad;
+};
+
+__global__ __launch_bounds__(256) void k_keep_count(const KcKeepJob* __restrict__ J, int nj)
+{
+    __shared__ uint32_t red[4];
+    const KcKeepJob& jb = kc_split_job(J, nj, blockIdx.x);
+    const uint32_t lb = blockIdx.x - jb.blk0;
+    const uint32_t base = lb * KC_CMP_ITEMS;
+    uint32_t c = 0;
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t i = base + q * 256 + threadIdx.x;
+        if (i < jb.n) c += jb.f[i] != 0;
+    }
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) jb.blk[lb] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(1024) void k_keep_scan(const KcKeepJob* __restrict__ J,
+                                                    uint32_t* __restrict__ out4)
+{
+    const KcKeepJob& jb = J[blockIdx.x];
+    const uint32_t tot = kc_scan_block_counts(jb.blk, jb.nb);
+    if (threadIdx.x == 0) {
+        uint32_t tw[2];
+        memcpy(tw, jb.tau, 8);
+        out4[4 * blockIdx.x + 0] = tot;
+        out4[4 * blockIdx.x + 1] = *jb.nexact;
+        out4[4 * blockIdx.x + 2] = tw[0];
+        out4[4 * blockIdx.x + 3] = tw[1];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_keep_scatter(const KcKeepJob* __restrict__ J, int nj)
+{
+    __shared__ uint32_t wcnt[4];
+    const KcKeepJob& jb = kc_split_job(J, nj, blockIdx.x);
+    const uint32_t lb = blockIdx.x - jb.blk0;
+    const uint32_t base = lb * KC_CMP_ITEMS;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t run = jb.blk[lb];
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t i = base + q * 256 + threadIdx.x;
+        const bool on = i < jb.n && jb.f[i] != 0;
+        const u64 mask = __ballot(on);
+        if (lane == 0) wcnt[w] = __popcll(mask);
         __syncthreads();
-        for (uint32_t b0 = 0; b0 < nb; b0 += blockDim.x) {
-            const uint32_t i = b0 + threadIdx.x;
-            const uint32_t v = i < nb ? blk[i] : 0u;
-            uint32_t x = v;
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t y = __shfl_up(x, off, 64);
-                if (lane >= off) x += y;
-            }
-            if (lane == 63) wsum[threadIdx.x >> 6] = x;
-            __syncthreads();
-            uint32_t wpre = 0;
-            for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) wpre += wsum[w];
-            const uint32_t excl = carry + wpre + x - v;
-            __syncthreads();
-            if (i < nb) blk[i] = excl;
-            if (threadIdx.x == blockDim.x - 1) carry = excl + v;
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) count3[3 * blockIdx.x + f] = carry;
+        uint32_t wpre = 0;
+        for (int v = 0; v < w; ++v) wpre += wcnt[v];
+        if (on) jb.out[run + wpre + __popcll(mask & ((1ull << lane) - 1ull))] = jb.in[i];
+        run += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
         __syncthreads();
     }
 }
@@ -1235,12 +1309,46 @@ static int kc_eim_keep_phase(kc_handle* h, KcEimLoop& P, hipStream_t s)
         if (rc) return rc;
     }
     h->eim_refined += P.refined_it;
-    kc_compact(P.C, P.keep, P.cand, P.nc, P.R2, P.cnt + 3, s);
-    std::swap(P.R, P.R2);
-    if (hipMemcpyAsync(P.hw + 4, P.cnt + 3, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(P.hw + 6, P.tau, 8, hipMemcpyDeviceToHost, s) != hipSuccess)
-        return h->fail(KC_EHIP, "readback failed");
     return KC_OK;
+}
+
+// R' of every problem that decided this iteration (kc_eim_keep_phase done):
+// shared compaction launches, then |R'|, the FP64-decided count and tau into
+// each problem's hw[4..7] through one readback; R and R2 swap.
+static int kc_eim_compact_phase(kc_handle* h, std::vector<KcEimLoop*>& dec, hipStream_t s)
+{
+    if (dec.empty()) return KC_OK;
+    std::vector<KcKeepJob> jobs(dec.size());
+    uint32_t total = 0;
+    for (size_t q = 0; q < dec.size(); ++q) {
+        KcEimLoop& P = *dec[q];
+        KcKeepJob& j = jobs[q];
+        j.f = P.keep;
+        j.in = P.cand;
+        j.out = P.R2;
+        j.blk = P.C.blk;
+        j.nexact = P.cnt + 4;
+        j.tau = P.tau;
+        j.n = P.nc;
+        j.nb = (P.nc + KC_CMP_ITEMS - 1) / KC_CMP_ITEMS;
+        j.blk0 = total;
+        j.pad = 0;
+        total += j.nb;
+        std::swap(P.R, P.R2);
+    }
+    const int nj = (int)jobs.size();
+    const KcKeepJob* J =
+        (const KcKeepJob*)h->upload("eim.kjobs", jobs.data(), sizeof(KcKeepJob) * nj, s);
+    uint32_t* o4 = (uint32_t*)h->ws("eim.k4", 16ull * nj);
+    uint32_t* o4h = (uint32_t*)h->pinned("eim.k4", 16ull * nj);
+    if (!J || !o4 || !o4h) return h->fail(KC_ENOMEM, "workspace allocation failed");
+    if (total) hipLaunchKernelGGL(k_keep_count, dim3(total), dim3(256), 0, s, J, nj);
+    hipLaunchKernelGGL(k_keep_scan, dim3(nj), dim3(1024), 0, s, J, o4);
+    if (total) hipLaunchKernelGGL(k_keep_scatter, dim3(total), dim3(256), 0, s, J, nj);
+    if (hipMemcpyAsync(o4h, o4, 16ull * nj, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return h->fail(KC_EHIP, "readback failed");
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? KC_OK : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
 }
 
 // Phase 5 (host): the iteration's record; R' becomes R.
@@ -1321,9 +1429,19 @@ static int kc_eim_loops(kc_handle* h, std::vector<KcEimLoop>& L, hipStream_t s)
                 }
             if (wait_ref && (rc = kc_eim_wait(h, s))) return rc;
         }
+        std::vector<KcEimLoop*> dec;
         for (KcEimLoop& P : L)
-            if (!P.done && (rc = kc_eim_keep_phase(h, P, s))) return fail_at(P, rc);
+            if (!P.done) {
+                if ((rc = kc_eim_keep_phase(h, P, s))) return fail_at(P, rc);
+                if (P.passed) dec.push_back(&P);
+            }
+        if ((rc = kc_eim_compact_phase(h, dec, s))) return rc;
         if ((rc = kc_eim_wait(h, s))) return rc;
+        if (!dec.empty()) {
+            const uint32_t* o4h = (const uint32_t*)h->pinned("eim.k4", 16ull * dec.size());
+            for (size_t q = 0; q < dec.size(); ++q)
+                for (int f = 0; f < 4; ++f) dec[q]->hw[4 + f] = o4h[4 * q + f];
+        }
         for (KcEimLoop& P : L)
             if (!P.done) kc_eim_end_iter(h, P);
     }
