@@ -561,6 +561,7 @@ def time_gon(kc, torch, Xd, k, steps, warmup, resident=True):
         st.synchronize()
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
+    nint = h.counter("resident_integer")   # read before the status clears it
     status = h.device_status()
     if status:
         raise SystemExit("device status 0x%x" % status)
@@ -573,7 +574,7 @@ def time_gon(kc, torch, Xd, k, steps, warmup, resident=True):
                    sources=["kc_block.hip", "kc_device.h"])
     elif res_l > 0:
         out.update(engine="k_gon_resident", kern_ms=res_ms, launches=res_l,
-                   sources=["kc_resident.hip", "kc_device.h"])
+                   sources=["kc_resident.hip", "kc_device.h"], integer_form=nint > 0)
     else:
         out.update(engine="k_gon_step", kern_ms=stp_ms, launches=stp_l,
                    sources=["kc_gon.hip", "kc_device.h"])
@@ -585,15 +586,17 @@ def gon_roofline(n, d, k, g):
     """Roofline of the dominant Gonzalez kernel.  Register-resident: bound by
     FP32 vector arithmetic, 3d flop per update (a subtraction and a fused
     multiply-add per coordinate) against the 157.3 TFLOP/s FP32 peak, with
-    the VALU issue-rate fraction beside it (2d + 1 instructions per update,
-    one integer min).  Streamed: bound by HBM, 4d + 8 bytes per point and
+    the VALU issue-rate fraction beside it: 2d + 1 instructions per update
+    (one integer min) in the canonical form, d + 1 in the resident engine's
+    exact-integer form (d fused multiply-adds and the min).  Streamed: bound by HBM, 4d + 8 bytes per point and
     step against 8 TB/s."""
     kern = g["engine"]
     if kern in ("k_gon_resident", "k_gon_block"):
         per = g["kern_ms"] / g["launches"]
         flops = n * k * 3 * d
         ach = flops / (per * 1e-3) / 1e12
-        ops = n * k * (2 * d + 1)
+        opu = d + 1 if g.get("integer_form") else 2 * d + 1
+        ops = n * k * opu
         issue = ops / (per * 1e-3) / 1e12
         roof = {"kernel": kern, "bound": "alu", "achieved": ach,
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -603,7 +606,8 @@ def gon_roofline(n, d, k, g):
                 "issue_rate": {"achieved": issue, "peak": VALU_PEAK_TOPS,
                                "unit": "T VALU lane-ops/s",
                                "frac": issue / VALU_PEAK_TOPS,
-                               "ops_per_update": 2 * d + 1}}
+                               "ops_per_update": opu,
+                               "form": "exact-integer" if g.get("integer_form") else "canonical"}}
     else:
         per = g["kern_ms"] / g["launches"]
         byt = n * (4 * d + 8)             # read d coords + mind, write mind

@@ -148,8 +148,11 @@ int kc_timing_read(kc_handle* h, const char* name, double* ms, int64_t* launches
  * exact FP64 (summed over its iterations; a batch sums over its EIM
  * problems that sample).  "assign_rescored": points the most recent assignment on the
  * handle rescored in FP64 (uncertified nearest center, or a possible
- * maximiser of the radius; a point may count twice).  KC_EINVAL for an
- * unknown name. */
+ * maximiser of the radius; a point may count twice).  "resident_integer":
+ * segments that the register-resident Gonzalez engine ran in its
+ * exact-integer form (d >= 8, every coordinate an integer of magnitude at
+ * most M with 5 d M^2 <= 2^24) since kc_device_status last cleared the
+ * handle's status.  KC_EINVAL for an unknown name. */
 int kc_counter_read(kc_handle* h, const char* name, int64_t* value);
 
 /* Synchronises `stream`, then reads and clears the handle's device status

@@ -828,6 +828,9 @@ int kc_counter_read(kc_handle* h, const char* name, int64_t* value)
     } else if (!strcmp(name, "eim_refined")) {
         *value = h->eim_refined;
         return KC_OK;
+    } else if (!strcmp(name, "resident_integer")) {
+        src = h->status_word + 2;   // counted by the resident kernels
+        words = 1;
     } else if (!strcmp(name, "assign_rescored")) {
         src = h->last_assign_nlist;   // one count
         words = 1;

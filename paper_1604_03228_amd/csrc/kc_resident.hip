@@ -35,6 +35,21 @@
 // so the leader runs ahead of the workers and only the workers' arithmetic
 // on their points remains per step.
 //
+// Exact-integer form.  When every coordinate of a segment is an integer of
+// magnitude at most M, with 5 d M^2 <= 2^24, every partial sum of the
+// canonical distance and of K + ||c||^2 - 2 x.c (K = d M^2) is an integer
+// of magnitude at most 2^24, so both are exact in FP32.  Such a segment's
+// workers then keep m' = min over centers of (K + ||c||^2 - 2 x.c), with
+// -2x in place of x, and apply a center in d FMAs and one min per point
+// instead of 2d + 1 instructions.  m' >= K - ||x||^2 >= 0, so the min is
+// the same unsigned compare of bit patterns; a key is (m' - K) + ||x||^2,
+// the canonical FP32 value bit for bit.
+// Each block checks its own points (and resumed min-distances) while
+// loading them and sets bit 63 of its first bound word when one fails
+// (keys are non-negative, so that bit is otherwise clear); every block of
+// the segment reads all of them in the first exchange and so takes the
+// same form.  The leader always computes canonical distances.
+//
 // Exchange words carry their round in the low word, so no word needs a
 // fence: (bits of the FP32 value << 32) | (tag << 16) | block-local index,
 // index 0xFFFF = "no point" (waves without points), tag = round + 1 mod 2^16.
@@ -44,6 +59,7 @@
 // whose wait exceeds the spin limit raises abort_flag; every block then
 // leaves its loop.
 #include <algorithm>
+#include <type_traits>
 
 #include "kc_device.h"
 #include "kc_internal.h"
@@ -71,6 +87,29 @@ struct KcLaCap {
 
 __device__ __forceinline__ uint32_t kc_la_tag(uint32_t r) { return (r + 1u) & 0xFFFFu; }
 
+#define KC_LA_NOTINT 0x8000000000000000ull   // bound word of round 0: a block's points fail
+// The exact-integer form is built for d >= 8 (at d = 2 and 3 its extra code
+// outside the apply loop makes the kernels spill).
+#define KC_LA_INT_FORM(d) ((d) >= 8)
+
+// Largest M with 5 d M^2 <= 2^24, and the offset K = d M^2: for integer
+// coordinates up to M, every partial sum of a squared distance and of
+// K + ||c||^2 - 2 x.c is an integer of magnitude at most 5 d M^2, so exact
+// in FP32, and K + ||c||^2 - 2 x.c = K - ||x||^2 + |x - c|^2 >= 0.
+constexpr unsigned long long kc_la_int_m(int d)
+{
+    unsigned long long m = 0;
+    while (5ull * (unsigned long long)d * (m + 1) * (m + 1) <= (1ull << 24)) ++m;
+    return m;
+}
+constexpr float kc_la_int_bound(int d) { return (float)kc_la_int_m(d); }
+constexpr float kc_la_int_offset(int d) { return (float)((unsigned long long)d * kc_la_int_m(d) * kc_la_int_m(d)); }
+
+__device__ __forceinline__ bool kc_la_small_int(float v, float bound)
+{
+    return __builtin_fabsf(v) <= bound && v == __builtin_rintf(v);
+}
+
 // Exchange word of key `key` (0: no point) of the block whose points start
 // at `blk0`, in round tag `tag`.
 __device__ __forceinline__ u64 kc_la_word(u64 key, uint32_t blk0, uint32_t tag)
@@ -92,6 +131,12 @@ __device__ __forceinline__ u64 kc_la_decode(u64 w, uint32_t g)
 // An opaque copy: the compiler cannot hoist expressions of it out of the
 // loop it is taken in.
 __device__ __forceinline__ uint32_t kc_opaque(uint32_t v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+__device__ __forceinline__ float kc_opaque_f(float v)
 {
     asm volatile("" : "+v"(v));
     return v;
@@ -131,6 +176,7 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
     if (len_ptr) len = min(len, *len_ptr);   // actual length known on the device
     __shared__ u64 sCk[CMAX];                 // candidate keys at the round's start
     __shared__ float sCx[D][CMAX];            // candidate coordinates
+    __shared__ float sCc[CMAX];               // K + their squared norms (exact-integer form)
     __shared__ uint32_t sQf[CMAX + 1];        // the round's queue: 0 empty, slot + 1 of a
                                               // center, KC_LA_END | state at the end
     __shared__ float sPm[CMAX];               // the leader's packing of live candidates
@@ -139,6 +185,8 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
     __shared__ u64 red[KC_LA_WAVES];
     __shared__ uint32_t sWc[KC_LA_WAVES];
     __shared__ u64 sT[KC_LA_WAVES];           // each worker wave's (K+1)-th key
+    __shared__ uint32_t sNi, sNx;             // this block's points / the segment's fail
+                                              // the exact-integer check
 
     const uint32_t NWB = gs * KC_LA_WPB;    // exchange words of this segment
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
@@ -158,6 +206,10 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
     float x[PPT][D];
     float m[PPT];
     if (tid < D) cc0[tid] = coord(first, tid);
+    if (tid == 0) {
+        sNi = 0;
+        sNx = 0;
+    }
     if (!leader) {
         if (xa_rows) {
             // kc_resident_row_floats(D) floats per load: the host takes this
@@ -215,7 +267,21 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                 if (i < len) m[p] = kc_fmin_nn(m[p], mind_in[base + i]);
             }
         }
+        // the exact-integer check of this lane's points and min-distances
+        constexpr float KM = kc_la_int_bound(D);
+        bool ok = KC_LA_INT_FORM(D);
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            if (i0 + p * KC_LA_WPTS < len) {
+                bool okp = m[p] == __builtin_rintf(m[p]) && m[p] <= 16777216.f;
+#pragma unroll
+                for (int j = 0; j < D; ++j) okp = okp && kc_la_small_int(x[p][j], KM);
+                ok = ok && okp;
+            }
+        }
+        if (__ballot(!ok) != 0 && lane == 0) sNi = 1u;
     }
+    bool exact = false;   // the segment's points passed the check (decided in round 0)
 
     int t = 0;   // keys recorded (tracked by the leader)
     for (uint32_t r = 0;; ++r) {
@@ -234,7 +300,15 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
                 const uint32_t i = i0_r + p * KC_LA_WPTS;
-                u64 v = i < len ? kc_pack(m[p], i) : 0ull;
+                float mv = m[p];
+                if (exact) {   // (m' - K) + ||x||^2, with x held as -2x
+                    // (recomputed each round, not held next to the points)
+                    float xx = kc_opaque_f(0.f);
+#pragma unroll
+                    for (int j = 0; j < D; ++j) xx = __builtin_fmaf(x[p][j], x[p][j], xx);
+                    mv = (m[p] - kc_la_int_offset(D)) + 0.25f * xx;
+                }
+                u64 v = i < len ? kc_pack(mv, i) : 0ull;
 #pragma unroll
                 for (int j = 0; j < KC_LA_KK; ++j) {
                     const u64 hi = kc_umax64(top[j], v);
@@ -270,13 +344,16 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
             u64 tb = 0;
 #pragma unroll
             for (int w = 1; w < KC_LA_WAVES; ++w) tb = kc_umax64(tb, sT[w]);
-            __hip_atomic_store(rbb + KC_LA_WPB - 1, kc_la_word(tb, blk0, tag), __ATOMIC_RELAXED,
+            u64 wb = kc_la_word(tb, blk0, tag);
+            if (r == 0 && sNi != 0) wb |= KC_LA_NOTINT;
+            __hip_atomic_store(rbb + KC_LA_WPB - 1, wb, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
 
         // ---- 2. every block's words of this round: each thread waits for
         // its own words, then the block meets once
         int ab = 0;
+        uint32_t ni = 0;   // a round-0 bound word carried the failed check
         u64 tl = 0;   // largest bound word this thread received
         u64 wv[KC_LA_NPT];   // this thread's words e = tid + q*KC_LA_BLOCK, decoded
 #pragma unroll
@@ -299,10 +376,15 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                 for (int q = 0; q < KC_LA_NPT; ++q) {
                     const uint32_t e = tid_r + q * KC_LA_BLOCK;
                     if (e < NWB && !((have >> q) & 1u)) {
-                        const u64 w = wr[q];
+                        u64 w = wr[q];
                         if ((((uint32_t)w) >> 16) == tag) {
+                            const bool bound = e % KC_LA_WPB == KC_LA_WPB - 1;
+                            if (bound) {
+                                ni |= (uint32_t)(w >> 63);
+                                w &= ~KC_LA_NOTINT;
+                            }
                             const u64 kw = kc_la_decode<PPT>(w, e / KC_LA_WPB);
-                            if (e % KC_LA_WPB == KC_LA_WPB - 1) tl = kc_umax64(tl, kw);
+                            if (bound) tl = kc_umax64(tl, kw);
                             else wv[q] = kw;   // bound words stay 0 here
                             have |= 1u << q;
                         } else {
@@ -331,9 +413,26 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
         tl = kc_wave_max_key(tl);
         if (lane == 0) red[wave] = tl;
         for (uint32_t e = tid; e <= CMAX; e += KC_LA_BLOCK) sQf[e] = 0;
+        if (ni) sNx = 1u;
         if (__syncthreads_or(ab)) {
             if (recorder && t < k) keys[t] = 0;
             break;
+        }
+        if (r == 0) {
+            exact = KC_LA_INT_FORM(D) && __builtin_amdgcn_readfirstlane(sNx) == 0;
+            if (exact && recorder) atomicAdd(status + 2, 1u);
+            if (exact && !leader) {
+                // into the exact-integer form: m' = (m - ||x||^2) + K, x -> -2x
+#pragma unroll
+                for (int p = 0; p < PPT; ++p) {
+                    float xx = 0.f;
+#pragma unroll
+                    for (int j = 0; j < D; ++j) xx = __builtin_fmaf(x[p][j], x[p][j], xx);
+                    m[p] = (m[p] - xx) + kc_la_int_offset(D);
+#pragma unroll
+                    for (int j = 0; j < D; ++j) x[p][j] *= -2.f;
+                }
+            }
         }
 
         // ---- 3. bound tau (the largest block bound) and candidate set C
@@ -405,8 +504,13 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
 #pragma unroll
                 for (int j = 0; j < D; ++j) v[j] = xs[(uint64_t)j * stride + base + ci];
             }
+            float vv = 0.f;
 #pragma unroll
-            for (int j = 0; j < D; ++j) sCx[j][tid_r] = v[j];
+            for (int j = 0; j < D; ++j) {
+                sCx[j][tid_r] = v[j];
+                vv = __builtin_fmaf(v[j], v[j], vv);
+            }
+            sCc[tid_r] = vv + kc_la_int_offset(D);   // K + ||c||^2
         }
         __syncthreads();
 
@@ -429,7 +533,15 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
             // round: it stops competing, and once the live candidates fit in
             // fewer chunks of 64 they are packed (through LDS) into the
             // first nv positions, so a step touches ceil(nv/64) chunks.
+            // In the exact-integer form a lane holds -2x for its candidates'
+            // coordinates and ||x||^2 - K beside them, and a step computes
+            // (K + ||c||^2) - 2 x.c + (||x||^2 - K), the exact distance.
+            uint32_t nq = 0;   // centers queued this round
+            auto lead = [&](auto form) {
+            constexpr bool EX = decltype(form)::value;
+            constexpr float K2 = 2.f * kc_la_int_offset(D);
             uint32_t ci[QL], os[QL];
+            float xq[EX ? QL : 1];
             u64 bl = 0;
             uint32_t bs = 0;
             uint32_t nv = nc, qn = (nc + 63) / 64;
@@ -447,7 +559,8 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                 ci[q] = kc_key_idx(kq);
                 os[q] = sl;
 #pragma unroll
-                for (int j = 0; j < D; ++j) x[q][j] = sCx[j][sl];
+                for (int j = 0; j < D; ++j) x[q][j] = EX ? -2.f * sCx[j][sl] : sCx[j][sl];
+                if constexpr (EX) xq[q] = sCc[sl] - K2;
                 if (kq > bl) {   // every key of C is above tau
                     bl = kq;
                     bs = sl;
@@ -455,10 +568,10 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
             }
             // coordinates of this lane's best candidate, read ahead of the
             // wave's argmax so the winner's come out of registers
-            float bx[D];
+            float bx[D], bq = 0.f;
 #pragma unroll
             for (int j = 0; j < D; ++j) bx[j] = sCx[j][bs];
-            uint32_t nq = 0;
+            if constexpr (EX) bq = sCc[bs];
             int ns = 0;
             do {
                 // the loop's control values are wave-uniform: keep them in
@@ -498,6 +611,8 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
 #pragma unroll
                     for (int j = 0; j < D; ++j)
                         cc[j] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bx[j]), wl));
+                    const float ccq =
+                        EX ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bq), wl)) : 0.f;
                     ++nq;
                     bl = 0;
                     uint32_t live = 0;
@@ -507,9 +622,17 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                         if (g < (int)qn) {
 #pragma unroll
                             for (int q = g; q < g + 2 && q < QL; ++q) {
-                                float s = 0.f;
+                                float s;
+                                if constexpr (EX) {
+                                    s = ccq;
 #pragma unroll
-                                for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[q][j], cc[j]);
+                                    for (int j = 0; j < D; ++j) s = __builtin_fmaf(x[q][j], cc[j], s);
+                                    s += xq[q];
+                                } else {
+                                    s = 0.f;
+#pragma unroll
+                                    for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[q][j], cc[j]);
+                                }
                                 m[q] = kc_fmin_nn(m[q], s);
                                 const u64 kq = kc_pack(m[q], ci[q]);
                                 const bool lv = q * 64 + lane < nv && kq > tau;
@@ -549,15 +672,25 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                                     ci[q] = sPi[p];
                                     os[q] = sPo[p];
 #pragma unroll
-                                    for (int j = 0; j < D; ++j) x[q][j] = sCx[j][os[q]];
+                                    for (int j = 0; j < D; ++j)
+                                        x[q][j] = EX ? -2.f * sCx[j][os[q]] : sCx[j][os[q]];
+                                    if constexpr (EX) xq[q] = sCc[os[q]] - K2;
                                 }
                             }
                         }
                     }
 #pragma unroll
                     for (int j = 0; j < D; ++j) bx[j] = sCx[j][bs];
+                    if constexpr (EX) bq = sCc[bs];
                 }
             } while (state == 0);
+            };
+            if constexpr (KC_LA_INT_FORM(D)) {
+                if (exact) lead(std::true_type{});
+                else lead(std::false_type{});
+            } else {
+                lead(std::false_type{});
+            }
             if (state == 3 && recorder) {
                 keys[t] = 0;
                 __hip_atomic_store(abort_flag, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -571,115 +704,136 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
             // Two forms of the apply loop: where registers allow, a
             // double-buffered one (no vector copies between steps); for the
             // variants whose points leave no room for it (it would spill
-            // VGPRs in this loop), the single-buffer one.
+            // VGPRs in this loop), the single-buffer one.  Each is built
+            // once per arithmetic form (canonical, or exact-integer), so a
+            // loop holds the registers of one form only.
             constexpr bool kDB = PPT * (D + 1) + 3 * D <= 180;
-            if constexpr (kDB) {
-                // Apply the queued centers in order.  While the center of entry
-                // i is applied, entry i+1 and its coordinates load from LDS; the
-                // coordinates then move into scalar registers (they are
-                // block-uniform), alternating between two scalar sets so that no
-                // vector copies are needed between steps.
-                auto apply = [&](const float(&c)[D]) {
+            auto work = [&](auto form) {
+                constexpr bool EX = decltype(form)::value;
+                // one center: coordinates c, and K + ||c||^2 in the
+                // exact-integer form (x then holds -2x)
+                auto apply = [&](const float(&c)[D], float cq) {
 #pragma unroll
                     for (int p = 0; p < PPT; ++p) {
-                        float s = 0.f;
+                        float s;
+                        if constexpr (EX) {
+                            s = cq;
 #pragma unroll
-                        for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[p][j], c[j]);
+                            for (int j = 0; j < D; ++j) s = __builtin_fmaf(x[p][j], c[j], s);
+                        } else {
+                            s = 0.f;
+#pragma unroll
+                            for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[p][j], c[j]);
+                        }
                         m[p] = kc_fmin_nn(m[p], s);
                     }
                 };
-                auto entry = [&](uint32_t at) -> uint32_t {
-                    return __builtin_amdgcn_readfirstlane(__hip_atomic_load(
-                        &sQf[at], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                auto to_sgpr = [](float v) -> float {
+                    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
                 };
-                auto wait_entry = [&](uint32_t at) -> uint32_t {
-                    uint32_t e;
-                    while ((e = entry(at)) == 0) __builtin_amdgcn_s_sleep(1);
-                    return e;
-                };
-                float tv[D];   // coordinates in flight (VGPRs)
-                auto load = [&](uint32_t e) {
+                if constexpr (kDB) {
+                    // Apply the queued centers in order.  While the center of
+                    // entry i is applied, entry i+1 and its coordinates load
+                    // from LDS; the coordinates then move into scalar registers
+                    // (they are block-uniform), alternating between two scalar
+                    // sets so that no vector copies are needed between steps.
+                    auto entry = [&](uint32_t at) -> uint32_t {
+                        return __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                            &sQf[at], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                    };
+                    auto wait_entry = [&](uint32_t at) -> uint32_t {
+                        uint32_t e;
+                        while ((e = entry(at)) == 0) __builtin_amdgcn_s_sleep(1);
+                        return e;
+                    };
+                    float tv[D], tq = 0.f;   // coordinates (and K + norm) in flight (VGPRs)
+                    auto load = [&](uint32_t e) {
 #pragma unroll
-                    for (int j = 0; j < D; ++j) tv[j] = sCx[j][e - 1];
-                };
-                auto uniform = [&](float(&c)[D]) {
+                        for (int j = 0; j < D; ++j) tv[j] = sCx[j][e - 1];
+                        if constexpr (EX) tq = sCc[e - 1];
+                    };
+                    auto uniform = [&](float(&c)[D], float& cq) {
 #pragma unroll
-                    for (int j = 0; j < D; ++j)
-                        c[j] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(tv[j])));
-                };
-                float ca[D], cb[D];   // scalar sets
-                uint32_t i = 0;
-                uint32_t f = wait_entry(0);
-                if (!(f & KC_LA_END)) {
-                    load(f);
-                    uniform(ca);
-                }
-                while (!(f & KC_LA_END)) {
-                    // entry i is a center, its coordinates in ca
-                    uint32_t g = entry(++i);
-                    if (g != 0 && !(g & KC_LA_END)) load(g);
-                    apply(ca);
-                    if (g == 0) {
-                        g = wait_entry(i);
-                        if (!(g & KC_LA_END)) load(g);
+                        for (int j = 0; j < D; ++j) c[j] = to_sgpr(tv[j]);
+                        if constexpr (EX) cq = to_sgpr(tq);
+                    };
+                    float ca[D], cb[D], qa = 0.f, qb = 0.f;   // scalar sets
+                    uint32_t i = 0;
+                    uint32_t f = wait_entry(0);
+                    if (!(f & KC_LA_END)) {
+                        load(f);
+                        uniform(ca, qa);
                     }
-                    if (g & KC_LA_END) {
-                        f = g;
-                        break;
+                    while (!(f & KC_LA_END)) {
+                        // entry i is a center, its coordinates in ca
+                        uint32_t g = entry(++i);
+                        if (g != 0 && !(g & KC_LA_END)) load(g);
+                        apply(ca, qa);
+                        if (g == 0) {
+                            g = wait_entry(i);
+                            if (!(g & KC_LA_END)) load(g);
+                        }
+                        if (g & KC_LA_END) {
+                            f = g;
+                            break;
+                        }
+                        uniform(cb, qb);
+                        // entry i is a center, its coordinates in cb
+                        f = entry(++i);
+                        if (f != 0 && !(f & KC_LA_END)) load(f);
+                        apply(cb, qb);
+                        if (f == 0) {
+                            f = wait_entry(i);
+                            if (!(f & KC_LA_END)) load(f);
+                        }
+                        if (!(f & KC_LA_END)) uniform(ca, qa);
                     }
-                    uniform(cb);
-                    // entry i is a center, its coordinates in cb
-                    f = entry(++i);
-                    if (f != 0 && !(f & KC_LA_END)) load(f);
-                    apply(cb);
-                    if (f == 0) {
-                        f = wait_entry(i);
-                        if (!(f & KC_LA_END)) load(f);
-                    }
-                    if (!(f & KC_LA_END)) uniform(ca);
-                }
-                state = f & ~KC_LA_END;
-            } else {
-                // apply the queued centers in order; entry i+1 and its
-                // coordinates are read before center i is applied, so most of
-                // the LDS latency hides behind the arithmetic
-                uint32_t i = 0, f = 0;
-                float cv[D];
-                for (;;) {
-                    if (f == 0) {
+                    state = f & ~KC_LA_END;
+                } else {
+                    // apply the queued centers in order; entry i+1 and its
+                    // coordinates are read before center i is applied, so most
+                    // of the LDS latency hides behind the arithmetic
+                    uint32_t i = 0, f = 0;
+                    float cv[D], cvq = 0.f;
+                    for (;;) {
+                        if (f == 0) {
+                            f = __hip_atomic_load(&sQf[i], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+                            if (f == 0) {
+                                __builtin_amdgcn_s_sleep(1);
+                                continue;
+                            }
+                            if (!(f & KC_LA_END)) {
+#pragma unroll
+                                for (int j = 0; j < D; ++j) cv[j] = sCx[j][f - 1];
+                                if constexpr (EX) cvq = sCc[f - 1];
+                            }
+                        }
+                        if (f & KC_LA_END) {
+                            state = f & ~KC_LA_END;
+                            break;
+                        }
+                        float cc[D];   // uniform: held in SGPRs
+#pragma unroll
+                        for (int j = 0; j < D; ++j) cc[j] = to_sgpr(cv[j]);
+                        const float ccq = EX ? to_sgpr(cvq) : 0.f;
+                        ++i;
                         f = __hip_atomic_load(&sQf[i], __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-                        if (f == 0) {
-                            __builtin_amdgcn_s_sleep(1);
-                            continue;
-                        }
-                        if (!(f & KC_LA_END)) {
+                        if (f != 0 && !(f & KC_LA_END)) {
 #pragma unroll
                             for (int j = 0; j < D; ++j) cv[j] = sCx[j][f - 1];
+                            if constexpr (EX) cvq = sCc[f - 1];
                         }
-                    }
-                    if (f & KC_LA_END) {
-                        state = f & ~KC_LA_END;
-                        break;
-                    }
-                    float cc[D];   // uniform: held in SGPRs
-#pragma unroll
-                    for (int j = 0; j < D; ++j)
-                        cc[j] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(cv[j])));
-                    ++i;
-                    f = __hip_atomic_load(&sQf[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    if (f != 0 && !(f & KC_LA_END)) {
-#pragma unroll
-                        for (int j = 0; j < D; ++j) cv[j] = sCx[j][f - 1];
-                    }
-#pragma unroll
-                    for (int p = 0; p < PPT; ++p) {
-                        float s = 0.f;
-#pragma unroll
-                        for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[p][j], cc[j]);
-                        m[p] = kc_fmin_nn(m[p], s);
+                        apply(cc, ccq);
                     }
                 }
+            };
+            if constexpr (KC_LA_INT_FORM(D)) {
+                if (exact) work(std::true_type{});
+                else work(std::false_type{});
+            } else {
+                work(std::false_type{});
             }
         }
         if (state >= 2) break;
@@ -688,7 +842,14 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             const uint32_t i = i0 + p * KC_LA_WPTS;
-            if (i < len) mind[base + i] = m[p];
+            float mv = m[p];
+            if (exact) {
+                float xx = 0.f;
+#pragma unroll
+                for (int j = 0; j < D; ++j) xx = __builtin_fmaf(x[p][j], x[p][j], xx);
+                mv = (m[p] - kc_la_int_offset(D)) + 0.25f * xx;
+            }
+            if (i < len) mind[base + i] = mv;
         }
     } else if (lb == 0) {
         // keys past an early stop (radius 0, or an abort) read as radius 0
