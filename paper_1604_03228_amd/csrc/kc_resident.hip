@@ -179,6 +179,7 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
     __shared__ float sCc[CMAX];               // K + their squared norms (exact-integer form)
     __shared__ uint32_t sQf[CMAX + 1];        // the round's queue: 0 empty, slot + 1 of a
                                               // center, KC_LA_END | state at the end
+    __shared__ u64 sQk[CMAX];                 // the keys of the round's certified steps
     __shared__ float sPm[CMAX];               // the leader's packing of live candidates
     __shared__ uint32_t sPi[CMAX], sPo[CMAX];
     __shared__ float cc0[D];
@@ -536,7 +537,9 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
             // In the exact-integer form a lane holds -2x for its candidates'
             // coordinates and ||x||^2 - K beside them, and a step computes
             // (K + ||c||^2) - 2 x.c + (||x||^2 - K), the exact distance.
-            uint32_t nq = 0;   // centers queued this round
+            uint32_t nq = 0;      // centers queued this round
+            int ns = 0;           // steps certified this round (at most nc)
+            const int t0 = t;     // their keys go to keys[t0 + i] at the round's end
             auto lead = [&](auto form) {
             constexpr bool EX = decltype(form)::value;
             constexpr float K2 = 2.f * kc_la_int_offset(D);
@@ -572,7 +575,6 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
 #pragma unroll
             for (int j = 0; j < D; ++j) bx[j] = sCx[j][bs];
             if constexpr (EX) bq = sCc[bs];
-            int ns = 0;
             do {
                 // the loop's control values are wave-uniform: keep them in
                 // SGPRs so its branches stay scalar
@@ -582,7 +584,7 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                 qn = __builtin_amdgcn_readfirstlane(qn);
                 const u64 b = kc_wave_max_key(bl);
                 if (b > tau) {
-                    if (recorder) keys[t] = b;
+                    if (lane == 0) sQk[ns] = b;
                     ++t;
                     ++ns;
                     state = ((b >> 32) == 0 || t >= k) ? 2u : 0u;   // radius 0 or k centers
@@ -601,19 +603,16 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                 }
                 state = __builtin_amdgcn_readfirstlane(state);
                 if (state == 0) {
-                    // queue the winner's slot for the workers; its
-                    // coordinates into SGPRs from the winning lane's copy
+                    // the winner's slot, and its coordinates into SGPRs from
+                    // the winning lane's copy
                     const int wl = (int)__builtin_ctzll(__ballot(bl == b));
-                    if (lane == 0)
-                        __hip_atomic_store(&sQf[nq], __builtin_amdgcn_readlane(bs, wl) + 1u,
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    const uint32_t wslot = __builtin_amdgcn_readlane(bs, wl) + 1u;
                     float cc[D];
 #pragma unroll
                     for (int j = 0; j < D; ++j)
                         cc[j] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bx[j]), wl));
                     const float ccq =
                         EX ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bq), wl)) : 0.f;
-                    ++nq;
                     bl = 0;
                     uint32_t live = 0;
                     // chunks in pairs without a branch between them
@@ -644,6 +643,14 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                             }
                         }
                     }
+                    // Queue the center for the workers only now: the worker
+                    // wave sharing the leader's SIMD then applies it during
+                    // the leader's next argmax (few vector instructions)
+                    // instead of competing with the update above.
+                    if (lane == 0)
+                        __hip_atomic_store(&sQf[nq], wslot, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                    ++nq;
                     if (live + 64 <= qn * 64) {
                         // pack the live candidates into positions 0..live-1
                         uint32_t pos = 0;
@@ -690,6 +697,9 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                 else lead(std::false_type{});
             } else {
                 lead(std::false_type{});
+            }
+            for (int u = (int)lane; u < ns; u += 64) {
+                if (lb == 0) keys[t0 + u] = sQk[u];
             }
             if (state == 3 && recorder) {
                 keys[t] = 0;
