@@ -607,6 +607,19 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                     // the winning lane's copy
                     const int wl = (int)__builtin_ctzll(__ballot(bl == b));
                     const uint32_t wslot = __builtin_amdgcn_readlane(bs, wl) + 1u;
+                    // Queue the center for the workers.  In the canonical
+                    // form the workers' arithmetic bounds the steps, so they
+                    // get it at once; in the exact-integer form the leader's
+                    // chain does, and the center is queued after the update
+                    // below, so that the worker wave sharing the leader's
+                    // SIMD applies it during the leader's next argmax (few
+                    // vector instructions) instead of during the update.
+                    if constexpr (!EX) {
+                        if (lane == 0)
+                            __hip_atomic_store(&sQf[nq], wslot, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                        ++nq;
+                    }
                     float cc[D];
 #pragma unroll
                     for (int j = 0; j < D; ++j)
@@ -643,14 +656,12 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                             }
                         }
                     }
-                    // Queue the center for the workers only now: the worker
-                    // wave sharing the leader's SIMD then applies it during
-                    // the leader's next argmax (few vector instructions)
-                    // instead of competing with the update above.
-                    if (lane == 0)
-                        __hip_atomic_store(&sQf[nq], wslot, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                    ++nq;
+                    if constexpr (EX) {
+                        if (lane == 0)
+                            __hip_atomic_store(&sQf[nq], wslot, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                        ++nq;
+                    }
                     if (live + 64 <= qn * 64) {
                         // pack the live candidates into positions 0..live-1
                         uint32_t pos = 0;
