@@ -710,6 +710,67 @@ __global__ __launch_bounds__(256) void k_bf16_err(const float* __restrict__ X,
         ex[p0 + threadIdx.x] = (float)(sqrt(acc) * (1.0 + 1e-12)) * (1.f + 1e-6f);
 }
 
+// The same radius for dense rows (ld == d, at most KC_ERR_DENSE_D
+// coordinates): a block's 64 rows are one contiguous span of 64 d elements,
+// streamed with 16-byte FP32 and 8-byte BF16 loads of 4 elements each (no
+// index arithmetic per element).  The squared differences go to LDS in
+// element order; then four threads per point sum fixed quarters of its row
+// and combine them in a fixed pairing, so the value does not depend on
+// scheduling.  The FP64 sum of d <= 96 non-negative terms is within
+// 96 * 2^-53 of exact, far inside the 1e-12 rounding-up margin.
+#define KC_ERR_DENSE_D 96
+__global__ __launch_bounds__(256) void k_bf16_err_dense(const float* __restrict__ X,
+                                                        const uint16_t* __restrict__ Xb, int d,
+                                                        uint32_t n, float* __restrict__ ex)
+{
+    extern __shared__ double se_d[];   // 64 * d squared differences, element order
+    const uint32_t p0 = blockIdx.x * 64u;
+    const uint32_t np = min(64u, n - p0);
+    const uint64_t e0 = (uint64_t)p0 * (uint64_t)d;
+    const uint32_t ne = np * (uint32_t)d;
+    for (uint32_t c = threadIdx.x; c * 4u < ne; c += blockDim.x) {
+        const uint32_t e = c * 4u;
+        float xv[4];
+        uint32_t bv[4];
+        if (e + 4u <= ne) {
+            const float4 x4 = *(const float4*)(X + e0 + e);
+            const uint2 b2 = *(const uint2*)(Xb + e0 + e);
+            xv[0] = x4.x;
+            xv[1] = x4.y;
+            xv[2] = x4.z;
+            xv[3] = x4.w;
+            bv[0] = b2.x & 0xFFFFu;
+            bv[1] = b2.x >> 16;
+            bv[2] = b2.y & 0xFFFFu;
+            bv[3] = b2.y >> 16;
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool in = e + (uint32_t)u < ne;
+                xv[u] = in ? X[e0 + e + u] : 0.f;
+                bv[u] = in ? (uint32_t)Xb[e0 + e + u] : 0u;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (e + (uint32_t)u < ne) {
+                const double v = (double)kc_bf16_to_f32((uint16_t)bv[u]) - (double)xv[u];
+                se_d[e + u] = v * v;
+            }
+    }
+    __syncthreads();
+    const uint32_t i = threadIdx.x >> 2, q = threadIdx.x & 3u;
+    const int per = (d + 3) / 4;
+    double acc = 0.0;
+    if (i < np) {
+        const int j0 = (int)q * per, j1 = min(d, j0 + per);
+        for (int j = j0; j < j1; ++j) acc += se_d[i * (uint32_t)d + (uint32_t)j];
+    }
+    acc += __shfl_xor(acc, 1, 64);   // (q0 + q1) and (q2 + q3), the same in both lanes
+    acc += __shfl_xor(acc, 2, 64);   // their sum, the same in all four
+    if (q == 0 && i < np) ex[p0 + i] = (float)(sqrt(acc) * (1.0 + 1e-12)) * (1.f + 1e-6f);
+}
+
 // ---------------------------------------------------------------------------
 // assignment epilogue: certify, collect ambiguous points, radius lower bound
 
@@ -1200,7 +1261,12 @@ void kc_local_origin(const float* X, int64_t ld, int d, uint32_t n, float* mu, h
 void kc_bf16_err(const float* X, const uint16_t* Xb, int64_t ld, int d, uint32_t n, float* ex,
                  hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bf16_err, dim3((n + 63) / 64), dim3(256), 0, s, X, Xb, ld, d, n, ex);
+    if (ld == d && d <= KC_ERR_DENSE_D && (uintptr_t)X % 16 == 0 && (uintptr_t)Xb % 8 == 0)
+        hipLaunchKernelGGL(k_bf16_err_dense, dim3((n + 63) / 64), dim3(256),
+                           (size_t)64 * (size_t)d * sizeof(double), s, X, Xb, d, n, ex);
+    else
+        hipLaunchKernelGGL(k_bf16_err, dim3((n + 63) / 64), dim3(256), 0, s, X, Xb, ld, d, n,
+                           ex);
 }
 
 bool kc_radius_direct(uint32_t n, int d, const float* X, int64_t ld, const float* Cf, int dp,
