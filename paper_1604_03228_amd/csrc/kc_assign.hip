@@ -797,27 +797,74 @@ __device__ __forceinline__ void kc_block_append(bool pred, uint32_t val, uint32_
     if (pred) list[off + (uint32_t)__builtin_popcountll(b & ((1ull << lane) - 1ull))] = val;
 }
 
+// kc_block_append for PP values per thread: one atomic per block for all of
+// them.  Every thread of the block must call it.
+template <int PP>
+__device__ __forceinline__ void kc_block_append_pp(const bool (&pred)[PP],
+                                                   const uint32_t (&val)[PP], uint32_t* list,
+                                                   uint32_t* nlist)
+{
+    __shared__ uint32_t s_cnt[PP][16];
+    __shared__ uint32_t s_base;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+    u64 b[PP];
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+        b[q] = __ballot(pred[q]);
+        if (lane == 0) s_cnt[q][wave] = (uint32_t)__builtin_popcountll(b[q]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int q = 0; q < PP; ++q)
+            for (int w = 0; w < nw; ++w) tot += s_cnt[q][w];
+        s_base = tot ? atomicAdd(nlist, tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t off = s_base;   // values in order (q, wave, lane)
+#pragma unroll
+    for (int q = 0; q < PP; ++q) {
+        uint32_t o = off;
+        for (int w = 0; w < nw; ++w) {
+            if (w < wave) o += s_cnt[q][w];
+            off += s_cnt[q][w];
+        }
+        if (pred[q]) list[o + (uint32_t)__builtin_popcountll(b[q] & ((1ull << lane) - 1ull))] = val[q];
+    }
+}
+
 // With labels == NULL only the radius is wanted: an ambiguous point matters
 // only if its upper bound reaches the largest lower bound, and
 // k_radius_candidates lists exactly those, so ambiguity lists nothing.
-__global__ void k_assign_epilogue(uint32_t n, int d, KcMinOut O, const float* __restrict__ ex,
+#define KC_EPI_PP 4
+__global__ __launch_bounds__(256) void k_assign_epilogue(uint32_t n, int d, KcMinOut O,
+                                                         const float* __restrict__ ex,
                                   KcCenters C, int32_t* __restrict__ labels,
                                   float* __restrict__ hi_out, uint32_t* __restrict__ list,
                                   uint32_t* __restrict__ nlist, float* __restrict__ lo_max)
 {
-    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    // KC_EPI_PP points per thread, so that a block appends its ambiguous
+    // points with one atomic for KC_EPI_PP * 256 points (hundreds of
+    // thousands of them in a BF16 pass queue at that one word)
+    bool amb[KC_EPI_PP];
+    uint32_t pv[KC_EPI_PP];
     float lo_f = 0.f;
-    bool amb = false;
-    if (p < n) {
-        const KcMdBounds B = kc_md_bounds(O, p, ex, C, d, labels != nullptr);
-        if (labels) {
-            amb = !(B.lo_other > B.hi);
-            labels[p] = amb ? -1 : O.arg[p];
+#pragma unroll
+    for (int q = 0; q < KC_EPI_PP; ++q) {
+        const uint32_t p = (blockIdx.x * KC_EPI_PP + q) * blockDim.x + threadIdx.x;
+        amb[q] = false;
+        pv[q] = p;
+        if (p < n) {
+            const KcMdBounds B = kc_md_bounds(O, p, ex, C, d, labels != nullptr);
+            if (labels) {
+                amb[q] = !(B.lo_other > B.hi);
+                labels[p] = amb[q] ? -1 : O.arg[p];
+            }
+            hi_out[p] = (float)B.hi * (1.f + 1e-6f);
+            lo_f = fmaxf(lo_f, (float)B.lo_min * (1.f - 1e-6f));
         }
-        hi_out[p] = (float)B.hi * (1.f + 1e-6f);
-        lo_f = (float)B.lo_min * (1.f - 1e-6f);
     }
-    kc_block_append(amb, p, list, nlist);
+    kc_block_append_pp<KC_EPI_PP>(amb, pv, list, nlist);
     // block max of the lower bounds, one atomic per block
     __shared__ float red[4];
     float v = lo_f;
@@ -1313,8 +1360,8 @@ void kc_assign_finish(uint32_t n, int d, const float* X, int64_t ld, const KcCen
     kc_fill_u32((uint32_t*)lo_max, 0u, 1, s);
     kc_fill_u64((u64*)radius2, 0ull, 1, s);
     const dim3 g((n + 255) / 256);
-    hipLaunchKernelGGL(k_assign_epilogue, g, dim3(256), 0, s, n, d, O, ex, C, labels, hi, list,
-                       nlist, lo_max);
+    hipLaunchKernelGGL(k_assign_epilogue, dim3((n + 256 * KC_EPI_PP - 1) / (256 * KC_EPI_PP)),
+                       dim3(256), 0, s, n, d, O, ex, C, labels, hi, list, nlist, lo_max);
     hipLaunchKernelGGL(k_radius_candidates, g, dim3(256), 0, s, n, hi, lo_max, list, nlist);
     if (!R2) {
         kc_rescore_f64(X, ld, d, C.Cf, C.dp, k, k_dev, list, nlist, 2 * n, labels, radius2, s);
