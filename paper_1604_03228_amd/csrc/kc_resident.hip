@@ -103,7 +103,10 @@ constexpr unsigned long long kc_la_int_m(int d)
     return m;
 }
 constexpr float kc_la_int_bound(int d) { return (float)kc_la_int_m(d); }
-constexpr float kc_la_int_offset(int d) { return (float)((unsigned long long)d * kc_la_int_m(d) * kc_la_int_m(d)); }
+constexpr float kc_la_int_offset(int d)
+{
+    return (float)((unsigned long long)d * kc_la_int_m(d) * kc_la_int_m(d));
+}
 
 __device__ __forceinline__ bool kc_la_small_int(float v, float bound)
 {
@@ -541,167 +544,172 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
             int ns = 0;           // steps certified this round (at most nc)
             const int t0 = t;     // their keys go to keys[t0 + i] at the round's end
             auto lead = [&](auto form) {
-            constexpr bool EX = decltype(form)::value;
-            constexpr float K2 = 2.f * kc_la_int_offset(D);
-            uint32_t ci[QL], os[QL];
-            float xq[EX ? QL : 1];
-            u64 bl = 0;
-            uint32_t bs = 0;
-            uint32_t nv = nc, qn = (nc + 63) / 64;
+                constexpr bool EX = decltype(form)::value;
+                constexpr float K2 = 2.f * kc_la_int_offset(D);
+                uint32_t ci[QL], os[QL];
+                float xq[EX ? QL : 1];
+                u64 bl = 0;
+                uint32_t bs = 0;
+                uint32_t nv = nc, qn = (nc + 63) / 64;
 #pragma unroll
-            for (int q = 0; q < QL; ++q) {
-                // slots past nc hold stale LDS values: their key is taken as 0
-                // (min-distance 0, never live), so their coordinates may be
-                // anything and the loads need no mask (at d = 16 with 9 points
-                // per lane this costs a few spilled VGPRs and is still faster)
-                const uint32_t sl = q * 64 + lane;
-                const bool v = sl < nc;
-                const u64 kraw = sCk[sl];
-                const u64 kq = v ? kraw : 0ull;
-                m[q] = kc_key_val(kq);
-                ci[q] = kc_key_idx(kq);
-                os[q] = sl;
+                for (int q = 0; q < QL; ++q) {
+                    // slots past nc hold stale LDS values: their key is taken as 0
+                    // (min-distance 0, never live), so their coordinates may be
+                    // anything and the loads need no mask (at d = 16 with 9 points
+                    // per lane this costs a few spilled VGPRs and is still faster)
+                    const uint32_t sl = q * 64 + lane;
+                    const bool v = sl < nc;
+                    const u64 kraw = sCk[sl];
+                    const u64 kq = v ? kraw : 0ull;
+                    m[q] = kc_key_val(kq);
+                    ci[q] = kc_key_idx(kq);
+                    os[q] = sl;
 #pragma unroll
-                for (int j = 0; j < D; ++j) x[q][j] = EX ? -2.f * sCx[j][sl] : sCx[j][sl];
-                if constexpr (EX) xq[q] = sCc[sl] - K2;
-                if (kq > bl) {   // every key of C is above tau
-                    bl = kq;
-                    bs = sl;
+                    for (int j = 0; j < D; ++j) x[q][j] = EX ? -2.f * sCx[j][sl] : sCx[j][sl];
+                    if constexpr (EX) xq[q] = sCc[sl] - K2;
+                    if (kq > bl) {   // every key of C is above tau
+                        bl = kq;
+                        bs = sl;
+                    }
                 }
-            }
-            // coordinates of this lane's best candidate, read ahead of the
-            // wave's argmax so the winner's come out of registers
-            float bx[D], bq = 0.f;
+                // coordinates of this lane's best candidate, read ahead of the
+                // wave's argmax so the winner's come out of registers
+                float bx[D], bq = 0.f;
 #pragma unroll
-            for (int j = 0; j < D; ++j) bx[j] = sCx[j][bs];
-            if constexpr (EX) bq = sCc[bs];
-            do {
-                // the loop's control values are wave-uniform: keep them in
-                // SGPRs so its branches stay scalar
-                t = __builtin_amdgcn_readfirstlane(t);
-                nq = __builtin_amdgcn_readfirstlane(nq);
-                nv = __builtin_amdgcn_readfirstlane(nv);
-                qn = __builtin_amdgcn_readfirstlane(qn);
-                const u64 b = kc_wave_max_key(bl);
-                if (b > tau) {
-                    if (lane == 0) sQk[ns] = b;
-                    ++t;
-                    ++ns;
-                    state = ((b >> 32) == 0 || t >= k) ? 2u : 0u;   // radius 0 or k centers
-                } else if (ns == 0) {
-                    // no certified step: only when the segment has no point
-                    // (b == 0, reported as radius 0); otherwise impossible
-                    if (b == 0) {
-                        if (recorder) keys[t] = 0;
+                for (int j = 0; j < D; ++j) bx[j] = sCx[j][bs];
+                if constexpr (EX) bq = sCc[bs];
+                do {
+                    // the loop's control values are wave-uniform: keep them in
+                    // SGPRs so its branches stay scalar
+                    t = __builtin_amdgcn_readfirstlane(t);
+                    nq = __builtin_amdgcn_readfirstlane(nq);
+                    nv = __builtin_amdgcn_readfirstlane(nv);
+                    qn = __builtin_amdgcn_readfirstlane(qn);
+                    const u64 b = kc_wave_max_key(bl);
+                    if (b > tau) {
+                        if (lane == 0) sQk[ns] = b;
                         ++t;
-                        state = 2;
+                        ++ns;
+                        state = ((b >> 32) == 0 || t >= k) ? 2u : 0u;   // radius 0 or k centers
+                    } else if (ns == 0) {
+                        // no certified step: only when the segment has no point
+                        // (b == 0, reported as radius 0); otherwise impossible
+                        if (b == 0) {
+                            if (recorder) keys[t] = 0;
+                            ++t;
+                            state = 2;
+                        } else {
+                            state = 3;
+                        }
                     } else {
-                        state = 3;
+                        state = 1;
                     }
-                } else {
-                    state = 1;
-                }
-                state = __builtin_amdgcn_readfirstlane(state);
-                if (state == 0) {
-                    // the winner's slot, and its coordinates into SGPRs from
-                    // the winning lane's copy
-                    const int wl = (int)__builtin_ctzll(__ballot(bl == b));
-                    const uint32_t wslot = __builtin_amdgcn_readlane(bs, wl) + 1u;
-                    // Queue the center for the workers.  In the canonical
-                    // form the workers' arithmetic bounds the steps, so they
-                    // get it at once; in the exact-integer form the leader's
-                    // chain does, and the center is queued after the update
-                    // below, so that the worker wave sharing the leader's
-                    // SIMD applies it during the leader's next argmax (few
-                    // vector instructions) instead of during the update.
-                    if constexpr (!EX) {
-                        if (lane == 0)
-                            __hip_atomic_store(&sQf[nq], wslot, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-                        ++nq;
-                    }
-                    float cc[D];
+                    state = __builtin_amdgcn_readfirstlane(state);
+                    if (state == 0) {
+                        // the winner's slot, and its coordinates into SGPRs from
+                        // the winning lane's copy
+                        const int wl = (int)__builtin_ctzll(__ballot(bl == b));
+                        const uint32_t wslot = __builtin_amdgcn_readlane(bs, wl) + 1u;
+                        // Queue the center for the workers.  In the canonical
+                        // form the workers' arithmetic bounds the steps, so they
+                        // get it at once; in the exact-integer form the leader's
+                        // chain does, and the center is queued after the update
+                        // below, so that the worker wave sharing the leader's
+                        // SIMD applies it during the leader's next argmax (few
+                        // vector instructions) instead of during the update.
+                        if constexpr (!EX) {
+                            if (lane == 0)
+                                __hip_atomic_store(&sQf[nq], wslot, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                            ++nq;
+                        }
+                        auto from_winner = [&](float v) -> float {
+                            return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), wl));
+                        };
+                        float cc[D];
 #pragma unroll
-                    for (int j = 0; j < D; ++j)
-                        cc[j] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bx[j]), wl));
-                    const float ccq =
-                        EX ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bq), wl)) : 0.f;
-                    bl = 0;
-                    uint32_t live = 0;
-                    // chunks in pairs without a branch between them
+                        for (int j = 0; j < D; ++j) cc[j] = from_winner(bx[j]);
+                        const float ccq = EX ? from_winner(bq) : 0.f;
+                        bl = 0;
+                        uint32_t live = 0;
+                        // chunks in pairs without a branch between them
 #pragma unroll
-                    for (int g = 0; g < QL; g += 2) {
-                        if (g < (int)qn) {
+                        for (int g = 0; g < QL; g += 2) {
+                            if (g < (int)qn) {
 #pragma unroll
-                            for (int q = g; q < g + 2 && q < QL; ++q) {
-                                float s;
-                                if constexpr (EX) {
-                                    s = ccq;
+                                for (int q = g; q < g + 2 && q < QL; ++q) {
+                                    float s;
+                                    if constexpr (EX) {
+                                        s = ccq;
 #pragma unroll
-                                    for (int j = 0; j < D; ++j) s = __builtin_fmaf(x[q][j], cc[j], s);
-                                    s += xq[q];
-                                } else {
-                                    s = 0.f;
+                                        for (int j = 0; j < D; ++j)
+                                            s = __builtin_fmaf(x[q][j], cc[j], s);
+                                        s += xq[q];
+                                    } else {
+                                        s = 0.f;
 #pragma unroll
-                                    for (int j = 0; j < D; ++j) s = kc_d32_step(s, x[q][j], cc[j]);
-                                }
-                                m[q] = kc_fmin_nn(m[q], s);
-                                const u64 kq = kc_pack(m[q], ci[q]);
-                                const bool lv = q * 64 + lane < nv && kq > tau;
-                                live += (uint32_t)__builtin_popcountll(__ballot(lv));
-                                if (lv && kq > bl) {
-                                    bl = kq;
-                                    bs = os[q];
+                                        for (int j = 0; j < D; ++j)
+                                            s = kc_d32_step(s, x[q][j], cc[j]);
+                                    }
+                                    m[q] = kc_fmin_nn(m[q], s);
+                                    const u64 kq = kc_pack(m[q], ci[q]);
+                                    const bool lv = q * 64 + lane < nv && kq > tau;
+                                    live += (uint32_t)__builtin_popcountll(__ballot(lv));
+                                    if (lv && kq > bl) {
+                                        bl = kq;
+                                        bs = os[q];
+                                    }
                                 }
                             }
                         }
-                    }
-                    if constexpr (EX) {
-                        if (lane == 0)
-                            __hip_atomic_store(&sQf[nq], wslot, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-                        ++nq;
-                    }
-                    if (live + 64 <= qn * 64) {
-                        // pack the live candidates into positions 0..live-1
-                        uint32_t pos = 0;
-#pragma unroll
-                        for (int q = 0; q < QL; ++q) {
-                            if (q < (int)qn) {
-                                const bool lv = q * 64 + lane < nv && kc_pack(m[q], ci[q]) > tau;
-                                const u64 bal = __ballot(lv);
-                                if (lv) {
-                                    const uint32_t p = pos + (uint32_t)__builtin_popcountll(bal & ltmask);
-                                    sPm[p] = m[q];
-                                    sPi[p] = ci[q];
-                                    sPo[p] = os[q];
-                                }
-                                pos += (uint32_t)__builtin_popcountll(bal);
-                            }
+                        if constexpr (EX) {
+                            if (lane == 0)
+                                __hip_atomic_store(&sQf[nq], wslot, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                            ++nq;
                         }
-                        nv = pos;
-                        qn = (pos + 63) / 64;
+                        if (live + 64 <= qn * 64) {
+                            // pack the live candidates into positions 0..live-1
+                            uint32_t pos = 0;
 #pragma unroll
-                        for (int q = 0; q < QL; ++q) {
-                            if (q < (int)qn) {
-                                const uint32_t p = q * 64 + lane;
-                                if (p < nv) {
-                                    m[q] = sPm[p];
-                                    ci[q] = sPi[p];
-                                    os[q] = sPo[p];
-#pragma unroll
-                                    for (int j = 0; j < D; ++j)
-                                        x[q][j] = EX ? -2.f * sCx[j][os[q]] : sCx[j][os[q]];
-                                    if constexpr (EX) xq[q] = sCc[os[q]] - K2;
+                            for (int q = 0; q < QL; ++q) {
+                                if (q < (int)qn) {
+                                    const bool lv =
+                                        q * 64 + lane < nv && kc_pack(m[q], ci[q]) > tau;
+                                    const u64 bal = __ballot(lv);
+                                    if (lv) {
+                                        const uint32_t p =
+                                            pos + (uint32_t)__builtin_popcountll(bal & ltmask);
+                                        sPm[p] = m[q];
+                                        sPi[p] = ci[q];
+                                        sPo[p] = os[q];
+                                    }
+                                    pos += (uint32_t)__builtin_popcountll(bal);
                                 }
                             }
-                        }
-                    }
+                            nv = pos;
+                            qn = (pos + 63) / 64;
 #pragma unroll
-                    for (int j = 0; j < D; ++j) bx[j] = sCx[j][bs];
-                    if constexpr (EX) bq = sCc[bs];
-                }
-            } while (state == 0);
+                            for (int q = 0; q < QL; ++q) {
+                                if (q < (int)qn) {
+                                    const uint32_t p = q * 64 + lane;
+                                    if (p < nv) {
+                                        m[q] = sPm[p];
+                                        ci[q] = sPi[p];
+                                        os[q] = sPo[p];
+#pragma unroll
+                                        for (int j = 0; j < D; ++j)
+                                            x[q][j] = EX ? -2.f * sCx[j][os[q]] : sCx[j][os[q]];
+                                        if constexpr (EX) xq[q] = sCc[os[q]] - K2;
+                                    }
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int j = 0; j < D; ++j) bx[j] = sCx[j][bs];
+                        if constexpr (EX) bq = sCc[bs];
+                    }
+                } while (state == 0);
             };
             if constexpr (KC_LA_INT_FORM(D)) {
                 if (exact) lead(std::true_type{});
