@@ -152,7 +152,8 @@ int kc_timing_read(kc_handle* h, const char* name, double* ms, int64_t* launches
  * segments that the register-resident Gonzalez engine ran in its
  * exact-integer form (d >= 8, every coordinate an integer of magnitude at
  * most M with 5 d M^2 <= 2^24) since kc_device_status last cleared the
- * handle's status.  KC_EINVAL for an unknown name. */
+ * handle's status (direct calls only: a batch runs on its plan's own
+ * status words).  KC_EINVAL for an unknown name. */
 int kc_counter_read(kc_handle* h, const char* name, int64_t* value);
 
 /* Synchronises `stream`, then reads and clears the handle's device status
