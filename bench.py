@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--batch-only", action="store_true",
                     help="time kcenter_batch on the 256-instance mixed batch "
                          "(GON / MRG / EIM, d in {2, 8, 32}) and exit")
+    ap.add_argument("--assign-only", action="store_true",
+                    help="time config 4's assignment (5,000,000 x 41 points, "
+                         "500 centers) in FP32 and BF16 and exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="copy 1 GiB device-to-device 5 times (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -535,6 +538,23 @@ def bench_gon_bf16(kc, torch, steps, cfg=None):
     return out
 
 
+def bench_assign_only(kc, torch, steps):
+    """Config 4's assignment alone: the 500 centers of one Gonzalez run on
+    the BF16 copy (with rescoring, the FP32 path's centers), then
+    bench_assign."""
+    from paper_1604_03228_amd import workloads as W
+    X, Xb = W.config4()
+    Xd = torch.from_numpy(X).cuda()
+    B = torch.from_numpy(Xb.view(np.int16)).cuda()
+    h = kc.Handle()
+    c, _, _ = kc.gonzalez(Xd, W.CONFIG4["k"], 0, bf16=B, handle=h)
+    torch.cuda.synchronize()
+    h.close()
+    a = bench_assign(kc, torch, Xd, B, c, steps)
+    a["workload"] = "assign_mixed41_n5000000_k500"
+    return a
+
+
 def time_gon(kc, torch, Xd, k, steps, warmup, resident=True):
     """kcenter_gonzalez on the HBM-resident points Xd, timed over `steps`
     calls on a non-default stream (so the library's HIP graphs apply), with
@@ -655,6 +675,9 @@ def main():
         return
     if a.batch_only:
         print(json.dumps({"batch": bench_batch(kc, torch, max(2, a.steps))}))
+        return
+    if a.assign_only:
+        print(json.dumps({"c4_assign": bench_assign_only(kc, torch, max(2, a.steps))}))
         return
     if a.mrg_only:
         print(json.dumps({"mrg": bench_mrg(kc, torch, max(2, a.steps)),
