@@ -532,7 +532,8 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
             __builtin_amdgcn_s_setprio(3);
             // Gonzalez's step on C: lane `lane` holds candidates q*64 + lane,
             // q < QL, in the registers of a worker's points (coordinates in
-            // x[q], min-distance in m[q], index ci[q], slot in C os[q]).  A
+            // x[q], min-distance in m[q], index ni[q] (held complemented, as
+            // in the low word of a key), slot in C os[q]).  A
             // candidate at or below tau can no longer be certified this
             // round: it stops competing, and once the live candidates fit in
             // fewer chunks of 64 they are packed (through LDS) into the
@@ -546,7 +547,10 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
             auto lead = [&](auto form) {
                 constexpr bool EX = decltype(form)::value;
                 constexpr float K2 = 2.f * kc_la_int_offset(D);
-                uint32_t ci[QL], os[QL];
+                uint32_t ni[QL], os[QL];
+                auto key_of = [](float mv, uint32_t n) -> u64 {
+                    return ((u64)__float_as_uint(mv) << 32) | (u64)n;
+                };
                 float xq[EX ? QL : 1];
                 u64 bl = 0;
                 uint32_t bs = 0;
@@ -562,7 +566,7 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                     const u64 kraw = sCk[sl];
                     const u64 kq = v ? kraw : 0ull;
                     m[q] = kc_key_val(kq);
-                    ci[q] = kc_key_idx(kq);
+                    ni[q] = (uint32_t)kq;   // the key's complemented index
                     os[q] = sl;
 #pragma unroll
                     for (int j = 0; j < D; ++j) x[q][j] = EX ? -2.f * sCx[j][sl] : sCx[j][sl];
@@ -652,10 +656,14 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                                             s = kc_d32_step(s, x[q][j], cc[j]);
                                     }
                                     m[q] = kc_fmin_nn(m[q], s);
-                                    const u64 kq = kc_pack(m[q], ci[q]);
-                                    const bool lv = q * 64 + lane < nv && kq > tau;
-                                    live += (uint32_t)__builtin_popcountll(__ballot(lv));
-                                    if (lv && kq > bl) {
+                                    const u64 kq = key_of(m[q], ni[q]);
+                                    // one ballot per compare: their masks
+                                    // combine on the scalar unit
+                                    const bool in = q * 64 + lane < nv, up = kq > tau;
+                                    live += (uint32_t)__builtin_popcountll(
+                                        __builtin_amdgcn_ballot_w64(in) &
+                                        __builtin_amdgcn_ballot_w64(up));
+                                    if (in && up && kq > bl) {
                                         bl = kq;
                                         bs = os[q];
                                     }
@@ -675,13 +683,13 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                             for (int q = 0; q < QL; ++q) {
                                 if (q < (int)qn) {
                                     const bool lv =
-                                        q * 64 + lane < nv && kc_pack(m[q], ci[q]) > tau;
-                                    const u64 bal = __ballot(lv);
+                                        q * 64 + lane < nv && key_of(m[q], ni[q]) > tau;
+                                    const u64 bal = __builtin_amdgcn_ballot_w64(lv);
                                     if (lv) {
                                         const uint32_t p =
                                             pos + (uint32_t)__builtin_popcountll(bal & ltmask);
                                         sPm[p] = m[q];
-                                        sPi[p] = ci[q];
+                                        sPi[p] = ni[q];
                                         sPo[p] = os[q];
                                     }
                                     pos += (uint32_t)__builtin_popcountll(bal);
@@ -695,7 +703,7 @@ __global__ __launch_bounds__(KC_LA_BLOCK, 1) void k_gon_resident(
                                     const uint32_t p = q * 64 + lane;
                                     if (p < nv) {
                                         m[q] = sPm[p];
-                                        ci[q] = sPi[p];
+                                        ni[q] = sPi[p];
                                         os[q] = sPo[p];
 #pragma unroll
                                         for (int j = 0; j < D; ++j)
