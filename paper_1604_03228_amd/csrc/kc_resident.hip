@@ -950,8 +950,11 @@ static int max_resident_blocks()
         return 0;
     }
     int dev = 0, cus = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;   // no resident grid: the caller streams
+    }
     const int g = per_cu * cus;
     return g < KC_LA_GMAX ? g : KC_LA_GMAX;   // the exchange buffer's capacity
 }
