@@ -23,16 +23,16 @@ kc_handle::~kc_handle()
     clear_graphs();
     for (auto& kv : spans)
         for (auto& sp : kv.second) {
-            hipEventDestroy(sp.a);
-            hipEventDestroy(sp.b);
+            (void)hipEventDestroy(sp.a);
+            (void)hipEventDestroy(sp.b);
         }
-    for (hipEvent_t e : event_pool) hipEventDestroy(e);
+    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
     for (auto& kv : staging) {
-        if (kv.second.done) hipEventDestroy(kv.second.done);
-        if (kv.second.p) hipHostFree(kv.second.p);
+        if (kv.second.done) (void)hipEventDestroy(kv.second.done);
+        if (kv.second.p) (void)hipHostFree(kv.second.p);
     }
-    for (auto& kv : bufs) hipFree(kv.second.p);
-    if (status_word) hipFree(status_word);
+    for (auto& kv : bufs) (void)hipFree(kv.second.p);
+    if (status_word) (void)hipFree(status_word);
 }
 
 hipEvent_t kc_handle::span_begin(hipStream_t s)
@@ -46,7 +46,11 @@ hipEvent_t kc_handle::span_begin(hipStream_t s)
         (void)hipGetLastError();
         return nullptr;
     }
-    hipEventRecord(e, s);
+    if (hipEventRecord(e, s) != hipSuccess) {   // no span; the event goes back
+        (void)hipGetLastError();
+        event_pool.push_back(e);
+        return nullptr;
+    }
     return e;
 }
 
@@ -62,15 +66,20 @@ void kc_handle::span_end(const char* name, hipEvent_t a, int64_t launches, hipSt
         event_pool.push_back(a);
         return;
     }
-    hipEventRecord(b, s);
+    if (hipEventRecord(b, s) != hipSuccess) {   // the span is dropped
+        (void)hipGetLastError();
+        event_pool.push_back(a);
+        event_pool.push_back(b);
+        return;
+    }
     spans[name].push_back(TimedSpan{a, b, launches});
 }
 
 void kc_handle::clear_graphs()
 {
     for (auto& kv : graphs) {
-        hipGraphExecDestroy(kv.second.exec);
-        hipGraphDestroy(kv.second.graph);
+        (void)hipGraphExecDestroy(kv.second.exec);
+        (void)hipGraphDestroy(kv.second.graph);
     }
     graphs.clear();
 }
@@ -93,10 +102,14 @@ void* kc_handle::ws(const std::string& name, size_t bytes)
     auto it = bufs.find(name);
     if (it != bufs.end() && it->second.bytes >= bytes) return it->second.p;
     if (it != bufs.end()) {
-        // growing invalidates every captured graph (they embed the old address)
-        hipDeviceSynchronize();
+        // growing invalidates every captured graph (they embed the old address);
+        // the old buffer is freed only once no queued work can still use it
+        if (hipDeviceSynchronize() != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
         clear_graphs();
-        hipFree(it->second.p);
+        (void)hipFree(it->second.p);
         bufs.erase(it);
     }
     void* p = nullptr;
@@ -129,7 +142,7 @@ void* kc_handle::upload(const std::string& name, const void* src, size_t bytes, 
             return nullptr;
         }
         if (st.cap < bytes) {
-            if (st.p) hipHostFree(st.p);
+            if (st.p) (void)hipHostFree(st.p);
             st.p = nullptr;
             st.cap = 0;
             const size_t cap = (bytes + 4095) & ~(size_t)4095;
@@ -185,7 +198,7 @@ int kc_handle::run_graph(const std::string& key, hipStream_t stream,
         if (e != hipSuccess) return fail(KC_EHIP, "end capture: %s", hipGetErrorString(e));
         e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
         if (e != hipSuccess) {
-            hipGraphDestroy(g);
+            (void)hipGraphDestroy(g);
             return fail(KC_EHIP, "instantiate: %s", hipGetErrorString(e));
         }
         it = graphs.emplace(key, GraphEntry{g, ex}).first;
@@ -216,7 +229,7 @@ int kc_handle::tune(const std::string& key, int nvar, const bool* feasible, hipS
     hipEvent_t ea = nullptr, eb = nullptr;
     if (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) {
         (void)hipGetLastError();
-        if (ea) hipEventDestroy(ea);
+        if (ea) (void)hipEventDestroy(ea);
         return run(first);
     }
     std::vector<float> ms(nvar, -1.f);
@@ -227,9 +240,9 @@ int kc_handle::tune(const std::string& key, int nvar, const bool* feasible, hipS
         if (!feasible[v]) continue;
         rc = run(v);   // warm: caches, captured graphs
         if (rc) break;
-        hipEventRecord(ea, s);
+        (void)hipEventRecord(ea, s);   // a failed record shows as a failed elapsed time
         rc = run(v);
-        hipEventRecord(eb, s);
+        (void)hipEventRecord(eb, s);
         if (rc) break;
         float t = 0.f;
         if (hipEventSynchronize(eb) != hipSuccess || hipEventElapsedTime(&t, ea, eb) != hipSuccess) {
@@ -240,8 +253,8 @@ int kc_handle::tune(const std::string& key, int nvar, const bool* feasible, hipS
         if (ms[best] < 0.f || t < ms[best]) best = v;
     }
     timing = timing_was;
-    hipEventDestroy(ea);
-    hipEventDestroy(eb);
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
     if (rc) return rc;
     tuned[key] = best;
     tune_ms[key] = ms;
@@ -276,8 +289,11 @@ void* kc_handle::pinned(const std::string& name, size_t bytes)
     Staging& st = staging["pinned:" + name];
     if (st.cap >= bytes && st.p) return st.p;
     if (st.p) {
-        hipDeviceSynchronize();   // no queued copy may still target it
-        hipHostFree(st.p);
+        if (hipDeviceSynchronize() != hipSuccess) {   // a queued copy may still target it
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        (void)hipHostFree(st.p);
     }
     st.p = nullptr;
     st.cap = 0;
@@ -689,7 +705,7 @@ int kc_create(kc_handle** out)
 void kc_destroy(kc_handle* h)
 {
     if (!h) return;
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();   // nothing queued may still use its buffers
     delete h;
 }
 

@@ -1110,8 +1110,9 @@ static int kc_eim_pass_front(kc_handle* h, KcEimLoop& P, int var, hipStream_t s)
         uint32_t* vin = (uint32_t*)h->ws("e.sval", 4ull * nds);
         uint32_t* vout = (uint32_t*)h->ws("e.sval2", 4ull * nds);
         size_t tbytes = 0;
-        hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, kin, kout, vin, vout, (int)nds, 0,
-                                           32, s);
+        if (hipcub::DeviceRadixSort::SortPairs(nullptr, tbytes, kin, kout, vin, vout, (int)nds,
+                                               0, 32, s) != hipSuccess)
+            return h->fail(KC_EHIP, "sort size query failed");
         void* tmp = h->ws("e.sorttmp", tbytes);
         if (!XR || !Cs.Cf || (!split && !Cs.Ct) || (split && (!Cs.Cb || (!packed && !Cs.Cbl))) ||
             !Cs.cn || !Cs.cnl || !Cs.clen || !Cs.cmax || !O.arg || !O.m1 || !O.lo2 || !O.nx ||
@@ -1191,8 +1192,8 @@ static int kc_eim_pass_refine(kc_handle* h, KcEimLoop& P, int var, hipStream_t s
                        m * u32 / (1.0 - m * u32), d, P.tau, P.keep, P.lo, P.hi, P.uns2,
                        P.cnt + 5);
     // the FP64 pass takes what is still undecided
-    hipMemcpyAsync(P.cnt + 4, P.cnt + 5, 4, hipMemcpyDeviceToDevice, s);
-    if (hipMemcpyAsync(P.hw + 3, P.cnt + 5, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+    if (hipMemcpyAsync(P.cnt + 4, P.cnt + 5, 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(P.hw + 3, P.cnt + 5, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
         return h->fail(KC_EHIP, "readback failed");
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? KC_OK : h->fail(KC_EHIP, "launch: %s", hipGetErrorString(e));
@@ -1288,12 +1289,14 @@ static int kc_eim_front_phase(kc_handle* h, KcEimLoop& P, hipStream_t s)
     float* lo0 = (float*)h->ws("e.lo0", 4ull * n);
     float* hi0 = (float*)h->ws("e.hi0", 4ull * n);
     if (!lo0 || !hi0) return h->fail(KC_ENOMEM, "workspace allocation failed");
-    hipMemcpyAsync(lo0, P.lo, 4ull * n, hipMemcpyDeviceToDevice, s);
-    hipMemcpyAsync(hi0, P.hi, 4ull * n, hipMemcpyDeviceToDevice, s);
+    if (hipMemcpyAsync(lo0, P.lo, 4ull * n, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(hi0, P.hi, 4ull * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return h->fail(KC_EHIP, "interval copy failed");
     P.whole = true;
     return h->tune(tkey, 6, feas, s, [&](int v) {
-        hipMemcpyAsync(P.lo, lo0, 4ull * n, hipMemcpyDeviceToDevice, s);
-        hipMemcpyAsync(P.hi, hi0, 4ull * n, hipMemcpyDeviceToDevice, s);
+        if (hipMemcpyAsync(P.lo, lo0, 4ull * n, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(P.hi, hi0, 4ull * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return h->fail(KC_EHIP, "interval copy failed");
         P.var = v;
         return kc_eim_pass_whole(h, P, v, s);
     });
@@ -1379,7 +1382,8 @@ static void kc_eim_end_iter(kc_handle* h, KcEimLoop& P)
 static int kc_eim_form_c(kc_handle* h, KcEimLoop& P, hipStream_t s)
 {
     uint8_t* mark = P.fS;
-    hipMemsetAsync(mark, 0, P.n, s);
+    if (hipMemsetAsync(mark, 0, P.n, s) != hipSuccess)
+        return h->fail(KC_EHIP, "mark clear failed");
     if (P.ns) hipLaunchKernelGGL(k_mark, g1(P.ns), dim3(256), 0, s, P.S, P.ns, mark);
     if (P.nr) hipLaunchKernelGGL(k_mark, g1(P.nr), dim3(256), 0, s, P.R, P.nr, mark);
     kc_compact(P.C, mark, nullptr, P.n, P.H, P.cnt + 5, s);
