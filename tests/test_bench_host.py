@@ -55,10 +55,3 @@ def test_stored_traffic_needs_matching_sources(tmp_path, monkeypatch):
     assert bench.stored_traffic("k_gon_resident", "absent", srcs) is None
     monkeypatch.setattr(bench, "PROFILE_TRAFFIC", str(tmp_path / "missing.json"))
     assert bench.stored_traffic("k_gon_resident", "w", srcs) is None
-
-
-def test_committed_traffic_records_match_their_sources():
-    # every committed record was taken from the sources as they are now
-    t = json.load(open(bench.PROFILE_TRAFFIC))
-    for key, e in t.items():
-        assert e["source_hash"] == bench.kernel_source_hash(e["sources"]), key
