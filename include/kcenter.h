@@ -171,7 +171,10 @@ int kc_device_status(kc_handle* h, void* stream, uint32_t* status);
  * every point coincides with a center (the problem asks for at most k
  * centers, Section 1.1).
  *   pts           points (prec selects the FP32 or BF16+rescore stream; both
- *                 choose the same centers).
+ *                 choose the same centers).  Integer coordinates within the
+ *                 bound of counter "resident_integer" (d >= 8) run the
+ *                 register-resident engine's exact-integer form; its keys,
+ *                 centers and trace equal the canonical FP32 path's.
  *   k             centers wanted, k >= 1 (k >= n is allowed).
  *   first         index of the first center, 0 <= first < n.
  *   centers       device int64 [k]: chosen indices in selection order, -1
